@@ -1,0 +1,185 @@
+/* bm.h -- Boolean-matrix frequent-itemset mining on MI355X (gfx950).
+ *
+ * C ABI of libbm.so.  The operations follow the method of "A Matrix Logic
+ * Approach to Efficient Frequent Itemset Discovery in Large Data Sets"
+ * (arXiv 2412.19420), Section III:
+ *   - matrix construction (Eq. 1): the transaction list becomes the n x m
+ *     Boolean matrix M, M[i,j] = 1 iff item j is in transaction i;
+ *   - support calculation (Eq. 2): the joint support of items a and b is the
+ *     number of rows where columns a and b are both 1; longer itemsets AND
+ *     further columns one after another;
+ *   - frequent-itemset extraction (Eq. 3): an itemset is frequent when its
+ *     support passes the threshold.  This library takes the threshold as an
+ *     absolute count `minsup` and reports X iff S(X) >= minsup; the paper's
+ *     strict S(X) > theta is minsup = floor(theta) + 1.
+ *
+ * Conventions shared by every call
+ *   Status     every call returns a bm_status; no C++ exception crosses the ABI.
+ *              On failure `*out` (where present) is set to NULL, nothing leaks,
+ *              and bm_last_error() holds a thread-local description.
+ *   Pointers   "host or device" arguments may point to host memory or to device
+ *              memory of the current HIP device; the library tells them apart
+ *              with hipPointerGetAttributes.  Inputs are borrowed: the caller
+ *              may free or reuse them as soon as the call returns.
+ *   Streams    `stream` is a hipStream_t (NULL = the default stream).  All work
+ *              of a call is issued on it and the call returns only once that
+ *              work has completed.
+ *   Ownership  handles (bm_db, bm_result, bm_model) belong to the library until
+ *              the matching *_free call; *_free(NULL) is a no-op.
+ *   Threads    distinct handles may be used from different host threads; one
+ *              handle must not be used by two calls at once.
+ *   Limits     n_tx < 2^31 (supports are counted in int32, exact); item ids are
+ *              uint32 and must be < n_items.  Larger n_tx gives BM_ERR_UNSUPPORTED.
+ *   Devices    a handle lives on the HIP device that was current when it was
+ *              created; later calls on it must be made with that device current.
+ */
+#ifndef BM_H_
+#define BM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BM_ABI_VERSION 1u
+#define BM_MAX_LEVELS 64
+
+typedef struct bm_db bm_db;
+typedef struct bm_result bm_result;
+typedef struct bm_model bm_model;
+
+typedef enum {
+  BM_OK = 0,
+  BM_ERR_INVALID_ARG = 1, /* NULL where a pointer is required, minsup == 0, bad option */
+  BM_ERR_CSR = 2,         /* row_ptr[0] != 0, row_ptr not monotone, or an item id >= n_items */
+  BM_ERR_OOM = 3,         /* a device or host allocation failed */
+  BM_ERR_DEVICE = 4,      /* a HIP runtime call or kernel failed */
+  BM_ERR_UNSUPPORTED = 5  /* size beyond the documented limits */
+} bm_status;
+
+/* Kernel classes timed in bm_stats (index into the per-kernel arrays). */
+enum {
+  BM_K_BUILD = 0,     /* CSR validation + packing of column bitsets */
+  BM_K_COLSUM = 1,    /* column popcount: single-item supports */
+  BM_K_GRAM_MFMA = 2, /* int8-MFMA (masked) Gram matrix: pair supports of a class */
+  BM_K_ANDPOP = 3,    /* AND + popcount of a prefix class's columns (VALU) */
+  BM_K_LEVEL = 4,     /* candidate/level bookkeeping: thresholds, scans, compaction */
+  BM_K_EMIT = 5,      /* canonical-order output */
+  BM_K_COUNT = 6
+};
+
+/* Statistics of one mining call.  Kernel times are filled only when the call
+ * ran with BM_FLAG_TIMING (hipEvents recorded around every launch on the call's
+ * stream); `ops` counts algorithmic work: int8 multiply-adds x2 for
+ * BM_K_GRAM_MFMA, AND+popcount word operations for BM_K_ANDPOP; `bytes` counts
+ * algorithmic bytes (see the library's design notes for each kernel). */
+typedef struct {
+  uint32_t max_len;                            /* longest frequent itemset */
+  uint32_t n_frequent_items;                   /* frequent single items (m') */
+  uint64_t candidates[BM_MAX_LEVELS + 1];      /* [k]: supports evaluated for length-k sets */
+  uint64_t frequent[BM_MAX_LEVELS + 1];        /* [k]: frequent length-k sets */
+  uint64_t candidates_total;                   /* sum over k >= 2 of candidates[k] */
+  uint64_t frequent_total;
+  uint64_t classes_mfma, classes_andpop;       /* prefix classes sent to each kernel */
+  double kernel_ms[BM_K_COUNT];
+  uint64_t kernel_launches[BM_K_COUNT];
+  double kernel_bytes[BM_K_COUNT];
+  double kernel_ops[BM_K_COUNT];
+  double wall_ms;                              /* host wall time of the call */
+  uint32_t host_syncs;                         /* device->host synchronisations */
+} bm_stats;
+
+/* Tuning and behaviour switches for bm_mine_ex / bm_mine_batch.  Zero fields
+ * take the library default (or the autotuned value, see bm_autotune).  No option
+ * changes the mined result. */
+#define BM_FLAG_TIMING 1u      /* record per-kernel hipEvent times into bm_stats */
+#define BM_FLAG_NO_MFMA 2u     /* send every class to the AND+popcount kernel */
+#define BM_FLAG_ALL_MFMA 4u    /* send every class with >= 2 children to the MFMA kernel */
+#define BM_FLAG_GRAPH 8u       /* bm_mine_batch: replay the launch sequence as a hipGraph */
+#define BM_FLAG_TRACE 16u      /* keep per-class features and subtree costs (bm_result_trace) */
+#define BM_FLAG_SHUFFLE 32u    /* bm_mine_batch: random task order (order-invariance tests) */
+
+typedef struct {
+  uint32_t flags;
+  uint32_t mfma_min_children; /* classes with at least this many children use MFMA (default tuned) */
+  uint32_t andpop_chunk_words;/* AND+popcount LDS chunk: 128 or 256 words */
+  uint32_t split_words;       /* word-range length of one task (multiple of 64; 0 = automatic) */
+  uint32_t shuffle_seed;      /* with BM_FLAG_SHUFFLE */
+  uint32_t reserved[7];
+} bm_options;
+
+uint32_t bm_abi_version(void);
+/* Static English text for a status code. */
+const char* bm_status_string(bm_status s);
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* bm_last_error(void);
+
+/* Route the library's device allocations through caller callbacks (for example
+ * a framework's caching allocator).  alloc(size, stream, ctx) returns device
+ * memory or NULL (reported as BM_ERR_OOM); free(ptr, stream, ctx) releases it.
+ * Passing alloc == NULL and free == NULL restores the built-in caching pool.
+ * Must not be called while any handle is alive. */
+bm_status bm_set_allocator(void* (*alloc)(size_t size, void* stream, void* ctx),
+                           void (*free_fn)(void* ptr, void* stream, void* ctx), void* ctx);
+/* Return every cached block of the built-in pool to the HIP runtime. */
+bm_status bm_release_cached_memory(void);
+
+/* Matrix construction (Section III, Eq. 1).
+ * row_ptr  host or device, uint64[n_tx + 1]; row_ptr[0] == 0, non-decreasing.
+ * col_idx  host or device, uint32[row_ptr[n_tx]]; item ids of transaction i are
+ *          col_idx[row_ptr[i] .. row_ptr[i+1]); order within a row is free and
+ *          duplicate ids collapse (M is 0/1).  May be NULL when row_ptr[n_tx] == 0.
+ * On success *out holds M as one bitset per item column on the device: 64-bit
+ * words, transaction i at bit (i & 63) of word (i >> 6), padding bits zero,
+ * plus every column's popcount (the single-item supports, Eq. 3).
+ * Errors: BM_ERR_INVALID_ARG (out or row_ptr NULL), BM_ERR_CSR, BM_ERR_UNSUPPORTED
+ * (n_tx >= 2^31), BM_ERR_OOM, BM_ERR_DEVICE.  n_tx == 0 or n_items == 0 is valid. */
+bm_status bm_build(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n_tx,
+                   uint32_t n_items, void* stream, bm_db** out);
+bm_status bm_db_info(const bm_db* db, uint64_t* n_tx, uint32_t* n_items, uint64_t* words_per_column);
+
+/* Single-item supports S({j}) = popcount of column j (Eq. 3's column aggregation).
+ * out: host or device uint32[n_items]. */
+bm_status bm_item_support(const bm_db* db, uint32_t* out, void* stream);
+
+/* Pair supports (Eq. 2) of the k items `items` (host or device uint32[k], ids <
+ * n_items, repeats allowed; NULL means all n_items items in id order, k must then
+ * equal n_items).  out: host or device uint32[k*k], row-major and symmetric,
+ * out[a*k+b] = S({items[a], items[b]}), diagonal = single-item supports.
+ * Computed as the Gram matrix A^T A of the selected columns on int8 MFMA with
+ * int32 accumulation (exact).  k == 0 is a no-op. */
+bm_status bm_pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* out,
+                          void* stream);
+
+/* Frequent-itemset mining (Section III, Eqs. 1-3 and the recursive extension of
+ * frequent prefixes by further column ANDs).  Reports every non-empty itemset X
+ * with S(X) >= minsup.  minsup == 0 gives BM_ERR_INVALID_ARG; minsup > n_tx or an
+ * empty database gives an empty result.  The result is in canonical order:
+ * each itemset is an ascending tuple of the caller's item ids and the list is
+ * sorted lexicographically, a proper prefix before its extensions. */
+bm_status bm_mine(const bm_db* db, uint32_t minsup, void* stream, bm_result** out);
+/* As bm_mine with options (NULL = defaults). */
+bm_status bm_mine_ex(const bm_db* db, uint32_t minsup, const bm_options* opt, void* stream,
+                     bm_result** out);
+
+/* Result access.  n_sets frequent itemsets holding n_items_total item ids. */
+bm_status bm_result_info(const bm_result* r, uint64_t* n_sets, uint64_t* n_items_total,
+                         uint32_t* max_len);
+/* Copy the result (any pointer may be NULL to skip that array):
+ *   offsets  host or device uint64[n_sets + 1]; itemset s is items[offsets[s] .. offsets[s+1])
+ *   items    host or device uint32[n_items_total]
+ *   supports host or device uint32[n_sets] */
+bm_status bm_result_copy(const bm_result* r, uint64_t* offsets, uint32_t* items,
+                         uint32_t* supports, void* stream);
+bm_status bm_result_stats(const bm_result* r, bm_stats* out);
+
+void bm_db_free(bm_db* db);
+void bm_result_free(bm_result* r);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BM_H_ */
