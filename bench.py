@@ -1,0 +1,202 @@
+"""Benchmark of the Boolean-matrix miner on one MI355X.
+
+One step = the whole hot path on one synthetic database already resident in
+HBM: matrix construction from the CSR transaction list (bm_build), single-item
+supports, pair supports (A^T A on int8 MFMA), the recursive extension of
+frequent prefixes (masked Gram on MFMA for large prefix classes, AND+popcount
+for small ones), and the canonical-order result (bm_mine).  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--workload 3]
+
+value = candidate supports counted per second of step wall time (pairs of
+frequent items plus every longer candidate), with the step's wall time in
+ms_per_step.  `roofline` describes the kernel with the largest total time,
+measured with hipEvents recorded by the library on the call's stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+INT8_PEAK_TOPS = 5000.0
+
+WORKLOADS = {
+    1: "basket_zipf 10,000 tx x 169 items, minsup 1% (100)",
+    2: "quest T10I4D100K-style 100,000 tx x 1,000 items, minsup 0.25% (250)",
+    3: "dense_planted 1,000,000 tx x 4,096 items, 500 planted 6-item patterns, minsup 1% (10,000)",
+    5: "quest T40I10D1M-style 1,000,000 tx x 2,000 items, minsup 0.5% (5,000)",
+}
+
+
+def cpu_baseline(db, budget_s: float = 12.0) -> dict:
+    """The C++ oracle as it stands, on a bounded sample of the same workload:
+    the subtrees of the first k frequent items (all itemsets whose smallest
+    item is one of them), k grown until the run takes about `budget_s`."""
+    from oracle import cpp as ocpp
+    threads = max(1, min(16, os.cpu_count() or 1))
+    o = ocpp.OracleDb(db.row_ptr, db.col_idx, db.n, db.m)
+    m1 = len(o.frequent_items(db.minsup))
+    k = max(1, threads)
+    dt, cands, sets_ = o.time_sample(db.minsup, 0, k, threads)
+    while dt < budget_s / 4 and k < m1:
+        k = min(m1, k * 2 if dt < budget_s / 8 else int(k * budget_s / max(dt, 1e-3) / 2) + 1)
+        dt, cands, sets_ = o.time_sample(db.minsup, 0, k, threads)
+    return {
+        "value": cands / dt if dt > 0 else None,
+        "unit": "candidate supports/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"C++ sorted-tid-vector oracle, {threads} threads, subtrees of the first {k} of "
+                  f"{m1} frequent items: {cands} candidate supports, {sets_} frequent sets in {dt:.2f} s",
+        "seconds": round(dt, 3),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=3, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
+    ap.add_argument("--mfma-min-children", type=int, default=0)
+    ap.add_argument("--split-words", type=int, default=0)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="instead of mining, copy a buffer of this size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); multi-GPU runs are not part "
+              "of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "needs a GPU"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+
+    if args.copy_probe_mb:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4}), flush=True)
+        return
+
+    import gen
+    import paper_2412_19420_amd as bm
+
+    t0 = time.time()
+    db = gen.make_config(args.workload)
+    print(f"# workload {args.workload}: {db.name} n={db.n} m={db.m} nnz={db.nnz} minsup={db.minsup} "
+          f"(generated in {time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
+    rp = torch.from_numpy(db.row_ptr.astype(np.uint64)).to(dev)
+    ci = torch.from_numpy(db.col_idx.astype(np.uint32)).to(dev)
+    stream = torch.cuda.current_stream()
+    flags = 0 if args.no_timing else bm.FLAG_TIMING
+    opts = bm.options(flags=flags, mfma_min_children=args.mfma_min_children,
+                      split_words=args.split_words)
+
+    def step():
+        h = bm.bm_build(rp, ci, db.n, db.m, stream=stream)
+        r = bm.bm_mine_ex(h, db.minsup, opts, stream=stream)
+        return h, r
+
+    for i in range(args.warmup):
+        h, r = step()
+        print(f"# warmup {i}: {r.stats()['wall_ms']:.2f} ms mine", file=sys.stderr, flush=True)
+        del h, r
+    torch.cuda.synchronize()
+    stats = []
+    times = []
+    results = []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        t1 = time.perf_counter()
+        h, r = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        stats.append(r.stats())
+        results.append(r.info())
+        del h, r
+        print(f"# step {i}: {times[-1] * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    ms_per_step = 1e3 * total / args.steps
+    st = stats[-1]
+    cands = st["candidates_total"]
+    assert all(x == results[0] for x in results), "result changed between steps"
+
+    # dominant kernel by total event time
+    names = list(st["kernel_ms"])
+    ms = {k: sum(s["kernel_ms"][k] for s in stats) for k in names}
+    launches = {k: sum(s["kernel_launches"][k] for s in stats) for k in names}
+    roofline = None
+    kernels = {}
+    for k in names:
+        if launches[k] == 0:
+            continue
+        per = ms[k] / launches[k]
+        by = sum(s["kernel_bytes"][k] for s in stats) / launches[k]
+        op = sum(s["kernel_ops"][k] for s in stats) / launches[k]
+        kernels[k] = {"ms_per_step": round(ms[k] / args.steps, 4), "launches_per_step":
+                      launches[k] / args.steps, "avg_launch_ms": round(per, 4)}
+        if k == "gram_mfma":
+            kernels[k]["achieved_TOPs"] = round(op / (per * 1e-3) / 1e12, 2)
+            kernels[k]["algorithmic_ops_per_launch"] = op
+        if k == "andpop":
+            kernels[k]["achieved_GBs"] = round(by / (per * 1e-3) / 1e9, 1)
+            kernels[k]["algorithmic_bytes_per_launch"] = by
+    if not args.no_timing and kernels:
+        dom = max((k for k in kernels if k in ("gram_mfma", "andpop")), key=lambda k: ms[k],
+                  default=None)
+        if dom == "gram_mfma":
+            a = kernels[dom]["achieved_TOPs"]
+            roofline = {"bound": "mfma", "kernel": "k_gram_mfma (int8 MFMA Gram of a prefix class)",
+                        "achieved": a, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+                        "frac": round(a / INT8_PEAK_TOPS, 4), "traffic": None}
+        elif dom == "andpop":
+            a = kernels[dom]["achieved_GBs"]
+            roofline = {"bound": "hbm", "kernel": "k_andpop (AND+popcount of a prefix class)",
+                        "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(a / HBM_PEAK_GBS, 4), "traffic": None}
+
+    out = {
+        "metric": "candidate supports counted/s + mine wall time at minsup; % of HBM peak",
+        "value": round(cands / (ms_per_step * 1e-3), 1),
+        "unit": "candidate supports/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64 bitsets; int8 MFMA, int32 accumulate",
+        "data": "synthetic (seeded generator, see DESIGN.md)",
+        "config": {"workload": WORKLOADS[args.workload], "n_tx": db.n, "n_items": db.m,
+                   "minsup": db.minsup, "frequent_itemsets": st["frequent_total"],
+                   "candidates": cands, "frequent_items": st["n_frequent_items"],
+                   "mine_ms": round(sum(s["wall_ms"] for s in stats) / len(stats), 3),
+                   "kernels": kernels},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(db)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

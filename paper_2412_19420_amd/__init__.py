@@ -1,0 +1,232 @@
+"""Boolean-matrix frequent-itemset mining on MI355X (gfx950).
+
+Python binding of libbm.so with the names of its C ABI (include/bm.h):
+
+    db  = bm_build(row_ptr, col_idx, n_tx, n_items)      # Eq. 1: column bitsets on the GPU
+    sup = bm_item_support(db)                             # Eq. 3: single-item supports
+    C   = bm_pair_support(db, items)                      # Eq. 2: pair supports (int8 MFMA Gram)
+    res = bm_mine(db, minsup)                             # all frequent itemsets, canonical order
+    offsets, items, supports = res.arrays()
+
+Arrays may be numpy arrays or torch tensors (host or device).  Work runs on
+torch's current HIP stream unless `stream` is given.  The package has no CPU
+fallback: importing it without the built library raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _bm
+from ._bm import (BM_K_NAMES, FLAG_ALL_MFMA, FLAG_GRAPH, FLAG_NO_MFMA, FLAG_SHUFFLE,
+                  FLAG_TIMING, FLAG_TRACE, BmError, BmOptions)
+
+__all__ = [
+    "bm_abi_version", "bm_build", "bm_item_support", "bm_pair_support", "bm_mine",
+    "bm_mine_ex", "bm_set_allocator", "bm_release_cached_memory", "Db", "Result", "BmError",
+    "options", "FLAG_TIMING", "FLAG_NO_MFMA", "FLAG_ALL_MFMA", "FLAG_GRAPH", "FLAG_TRACE",
+    "FLAG_SHUFFLE", "LIB_PATH",
+]
+
+LIB_PATH = _bm.LIB_PATH
+
+
+def bm_abi_version() -> int:
+    return int(_bm.lib.bm_abi_version())
+
+
+class Db:
+    """A transaction database resident on the GPU as packed column bitsets."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        n = ctypes.c_uint64()
+        m = ctypes.c_uint32()
+        w = ctypes.c_uint64()
+        _bm.check(_bm.lib.bm_db_info(self._h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(w)),
+                  "bm_db_info")
+        return int(n.value), int(m.value), int(w.value)
+
+    def free(self):
+        if self._h:
+            _bm.lib.bm_db_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Result:
+    """Frequent itemsets with supports, held on the GPU until copied out."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def info(self):
+        s = ctypes.c_uint64()
+        t = ctypes.c_uint64()
+        k = ctypes.c_uint32()
+        _bm.check(_bm.lib.bm_result_info(self._h, ctypes.byref(s), ctypes.byref(t), ctypes.byref(k)),
+                  "bm_result_info")
+        return int(s.value), int(t.value), int(k.value)
+
+    def __len__(self):
+        return self.info()[0]
+
+    def arrays(self, stream=None):
+        """(offsets u64[F+1], items u32[T], supports u32[F]) as host numpy arrays."""
+        F, T, _ = self.info()
+        offs = np.zeros(F + 1, dtype=np.uint64)
+        items = np.zeros(max(T, 1), dtype=np.uint32)
+        supp = np.zeros(max(F, 1), dtype=np.uint32)
+        _bm.check(_bm.lib.bm_result_copy(self._h, offs.ctypes.data, items.ctypes.data,
+                                         supp.ctypes.data, _bm._stream_ptr(stream)),
+                  "bm_result_copy")
+        return offs, items[:T], supp[:F]
+
+    def tensors(self, device="cuda", stream=None):
+        """The same three arrays copied into torch tensors on `device`."""
+        import torch
+        F, T, _ = self.info()
+        offs = torch.empty(F + 1, dtype=torch.uint64, device=device)
+        items = torch.empty(max(T, 1), dtype=torch.uint32, device=device)
+        supp = torch.empty(max(F, 1), dtype=torch.uint32, device=device)
+        _bm.check(_bm.lib.bm_result_copy(self._h, offs.data_ptr(), items.data_ptr(),
+                                         supp.data_ptr(), _bm._stream_ptr(stream)),
+                  "bm_result_copy")
+        return offs, items[:T], supp[:F]
+
+    def to_list(self):
+        offs, items, supp = self.arrays()
+        offs = offs.astype(np.int64)
+        return [(tuple(int(x) for x in items[offs[i]:offs[i + 1]]), int(supp[i]))
+                for i in range(len(offs) - 1)]
+
+    def stats(self) -> dict:
+        st = _bm.BmStats()
+        _bm.check(_bm.lib.bm_result_stats(self._h, ctypes.byref(st)), "bm_result_stats")
+        K = st.max_len
+        return {
+            "max_len": K,
+            "n_frequent_items": st.n_frequent_items,
+            "candidates": {k: int(st.candidates[k]) for k in range(2, _bm.BM_MAX_LEVELS + 1)
+                           if st.candidates[k]},
+            "frequent": {k: int(st.frequent[k]) for k in range(1, _bm.BM_MAX_LEVELS + 1)
+                         if st.frequent[k]},
+            "candidates_total": int(st.candidates_total),
+            "frequent_total": int(st.frequent_total),
+            "classes_mfma": int(st.classes_mfma),
+            "classes_andpop": int(st.classes_andpop),
+            "kernel_ms": {n: float(st.kernel_ms[i]) for i, n in enumerate(BM_K_NAMES)},
+            "kernel_launches": {n: int(st.kernel_launches[i]) for i, n in enumerate(BM_K_NAMES)},
+            "kernel_bytes": {n: float(st.kernel_bytes[i]) for i, n in enumerate(BM_K_NAMES)},
+            "kernel_ops": {n: float(st.kernel_ops[i]) for i, n in enumerate(BM_K_NAMES)},
+            "wall_ms": float(st.wall_ms),
+            "host_syncs": int(st.host_syncs),
+        }
+
+    def free(self):
+        if self._h:
+            _bm.lib.bm_result_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def options(flags: int = 0, mfma_min_children: int = 0, andpop_chunk_words: int = 0,
+            split_words: int = 0, shuffle_seed: int = 0) -> BmOptions:
+    o = BmOptions()
+    o.flags = flags
+    o.mfma_min_children = mfma_min_children
+    o.andpop_chunk_words = andpop_chunk_words
+    o.split_words = split_words
+    o.shuffle_seed = shuffle_seed
+    return o
+
+
+def bm_build(row_ptr, col_idx, n_tx: int, n_items: int, stream=None) -> Db:
+    rp, k1 = _bm._ptr(row_ptr, np.uint64)
+    ci, k2 = _bm._ptr(col_idx, np.uint32) if col_idx is not None and len(col_idx) else (ctypes.c_void_p(0), None)
+    h = ctypes.c_void_p()
+    _bm.check(_bm.lib.bm_build(rp, ci, n_tx, n_items, _bm._stream_ptr(stream), ctypes.byref(h)),
+              "bm_build")
+    del k1, k2
+    return Db(h)
+
+
+def bm_item_support(db: Db, stream=None) -> np.ndarray:
+    _, m, _ = db.info()
+    out = np.zeros(max(m, 1), dtype=np.uint32)
+    _bm.check(_bm.lib.bm_item_support(db.handle, out.ctypes.data, _bm._stream_ptr(stream)),
+              "bm_item_support")
+    return out[:m]
+
+
+def bm_pair_support(db: Db, items=None, stream=None, out=None):
+    """k x k pair-support matrix of `items` (None = all items).  Returns a numpy array
+    unless `out` (a uint32 torch tensor with k*k elements) is given."""
+    if items is None:
+        _, k, _ = db.info()
+        ip, keep = ctypes.c_void_p(0), None
+    else:
+        ip, keep = _bm._ptr(items, np.uint32)
+        k = len(items)
+    if out is None:
+        res = np.zeros((max(k, 1), max(k, 1)), dtype=np.uint32)
+        _bm.check(_bm.lib.bm_pair_support(db.handle, ip, k, res.ctypes.data, _bm._stream_ptr(stream)),
+                  "bm_pair_support")
+        return res[:k, :k]
+    _bm.check(_bm.lib.bm_pair_support(db.handle, ip, k, out.data_ptr(), _bm._stream_ptr(stream)),
+              "bm_pair_support")
+    del keep
+    return out
+
+
+def bm_mine(db: Db, minsup: int, stream=None) -> Result:
+    h = ctypes.c_void_p()
+    _bm.check(_bm.lib.bm_mine(db.handle, minsup, _bm._stream_ptr(stream), ctypes.byref(h)), "bm_mine")
+    return Result(h)
+
+
+def bm_mine_ex(db: Db, minsup: int, opts: BmOptions | None = None, stream=None) -> Result:
+    h = ctypes.c_void_p()
+    op = ctypes.byref(opts) if opts is not None else None
+    _bm.check(_bm.lib.bm_mine_ex(db.handle, minsup, op, _bm._stream_ptr(stream), ctypes.byref(h)),
+              "bm_mine_ex")
+    return Result(h)
+
+
+_allocator_keepalive = None
+
+
+def bm_set_allocator(alloc=None, free=None):
+    """Route device allocations through Python callables alloc(size, stream) -> int pointer and
+    free(ptr, stream); None, None restores the built-in pool."""
+    global _allocator_keepalive
+    if alloc is None and free is None:
+        st = _bm.lib.bm_set_allocator(_bm.ALLOC_FN(), _bm.FREE_FN(), None)
+        _bm.check(st, "bm_set_allocator")
+        _allocator_keepalive = None
+        return
+    a = _bm.ALLOC_FN(lambda size, stream, ctx: alloc(int(size), stream) or 0)
+    f = _bm.FREE_FN(lambda ptr, stream, ctx: free(int(ptr), stream))
+    _bm.check(_bm.lib.bm_set_allocator(a, f, None), "bm_set_allocator")
+    _allocator_keepalive = (a, f)
+
+
+def bm_release_cached_memory():
+    _bm.check(_bm.lib.bm_release_cached_memory(), "bm_release_cached_memory")

@@ -1,0 +1,144 @@
+// extern "C" entry points of libbm (declared and documented in bm.h).
+#include <cstring>
+
+#include "handles.hpp"
+
+namespace {
+
+template <class F>
+bm_status guarded(F&& f) {
+  try {
+    bm::set_last_error("");
+    f();
+    return BM_OK;
+  } catch (const bm::Error& e) {
+    bm::set_last_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    bm::set_last_error("host allocation failed");
+    return BM_ERR_OOM;
+  } catch (const std::exception& e) {
+    bm::set_last_error(e.what());
+    return BM_ERR_DEVICE;
+  } catch (...) {
+    bm::set_last_error("unknown failure");
+    return BM_ERR_DEVICE;
+  }
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+uint32_t bm_abi_version(void) { return BM_ABI_VERSION; }
+
+const char* bm_status_string(bm_status s) {
+  switch (s) {
+    case BM_OK: return "ok";
+    case BM_ERR_INVALID_ARG: return "invalid argument";
+    case BM_ERR_CSR: return "malformed CSR transaction list";
+    case BM_ERR_OOM: return "out of memory";
+    case BM_ERR_DEVICE: return "device error";
+    case BM_ERR_UNSUPPORTED: return "unsupported size";
+  }
+  return "unknown status";
+}
+
+const char* bm_last_error(void) { return bm::last_error(); }
+
+bm_status bm_set_allocator(void* (*alloc)(size_t, void*, void*), void (*free_fn)(void*, void*, void*),
+                           void* ctx) {
+  return bm::set_allocator(alloc, free_fn, ctx);
+}
+
+bm_status bm_release_cached_memory(void) {
+  return guarded([&] { bm::release_cached(); });
+}
+
+bm_status bm_build(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n_tx,
+                   uint32_t n_items, void* stream, bm_db** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!out) bm::fail(BM_ERR_INVALID_ARG, "out is NULL");
+    *out = bm::build_db(row_ptr, col_idx, n_tx, n_items, as_stream(stream));
+  });
+}
+
+bm_status bm_db_info(const bm_db* db, uint64_t* n_tx, uint32_t* n_items, uint64_t* words) {
+  return guarded([&] {
+    if (!db) bm::fail(BM_ERR_INVALID_ARG, "db is NULL");
+    if (n_tx) *n_tx = db->n;
+    if (n_items) *n_items = db->m;
+    if (words) *words = db->Wp;
+  });
+}
+
+bm_status bm_item_support(const bm_db* db, uint32_t* out, void* stream) {
+  return guarded([&] {
+    if (!db || !out) bm::fail(BM_ERR_INVALID_ARG, "db or out is NULL");
+    if (db->m == 0) return;
+    hipStream_t s = as_stream(stream);
+    BM_HIP(hipMemcpyAsync(out, db->colsum.get(), (size_t)db->m * 4, hipMemcpyDefault, s));
+    BM_HIP(hipStreamSynchronize(s));
+  });
+}
+
+bm_status bm_pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* out,
+                          void* stream) {
+  return guarded([&] {
+    if (!db) bm::fail(BM_ERR_INVALID_ARG, "db is NULL");
+    bm::pair_support(db, items, k, out, as_stream(stream));
+  });
+}
+
+bm_status bm_mine_ex(const bm_db* db, uint32_t minsup, const bm_options* opt, void* stream,
+                     bm_result** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!db || !out) bm::fail(BM_ERR_INVALID_ARG, "db or out is NULL");
+    *out = bm::mine(db, minsup, opt, as_stream(stream));
+  });
+}
+
+bm_status bm_mine(const bm_db* db, uint32_t minsup, void* stream, bm_result** out) {
+  return bm_mine_ex(db, minsup, nullptr, stream, out);
+}
+
+bm_status bm_result_info(const bm_result* r, uint64_t* n_sets, uint64_t* n_items_total,
+                         uint32_t* max_len) {
+  return guarded([&] {
+    if (!r) bm::fail(BM_ERR_INVALID_ARG, "result is NULL");
+    if (n_sets) *n_sets = r->n_sets;
+    if (n_items_total) *n_items_total = r->n_items;
+    if (max_len) *max_len = r->max_len;
+  });
+}
+
+bm_status bm_result_copy(const bm_result* r, uint64_t* offsets, uint32_t* items,
+                         uint32_t* supports, void* stream) {
+  return guarded([&] {
+    if (!r) bm::fail(BM_ERR_INVALID_ARG, "result is NULL");
+    hipStream_t s = as_stream(stream);
+    if (offsets)
+      BM_HIP(hipMemcpyAsync(offsets, r->offsets.get(), (r->n_sets + 1) * 8, hipMemcpyDefault, s));
+    if (items && r->n_items)
+      BM_HIP(hipMemcpyAsync(items, r->items.get(), r->n_items * 4, hipMemcpyDefault, s));
+    if (supports && r->n_sets)
+      BM_HIP(hipMemcpyAsync(supports, r->supports.get(), r->n_sets * 4, hipMemcpyDefault, s));
+    BM_HIP(hipStreamSynchronize(s));
+  });
+}
+
+bm_status bm_result_stats(const bm_result* r, bm_stats* out) {
+  return guarded([&] {
+    if (!r || !out) bm::fail(BM_ERR_INVALID_ARG, "result or out is NULL");
+    std::memcpy(out, &r->stats, sizeof(bm_stats));
+  });
+}
+
+void bm_db_free(bm_db* db) { delete db; }
+void bm_result_free(bm_result* r) { delete r; }
+
+}  // extern "C"

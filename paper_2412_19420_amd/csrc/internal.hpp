@@ -1,0 +1,179 @@
+// Internal declarations of libbm: device data layout, task records, launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "bm.h"
+
+namespace bm {
+
+// ------------------------------------------------------------------ errors
+
+struct Error {
+  bm_status status;
+  std::string msg;
+};
+
+[[noreturn]] void fail(bm_status st, const char* fmt, ...);
+void set_last_error(const std::string& s);
+
+#define BM_HIP(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      ::bm::fail(BM_ERR_DEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),       \
+                 __FILE__, __LINE__);                                                         \
+  } while (0)
+
+#define BM_LAUNCH_CHECK() BM_HIP(hipGetLastError())
+
+// ------------------------------------------------------------------ memory
+
+void* dalloc(size_t bytes, hipStream_t s);  // throws Error{BM_ERR_OOM}
+void dfree(void* p, hipStream_t s) noexcept;
+
+// Owning device buffer, returned to the pool on destruction.
+template <class T>
+class DBuf {
+ public:
+  DBuf() = default;
+  DBuf(size_t n, hipStream_t s) : s_(s) { reset(n, s); }
+  ~DBuf() { release(); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p_(o.p_), n_(o.n_), s_(o.s_) { o.p_ = nullptr; o.n_ = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p_ = o.p_; n_ = o.n_; s_ = o.s_;
+      o.p_ = nullptr; o.n_ = 0;
+    }
+    return *this;
+  }
+  void reset(size_t n, hipStream_t s) {
+    release();
+    s_ = s;
+    n_ = n;
+    p_ = n ? static_cast<T*>(dalloc(n * sizeof(T), s)) : nullptr;
+  }
+  void release() {
+    if (p_) dfree(p_, s_);
+    p_ = nullptr;
+    n_ = 0;
+  }
+  T* get() const { return p_; }
+  size_t size() const { return n_; }
+  size_t bytes() const { return n_ * sizeof(T); }
+
+ private:
+  T* p_ = nullptr;
+  size_t n_ = 0;
+  hipStream_t s_ = nullptr;
+};
+
+// ------------------------------------------------------------------ layout
+
+// Words per bitset column: ceil(n/64) rounded up to a multiple of 64 words, so
+// every 16-word MFMA stage and 64-word split boundary stays inside the column;
+// padding bits are zero.
+inline uint64_t padded_words(uint64_t n_tx) {
+  uint64_t w = (n_tx + 63) / 64;
+  uint64_t wp = (w + 63) / 64 * 64;
+  return wp ? wp : 64;
+}
+
+// One prefix class of a level step: a frequent prefix P and its q frequent
+// one-item extensions ("children").  The class's candidates are the q(q-1)/2
+// pairs of children (i < l); candidate (i, l) is P + child_i + child_l.
+struct ClassDesc {
+  uint64_t tri_off;   // offset of this class's q(q-1)/2 supports in the step's buffer
+  uint32_t child0;    // index of the first child in the child-item array
+  uint32_t q;         // number of children
+  uint32_t pre_off;   // offset of P's columns in the prefix-column array
+  uint32_t pre_len;   // |P| (0 for the root class of single items)
+};
+
+// One unit of kernel work: a block pair (bi <= bl) of a class's q x q triangle
+// over a word range.  Block size is the kernel's (128 for MFMA, 16 for AND+popcount).
+struct Task {
+  uint32_t cls;
+  uint16_t bi, bl;
+  uint32_t w0, w1;
+};
+
+// Upper-triangle index of pair (i, l), i < l, in a q x q triangle.
+__host__ __device__ inline uint64_t tri_index(uint64_t i, uint64_t l, uint64_t q) {
+  return i * (2 * q - i - 1) / 2 + (l - i - 1);
+}
+
+constexpr int GRAM_TILE = 128;  // MFMA kernel output tile (children per block)
+constexpr int GRAM_KW = 16;     // MFMA kernel words per LDS stage
+constexpr int AP_BLOCK = 16;    // AND+popcount kernel children per block
+
+// Arguments shared by both class kernels.
+struct ClassArgs {
+  const uint64_t* B;          // bitset matrix, column-major, Wp words per column
+  uint64_t Wp;
+  const uint32_t* f1;         // child item -> column id (nullptr: identity)
+  const uint32_t* child_item; // item of each child (indexed by class child0 + i)
+  const ClassDesc* cls;
+  const uint32_t* pre_cols;   // prefix column ids
+  const Task* tasks;
+  uint32_t ntasks;
+  uint32_t* tri;              // per-class triangles of supports (accumulated atomically)
+};
+
+// ------------------------------------------------------------------ launchers
+
+// Device timing of launches (hipEvents on the call's stream).
+class KTimer {
+ public:
+  explicit KTimer(bool on, hipStream_t s) : on_(on), s_(s) {}
+  ~KTimer();
+  void begin(int kind);
+  void end(double bytes = 0, double ops = 0);
+  // Adds accumulated times to stats (synchronises on the recorded events).
+  void collect(bm_stats* st);
+  bool on() const { return on_; }
+
+ private:
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes, ops;
+  };
+  bool on_;
+  hipStream_t s_;
+  std::vector<Rec> recs_;
+  int cur_kind_ = -1;
+  hipEvent_t cur_a_ = nullptr;
+};
+
+// build
+void launch_validate(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t nnz, uint32_t m,
+                     uint32_t* err, hipStream_t s);
+void launch_pack(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t* B, uint64_t Wp,
+                 hipStream_t s);
+void launch_colsum(const uint64_t* B, uint64_t Wp, uint32_t m, uint32_t* colsum, hipStream_t s);
+void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
+
+// scans: out[0..n] exclusive, out[n] = total.  tmp sized by scan_tmp_words(n).
+size_t scan_tmp_words(uint64_t n);
+void scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s);
+void scan_u32_to_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s);
+// out[0..n]: exclusive scan of (in[i] >= thr)
+void scan_ge_u32(const uint32_t* in, uint32_t thr, uint64_t* out, uint64_t n, uint64_t* tmp,
+                 hipStream_t s);
+
+// class kernels
+void launch_gram_mfma(const ClassArgs& a, uint32_t grid, hipStream_t s);
+void launch_andpop(const ClassArgs& a, uint32_t chunk_words, uint32_t grid, hipStream_t s);
+
+}  // namespace bm

@@ -1,0 +1,258 @@
+// Matrix construction (Eq. 1) and column aggregation (Eq. 3), plus the
+// generic fill and prefix-sum kernels the level bookkeeping uses.
+//
+// Layout of M: one bitset per item column, Wp 64-bit words per column
+// (column-major), transaction i at bit (i & 63) of word (i >> 6).  Column-major
+// keeps every column contiguous, so the support kernels stream whole columns
+// with coalesced 16-byte loads.
+#include "internal.hpp"
+
+namespace bm {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ void k_validate_rows(const uint64_t* __restrict__ rp, uint64_t n, uint32_t* err) {
+  uint32_t bad = 0;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    if (rp[i + 1] < rp[i]) bad |= 1u;
+  }
+  if (bad) atomicOr(err, bad);
+}
+
+__global__ void k_validate_cols(const uint32_t* __restrict__ ci, uint64_t nnz, uint32_t m,
+                                uint32_t* err) {
+  uint32_t bad = 0;
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    if (ci[e] >= m) bad |= 2u;
+  }
+  if (bad) atomicOr(err, bad);
+}
+
+// One workgroup per 256 consecutive rows.  The rows' slice of row_ptr is kept
+// in LDS; threads walk the rows' item ids with unit stride (coalesced) and find
+// each id's row by binary search in LDS, then set the bit with a 64-bit atomic
+// OR (idempotent, so duplicate ids collapse as M is 0/1).
+__global__ __launch_bounds__(kThreads) void k_pack(const uint64_t* __restrict__ rp,
+                                                   const uint32_t* __restrict__ ci, uint64_t n,
+                                                   unsigned long long* __restrict__ B, uint64_t Wp) {
+  __shared__ uint64_t s_rp[kThreads + 1];
+  const uint64_t r0 = (uint64_t)blockIdx.x * kThreads;
+  const uint32_t nr = (uint32_t)min<uint64_t>(kThreads, n - r0);
+  for (uint32_t t = threadIdx.x; t <= nr; t += kThreads) s_rp[t] = rp[r0 + t];
+  __syncthreads();
+  const uint64_t e0 = s_rp[0], e1 = s_rp[nr];
+  for (uint64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
+    // largest r with s_rp[r] <= e (rows may be empty, so skip equal starts)
+    uint32_t lo = 0, hi = nr;  // invariant: s_rp[lo] <= e < s_rp[hi]
+    while (hi - lo > 1) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (s_rp[mid] <= e) lo = mid; else hi = mid;
+    }
+    const uint64_t row = r0 + lo;
+    const uint32_t j = ci[e];
+    atomicOr(&B[(uint64_t)j * Wp + (row >> 6)], 1ull << (row & 63));
+  }
+}
+
+// Support of each single item: popcount of its column, one workgroup per column.
+__global__ __launch_bounds__(kThreads) void k_colsum(const uint64_t* __restrict__ B, uint64_t Wp,
+                                                     uint32_t m, uint32_t* __restrict__ out) {
+  __shared__ uint32_t s_part[kThreads / 64];
+  for (uint64_t j = blockIdx.x; j < m; j += gridDim.x) {
+    const uint64_t* col = B + j * Wp;
+    uint32_t c = 0;
+    for (uint64_t w = threadIdx.x; w < Wp; w += kThreads) c += __popcll(col[w]);
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t t = 0;
+      for (int k = 0; k < kThreads / 64; ++k) t += s_part[k];
+      out[j] = t;
+    }
+    __syncthreads();
+  }
+}
+
+template <class T>
+__global__ void k_fill(T* __restrict__ p, T v, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+uint32_t grid_for(uint64_t work, uint32_t per_block = kThreads, uint32_t cap = 65536) {
+  uint64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (uint32_t)g;
+}
+
+// ---------------------------------------------------------------- prefix sums
+// Three-phase exclusive scan: each workgroup scans 1024 values (4 per thread),
+// the per-workgroup totals are scanned recursively, and offsets are added back.
+
+constexpr int kScanPer = 4;
+constexpr int kScanBlock = kThreads * kScanPer;
+
+struct InU64 {
+  const uint64_t* p;
+  __device__ uint64_t operator()(uint64_t i) const { return p[i]; }
+};
+struct InU32 {
+  const uint32_t* p;
+  __device__ uint64_t operator()(uint64_t i) const { return p[i]; }
+};
+struct InGe {
+  const uint32_t* p;
+  uint32_t thr;
+  __device__ uint64_t operator()(uint64_t i) const { return p[i] >= thr ? 1u : 0u; }
+};
+
+__device__ inline uint64_t block_exclusive_scan(uint64_t v, uint64_t* s_wave, uint64_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t inc = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    uint64_t y = __shfl_up(inc, off);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) s_wave[wave] = inc;
+  __syncthreads();
+  uint64_t base = 0, tot = 0;
+  for (int k = 0; k < kThreads / 64; ++k) {
+    if (k < wave) base += s_wave[k];
+    tot += s_wave[k];
+  }
+  *total = tot;
+  return base + inc - v;
+}
+
+template <class In>
+__global__ __launch_bounds__(kThreads) void k_scan_local(In in, uint64_t* __restrict__ out,
+                                                         uint64_t n, uint64_t* __restrict__ sums) {
+  __shared__ uint64_t s_wave[kThreads / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanPer;
+  uint64_t v[kScanPer];
+  uint64_t t = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = (base + k < n) ? in(base + k) : 0;
+    t += v[k];
+  }
+  uint64_t total;
+  uint64_t ex = block_exclusive_scan(t, s_wave, &total);
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < n) out[base + k] = ex;
+    ex += v[k];
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_add(uint64_t* __restrict__ out, uint64_t n,
+                                                       const uint64_t* __restrict__ offs) {
+  const uint64_t add = offs[blockIdx.x];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanBlock;
+  for (int k = threadIdx.x; k < kScanBlock; k += kThreads) {
+    if (base + k < n) out[base + k] += add;
+  }
+}
+
+__global__ void k_scan_total(uint64_t* __restrict__ out, uint64_t n, const uint64_t* __restrict__ s) {
+  // out[n] = scanned offset of the last block + its total
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = s[0];
+}
+
+template <class In>
+void scan_impl(In in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s) {
+  if (n == 0) {
+    k_fill<uint64_t><<<1, 64, 0, s>>>(out, 0ull, 1);
+    BM_LAUNCH_CHECK();
+    return;
+  }
+  const uint64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  if (nb > 0x7fffffffull) fail(BM_ERR_UNSUPPORTED, "scan of %llu elements", (unsigned long long)n);
+  uint64_t* sums = tmp;           // nb + 1 entries
+  uint64_t* rest = tmp + nb + 1;  // recursion scratch
+  k_scan_local<<<(uint32_t)nb, kThreads, 0, s>>>(in, out, n, sums);
+  BM_LAUNCH_CHECK();
+  if (nb == 1) {
+    // total of the single block sits in sums[0]
+    k_scan_total<<<1, 64, 0, s>>>(out, n, sums);
+    BM_LAUNCH_CHECK();
+    return;
+  }
+  // scan the block totals in place into sums (exclusive, sums[nb] = grand total)
+  uint64_t* soff = rest;               // nb + 1 entries
+  uint64_t* rest2 = rest + nb + 1;
+  scan_impl(InU64{sums}, soff, nb, rest2, s);
+  k_scan_add<<<(uint32_t)nb, kThreads, 0, s>>>(out, n, soff);
+  BM_LAUNCH_CHECK();
+  k_scan_total<<<1, 64, 0, s>>>(out, n, soff + nb);
+  BM_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+size_t scan_tmp_words(uint64_t n) {
+  if (n == 0) return 2;
+  uint64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  if (nb == 1) return 2;
+  return 2 * (nb + 1) + scan_tmp_words(nb);
+}
+
+void scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s) {
+  scan_impl(InU64{in}, out, n, tmp, s);
+}
+void scan_u32_to_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s) {
+  scan_impl(InU32{in}, out, n, tmp, s);
+}
+void scan_ge_u32(const uint32_t* in, uint32_t thr, uint64_t* out, uint64_t n, uint64_t* tmp,
+                 hipStream_t s) {
+  scan_impl(InGe{in, thr}, out, n, tmp, s);
+}
+
+void launch_validate(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t nnz, uint32_t m,
+                     uint32_t* err, hipStream_t s) {
+  if (n > 0) {
+    k_validate_rows<<<grid_for(n, kThreads, 4096), kThreads, 0, s>>>(rp, n, err);
+    BM_LAUNCH_CHECK();
+  }
+  if (nnz > 0) {
+    k_validate_cols<<<grid_for(nnz, kThreads, 8192), kThreads, 0, s>>>(ci, nnz, m, err);
+    BM_LAUNCH_CHECK();
+  }
+}
+
+void launch_pack(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t* B, uint64_t Wp,
+                 hipStream_t s) {
+  if (n == 0) return;
+  const uint64_t nb = (n + kThreads - 1) / kThreads;
+  if (nb > 0x7fffffffull) fail(BM_ERR_UNSUPPORTED, "too many rows");
+  k_pack<<<(uint32_t)nb, kThreads, 0, s>>>(rp, ci, n, reinterpret_cast<unsigned long long*>(B), Wp);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_colsum(const uint64_t* B, uint64_t Wp, uint32_t m, uint32_t* colsum, hipStream_t s) {
+  if (m == 0) return;
+  k_colsum<<<(uint32_t)std::min<uint64_t>(m, 1u << 20), kThreads, 0, s>>>(B, Wp, m, colsum);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
+  if (n == 0) return;
+  k_fill<uint32_t><<<grid_for(n, kThreads, 16384), kThreads, 0, s>>>(p, v, n);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s) {
+  if (n == 0) return;
+  k_fill<uint64_t><<<grid_for(n, kThreads, 16384), kThreads, 0, s>>>(p, v, n);
+  BM_LAUNCH_CHECK();
+}
+
+}  // namespace bm

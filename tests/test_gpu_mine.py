@@ -1,0 +1,270 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer work, so the bar is bit-exact: the canonical result arrays (offsets,
+items, supports) must equal the oracle's byte for byte.  Small and mid-size
+inputs are compared with the full oracle result; the full-size dense
+workloads are checked with the certificate (every reported support recomputed
+by the oracle, downward closure, and a sample of the negative border).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import gen
+from oracle import brute, certify, pairs, sets
+from oracle import cpp as ocpp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bm():
+    import torch
+    assert torch.cuda.is_available(), "needs a GPU"
+    torch.cuda.init()
+    import paper_2412_19420_amd as bm
+    return bm
+
+
+def gpu_mine(bm, db, minsup, opts=None, device_inputs=False):
+    if device_inputs:
+        import torch
+        rp = torch.from_numpy(db.row_ptr.astype(np.uint64)).cuda()
+        ci = torch.from_numpy(db.col_idx.astype(np.uint32)).cuda() if db.col_idx.size else None
+        h = bm.bm_build(rp, ci, db.n, db.m)
+    else:
+        h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    r = bm.bm_mine_ex(h, minsup, opts) if opts is not None else bm.bm_mine(h, minsup)
+    return h, r
+
+
+def oracle_arrays(db, minsup):
+    o = ocpp.OracleDb(db.row_ptr, db.col_idx, db.n, db.m)
+    offs, items, supp, cands = o.mine_arrays(minsup)
+    return o, (offs, items, supp), cands
+
+
+def assert_same(a, b):
+    for x, y, name in zip(a, b, ("offsets", "items", "supports")):
+        x = np.asarray(x)
+        y = np.asarray(y)
+        assert x.shape == y.shape, f"{name}: shape {x.shape} vs {y.shape}"
+        assert np.array_equal(x.astype(np.int64), y.astype(np.int64)), f"{name} differ"
+
+
+# ------------------------------------------------------------ build / singletons
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 4097, 70_001])
+def test_item_support_equals_column_sums(bm, n):
+    print(f"item_support n={n}", flush=True)
+    db = gen.random_small(n, min(n, 300), 37, density=0.2, dup_rate=0.2, shuffle=True,
+                          empty_rate=0.05) if n <= 300 else gen.quest(7, n, 500, 8.0, 200, 3.0)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    got = bm.bm_item_support(h)
+    want = pairs.column_sums(db.row_ptr, db.col_idx, db.n, db.m)
+    assert np.array_equal(got.astype(np.int64), want)
+
+
+def test_build_from_device_pointers(bm):
+    db = gen.make_config(1)
+    h1 = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    h2, r2 = gpu_mine(bm, db, db.minsup, device_inputs=True)
+    assert np.array_equal(bm.bm_item_support(h1), bm.bm_item_support(h2))
+    _, want, _ = oracle_arrays(db, db.minsup)
+    assert_same(r2.arrays(), want)
+    import torch
+    offs, items, supp = r2.tensors("cuda")
+    assert_same((offs.cpu().numpy(), items.cpu().numpy(), supp.cpu().numpy()), want)
+
+
+# ------------------------------------------------------------ pair supports (Eq. 2)
+
+@pytest.mark.parametrize("n,m,k,density", [
+    (10_000, 169, None, None),      # basket workload, all items (MFMA path)
+    (5_000, 40, None, 0.3),         # few items (AND+popcount path)
+    (3_001, 300, None, 0.1),        # three MFMA tiles, ragged in both dims
+    (65, 70, None, 0.5),            # one word plus one bit
+])
+def test_pair_support_equals_gram(bm, n, m, k, density):
+    print(f"pair_support n={n} m={m}", flush=True)
+    if density is None:
+        db = gen.make_config(1)
+    else:
+        rng = np.random.default_rng(n + m)
+        rows = [list(np.nonzero(rng.random(m) < density)[0]) for _ in range(n)]
+        db = gen.from_rows(rows, m=m)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    got = bm.bm_pair_support(h)
+    want = pairs.pair_support(db.row_ptr, db.col_idx, db.n, db.m)
+    assert np.array_equal(got.astype(np.int64), want)
+
+
+def test_pair_support_item_subset_with_repeats(bm):
+    db = gen.make_config(2, scale=0.3)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    rng = np.random.default_rng(5)
+    for k in (1, 2, 17, 63, 64, 65, 200):
+        items = rng.integers(0, db.m, size=k).astype(np.uint32)
+        items[k // 2] = items[0]
+        got = bm.bm_pair_support(h, items)
+        want = pairs.pair_support(db.row_ptr, db.col_idx, db.n, db.m, cols=items)
+        assert np.array_equal(got.astype(np.int64), want), k
+
+
+# ------------------------------------------------------------ mining
+
+@pytest.mark.parametrize("seed", range(10))
+def test_mine_matches_brute_force(bm, seed):
+    rng = np.random.default_rng(1000 + seed)
+    m = int(rng.integers(1, 15))
+    n = int(rng.integers(1, 400))
+    db = gen.random_small(seed, n, m, density=float(rng.uniform(0.2, 0.8)),
+                          dup_rate=0.2 if seed % 2 else 0.0, shuffle=seed % 3 == 0,
+                          empty_rate=0.1 if seed % 4 == 0 else 0.0)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    for minsup in sorted({1, 2, max(1, n // 5), max(1, n // 2), n, n + 1}):
+        print(f"brute seed={seed} n={n} m={m} minsup={minsup}", flush=True)
+        want = brute.mine(db.row_ptr, db.col_idx, db.n, db.m, minsup)
+        for flags in (0, bm.FLAG_NO_MFMA, bm.FLAG_ALL_MFMA):
+            r = bm.bm_mine_ex(h, minsup, bm.options(flags=flags))
+            assert r.to_list() == want, (flags, minsup)
+
+
+def test_hand_example(bm):
+    from test_oracle import load_hand_example
+    db, F, C, _ = load_hand_example()
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    r = bm.bm_mine(h, db.minsup)
+    assert r.to_list() == F
+    st = r.stats()
+    assert st["candidates"] == C
+
+
+def test_mine_basket_workload_exact(bm):
+    db = gen.make_config(1)
+    want = sets.mine(db.row_ptr, db.col_idx, db.n, db.m, db.minsup)
+    _, want_arr, cands = oracle_arrays(db, db.minsup)
+    for flags in (0, bm.FLAG_NO_MFMA, bm.FLAG_ALL_MFMA):
+        h, r = gpu_mine(bm, db, db.minsup, bm.options(flags=flags))
+        assert r.to_list() == want
+        assert_same(r.arrays(), want_arr)
+        assert r.stats()["candidates_total"] == cands
+
+
+def test_mine_quest_workload_exact(bm):
+    db = gen.make_config(2)
+    print("quest 100k x 1000", flush=True)
+    _, want, cands = oracle_arrays(db, db.minsup)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    r = bm.bm_mine(h, db.minsup)
+    assert_same(r.arrays(), want)
+    assert r.stats()["candidates_total"] == cands
+    for opts in (bm.options(flags=bm.FLAG_NO_MFMA), bm.options(split_words=64, andpop_chunk_words=128),
+                 bm.options(mfma_min_children=2, split_words=128)):
+        assert_same(bm.bm_mine_ex(h, db.minsup, opts).arrays(), want)
+
+
+@pytest.mark.parametrize("minsup_scale", [0.5, 2.0])
+def test_mine_quest_other_thresholds(bm, minsup_scale):
+    db = gen.make_config(2, scale=0.2)
+    s = max(1, int(db.minsup * minsup_scale))
+    _, want, _ = oracle_arrays(db, s)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    assert_same(bm.bm_mine(h, s).arrays(), want)
+
+
+def test_mine_dense_planted_reduced_exact(bm):
+    """Dense-ish workload at reduced size: several MFMA tiles, deep levels."""
+    db = gen.dense_planted(seed=3, n=100_000, m=1024, n_patterns=60, pat_rate=0.02,
+                           minsup_ppm=10_000)
+    _, want, cands = oracle_arrays(db, db.minsup)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    r = bm.bm_mine(h, db.minsup)
+    assert_same(r.arrays(), want)
+    assert r.stats()["candidates_total"] == cands
+
+
+def _certify_full(bm, k, border_sample):
+    db = gen.make_config(k)
+    print(f"workload {k} full size: n={db.n} m={db.m} nnz={db.nnz}", flush=True)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    r = bm.bm_mine_ex(h, db.minsup, bm.options(flags=bm.FLAG_TIMING))
+    offs, items, supp = r.arrays()
+    st = r.stats()
+    print(f"mined {len(supp)} sets, {st['candidates_total']} candidates, {st['wall_ms']:.1f} ms",
+          flush=True)
+    o = ocpp.OracleDb(db.row_ptr, db.col_idx, db.n, db.m)
+    info = certify.certify(o, (offs, items, supp), db.minsup, border_sample=border_sample)
+    print("certificate", info, flush=True)
+    # level-2 border in full from the closed-form pair matrix on the GPU's own
+    # frequent items is too slow on the host; the single-item border is complete.
+    return st
+
+
+def test_mine_dense_planted_full_certified(bm):
+    st = _certify_full(bm, 3, border_sample=3000)
+    assert st["n_frequent_items"] > 2000
+
+
+def test_mine_quest_long_full_certified(bm):
+    st = _certify_full(bm, 5, border_sample=2000)
+    assert st["frequent_total"] > 10_000
+
+
+# ------------------------------------------------------------ edge cases / errors
+
+def test_empty_and_degenerate(bm):
+    cases = [gen.from_rows([], m=0), gen.from_rows([], m=7), gen.from_rows([[], []], m=3),
+             gen.from_rows([[0, 1, 2]], m=3), gen.from_rows([[5, 5, 5]], m=6)]
+    for db in cases:
+        h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+        for s in (1, 2):
+            want = sets.mine(db.row_ptr, db.col_idx, db.n, db.m, s)
+            assert bm.bm_mine(h, s).to_list() == want
+    db = gen.make_config(1)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    assert len(bm.bm_mine(h, db.n + 1)) == 0
+    # minsup = n: the subsets of the intersection of all rows (here empty)
+    assert len(bm.bm_mine(h, db.n)) == 0
+
+
+def test_errors(bm):
+    db = gen.make_config(1)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    with pytest.raises(bm.BmError) as e:
+        bm.bm_mine(h, 0)
+    assert e.value.name == "BM_ERR_INVALID_ARG"
+    bad = db.col_idx.copy()
+    bad[17] = db.m
+    with pytest.raises(bm.BmError) as e:
+        bm.bm_build(db.row_ptr, bad, db.n, db.m)
+    assert e.value.name == "BM_ERR_CSR"
+    rp = db.row_ptr.copy()
+    rp[6] = rp[5] - 1
+    with pytest.raises(bm.BmError) as e:
+        bm.bm_build(rp, db.col_idx, db.n, db.m)
+    assert e.value.name == "BM_ERR_CSR"
+    rp = db.row_ptr.copy()
+    rp[0] = 1
+    with pytest.raises(bm.BmError):
+        bm.bm_build(rp, db.col_idx, db.n, db.m)
+    with pytest.raises(bm.BmError) as e:
+        bm.bm_pair_support(h, np.array([0, db.m], dtype=np.uint32))
+    assert e.value.name == "BM_ERR_INVALID_ARG"
+    with pytest.raises(bm.BmError) as e:
+        bm.bm_mine_ex(h, 100, bm.options(andpop_chunk_words=100))
+    assert e.value.name == "BM_ERR_INVALID_ARG"
+    # the library still works after errors
+    _, want, _ = oracle_arrays(db, db.minsup)
+    assert_same(bm.bm_mine(h, db.minsup).arrays(), want)
+
+
+def test_repeated_calls_reuse_pool(bm):
+    db = gen.make_config(2, scale=0.1)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    first = bm.bm_mine(h, db.minsup).arrays()
+    for _ in range(5):
+        assert_same(bm.bm_mine(h, db.minsup).arrays(), first)
+    bm.bm_release_cached_memory()
+    assert_same(bm.bm_mine(h, db.minsup).arrays(), first)
