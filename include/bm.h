@@ -64,10 +64,11 @@ enum {
   BM_K_BUILD = 0,     /* CSR validation + packing of column bitsets */
   BM_K_COLSUM = 1,    /* column popcount: single-item supports */
   BM_K_GRAM_MFMA = 2, /* int8-MFMA (masked) Gram matrix: pair supports of a class */
-  BM_K_ANDPOP = 3,    /* AND + popcount of a prefix class's columns (VALU) */
-  BM_K_LEVEL = 4,     /* candidate/level bookkeeping: thresholds, scans, compaction */
-  BM_K_EMIT = 5,      /* canonical-order output */
-  BM_K_COUNT = 6
+  BM_K_ANDPOP = 3,    /* AND + popcount of a prefix class's columns, LDS-blocked (VALU) */
+  BM_K_ANDPOP_REG = 4,/* AND + popcount of a small prefix class held in registers (VALU) */
+  BM_K_LEVEL = 5,     /* candidate/level bookkeeping: thresholds, scans, compaction */
+  BM_K_EMIT = 6,      /* canonical-order output */
+  BM_K_COUNT = 7
 };
 
 /* Statistics of one mining call.  Kernel times are filled only when the call
@@ -82,7 +83,7 @@ typedef struct {
   uint64_t frequent[BM_MAX_LEVELS + 1];        /* [k]: frequent length-k sets */
   uint64_t candidates_total;                   /* sum over k >= 2 of candidates[k] */
   uint64_t frequent_total;
-  uint64_t classes_mfma, classes_andpop;       /* prefix classes sent to each kernel */
+  uint64_t classes_mfma, classes_andpop;       /* prefix classes sent to MFMA / to AND+popcount */
   double kernel_ms[BM_K_COUNT];
   uint64_t kernel_launches[BM_K_COUNT];
   double kernel_bytes[BM_K_COUNT];

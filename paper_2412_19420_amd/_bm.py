@@ -22,7 +22,7 @@ if not os.path.exists(LIB_PATH):
 lib = ctypes.CDLL(LIB_PATH)
 
 BM_MAX_LEVELS = 64
-BM_K_NAMES = ["build", "colsum", "gram_mfma", "andpop", "level", "emit"]
+BM_K_NAMES = ["build", "colsum", "gram_mfma", "andpop", "andpop_reg", "level", "emit"]
 BM_K_COUNT = len(BM_K_NAMES)
 
 FLAG_TIMING = 1

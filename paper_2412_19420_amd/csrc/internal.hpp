@@ -115,6 +115,7 @@ __host__ __device__ inline uint64_t tri_index(uint64_t i, uint64_t l, uint64_t q
 constexpr int GRAM_TILE = 128;  // MFMA kernel output tile (children per block)
 constexpr int GRAM_KW = 16;     // MFMA kernel words per LDS stage
 constexpr int AP_BLOCK = 16;    // AND+popcount kernel children per block
+constexpr int TINY_Q = 8;       // classes up to this many children use the register kernel
 
 // Arguments shared by both class kernels.
 struct ClassArgs {
@@ -161,6 +162,10 @@ void launch_validate(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_
 void launch_pack(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t* B, uint64_t Wp,
                  hipStream_t s);
 void launch_colsum(const uint64_t* B, uint64_t Wp, uint32_t m, uint32_t* colsum, hipStream_t s);
+// Tiled build of M and its column sums in one pass (colsum and err must be
+// zeroed); returns false when the shape needs the atomic path (m > 16384).
+bool launch_pack_tiled(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t nnz, uint32_t m,
+                       uint64_t* B, uint64_t Wp, uint32_t* colsum, uint32_t* err, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
 
@@ -168,6 +173,20 @@ void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
 size_t scan_tmp_words(uint64_t n);
 void scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s);
 void scan_u32_to_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s);
+// Up to 8 arrays of the same length n <= kSingleMaxN scanned by one launch
+// (false when n is too large: use the per-array scans).
+struct ScanMulti {
+  const void* in[8];
+  uint32_t is64[8];
+  uint64_t* out[8];
+};
+constexpr uint64_t kSingleMaxN = 1ull << 18;
+// dst[i] = *src[i] for i < count (count <= 32): one small D2H copy instead of many.
+struct GatherU64 {
+  const uint64_t* src[32];
+};
+void launch_gather_u64(const GatherU64& g, int count, uint64_t* dst, hipStream_t s);
+bool scan_multi_single(const ScanMulti& sm, int count, uint64_t n, hipStream_t s);
 // out[0..n]: exclusive scan of (in[i] >= thr)
 void scan_ge_u32(const uint32_t* in, uint32_t thr, uint64_t* out, uint64_t n, uint64_t* tmp,
                  hipStream_t s);
@@ -175,5 +194,6 @@ void scan_ge_u32(const uint32_t* in, uint32_t thr, uint64_t* out, uint64_t n, ui
 // class kernels
 void launch_gram_mfma(const ClassArgs& a, uint32_t grid, hipStream_t s);
 void launch_andpop(const ClassArgs& a, uint32_t chunk_words, uint32_t grid, hipStream_t s);
+void launch_andpop_reg(const ClassArgs& a, uint32_t grid, hipStream_t s);
 
 }  // namespace bm

@@ -131,7 +131,88 @@ __global__ __launch_bounds__(256) void k_andpop(ClassArgs a) {
   }
 }
 
+// Classes with at most TINY_Q children: no LDS staging.  Each thread streams
+// two consecutive words of the prefix and of every child column with 16-byte
+// loads, ANDs them in registers and keeps one popcount accumulator per child
+// pair; the accumulators are reduced across the wavefront with shuffles and
+// across the workgroup through LDS once per task.
+constexpr int TQ = TINY_Q;
+constexpr int TNP = TQ * (TQ - 1) / 2;
+
+__global__ __launch_bounds__(256) void k_andpop_reg(ClassArgs a) {
+  __shared__ uint32_t s_red[4][TNP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (uint32_t t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+    const Task task = a.tasks[t];
+    const ClassDesc cd = a.cls[task.cls];
+    const int q = (int)cd.q;
+    const uint64_t* col[TQ];
+#pragma unroll
+    for (int i = 0; i < TQ; ++i) {
+      col[i] = a.B;
+      if (i < q) {
+        const uint32_t item = a.child_item[cd.child0 + i];
+        col[i] = a.B + (uint64_t)(a.f1 ? a.f1[item] : item) * a.Wp;
+      }
+    }
+    const uint32_t* pre = a.pre_cols + cd.pre_off;
+    const uint32_t pre_len = cd.pre_len;
+    uint32_t acc[TNP];
+#pragma unroll
+    for (int p = 0; p < TNP; ++p) acc[p] = 0;
+    for (uint32_t w = task.w0 + 2 * tid; w < task.w1; w += 512) {
+      uint64_t m0 = ~0ull, m1 = (w + 1 < task.w1) ? ~0ull : 0ull;
+      for (uint32_t j = 0; j < pre_len; ++j) {
+        const uint4 x = *reinterpret_cast<const uint4*>(a.B + (uint64_t)pre[j] * a.Wp + w);
+        m0 &= (uint64_t)x.x | ((uint64_t)x.y << 32);
+        m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
+      }
+      uint64_t x0[TQ], x1[TQ];
+#pragma unroll
+      for (int i = 0; i < TQ; ++i) {
+        x0[i] = 0;
+        x1[i] = 0;
+        if (i < q) {
+          const uint4 v = *reinterpret_cast<const uint4*>(col[i] + w);
+          x0[i] = ((uint64_t)v.x | ((uint64_t)v.y << 32)) & m0;
+          x1[i] = ((uint64_t)v.z | ((uint64_t)v.w << 32)) & m1;
+        }
+      }
+      int p = 0;
+#pragma unroll
+      for (int i = 0; i < TQ; ++i)
+#pragma unroll
+        for (int l = i + 1; l < TQ; ++l, ++p)
+          if (l < q) acc[p] += (uint32_t)(__popcll(x0[i] & x0[l]) + __popcll(x1[i] & x1[l]));
+    }
+#pragma unroll
+    for (int p = 0; p < TNP; ++p) {
+      uint32_t v = acc[p];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) s_red[wave][p] = v;
+    }
+    __syncthreads();
+    if (tid < TNP) {
+      int i = 0, r = tid;
+      while (r >= TQ - 1 - i) {
+        r -= TQ - 1 - i;
+        ++i;
+      }
+      const int l = i + 1 + r;
+      const uint32_t v = s_red[0][tid] + s_red[1][tid] + s_red[2][tid] + s_red[3][tid];
+      if (l < q && v) atomicAdd(a.tri + cd.tri_off + tri_index(i, l, q), v);
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
+
+void launch_andpop_reg(const ClassArgs& a, uint32_t grid, hipStream_t s) {
+  if (a.ntasks == 0) return;
+  k_andpop_reg<<<grid, 256, 0, s>>>(a);
+  BM_LAUNCH_CHECK();
+}
 
 void launch_andpop(const ClassArgs& a, uint32_t chunk_words, uint32_t grid, hipStream_t s) {
   if (a.ntasks == 0) return;

@@ -58,6 +58,133 @@ __global__ __launch_bounds__(kThreads) void k_pack(const uint64_t* __restrict__ 
   }
 }
 
+// Tiled construction: one workgroup builds a 512-row block of M (8 words per
+// column), one 512-column window at a time in LDS, and writes each window out
+// as 64-byte column segments.  Every word of M is written exactly once (zeros
+// included), so no clearing pass is needed, and each window's column popcounts
+// are added to the single-item supports on the way out.
+//   * the block's item ids are loaded once, coalesced and several per thread in
+//     flight, into LDS as packed (column << 9 | local row) entries -- the row is
+//     filled in row by row -- and every column window is then replayed from LDS;
+//   * bits are set with LDS atomic ORs (idempotent: duplicate ids collapse, as
+//     M is 0/1); ids >= m are flagged;
+//   * element ranges are clamped to [0, nnz] and local rows are masked, so a
+//     malformed row_ptr (flagged by the row validation kernel) cannot send any
+//     access out of bounds.
+constexpr int PK_KR = 8;                  // words per column per tile
+constexpr int PK_ROWS = PK_KR * 64;       // 512 rows
+constexpr int PK_RBITS = 9;               // bits of a local row
+constexpr int PK_CW = 512;                // columns per window
+constexpr int PK_LD = PK_KR + 1;          // padded LDS row (conflict-free OR)
+constexpr int PK_ECAP = 20480;            // staged elements per chunk (80 KB)
+constexpr int PK_UNROLL = 8;
+
+__global__ __launch_bounds__(kThreads) void k_pack_tiled(
+    const uint64_t* __restrict__ rp, const uint32_t* __restrict__ ci, uint64_t n, uint64_t nnz,
+    uint32_t m, unsigned long long* __restrict__ B, uint64_t Wp, uint32_t* __restrict__ colsum,
+    uint32_t* __restrict__ err) {
+  __shared__ unsigned long long X[PK_CW * PK_LD];
+  __shared__ uint32_t s_e[PK_ECAP];
+  __shared__ uint64_t s_rp[PK_ROWS + 1];
+  const int tid = threadIdx.x;
+  const uint64_t blk = blockIdx.x;
+  const uint64_t r0 = blk * PK_ROWS;
+  const int nr = (int)(r0 < n ? min<uint64_t>(PK_ROWS, n - r0) : 0);
+  if (nr == 0) {
+    if (tid == 0) s_rp[0] = 0;
+  } else {
+    for (int t = tid; t <= nr; t += kThreads) s_rp[t] = min(rp[r0 + t], nnz);
+  }
+  __syncthreads();
+  const uint64_t e0 = s_rp[0];
+  const uint64_t e1 = max(e0, s_rp[nr]);
+  const uint32_t nwin = (m + PK_CW - 1) / PK_CW;
+  uint32_t bad = 0;
+  const bool single_chunk = e1 - e0 <= PK_ECAP;
+  for (uint64_t ea = e0; ea < e1 || (ea == e0 && e0 == e1); ea += PK_ECAP) {
+    const uint64_t eb = min<uint64_t>(e1, ea + PK_ECAP);
+    const int ne = (int)(eb - ea);
+    __syncthreads();  // previous chunk fully consumed
+    for (int base = 0; base < ne; base += kThreads * PK_UNROLL) {
+      uint32_t v[PK_UNROLL];
+#pragma unroll
+      for (int u = 0; u < PK_UNROLL; ++u) {
+        const int k = base + u * kThreads + tid;
+        v[u] = k < ne ? ci[ea + k] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < PK_UNROLL; ++u) {
+        const int k = base + u * kThreads + tid;
+        if (k < ne) {
+          if (v[u] >= m) bad |= 2u;
+          s_e[k] = v[u] < m ? (v[u] << PK_RBITS) : 0xffffffffu;
+        }
+      }
+    }
+    __syncthreads();
+    for (int r = tid; r < nr; r += kThreads) {
+      const uint64_t a = max(s_rp[r], ea), b = max(a, min(s_rp[r + 1], eb));
+      uint64_t e = a;
+      for (; e + 4 <= b; e += 4) {  // four independent LDS round trips at a time
+        const uint32_t x0 = s_e[e - ea], x1 = s_e[e - ea + 1], x2 = s_e[e - ea + 2],
+                       x3 = s_e[e - ea + 3];
+        s_e[e - ea] = x0 | (uint32_t)r;
+        s_e[e - ea + 1] = x1 | (uint32_t)r;
+        s_e[e - ea + 2] = x2 | (uint32_t)r;
+        s_e[e - ea + 3] = x3 | (uint32_t)r;
+      }
+      for (; e < b; ++e) s_e[e - ea] |= (uint32_t)r;
+    }
+    for (uint32_t win = 0; win < nwin; ++win) {
+      const uint32_t c0 = win * PK_CW;
+      const uint32_t cw = min<uint32_t>(PK_CW, m - c0);
+      if (single_chunk || ea == e0) {
+        for (int i = tid; i < PK_CW * PK_LD; i += kThreads) X[i] = 0ull;
+      }
+      __syncthreads();
+      if (!single_chunk && ea != e0) {
+        // several chunks: accumulate this window on top of what B already holds
+        const int wi = tid & (PK_KR - 1), cs = tid / PK_KR;
+        for (uint32_t c = cs; c < cw; c += kThreads / PK_KR)
+          X[c * PK_LD + wi] = B[(uint64_t)(c0 + c) * Wp + blk * PK_KR + wi];
+        __syncthreads();
+      }
+      for (int k0 = 0; k0 < ne; k0 += 4 * kThreads) {
+        uint32_t x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + u * kThreads + tid;
+          x[u] = k < ne ? s_e[k] : 0xffffffffu;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (x[u] == 0xffffffffu) continue;
+          const uint32_t d = (x[u] >> PK_RBITS) - c0;
+          if (d < cw) {
+            const int lr = x[u] & (PK_ROWS - 1);
+            atomicOr(X + d * PK_LD + (lr >> 6), 1ull << (lr & 63));
+          }
+        }
+      }
+      __syncthreads();
+      const bool last = eb == e1;
+      const int wi = tid & (PK_KR - 1), cs = tid / PK_KR;
+      for (uint32_t c = cs; c < cw; c += kThreads / PK_KR) {
+        const unsigned long long v = X[c * PK_LD + wi];
+        B[(uint64_t)(c0 + c) * Wp + blk * PK_KR + wi] = v;
+        if (last) {
+          uint32_t pc = (uint32_t)__popcll(v);
+          for (int off = PK_KR / 2; off > 0; off >>= 1) pc += __shfl_xor(pc, off);
+          if (wi == 0 && pc) atomicAdd(colsum + c0 + c, pc);
+        }
+      }
+      __syncthreads();
+    }
+    if (e0 == e1) break;
+  }
+  if (bad) atomicOr(err, bad);
+}
+
 // Support of each single item: popcount of its column, one workgroup per column.
 __global__ __launch_bounds__(kThreads) void k_colsum(const uint64_t* __restrict__ B, uint64_t Wp,
                                                      uint32_t m, uint32_t* __restrict__ out) {
@@ -196,13 +323,79 @@ void scan_impl(In in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s) {
   BM_LAUNCH_CHECK();
 }
 
+// Single-workgroup looped scan of up to 8 arrays at once (one workgroup per
+// array): for the per-node arrays of a level step, one launch replaces three
+// launches per array.
+constexpr int kSingleThreads = 1024;
+constexpr int kSingleChunk = kSingleThreads * kScanPer;
+
+__global__ __launch_bounds__(kSingleThreads) void k_scan_single(ScanMulti sm, uint64_t n) {
+  __shared__ uint64_t s_wave[kSingleThreads / 64];
+  const int a = blockIdx.x;
+  const void* in = sm.in[a];
+  const bool is64 = sm.is64[a] != 0;
+  uint64_t* out = sm.out[a];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t base = 0;
+  for (uint64_t c0 = 0; c0 < n; c0 += kSingleChunk) {
+    const uint64_t i0 = c0 + (uint64_t)threadIdx.x * kScanPer;
+    uint64_t v[kScanPer];
+    uint64_t t = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      const uint64_t i = i0 + k;
+      v[k] = i < n ? (is64 ? static_cast<const uint64_t*>(in)[i] : static_cast<const uint32_t*>(in)[i])
+                   : 0ull;
+      t += v[k];
+    }
+    uint64_t inc = t;
+    for (int off = 1; off < 64; off <<= 1) {
+      uint64_t y = __shfl_up(inc, off);
+      if (lane >= off) inc += y;
+    }
+    if (lane == 63) s_wave[wave] = inc;
+    __syncthreads();
+    uint64_t wb = 0, tot = 0;
+    for (int k = 0; k < kSingleThreads / 64; ++k) {
+      if (k < wave) wb += s_wave[k];
+      tot += s_wave[k];
+    }
+    uint64_t ex = base + wb + inc - t;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      if (i0 + k < n) out[i0 + k] = ex;
+      ex += v[k];
+    }
+    base += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[n] = base;
+}
+
+__global__ void k_gather_u64(GatherU64 g, int count, uint64_t* __restrict__ dst) {
+  const int i = threadIdx.x;
+  if (i < count) dst[i] = *g.src[i];
+}
+
 }  // namespace
+
+void launch_gather_u64(const GatherU64& g, int count, uint64_t* dst, hipStream_t s) {
+  k_gather_u64<<<1, 64, 0, s>>>(g, count, dst);
+  BM_LAUNCH_CHECK();
+}
 
 size_t scan_tmp_words(uint64_t n) {
   if (n == 0) return 2;
   uint64_t nb = (n + kScanBlock - 1) / kScanBlock;
   if (nb == 1) return 2;
   return 2 * (nb + 1) + scan_tmp_words(nb);
+}
+
+bool scan_multi_single(const ScanMulti& sm, int count, uint64_t n, hipStream_t s) {
+  if (n > kSingleMaxN || count < 1 || count > 8) return false;
+  k_scan_single<<<count, kSingleThreads, 0, s>>>(sm, n);
+  BM_LAUNCH_CHECK();
+  return true;
 }
 
 void scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s) {
@@ -235,6 +428,17 @@ void launch_pack(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t* B
   if (nb > 0x7fffffffull) fail(BM_ERR_UNSUPPORTED, "too many rows");
   k_pack<<<(uint32_t)nb, kThreads, 0, s>>>(rp, ci, n, reinterpret_cast<unsigned long long*>(B), Wp);
   BM_LAUNCH_CHECK();
+}
+
+bool launch_pack_tiled(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t nnz, uint32_t m,
+                       uint64_t* B, uint64_t Wp, uint32_t* colsum, uint32_t* err, hipStream_t s) {
+  const uint64_t windows = (m + PK_CW - 1) / PK_CW;
+  if (m == 0 || windows > 32 || Wp % PK_KR || ((uint64_t)m << PK_RBITS) >= 0xffffffffull) return false;
+  dim3 grid((uint32_t)(Wp / PK_KR));
+  k_pack_tiled<<<grid, kThreads, 0, s>>>(rp, ci, n, nnz, m, reinterpret_cast<unsigned long long*>(B),
+                                         Wp, colsum, err);
+  BM_LAUNCH_CHECK();
+  return true;
 }
 
 void launch_colsum(const uint64_t* B, uint64_t Wp, uint32_t m, uint32_t* colsum, hipStream_t s) {

@@ -63,11 +63,14 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
     uint64_t n, uint32_t k, const uint32_t* __restrict__ parent, const int32_t* __restrict__ pcls,
     const ClassDesc* __restrict__ cls, const uint64_t* __restrict__ S, uint32_t mfma_min_q,
     uint32_t* __restrict__ cnt, uint32_t* __restrict__ is_cls, uint64_t* __restrict__ tri_sz,
-    uint32_t* __restrict__ pm, uint32_t* __restrict__ pv, unsigned long long* __restrict__ st) {
+    uint32_t* __restrict__ pm, uint32_t* __restrict__ pv, uint32_t* __restrict__ pt,
+    unsigned long long* __restrict__ st) {
   __shared__ unsigned long long s_st[ST_COUNT];
   if (threadIdx.x < ST_COUNT) s_st[threadIdx.x] = 0;
   __syncthreads();
-  unsigned long long loc[ST_COUNT] = {0, 0, 0, 0, 0, 0};
+  unsigned long long loc[ST_COUNT];
+#pragma unroll
+  for (int j = 0; j < ST_COUNT; ++j) loc[j] = 0;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const int32_t c = pcls[parent[i]];
@@ -83,16 +86,17 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
     }
     cnt[i] = kc;
     const bool cl = kc >= 2;
-    const bool mf = cl && kc >= mfma_min_q;
+    const int kind = cl ? class_kind(kc, mfma_min_q) : -1;
     const uint64_t tsz = cl ? (uint64_t)kc * (kc - 1) / 2 : 0ull;
     is_cls[i] = cl ? 1u : 0u;
     tri_sz[i] = tsz;
-    pm[i] = mf ? mfma_pairs(kc) : 0u;
-    pv[i] = (cl && !mf) ? andpop_pairs(kc) : 0u;
+    pm[i] = kind == 0 ? mfma_pairs(kc) : 0u;
+    pv[i] = kind == 1 ? andpop_pairs(kc) : 0u;
+    pt[i] = kind == 2 ? 1u : 0u;
     if (cl) {
-      loc[mf ? ST_CAND_M : ST_CAND_V] += tsz;
-      loc[mf ? ST_COLS_M : ST_COLS_V] += kc + k;
-      loc[mf ? ST_CLS_M : ST_CLS_V] += 1;
+      loc[ST_CAND_M + kind] += tsz;
+      loc[ST_COLS_M + kind] += kc + k;
+      loc[ST_CLS_M + kind] += 1;
     }
   }
   for (int j = 0; j < ST_COUNT; ++j)
@@ -163,10 +167,11 @@ __global__ void k_fill_classes(uint64_t n, uint32_t k, const uint32_t* __restric
                                const uint64_t* __restrict__ cls_pos,
                                const uint64_t* __restrict__ tri_off,
                                const uint64_t* __restrict__ pm_off, const uint64_t* __restrict__ pv_off,
-                               uint32_t mfma_min_q, LevelPtrs lv, const uint32_t* __restrict__ f1,
-                               ClassDesc* __restrict__ ocls, uint32_t* __restrict__ opre,
-                               int32_t* __restrict__ pcls_out, TaskGeom geo,
-                               Task* __restrict__ tm, Task* __restrict__ tv) {
+                               const uint64_t* __restrict__ pt_off, uint32_t mfma_min_q, LevelPtrs lv,
+                               const uint32_t* __restrict__ f1, ClassDesc* __restrict__ ocls,
+                               uint32_t* __restrict__ opre, int32_t* __restrict__ pcls_out,
+                               TaskGeom geo, Task* __restrict__ tm, Task* __restrict__ tv,
+                               Task* __restrict__ tt) {
   const int lane = threadIdx.x & 63;
   const uint64_t wave0 = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
@@ -192,14 +197,18 @@ __global__ void k_fill_classes(uint64_t n, uint32_t k, const uint32_t* __restric
         x = lv.parent[lev][x];
       }
     }
-    if (q >= mfma_min_q) {
+    const int kind = class_kind(q, mfma_min_q);
+    if (kind == 0) {
       const uint32_t np = (uint32_t)(pm_off[i + 1] - pm_off[i]);
       write_tasks(ci, q, np, GRAM_TILE, geo.nsplit_m, geo.split_m, geo.wend_m,
                   tm + pm_off[i] * geo.nsplit_m, lane, 64);
-    } else {
+    } else if (kind == 1) {
       const uint32_t np = (uint32_t)(pv_off[i + 1] - pv_off[i]);
       write_tasks(ci, q, np, AP_BLOCK, geo.nsplit_v, geo.split_v, geo.wend_v,
                   tv + pv_off[i] * geo.nsplit_v, lane, 64);
+    } else {
+      write_tasks(ci, q, 1, TINY_Q, geo.nsplit_t, geo.split_t, geo.wend_t,
+                  tt + pt_off[i] * geo.nsplit_t, lane, 64);
     }
   }
 }
@@ -299,11 +308,11 @@ void launch_init_level1(const uint32_t* colsum, const uint32_t* f1, uint32_t n1,
 void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const int32_t* pcls,
                         const ClassDesc* cls, const uint64_t* S, uint32_t mfma_min_q,
                         uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz, uint32_t* pm,
-                        uint32_t* pv, unsigned long long* st, hipStream_t s) {
+                        uint32_t* pv, uint32_t* pt, unsigned long long* st, hipStream_t s) {
   if (n == 0) return;
   k_node_counts<<<grid_for(n, kThreads, 2048), kThreads, 0, s>>>(n, k, parent, pcls, cls, S,
                                                                   mfma_min_q, cnt, is_cls, tri_sz,
-                                                                  pm, pv, st);
+                                                                  pm, pv, pt, st);
   BM_LAUNCH_CHECK();
 }
 
@@ -319,13 +328,14 @@ void launch_fill_level(uint64_t n, const uint32_t* parent, const int32_t* pcls,
 
 void launch_fill_classes(uint64_t n, uint32_t k, const uint32_t* cnt, const uint64_t* child_start,
                          const uint64_t* cls_pos, const uint64_t* tri_off, const uint64_t* pm_off,
-                         const uint64_t* pv_off, uint32_t mfma_min_q, const LevelPtrs& lv,
-                         const uint32_t* f1, ClassDesc* ocls, uint32_t* opre, int32_t* pcls_out,
-                         const TaskGeom& geo, Task* tm, Task* tv, hipStream_t s) {
+                         const uint64_t* pv_off, const uint64_t* pt_off, uint32_t mfma_min_q,
+                         const LevelPtrs& lv, const uint32_t* f1, ClassDesc* ocls, uint32_t* opre,
+                         int32_t* pcls_out, const TaskGeom& geo, Task* tm, Task* tv, Task* tt,
+                         hipStream_t s) {
   if (n == 0) return;
   k_fill_classes<<<grid_for(n * 64, kThreads), kThreads, 0, s>>>(
-      n, k, cnt, child_start, cls_pos, tri_off, pm_off, pv_off, mfma_min_q, lv, f1, ocls, opre,
-      pcls_out, geo, tm, tv);
+      n, k, cnt, child_start, cls_pos, tri_off, pm_off, pv_off, pt_off, mfma_min_q, lv, f1, ocls,
+      opre, pcls_out, geo, tm, tv, tt);
   BM_LAUNCH_CHECK();
 }
 

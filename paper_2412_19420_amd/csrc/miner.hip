@@ -88,7 +88,8 @@ void scan64(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s) {
 uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 uint64_t round_up(uint64_t a, uint64_t b) { return ceil_div(a, b) * b; }
 
-TaskGeom make_geom(uint64_t W, uint64_t pairs_m, uint64_t pairs_v, const Tuning& tu) {
+TaskGeom make_geom(uint64_t W, uint64_t pairs_m, uint64_t pairs_v, uint64_t classes_t,
+                   const Tuning& tu) {
   const uint64_t target = (uint64_t)cu_count() * 8;
   TaskGeom g{};
   const uint64_t Wm = std::max<uint64_t>(16, round_up(W, GRAM_KW));
@@ -115,6 +116,17 @@ TaskGeom make_geom(uint64_t W, uint64_t pairs_m, uint64_t pairs_v, const Tuning&
   g.split_v = (uint32_t)sv;
   g.nsplit_v = (uint32_t)ceil_div(Wv, sv);
   g.wend_v = (uint32_t)Wv;
+  uint64_t st;
+  if (tu.split_words) {
+    st = tu.split_words;
+  } else {
+    uint64_t ns = classes_t ? ceil_div(target, classes_t) : 1;
+    ns = std::min<uint64_t>(ns, std::max<uint64_t>(1, Wv / 2048));
+    st = round_up(ceil_div(Wv, ns), 64);
+  }
+  g.split_t = (uint32_t)st;
+  g.nsplit_t = (uint32_t)ceil_div(Wv, st);
+  g.wend_t = (uint32_t)Wv;
   return g;
 }
 
@@ -122,11 +134,11 @@ TaskGeom make_geom(uint64_t W, uint64_t pairs_m, uint64_t pairs_v, const Tuning&
 struct StepWork {
   TBuf<ClassDesc> cls;
   TBuf<uint32_t> pre;
-  TBuf<Task> tm, tv;
-  uint64_t ntm = 0, ntv = 0;
+  TBuf<Task> tm, tv, tt;
+  uint64_t ntm = 0, ntv = 0, ntt = 0;
   TBuf<uint32_t> tri;
   uint64_t T = 0;
-  uint64_t st[ST_COUNT] = {0, 0, 0, 0, 0, 0};
+  uint64_t st[ST_COUNT] = {};
 };
 
 void run_class_kernels(const bm_db* db, const uint32_t* f1, const uint32_t* child_item,
@@ -150,6 +162,14 @@ void run_class_kernels(const bm_db* db, const uint32_t* f1, const uint32_t* chil
     launch_andpop(a, tu.andpop_chunk, (uint32_t)std::min<uint64_t>(w.ntv, ncu * 8), s);
     tm.end(8.0 * (double)db->W * (double)w.st[ST_COLS_V], (double)w.st[ST_CAND_V] * (double)db->W);
   }
+  if (w.ntt) {
+    if (w.ntt > 0xffffffffull) fail(BM_ERR_UNSUPPORTED, "too many AND+popcount tasks");
+    a.tasks = w.tt.get();
+    a.ntasks = (uint32_t)w.ntt;
+    tm.begin(BM_K_ANDPOP_REG);
+    launch_andpop_reg(a, (uint32_t)std::min<uint64_t>(w.ntt, ncu * 8), s);
+    tm.end(8.0 * (double)db->W * (double)w.st[ST_COLS_T], (double)w.st[ST_CAND_T] * (double)db->W);
+  }
 }
 
 // One class (the root, or an explicit column list) with q children.
@@ -162,24 +182,26 @@ void single_class(StepWork& w, uint32_t q, uint64_t W, const Tuning& tu, hipStre
   w.T = (uint64_t)q * (q - 1) / 2;
   w.tri.alloc(w.T, s);
   launch_fill_u32(w.tri.get(), 0, w.T, s);
-  const bool mf = q >= tu.mfma_min_q;
-  const uint64_t pm = mf ? host_mfma_pairs(q) : 0, pv = mf ? 0 : host_andpop_pairs(q);
-  const TaskGeom g = make_geom(W, pm, pv, tu);
-  if (mf) {
+  const int kind = class_kind(q, tu.mfma_min_q);
+  const uint64_t pm = kind == 0 ? host_mfma_pairs(q) : 0;
+  const uint64_t pv = kind == 1 ? host_andpop_pairs(q) : 0;
+  const TaskGeom g = make_geom(W, pm, pv, kind == 2 ? 1 : 0, tu);
+  if (kind == 0) {
     w.ntm = pm * g.nsplit_m;
     w.tm.alloc(w.ntm, s);
     launch_root_tasks(q, (uint32_t)pm, GRAM_TILE, g.nsplit_m, g.split_m, g.wend_m, w.tm.get(), s);
-    w.st[ST_CAND_M] = w.T;
-    w.st[ST_COLS_M] = q;
-    w.st[ST_CLS_M] = 1;
-  } else {
+  } else if (kind == 1) {
     w.ntv = pv * g.nsplit_v;
     w.tv.alloc(w.ntv, s);
     launch_root_tasks(q, (uint32_t)pv, AP_BLOCK, g.nsplit_v, g.split_v, g.wend_v, w.tv.get(), s);
-    w.st[ST_CAND_V] = w.T;
-    w.st[ST_COLS_V] = q;
-    w.st[ST_CLS_V] = 1;
+  } else {
+    w.ntt = g.nsplit_t;
+    w.tt.alloc(w.ntt, s);
+    launch_root_tasks(q, 1, TINY_Q, g.nsplit_t, g.split_t, g.wend_t, w.tt.get(), s);
   }
+  w.st[ST_CAND_M + kind] = w.T;
+  w.st[ST_COLS_M + kind] = q;
+  w.st[ST_CLS_M + kind] = 1;
   // hipMemcpyAsync from pageable memory may still read `cd` after returning
   BM_HIP(hipStreamSynchronize(s));
 }
@@ -258,18 +280,29 @@ bm_db* build_db(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n, ui
   }
   TBuf<uint32_t> err(1, s);
   launch_fill_u32(err.get(), 0, 1, s);
-  launch_validate(d_rp, d_ci, n, nnz, m, err.get(), s);
-  const uint32_t e = read_back(err.get(), s);
-  if (e & 1u) fail(BM_ERR_CSR, "row_ptr is not non-decreasing");
-  if (e & 2u) fail(BM_ERR_CSR, "an item id is >= n_items (%u)", m);
-
   db->B.reset((size_t)m * db->Wp, s);
   db->colsum.reset(m, s);
   if (m > 0) {
-    launch_fill_u64(db->B.get(), 0, (uint64_t)m * db->Wp, s);
-    launch_pack(d_rp, d_ci, n, db->B.get(), db->Wp, s);
-    launch_colsum(db->B.get(), db->Wp, m, db->colsum.get(), s);
+    launch_fill_u32(db->colsum.get(), 0, m, s);
+    // row_ptr monotonicity first (flag only); the tiled pack clamps element
+    // ranges, flags ids >= m and writes every word of M.
+    launch_validate(d_rp, nullptr, n, 0, m, err.get(), s);
+    if (!launch_pack_tiled(d_rp, d_ci, n, nnz, m, db->B.get(), db->Wp, db->colsum.get(), err.get(),
+                           s)) {
+      launch_validate(d_rp, d_ci, n, nnz, m, err.get(), s);
+      const uint32_t e0 = read_back(err.get(), s);
+      if (e0 & 1u) fail(BM_ERR_CSR, "row_ptr is not non-decreasing");
+      if (e0 & 2u) fail(BM_ERR_CSR, "an item id is >= n_items (%u)", m);
+      launch_fill_u64(db->B.get(), 0, (uint64_t)m * db->Wp, s);
+      launch_pack(d_rp, d_ci, n, db->B.get(), db->Wp, s);
+      launch_colsum(db->B.get(), db->Wp, m, db->colsum.get(), s);
+    }
+  } else {
+    launch_validate(d_rp, d_ci, n, nnz, m, err.get(), s);
   }
+  const uint32_t e = read_back(err.get(), s);
+  if (e & 1u) fail(BM_ERR_CSR, "row_ptr is not non-decreasing");
+  if (e & 2u) fail(BM_ERR_CSR, "an item id is >= n_items (%u)", m);
   BM_HIP(hipStreamSynchronize(s));
   return db.release();
 }
@@ -372,37 +405,50 @@ bm_result* mine(const bm_db* db, uint32_t minsup, const bm_options* opt, hipStre
         st.candidates[k + 1] = w->T;
         st.candidates_total += w->T;
         st.classes_mfma += w->st[ST_CLS_M];
-        st.classes_andpop += w->st[ST_CLS_V];
+        st.classes_andpop += w->st[ST_CLS_V] + w->st[ST_CLS_T];
         run_class_kernels(db, f1.get(), L[k].item.get(), *w, tu, tm, s);
 
         tm.begin(BM_K_LEVEL);
         TBuf<uint64_t> S(w->T + 1, s);
         scan_ge(w->tri.get(), minsup, S.get(), w->T, s);
-        TBuf<uint32_t> cnt(nk, s), iscls(nk, s), pm(nk, s), pv(nk, s);
+        TBuf<uint32_t> cnt(nk, s), iscls(nk, s), pm(nk, s), pv(nk, s), pt(nk, s);
         TBuf<uint64_t> trisz(nk, s);
         TBuf<unsigned long long> dst(ST_COUNT, s);
         launch_fill_u64(reinterpret_cast<uint64_t*>(dst.get()), 0, ST_COUNT, s);
         launch_node_counts(nk, k, L[k].parent.get(), pcls_prev.get(), w->cls.get(), S.get(),
                            tu.mfma_min_q, cnt.get(), iscls.get(), trisz.get(), pm.get(), pv.get(),
-                           dst.get(), s);
+                           pt.get(), dst.get(), s);
         L[k].cstart.alloc(nk + 1, s);
-        TBuf<uint64_t> clspos(nk + 1, s), trioff(nk + 1, s), pmoff(nk + 1, s), pvoff(nk + 1, s);
-        scan32(cnt.get(), L[k].cstart.get(), nk, s);
-        scan32(iscls.get(), clspos.get(), nk, s);
-        scan64(trisz.get(), trioff.get(), nk, s);
-        scan32(pm.get(), pmoff.get(), nk, s);
-        scan32(pv.get(), pvoff.get(), nk, s);
+        TBuf<uint64_t> clspos(nk + 1, s), trioff(nk + 1, s), pmoff(nk + 1, s), pvoff(nk + 1, s),
+            ptoff(nk + 1, s);
+        ScanMulti sm{};
+        const void* ins[6] = {cnt.get(), iscls.get(), trisz.get(), pm.get(), pv.get(), pt.get()};
+        uint64_t* outs[6] = {L[k].cstart.get(), clspos.get(), trioff.get(), pmoff.get(), pvoff.get(),
+                             ptoff.get()};
+        for (int j = 0; j < 6; ++j) {
+          sm.in[j] = ins[j];
+          sm.is64[j] = j == 2;
+          sm.out[j] = outs[j];
+        }
+        if (!scan_multi_single(sm, 6, nk, s)) {
+          for (int j = 0; j < 6; ++j) {
+            if (j == 2) scan64(trisz.get(), outs[j], nk, s);
+            else scan32(static_cast<const uint32_t*>(ins[j]), outs[j], nk, s);
+          }
+        }
         tm.end();
-        uint64_t tot[5 + ST_COUNT];
-        BM_HIP(hipMemcpyAsync(&tot[0], L[k].cstart.get() + nk, 8, hipMemcpyDeviceToHost, s));
-        BM_HIP(hipMemcpyAsync(&tot[1], clspos.get() + nk, 8, hipMemcpyDeviceToHost, s));
-        BM_HIP(hipMemcpyAsync(&tot[2], trioff.get() + nk, 8, hipMemcpyDeviceToHost, s));
-        BM_HIP(hipMemcpyAsync(&tot[3], pmoff.get() + nk, 8, hipMemcpyDeviceToHost, s));
-        BM_HIP(hipMemcpyAsync(&tot[4], pvoff.get() + nk, 8, hipMemcpyDeviceToHost, s));
-        BM_HIP(hipMemcpyAsync(&tot[5], dst.get(), 8 * ST_COUNT, hipMemcpyDeviceToHost, s));
+        uint64_t tot[6 + ST_COUNT];
+        GatherU64 gsrc{};
+        for (int j = 0; j < 6; ++j) gsrc.src[j] = outs[j] + nk;
+        for (int j = 0; j < ST_COUNT; ++j)
+          gsrc.src[6 + j] = reinterpret_cast<const uint64_t*>(dst.get()) + j;
+        TBuf<uint64_t> dtot(6 + ST_COUNT, s);
+        launch_gather_u64(gsrc, 6 + ST_COUNT, dtot.get(), s);
+        BM_HIP(hipMemcpyAsync(tot, dtot.get(), sizeof(tot), hipMemcpyDeviceToHost, s));
         BM_HIP(hipStreamSynchronize(s));
         st.host_syncs++;
-        const uint64_t n_next = tot[0], ncls = tot[1], Tn = tot[2], PM = tot[3], PV = tot[4];
+        const uint64_t n_next = tot[0], ncls = tot[1], Tn = tot[2], PM = tot[3], PV = tot[4],
+                       PT = tot[5];
         if (n_next == 0) break;
         if (k + 1 > BM_MAX_LEVELS)
           fail(BM_ERR_UNSUPPORTED, "frequent itemsets longer than %d items", BM_MAX_LEVELS);
@@ -430,12 +476,14 @@ bm_result* mine(const bm_db* db, uint32_t minsup, const bm_options* opt, hipStre
         nw->T = Tn;
         nw->tri.alloc(Tn, s);
         launch_fill_u32(nw->tri.get(), 0, Tn, s);
-        const TaskGeom g = make_geom(db->W, PM, PV, tu);
+        const TaskGeom g = make_geom(db->W, PM, PV, PT, tu);
         nw->ntm = PM * g.nsplit_m;
         nw->ntv = PV * g.nsplit_v;
+        nw->ntt = PT * g.nsplit_t;
         nw->tm.alloc(nw->ntm, s);
         nw->tv.alloc(nw->ntv, s);
-        for (int j = 0; j < ST_COUNT; ++j) nw->st[j] = tot[5 + j];
+        nw->tt.alloc(nw->ntt, s);
+        for (int j = 0; j < ST_COUNT; ++j) nw->st[j] = tot[6 + j];
         LevelPtrs lv{};
         for (uint32_t j = 1; j <= k; ++j) {
           lv.item[j] = L[j].item.get();
@@ -443,8 +491,9 @@ bm_result* mine(const bm_db* db, uint32_t minsup, const bm_options* opt, hipStre
         }
         tm.begin(BM_K_LEVEL);
         launch_fill_classes(nk, k, cnt.get(), L[k].cstart.get(), clspos.get(), trioff.get(),
-                            pmoff.get(), pvoff.get(), tu.mfma_min_q, lv, f1.get(), nw->cls.get(),
-                            nw->pre.get(), pcls_k.get(), g, nw->tm.get(), nw->tv.get(), s);
+                            pmoff.get(), pvoff.get(), ptoff.get(), tu.mfma_min_q, lv, f1.get(),
+                            nw->cls.get(), nw->pre.get(), pcls_k.get(), g, nw->tm.get(),
+                            nw->tv.get(), nw->tt.get(), s);
         tm.end();
         w = std::move(nw);
         pcls_prev = pcls_k;
@@ -480,8 +529,16 @@ bm_result* mine(const bm_db* db, uint32_t minsup, const bm_options* opt, hipStre
                           sz.get(), isz.get(), s);
         SZ[k].alloc(L[k].n + 1, s);
         ISZ[k].alloc(L[k].n + 1, s);
-        scan64(sz.get(), SZ[k].get(), L[k].n, s);
-        scan64(isz.get(), ISZ[k].get(), L[k].n, s);
+        ScanMulti sm{};
+        sm.in[0] = sz.get();
+        sm.in[1] = isz.get();
+        sm.is64[0] = sm.is64[1] = 1;
+        sm.out[0] = SZ[k].get();
+        sm.out[1] = ISZ[k].get();
+        if (!scan_multi_single(sm, 2, L[k].n, s)) {
+          scan64(sz.get(), SZ[k].get(), L[k].n, s);
+          scan64(isz.get(), ISZ[k].get(), L[k].n, s);
+        }
       }
       LevelPtrs lv{};
       for (uint32_t k = 1; k <= K; ++k) {
