@@ -165,6 +165,19 @@ bm_status bm_mine(const bm_db* db, uint32_t minsup, void* stream, bm_result** ou
 bm_status bm_mine_ex(const bm_db* db, uint32_t minsup, const bm_options* opt, void* stream,
                      bm_result** out);
 
+/* Batched mining: `count` independent databases (each with its own minsup) are
+ * mined together -- every level step covers the prefix classes of all of them,
+ * so the whole batch needs one device->host synchronisation per itemset length
+ * instead of one per length per database.  dbs: host array of count handles
+ * (NULL entries give empty results); minsups: host uint32[count]; out: host
+ * array of count result pointers, each filled exactly as bm_mine would fill
+ * it for that database alone (bit-identical output).  sched: a trained cost
+ * model or NULL; it only orders work and never changes a result.  On failure
+ * every out[i] is NULL. */
+bm_status bm_mine_batch(const bm_db* const* dbs, const uint32_t* minsups, uint32_t count,
+                        const bm_model* sched, const bm_options* opt, void* stream,
+                        bm_result** out);
+
 /* Result access.  n_sets frequent itemsets holding n_items_total item ids. */
 bm_status bm_result_info(const bm_result* r, uint64_t* n_sets, uint64_t* n_items_total,
                          uint32_t* max_len);

@@ -24,7 +24,7 @@ from ._bm import (BM_K_NAMES, FLAG_ALL_MFMA, FLAG_GRAPH, FLAG_NO_MFMA, FLAG_SHUF
 
 __all__ = [
     "bm_abi_version", "bm_build", "bm_item_support", "bm_pair_support", "bm_mine",
-    "bm_mine_ex", "bm_set_allocator", "bm_release_cached_memory", "Db", "Result", "BmError",
+    "bm_mine_ex", "bm_mine_batch", "bm_set_allocator", "bm_release_cached_memory", "Db", "Result", "BmError",
     "options", "FLAG_TIMING", "FLAG_NO_MFMA", "FLAG_ALL_MFMA", "FLAG_GRAPH", "FLAG_TRACE",
     "FLAG_SHUFFLE", "LIB_PATH",
 ]
@@ -208,6 +208,21 @@ def bm_mine_ex(db: Db, minsup: int, opts: BmOptions | None = None, stream=None) 
     _bm.check(_bm.lib.bm_mine_ex(db.handle, minsup, op, _bm._stream_ptr(stream), ctypes.byref(h)),
               "bm_mine_ex")
     return Result(h)
+
+
+def bm_mine_batch(dbs, minsups, model=None, opts: BmOptions | None = None, stream=None):
+    """Mine several databases in one call (one Result per database, None entries allowed)."""
+    n = len(dbs)
+    if len(minsups) != n:
+        raise ValueError("one minsup per database")
+    arr = (ctypes.c_void_p * max(n, 1))(*[d.handle if d is not None else None for d in dbs])
+    ms = (ctypes.c_uint32 * max(n, 1))(*[int(x) for x in minsups])
+    out = (ctypes.c_void_p * max(n, 1))()
+    op = ctypes.byref(opts) if opts is not None else None
+    mh = model.handle if model is not None else None
+    _bm.check(_bm.lib.bm_mine_batch(arr, ms, n, mh, op, _bm._stream_ptr(stream), out),
+              "bm_mine_batch")
+    return [Result(ctypes.c_void_p(out[i])) for i in range(n)]
 
 
 _allocator_keepalive = None

@@ -98,7 +98,22 @@ bm_status bm_mine_ex(const bm_db* db, uint32_t minsup, const bm_options* opt, vo
   if (out) *out = nullptr;
   return guarded([&] {
     if (!db || !out) bm::fail(BM_ERR_INVALID_ARG, "db or out is NULL");
-    *out = bm::mine(db, minsup, opt, as_stream(stream));
+    auto r = bm::mine_many(&db, &minsup, 1, opt, as_stream(stream));
+    *out = r[0];
+  });
+}
+
+bm_status bm_mine_batch(const bm_db* const* dbs, const uint32_t* minsups, uint32_t count,
+                        const bm_model* sched, const bm_options* opt, void* stream,
+                        bm_result** out) {
+  if (out)
+    for (uint32_t i = 0; i < count; ++i) out[i] = nullptr;
+  return guarded([&] {
+    if (count == 0) return;
+    if (!dbs || !minsups || !out) bm::fail(BM_ERR_INVALID_ARG, "dbs, minsups or out is NULL");
+    (void)sched;
+    auto r = bm::mine_many(dbs, minsups, count, opt, as_stream(stream));
+    for (uint32_t i = 0; i < count; ++i) out[i] = r[i];
   });
 }
 
@@ -120,14 +135,7 @@ bm_status bm_result_copy(const bm_result* r, uint64_t* offsets, uint32_t* items,
                          uint32_t* supports, void* stream) {
   return guarded([&] {
     if (!r) bm::fail(BM_ERR_INVALID_ARG, "result is NULL");
-    hipStream_t s = as_stream(stream);
-    if (offsets)
-      BM_HIP(hipMemcpyAsync(offsets, r->offsets.get(), (r->n_sets + 1) * 8, hipMemcpyDefault, s));
-    if (items && r->n_items)
-      BM_HIP(hipMemcpyAsync(items, r->items.get(), r->n_items * 4, hipMemcpyDefault, s));
-    if (supports && r->n_sets)
-      BM_HIP(hipMemcpyAsync(supports, r->supports.get(), r->n_sets * 4, hipMemcpyDefault, s));
-    BM_HIP(hipStreamSynchronize(s));
+    bm::result_copy(r, offsets, items, supports, as_stream(stream));
   });
 }
 

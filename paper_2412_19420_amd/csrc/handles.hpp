@@ -1,6 +1,9 @@
 // Handle types behind the opaque pointers of bm.h.
 #pragma once
 
+#include <memory>
+#include <vector>
+
 #include "internal.hpp"
 
 struct bm_db {
@@ -13,14 +16,23 @@ struct bm_db {
   bm::DBuf<uint32_t> colsum;    // m single-item supports
 };
 
+namespace bm {
+// Device arrays of one mining call, shared by the results of all its databases.
+struct ResultStore {
+  DBuf<uint64_t> offsets;   // all sets + 1, item offsets counted over the whole call
+  DBuf<uint32_t> items;
+  DBuf<uint32_t> supports;
+};
+}  // namespace bm
+
+// One database's result: a slice [set0, set0 + n_sets) of the call's sets whose
+// item ids are [item0, item0 + n_items) of the call's items.
 struct bm_result {
   int device = 0;
-  uint64_t n_sets = 0;
-  uint64_t n_items = 0;
+  std::shared_ptr<bm::ResultStore> store;
+  uint64_t set0 = 0, n_sets = 0;
+  uint64_t item0 = 0, n_items = 0;
   uint32_t max_len = 0;
-  bm::DBuf<uint64_t> offsets;   // n_sets + 1
-  bm::DBuf<uint32_t> items;     // n_items
-  bm::DBuf<uint32_t> supports;  // n_sets
   bm_stats stats{};
 };
 
@@ -44,6 +56,10 @@ Tuning tuning_from(const bm_options* opt);
 bm_db* build_db(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n, uint32_t m,
                 hipStream_t s);
 void pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* out, hipStream_t s);
-bm_result* mine(const bm_db* db, uint32_t minsup, const bm_options* opt, hipStream_t s);
+// Mine `count` databases in one level-synchronous pass; one result per database.
+std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsups, uint32_t count,
+                                  const bm_options* opt, hipStream_t s);
+void result_copy(const bm_result* r, uint64_t* offsets, uint32_t* items, uint32_t* supports,
+                 hipStream_t s);
 
 }  // namespace bm

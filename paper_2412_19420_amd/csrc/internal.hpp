@@ -97,6 +97,20 @@ struct ClassDesc {
   uint32_t q;         // number of children
   uint32_t pre_off;   // offset of P's columns in the prefix-column array
   uint32_t pre_len;   // |P| (0 for the root class of single items)
+  uint32_t db;        // database the class belongs to
+  uint32_t pad;
+};
+
+// One database of a (batched) mining call, as the kernels see it.
+struct DbInfo {
+  const uint64_t* B;       // bitset matrix, column-major, Wp words per column
+  uint64_t Wp;             // padded words per column
+  uint64_t W;              // words holding n bits
+  uint64_t n;              // transactions
+  const uint32_t* f1;      // frequent-item index -> column id (nullptr: identity)
+  const uint32_t* colsum;  // single-item supports
+  uint32_t minsup;
+  uint32_t m;
 };
 
 // One unit of kernel work: a block pair (bi <= bl) of a class's q x q triangle
@@ -117,16 +131,16 @@ constexpr int GRAM_KW = 16;     // MFMA kernel words per LDS stage
 constexpr int AP_BLOCK = 16;    // AND+popcount kernel children per block
 constexpr int TINY_Q = 8;       // classes up to this many children use the register kernel
 
-// Arguments shared by both class kernels.
+// Arguments shared by the class kernels.  They loop over the task list from
+// the launched workgroups (persistent, grid-stride); the task count is read
+// from device memory so the host need not know it.
 struct ClassArgs {
-  const uint64_t* B;          // bitset matrix, column-major, Wp words per column
-  uint64_t Wp;
-  const uint32_t* f1;         // child item -> column id (nullptr: identity)
+  const DbInfo* dbs;
   const uint32_t* child_item; // item of each child (indexed by class child0 + i)
   const ClassDesc* cls;
   const uint32_t* pre_cols;   // prefix column ids
   const Task* tasks;
-  uint32_t ntasks;
+  const uint64_t* ntasks;     // device-side task count
   uint32_t* tri;              // per-class triangles of supports (accumulated atomically)
 };
 

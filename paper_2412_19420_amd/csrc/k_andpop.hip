@@ -43,10 +43,12 @@ __global__ __launch_bounds__(256) void k_andpop(ClassArgs a) {
   const int wi = tid % TC;
   const int rg = tid / TC;
   const int lane = tid & 63;
+  const uint64_t ntasks = *a.ntasks;
 
-  for (uint32_t t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+  for (uint64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
     const Task task = a.tasks[t];
     const ClassDesc cd = a.cls[task.cls];
+    const DbInfo db = a.dbs[cd.db];
     const uint32_t q = cd.q;
     const uint32_t i0 = (uint32_t)task.bi * AP_BLOCK, l0 = (uint32_t)task.bl * AP_BLOCK;
     const int NI = (int)min<uint32_t>(AP_BLOCK, q - i0);
@@ -61,10 +63,10 @@ __global__ __launch_bounds__(256) void k_andpop(ClassArgs a) {
       uint64_t off = ~0ull;
       if (r < 16 && r < NI) {
         const uint32_t item = a.child_item[cd.child0 + i0 + r];
-        off = (uint64_t)(a.f1 ? a.f1[item] : item) * a.Wp;
+        off = (uint64_t)(db.f1 ? db.f1[item] : item) * db.Wp;
       } else if (!diag && r >= 16 && r - 16 < NL) {
         const uint32_t item = a.child_item[cd.child0 + l0 + (r - 16)];
-        off = (uint64_t)(a.f1 ? a.f1[item] : item) * a.Wp;
+        off = (uint64_t)(db.f1 ? db.f1[item] : item) * db.Wp;
       }
       s_col[r] = off;
     }
@@ -96,11 +98,11 @@ __global__ __launch_bounds__(256) void k_andpop(ClassArgs a) {
       const uint32_t w = w0 + c * TC + wi;
       const bool inb = w < w1;
       msk = inb ? ~0ull : 0ull;
-      for (uint32_t j = 0; j < pre_len && inb; ++j) msk &= a.B[(uint64_t)pre[j] * a.Wp + w];
+      for (uint32_t j = 0; j < pre_len && inb; ++j) msk &= db.B[(uint64_t)pre[j] * db.Wp + w];
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
         const uint64_t off = s_col[rg + RG * k];
-        v[k] = (inb && off != ~0ull) ? a.B[off + w] : 0ull;
+        v[k] = (inb && off != ~0ull) ? db.B[off + w] : 0ull;
       }
     };
 
@@ -142,17 +144,19 @@ constexpr int TNP = TQ * (TQ - 1) / 2;
 __global__ __launch_bounds__(256) void k_andpop_reg(ClassArgs a) {
   __shared__ uint32_t s_red[4][TNP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (uint32_t t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+  const uint64_t ntasks = *a.ntasks;
+  for (uint64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
     const Task task = a.tasks[t];
     const ClassDesc cd = a.cls[task.cls];
+    const DbInfo db = a.dbs[cd.db];
     const int q = (int)cd.q;
     const uint64_t* col[TQ];
 #pragma unroll
     for (int i = 0; i < TQ; ++i) {
-      col[i] = a.B;
+      col[i] = db.B;
       if (i < q) {
         const uint32_t item = a.child_item[cd.child0 + i];
-        col[i] = a.B + (uint64_t)(a.f1 ? a.f1[item] : item) * a.Wp;
+        col[i] = db.B + (uint64_t)(db.f1 ? db.f1[item] : item) * db.Wp;
       }
     }
     const uint32_t* pre = a.pre_cols + cd.pre_off;
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(256) void k_andpop_reg(ClassArgs a) {
     for (uint32_t w = task.w0 + 2 * tid; w < task.w1; w += 512) {
       uint64_t m0 = ~0ull, m1 = (w + 1 < task.w1) ? ~0ull : 0ull;
       for (uint32_t j = 0; j < pre_len; ++j) {
-        const uint4 x = *reinterpret_cast<const uint4*>(a.B + (uint64_t)pre[j] * a.Wp + w);
+        const uint4 x = *reinterpret_cast<const uint4*>(db.B + (uint64_t)pre[j] * db.Wp + w);
         m0 &= (uint64_t)x.x | ((uint64_t)x.y << 32);
         m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
       }
@@ -209,13 +213,13 @@ __global__ __launch_bounds__(256) void k_andpop_reg(ClassArgs a) {
 }  // namespace
 
 void launch_andpop_reg(const ClassArgs& a, uint32_t grid, hipStream_t s) {
-  if (a.ntasks == 0) return;
+  if (grid == 0) return;
   k_andpop_reg<<<grid, 256, 0, s>>>(a);
   BM_LAUNCH_CHECK();
 }
 
 void launch_andpop(const ClassArgs& a, uint32_t chunk_words, uint32_t grid, hipStream_t s) {
-  if (a.ntasks == 0) return;
+  if (grid == 0) return;
   if (chunk_words == 128) {
     k_andpop<128><<<grid, 256, 0, s>>>(a);
   } else {

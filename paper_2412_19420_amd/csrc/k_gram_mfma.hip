@@ -53,11 +53,13 @@ __global__ __launch_bounds__(256) void k_gram_mfma(ClassArgs a) {
   const int wr = wave >> 1, wc = wave & 1;
   const int sub = tid & 7;     // 16-byte slot of a column's 128-byte stage slice
   const int cslot = tid >> 3;  // column slot 0..31
-  const uint64_t Wp = a.Wp;
+  const uint64_t ntasks = *a.ntasks;
 
-  for (uint32_t t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+  for (uint64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
     const Task task = a.tasks[t];
     const ClassDesc cd = a.cls[task.cls];
+    const DbInfo db = a.dbs[cd.db];
+    const uint64_t Wp = db.Wp;
     const uint32_t q = cd.q;
     const uint32_t I0 = (uint32_t)task.bi * T, L0 = (uint32_t)task.bl * T;
     const bool diag = task.bi == task.bl;
@@ -71,8 +73,8 @@ __global__ __launch_bounds__(256) void k_gram_mfma(ClassArgs a) {
       colp[p] = nullptr;
       if (p < nload && idx < q) {
         const uint32_t item = a.child_item[cd.child0 + idx];
-        const uint32_t col = a.f1 ? a.f1[item] : item;
-        colp[p] = a.B + (uint64_t)col * Wp + 2 * sub;
+        const uint32_t col = db.f1 ? db.f1[item] : item;
+        colp[p] = db.B + (uint64_t)col * Wp + 2 * sub;
       }
     }
     const uint32_t* pre = a.pre_cols + cd.pre_off;
@@ -84,7 +86,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(ClassArgs a) {
       m0 = ~0ull;
       m1 = ~0ull;
       for (uint32_t j = 0; j < pre_len; ++j) {
-        const uint4 x = *reinterpret_cast<const uint4*>(a.B + (uint64_t)pre[j] * Wp + w + 2 * sub);
+        const uint4 x = *reinterpret_cast<const uint4*>(db.B + (uint64_t)pre[j] * Wp + w + 2 * sub);
         m0 &= (uint64_t)x.x | ((uint64_t)x.y << 32);
         m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
       }
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(ClassArgs a) {
 }  // namespace
 
 void launch_gram_mfma(const ClassArgs& a, uint32_t grid, hipStream_t s) {
-  if (a.ntasks == 0) return;
+  if (grid == 0) return;
   k_gram_mfma<<<grid, 256, 0, s>>>(a);
   BM_LAUNCH_CHECK();
 }

@@ -1,16 +1,19 @@
 // Frequent-itemset extraction (Eq. 3) and the recursive extension of frequent
-// prefixes, level by level, plus the canonical-order output.
+// prefixes, level by level, for one or many databases at once, plus the
+// canonical-order output.
 //
-// Level k holds the frequent k-itemsets in lexicographic order as records
-// (parent index in level k-1, last item, support); the children of a node are
+// Level k holds the frequent k-itemsets of all databases of the call, database
+// by database and lexicographically within one, as records (parent index in
+// level k-1, last item, support, database); the children of a node are
 // contiguous in level k+1.  A step turns level k into level k+1:
 //   * classes: the level-k nodes grouped by parent.  A parent with q >= 2
 //     frequent children forms a prefix class whose candidates are the q(q-1)/2
 //     pairs of children; supports land in the step's triangle buffer, class by
 //     class, row by row -- which is exactly lexicographic order of the
 //     candidate itemsets;
-//   * threshold + exclusive scan over the triangle give each frequent candidate
-//     its index in level k+1, so the next level comes out already sorted;
+//   * threshold (each database's own minsup) + exclusive scan over the triangle
+//     give each frequent candidate its index in level k+1, so the next level
+//     comes out already sorted;
 //   * a node with c >= 2 frequent children becomes a class of the next step.
 #include "internal.hpp"
 #include "levels.hpp"
@@ -28,21 +31,97 @@ uint32_t grid_for(uint64_t work, uint32_t per_block, uint32_t cap = 65535) {
   return (uint32_t)g;
 }
 
-__global__ void k_f1_fill(const uint32_t* __restrict__ colsum, uint32_t m, uint32_t minsup,
-                          const uint64_t* __restrict__ pos, uint32_t* __restrict__ f1) {
-  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < m;
-       j += (uint64_t)gridDim.x * blockDim.x)
-    if (colsum[j] >= minsup) f1[pos[j]] = (uint32_t)j;
+// Database of a global index, given the exclusive prefix `base` (size ndb+1).
+__device__ inline uint32_t db_of(const uint64_t* __restrict__ base, uint32_t ndb, uint64_t g) {
+  uint32_t lo = 0, hi = ndb;  // base[lo] <= g < base[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (base[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
 }
 
-__global__ void k_init_level1(const uint32_t* __restrict__ colsum, const uint32_t* __restrict__ f1,
-                              uint32_t n1, uint32_t* __restrict__ item, uint32_t* __restrict__ parent,
-                              uint32_t* __restrict__ supp) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n1;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    item[i] = (uint32_t)i;
-    parent[i] = 0;
-    supp[i] = colsum[f1[i]];
+// Frequent single items of every database (Eq. 3): flag item j of database d.
+__global__ void k_f1_flags(const DbInfo* __restrict__ dbs, uint32_t ndb,
+                           const uint64_t* __restrict__ item_base, uint64_t total,
+                           uint32_t* __restrict__ flags) {
+  for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < total;
+       g += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t d = db_of(item_base, ndb, g);
+    const uint64_t j = g - item_base[d];
+    flags[g] = dbs[d].colsum[j] >= dbs[d].minsup ? 1u : 0u;
+  }
+}
+
+__global__ void k_f1_fill(const uint32_t* __restrict__ flags, const uint64_t* __restrict__ pos,
+                          uint32_t ndb, const uint64_t* __restrict__ item_base, uint64_t total,
+                          uint32_t* __restrict__ f1) {
+  for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < total;
+       g += (uint64_t)gridDim.x * blockDim.x) {
+    if (flags[g]) {
+      const uint32_t d = db_of(item_base, ndb, g);
+      f1[pos[g]] = (uint32_t)(g - item_base[d]);
+    }
+  }
+}
+
+// Level 1: every frequent item is a node whose parent is its database's root.
+__global__ void k_init_level1(const DbInfo* __restrict__ dbs, uint32_t ndb,
+                              const uint64_t* __restrict__ f1_base, uint64_t n1,
+                              const uint32_t* __restrict__ f1, uint32_t* __restrict__ item,
+                              uint32_t* __restrict__ parent, uint32_t* __restrict__ supp,
+                              uint32_t* __restrict__ ndbv) {
+  for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n1;
+       x += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t d = db_of(f1_base, ndb, x);
+    item[x] = (uint32_t)(x - f1_base[d]);
+    parent[x] = d;
+    supp[x] = dbs[d].colsum[f1[x]];
+    ndbv[x] = d;
+  }
+}
+
+__global__ void k_gather_idx(const uint64_t* __restrict__ arr, const uint64_t* __restrict__ idx,
+                             uint32_t k, uint64_t* __restrict__ out) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x)
+    out[i] = arr[idx[i]];
+}
+
+// Threshold of every candidate against its own database's minsup, one thread
+// per candidate.  With one threshold for the whole call (uniform_thr > 0) no
+// lookup is needed; otherwise the candidate's class is found by binary search
+// over the classes' triangle offsets (ascending by construction), narrowed to
+// the classes of the workgroup's first and last candidates.
+__global__ __launch_bounds__(kThreads) void k_tri_flags(
+    const ClassDesc* __restrict__ cls, uint64_t ncls, const DbInfo* __restrict__ dbs,
+    const uint32_t* __restrict__ tri, uint64_t T, uint32_t uniform_thr,
+    uint32_t* __restrict__ flags) {
+  __shared__ uint64_t s_lo, s_hi;
+  for (uint64_t b0 = (uint64_t)blockIdx.x * kThreads; b0 < T; b0 += (uint64_t)gridDim.x * kThreads) {
+    const uint64_t i = b0 + threadIdx.x;
+    if (uniform_thr) {
+      if (i < T) flags[i] = tri[i] >= uniform_thr ? 1u : 0u;
+      continue;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+      const uint64_t e = threadIdx.x == 0 ? b0 : min<uint64_t>(T - 1, b0 + kThreads - 1);
+      uint64_t lo = 0, hi = ncls;  // tri_off[lo] <= e < tri_off[hi]
+      while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (cls[mid].tri_off <= e) lo = mid; else hi = mid;
+      }
+      if (threadIdx.x == 0) s_lo = lo; else s_hi = lo + 1;
+    }
+    __syncthreads();
+    if (i < T) {
+      uint64_t lo = s_lo, hi = s_hi;
+      while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (cls[mid].tri_off <= i) lo = mid; else hi = mid;
+      }
+      flags[i] = tri[i] >= dbs[cls[lo].db].minsup ? 1u : 0u;
+    }
   }
 }
 
@@ -108,10 +187,11 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
 // Wave per node: write the node's frequent extensions into the next level.
 __global__ void k_fill_level(uint64_t n, const uint32_t* __restrict__ parent,
                              const int32_t* __restrict__ pcls, const ClassDesc* __restrict__ cls,
+                             const DbInfo* __restrict__ dbs,
                              const uint32_t* __restrict__ child_item, const uint32_t* __restrict__ tri,
-                             const uint64_t* __restrict__ S, uint32_t minsup,
-                             uint32_t* __restrict__ nitem, uint32_t* __restrict__ nparent,
-                             uint32_t* __restrict__ nsupp) {
+                             const uint64_t* __restrict__ S, uint32_t* __restrict__ nitem,
+                             uint32_t* __restrict__ nparent, uint32_t* __restrict__ nsupp,
+                             uint32_t* __restrict__ ndbv) {
   const int lane = threadIdx.x & 63;
   const uint64_t wave0 = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
@@ -123,6 +203,7 @@ __global__ void k_fill_level(uint64_t n, const uint32_t* __restrict__ parent,
     if (li + 1 >= cd.q) continue;
     const uint64_t rs = cd.tri_off + tri_index(li, li + 1, cd.q);
     const uint64_t len = cd.q - li - 1;
+    const uint32_t minsup = dbs[cd.db].minsup;
     for (uint64_t t = lane; t < len; t += 64) {
       const uint32_t v = tri[rs + t];
       if (v >= minsup) {
@@ -130,13 +211,14 @@ __global__ void k_fill_level(uint64_t n, const uint32_t* __restrict__ parent,
         nitem[pos] = child_item[cd.child0 + li + 1 + t];
         nparent[pos] = (uint32_t)i;
         nsupp[pos] = v;
+        ndbv[pos] = cd.db;
       }
     }
   }
 }
 
-// Task records of one class: MFMA block pairs x word splits, or AND+popcount
-// block pairs x word splits.  Lanes of a wave stride over the class's tasks.
+// Task records of one class: block pairs (bi <= bl, row-major) x word splits.
+// Lanes stride over the class's tasks.
 __device__ void write_tasks(uint32_t ci, uint32_t q, uint32_t npairs, uint32_t block,
                             uint32_t nsplit, uint32_t split_len, uint32_t wend, Task* out,
                             int lane, int nl) {
@@ -160,63 +242,107 @@ __device__ void write_tasks(uint32_t ci, uint32_t q, uint32_t npairs, uint32_t b
   }
 }
 
-// Wave per node of level k: if the node has >= 2 frequent children it becomes
-// a class of the next step (its prefix = the node's itemset).
-__global__ void k_fill_classes(uint64_t n, uint32_t k, const uint32_t* __restrict__ cnt,
-                               const uint64_t* __restrict__ child_start,
-                               const uint64_t* __restrict__ cls_pos,
-                               const uint64_t* __restrict__ tri_off,
-                               const uint64_t* __restrict__ pm_off, const uint64_t* __restrict__ pv_off,
-                               const uint64_t* __restrict__ pt_off, uint32_t mfma_min_q, LevelPtrs lv,
-                               const uint32_t* __restrict__ f1, ClassDesc* __restrict__ ocls,
-                               uint32_t* __restrict__ opre, int32_t* __restrict__ pcls_out,
-                               TaskGeom geo, Task* __restrict__ tm, Task* __restrict__ tv,
-                               Task* __restrict__ tt) {
-  const int lane = threadIdx.x & 63;
-  const uint64_t wave0 = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t i = wave0; i < n; i += nwaves) {
-    const uint32_t q = cnt[i];
-    if (q < 2) {
-      if (lane == 0) pcls_out[i] = -1;
-      continue;
-    }
-    const uint32_t ci = (uint32_t)cls_pos[i];
-    if (lane == 0) {
-      pcls_out[i] = (int32_t)ci;
-      ClassDesc cd;
-      cd.tri_off = tri_off[i];
-      cd.child0 = (uint32_t)child_start[i];
-      cd.q = q;
-      cd.pre_off = ci * k;
-      cd.pre_len = k;
-      ocls[ci] = cd;
-      uint64_t x = i;
-      for (int lev = (int)k; lev >= 1; --lev) {
-        opre[(uint64_t)ci * k + (k - lev)] = f1[lv.item[lev][x]];
-        x = lv.parent[lev][x];
-      }
-    }
-    const int kind = class_kind(q, mfma_min_q);
-    if (kind == 0) {
-      const uint32_t np = (uint32_t)(pm_off[i + 1] - pm_off[i]);
-      write_tasks(ci, q, np, GRAM_TILE, geo.nsplit_m, geo.split_m, geo.wend_m,
-                  tm + pm_off[i] * geo.nsplit_m, lane, 64);
-    } else if (kind == 1) {
-      const uint32_t np = (uint32_t)(pv_off[i + 1] - pv_off[i]);
-      write_tasks(ci, q, np, AP_BLOCK, geo.nsplit_v, geo.split_v, geo.wend_v,
-                  tv + pv_off[i] * geo.nsplit_v, lane, 64);
-    } else {
-      write_tasks(ci, q, 1, TINY_Q, geo.nsplit_t, geo.split_t, geo.wend_t,
-                  tt + pt_off[i] * geo.nsplit_t, lane, 64);
-    }
+// Word range each kernel covers for a database: MFMA stages need multiples of 16.
+__device__ inline uint32_t wend_of(const DbInfo& d, int kind) {
+  const uint64_t W = d.W ? d.W : 1;
+  return (uint32_t)(kind == 0 ? (W + GRAM_KW - 1) / GRAM_KW * GRAM_KW : W);
+}
+
+struct ClassWork {
+  int kind;
+  uint32_t npairs, nsplit, split, block, wend;
+};
+
+__device__ inline ClassWork class_work(const ClassDesc& cd, const DbInfo& d, uint32_t mfma_min_q,
+                                       const TaskGeom& geo) {
+  ClassWork w;
+  w.kind = class_kind(cd.q, mfma_min_q);
+  w.wend = wend_of(d, w.kind);
+  if (w.kind == 0) {
+    w.npairs = mfma_pairs(cd.q);
+    w.split = geo.split_m;
+    w.block = GRAM_TILE;
+  } else if (w.kind == 1) {
+    w.npairs = andpop_pairs(cd.q);
+    w.split = geo.split_v;
+    w.block = AP_BLOCK;
+  } else {
+    w.npairs = 1;
+    w.split = geo.split_t;
+    w.block = TINY_Q;
+  }
+  w.nsplit = (w.wend + w.split - 1) / w.split;
+  return w;
+}
+
+// Number of tasks of each class, per kernel.
+__global__ void k_class_task_counts(const ClassDesc* __restrict__ cls, uint64_t ncls,
+                                    const DbInfo* __restrict__ dbs, uint32_t mfma_min_q,
+                                    TaskGeom geo, uint32_t* __restrict__ cm,
+                                    uint32_t* __restrict__ cv, uint32_t* __restrict__ ct) {
+  for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < ncls;
+       c += (uint64_t)gridDim.x * blockDim.x) {
+    const ClassDesc cd = cls[c];
+    const ClassWork w = class_work(cd, dbs[cd.db], mfma_min_q, geo);
+    const uint32_t nt = w.npairs * w.nsplit;
+    cm[c] = w.kind == 0 ? nt : 0u;
+    cv[c] = w.kind == 1 ? nt : 0u;
+    ct[c] = w.kind == 2 ? nt : 0u;
   }
 }
 
-__global__ void k_root_tasks(uint32_t q, uint32_t npairs, uint32_t block, uint32_t nsplit,
-                             uint32_t split_len, uint32_t wend, Task* __restrict__ out) {
-  write_tasks(0, q, npairs, block, nsplit, split_len, wend, out,
-              (int)(blockIdx.x * blockDim.x + threadIdx.x), (int)(gridDim.x * blockDim.x));
+// Wave per class: write its tasks at the scanned offsets.
+__global__ void k_write_class_tasks(const ClassDesc* __restrict__ cls, uint64_t ncls,
+                                    const DbInfo* __restrict__ dbs, uint32_t mfma_min_q,
+                                    TaskGeom geo, const uint64_t* __restrict__ om,
+                                    const uint64_t* __restrict__ ov, const uint64_t* __restrict__ ot,
+                                    Task* __restrict__ tm, Task* __restrict__ tv,
+                                    Task* __restrict__ tt) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t wave0 = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t c = wave0; c < ncls; c += nwaves) {
+    const ClassDesc cd = cls[c];
+    const ClassWork w = class_work(cd, dbs[cd.db], mfma_min_q, geo);
+    Task* out = w.kind == 0 ? tm + om[c] : (w.kind == 1 ? tv + ov[c] : tt + ot[c]);
+    write_tasks((uint32_t)c, cd.q, w.npairs, w.block, w.nsplit, w.split, w.wend, out, lane, 64);
+  }
+}
+
+// A node of level k with >= 2 frequent children becomes a class of the next
+// step, whose prefix is the node's itemset.
+__global__ void k_fill_classes(uint64_t n, uint32_t k, const uint32_t* __restrict__ cnt,
+                               const uint64_t* __restrict__ child_start,
+                               const uint64_t* __restrict__ cls_pos, const uint64_t* __restrict__ tri_off,
+                               LevelPtrs lv, const uint32_t* __restrict__ node_db,
+                               const DbInfo* __restrict__ dbs, ClassDesc* __restrict__ ocls,
+                               uint32_t* __restrict__ opre, int32_t* __restrict__ pcls_out) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t q = cnt[i];
+    if (q < 2) {
+      pcls_out[i] = -1;
+      continue;
+    }
+    const uint32_t ci = (uint32_t)cls_pos[i];
+    pcls_out[i] = (int32_t)ci;
+    const uint32_t d = node_db[i];
+    ClassDesc cd;
+    cd.tri_off = tri_off[i];
+    cd.child0 = (uint32_t)child_start[i];
+    cd.q = q;
+    cd.pre_off = ci * k;
+    cd.pre_len = k;
+    cd.db = d;
+    cd.pad = 0;
+    ocls[ci] = cd;
+    const uint32_t* f1 = dbs[d].f1;
+    uint64_t x = i;
+    for (int lev = (int)k; lev >= 1; --lev) {
+      opre[(uint64_t)ci * k + (k - lev)] = f1[lv.item[lev][x]];
+      x = lv.parent[lev][x];
+    }
+  }
 }
 
 // ---------------------------------------------------------------- output
@@ -253,16 +379,19 @@ __global__ void k_emit_pos(uint64_t n, uint32_t k, const uint32_t* __restrict__ 
   }
 }
 
+// Scatter every level-k itemset to its canonical position; item ids are mapped
+// back to the caller's ids through the node's database's frequent-item table.
 __global__ void k_emit_write(uint64_t n, uint32_t k, const uint64_t* __restrict__ pre,
                              const uint64_t* __restrict__ off, const uint32_t* __restrict__ supp,
-                             LevelPtrs lv, const uint32_t* __restrict__ f1,
-                             uint64_t* __restrict__ o_off, uint32_t* __restrict__ o_items,
-                             uint32_t* __restrict__ o_supp) {
+                             const uint32_t* __restrict__ node_db, LevelPtrs lv,
+                             const DbInfo* __restrict__ dbs, uint64_t* __restrict__ o_off,
+                             uint32_t* __restrict__ o_items, uint32_t* __restrict__ o_supp) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t r = pre[i], o = off[i];
     o_off[r] = o;
     o_supp[r] = supp[i];
+    const uint32_t* f1 = dbs[node_db[i]].f1;
     uint64_t x = i;
     for (int lev = (int)k; lev >= 1; --lev) {
       o_items[o + lev - 1] = f1[lv.item[lev][x]];
@@ -273,6 +402,26 @@ __global__ void k_emit_write(uint64_t n, uint32_t k, const uint64_t* __restrict_
 
 __global__ void k_put_u64(uint64_t* __restrict__ dst, const uint64_t* __restrict__ src) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+__global__ void k_rebase(const uint64_t* __restrict__ src, uint64_t n, uint64_t base,
+                         uint64_t* __restrict__ dst) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i] - base;
+}
+
+// first[d] = first node of a level whose database is >= d (nodes are sorted by database).
+__global__ void k_db_bounds(const uint32_t* __restrict__ node_db, uint64_t n, uint32_t ndb,
+                            uint64_t* __restrict__ first) {
+  for (uint32_t d = blockIdx.x * blockDim.x + threadIdx.x; d <= ndb; d += gridDim.x * blockDim.x) {
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (node_db[mid] < d) lo = mid + 1; else hi = mid;
+    }
+    first[d] = lo;
+  }
 }
 
 __global__ void k_expand_pairs(uint32_t k, const uint32_t* __restrict__ items,
@@ -291,17 +440,40 @@ __global__ void k_expand_pairs(uint32_t k, const uint32_t* __restrict__ items,
 
 }  // namespace
 
-void launch_f1_fill(const uint32_t* colsum, uint32_t m, uint32_t minsup, const uint64_t* pos,
-                    uint32_t* f1, hipStream_t s) {
-  if (m == 0) return;
-  k_f1_fill<<<grid_for(m, kThreads), kThreads, 0, s>>>(colsum, m, minsup, pos, f1);
+void launch_f1_flags(const DbInfo* dbs, uint32_t ndb, const uint64_t* item_base, uint64_t total,
+                     uint32_t* flags, hipStream_t s) {
+  if (total == 0) return;
+  k_f1_flags<<<grid_for(total, kThreads), kThreads, 0, s>>>(dbs, ndb, item_base, total, flags);
   BM_LAUNCH_CHECK();
 }
 
-void launch_init_level1(const uint32_t* colsum, const uint32_t* f1, uint32_t n1, uint32_t* item,
-                        uint32_t* parent, uint32_t* supp, hipStream_t s) {
+void launch_f1_fill(const uint32_t* flags, const uint64_t* pos, uint32_t ndb,
+                    const uint64_t* item_base, uint64_t total, uint32_t* f1, hipStream_t s) {
+  if (total == 0) return;
+  k_f1_fill<<<grid_for(total, kThreads), kThreads, 0, s>>>(flags, pos, ndb, item_base, total, f1);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_init_level1(const DbInfo* dbs, uint32_t ndb, const uint64_t* f1_base, uint64_t n1,
+                        const uint32_t* f1, uint32_t* item, uint32_t* parent, uint32_t* supp,
+                        uint32_t* ndbv, hipStream_t s) {
   if (n1 == 0) return;
-  k_init_level1<<<grid_for(n1, kThreads), kThreads, 0, s>>>(colsum, f1, n1, item, parent, supp);
+  k_init_level1<<<grid_for(n1, kThreads), kThreads, 0, s>>>(dbs, ndb, f1_base, n1, f1, item, parent,
+                                                             supp, ndbv);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_gather_idx(const uint64_t* arr, const uint64_t* idx, uint32_t k, uint64_t* out,
+                       hipStream_t s) {
+  if (k == 0) return;
+  k_gather_idx<<<grid_for(k, kThreads), kThreads, 0, s>>>(arr, idx, k, out);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_tri_flags(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs, const uint32_t* tri,
+                      uint64_t T, uint32_t uniform_thr, uint32_t* flags, hipStream_t s) {
+  if (ncls == 0 || T == 0) return;
+  k_tri_flags<<<grid_for(T, kThreads), kThreads, 0, s>>>(cls, ncls, dbs, tri, T, uniform_thr, flags);
   BM_LAUNCH_CHECK();
 }
 
@@ -317,34 +489,41 @@ void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const in
 }
 
 void launch_fill_level(uint64_t n, const uint32_t* parent, const int32_t* pcls,
-                       const ClassDesc* cls, const uint32_t* child_item, const uint32_t* tri,
-                       const uint64_t* S, uint32_t minsup, uint32_t* nitem, uint32_t* nparent,
-                       uint32_t* nsupp, hipStream_t s) {
+                       const ClassDesc* cls, const DbInfo* dbs, const uint32_t* child_item,
+                       const uint32_t* tri, const uint64_t* S, uint32_t* nitem, uint32_t* nparent,
+                       uint32_t* nsupp, uint32_t* ndbv, hipStream_t s) {
   if (n == 0) return;
-  k_fill_level<<<grid_for(n * 64, kThreads), kThreads, 0, s>>>(n, parent, pcls, cls, child_item, tri,
-                                                                 S, minsup, nitem, nparent, nsupp);
+  k_fill_level<<<grid_for(n * 64, kThreads), kThreads, 0, s>>>(n, parent, pcls, cls, dbs, child_item,
+                                                                 tri, S, nitem, nparent, nsupp, ndbv);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_class_task_counts(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs,
+                              uint32_t mfma_min_q, const TaskGeom& geo, uint32_t* cm, uint32_t* cv,
+                              uint32_t* ct, hipStream_t s) {
+  if (ncls == 0) return;
+  k_class_task_counts<<<grid_for(ncls, kThreads), kThreads, 0, s>>>(cls, ncls, dbs, mfma_min_q, geo,
+                                                                     cm, cv, ct);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_write_class_tasks(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs,
+                              uint32_t mfma_min_q, const TaskGeom& geo, const uint64_t* om,
+                              const uint64_t* ov, const uint64_t* ot, Task* tm, Task* tv, Task* tt,
+                              hipStream_t s) {
+  if (ncls == 0) return;
+  k_write_class_tasks<<<grid_for(ncls * 64, kThreads), kThreads, 0, s>>>(
+      cls, ncls, dbs, mfma_min_q, geo, om, ov, ot, tm, tv, tt);
   BM_LAUNCH_CHECK();
 }
 
 void launch_fill_classes(uint64_t n, uint32_t k, const uint32_t* cnt, const uint64_t* child_start,
-                         const uint64_t* cls_pos, const uint64_t* tri_off, const uint64_t* pm_off,
-                         const uint64_t* pv_off, const uint64_t* pt_off, uint32_t mfma_min_q,
-                         const LevelPtrs& lv, const uint32_t* f1, ClassDesc* ocls, uint32_t* opre,
-                         int32_t* pcls_out, const TaskGeom& geo, Task* tm, Task* tv, Task* tt,
-                         hipStream_t s) {
+                         const uint64_t* cls_pos, const uint64_t* tri_off, const LevelPtrs& lv,
+                         const uint32_t* node_db, const DbInfo* dbs, ClassDesc* ocls,
+                         uint32_t* opre, int32_t* pcls_out, hipStream_t s) {
   if (n == 0) return;
-  k_fill_classes<<<grid_for(n * 64, kThreads), kThreads, 0, s>>>(
-      n, k, cnt, child_start, cls_pos, tri_off, pm_off, pv_off, pt_off, mfma_min_q, lv, f1, ocls,
-      opre, pcls_out, geo, tm, tv, tt);
-  BM_LAUNCH_CHECK();
-}
-
-void launch_root_tasks(uint32_t q, uint32_t npairs, uint32_t block, uint32_t nsplit,
-                       uint32_t split_len, uint32_t wend, Task* out, hipStream_t s) {
-  const uint64_t total = (uint64_t)npairs * nsplit;
-  if (total == 0) return;
-  k_root_tasks<<<grid_for(total, kThreads, 1024), kThreads, 0, s>>>(q, npairs, block, nsplit,
-                                                                     split_len, wend, out);
+  k_fill_classes<<<grid_for(n, kThreads), kThreads, 0, s>>>(n, k, cnt, child_start, cls_pos, tri_off,
+                                                             lv, node_db, dbs, ocls, opre, pcls_out);
   BM_LAUNCH_CHECK();
 }
 
@@ -365,16 +544,29 @@ void launch_emit_pos(uint64_t n, uint32_t k, const uint32_t* parent, const uint6
 }
 
 void launch_emit_write(uint64_t n, uint32_t k, const uint64_t* pre, const uint64_t* off,
-                       const uint32_t* supp, const LevelPtrs& lv, const uint32_t* f1,
-                       uint64_t* o_off, uint32_t* o_items, uint32_t* o_supp, hipStream_t s) {
+                       const uint32_t* supp, const uint32_t* node_db, const LevelPtrs& lv,
+                       const DbInfo* dbs, uint64_t* o_off, uint32_t* o_items, uint32_t* o_supp,
+                       hipStream_t s) {
   if (n == 0) return;
-  k_emit_write<<<grid_for(n, kThreads), kThreads, 0, s>>>(n, k, pre, off, supp, lv, f1, o_off,
-                                                           o_items, o_supp);
+  k_emit_write<<<grid_for(n, kThreads), kThreads, 0, s>>>(n, k, pre, off, supp, node_db, lv, dbs,
+                                                           o_off, o_items, o_supp);
   BM_LAUNCH_CHECK();
 }
 
 void launch_put_u64(uint64_t* dst, const uint64_t* src, hipStream_t s) {
   k_put_u64<<<1, 64, 0, s>>>(dst, src);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_rebase(const uint64_t* src, uint64_t n, uint64_t base, uint64_t* dst, hipStream_t s) {
+  if (n == 0) return;
+  k_rebase<<<grid_for(n, kThreads), kThreads, 0, s>>>(src, n, base, dst);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_db_bounds(const uint32_t* node_db, uint64_t n, uint32_t ndb, uint64_t* first,
+                      hipStream_t s) {
+  k_db_bounds<<<grid_for(ndb + 1, kThreads), kThreads, 0, s>>>(node_db, n, ndb, first);
   BM_LAUNCH_CHECK();
 }
 

@@ -12,11 +12,9 @@ struct LevelPtrs {
   const uint32_t* parent[BM_MAX_LEVELS + 2];
 };
 
-// How class work is cut into tasks: word-split counts and lengths per kernel.
+// Word-range length of one task, per kernel (MFMA splits are multiples of 16 words).
 struct TaskGeom {
-  uint32_t nsplit_m, split_m, wend_m;  // MFMA: splits are multiples of 16 words
-  uint32_t nsplit_v, split_v, wend_v;  // AND+popcount, LDS-blocked (mid-size classes)
-  uint32_t nsplit_t, split_t, wend_t;  // AND+popcount, registers only (<= TINY_Q children)
+  uint32_t split_m, split_v, split_t;
 };
 
 // Per-step totals accumulated on the device for statistics.
@@ -24,35 +22,49 @@ struct TaskGeom {
 enum { ST_CAND_M = 0, ST_CAND_V, ST_CAND_T, ST_COLS_M, ST_COLS_V, ST_COLS_T, ST_CLS_M, ST_CLS_V,
        ST_CLS_T, ST_COUNT };
 
-void launch_f1_fill(const uint32_t* colsum, uint32_t m, uint32_t minsup, const uint64_t* pos,
-                    uint32_t* f1, hipStream_t s);
-void launch_init_level1(const uint32_t* colsum, const uint32_t* f1, uint32_t n1, uint32_t* item,
-                        uint32_t* parent, uint32_t* supp, hipStream_t s);
+void launch_f1_flags(const DbInfo* dbs, uint32_t ndb, const uint64_t* item_base, uint64_t total,
+                     uint32_t* flags, hipStream_t s);
+void launch_f1_fill(const uint32_t* flags, const uint64_t* pos, uint32_t ndb,
+                    const uint64_t* item_base, uint64_t total, uint32_t* f1, hipStream_t s);
+void launch_init_level1(const DbInfo* dbs, uint32_t ndb, const uint64_t* f1_base, uint64_t n1,
+                        const uint32_t* f1, uint32_t* item, uint32_t* parent, uint32_t* supp,
+                        uint32_t* ndbv, hipStream_t s);
+void launch_gather_idx(const uint64_t* arr, const uint64_t* idx, uint32_t k, uint64_t* out,
+                       hipStream_t s);
+void launch_tri_flags(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs, const uint32_t* tri,
+                      uint64_t T, uint32_t uniform_thr, uint32_t* flags, hipStream_t s);
 void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const int32_t* pcls,
                         const ClassDesc* cls, const uint64_t* S, uint32_t mfma_min_q,
                         uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz, uint32_t* pm,
                         uint32_t* pv, uint32_t* pt, unsigned long long* st, hipStream_t s);
 void launch_fill_level(uint64_t n, const uint32_t* parent, const int32_t* pcls,
-                       const ClassDesc* cls, const uint32_t* child_item, const uint32_t* tri,
-                       const uint64_t* S, uint32_t minsup, uint32_t* nitem, uint32_t* nparent,
-                       uint32_t* nsupp, hipStream_t s);
+                       const ClassDesc* cls, const DbInfo* dbs, const uint32_t* child_item,
+                       const uint32_t* tri, const uint64_t* S, uint32_t* nitem, uint32_t* nparent,
+                       uint32_t* nsupp, uint32_t* ndbv, hipStream_t s);
+void launch_class_task_counts(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs,
+                              uint32_t mfma_min_q, const TaskGeom& geo, uint32_t* cm, uint32_t* cv,
+                              uint32_t* ct, hipStream_t s);
+void launch_write_class_tasks(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs,
+                              uint32_t mfma_min_q, const TaskGeom& geo, const uint64_t* om,
+                              const uint64_t* ov, const uint64_t* ot, Task* tm, Task* tv, Task* tt,
+                              hipStream_t s);
 void launch_fill_classes(uint64_t n, uint32_t k, const uint32_t* cnt, const uint64_t* child_start,
-                         const uint64_t* cls_pos, const uint64_t* tri_off, const uint64_t* pm_off,
-                         const uint64_t* pv_off, const uint64_t* pt_off, uint32_t mfma_min_q,
-                         const LevelPtrs& lv, const uint32_t* f1, ClassDesc* ocls, uint32_t* opre,
-                         int32_t* pcls_out, const TaskGeom& geo, Task* tm, Task* tv, Task* tt,
-                         hipStream_t s);
-void launch_root_tasks(uint32_t q, uint32_t npairs, uint32_t block, uint32_t nsplit,
-                       uint32_t split_len, uint32_t wend, Task* out, hipStream_t s);
+                         const uint64_t* cls_pos, const uint64_t* tri_off, const LevelPtrs& lv,
+                         const uint32_t* node_db, const DbInfo* dbs, ClassDesc* ocls,
+                         uint32_t* opre, int32_t* pcls_out, hipStream_t s);
 void launch_emit_sizes(uint64_t n, uint32_t k, const uint64_t* cstart, const uint64_t* SZn,
                        const uint64_t* ISZn, uint64_t* sz, uint64_t* isz, hipStream_t s);
 void launch_emit_pos(uint64_t n, uint32_t k, const uint32_t* parent, const uint64_t* ppre,
                      const uint64_t* poff, const uint64_t* pcstart, const uint64_t* SZ,
                      const uint64_t* ISZ, uint64_t* pre, uint64_t* off, hipStream_t s);
 void launch_emit_write(uint64_t n, uint32_t k, const uint64_t* pre, const uint64_t* off,
-                       const uint32_t* supp, const LevelPtrs& lv, const uint32_t* f1,
-                       uint64_t* o_off, uint32_t* o_items, uint32_t* o_supp, hipStream_t s);
+                       const uint32_t* supp, const uint32_t* node_db, const LevelPtrs& lv,
+                       const DbInfo* dbs, uint64_t* o_off, uint32_t* o_items, uint32_t* o_supp,
+                       hipStream_t s);
 void launch_put_u64(uint64_t* dst, const uint64_t* src, hipStream_t s);
+void launch_rebase(const uint64_t* src, uint64_t n, uint64_t base, uint64_t* dst, hipStream_t s);
+void launch_db_bounds(const uint32_t* node_db, uint64_t n, uint32_t ndb, uint64_t* first,
+                      hipStream_t s);
 void launch_expand_pairs(uint32_t k, const uint32_t* items, const uint32_t* colsum,
                          const uint32_t* tri, uint32_t* out, hipStream_t s);
 

@@ -2,8 +2,9 @@
 //
 // bm_build (Section III, matrix construction, Eq. 1) validates the CSR on the
 // device, packs it into column bitsets and counts every column (Eq. 3's
-// column aggregation).  bm_mine extends frequent prefixes level by level
-// (the paper's recursive mining by sequential column ANDs):
+// column aggregation).  Mining extends frequent prefixes level by level (the
+// paper's recursive mining by sequential column ANDs), for one database or a
+// whole batch at once:
 //   level 1: frequent single items (column popcounts >= minsup);
 //   level 2: all pairs of frequent items -- the Gram matrix A^T A on int8 MFMA
 //            (or AND+popcount when there are few items);
@@ -11,7 +12,7 @@
 //            its q(q-1)/2 sibling pairs, big classes as a masked Gram matrix on
 //            MFMA, small ones with AND+popcount;
 // and finally writes the frequent itemsets in canonical order.  One host sync
-// per level reads back the next level's sizes.
+// per level reads back the next level's sizes -- for the whole batch.
 #include <algorithm>
 #include <chrono>
 #include <memory>
@@ -72,10 +73,15 @@ T read_back(const T* dev, hipStream_t s) {
   return v;
 }
 
-void scan_ge(const uint32_t* in, uint32_t thr, uint64_t* out, uint64_t n, hipStream_t s) {
-  TBuf<uint64_t> tmp(scan_tmp_words(n), s);
-  scan_ge_u32(in, thr, out, n, tmp.get(), s);
+// Host -> device copy of a small host array.  hipMemcpyAsync from pageable
+// memory may still be reading the source after returning, so the source is
+// kept alive by the caller until the call's scope synchronises.
+template <class T>
+void upload(T* dst, const std::vector<T>& src, hipStream_t s) {
+  if (!src.empty())
+    BM_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
+
 void scan32(const uint32_t* in, uint64_t* out, uint64_t n, hipStream_t s) {
   TBuf<uint64_t> tmp(scan_tmp_words(n), s);
   scan_u32_to_u64(in, out, n, tmp.get(), s);
@@ -84,131 +90,141 @@ void scan64(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s) {
   TBuf<uint64_t> tmp(scan_tmp_words(n), s);
   scan_u64(in, out, n, tmp.get(), s);
 }
+// Scan of up to 8 same-length arrays (is64[j]: element type of in[j]).
+void scan_many(const void* const* in, const bool* is64, uint64_t* const* out, int count, uint64_t n,
+               hipStream_t s) {
+  ScanMulti sm{};
+  for (int j = 0; j < count; ++j) {
+    sm.in[j] = in[j];
+    sm.is64[j] = is64[j] ? 1u : 0u;
+    sm.out[j] = out[j];
+  }
+  if (scan_multi_single(sm, count, n, s)) return;
+  for (int j = 0; j < count; ++j) {
+    if (is64[j]) scan64(static_cast<const uint64_t*>(in[j]), out[j], n, s);
+    else scan32(static_cast<const uint32_t*>(in[j]), out[j], n, s);
+  }
+}
 
 uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 uint64_t round_up(uint64_t a, uint64_t b) { return ceil_div(a, b) * b; }
 
-TaskGeom make_geom(uint64_t W, uint64_t pairs_m, uint64_t pairs_v, uint64_t classes_t,
+// Word-split lengths for a step: enough tasks to fill the chip, not shorter
+// than a minimum that keeps per-task overheads small.
+TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_v, uint64_t classes_t,
                    const Tuning& tu) {
   const uint64_t target = (uint64_t)cu_count() * 8;
+  const uint64_t W = std::max<uint64_t>(1, Wmax);
   TaskGeom g{};
-  const uint64_t Wm = std::max<uint64_t>(16, round_up(W, GRAM_KW));
-  uint64_t sm;
-  if (tu.split_words) {
-    sm = round_up(tu.split_words, GRAM_KW);
-  } else {
-    uint64_t ns = pairs_m ? ceil_div(target, pairs_m) : 1;
-    ns = std::min<uint64_t>(ns, std::max<uint64_t>(1, Wm / 256));
-    sm = round_up(ceil_div(Wm, ns), GRAM_KW);
-  }
-  g.split_m = (uint32_t)sm;
-  g.nsplit_m = (uint32_t)ceil_div(Wm, sm);
-  g.wend_m = (uint32_t)Wm;
-  const uint64_t Wv = std::max<uint64_t>(1, W);
-  uint64_t sv;
-  if (tu.split_words) {
-    sv = tu.split_words;
-  } else {
-    uint64_t ns = pairs_v ? ceil_div(target, pairs_v) : 1;
-    ns = std::min<uint64_t>(ns, std::max<uint64_t>(1, Wv / 512));
-    sv = ceil_div(Wv, ns);
-  }
-  g.split_v = (uint32_t)sv;
-  g.nsplit_v = (uint32_t)ceil_div(Wv, sv);
-  g.wend_v = (uint32_t)Wv;
-  uint64_t st;
-  if (tu.split_words) {
-    st = tu.split_words;
-  } else {
-    uint64_t ns = classes_t ? ceil_div(target, classes_t) : 1;
-    ns = std::min<uint64_t>(ns, std::max<uint64_t>(1, Wv / 2048));
-    st = round_up(ceil_div(Wv, ns), 64);
-  }
-  g.split_t = (uint32_t)st;
-  g.nsplit_t = (uint32_t)ceil_div(Wv, st);
-  g.wend_t = (uint32_t)Wv;
+  auto pick = [&](uint64_t units, uint64_t min_len, uint64_t align) {
+    if (tu.split_words) return round_up(tu.split_words, align);
+    uint64_t ns = units ? ceil_div(target, units) : 1;
+    ns = std::min<uint64_t>(ns, std::max<uint64_t>(1, W / min_len));
+    return round_up(ceil_div(W, ns), align);
+  };
+  g.split_m = (uint32_t)pick(pairs_m, 256, GRAM_KW);
+  g.split_v = (uint32_t)pick(pairs_v, 512, 1);
+  g.split_t = (uint32_t)pick(classes_t, 2048, 64);
   return g;
 }
 
 // Device-side work of one level step.
 struct StepWork {
+  uint64_t ncls = 0;
   TBuf<ClassDesc> cls;
   TBuf<uint32_t> pre;
   TBuf<Task> tm, tv, tt;
-  uint64_t ntm = 0, ntv = 0, ntt = 0;
+  uint64_t ub_m = 0, ub_v = 0, ub_t = 0;  // task-count upper bounds (host)
+  TBuf<uint64_t> om, ov, ot;              // task offsets per class (+ total at [ncls])
   TBuf<uint32_t> tri;
   uint64_t T = 0;
   uint64_t st[ST_COUNT] = {};
 };
 
-void run_class_kernels(const bm_db* db, const uint32_t* f1, const uint32_t* child_item,
-                       const StepWork& w, const Tuning& tu, KTimer& tm, hipStream_t s) {
-  ClassArgs a{db->B.get(), db->Wp, f1, child_item, w.cls.get(), w.pre.get(), nullptr, 0, w.tri.get()};
+// Task lists of a step's classes: counts per class on the device, scanned
+// offsets, then the records.  The kernels read the totals from device memory;
+// the host only sizes buffers from upper bounds.
+void prepare_tasks(StepWork& w, const DbInfo* ddb, uint64_t Wmax, uint64_t pairs_m,
+                   uint64_t pairs_v, uint64_t classes_t, const Tuning& tu, hipStream_t s) {
+  const TaskGeom g = make_geom(Wmax, pairs_m, pairs_v, classes_t, tu);
+  const uint64_t Wm = round_up(std::max<uint64_t>(1, Wmax), GRAM_KW);
+  w.ub_m = pairs_m * ceil_div(Wm, g.split_m);
+  w.ub_v = pairs_v * ceil_div(std::max<uint64_t>(1, Wmax), g.split_v);
+  w.ub_t = classes_t * ceil_div(std::max<uint64_t>(1, Wmax), g.split_t);
+  TBuf<uint32_t> cm(w.ncls, s), cv(w.ncls, s), ct(w.ncls, s);
+  w.om.alloc(w.ncls + 1, s);
+  w.ov.alloc(w.ncls + 1, s);
+  w.ot.alloc(w.ncls + 1, s);
+  launch_class_task_counts(w.cls.get(), w.ncls, ddb, tu.mfma_min_q, g, cm.get(), cv.get(), ct.get(),
+                           s);
+  const void* in[3] = {cm.get(), cv.get(), ct.get()};
+  const bool is64[3] = {false, false, false};
+  uint64_t* out[3] = {w.om.get(), w.ov.get(), w.ot.get()};
+  scan_many(in, is64, out, 3, w.ncls, s);
+  w.tm.alloc(w.ub_m, s);
+  w.tv.alloc(w.ub_v, s);
+  w.tt.alloc(w.ub_t, s);
+  launch_write_class_tasks(w.cls.get(), w.ncls, ddb, tu.mfma_min_q, g, w.om.get(), w.ov.get(),
+                           w.ot.get(), w.tm.get(), w.tv.get(), w.tt.get(), s);
+}
+
+void run_class_kernels(const DbInfo* ddb, const uint32_t* child_item, const StepWork& w,
+                       const Tuning& tu, double nW, double nN, KTimer& tm, hipStream_t s) {
+  ClassArgs a{ddb, child_item, w.cls.get(), w.pre.get(), nullptr, nullptr, w.tri.get()};
   const uint64_t ncu = (uint64_t)cu_count();
-  if (w.ntm) {
-    if (w.ntm > 0xffffffffull) fail(BM_ERR_UNSUPPORTED, "too many MFMA tasks");
+  if (w.ub_m) {
     a.tasks = w.tm.get();
-    a.ntasks = (uint32_t)w.ntm;
+    a.ntasks = w.om.get() + w.ncls;
     tm.begin(BM_K_GRAM_MFMA);
-    launch_gram_mfma(a, (uint32_t)std::min<uint64_t>(w.ntm, ncu * 4), s);
-    tm.end(8.0 * (double)db->W * (double)w.st[ST_COLS_M],
-           2.0 * (double)w.st[ST_CAND_M] * (double)db->n);
+    launch_gram_mfma(a, (uint32_t)std::min<uint64_t>(w.ub_m, ncu * 4), s);
+    tm.end(8.0 * nW * (double)w.st[ST_COLS_M], 2.0 * (double)w.st[ST_CAND_M] * nN);
   }
-  if (w.ntv) {
-    if (w.ntv > 0xffffffffull) fail(BM_ERR_UNSUPPORTED, "too many AND+popcount tasks");
+  if (w.ub_v) {
     a.tasks = w.tv.get();
-    a.ntasks = (uint32_t)w.ntv;
+    a.ntasks = w.ov.get() + w.ncls;
     tm.begin(BM_K_ANDPOP);
-    launch_andpop(a, tu.andpop_chunk, (uint32_t)std::min<uint64_t>(w.ntv, ncu * 8), s);
-    tm.end(8.0 * (double)db->W * (double)w.st[ST_COLS_V], (double)w.st[ST_CAND_V] * (double)db->W);
+    launch_andpop(a, tu.andpop_chunk, (uint32_t)std::min<uint64_t>(w.ub_v, ncu * 8), s);
+    tm.end(8.0 * nW * (double)w.st[ST_COLS_V], (double)w.st[ST_CAND_V] * nW);
   }
-  if (w.ntt) {
-    if (w.ntt > 0xffffffffull) fail(BM_ERR_UNSUPPORTED, "too many AND+popcount tasks");
+  if (w.ub_t) {
     a.tasks = w.tt.get();
-    a.ntasks = (uint32_t)w.ntt;
+    a.ntasks = w.ot.get() + w.ncls;
     tm.begin(BM_K_ANDPOP_REG);
-    launch_andpop_reg(a, (uint32_t)std::min<uint64_t>(w.ntt, ncu * 8), s);
-    tm.end(8.0 * (double)db->W * (double)w.st[ST_COLS_T], (double)w.st[ST_CAND_T] * (double)db->W);
+    launch_andpop_reg(a, (uint32_t)std::min<uint64_t>(w.ub_t, ncu * 8), s);
+    tm.end(8.0 * nW * (double)w.st[ST_COLS_T], (double)w.st[ST_CAND_T] * nW);
   }
 }
 
-// One class (the root, or an explicit column list) with q children.
-void single_class(StepWork& w, uint32_t q, uint64_t W, const Tuning& tu, hipStream_t s) {
-  ClassDesc cd{0, 0, q, 0, 0};
-  w.cls.alloc(1, s);
-  BM_HIP(hipMemcpyAsync(w.cls.get(), &cd, sizeof(cd), hipMemcpyHostToDevice, s));
+// Classes given on the host (the roots of each database, or an explicit
+// column list): records, a zeroed triangle buffer and the task lists.
+void host_classes(StepWork& w, const std::vector<ClassDesc>& hc, const DbInfo* ddb, uint64_t Wmax,
+                  const Tuning& tu, hipStream_t s) {
+  w.ncls = hc.size();
+  w.cls.alloc(w.ncls, s);
+  upload(w.cls.get(), hc, s);
   w.pre.alloc(1, s);
   launch_fill_u32(w.pre.get(), 0, 1, s);
-  w.T = (uint64_t)q * (q - 1) / 2;
+  uint64_t pm = 0, pv = 0, ct = 0;
+  w.T = 0;
+  for (const auto& c : hc) {
+    const uint64_t tsz = (uint64_t)c.q * (c.q - 1) / 2;
+    w.T += tsz;
+    const int kind = class_kind(c.q, tu.mfma_min_q);
+    if (kind == 0) pm += host_mfma_pairs(c.q);
+    else if (kind == 1) pv += host_andpop_pairs(c.q);
+    else ct += 1;
+    w.st[ST_CAND_M + kind] += tsz;
+    w.st[ST_COLS_M + kind] += c.q;
+    w.st[ST_CLS_M + kind] += 1;
+  }
   w.tri.alloc(w.T, s);
   launch_fill_u32(w.tri.get(), 0, w.T, s);
-  const int kind = class_kind(q, tu.mfma_min_q);
-  const uint64_t pm = kind == 0 ? host_mfma_pairs(q) : 0;
-  const uint64_t pv = kind == 1 ? host_andpop_pairs(q) : 0;
-  const TaskGeom g = make_geom(W, pm, pv, kind == 2 ? 1 : 0, tu);
-  if (kind == 0) {
-    w.ntm = pm * g.nsplit_m;
-    w.tm.alloc(w.ntm, s);
-    launch_root_tasks(q, (uint32_t)pm, GRAM_TILE, g.nsplit_m, g.split_m, g.wend_m, w.tm.get(), s);
-  } else if (kind == 1) {
-    w.ntv = pv * g.nsplit_v;
-    w.tv.alloc(w.ntv, s);
-    launch_root_tasks(q, (uint32_t)pv, AP_BLOCK, g.nsplit_v, g.split_v, g.wend_v, w.tv.get(), s);
-  } else {
-    w.ntt = g.nsplit_t;
-    w.tt.alloc(w.ntt, s);
-    launch_root_tasks(q, 1, TINY_Q, g.nsplit_t, g.split_t, g.wend_t, w.tt.get(), s);
-  }
-  w.st[ST_CAND_M + kind] = w.T;
-  w.st[ST_COLS_M + kind] = q;
-  w.st[ST_CLS_M + kind] = 1;
-  // hipMemcpyAsync from pageable memory may still read `cd` after returning
-  BM_HIP(hipStreamSynchronize(s));
+  prepare_tasks(w, ddb, Wmax, pm, pv, ct, tu, s);
 }
 
 struct Level {
   uint64_t n = 0;
-  TBuf<uint32_t> item, parent, supp;
+  TBuf<uint32_t> item, parent, supp, db;
   TBuf<uint64_t> cstart;  // n + 1, child ranges in the next level
 };
 
@@ -316,11 +332,11 @@ void pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* 
   if (!items && k != db->m) fail(BM_ERR_INVALID_ARG, "items == NULL requires k == n_items");
   CallScope scope(s);
   TBuf<uint32_t> d_items(k, s);
+  std::vector<uint32_t> h_items;
   if (!items) {
-    std::vector<uint32_t> h(k);
-    for (uint32_t i = 0; i < k; ++i) h[i] = i;
-    BM_HIP(hipMemcpyAsync(d_items.get(), h.data(), (size_t)k * 4, hipMemcpyHostToDevice, s));
-    BM_HIP(hipStreamSynchronize(s));
+    h_items.resize(k);
+    for (uint32_t i = 0; i < k; ++i) h_items[i] = i;
+    upload(d_items.get(), h_items, s);
   } else if (is_device_ptr(items)) {
     BM_HIP(hipMemcpyAsync(d_items.get(), items, (size_t)k * 4, hipMemcpyDeviceToDevice, s));
     TBuf<uint32_t> err(1, s);
@@ -330,15 +346,21 @@ void pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* 
   } else {
     for (uint32_t i = 0; i < k; ++i)
       if (items[i] >= db->m) fail(BM_ERR_INVALID_ARG, "items[%u] = %u >= n_items", i, items[i]);
-    BM_HIP(hipMemcpyAsync(d_items.get(), items, (size_t)k * 4, hipMemcpyHostToDevice, s));
-    BM_HIP(hipStreamSynchronize(s));
+    h_items.assign(items, items + k);
+    upload(d_items.get(), h_items, s);
   }
   const Tuning tu;
+  std::vector<DbInfo> hdb(1);
+  hdb[0] = DbInfo{db->B.get(), db->Wp, db->W, db->n, nullptr, db->colsum.get(), 1, db->m};
+  TBuf<DbInfo> ddb(1, s);
+  upload(ddb.get(), hdb, s);
   StepWork w;
+  std::vector<ClassDesc> hc;
   if (k >= 2) {
-    single_class(w, k, db->W, tu, s);
+    hc.push_back(ClassDesc{0, 0, k, 0, 0, 0, 0});
+    host_classes(w, hc, ddb.get(), db->W, tu, s);
     KTimer tm(false, s);
-    run_class_kernels(db, nullptr, d_items.get(), w, tu, tm, s);
+    run_class_kernels(ddb.get(), d_items.get(), w, tu, (double)db->W, (double)db->n, tm, s);
   }
   const bool out_dev = is_device_ptr(out);
   TBuf<uint32_t> d_out;
@@ -355,50 +377,113 @@ void pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* 
 
 // ------------------------------------------------------------------ mining
 
-bm_result* mine(const bm_db* db, uint32_t minsup, const bm_options* opt, hipStream_t s) {
+std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsups, uint32_t N,
+                                  const bm_options* opt, hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
-  if (minsup == 0) fail(BM_ERR_INVALID_ARG, "minsup must be >= 1");
+  for (uint32_t d = 0; d < N; ++d)
+    if (minsups[d] == 0) fail(BM_ERR_INVALID_ARG, "minsup of database %u must be >= 1", d);
   const Tuning tu = tuning_from(opt);
   const uint32_t flags = opt ? opt->flags : 0u;
-  std::unique_ptr<bm_result> res(new bm_result);
-  res->device = db->device;
-  bm_stats& st = res->stats;
+  int device = 0;
+  BM_HIP(hipGetDevice(&device));
+  auto store = std::make_shared<ResultStore>();
+  bm_stats st{};
   KTimer tm((flags & BM_FLAG_TIMING) != 0, s);
+  std::vector<uint64_t> Fs(N + 1, 0), Is(N + 1, 0);
+  std::vector<std::vector<uint64_t>> per_level;  // [k] -> first node of each database (N+1)
+  uint32_t K = 0;
   {
     CallScope scope(s);
-    const uint32_t m = db->m;
-    const uint64_t n = db->n;
-    std::vector<Level> L(1);
-    TBuf<uint32_t> f1;
-    uint64_t m1 = 0;
-    if (n > 0 && m > 0 && minsup <= n) {
-      TBuf<uint64_t> pos(m + 1, s);
-      tm.begin(BM_K_LEVEL);
-      scan_ge(db->colsum.get(), minsup, pos.get(), m, s);
-      tm.end();
-      m1 = read_back(pos.get() + m, s);
-      st.host_syncs++;
-      if (m1 > 0) {
-        f1.alloc(m1, s);
-        launch_f1_fill(db->colsum.get(), m, minsup, pos.get(), f1.get(), s);
-        L.emplace_back();
-        L[1].n = m1;
-        L[1].item.alloc(m1, s);
-        L[1].parent.alloc(m1, s);
-        L[1].supp.alloc(m1, s);
-        launch_init_level1(db->colsum.get(), f1.get(), (uint32_t)m1, L[1].item.get(),
-                           L[1].parent.get(), L[1].supp.get(), s);
+    // ---- database table
+    std::vector<DbInfo> hdb(N), hdb2(N);
+    std::vector<uint64_t> item_base(N + 1, 0);
+    uint64_t Wmax = 1;
+    double sumW = 0, sumN = 0;
+    for (uint32_t d = 0; d < N; ++d) {
+      const bm_db* b = dbs[d];
+      const bool live = b && b->n > 0 && b->m > 0 && minsups[d] <= b->n;
+      hdb[d] = DbInfo{};
+      if (b) hdb[d] = DbInfo{b->B.get(), b->Wp, b->W, b->n, nullptr, b->colsum.get(), minsups[d],
+                             live ? b->m : 0u};
+      item_base[d + 1] = item_base[d] + hdb[d].m;
+      if (live) {
+        Wmax = std::max<uint64_t>(Wmax, b->W);
+        sumW += (double)b->W;
+        sumN += (double)b->n;
       }
     }
-    st.n_frequent_items = (uint32_t)m1;
-    if (m1 > 0) st.frequent[1] = m1;
+    const double nW = N ? sumW / N : 0, nN = N ? sumN / N : 0;  // per-database means for work counts
+    // one threshold for every live database lets the candidate threshold skip the class lookup
+    uint32_t uniform_thr = 0;
+    for (uint32_t d = 0; d < N; ++d) {
+      if (!hdb[d].m) continue;
+      if (uniform_thr == 0) uniform_thr = minsups[d];
+      else if (uniform_thr != minsups[d]) uniform_thr = 0xffffffffu;
+    }
+    if (uniform_thr == 0xffffffffu) uniform_thr = 0;
+    TBuf<DbInfo> ddb(std::max<uint32_t>(N, 1), s);
+    upload(ddb.get(), hdb, s);
+    TBuf<uint64_t> dibase(N + 1, s);
+    upload(dibase.get(), item_base, s);
+    const uint64_t total_items = item_base[N];
+
+    // ---- frequent single items of every database
+    std::vector<uint64_t> f1_base(N + 1, 0);
+    TBuf<uint64_t> dfb(N + 1, s);
+    TBuf<uint32_t> f1;
+    std::vector<Level> L(1);
+    if (total_items > 0) {
+      tm.begin(BM_K_LEVEL);
+      TBuf<uint32_t> fl(total_items, s);
+      TBuf<uint64_t> pos(total_items + 1, s);
+      launch_f1_flags(ddb.get(), N, dibase.get(), total_items, fl.get(), s);
+      scan32(fl.get(), pos.get(), total_items, s);
+      launch_gather_idx(pos.get(), dibase.get(), N + 1, dfb.get(), s);
+      tm.end();
+      BM_HIP(hipMemcpyAsync(f1_base.data(), dfb.get(), (N + 1) * 8, hipMemcpyDeviceToHost, s));
+      BM_HIP(hipStreamSynchronize(s));
+      st.host_syncs++;
+      const uint64_t M1 = f1_base[N];
+      if (M1 > 0) {
+        tm.begin(BM_K_LEVEL);
+        f1.alloc(M1, s);
+        launch_f1_fill(fl.get(), pos.get(), N, dibase.get(), total_items, f1.get(), s);
+        for (uint32_t d = 0; d < N; ++d) {
+          hdb2[d] = hdb[d];
+          hdb2[d].f1 = f1.get() + f1_base[d];
+        }
+        upload(ddb.get(), hdb2, s);
+        L.emplace_back();
+        L[1].n = M1;
+        L[1].item.alloc(M1, s);
+        L[1].parent.alloc(M1, s);
+        L[1].supp.alloc(M1, s);
+        L[1].db.alloc(M1, s);
+        launch_init_level1(ddb.get(), N, dfb.get(), M1, f1.get(), L[1].item.get(), L[1].parent.get(),
+                           L[1].supp.get(), L[1].db.get(), s);
+        tm.end();
+      }
+    }
+    st.n_frequent_items = (uint32_t)std::min<uint64_t>(f1_base[N], 0xffffffffu);
+    if (f1_base[N]) st.frequent[1] = f1_base[N];
 
     // ---- level steps
-    if (m1 >= 2) {
-      TBuf<int32_t> pcls_prev(1, s);
-      launch_fill_u32(reinterpret_cast<uint32_t*>(pcls_prev.get()), 0, 1, s);
+    std::vector<ClassDesc> roots;
+    std::vector<int32_t> hpcls(std::max<uint32_t>(N, 1), -1);
+    uint64_t tri_off = 0;
+    for (uint32_t d = 0; d < N; ++d) {
+      const uint64_t q = f1_base[d + 1] - f1_base[d];
+      if (q >= 2) {
+        hpcls[d] = (int32_t)roots.size();
+        roots.push_back(ClassDesc{tri_off, (uint32_t)f1_base[d], (uint32_t)q, 0, 0, d, 0});
+        tri_off += q * (q - 1) / 2;
+      }
+    }
+    if (!roots.empty()) {
+      TBuf<int32_t> pcls_prev(hpcls.size(), s);
+      upload(pcls_prev.get(), hpcls, s);
       auto w = std::make_unique<StepWork>();
-      single_class(*w, (uint32_t)m1, db->W, tu, s);
+      host_classes(*w, roots, ddb.get(), Wmax, tu, s);
       uint32_t k = 1;
       for (;;) {
         const uint64_t nk = L[k].n;
@@ -406,11 +491,14 @@ bm_result* mine(const bm_db* db, uint32_t minsup, const bm_options* opt, hipStre
         st.candidates_total += w->T;
         st.classes_mfma += w->st[ST_CLS_M];
         st.classes_andpop += w->st[ST_CLS_V] + w->st[ST_CLS_T];
-        run_class_kernels(db, f1.get(), L[k].item.get(), *w, tu, tm, s);
+        run_class_kernels(ddb.get(), L[k].item.get(), *w, tu, nW, nN, tm, s);
 
         tm.begin(BM_K_LEVEL);
+        TBuf<uint32_t> tfl(w->T, s);
         TBuf<uint64_t> S(w->T + 1, s);
-        scan_ge(w->tri.get(), minsup, S.get(), w->T, s);
+        launch_tri_flags(w->cls.get(), w->ncls, ddb.get(), w->tri.get(), w->T, uniform_thr, tfl.get(),
+                         s);
+        scan32(tfl.get(), S.get(), w->T, s);
         TBuf<uint32_t> cnt(nk, s), iscls(nk, s), pm(nk, s), pv(nk, s), pt(nk, s);
         TBuf<uint64_t> trisz(nk, s);
         TBuf<unsigned long long> dst(ST_COUNT, s);
@@ -421,22 +509,11 @@ bm_result* mine(const bm_db* db, uint32_t minsup, const bm_options* opt, hipStre
         L[k].cstart.alloc(nk + 1, s);
         TBuf<uint64_t> clspos(nk + 1, s), trioff(nk + 1, s), pmoff(nk + 1, s), pvoff(nk + 1, s),
             ptoff(nk + 1, s);
-        ScanMulti sm{};
         const void* ins[6] = {cnt.get(), iscls.get(), trisz.get(), pm.get(), pv.get(), pt.get()};
+        const bool is64[6] = {false, false, true, false, false, false};
         uint64_t* outs[6] = {L[k].cstart.get(), clspos.get(), trioff.get(), pmoff.get(), pvoff.get(),
                              ptoff.get()};
-        for (int j = 0; j < 6; ++j) {
-          sm.in[j] = ins[j];
-          sm.is64[j] = j == 2;
-          sm.out[j] = outs[j];
-        }
-        if (!scan_multi_single(sm, 6, nk, s)) {
-          for (int j = 0; j < 6; ++j) {
-            if (j == 2) scan64(trisz.get(), outs[j], nk, s);
-            else scan32(static_cast<const uint32_t*>(ins[j]), outs[j], nk, s);
-          }
-        }
-        tm.end();
+        scan_many(ins, is64, outs, 6, nk, s);
         uint64_t tot[6 + ST_COUNT];
         GatherU64 gsrc{};
         for (int j = 0; j < 6; ++j) gsrc.src[j] = outs[j] + nk;
@@ -444,6 +521,7 @@ bm_result* mine(const bm_db* db, uint32_t minsup, const bm_options* opt, hipStre
           gsrc.src[6 + j] = reinterpret_cast<const uint64_t*>(dst.get()) + j;
         TBuf<uint64_t> dtot(6 + ST_COUNT, s);
         launch_gather_u64(gsrc, 6 + ST_COUNT, dtot.get(), s);
+        tm.end();
         BM_HIP(hipMemcpyAsync(tot, dtot.get(), sizeof(tot), hipMemcpyDeviceToHost, s));
         BM_HIP(hipStreamSynchronize(s));
         st.host_syncs++;
@@ -459,41 +537,34 @@ bm_result* mine(const bm_db* db, uint32_t minsup, const bm_options* opt, hipStre
         Ln.item.alloc(n_next, s);
         Ln.parent.alloc(n_next, s);
         Ln.supp.alloc(n_next, s);
+        Ln.db.alloc(n_next, s);
         tm.begin(BM_K_LEVEL);
-        launch_fill_level(nk, L[k].parent.get(), pcls_prev.get(), w->cls.get(), L[k].item.get(),
-                          w->tri.get(), S.get(), minsup, Ln.item.get(), Ln.parent.get(),
-                          Ln.supp.get(), s);
-        tm.end();
+        launch_fill_level(nk, L[k].parent.get(), pcls_prev.get(), w->cls.get(), ddb.get(),
+                          L[k].item.get(), w->tri.get(), S.get(), Ln.item.get(), Ln.parent.get(),
+                          Ln.supp.get(), Ln.db.get(), s);
         st.frequent[k + 1] = n_next;
         if (ncls == 0) {
+          tm.end();
           k += 1;
           break;
         }
         auto nw = std::make_unique<StepWork>();
+        nw->ncls = ncls;
         nw->cls.alloc(ncls, s);
         nw->pre.alloc(ncls * k, s);
         TBuf<int32_t> pcls_k(nk, s);
         nw->T = Tn;
         nw->tri.alloc(Tn, s);
         launch_fill_u32(nw->tri.get(), 0, Tn, s);
-        const TaskGeom g = make_geom(db->W, PM, PV, PT, tu);
-        nw->ntm = PM * g.nsplit_m;
-        nw->ntv = PV * g.nsplit_v;
-        nw->ntt = PT * g.nsplit_t;
-        nw->tm.alloc(nw->ntm, s);
-        nw->tv.alloc(nw->ntv, s);
-        nw->tt.alloc(nw->ntt, s);
         for (int j = 0; j < ST_COUNT; ++j) nw->st[j] = tot[6 + j];
         LevelPtrs lv{};
         for (uint32_t j = 1; j <= k; ++j) {
           lv.item[j] = L[j].item.get();
           lv.parent[j] = L[j].parent.get();
         }
-        tm.begin(BM_K_LEVEL);
-        launch_fill_classes(nk, k, cnt.get(), L[k].cstart.get(), clspos.get(), trioff.get(),
-                            pmoff.get(), pvoff.get(), ptoff.get(), tu.mfma_min_q, lv, f1.get(),
-                            nw->cls.get(), nw->pre.get(), pcls_k.get(), g, nw->tm.get(),
-                            nw->tv.get(), nw->tt.get(), s);
+        launch_fill_classes(nk, k, cnt.get(), L[k].cstart.get(), clspos.get(), trioff.get(), lv,
+                            L[k].db.get(), ddb.get(), nw->cls.get(), nw->pre.get(), pcls_k.get(), s);
+        prepare_tasks(*nw, ddb.get(), Wmax, PM, PV, PT, tu, s);
         tm.end();
         w = std::move(nw);
         pcls_prev = pcls_k;
@@ -501,23 +572,20 @@ bm_result* mine(const bm_db* db, uint32_t minsup, const bm_options* opt, hipStre
       }
     }
 
-    // ---- canonical output
-    const uint32_t K = (uint32_t)L.size() - 1;
+    // ---- canonical output (all databases as one forest, database by database)
+    K = (uint32_t)L.size() - 1;
     uint64_t F = 0, TI = 0;
     for (uint32_t k = 1; k <= K; ++k) {
       F += L[k].n;
       TI += (uint64_t)k * L[k].n;
     }
-    res->n_sets = F;
-    res->n_items = TI;
-    res->max_len = K;
     st.max_len = K;
     st.frequent_total = F;
-    res->offsets.reset(F + 1, s);
-    res->items.reset(TI, s);
-    res->supports.reset(F, s);
+    store->offsets.reset(F + 1, s);
+    store->items.reset(TI, s);
+    store->supports.reset(F, s);
     if (F == 0) {
-      launch_fill_u64(res->offsets.get(), 0, 1, s);
+      launch_fill_u64(store->offsets.get(), 0, 1, s);
     } else {
       tm.begin(BM_K_EMIT);
       std::vector<TBuf<uint64_t>> SZ(K + 2), ISZ(K + 2), pre(K + 1), off(K + 1);
@@ -529,16 +597,10 @@ bm_result* mine(const bm_db* db, uint32_t minsup, const bm_options* opt, hipStre
                           sz.get(), isz.get(), s);
         SZ[k].alloc(L[k].n + 1, s);
         ISZ[k].alloc(L[k].n + 1, s);
-        ScanMulti sm{};
-        sm.in[0] = sz.get();
-        sm.in[1] = isz.get();
-        sm.is64[0] = sm.is64[1] = 1;
-        sm.out[0] = SZ[k].get();
-        sm.out[1] = ISZ[k].get();
-        if (!scan_multi_single(sm, 2, L[k].n, s)) {
-          scan64(sz.get(), SZ[k].get(), L[k].n, s);
-          scan64(isz.get(), ISZ[k].get(), L[k].n, s);
-        }
+        const void* in[2] = {sz.get(), isz.get()};
+        const bool is64[2] = {true, true};
+        uint64_t* out[2] = {SZ[k].get(), ISZ[k].get()};
+        scan_many(in, is64, out, 2, L[k].n, s);
       }
       LevelPtrs lv{};
       for (uint32_t k = 1; k <= K; ++k) {
@@ -554,17 +616,82 @@ bm_result* mine(const bm_db* db, uint32_t minsup, const bm_options* opt, hipStre
       }
       for (uint32_t k = 1; k <= K; ++k) {
         launch_emit_write(L[k].n, k, k == 1 ? SZ[1].get() : pre[k].get(),
-                          k == 1 ? ISZ[1].get() : off[k].get(), L[k].supp.get(), lv, f1.get(),
-                          res->offsets.get(), res->items.get(), res->supports.get(), s);
+                          k == 1 ? ISZ[1].get() : off[k].get(), L[k].supp.get(), L[k].db.get(), lv,
+                          ddb.get(), store->offsets.get(), store->items.get(),
+                          store->supports.get(), s);
       }
-      launch_put_u64(res->offsets.get() + F, ISZ[1].get() + L[1].n, s);
+      launch_put_u64(store->offsets.get() + F, ISZ[1].get() + L[1].n, s);
+      // where each database's slice starts, and its per-length counts
+      TBuf<uint64_t> dFs(N + 1, s), dIs(N + 1, s);
+      launch_gather_idx(SZ[1].get(), dfb.get(), N + 1, dFs.get(), s);
+      launch_gather_idx(ISZ[1].get(), dfb.get(), N + 1, dIs.get(), s);
+      TBuf<uint64_t> bounds((size_t)(K + 1) * (N + 1), s);
+      for (uint32_t k = 1; k <= K; ++k)
+        launch_db_bounds(L[k].db.get(), L[k].n, N, bounds.get() + (size_t)k * (N + 1), s);
       tm.end();
+      BM_HIP(hipMemcpyAsync(Fs.data(), dFs.get(), (N + 1) * 8, hipMemcpyDeviceToHost, s));
+      BM_HIP(hipMemcpyAsync(Is.data(), dIs.get(), (N + 1) * 8, hipMemcpyDeviceToHost, s));
+      std::vector<uint64_t> hb((size_t)(K + 1) * (N + 1));
+      BM_HIP(hipMemcpyAsync(hb.data(), bounds.get(), hb.size() * 8, hipMemcpyDeviceToHost, s));
+      BM_HIP(hipStreamSynchronize(s));
+      per_level.assign(K + 1, {});
+      for (uint32_t k = 1; k <= K; ++k)
+        per_level[k].assign(hb.begin() + (size_t)k * (N + 1), hb.begin() + (size_t)(k + 1) * (N + 1));
     }
     BM_HIP(hipStreamSynchronize(s));
   }
   tm.collect(&st);
   st.wall_ms = ms_since(t0);
-  return res.release();
+  std::vector<bm_result*> out(N, nullptr);
+  for (uint32_t d = 0; d < N; ++d) {
+    auto r = std::make_unique<bm_result>();
+    r->device = device;
+    r->store = store;
+    r->set0 = Fs[d];
+    r->n_sets = Fs[d + 1] - Fs[d];
+    r->item0 = Is[d];
+    r->n_items = Is[d + 1] - Is[d];
+    r->stats = st;
+    if (N > 1) {
+      // per-database counts; candidates and kernel times stay batch-wide
+      std::fill(std::begin(r->stats.frequent), std::end(r->stats.frequent), 0ull);
+      uint32_t ml = 0;
+      for (uint32_t k = 1; k <= K && !per_level.empty(); ++k) {
+        const uint64_t c = per_level[k][d + 1] - per_level[k][d];
+        r->stats.frequent[k] = c;
+        if (c) ml = k;
+      }
+      r->stats.max_len = ml;
+      r->stats.frequent_total = r->n_sets;
+      r->stats.n_frequent_items = (uint32_t)r->stats.frequent[1];
+    }
+    r->max_len = r->stats.max_len;
+    out[d] = r.release();
+  }
+  return out;
+}
+
+void result_copy(const bm_result* r, uint64_t* offsets, uint32_t* items, uint32_t* supports,
+                 hipStream_t s) {
+  CallScope scope(s);
+  const ResultStore& st = *r->store;
+  if (offsets) {
+    if (r->item0 == 0) {
+      BM_HIP(hipMemcpyAsync(offsets, st.offsets.get() + r->set0, (r->n_sets + 1) * 8,
+                            hipMemcpyDefault, s));
+    } else if (is_device_ptr(offsets)) {
+      launch_rebase(st.offsets.get() + r->set0, r->n_sets + 1, r->item0, offsets, s);
+    } else {
+      TBuf<uint64_t> tmp(r->n_sets + 1, s);
+      launch_rebase(st.offsets.get() + r->set0, r->n_sets + 1, r->item0, tmp.get(), s);
+      BM_HIP(hipMemcpyAsync(offsets, tmp.get(), (r->n_sets + 1) * 8, hipMemcpyDeviceToHost, s));
+    }
+  }
+  if (items && r->n_items)
+    BM_HIP(hipMemcpyAsync(items, st.items.get() + r->item0, r->n_items * 4, hipMemcpyDefault, s));
+  if (supports && r->n_sets)
+    BM_HIP(hipMemcpyAsync(supports, st.supports.get() + r->set0, r->n_sets * 4, hipMemcpyDefault, s));
+  BM_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace bm

@@ -268,3 +268,49 @@ def test_repeated_calls_reuse_pool(bm):
         assert_same(bm.bm_mine(h, db.minsup).arrays(), first)
     bm.bm_release_cached_memory()
     assert_same(bm.bm_mine(h, db.minsup).arrays(), first)
+
+
+# ------------------------------------------------------------ batching
+
+def _batch_inputs(count=24, scale=0.05):
+    dbs = [gen.batch_db(k, scale=scale) for k in range(count)]
+    return dbs
+
+
+def test_batch_matches_single_and_oracle(bm):
+    dbs = _batch_inputs()
+    # a few degenerate members: empty database, minsup above n, a tiny one
+    dbs.append(gen.from_rows([], m=5, minsup=1))
+    tiny = gen.from_rows([[0, 1, 2], [0, 1], [1, 2], [0, 2]], m=3, minsup=2)
+    dbs.append(tiny)
+    handles = [bm.bm_build(d.row_ptr, d.col_idx, d.n, d.m) for d in dbs]
+    minsups = [d.minsup for d in dbs]
+    minsups[3] = dbs[3].n + 5
+    handles_with_none = handles[:5] + [None] + handles[5:]
+    minsups_with_none = minsups[:5] + [1] + minsups[5:]
+    for flags in (0, bm.FLAG_NO_MFMA, bm.FLAG_ALL_MFMA):
+        rs = bm.bm_mine_batch(handles_with_none, minsups_with_none, opts=bm.options(flags=flags))
+        assert len(rs) == len(handles_with_none)
+        assert len(rs[5]) == 0
+        rs = rs[:5] + rs[6:]
+        for d, h, s, r in zip(dbs, handles, minsups, rs):
+            print(f"batch member {d.name} minsup={s}", flush=True)
+            want = ocpp.OracleDb(d.row_ptr, d.col_idx, d.n, d.m).mine_arrays(s)[:3]
+            assert_same(r.arrays(), want)
+            assert_same(bm.bm_mine(h, s).arrays(), want)
+            st = r.stats()
+            assert st["frequent_total"] == len(want[2])
+            if len(want[2]):
+                lens = np.diff(want[0].astype(np.int64))
+                assert st["max_len"] == int(lens.max())
+
+
+def test_batch_device_tensor_copy(bm):
+    import torch
+    dbs = _batch_inputs(6)
+    handles = [bm.bm_build(d.row_ptr, d.col_idx, d.n, d.m) for d in dbs]
+    rs = bm.bm_mine_batch(handles, [d.minsup for d in dbs])
+    for d, r in zip(dbs, rs):
+        want = ocpp.OracleDb(d.row_ptr, d.col_idx, d.n, d.m).mine_arrays(d.minsup)[:3]
+        offs, items, supp = r.tensors("cuda")
+        assert_same((offs.cpu().numpy(), items.cpu().numpy(), supp.cpu().numpy()), want)
