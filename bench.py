@@ -28,6 +28,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 INT8_PEAK_TOPS = 5000.0
+# streaming kernels priced against HBM: algorithmic bytes = column words read
+HBM_KERNELS = {
+    "andpop": "k_andpop (AND+popcount of a prefix class, LDS-blocked)",
+    "andpop_reg": "k_andpop_reg (AND+popcount of a small prefix class in registers)",
+    "dfs": "k_dfs (persistent depth-first subtree mining from a work queue)",
+}
 
 WORKLOADS = {
     1: "basket_zipf 10,000 tx x 169 items, minsup 1% (100)",
@@ -71,6 +77,13 @@ def main():
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--mfma-min-children", type=int, default=0)
     ap.add_argument("--split-words", type=int, default=0)
+    ap.add_argument("--levelsync", action="store_true",
+                    help="plain level-synchronous miner (no depth-first phase)")
+    ap.add_argument("--dfs-threads", type=int, default=0)
+    ap.add_argument("--dfs-max-words", type=int, default=0)
+    ap.add_argument("--shuffle", type=int, default=0, help="random subtree-task order with this seed")
+    ap.add_argument("--sched", choices=["none", "learned"], default="none",
+                    help="learned: order subtree tasks by a cost model trained on a traced run")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="instead of mining, copy a buffer of this size (counter calibration)")
     args = ap.parse_args()
@@ -106,12 +119,30 @@ def main():
     ci = torch.from_numpy(db.col_idx.astype(np.uint32)).to(dev)
     stream = torch.cuda.current_stream()
     flags = 0 if args.no_timing else bm.FLAG_TIMING
+    if args.levelsync:
+        flags |= bm.FLAG_LEVELSYNC
+    if args.shuffle:
+        flags |= bm.FLAG_SHUFFLE
     opts = bm.options(flags=flags, mfma_min_children=args.mfma_min_children,
-                      split_words=args.split_words)
+                      split_words=args.split_words, shuffle_seed=args.shuffle,
+                      dfs_threads=args.dfs_threads, dfs_max_words=args.dfs_max_words)
+    model = None
+    if args.sched == "learned":
+        h = bm.bm_build(rp, ci, db.n, db.m, stream=stream)
+        topts = bm.options(flags=bm.FLAG_TRACE, dfs_max_words=args.dfs_max_words)
+        f, y = bm.bm_mine_ex(h, db.minsup, topts, stream=stream).trace()
+        model = bm.Model(seed=1)
+        loss = model.train(f, y, epochs=30, lr=3e-3, batch=256, stream=stream)
+        print(f"# cost model trained on {len(y)} traced tasks, loss {loss:.4f}", file=sys.stderr,
+              flush=True)
+        del h
 
     def step():
         h = bm.bm_build(rp, ci, db.n, db.m, stream=stream)
-        r = bm.bm_mine_ex(h, db.minsup, opts, stream=stream)
+        if model is not None:
+            r = bm.bm_mine_batch([h], [db.minsup], model=model, opts=opts, stream=stream)[0]
+        else:
+            r = bm.bm_mine_ex(h, db.minsup, opts, stream=stream)
         return h, r
 
     for i in range(args.warmup):
@@ -156,20 +187,20 @@ def main():
         if k == "gram_mfma":
             kernels[k]["achieved_TOPs"] = round(op / (per * 1e-3) / 1e12, 2)
             kernels[k]["algorithmic_ops_per_launch"] = op
-        if k == "andpop":
+        if k in HBM_KERNELS:
             kernels[k]["achieved_GBs"] = round(by / (per * 1e-3) / 1e9, 1)
             kernels[k]["algorithmic_bytes_per_launch"] = by
     if not args.no_timing and kernels:
-        dom = max((k for k in kernels if k in ("gram_mfma", "andpop")), key=lambda k: ms[k],
+        dom = max((k for k in kernels if k == "gram_mfma" or k in HBM_KERNELS), key=lambda k: ms[k],
                   default=None)
         if dom == "gram_mfma":
             a = kernels[dom]["achieved_TOPs"]
             roofline = {"bound": "mfma", "kernel": "k_gram_mfma (int8 MFMA Gram of a prefix class)",
                         "achieved": a, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
                         "frac": round(a / INT8_PEAK_TOPS, 4), "traffic": None}
-        elif dom == "andpop":
+        elif dom is not None:
             a = kernels[dom]["achieved_GBs"]
-            roofline = {"bound": "hbm", "kernel": "k_andpop (AND+popcount of a prefix class)",
+            roofline = {"bound": "hbm", "kernel": HBM_KERNELS[dom],
                         "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(a / HBM_PEAK_GBS, 4), "traffic": None}
 
@@ -190,6 +221,10 @@ def main():
                    "minsup": db.minsup, "frequent_itemsets": st["frequent_total"],
                    "candidates": cands, "frequent_items": st["n_frequent_items"],
                    "mine_ms": round(sum(s["wall_ms"] for s in stats) / len(stats), 3),
+                   "dfs_tasks": st["dfs_tasks"], "host_syncs": st["host_syncs"],
+                   "mode": ("levelsync" if args.levelsync else "depth-first") +
+                           ("+learned" if model is not None else "") +
+                           (f"+shuffle{args.shuffle}" if args.shuffle else ""),
                    "kernels": kernels},
         "roofline": roofline,
     }

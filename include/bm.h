@@ -67,8 +67,10 @@ enum {
   BM_K_ANDPOP = 3,    /* AND + popcount of a prefix class's columns, LDS-blocked (VALU) */
   BM_K_ANDPOP_REG = 4,/* AND + popcount of a small prefix class held in registers (VALU) */
   BM_K_LEVEL = 5,     /* candidate/level bookkeeping: thresholds, scans, compaction */
-  BM_K_EMIT = 6,      /* canonical-order output */
-  BM_K_COUNT = 7
+  BM_K_EMIT = 6,      /* canonical-order output (and the merge of depth-first output) */
+  BM_K_DFS = 7,       /* persistent depth-first subtree kernel (small classes) */
+  BM_K_SCHED = 8,     /* cost-model features, prediction and task ordering */
+  BM_K_COUNT = 9
 };
 
 /* Statistics of one mining call.  Kernel times are filled only when the call
@@ -90,6 +92,7 @@ typedef struct {
   double kernel_ops[BM_K_COUNT];
   double wall_ms;                              /* host wall time of the call */
   uint32_t host_syncs;                         /* device->host synchronisations */
+  uint64_t dfs_tasks;                          /* subtree tasks run by the depth-first kernel */
 } bm_stats;
 
 /* Tuning and behaviour switches for bm_mine_ex / bm_mine_batch.  Zero fields
@@ -100,7 +103,8 @@ typedef struct {
 #define BM_FLAG_ALL_MFMA 4u    /* send every class with >= 2 children to the MFMA kernel */
 #define BM_FLAG_GRAPH 8u       /* bm_mine_batch: replay the launch sequence as a hipGraph */
 #define BM_FLAG_TRACE 16u      /* keep per-class features and subtree costs (bm_result_trace) */
-#define BM_FLAG_SHUFFLE 32u    /* bm_mine_batch: random task order (order-invariance tests) */
+#define BM_FLAG_SHUFFLE 32u    /* random subtree-task order (order-invariance tests) */
+#define BM_FLAG_LEVELSYNC 64u  /* evaluate small classes level by level too (no depth-first kernel) */
 
 typedef struct {
   uint32_t flags;
@@ -108,7 +112,10 @@ typedef struct {
   uint32_t andpop_chunk_words;/* AND+popcount LDS chunk: 128 or 256 words */
   uint32_t split_words;       /* word-range length of one task (multiple of 64; 0 = automatic) */
   uint32_t shuffle_seed;      /* with BM_FLAG_SHUFFLE */
-  uint32_t reserved[7];
+  uint32_t dfs_threads;       /* threads per workgroup of the depth-first kernel: 256, 512 or 1024 */
+  uint32_t dfs_max_words;     /* depth-first phase only when every database has at most this many
+                               * 64-bit words per column (0 = default; 0xffffffff = always) */
+  uint32_t reserved[5];
 } bm_options;
 
 uint32_t bm_abi_version(void);
@@ -189,8 +196,45 @@ bm_status bm_result_copy(const bm_result* r, uint64_t* offsets, uint32_t* items,
                          uint32_t* supports, void* stream);
 bm_status bm_result_stats(const bm_result* r, bm_stats* out);
 
+/* Trace of a call made with BM_FLAG_TRACE (shared by all results of a batch):
+ * one row per subtree task handed to the depth-first kernel -- 8 features of
+ * the task's prefix class (itemset length of its children, log2 support of the
+ * prefix, log2(1 + children), mean log2 child support, max and mean child /
+ * prefix support ratio, log2 minsup, log2 words per column) and the label
+ * log2(1 + candidate supports evaluated in the task's subtree), which is
+ * deterministic.  feats: host float[rows*8] or NULL; labels: host float[rows]
+ * or NULL; *rows receives the row count (0 without a trace). */
+bm_status bm_result_trace(const bm_result* r, float* feats, float* labels, uint64_t* rows);
+
+/* Scheduler cost model: an 8 -> 64 -> 64 -> 1 perceptron with ReLU, BF16
+ * weights and FP32 accumulation, predicting log2(1 + subtree candidates) of a
+ * subtree task from its 8 trace features.  Passed to bm_mine_batch it only
+ * orders the depth-first work queue (longest predicted first); results are
+ * identical with and without it.  Training runs on the device (forward,
+ * backward and Adam kernels on an FP32 master copy); inputs are standardised
+ * with statistics of the first training set.  Arrays are host or device. */
+bm_status bm_model_create(uint32_t seed, bm_model** out);  /* He-uniform init from `seed` */
+bm_status bm_model_load(const char* path, bm_model** out);
+bm_status bm_model_save(const bm_model* m, const char* path);
+/* Minibatch Adam (batch rows per step, 0 = 256) over `epochs` passes; *final_loss
+ * (may be NULL) receives the last epoch's mean squared error. */
+bm_status bm_model_train(bm_model* m, const float* feats, const float* labels, uint64_t rows,
+                         uint32_t epochs, float lr, uint32_t batch, float* final_loss,
+                         void* stream);
+bm_status bm_model_predict(const bm_model* m, const float* feats, uint64_t rows, float* out,
+                           void* stream);
+/* Gradient of the mean squared error over `rows` (float[4801]) and the loss,
+ * without updating the model (for checking the backward kernel). */
+bm_status bm_model_grad(bm_model* m, const float* feats, const float* labels, uint64_t rows,
+                        float* grad, float* loss, void* stream);
+/* Parameters: FP32 master copy, the BF16 weights the kernels use (as floats),
+ * and the 16 normalisation values (mean[8], 1/std[8]); any pointer may be NULL. */
+bm_status bm_model_params(const bm_model* m, float* master, float* weights_bf16, float* norm);
+bm_status bm_model_set_params(bm_model* m, const float* master, const float* norm);
+
 void bm_db_free(bm_db* db);
 void bm_result_free(bm_result* r);
+void bm_model_free(bm_model* m);
 
 #ifdef __cplusplus
 }

@@ -19,14 +19,14 @@ import ctypes
 import numpy as np
 
 from . import _bm
-from ._bm import (BM_K_NAMES, FLAG_ALL_MFMA, FLAG_GRAPH, FLAG_NO_MFMA, FLAG_SHUFFLE,
-                  FLAG_TIMING, FLAG_TRACE, BmError, BmOptions)
+from ._bm import (BM_K_NAMES, FLAG_ALL_MFMA, FLAG_GRAPH, FLAG_LEVELSYNC, FLAG_NO_MFMA,
+                  FLAG_SHUFFLE, FLAG_TIMING, FLAG_TRACE, MLP_PARAMS, BmError, BmOptions)
 
 __all__ = [
     "bm_abi_version", "bm_build", "bm_item_support", "bm_pair_support", "bm_mine",
     "bm_mine_ex", "bm_mine_batch", "bm_set_allocator", "bm_release_cached_memory", "Db", "Result", "BmError",
     "options", "FLAG_TIMING", "FLAG_NO_MFMA", "FLAG_ALL_MFMA", "FLAG_GRAPH", "FLAG_TRACE",
-    "FLAG_SHUFFLE", "LIB_PATH",
+    "FLAG_SHUFFLE", "FLAG_LEVELSYNC", "LIB_PATH", "Model", "MLP_PARAMS",
 ]
 
 LIB_PATH = _bm.LIB_PATH
@@ -133,7 +133,19 @@ class Result:
             "kernel_ops": {n: float(st.kernel_ops[i]) for i, n in enumerate(BM_K_NAMES)},
             "wall_ms": float(st.wall_ms),
             "host_syncs": int(st.host_syncs),
+            "dfs_tasks": int(st.dfs_tasks),
         }
+
+    def trace(self):
+        """(features float32[rows, 8], labels float32[rows]) of a BM_FLAG_TRACE call."""
+        rows = ctypes.c_uint64()
+        _bm.check(_bm.lib.bm_result_trace(self._h, None, None, ctypes.byref(rows)), "bm_result_trace")
+        n = int(rows.value)
+        f = np.zeros((max(n, 1), 8), dtype=np.float32)
+        y = np.zeros(max(n, 1), dtype=np.float32)
+        _bm.check(_bm.lib.bm_result_trace(self._h, f.ctypes.data, y.ctypes.data, ctypes.byref(rows)),
+                  "bm_result_trace")
+        return f[:n], y[:n]
 
     def free(self):
         if self._h:
@@ -148,13 +160,16 @@ class Result:
 
 
 def options(flags: int = 0, mfma_min_children: int = 0, andpop_chunk_words: int = 0,
-            split_words: int = 0, shuffle_seed: int = 0) -> BmOptions:
+            split_words: int = 0, shuffle_seed: int = 0, dfs_threads: int = 0,
+            dfs_max_words: int = 0) -> BmOptions:
     o = BmOptions()
     o.flags = flags
     o.mfma_min_children = mfma_min_children
     o.andpop_chunk_words = andpop_chunk_words
     o.split_words = split_words
     o.shuffle_seed = shuffle_seed
+    o.dfs_threads = dfs_threads
+    o.dfs_max_words = dfs_max_words
     return o
 
 
@@ -223,6 +238,78 @@ def bm_mine_batch(dbs, minsups, model=None, opts: BmOptions | None = None, strea
     _bm.check(_bm.lib.bm_mine_batch(arr, ms, n, mh, op, _bm._stream_ptr(stream), out),
               "bm_mine_batch")
     return [Result(ctypes.c_void_p(out[i])) for i in range(n)]
+
+
+class Model:
+    """Scheduler cost model (8 -> 64 -> 64 -> 1, BF16 weights, trained on the GPU)."""
+
+    def __init__(self, seed: int = 0, path: str | None = None):
+        h = ctypes.c_void_p()
+        if path is not None:
+            _bm.check(_bm.lib.bm_model_load(path.encode(), ctypes.byref(h)), "bm_model_load")
+        else:
+            _bm.check(_bm.lib.bm_model_create(seed, ctypes.byref(h)), "bm_model_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def save(self, path: str):
+        _bm.check(_bm.lib.bm_model_save(self._h, path.encode()), "bm_model_save")
+
+    def train(self, feats, labels, epochs: int = 20, lr: float = 1e-3, batch: int = 256,
+              stream=None) -> float:
+        X = np.ascontiguousarray(feats, dtype=np.float32)
+        Y = np.ascontiguousarray(labels, dtype=np.float32)
+        loss = ctypes.c_float()
+        _bm.check(_bm.lib.bm_model_train(self._h, X.ctypes.data, Y.ctypes.data, len(Y), epochs, lr,
+                                         batch, ctypes.byref(loss), _bm._stream_ptr(stream)),
+                  "bm_model_train")
+        return float(loss.value)
+
+    def predict(self, feats, stream=None) -> np.ndarray:
+        X = np.ascontiguousarray(feats, dtype=np.float32)
+        out = np.zeros(max(len(X), 1), dtype=np.float32)
+        _bm.check(_bm.lib.bm_model_predict(self._h, X.ctypes.data, len(X), out.ctypes.data,
+                                           _bm._stream_ptr(stream)), "bm_model_predict")
+        return out[:len(X)]
+
+    def grad(self, feats, labels, stream=None):
+        X = np.ascontiguousarray(feats, dtype=np.float32)
+        Y = np.ascontiguousarray(labels, dtype=np.float32)
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        loss = ctypes.c_float()
+        _bm.check(_bm.lib.bm_model_grad(self._h, X.ctypes.data, Y.ctypes.data, len(Y), g.ctypes.data,
+                                        ctypes.byref(loss), _bm._stream_ptr(stream)), "bm_model_grad")
+        return g, float(loss.value)
+
+    def params(self):
+        """(FP32 master copy, BF16 weights as float32, normalisation [16])."""
+        m = np.zeros(MLP_PARAMS, dtype=np.float32)
+        w = np.zeros(MLP_PARAMS, dtype=np.float32)
+        nrm = np.zeros(16, dtype=np.float32)
+        _bm.check(_bm.lib.bm_model_params(self._h, m.ctypes.data, w.ctypes.data, nrm.ctypes.data),
+                  "bm_model_params")
+        return m, w, nrm
+
+    def set_params(self, master=None, norm=None):
+        mp = np.ascontiguousarray(master, dtype=np.float32) if master is not None else None
+        npp = np.ascontiguousarray(norm, dtype=np.float32) if norm is not None else None
+        _bm.check(_bm.lib.bm_model_set_params(self._h, mp.ctypes.data if mp is not None else None,
+                                              npp.ctypes.data if npp is not None else None),
+                  "bm_model_set_params")
+
+    def free(self):
+        if self._h:
+            _bm.lib.bm_model_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 _allocator_keepalive = None

@@ -22,7 +22,8 @@ if not os.path.exists(LIB_PATH):
 lib = ctypes.CDLL(LIB_PATH)
 
 BM_MAX_LEVELS = 64
-BM_K_NAMES = ["build", "colsum", "gram_mfma", "andpop", "andpop_reg", "level", "emit"]
+BM_K_NAMES = ["build", "colsum", "gram_mfma", "andpop", "andpop_reg", "level", "emit", "dfs",
+              "sched"]
 BM_K_COUNT = len(BM_K_NAMES)
 
 FLAG_TIMING = 1
@@ -31,6 +32,8 @@ FLAG_ALL_MFMA = 4
 FLAG_GRAPH = 8
 FLAG_TRACE = 16
 FLAG_SHUFFLE = 32
+FLAG_LEVELSYNC = 64
+MLP_PARAMS = 4801
 
 STATUS = {0: "BM_OK", 1: "BM_ERR_INVALID_ARG", 2: "BM_ERR_CSR", 3: "BM_ERR_OOM",
           4: "BM_ERR_DEVICE", 5: "BM_ERR_UNSUPPORTED"}
@@ -52,6 +55,7 @@ class BmStats(ctypes.Structure):
         ("kernel_ops", ctypes.c_double * BM_K_COUNT),
         ("wall_ms", ctypes.c_double),
         ("host_syncs", ctypes.c_uint32),
+        ("dfs_tasks", ctypes.c_uint64),
     ]
 
 
@@ -62,7 +66,9 @@ class BmOptions(ctypes.Structure):
         ("andpop_chunk_words", ctypes.c_uint32),
         ("split_words", ctypes.c_uint32),
         ("shuffle_seed", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 7),
+        ("dfs_threads", ctypes.c_uint32),
+        ("dfs_max_words", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 5),
     ]
 
 
@@ -100,6 +106,28 @@ lib.bm_result_copy.restype = ctypes.c_int
 lib.bm_result_copy.argtypes = [_vp, _vp, _vp, _vp, _vp]
 lib.bm_result_stats.restype = ctypes.c_int
 lib.bm_result_stats.argtypes = [_vp, ctypes.POINTER(BmStats)]
+_f32p = ctypes.POINTER(ctypes.c_float)
+lib.bm_result_trace.restype = ctypes.c_int
+lib.bm_result_trace.argtypes = [_vp, _vp, _vp, _u64p]
+lib.bm_model_create.restype = ctypes.c_int
+lib.bm_model_create.argtypes = [ctypes.c_uint32, ctypes.POINTER(_vp)]
+lib.bm_model_load.restype = ctypes.c_int
+lib.bm_model_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(_vp)]
+lib.bm_model_save.restype = ctypes.c_int
+lib.bm_model_save.argtypes = [_vp, ctypes.c_char_p]
+lib.bm_model_train.restype = ctypes.c_int
+lib.bm_model_train.argtypes = [_vp, _vp, _vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_float,
+                               ctypes.c_uint32, _f32p, _vp]
+lib.bm_model_predict.restype = ctypes.c_int
+lib.bm_model_predict.argtypes = [_vp, _vp, ctypes.c_uint64, _vp, _vp]
+lib.bm_model_grad.restype = ctypes.c_int
+lib.bm_model_grad.argtypes = [_vp, _vp, _vp, ctypes.c_uint64, _vp, _f32p, _vp]
+lib.bm_model_params.restype = ctypes.c_int
+lib.bm_model_params.argtypes = [_vp, _vp, _vp, _vp]
+lib.bm_model_set_params.restype = ctypes.c_int
+lib.bm_model_set_params.argtypes = [_vp, _vp, _vp]
+lib.bm_model_free.restype = None
+lib.bm_model_free.argtypes = [_vp]
 lib.bm_db_free.restype = None
 lib.bm_db_free.argtypes = [_vp]
 lib.bm_result_free.restype = None

@@ -28,7 +28,7 @@ CFLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 SOURCES = ["runtime.hip", "k_build.hip", "k_gram_mfma.hip", "k_andpop.hip", "k_levels.hip",
-           "miner.hip", "api.hip"]
+           "k_dfs.hip", "k_mlp.hip", "model.hip", "miner.hip", "api.hip"]
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -98,7 +98,7 @@ bm_status bm_mine_ex(const bm_db* db, uint32_t minsup, const bm_options* opt, vo
   if (out) *out = nullptr;
   return guarded([&] {
     if (!db || !out) bm::fail(BM_ERR_INVALID_ARG, "db or out is NULL");
-    auto r = bm::mine_many(&db, &minsup, 1, opt, as_stream(stream));
+    auto r = bm::mine_many(&db, &minsup, 1, nullptr, opt, as_stream(stream));
     *out = r[0];
   });
 }
@@ -111,8 +111,7 @@ bm_status bm_mine_batch(const bm_db* const* dbs, const uint32_t* minsups, uint32
   return guarded([&] {
     if (count == 0) return;
     if (!dbs || !minsups || !out) bm::fail(BM_ERR_INVALID_ARG, "dbs, minsups or out is NULL");
-    (void)sched;
-    auto r = bm::mine_many(dbs, minsups, count, opt, as_stream(stream));
+    auto r = bm::mine_many(dbs, minsups, count, sched, opt, as_stream(stream));
     for (uint32_t i = 0; i < count; ++i) out[i] = r[i];
   });
 }
@@ -145,6 +144,79 @@ bm_status bm_result_stats(const bm_result* r, bm_stats* out) {
     std::memcpy(out, &r->stats, sizeof(bm_stats));
   });
 }
+
+bm_status bm_result_trace(const bm_result* r, float* feats, float* labels, uint64_t* rows) {
+  return guarded([&] {
+    if (!r) bm::fail(BM_ERR_INVALID_ARG, "result is NULL");
+    bm::result_trace(r, feats, labels, rows);
+  });
+}
+
+bm_status bm_model_create(uint32_t seed, bm_model** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!out) bm::fail(BM_ERR_INVALID_ARG, "out is NULL");
+    *out = bm::model_create(seed);
+  });
+}
+
+bm_status bm_model_load(const char* path, bm_model** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!out || !path) bm::fail(BM_ERR_INVALID_ARG, "path or out is NULL");
+    *out = bm::model_load(path);
+  });
+}
+
+bm_status bm_model_save(const bm_model* m, const char* path) {
+  return guarded([&] {
+    if (!m || !path) bm::fail(BM_ERR_INVALID_ARG, "model or path is NULL");
+    bm::model_save(m, path);
+  });
+}
+
+bm_status bm_model_train(bm_model* m, const float* feats, const float* labels, uint64_t rows,
+                         uint32_t epochs, float lr, uint32_t batch, float* final_loss, void* stream) {
+  return guarded([&] {
+    if (!m || (rows && (!feats || !labels))) bm::fail(BM_ERR_INVALID_ARG, "NULL argument");
+    if (!(lr > 0.f)) bm::fail(BM_ERR_INVALID_ARG, "lr must be > 0");
+    const float l = bm::model_train(m, feats, labels, rows, epochs, lr, batch, as_stream(stream));
+    if (final_loss) *final_loss = l;
+  });
+}
+
+bm_status bm_model_predict(const bm_model* m, const float* feats, uint64_t rows, float* out,
+                           void* stream) {
+  return guarded([&] {
+    if (!m || (rows && (!feats || !out))) bm::fail(BM_ERR_INVALID_ARG, "NULL argument");
+    bm::model_predict(m, feats, rows, out, as_stream(stream));
+  });
+}
+
+bm_status bm_model_grad(bm_model* m, const float* feats, const float* labels, uint64_t rows,
+                        float* grad, float* loss, void* stream) {
+  return guarded([&] {
+    if (!m || (rows && (!feats || !labels))) bm::fail(BM_ERR_INVALID_ARG, "NULL argument");
+    const float l = bm::model_grad(m, feats, labels, rows, grad, as_stream(stream));
+    if (loss) *loss = l;
+  });
+}
+
+bm_status bm_model_params(const bm_model* m, float* master, float* weights_bf16, float* norm) {
+  return guarded([&] {
+    if (!m) bm::fail(BM_ERR_INVALID_ARG, "model is NULL");
+    bm::model_params(m, master, weights_bf16, norm);
+  });
+}
+
+bm_status bm_model_set_params(bm_model* m, const float* master, const float* norm) {
+  return guarded([&] {
+    if (!m) bm::fail(BM_ERR_INVALID_ARG, "model is NULL");
+    bm::model_set_params(m, master, norm);
+  });
+}
+
+void bm_model_free(bm_model* m) { delete m; }
 
 void bm_db_free(bm_db* db) { delete db; }
 void bm_result_free(bm_result* r) { delete r; }

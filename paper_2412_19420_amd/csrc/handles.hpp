@@ -22,8 +22,22 @@ struct ResultStore {
   DBuf<uint64_t> offsets;   // all sets + 1, item offsets counted over the whole call
   DBuf<uint32_t> items;
   DBuf<uint32_t> supports;
+  // with BM_FLAG_TRACE: features and realised cost of every subtree task
+  DBuf<float> trace_feats;  // [rows][8]
+  DBuf<float> trace_cost;   // [rows] candidates evaluated in the subtree
+  uint64_t trace_rows = 0;
 };
 }  // namespace bm
+
+// Scheduler cost model (8 -> 64 -> 64 -> 1 perceptron).
+struct bm_model {
+  int device = 0;
+  bm::DBuf<float> master, m, v, grad, norm;  // FP32 master copy, Adam moments, gradient, norm
+  bm::DBuf<uint16_t> wbf;                    // BF16 weights used by the kernels
+  float h_norm[16] = {};                     // feature mean[8], 1/std[8]
+  bool has_norm = false;
+  uint64_t step = 0;
+};
 
 // One database's result: a slice [set0, set0 + n_sets) of the call's sets whose
 // item ids are [item0, item0 + n_items) of the call's items.
@@ -50,6 +64,9 @@ struct Tuning {
   uint32_t mfma_min_q = 64;     // classes with this many children or more go to MFMA
   uint32_t andpop_chunk = 256;  // AND+popcount LDS chunk (words)
   uint32_t split_words = 0;     // 0 = automatic word split
+  bool dfs = true;              // small classes: depth-first subtree kernel
+  uint32_t dfs_threads = 256;   // threads per depth-first workgroup
+  uint32_t dfs_max_words = 4096;  // depth-first only when every column has <= this many words
 };
 Tuning tuning_from(const bm_options* opt);
 
@@ -58,7 +75,22 @@ bm_db* build_db(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n, ui
 void pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* out, hipStream_t s);
 // Mine `count` databases in one level-synchronous pass; one result per database.
 std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsups, uint32_t count,
-                                  const bm_options* opt, hipStream_t s);
+                                  const bm_model* sched, const bm_options* opt, hipStream_t s);
+void result_trace(const bm_result* r, float* feats, float* labels, uint64_t* rows);
+
+bm_model* model_create(uint32_t seed);
+bm_model* model_load(const char* path);
+void model_save(const bm_model* m, const char* path);
+void model_set_norm_from(bm_model* m, const float* feats, uint64_t rows, hipStream_t s);
+float model_train(bm_model* m, const float* feats, const float* labels, uint64_t rows,
+                  uint32_t epochs, float lr, uint32_t batch, hipStream_t s);
+void model_predict(const bm_model* m, const float* feats, uint64_t rows, float* out, hipStream_t s);
+void model_predict_device(const bm_model* m, const float* dfeats, uint64_t rows, float* dout,
+                          hipStream_t s);
+float model_grad(bm_model* m, const float* feats, const float* labels, uint64_t rows,
+                 float* grad_out, hipStream_t s);
+void model_params(const bm_model* m, float* master, float* rounded, float* norm);
+void model_set_params(bm_model* m, const float* master, const float* norm);
 void result_copy(const bm_result* r, uint64_t* offsets, uint32_t* items, uint32_t* supports,
                  hipStream_t s);
 

@@ -153,6 +153,8 @@ class KTimer {
   ~KTimer();
   void begin(int kind);
   void end(double bytes = 0, double ops = 0);
+  // Work counts of the last recorded launch, when they are known only afterwards.
+  void set_last(double bytes, double ops);
   // Adds accumulated times to stats (synchronises on the recorded events).
   void collect(bm_stats* st);
   bool on() const { return on_; }

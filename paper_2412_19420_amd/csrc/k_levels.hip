@@ -17,6 +17,7 @@
 //   * a node with c >= 2 frequent children becomes a class of the next step.
 #include "internal.hpp"
 #include "levels.hpp"
+#include "dfs.hpp"
 
 namespace bm {
 
@@ -275,10 +276,11 @@ __device__ inline ClassWork class_work(const ClassDesc& cd, const DbInfo& d, uin
   return w;
 }
 
-// Number of tasks of each class, per kernel.
+// Number of tasks of each class, per kernel.  With dfs set, every small class
+// becomes one depth-first subtree task instead of level-synchronous tasks.
 __global__ void k_class_task_counts(const ClassDesc* __restrict__ cls, uint64_t ncls,
                                     const DbInfo* __restrict__ dbs, uint32_t mfma_min_q,
-                                    TaskGeom geo, uint32_t* __restrict__ cm,
+                                    TaskGeom geo, uint32_t dfs, uint32_t* __restrict__ cm,
                                     uint32_t* __restrict__ cv, uint32_t* __restrict__ ct) {
   for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < ncls;
        c += (uint64_t)gridDim.x * blockDim.x) {
@@ -287,23 +289,38 @@ __global__ void k_class_task_counts(const ClassDesc* __restrict__ cls, uint64_t 
     const uint32_t nt = w.npairs * w.nsplit;
     cm[c] = w.kind == 0 ? nt : 0u;
     cv[c] = w.kind == 1 ? nt : 0u;
-    ct[c] = w.kind == 2 ? nt : 0u;
+    ct[c] = w.kind == 2 ? (dfs ? 1u : nt) : 0u;
   }
 }
 
-// Wave per class: write its tasks at the scanned offsets.
+// Wave per class: write its tasks at the scanned offsets (with dfs set, small
+// classes become depth-first subtree tasks whose children are level `level`).
 __global__ void k_write_class_tasks(const ClassDesc* __restrict__ cls, uint64_t ncls,
                                     const DbInfo* __restrict__ dbs, uint32_t mfma_min_q,
                                     TaskGeom geo, const uint64_t* __restrict__ om,
                                     const uint64_t* __restrict__ ov, const uint64_t* __restrict__ ot,
                                     Task* __restrict__ tm, Task* __restrict__ tv,
-                                    Task* __restrict__ tt) {
+                                    Task* __restrict__ tt, DfsTask* __restrict__ dt,
+                                    uint32_t level) {
   const int lane = threadIdx.x & 63;
   const uint64_t wave0 = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   for (uint64_t c = wave0; c < ncls; c += nwaves) {
     const ClassDesc cd = cls[c];
     const ClassWork w = class_work(cd, dbs[cd.db], mfma_min_q, geo);
+    if (w.kind == 2 && dt) {
+      if (lane == 0) {
+        DfsTask k;
+        k.db = cd.db;
+        k.level = level;
+        k.child0 = cd.child0;
+        k.q = cd.q;
+        k.pre_off = cd.pre_off;
+        k.pre_len = cd.pre_len;
+        dt[ot[c]] = k;
+      }
+      continue;
+    }
     Task* out = w.kind == 0 ? tm + om[c] : (w.kind == 1 ? tv + ov[c] : tt + ot[c]);
     write_tasks((uint32_t)c, cd.q, w.npairs, w.block, w.nsplit, w.split, w.wend, out, lane, 64);
   }
@@ -499,21 +516,21 @@ void launch_fill_level(uint64_t n, const uint32_t* parent, const int32_t* pcls,
 }
 
 void launch_class_task_counts(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs,
-                              uint32_t mfma_min_q, const TaskGeom& geo, uint32_t* cm, uint32_t* cv,
-                              uint32_t* ct, hipStream_t s) {
+                              uint32_t mfma_min_q, const TaskGeom& geo, bool dfs, uint32_t* cm,
+                              uint32_t* cv, uint32_t* ct, hipStream_t s) {
   if (ncls == 0) return;
   k_class_task_counts<<<grid_for(ncls, kThreads), kThreads, 0, s>>>(cls, ncls, dbs, mfma_min_q, geo,
-                                                                     cm, cv, ct);
+                                                                     dfs ? 1u : 0u, cm, cv, ct);
   BM_LAUNCH_CHECK();
 }
 
 void launch_write_class_tasks(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs,
                               uint32_t mfma_min_q, const TaskGeom& geo, const uint64_t* om,
                               const uint64_t* ov, const uint64_t* ot, Task* tm, Task* tv, Task* tt,
-                              hipStream_t s) {
+                              DfsTask* dt, uint32_t level, hipStream_t s) {
   if (ncls == 0) return;
   k_write_class_tasks<<<grid_for(ncls * 64, kThreads), kThreads, 0, s>>>(
-      cls, ncls, dbs, mfma_min_q, geo, om, ov, ot, tm, tv, tt);
+      cls, ncls, dbs, mfma_min_q, geo, om, ov, ot, tm, tv, tt, dt, level);
   BM_LAUNCH_CHECK();
 }
 

@@ -42,12 +42,13 @@ void launch_fill_level(uint64_t n, const uint32_t* parent, const int32_t* pcls,
                        const uint32_t* tri, const uint64_t* S, uint32_t* nitem, uint32_t* nparent,
                        uint32_t* nsupp, uint32_t* ndbv, hipStream_t s);
 void launch_class_task_counts(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs,
-                              uint32_t mfma_min_q, const TaskGeom& geo, uint32_t* cm, uint32_t* cv,
-                              uint32_t* ct, hipStream_t s);
+                              uint32_t mfma_min_q, const TaskGeom& geo, bool dfs, uint32_t* cm,
+                              uint32_t* cv, uint32_t* ct, hipStream_t s);
+struct DfsTask;
 void launch_write_class_tasks(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs,
                               uint32_t mfma_min_q, const TaskGeom& geo, const uint64_t* om,
                               const uint64_t* ov, const uint64_t* ot, Task* tm, Task* tv, Task* tt,
-                              hipStream_t s);
+                              DfsTask* dt, uint32_t level, hipStream_t s);
 void launch_fill_classes(uint64_t n, uint32_t k, const uint32_t* cnt, const uint64_t* child_start,
                          const uint64_t* cls_pos, const uint64_t* tri_off, const LevelPtrs& lv,
                          const uint32_t* node_db, const DbInfo* dbs, ClassDesc* ocls,

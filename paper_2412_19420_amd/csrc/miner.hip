@@ -15,11 +15,14 @@
 // per level reads back the next level's sizes -- for the whole batch.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <memory>
 #include <vector>
 
+#include "dfs.hpp"
 #include "handles.hpp"
 #include "levels.hpp"
+#include "mlp.hpp"
 
 namespace bm {
 
@@ -139,24 +142,31 @@ struct StepWork {
   TBuf<uint32_t> tri;
   uint64_t T = 0;
   uint64_t st[ST_COUNT] = {};
+  TBuf<DfsTask> dt;  // small classes handed to the depth-first kernel
+  uint64_t ndt = 0;
 };
 
 // Task lists of a step's classes: counts per class on the device, scanned
 // offsets, then the records.  The kernels read the totals from device memory;
 // the host only sizes buffers from upper bounds.
 void prepare_tasks(StepWork& w, const DbInfo* ddb, uint64_t Wmax, uint64_t pairs_m,
-                   uint64_t pairs_v, uint64_t classes_t, const Tuning& tu, hipStream_t s) {
+                   uint64_t pairs_v, uint64_t classes_t, const Tuning& tu, bool dfs, uint32_t level,
+                   hipStream_t s) {
   const TaskGeom g = make_geom(Wmax, pairs_m, pairs_v, classes_t, tu);
   const uint64_t Wm = round_up(std::max<uint64_t>(1, Wmax), GRAM_KW);
   w.ub_m = pairs_m * ceil_div(Wm, g.split_m);
   w.ub_v = pairs_v * ceil_div(std::max<uint64_t>(1, Wmax), g.split_v);
-  w.ub_t = classes_t * ceil_div(std::max<uint64_t>(1, Wmax), g.split_t);
+  w.ub_t = dfs ? 0 : classes_t * ceil_div(std::max<uint64_t>(1, Wmax), g.split_t);
+  if (dfs) {
+    w.ndt = classes_t;
+    w.dt.alloc(classes_t, s);
+  }
   TBuf<uint32_t> cm(w.ncls, s), cv(w.ncls, s), ct(w.ncls, s);
   w.om.alloc(w.ncls + 1, s);
   w.ov.alloc(w.ncls + 1, s);
   w.ot.alloc(w.ncls + 1, s);
-  launch_class_task_counts(w.cls.get(), w.ncls, ddb, tu.mfma_min_q, g, cm.get(), cv.get(), ct.get(),
-                           s);
+  launch_class_task_counts(w.cls.get(), w.ncls, ddb, tu.mfma_min_q, g, dfs, cm.get(), cv.get(),
+                           ct.get(), s);
   const void* in[3] = {cm.get(), cv.get(), ct.get()};
   const bool is64[3] = {false, false, false};
   uint64_t* out[3] = {w.om.get(), w.ov.get(), w.ot.get()};
@@ -165,7 +175,8 @@ void prepare_tasks(StepWork& w, const DbInfo* ddb, uint64_t Wmax, uint64_t pairs
   w.tv.alloc(w.ub_v, s);
   w.tt.alloc(w.ub_t, s);
   launch_write_class_tasks(w.cls.get(), w.ncls, ddb, tu.mfma_min_q, g, w.om.get(), w.ov.get(),
-                           w.ot.get(), w.tm.get(), w.tv.get(), w.tt.get(), s);
+                           w.ot.get(), w.tm.get(), w.tv.get(), w.tt.get(), dfs ? w.dt.get() : nullptr,
+                           level, s);
 }
 
 void run_class_kernels(const DbInfo* ddb, const uint32_t* child_item, const StepWork& w,
@@ -198,7 +209,7 @@ void run_class_kernels(const DbInfo* ddb, const uint32_t* child_item, const Step
 // Classes given on the host (the roots of each database, or an explicit
 // column list): records, a zeroed triangle buffer and the task lists.
 void host_classes(StepWork& w, const std::vector<ClassDesc>& hc, const DbInfo* ddb, uint64_t Wmax,
-                  const Tuning& tu, hipStream_t s) {
+                  const Tuning& tu, bool dfs, hipStream_t s) {
   w.ncls = hc.size();
   w.cls.alloc(w.ncls, s);
   upload(w.cls.get(), hc, s);
@@ -219,7 +230,7 @@ void host_classes(StepWork& w, const std::vector<ClassDesc>& hc, const DbInfo* d
   }
   w.tri.alloc(w.T, s);
   launch_fill_u32(w.tri.get(), 0, w.T, s);
-  prepare_tasks(w, ddb, Wmax, pm, pv, ct, tu, s);
+  prepare_tasks(w, ddb, Wmax, pm, pv, ct, tu, dfs, 1, s);
 }
 
 struct Level {
@@ -247,6 +258,13 @@ Tuning tuning_from(const bm_options* opt) {
     if (opt->split_words % 64) fail(BM_ERR_INVALID_ARG, "split_words must be a multiple of 64");
     t.split_words = opt->split_words;
   }
+  if (opt->dfs_threads) {
+    if (opt->dfs_threads != 256 && opt->dfs_threads != 512 && opt->dfs_threads != 1024)
+      fail(BM_ERR_INVALID_ARG, "dfs_threads must be 256, 512 or 1024");
+    t.dfs_threads = opt->dfs_threads;
+  }
+  if (opt->dfs_max_words) t.dfs_max_words = opt->dfs_max_words;
+  if (opt->flags & BM_FLAG_LEVELSYNC) t.dfs = false;
   if (opt->flags & BM_FLAG_NO_MFMA) t.mfma_min_q = 0xffffffffu;
   if (opt->flags & BM_FLAG_ALL_MFMA) t.mfma_min_q = 2;
   return t;
@@ -358,7 +376,7 @@ void pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* 
   std::vector<ClassDesc> hc;
   if (k >= 2) {
     hc.push_back(ClassDesc{0, 0, k, 0, 0, 0, 0});
-    host_classes(w, hc, ddb.get(), db->W, tu, s);
+    host_classes(w, hc, ddb.get(), db->W, tu, false, s);
     KTimer tm(false, s);
     run_class_kernels(ddb.get(), d_items.get(), w, tu, (double)db->W, (double)db->n, tm, s);
   }
@@ -378,11 +396,11 @@ void pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* 
 // ------------------------------------------------------------------ mining
 
 std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsups, uint32_t N,
-                                  const bm_options* opt, hipStream_t s) {
+                                  const bm_model* sched, const bm_options* opt, hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
   for (uint32_t d = 0; d < N; ++d)
     if (minsups[d] == 0) fail(BM_ERR_INVALID_ARG, "minsup of database %u must be >= 1", d);
-  const Tuning tu = tuning_from(opt);
+  Tuning tu = tuning_from(opt);
   const uint32_t flags = opt ? opt->flags : 0u;
   int device = 0;
   BM_HIP(hipGetDevice(&device));
@@ -413,6 +431,8 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       }
     }
     const double nW = N ? sumW / N : 0, nN = N ? sumN / N : 0;  // per-database means for work counts
+    // one workgroup walks a whole subtree, so long columns favour the level-synchronous path
+    if (Wmax > tu.dfs_max_words) tu.dfs = false;
     // one threshold for every live database lets the candidate threshold skip the class lookup
     uint32_t uniform_thr = 0;
     for (uint32_t d = 0; d < N; ++d) {
@@ -468,6 +488,12 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
     if (f1_base[N]) st.frequent[1] = f1_base[N];
 
     // ---- level steps
+    struct Part {
+      const DfsTask* p;
+      uint64_t n;
+    };
+    std::vector<Part> parts;                            // depth-first tasks of each step
+    std::vector<const uint32_t*> step_pre(BM_MAX_LEVELS + 2, nullptr);
     std::vector<ClassDesc> roots;
     std::vector<int32_t> hpcls(std::max<uint32_t>(N, 1), -1);
     uint64_t tri_off = 0;
@@ -483,12 +509,15 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       TBuf<int32_t> pcls_prev(hpcls.size(), s);
       upload(pcls_prev.get(), hpcls, s);
       auto w = std::make_unique<StepWork>();
-      host_classes(*w, roots, ddb.get(), Wmax, tu, s);
+      host_classes(*w, roots, ddb.get(), Wmax, tu, tu.dfs, s);
       uint32_t k = 1;
       for (;;) {
         const uint64_t nk = L[k].n;
-        st.candidates[k + 1] = w->T;
-        st.candidates_total += w->T;
+        const uint64_t ls_cand = w->T - (tu.dfs ? w->st[ST_CAND_T] : 0);
+        st.candidates[k + 1] += ls_cand;
+        st.candidates_total += ls_cand;
+        if (w->ndt) parts.push_back({w->dt.get(), w->ndt});
+        step_pre[k] = w->pre.get();
         st.classes_mfma += w->st[ST_CLS_M];
         st.classes_andpop += w->st[ST_CLS_V] + w->st[ST_CLS_T];
         run_class_kernels(ddb.get(), L[k].item.get(), *w, tu, nW, nN, tm, s);
@@ -564,12 +593,201 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         }
         launch_fill_classes(nk, k, cnt.get(), L[k].cstart.get(), clspos.get(), trioff.get(), lv,
                             L[k].db.get(), ddb.get(), nw->cls.get(), nw->pre.get(), pcls_k.get(), s);
-        prepare_tasks(*nw, ddb.get(), Wmax, PM, PV, PT, tu, s);
+        prepare_tasks(*nw, ddb.get(), Wmax, PM, PV, PT, tu, tu.dfs, k + 1, s);
         tm.end();
         w = std::move(nw);
         pcls_prev = pcls_k;
         k += 1;
       }
+    }
+
+    // ---- depth-first subtrees of the small classes, then the merged levels
+    uint64_t D = 0;
+    for (const auto& pt : parts) D += pt.n;
+    if (D > 0) {
+      if (D > 0xffffffffull) fail(BM_ERR_UNSUPPORTED, "too many subtree tasks");
+      st.dfs_tasks = D;
+      const uint32_t Kls = (uint32_t)L.size() - 1;
+      TBuf<DfsTask> tasks(D, s);
+      uint64_t at = 0;
+      for (const auto& pt : parts) {
+        BM_HIP(hipMemcpyAsync(tasks.get() + at, pt.p, pt.n * sizeof(DfsTask), hipMemcpyDeviceToDevice,
+                              s));
+        at += pt.n;
+      }
+      const bool trace = (flags & BM_FLAG_TRACE) != 0;
+      TBuf<uint32_t> order;
+      TBuf<float> feats;
+      tm.begin(BM_K_SCHED);
+      if (sched || trace) {
+        feats.alloc(D * MLP_IN, s);
+        FeatArgs fa{};
+        fa.dbs = ddb.get();
+        fa.tasks = tasks.get();
+        fa.ntasks = (uint32_t)D;
+        for (uint32_t j = 1; j <= Kls; ++j) {
+          fa.lv_supp[j] = L[j].supp.get();
+          fa.lv_parent[j] = L[j].parent.get();
+        }
+        fa.feats = feats.get();
+        launch_dfs_features(fa, s);
+      }
+      std::vector<uint32_t> perm;
+      if (sched) {
+        TBuf<float> pred(D, s);
+        TBuf<uint32_t> hist(256, s);
+        TBuf<uint64_t> hoff(257, s);
+        order.alloc(D, s);
+        model_predict_device(sched, feats.get(), D, pred.get(), s);
+        launch_order_by_key(pred.get(), (uint32_t)D, hist.get(), hoff.get(), order.get(), s);
+      } else if (flags & BM_FLAG_SHUFFLE) {
+        perm.resize(D);
+        for (uint64_t i = 0; i < D; ++i) perm[i] = (uint32_t)i;
+        uint64_t x = 0x243F6A8885A308D3ull ^ (opt ? opt->shuffle_seed : 0u);
+        for (uint64_t i = D - 1; i > 0; --i) {  // Fisher-Yates with splitmix64 draws
+          x += 0x9E3779B97F4A7C15ull;
+          uint64_t z = x;
+          z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+          z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+          z ^= z >> 31;
+          std::swap(perm[i], perm[z % (i + 1)]);
+        }
+        order.alloc(D, s);
+        upload(order.get(), perm, s);
+      }
+      tm.end();
+      std::vector<TBuf<uint32_t>> ls_first(Kls + 2), ls_count(Kls + 2);
+      TBuf<uint32_t> ctrl(2, s);                  // [0] queue head, [1] arena count
+      TBuf<uint32_t> dflags(1, s);
+      TBuf<unsigned long long> lstat(2 * (BM_MAX_LEVELS + 1) + 1, s);
+      TBuf<float> cost;
+      if (trace) cost.alloc(D, s);
+      uint64_t cap = std::max<uint64_t>(1u << 16, 32 * D);
+      TBuf<ArenaNode> arena;
+      std::vector<unsigned long long> hstat(2 * (BM_MAX_LEVELS + 1) + 1);
+      for (int attempt = 0;; ++attempt) {
+        if (cap > 0xffffffffull) fail(BM_ERR_UNSUPPORTED, "depth-first output too large");
+        arena.alloc(cap, s);
+        for (uint32_t j = 1; j <= Kls; ++j) {
+          if (!ls_first[j].p) {
+            ls_first[j].alloc(L[j].n, s);
+            ls_count[j].alloc(L[j].n, s);
+          }
+          launch_fill_u32(ls_count[j].get(), 0, L[j].n, s);
+        }
+        launch_fill_u32(ctrl.get(), 0, 2, s);
+        launch_fill_u32(dflags.get(), 0, 1, s);
+        launch_fill_u64(reinterpret_cast<uint64_t*>(lstat.get()), 0, hstat.size(), s);
+        DfsArgs da{};
+        da.dbs = ddb.get();
+        da.tasks = tasks.get();
+        da.ntasks = (uint32_t)D;
+        da.order = order.get();
+        da.queue_head = ctrl.get();
+        for (uint32_t j = 1; j <= Kls; ++j) {
+          da.lv_item[j] = L[j].item.get();
+          da.step_pre[j] = step_pre[j];
+          da.ls_first[j] = ls_first[j].get();
+          da.ls_count[j] = ls_count[j].get();
+        }
+        da.arena = arena.get();
+        da.arena_count = ctrl.get() + 1;
+        da.arena_cap = (uint32_t)cap;
+        da.flags = dflags.get();
+        da.level_cand = lstat.get();
+        da.level_freq = lstat.get() + (BM_MAX_LEVELS + 1);
+        da.words_read = lstat.get() + 2 * (BM_MAX_LEVELS + 1);
+        da.task_cost = trace ? cost.get() : nullptr;
+        tm.begin(BM_K_DFS);
+        launch_dfs(da, tu.dfs_threads,
+                   (uint32_t)std::min<uint64_t>(D, (uint64_t)cu_count() * (2048 / tu.dfs_threads)), s);
+        tm.end();
+        uint32_t hc[2], hf = 0;
+        BM_HIP(hipMemcpyAsync(hc, ctrl.get(), 8, hipMemcpyDeviceToHost, s));
+        BM_HIP(hipMemcpyAsync(&hf, dflags.get(), 4, hipMemcpyDeviceToHost, s));
+        BM_HIP(hipMemcpyAsync(hstat.data(), lstat.get(), hstat.size() * 8, hipMemcpyDeviceToHost, s));
+        BM_HIP(hipStreamSynchronize(s));
+        st.host_syncs++;
+        if (hf & DFS_TOO_LONG)
+          fail(BM_ERR_UNSUPPORTED, "frequent itemsets longer than %d items", BM_MAX_LEVELS);
+        if (hf & DFS_STACK) fail(BM_ERR_DEVICE, "depth-first stack exhausted");
+        if (hf & DFS_OVERFLOW) {
+          // the count includes the blocks that did not fit but not their
+          // unexplored subtrees: grow at least fourfold per attempt
+          if (attempt >= 8) fail(BM_ERR_OOM, "depth-first output keeps overflowing");
+          cap = std::max<uint64_t>(4 * cap, 2 * (uint64_t)hc[1]);
+          continue;
+        }
+        break;
+      }
+      double dfs_cand = 0;
+      for (int len = 0; len <= BM_MAX_LEVELS; ++len) {
+        st.candidates[len] += hstat[len];
+        st.candidates_total += hstat[len];
+        dfs_cand += (double)hstat[len];
+      }
+      tm.set_last(8.0 * (double)hstat[2 * (BM_MAX_LEVELS + 1)], dfs_cand * nW);
+      if (trace) {
+        store->trace_rows = D;
+        store->trace_feats.reset(D * MLP_IN, s);
+        store->trace_cost.reset(D, s);
+        BM_HIP(hipMemcpyAsync(store->trace_feats.get(), feats.get(), D * MLP_IN * 4,
+                              hipMemcpyDeviceToDevice, s));
+        BM_HIP(hipMemcpyAsync(store->trace_cost.get(), cost.get(), D * 4, hipMemcpyDeviceToDevice, s));
+      }
+
+      // merge: final level k+1 = the children of final level k's nodes, in order,
+      // taken from the level-synchronous level k+1 or from the arena
+      tm.begin(BM_K_EMIT);
+      std::vector<Level> FL(2);
+      std::vector<TBuf<uint32_t>> skind(2), sfirst(2), scount(2);
+      FL[1].n = L[1].n;
+      FL[1].item.alloc(L[1].n, s);
+      FL[1].parent.alloc(L[1].n, s);
+      FL[1].supp.alloc(L[1].n, s);
+      FL[1].db.alloc(L[1].n, s);
+      skind[1].alloc(L[1].n, s);
+      sfirst[1].alloc(L[1].n, s);
+      scount[1].alloc(L[1].n, s);
+      launch_fin_level1(L[1].n, L[1].item.get(), L[1].parent.get(), L[1].supp.get(), L[1].db.get(),
+                        Kls >= 2 ? L[1].cstart.get() : nullptr, ls_first[1].get(),
+                        ls_count[1].get(), FL[1].item.get(), FL[1].parent.get(), FL[1].supp.get(),
+                        FL[1].db.get(), skind[1].get(), sfirst[1].get(), scount[1].get(), s);
+      for (uint32_t k = 1;; ++k) {
+        const uint64_t nk = FL[k].n;
+        FL[k].cstart.alloc(nk + 1, s);
+        scan32(scount[k].get(), FL[k].cstart.get(), nk, s);
+        const uint64_t nn = read_back(FL[k].cstart.get() + nk, s);
+        st.host_syncs++;
+        if (nn == 0) break;
+        if (k + 1 > BM_MAX_LEVELS)
+          fail(BM_ERR_UNSUPPORTED, "frequent itemsets longer than %d items", BM_MAX_LEVELS);
+        FL.emplace_back();
+        skind.emplace_back();
+        sfirst.emplace_back();
+        scount.emplace_back();
+        Level& Fn = FL[k + 1];
+        Fn.n = nn;
+        Fn.item.alloc(nn, s);
+        Fn.parent.alloc(nn, s);
+        Fn.supp.alloc(nn, s);
+        Fn.db.alloc(nn, s);
+        skind[k + 1].alloc(nn, s);
+        sfirst[k + 1].alloc(nn, s);
+        scount[k + 1].alloc(nn, s);
+        const bool has_ls = k + 1 <= Kls;
+        launch_fin_gather(nk, FL[k].db.get(), skind[k].get(), sfirst[k].get(), scount[k].get(),
+                          FL[k].cstart.get(), has_ls ? L[k + 1].item.get() : nullptr,
+                          has_ls ? L[k + 1].supp.get() : nullptr, has_ls ? L[k + 1].db.get() : nullptr,
+                          (k + 2 <= Kls) ? L[k + 1].cstart.get() : nullptr,
+                          has_ls ? ls_first[k + 1].get() : nullptr,
+                          has_ls ? ls_count[k + 1].get() : nullptr, arena.get(), Fn.item.get(),
+                          Fn.parent.get(), Fn.supp.get(), Fn.db.get(), skind[k + 1].get(),
+                          sfirst[k + 1].get(), scount[k + 1].get(), s);
+      }
+      tm.end();
+      for (uint32_t k = 1; k < FL.size(); ++k) st.frequent[k] = FL[k].n;
+      L.swap(FL);
     }
 
     // ---- canonical output (all databases as one forest, database by database)
@@ -692,6 +910,19 @@ void result_copy(const bm_result* r, uint64_t* offsets, uint32_t* items, uint32_
   if (supports && r->n_sets)
     BM_HIP(hipMemcpyAsync(supports, st.supports.get() + r->set0, r->n_sets * 4, hipMemcpyDefault, s));
   BM_HIP(hipStreamSynchronize(s));
+}
+
+void result_trace(const bm_result* r, float* feats, float* labels, uint64_t* rows) {
+  const ResultStore& st = *r->store;
+  const uint64_t n = st.trace_rows;
+  if (rows) *rows = n;
+  if (n == 0) return;
+  if (feats) BM_HIP(hipMemcpy(feats, st.trace_feats.get(), n * MLP_IN * 4, hipMemcpyDefault));
+  if (labels) {
+    std::vector<float> c(n);
+    BM_HIP(hipMemcpy(c.data(), st.trace_cost.get(), n * 4, hipMemcpyDeviceToHost));
+    for (uint64_t i = 0; i < n; ++i) labels[i] = std::log2(1.0f + c[i]);
+  }
 }
 
 }  // namespace bm

@@ -160,6 +160,12 @@ void KTimer::end(double bytes, double ops) {
   cur_a_ = nullptr;
 }
 
+void KTimer::set_last(double bytes, double ops) {
+  if (!on_ || recs_.empty()) return;
+  recs_.back().bytes = bytes;
+  recs_.back().ops = ops;
+}
+
 void KTimer::collect(bm_stats* st) {
   for (auto& r : recs_) {
     BM_HIP(hipEventSynchronize(r.b));

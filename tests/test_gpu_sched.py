@@ -1,0 +1,250 @@
+"""GPU tests of the depth-first subtree phase and the learned scheduler.
+
+* The depth-first path (default) must give the same canonical result, byte for
+  byte, as the purely level-synchronous path and as the oracle, whatever order
+  the subtree tasks are taken in (shuffled queues, learned order).
+* The cost model's forward pass, backward pass and Adam step on the device
+  must match the float64 oracle (oracle/mlp.py) evaluated on the same
+  BF16-rounded weights; the tolerance follows from FP32 accumulation over at
+  most 64-term dot products and a few hundred rows (relative error well
+  below 1e-4), and rows whose pre-activations lie within 1e-3 of a ReLU kink
+  are left out so that FP32 and FP64 take the same branch.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import gen
+from oracle import mlp as omlp
+from oracle import cpp as ocpp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bm():
+    import torch
+    assert torch.cuda.is_available(), "needs a GPU"
+    torch.cuda.init()
+    import paper_2412_19420_amd as bm
+    return bm
+
+
+def _arrays_equal(a, b):
+    return all(np.array_equal(np.asarray(x).astype(np.int64), np.asarray(y).astype(np.int64))
+               for x, y in zip(a, b))
+
+
+def _oracle(db, minsup):
+    o = ocpp.OracleDb(db.row_ptr, db.col_idx, db.n, db.m)
+    offs, items, supp, _ = o.mine_arrays(minsup)
+    return offs, items, supp
+
+
+def _cases():
+    out = []
+    for seed in range(4):
+        d = gen.random_small(seed, 300 + 40 * seed, 24, density=0.2 + 0.05 * seed)
+        out.append((f"small{seed}", d, 12 + seed))
+    out.append(("basket", gen.make_config(1), None))
+    out.append(("quest", gen.make_config(2), None))
+    out.append(("dense_reduced", gen.make_config(3, scale=0.02), None))
+    return out
+
+
+@pytest.mark.parametrize("name,db,minsup", _cases(), ids=[c[0] for c in _cases()])
+def test_depth_first_equals_level_sync_and_oracle(bm, name, db, minsup):
+    minsup = db.minsup if minsup is None else minsup
+    print(f"dfs vs levelsync {name} n={db.n} m={db.m} minsup={minsup}", flush=True)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    r_dfs = bm.bm_mine(h, minsup)
+    r_ls = bm.bm_mine_ex(h, minsup, bm.options(bm.FLAG_LEVELSYNC))
+    want = _oracle(db, minsup)
+    assert _arrays_equal(r_dfs.arrays(), want)
+    assert _arrays_equal(r_ls.arrays(), want)
+    s1, s2 = r_dfs.stats(), r_ls.stats()
+    assert s1["candidates"] == s2["candidates"]
+    assert s1["frequent"] == s2["frequent"]
+
+
+@pytest.mark.parametrize("mmc", [2, 9, 16, 64])
+def test_depth_first_under_class_routings(bm, mmc):
+    db = gen.make_config(2)
+    print(f"dfs routing mfma_min_children={mmc}", flush=True)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    r = bm.bm_mine_ex(h, db.minsup, bm.options(mfma_min_children=mmc))
+    assert _arrays_equal(r.arrays(), _oracle(db, db.minsup))
+
+
+def test_queue_order_does_not_change_result(bm):
+    db = gen.make_config(3, scale=0.02)
+    print("shuffled queues", flush=True)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    base = bm.bm_mine(h, db.minsup).arrays()
+    for seed in (1, 2, 3):
+        r = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_SHUFFLE, shuffle_seed=seed))
+        assert _arrays_equal(r.arrays(), base), seed
+
+
+def test_trace_rows_and_labels(bm):
+    db = gen.make_config(3, scale=0.02)
+    print("trace", flush=True)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    r1 = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_TRACE))
+    r2 = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_TRACE | bm.FLAG_SHUFFLE, shuffle_seed=5))
+    f1, y1 = r1.trace()
+    f2, y2 = r2.trace()
+    assert len(y1) > 0 and f1.shape == (len(y1), 8)
+    # features and per-task costs do not depend on the order tasks are taken in
+    assert np.array_equal(f1, f2) and np.array_equal(y1, y2)
+    assert np.all(np.isfinite(f1)) and np.all(y1 >= 0)
+    # label = log2(1 + candidates in the subtree); they add up to the depth-first share
+    cost = np.exp2(y1.astype(np.float64)) - 1
+    assert np.all(cost >= 1 - 1e-3)  # a task is a class with >= 2 children: >= 1 candidate
+    st = r1.stats()
+    assert cost.sum() <= st["candidates_total"] * (1 + 1e-4)
+    # feature 0 is the level of the task's children, feature 2 is log2(1 + q) with 2 <= q <= 8
+    assert np.all(f1[:, 0] >= 1)
+    q = np.exp2(f1[:, 2].astype(np.float64)) - 1
+    assert np.all((q > 1.99) & (q < 8.01))
+    assert np.allclose(q, np.round(q), atol=1e-3)
+
+
+# ------------------------------------------------------------------ cost model
+
+def _model_data(seed, rows):
+    rng = np.random.default_rng(seed)
+    X = np.column_stack([
+        rng.integers(1, 12, rows), rng.uniform(4, 20, rows), np.log2(1 + rng.integers(2, 9, rows)),
+        rng.uniform(2, 18, rows), rng.uniform(0, 1, rows), rng.uniform(0, 1, rows),
+        rng.uniform(3, 16, rows), rng.uniform(6, 14, rows)]).astype(np.float32)
+    Y = rng.uniform(0, 12, rows).astype(np.float32)
+    return X, Y
+
+
+def _norm_of(X):
+    mean = X.astype(np.float64).mean(axis=0)
+    sd = X.astype(np.float64).std(axis=0, ddof=1)
+    return np.concatenate([mean, 1.0 / np.where(sd > 1e-6, sd, 1.0)]).astype(np.float32)
+
+
+def _away_from_kinks(p, norm, X, eps=1e-3):
+    _, (_, z1, _, z2, _) = omlp.forward(p, norm, X)
+    return (np.abs(z1).min(axis=1) > eps) & (np.abs(z2).min(axis=1) > eps)
+
+
+def _setup_model(bm, seed, rows):
+    """A fresh model with standardisation set, and exactly `rows` rows away from kinks."""
+    X, Y = _model_data(seed, 2 * rows + 64)
+    norm = _norm_of(X)
+    m = bm.Model(seed=seed)
+    m.set_params(norm=norm)
+    master, wbf, nrm = m.params()
+    assert np.array_equal(nrm, norm)
+    # the device weights are the master copy rounded to BF16
+    assert np.array_equal(wbf, omlp.bf16_round(master))
+    keep = np.flatnonzero(_away_from_kinks(wbf.astype(np.float64), nrm.astype(np.float64), X))
+    assert len(keep) >= rows
+    keep = keep[:rows]
+    return m, X[keep], Y[keep], master, wbf, nrm
+
+
+@pytest.mark.parametrize("rows", [1, 63, 64, 65, 300, 5000])
+def test_model_forward_matches_oracle(bm, rows):
+    print(f"model forward rows={rows}", flush=True)
+    m, X, Y, master, wbf, nrm = _setup_model(bm, 11, rows)
+    got = m.predict(X).astype(np.float64)
+    want, _ = omlp.forward(wbf.astype(np.float64), nrm, X)
+    tol = 1e-4 * np.abs(want) + 1e-5 * max(1.0, np.abs(want).max(initial=0))
+    assert np.all(np.abs(got - want) <= tol)
+
+
+@pytest.mark.parametrize("rows", [1, 64, 65, 300, 4097])
+def test_model_grad_matches_oracle(bm, rows):
+    print(f"model grad rows={rows}", flush=True)
+    m, X, Y, master, wbf, nrm = _setup_model(bm, 12, rows)
+    n = len(Y)
+    g, loss = m.grad(X, Y)
+    scale = 1.0 / n
+    go = omlp.grad(wbf.astype(np.float64), nrm, X, Y, scale)
+    lo = omlp.loss(wbf.astype(np.float64), nrm, X, Y, scale)
+    assert abs(loss - lo) <= 1e-4 * abs(lo) + 1e-6
+    tol = 1e-4 * np.abs(go) + 1e-5 * np.abs(go).max()
+    assert np.all(np.abs(g - go) <= tol)
+
+
+def test_model_adam_step_matches_oracle(bm):
+    print("model adam step", flush=True)
+    m, X, Y, master, wbf, nrm = _setup_model(bm, 13, 256)
+    lr = 1e-3
+    m.train(X, Y, epochs=1, lr=lr, batch=len(Y))
+    got, wbf_new, _ = m.params()
+    go = omlp.grad(wbf.astype(np.float64), nrm, X, Y, 1.0 / len(Y))
+    want, _, _ = omlp.adam(master.astype(np.float64), 0.0, 0.0, go, lr, 1)
+    big = np.abs(go) > 1e-3 * np.abs(go).max()
+    # where the gradient is clearly non-zero the first step is lr * sign(g)
+    assert np.allclose(got[big], want[big], rtol=0, atol=1e-6)
+    assert np.all(np.abs(got - master) <= lr * (1 + 1e-3))
+    assert np.array_equal(wbf_new, omlp.bf16_round(got))
+
+
+def test_model_training_reduces_loss_and_roundtrips(bm, tmp_path):
+    print("model training", flush=True)
+    rng = np.random.default_rng(5)
+    X, _ = _model_data(5, 4096)
+    # a smooth target of the features
+    Y = (0.8 * X[:, 0] + 2.0 * X[:, 2] + 0.3 * X[:, 1] - X[:, 4] + rng.normal(0, 0.1, len(X)))
+    Y = Y.astype(np.float32)
+    m = bm.Model(seed=1)
+    first = m.train(X, Y, epochs=1, lr=3e-3, batch=256)
+    last = m.train(X, Y, epochs=30, lr=3e-3, batch=256)
+    assert last < 0.2 * first, (first, last)
+    path = str(tmp_path / "model.bin")
+    m.save(path)
+    m2 = bm.Model(path=path)
+    a, b = m.params(), m2.params()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert np.array_equal(m.predict(X), m2.predict(X))
+
+
+def test_learned_order_keeps_results(bm):
+    print("learned order on a batch", flush=True)
+    dbs = [gen.batch_db(k, scale=0.05) for k in range(6)]
+    hs = [bm.bm_build(d.row_ptr, d.col_idx, d.n, d.m) for d in dbs]
+    ms = [d.minsup for d in dbs]
+    plain = bm.bm_mine_batch(hs, ms, opts=bm.options(bm.FLAG_TRACE))
+    f, y = plain[0].trace()
+    assert len(y) > 0
+    model = bm.Model(seed=3)
+    model.train(f, y, epochs=10, lr=3e-3, batch=256)
+    learned = bm.bm_mine_batch(hs, ms, model=model)
+    for d, a, b in zip(dbs, plain, learned):
+        assert _arrays_equal(a.arrays(), b.arrays())
+        assert _arrays_equal(a.arrays(), _oracle(d, d.minsup))
+
+
+@pytest.mark.parametrize("threads", [256, 512, 1024])
+def test_depth_first_block_sizes(bm, threads):
+    db = gen.make_config(3, scale=0.02)
+    print(f"dfs threads={threads}", flush=True)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    base = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_LEVELSYNC)).arrays()
+    r = bm.bm_mine_ex(h, db.minsup, bm.options(dfs_threads=threads))
+    assert r.stats()["dfs_tasks"] > 0
+    assert _arrays_equal(r.arrays(), base)
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_depth_first_forced_on_full_size(bm, k):
+    # full-size columns (15,625 words) exceed the default depth-first cut-off;
+    # forcing the depth-first phase must still give the level-synchronous result
+    db = gen.make_config(k)
+    print(f"forced dfs on workload {k} n={db.n}", flush=True)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    base = bm.bm_mine(h, db.minsup)
+    assert base.stats()["dfs_tasks"] == 0
+    r = bm.bm_mine_ex(h, db.minsup, bm.options(dfs_threads=1024, dfs_max_words=0xFFFFFFFF))
+    assert r.stats()["dfs_tasks"] > 0
+    assert _arrays_equal(r.arrays(), base.arrays())
