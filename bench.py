@@ -39,6 +39,8 @@ WORKLOADS = {
     1: "basket_zipf 10,000 tx x 169 items, minsup 1% (100)",
     2: "quest T10I4D100K-style 100,000 tx x 1,000 items, minsup 0.25% (250)",
     3: "dense_planted 1,000,000 tx x 4,096 items, 500 planted 6-item patterns, minsup 1% (10,000)",
+    4: "batch of 256 quest-style databases (1k-200k tx log-uniform, 50-2,000 items, mean length "
+       "5-20, minsup 0.5-5%)",
     5: "quest T40I10D1M-style 1,000,000 tx x 2,000 items, minsup 0.5% (5,000)",
 }
 
@@ -67,12 +69,165 @@ def cpu_baseline(db, budget_s: float = 12.0) -> dict:
     }
 
 
+def _kernel_table(stats, steps):
+    names = list(stats[0]["kernel_ms"])
+    ms = {k: sum(s["kernel_ms"][k] for s in stats) for k in names}
+    launches = {k: sum(s["kernel_launches"][k] for s in stats) for k in names}
+    kernels = {}
+    for k in names:
+        if launches[k] == 0:
+            continue
+        per = ms[k] / launches[k]
+        by = sum(s["kernel_bytes"][k] for s in stats) / launches[k]
+        op = sum(s["kernel_ops"][k] for s in stats) / launches[k]
+        kernels[k] = {"ms_per_step": round(ms[k] / steps, 4), "launches_per_step":
+                      launches[k] / steps, "avg_launch_ms": round(per, 4)}
+        if k == "gram_mfma":
+            kernels[k]["achieved_TOPs"] = round(op / (per * 1e-3) / 1e12, 2)
+            kernels[k]["algorithmic_ops_per_launch"] = op
+        if k in HBM_KERNELS:
+            kernels[k]["achieved_GBs"] = round(by / (per * 1e-3) / 1e9, 1)
+            kernels[k]["algorithmic_bytes_per_launch"] = by
+    return kernels, ms
+
+
+def _roofline(kernels, ms):
+    dom = max((k for k in kernels if k == "gram_mfma" or k in HBM_KERNELS), key=lambda k: ms[k],
+              default=None)
+    if dom == "gram_mfma":
+        a = kernels[dom]["achieved_TOPs"]
+        return {"bound": "mfma", "kernel": "k_gram_mfma (int8 MFMA Gram of a prefix class)",
+                "achieved": a, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+                "frac": round(a / INT8_PEAK_TOPS, 4), "traffic": None}
+    if dom is not None:
+        a = kernels[dom]["achieved_GBs"]
+        return {"bound": "hbm", "kernel": HBM_KERNELS[dom], "achieved": a, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(a / HBM_PEAK_GBS, 4), "traffic": None}
+    return None
+
+
+def run_batched(args, bm, torch, dev):
+    """The batched workload: 256 databases per step, mined four ways on the same
+    device-resident inputs -- one plain level-synchronous call per database
+    (the plain GPU miner), one batched level-synchronous call, one batched call
+    with the depth-first phase in queue order, and one batched call whose
+    subtree queue is ordered by the cost model.  The model is trained first, on
+    the GPU, on traces of 64 held-out databases of the same distribution."""
+    import gen
+    t0 = time.time()
+    dbs = gen.make_config(4)
+    held = [gen.batch_db(k) for k in range(256, 320)]
+    print(f"# 256 + 64 databases generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    dev_in = [(torch.from_numpy(d.row_ptr.astype(np.uint64)).to(dev),
+               torch.from_numpy(d.col_idx.astype(np.uint32)).to(dev)) for d in dbs]
+    ms_list = [d.minsup for d in dbs]
+
+    def build_each(items, src):
+        return [bm.bm_build(rp, ci, d.n, d.m, stream=stream) for d, (rp, ci) in zip(items, src)]
+
+    def build_batch(items, src):
+        return bm.bm_build_batch([(rp, ci, d.n, d.m) for d, (rp, ci) in zip(items, src)],
+                                 stream=stream)
+
+    # cost model: trained on the GPU from traces of the held-out databases
+    hh = build_batch(held, [(torch.from_numpy(d.row_ptr.astype(np.uint64)).to(dev),
+                           torch.from_numpy(d.col_idx.astype(np.uint32)).to(dev)) for d in held])
+    tr = bm.bm_mine_batch(hh, [d.minsup for d in held], opts=bm.options(bm.FLAG_TRACE),
+                          stream=stream)
+    f, y = tr[0].trace()
+    model = bm.Model(seed=1)
+    t1 = time.time()
+    loss = model.train(f, y, epochs=40, lr=3e-3, batch=256, stream=stream)
+    print(f"# cost model: {len(y)} traced tasks, final loss {loss:.4f}, trained in "
+          f"{time.time() - t1:.2f} s", file=sys.stderr, flush=True)
+    del tr, hh
+
+    timing = 0 if args.no_timing else bm.FLAG_TIMING
+    o_ls = bm.options(timing | bm.FLAG_LEVELSYNC)
+    o_dfs = bm.options(timing)
+    # mode: (build, mine); the plain miner builds and mines one database per call
+    modes = {
+        "plain_per_db": (build_each, lambda hs: [bm.bm_mine_ex(h, m, o_ls, stream=stream)
+                                                 for h, m in zip(hs, ms_list)]),
+        "batched_levelsync": (build_batch, lambda hs: bm.bm_mine_batch(hs, ms_list, opts=o_ls,
+                                                                       stream=stream)),
+        "batched_depth_first": (build_batch, lambda hs: bm.bm_mine_batch(hs, ms_list, opts=o_dfs,
+                                                                         stream=stream)),
+        "batched_learned": (build_batch, lambda hs: bm.bm_mine_batch(hs, ms_list, model=model,
+                                                                     opts=o_dfs, stream=stream)),
+    }
+    # identical output in every mode (checked once, untimed)
+    ref = [r.arrays() for r in modes["plain_per_db"][1](build_each(dbs, dev_in))]
+    for name in list(modes)[1:]:
+        build, fn = modes[name]
+        got = fn(build(dbs, dev_in))
+        for a, b in zip(ref, got):
+            assert all(np.array_equal(x, y) for x, y in zip(a, b.arrays())), name
+    print("# all modes give identical results", file=sys.stderr, flush=True)
+
+    res = {}
+    for name, (build, fn) in modes.items():
+        for _ in range(args.warmup):
+            fn(build(dbs, dev_in))
+        torch.cuda.synchronize()
+        stats = []
+        t_start = time.perf_counter()
+        build_s = 0.0
+        for i in range(args.steps):
+            tb = time.perf_counter()
+            hs = build(dbs, dev_in)
+            torch.cuda.synchronize()
+            build_s += time.perf_counter() - tb
+            rs = fn(hs)
+            torch.cuda.synchronize()
+            stats.append(rs[0].stats() if name != "plain_per_db" else None)
+            if name == "plain_per_db":
+                cand = sum(r.stats()["candidates_total"] for r in rs)
+            else:
+                cand = rs[0].stats()["candidates_total"]
+            del hs, rs
+        total = time.perf_counter() - t_start
+        res[name] = {"ms_per_step": round(1e3 * total / args.steps, 3),
+                     "build_ms": round(1e3 * build_s / args.steps, 3),
+                     "mine_ms": round(1e3 * (total - build_s) / args.steps, 3),
+                     "candidates": cand, "stats": stats}
+        print(f"# {name}: {res[name]['ms_per_step']} ms/step (mine {res[name]['mine_ms']} ms)",
+              file=sys.stderr, flush=True)
+
+    best = res["batched_learned"]
+    kernels, kms = (_kernel_table(best["stats"], args.steps) if not args.no_timing else ({}, {}))
+    st = best["stats"][-1]
+    out = {
+        "metric": "candidate supports counted/s + mine wall time at minsup; % of HBM peak",
+        "value": round(best["candidates"] / (best["ms_per_step"] * 1e-3), 1),
+        "unit": "candidate supports/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": best["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64 bitsets; int8 MFMA, int32 accumulate",
+        "data": "synthetic (seeded generator, see DESIGN.md)",
+        "config": {"workload": WORKLOADS[4], "databases": len(dbs), "candidates": best["candidates"],
+                   "dfs_tasks": st["dfs_tasks"], "host_syncs": st["host_syncs"],
+                   "modes": {k: {kk: vv for kk, vv in v.items() if kk != "stats"}
+                             for k, v in res.items()},
+                   "learned_vs_plain_speedup": round(res["plain_per_db"]["ms_per_step"] /
+                                                     best["ms_per_step"], 3),
+                   "learned_vs_batched_depth_first": round(res["batched_depth_first"]["mine_ms"] /
+                                                           best["mine_ms"], 3),
+                   "kernels": kernels},
+        "roofline": _roofline(kernels, kms) if kernels else None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", type=int, default=3, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", type=int, default=3, choices=sorted(WORKLOADS),
+                    help="1-3, 5: one database; 4: the batch of 256 (mode comparison)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--mfma-min-children", type=int, default=0)
@@ -110,6 +265,10 @@ def main():
 
     import gen
     import paper_2412_19420_amd as bm
+
+    if args.workload == 4:
+        run_batched(args, bm, torch, dev)
+        return
 
     t0 = time.time()
     db = gen.make_config(args.workload)
@@ -171,38 +330,8 @@ def main():
     assert all(x == results[0] for x in results), "result changed between steps"
 
     # dominant kernel by total event time
-    names = list(st["kernel_ms"])
-    ms = {k: sum(s["kernel_ms"][k] for s in stats) for k in names}
-    launches = {k: sum(s["kernel_launches"][k] for s in stats) for k in names}
-    roofline = None
-    kernels = {}
-    for k in names:
-        if launches[k] == 0:
-            continue
-        per = ms[k] / launches[k]
-        by = sum(s["kernel_bytes"][k] for s in stats) / launches[k]
-        op = sum(s["kernel_ops"][k] for s in stats) / launches[k]
-        kernels[k] = {"ms_per_step": round(ms[k] / args.steps, 4), "launches_per_step":
-                      launches[k] / args.steps, "avg_launch_ms": round(per, 4)}
-        if k == "gram_mfma":
-            kernels[k]["achieved_TOPs"] = round(op / (per * 1e-3) / 1e12, 2)
-            kernels[k]["algorithmic_ops_per_launch"] = op
-        if k in HBM_KERNELS:
-            kernels[k]["achieved_GBs"] = round(by / (per * 1e-3) / 1e9, 1)
-            kernels[k]["algorithmic_bytes_per_launch"] = by
-    if not args.no_timing and kernels:
-        dom = max((k for k in kernels if k == "gram_mfma" or k in HBM_KERNELS), key=lambda k: ms[k],
-                  default=None)
-        if dom == "gram_mfma":
-            a = kernels[dom]["achieved_TOPs"]
-            roofline = {"bound": "mfma", "kernel": "k_gram_mfma (int8 MFMA Gram of a prefix class)",
-                        "achieved": a, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
-                        "frac": round(a / INT8_PEAK_TOPS, 4), "traffic": None}
-        elif dom is not None:
-            a = kernels[dom]["achieved_GBs"]
-            roofline = {"bound": "hbm", "kernel": HBM_KERNELS[dom],
-                        "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(a / HBM_PEAK_GBS, 4), "traffic": None}
+    kernels, kms = _kernel_table(stats, args.steps)
+    roofline = _roofline(kernels, kms) if (not args.no_timing and kernels) else None
 
     out = {
         "metric": "candidate supports counted/s + mine wall time at minsup; % of HBM peak",

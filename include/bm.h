@@ -101,7 +101,7 @@ typedef struct {
 #define BM_FLAG_TIMING 1u      /* record per-kernel hipEvent times into bm_stats */
 #define BM_FLAG_NO_MFMA 2u     /* send every class to the AND+popcount kernel */
 #define BM_FLAG_ALL_MFMA 4u    /* send every class with >= 2 children to the MFMA kernel */
-#define BM_FLAG_GRAPH 8u       /* bm_mine_batch: replay the launch sequence as a hipGraph */
+#define BM_FLAG_GRAPH 8u       /* bm_model_train_ex: replay each training epoch as a hipGraph */
 #define BM_FLAG_TRACE 16u      /* keep per-class features and subtree costs (bm_result_trace) */
 #define BM_FLAG_SHUFFLE 32u    /* random subtree-task order (order-invariance tests) */
 #define BM_FLAG_LEVELSYNC 64u  /* evaluate small classes level by level too (no depth-first kernel) */
@@ -146,6 +146,17 @@ bm_status bm_release_cached_memory(void);
  * (n_tx >= 2^31), BM_ERR_OOM, BM_ERR_DEVICE.  n_tx == 0 or n_items == 0 is valid. */
 bm_status bm_build(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n_tx,
                    uint32_t n_items, void* stream, bm_db** out);
+
+/* Batched bm_build: `count` databases (host arrays of per-database row_ptr
+ * and col_idx pointers, each host or device, and of sizes; col_idxs may be
+ * NULL when every database is empty) are validated and packed by two kernel
+ * launches for the whole batch and one synchronisation, instead of one call
+ * each.  out[i] equals what bm_build would return for database i.  All or
+ * nothing: on failure every out[i] is NULL and bm_last_error names the first
+ * failing database. */
+bm_status bm_build_batch(uint32_t count, const uint64_t* const* row_ptrs,
+                         const uint32_t* const* col_idxs, const uint64_t* n_tx,
+                         const uint32_t* n_items, void* stream, bm_db** out);
 bm_status bm_db_info(const bm_db* db, uint64_t* n_tx, uint32_t* n_items, uint64_t* words_per_column);
 
 /* Single-item supports S({j}) = popcount of column j (Eq. 3's column aggregation).
@@ -185,6 +196,18 @@ bm_status bm_mine_batch(const bm_db* const* dbs, const uint32_t* minsups, uint32
                         const bm_model* sched, const bm_options* opt, void* stream,
                         bm_result** out);
 
+/* Autotuner (batching design, word tiles and block shapes): times real calls of
+ * bm_mine_batch on these databases over a coordinate search of the tuning
+ * fields of bm_options -- depth-first phase off / default cut-off / always,
+ * mfma_min_children, split_words, andpop_chunk_words, dfs_threads -- and writes
+ * the fastest combination to *best (base's other flags kept; NULL base =
+ * defaults).  Each point is the minimum of `reps` calls (0 = 3); *best_ms
+ * (optional) receives its wall time.  No tuning field changes the mined
+ * result, so *best can be passed to bm_mine_ex / bm_mine_batch as is. */
+bm_status bm_autotune(const bm_db* const* dbs, const uint32_t* minsups, uint32_t count,
+                      const bm_model* sched, const bm_options* base, uint32_t reps, void* stream,
+                      bm_options* best, double* best_ms);
+
 /* Result access.  n_sets frequent itemsets holding n_items_total item ids. */
 bm_status bm_result_info(const bm_result* r, uint64_t* n_sets, uint64_t* n_items_total,
                          uint32_t* max_len);
@@ -216,11 +239,20 @@ bm_status bm_result_trace(const bm_result* r, float* feats, float* labels, uint6
 bm_status bm_model_create(uint32_t seed, bm_model** out);  /* He-uniform init from `seed` */
 bm_status bm_model_load(const char* path, bm_model** out);
 bm_status bm_model_save(const bm_model* m, const char* path);
-/* Minibatch Adam (batch rows per step, 0 = 256) over `epochs` passes; *final_loss
- * (may be NULL) receives the last epoch's mean squared error. */
+/* Minibatch Adam (batch rows per step, 0 = 256) over `epochs` passes, rows in
+ * order; *final_loss (may be NULL) receives the last epoch's mean over batches
+ * of the batch mean squared error.  Epochs after capture are replayed as one
+ * hipGraph each (bm_model_train_ex with BM_FLAG_GRAPH).  Training is
+ * deterministic: gradients are summed per workgroup and then in a fixed order. */
 bm_status bm_model_train(bm_model* m, const float* feats, const float* labels, uint64_t rows,
                          uint32_t epochs, float lr, uint32_t batch, float* final_loss,
                          void* stream);
+/* As bm_model_train; flags: 0 (every launch issued from the host) or
+ * BM_FLAG_GRAPH (one epoch captured as a hipGraph and replayed `epochs`
+ * times; identical results).  epoch_losses: NULL or host float[epochs]. */
+bm_status bm_model_train_ex(bm_model* m, const float* feats, const float* labels, uint64_t rows,
+                            uint32_t epochs, float lr, uint32_t batch, uint32_t flags,
+                            float* epoch_losses, void* stream);
 bm_status bm_model_predict(const bm_model* m, const float* feats, uint64_t rows, float* out,
                            void* stream);
 /* Gradient of the mean squared error over `rows` (float[4801]) and the loss,

@@ -15,6 +15,7 @@ fallback: importing it without the built library raises ImportError.
 from __future__ import annotations
 
 import ctypes
+import os
 
 import numpy as np
 
@@ -23,10 +24,11 @@ from ._bm import (BM_K_NAMES, FLAG_ALL_MFMA, FLAG_GRAPH, FLAG_LEVELSYNC, FLAG_NO
                   FLAG_SHUFFLE, FLAG_TIMING, FLAG_TRACE, MLP_PARAMS, BmError, BmOptions)
 
 __all__ = [
-    "bm_abi_version", "bm_build", "bm_item_support", "bm_pair_support", "bm_mine",
+    "bm_abi_version", "bm_build", "bm_build_batch", "bm_item_support", "bm_pair_support", "bm_mine",
     "bm_mine_ex", "bm_mine_batch", "bm_set_allocator", "bm_release_cached_memory", "Db", "Result", "BmError",
     "options", "FLAG_TIMING", "FLAG_NO_MFMA", "FLAG_ALL_MFMA", "FLAG_GRAPH", "FLAG_TRACE",
-    "FLAG_SHUFFLE", "FLAG_LEVELSYNC", "LIB_PATH", "Model", "MLP_PARAMS",
+    "FLAG_SHUFFLE", "FLAG_LEVELSYNC", "LIB_PATH", "Model", "MLP_PARAMS", "bm_autotune",
+    "autotune_cached", "options_to_dict", "options_from_dict", "shape_key",
 ]
 
 LIB_PATH = _bm.LIB_PATH
@@ -183,6 +185,39 @@ def bm_build(row_ptr, col_idx, n_tx: int, n_items: int, stream=None) -> Db:
     return Db(h)
 
 
+def bm_build_batch(items, stream=None) -> list:
+    """Build many databases at once: items = [(row_ptr, col_idx, n_tx, n_items), ...]
+    (numpy arrays or torch tensors; col_idx may be None for an empty database)."""
+    n = len(items)
+    if n == 0:
+        return []
+    keep = []
+    rps = (ctypes.c_void_p * n)()
+    cis = (ctypes.c_void_p * n)()
+    ns = (ctypes.c_uint64 * n)()
+    ms = (ctypes.c_uint32 * n)()
+    for i, (rp, ci, n_tx, n_items) in enumerate(items):
+        if isinstance(rp, np.ndarray):
+            if len(rp) != int(n_tx) + 1:
+                raise ValueError(f"database {i}: row_ptr has {len(rp)} entries, expected {n_tx + 1}")
+            if isinstance(ci, np.ndarray) and len(ci) < int(rp[-1]):
+                raise ValueError(f"database {i}: col_idx has {len(ci)} entries, row_ptr[n] = {rp[-1]}")
+        p, k = _bm._ptr(rp, np.uint64)
+        rps[i] = p.value
+        keep.append(k)
+        if ci is not None and len(ci):
+            p, k = _bm._ptr(ci, np.uint32)
+            cis[i] = p.value
+            keep.append(k)
+        ns[i] = int(n_tx)
+        ms[i] = int(n_items)
+    out = (ctypes.c_void_p * n)()
+    _bm.check(_bm.lib.bm_build_batch(n, rps, cis, ns, ms, _bm._stream_ptr(stream), out),
+              "bm_build_batch")
+    del keep
+    return [Db(ctypes.c_void_p(out[i])) for i in range(n)]
+
+
 def bm_item_support(db: Db, stream=None) -> np.ndarray:
     _, m, _ = db.info()
     out = np.zeros(max(m, 1), dtype=np.uint32)
@@ -240,6 +275,70 @@ def bm_mine_batch(dbs, minsups, model=None, opts: BmOptions | None = None, strea
     return [Result(ctypes.c_void_p(out[i])) for i in range(n)]
 
 
+def bm_autotune(dbs, minsups, model=None, base: BmOptions | None = None, reps: int = 3,
+                stream=None):
+    """(fastest BmOptions, its wall ms) for mining these databases together."""
+    n = len(dbs)
+    if n == 0 or len(minsups) != n:
+        raise ValueError("one minsup per database, at least one database")
+    arr = (ctypes.c_void_p * n)(*[d.handle if d is not None else None for d in dbs])
+    ms = (ctypes.c_uint32 * n)(*[int(x) for x in minsups])
+    best = BmOptions()
+    best_ms = ctypes.c_double()
+    _bm.check(_bm.lib.bm_autotune(arr, ms, n, model.handle if model is not None else None,
+                                  ctypes.byref(base) if base is not None else None, reps,
+                                  _bm._stream_ptr(stream), ctypes.byref(best),
+                                  ctypes.byref(best_ms)), "bm_autotune")
+    return best, float(best_ms.value)
+
+
+_TUNE_FIELDS = ("flags", "mfma_min_children", "andpop_chunk_words", "split_words", "dfs_threads",
+                "dfs_max_words")
+
+
+def options_to_dict(o: BmOptions) -> dict:
+    return {k: int(getattr(o, k)) for k in _TUNE_FIELDS}
+
+
+def options_from_dict(d: dict) -> BmOptions:
+    o = BmOptions()
+    for k in _TUNE_FIELDS:
+        setattr(o, k, int(d.get(k, 0)))
+    return o
+
+
+def shape_key(dbs, minsups) -> str:
+    """Cache key of a tuning problem: database count and rounded size statistics."""
+    import math
+    live = [(d, m) for d, m in zip(dbs, minsups) if d is not None]
+    info = [d.info() for d, _ in live]
+    ns = [i[0] for i in info] or [0]
+    ms_ = [i[1] for i in info] or [0]
+    rel = [m / max(1, i[0]) for (_, m), i in zip(live, info)] or [0]
+    b = lambda x: int(round(math.log2(max(1, x)) * 2))
+    return (f"n{len(dbs)}-tx{b(max(ns))}.{b(sum(ns) / len(ns))}-items{b(max(ms_))}"
+            f"-minsup{b(1e6 * min(rel))}.{b(1e6 * max(rel))}")
+
+
+def autotune_cached(dbs, minsups, cache_path: str, model=None, reps: int = 3, stream=None):
+    """bm_autotune with a JSON cache keyed by shape_key (created or extended in place)."""
+    import json
+    key = shape_key(dbs, minsups)
+    cache = {}
+    if os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+    if key in cache:
+        return options_from_dict(cache[key]["options"]), cache[key]["ms"], True
+    best, ms = bm_autotune(dbs, minsups, model=model, reps=reps, stream=stream)
+    cache[key] = {"options": options_to_dict(best), "ms": ms}
+    tmp = cache_path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, cache_path)
+    return best, ms, False
+
+
 class Model:
     """Scheduler cost model (8 -> 64 -> 64 -> 1, BF16 weights, trained on the GPU)."""
 
@@ -259,14 +358,19 @@ class Model:
         _bm.check(_bm.lib.bm_model_save(self._h, path.encode()), "bm_model_save")
 
     def train(self, feats, labels, epochs: int = 20, lr: float = 1e-3, batch: int = 256,
-              stream=None) -> float:
+              stream=None, graph: bool = True, all_losses: bool = False):
+        """Train on the device; returns the last epoch's loss (or every epoch's)."""
         X = np.ascontiguousarray(feats, dtype=np.float32)
         Y = np.ascontiguousarray(labels, dtype=np.float32)
-        loss = ctypes.c_float()
-        _bm.check(_bm.lib.bm_model_train(self._h, X.ctypes.data, Y.ctypes.data, len(Y), epochs, lr,
-                                         batch, ctypes.byref(loss), _bm._stream_ptr(stream)),
-                  "bm_model_train")
-        return float(loss.value)
+        losses = np.zeros(max(epochs, 1), dtype=np.float32)
+        _bm.check(_bm.lib.bm_model_train_ex(
+            self._h, X.ctypes.data, Y.ctypes.data, len(Y), epochs, lr, batch,
+            FLAG_GRAPH if graph else 0, losses.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+            _bm._stream_ptr(stream)), "bm_model_train_ex")
+        losses = losses[:epochs]
+        if all_losses:
+            return losses
+        return float(losses[-1]) if epochs else 0.0
 
     def predict(self, feats, stream=None) -> np.ndarray:
         X = np.ascontiguousarray(feats, dtype=np.float32)

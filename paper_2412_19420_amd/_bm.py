@@ -118,6 +118,9 @@ lib.bm_model_save.argtypes = [_vp, ctypes.c_char_p]
 lib.bm_model_train.restype = ctypes.c_int
 lib.bm_model_train.argtypes = [_vp, _vp, _vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_float,
                                ctypes.c_uint32, _f32p, _vp]
+lib.bm_model_train_ex.restype = ctypes.c_int
+lib.bm_model_train_ex.argtypes = [_vp, _vp, _vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_float,
+                                  ctypes.c_uint32, ctypes.c_uint32, _f32p, _vp]
 lib.bm_model_predict.restype = ctypes.c_int
 lib.bm_model_predict.argtypes = [_vp, _vp, ctypes.c_uint64, _vp, _vp]
 lib.bm_model_grad.restype = ctypes.c_int
@@ -126,6 +129,11 @@ lib.bm_model_params.restype = ctypes.c_int
 lib.bm_model_params.argtypes = [_vp, _vp, _vp, _vp]
 lib.bm_model_set_params.restype = ctypes.c_int
 lib.bm_model_set_params.argtypes = [_vp, _vp, _vp]
+lib.bm_build_batch.restype = ctypes.c_int
+lib.bm_build_batch.argtypes = [ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp]
+lib.bm_autotune.restype = ctypes.c_int
+lib.bm_autotune.argtypes = [_vp, _vp, ctypes.c_uint32, _vp, _vp, ctypes.c_uint32, _vp, _vp,
+                            ctypes.POINTER(ctypes.c_double)]
 lib.bm_model_free.restype = None
 lib.bm_model_free.argtypes = [_vp]
 lib.bm_db_free.restype = None

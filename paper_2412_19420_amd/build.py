@@ -1,6 +1,6 @@
 """Build libbm.so (HIP, gfx950) in-tree with hipcc.
 
-    python -m paper_2412_19420_amd.build [-v]
+    python paper_2412_19420_amd/build.py [-v]
 
 Every source under csrc/ is compiled for gfx950 only and linked into
 paper_2412_19420_amd/libbm.so.  Objects go to paper_2412_19420_amd/_build/.
@@ -28,7 +28,7 @@ CFLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 SOURCES = ["runtime.hip", "k_build.hip", "k_gram_mfma.hip", "k_andpop.hip", "k_levels.hip",
-           "k_dfs.hip", "k_mlp.hip", "model.hip", "miner.hip", "api.hip"]
+           "k_dfs.hip", "k_mlp.hip", "model.hip", "miner.hip", "autotune.hip", "api.hip"]
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -116,6 +116,30 @@ bm_status bm_mine_batch(const bm_db* const* dbs, const uint32_t* minsups, uint32
   });
 }
 
+bm_status bm_build_batch(uint32_t count, const uint64_t* const* row_ptrs,
+                         const uint32_t* const* col_idxs, const uint64_t* n_tx,
+                         const uint32_t* n_items, void* stream, bm_db** out) {
+  if (out)
+    for (uint32_t i = 0; i < count; ++i) out[i] = nullptr;
+  return guarded([&] {
+    if (count == 0) return;
+    if (!row_ptrs || !n_tx || !n_items || !out)
+      bm::fail(BM_ERR_INVALID_ARG, "row_ptrs, n_tx, n_items or out is NULL");
+    auto r = bm::build_many(count, row_ptrs, col_idxs, n_tx, n_items, as_stream(stream));
+    for (uint32_t i = 0; i < count; ++i) out[i] = r[i];
+  });
+}
+
+bm_status bm_autotune(const bm_db* const* dbs, const uint32_t* minsups, uint32_t count,
+                      const bm_model* sched, const bm_options* base, uint32_t reps, void* stream,
+                      bm_options* best, double* best_ms) {
+  return guarded([&] {
+    if (count == 0 || !dbs || !minsups || !best)
+      bm::fail(BM_ERR_INVALID_ARG, "dbs, minsups or best is NULL, or count is 0");
+    *best = bm::autotune(dbs, minsups, count, sched, base, reps, as_stream(stream), best_ms);
+  });
+}
+
 bm_status bm_mine(const bm_db* db, uint32_t minsup, void* stream, bm_result** out) {
   return bm_mine_ex(db, minsup, nullptr, stream, out);
 }
@@ -175,13 +199,28 @@ bm_status bm_model_save(const bm_model* m, const char* path) {
   });
 }
 
+bm_status bm_model_train_ex(bm_model* m, const float* feats, const float* labels, uint64_t rows,
+                            uint32_t epochs, float lr, uint32_t batch, uint32_t flags,
+                            float* epoch_losses, void* stream) {
+  return guarded([&] {
+    if (!m || (rows && (!feats || !labels))) bm::fail(BM_ERR_INVALID_ARG, "NULL argument");
+    if (!(lr > 0.f)) bm::fail(BM_ERR_INVALID_ARG, "lr must be > 0");
+    if (flags & ~BM_FLAG_GRAPH) bm::fail(BM_ERR_INVALID_ARG, "only BM_FLAG_GRAPH applies to training");
+    const std::vector<float> l = bm::model_train(m, feats, labels, rows, epochs, lr, batch,
+                                                 (flags & BM_FLAG_GRAPH) != 0, as_stream(stream));
+    if (epoch_losses)
+      for (size_t i = 0; i < l.size(); ++i) epoch_losses[i] = l[i];
+  });
+}
+
 bm_status bm_model_train(bm_model* m, const float* feats, const float* labels, uint64_t rows,
                          uint32_t epochs, float lr, uint32_t batch, float* final_loss, void* stream) {
   return guarded([&] {
     if (!m || (rows && (!feats || !labels))) bm::fail(BM_ERR_INVALID_ARG, "NULL argument");
     if (!(lr > 0.f)) bm::fail(BM_ERR_INVALID_ARG, "lr must be > 0");
-    const float l = bm::model_train(m, feats, labels, rows, epochs, lr, batch, as_stream(stream));
-    if (final_loss) *final_loss = l;
+    const std::vector<float> l =
+        bm::model_train(m, feats, labels, rows, epochs, lr, batch, true, as_stream(stream));
+    if (final_loss) *final_loss = l.empty() ? 0.f : l.back();
   });
 }
 

@@ -72,8 +72,14 @@ Tuning tuning_from(const bm_options* opt);
 
 bm_db* build_db(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n, uint32_t m,
                 hipStream_t s);
+std::vector<bm_db*> build_many(uint32_t count, const uint64_t* const* row_ptrs,
+                               const uint32_t* const* col_idxs, const uint64_t* ns,
+                               const uint32_t* ms, hipStream_t s);
 void pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* out, hipStream_t s);
 // Mine `count` databases in one level-synchronous pass; one result per database.
+bm_options autotune(const bm_db* const* dbs, const uint32_t* minsups, uint32_t count,
+                    const bm_model* sched, const bm_options* base, uint32_t reps, hipStream_t s,
+                    double* best_ms);
 std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsups, uint32_t count,
                                   const bm_model* sched, const bm_options* opt, hipStream_t s);
 void result_trace(const bm_result* r, float* feats, float* labels, uint64_t* rows);
@@ -82,8 +88,8 @@ bm_model* model_create(uint32_t seed);
 bm_model* model_load(const char* path);
 void model_save(const bm_model* m, const char* path);
 void model_set_norm_from(bm_model* m, const float* feats, uint64_t rows, hipStream_t s);
-float model_train(bm_model* m, const float* feats, const float* labels, uint64_t rows,
-                  uint32_t epochs, float lr, uint32_t batch, hipStream_t s);
+std::vector<float> model_train(bm_model* m, const float* feats, const float* labels, uint64_t rows,
+                               uint32_t epochs, float lr, uint32_t batch, bool graph, hipStream_t s);
 void model_predict(const bm_model* m, const float* feats, uint64_t rows, float* out, hipStream_t s);
 void model_predict_device(const bm_model* m, const float* dfeats, uint64_t rows, float* dout,
                           hipStream_t s);

@@ -182,6 +182,25 @@ void launch_colsum(const uint64_t* B, uint64_t Wp, uint32_t m, uint32_t* colsum,
 // zeroed); returns false when the shape needs the atomic path (m > 16384).
 bool launch_pack_tiled(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t nnz, uint32_t m,
                        uint64_t* B, uint64_t Wp, uint32_t* colsum, uint32_t* err, hipStream_t s);
+// One database of a batched matrix construction (nnz is filled on the device).
+struct PackJob {
+  const uint64_t* rp;
+  const uint32_t* ci;
+  uint64_t n;
+  uint32_t m;
+  uint32_t pad;
+  uint64_t* B;
+  uint64_t Wp;
+  uint32_t* colsum;
+  uint64_t nnz;
+};
+// Whether the tiled construction handles m items (else the atomic one is used).
+bool pack_tiled_ok(uint32_t m, uint64_t Wp);
+uint64_t pack_blocks(uint64_t Wp);
+// Validate and pack njobs databases in two launches; err[j] gets database j's
+// flags (1 decreasing row_ptr, 2 item id >= m, 4 NULL col_idx, 8 row_ptr[0] != 0).
+void launch_build_multi(PackJob* jobs, uint32_t njobs, const uint64_t* blk_start, uint64_t total_blk,
+                        uint32_t* err, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
 

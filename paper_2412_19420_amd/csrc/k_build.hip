@@ -79,15 +79,21 @@ constexpr int PK_LD = PK_KR + 1;          // padded LDS row (conflict-free OR)
 constexpr int PK_ECAP = 20480;            // staged elements per chunk (80 KB)
 constexpr int PK_UNROLL = 8;
 
-__global__ __launch_bounds__(kThreads) void k_pack_tiled(
-    const uint64_t* __restrict__ rp, const uint32_t* __restrict__ ci, uint64_t n, uint64_t nnz,
-    uint32_t m, unsigned long long* __restrict__ B, uint64_t Wp, uint32_t* __restrict__ colsum,
-    uint32_t* __restrict__ err) {
-  __shared__ unsigned long long X[PK_CW * PK_LD];
-  __shared__ uint32_t s_e[PK_ECAP];
-  __shared__ uint64_t s_rp[PK_ROWS + 1];
+struct PackSmem {
+  unsigned long long X[PK_CW * PK_LD];
+  uint32_t s_e[PK_ECAP];
+  uint64_t s_rp[PK_ROWS + 1];
+};
+
+__device__ __forceinline__ void pack_tile(PackSmem& sm, const uint64_t* __restrict__ rp,
+                                          const uint32_t* __restrict__ ci, uint64_t n, uint64_t nnz,
+                                          uint32_t m, unsigned long long* __restrict__ B, uint64_t Wp,
+                                          uint32_t* __restrict__ colsum, uint32_t* __restrict__ err,
+                                          uint64_t blk) {
+  unsigned long long* X = sm.X;
+  uint32_t* s_e = sm.s_e;
+  uint64_t* s_rp = sm.s_rp;
   const int tid = threadIdx.x;
-  const uint64_t blk = blockIdx.x;
   const uint64_t r0 = blk * PK_ROWS;
   const int nr = (int)(r0 < n ? min<uint64_t>(PK_ROWS, n - r0) : 0);
   if (nr == 0) {
@@ -183,6 +189,54 @@ __global__ __launch_bounds__(kThreads) void k_pack_tiled(
     if (e0 == e1) break;
   }
   if (bad) atomicOr(err, bad);
+}
+
+__global__ __launch_bounds__(kThreads) void k_pack_tiled(
+    const uint64_t* __restrict__ rp, const uint32_t* __restrict__ ci, uint64_t n, uint64_t nnz,
+    uint32_t m, unsigned long long* __restrict__ B, uint64_t Wp, uint32_t* __restrict__ colsum,
+    uint32_t* __restrict__ err) {
+  __shared__ PackSmem sm;
+  pack_tile(sm, rp, ci, n, nnz, m, B, Wp, colsum, err, blockIdx.x);
+}
+
+// Batched construction, part 1 -- one workgroup per database: read nnz =
+// row_ptr[n] into the job, flag row_ptr[0] != 0 (8), a NULL col_idx with
+// nnz > 0 (4) and a decreasing row_ptr (1), and zero the column sums.
+__global__ __launch_bounds__(kThreads) void k_build_multi_pre(PackJob* __restrict__ jobs,
+                                                              uint32_t* __restrict__ err) {
+  PackJob& j = jobs[blockIdx.x];
+  const uint64_t n = j.n;
+  uint32_t bad = 0;
+  if (threadIdx.x == 0) {
+    const uint64_t nnz = j.rp[n];
+    j.nnz = nnz;
+    if (j.rp[0] != 0) bad |= 8u;
+    if (nnz > 0 && j.ci == nullptr) bad |= 4u;
+  }
+  for (uint64_t i = threadIdx.x; i < n; i += kThreads)
+    if (j.rp[i + 1] < j.rp[i]) bad |= 1u;
+  for (uint32_t c = threadIdx.x; c < j.m; c += kThreads) j.colsum[c] = 0u;
+  if (bad) atomicOr(err + blockIdx.x, bad);
+}
+
+// Batched construction, part 2 -- every 512-row block of every database in one
+// grid: block b belongs to the job whose [blk_start[j], blk_start[j + 1])
+// holds it.  Jobs already flagged are skipped (the call fails as a whole).
+__global__ __launch_bounds__(kThreads) void k_pack_tiled_multi(const PackJob* __restrict__ jobs,
+                                                               uint32_t njobs,
+                                                               const uint64_t* __restrict__ blk_start,
+                                                               uint32_t* __restrict__ err) {
+  __shared__ PackSmem sm;
+  const uint64_t b = blockIdx.x;
+  uint32_t lo = 0, hi = njobs;  // blk_start[lo] <= b < blk_start[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (blk_start[mid] <= b) lo = mid; else hi = mid;
+  }
+  if (err[lo] & (4u | 8u)) return;
+  const PackJob j = jobs[lo];
+  pack_tile(sm, j.rp, j.ci, j.n, j.nnz, j.m, reinterpret_cast<unsigned long long*>(j.B), j.Wp,
+            j.colsum, err + lo, b - blk_start[lo]);
 }
 
 // Support of each single item: popcount of its column, one workgroup per column.
@@ -433,13 +487,31 @@ void launch_pack(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t* B
 bool launch_pack_tiled(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t nnz, uint32_t m,
                        uint64_t* B, uint64_t Wp, uint32_t* colsum, uint32_t* err, hipStream_t s) {
   const uint64_t windows = (m + PK_CW - 1) / PK_CW;
-  if (m == 0 || windows > 32 || Wp % PK_KR || ((uint64_t)m << PK_RBITS) >= 0xffffffffull) return false;
+  (void)windows;
+  if (!pack_tiled_ok(m, Wp)) return false;
   dim3 grid((uint32_t)(Wp / PK_KR));
   k_pack_tiled<<<grid, kThreads, 0, s>>>(rp, ci, n, nnz, m, reinterpret_cast<unsigned long long*>(B),
                                          Wp, colsum, err);
   BM_LAUNCH_CHECK();
   return true;
 }
+
+bool pack_tiled_ok(uint32_t m, uint64_t Wp) {
+  const uint64_t windows = (m + PK_CW - 1) / PK_CW;
+  return m > 0 && windows <= 32 && Wp % PK_KR == 0 && ((uint64_t)m << PK_RBITS) < 0xffffffffull;
+}
+
+void launch_build_multi(PackJob* jobs, uint32_t njobs, const uint64_t* blk_start, uint64_t total_blk,
+                        uint32_t* err, hipStream_t s) {
+  if (njobs == 0) return;
+  if (total_blk > 0x7fffffffull) fail(BM_ERR_UNSUPPORTED, "batch too large for one build");
+  k_build_multi_pre<<<njobs, kThreads, 0, s>>>(jobs, err);
+  BM_LAUNCH_CHECK();
+  k_pack_tiled_multi<<<(uint32_t)total_blk, kThreads, 0, s>>>(jobs, njobs, blk_start, err);
+  BM_LAUNCH_CHECK();
+}
+
+uint64_t pack_blocks(uint64_t Wp) { return Wp / PK_KR; }
 
 void launch_colsum(const uint64_t* B, uint64_t Wp, uint32_t m, uint32_t* colsum, hipStream_t s) {
   if (m == 0) return;

@@ -305,16 +305,39 @@ __device__ inline uint32_t bucket_of(float key) {
   return (uint32_t)(kBuckets - 1 - b);
 }
 
+// Counting sort of tasks by bucket, descending predicted cost.  Per-workgroup
+// LDS counts keep global atomics to one per (workgroup, bucket): the keys of
+// many tasks fall into a handful of buckets.
 __global__ void k_bucket_hist(const float* __restrict__ key, uint32_t n, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kBuckets];
+  for (int b = threadIdx.x; b < kBuckets; b += blockDim.x) h[b] = 0;
+  __syncthreads();
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
-    atomicAdd(&hist[bucket_of(key[t])], 1u);
+    atomicAdd(&h[bucket_of(key[t])], 1u);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kBuckets; b += blockDim.x)
+    if (h[b]) atomicAdd(&hist[b], h[b]);
 }
 
-__global__ void k_bucket_scatter(const float* __restrict__ key, uint32_t n,
+// Each workgroup takes a contiguous chunk: count its tasks per bucket, reserve
+// a range of each bucket with one atomic, then place the tasks.
+__global__ void k_bucket_scatter(const float* __restrict__ key, uint32_t n, uint32_t chunk,
                                  unsigned long long* __restrict__ cursor, uint32_t* __restrict__ order) {
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const unsigned long long p = atomicAdd(&cursor[bucket_of(key[t])], 1ull);
-    order[p] = t;
+  __shared__ uint32_t cnt[kBuckets];
+  __shared__ unsigned long long base[kBuckets];
+  const uint32_t c0 = blockIdx.x * chunk, c1 = min(n, c0 + chunk);
+  for (int b = threadIdx.x; b < kBuckets; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
+  for (uint32_t t = c0 + threadIdx.x; t < c1; t += blockDim.x) atomicAdd(&cnt[bucket_of(key[t])], 1u);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kBuckets; b += blockDim.x) {
+    base[b] = cnt[b] ? atomicAdd(&cursor[b], (unsigned long long)cnt[b]) : 0ull;
+    cnt[b] = 0;
+  }
+  __syncthreads();
+  for (uint32_t t = c0 + threadIdx.x; t < c1; t += blockDim.x) {
+    const uint32_t b = bucket_of(key[t]);
+    order[base[b] + atomicAdd(&cnt[b], 1u)] = t;
   }
 }
 
@@ -419,15 +442,17 @@ void launch_order_by_key(const float* key, uint32_t n, uint32_t* hist, uint64_t*
                          uint32_t* order, hipStream_t s) {
   if (n == 0) return;
   launch_fill_u32(hist, 0, kBuckets, s);
-  k_bucket_hist<<<grid_for(n, kThreads), kThreads, 0, s>>>(key, n, hist);
+  k_bucket_hist<<<grid_for(n, 4 * kThreads, 1024), kThreads, 0, s>>>(key, n, hist);
   BM_LAUNCH_CHECK();
   ScanMulti sm{};
   sm.in[0] = hist;
   sm.is64[0] = 0;
   sm.out[0] = hist_off;
   if (!scan_multi_single(sm, 1, kBuckets, s)) fail(BM_ERR_DEVICE, "bucket scan");
-  k_bucket_scatter<<<grid_for(n, kThreads), kThreads, 0, s>>>(
-      key, n, reinterpret_cast<unsigned long long*>(hist_off), order);
+  const uint32_t g = grid_for(n, 4 * kThreads, 1024);
+  const uint32_t chunk = (n + g - 1) / g;
+  k_bucket_scatter<<<g, kThreads, 0, s>>>(key, n, chunk,
+                                          reinterpret_cast<unsigned long long*>(hist_off), order);
   BM_LAUNCH_CHECK();
 }
 

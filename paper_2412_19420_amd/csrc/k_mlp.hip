@@ -53,34 +53,67 @@ __device__ inline float forward_row(const float* w, const float* x, float* h1, f
   return out;
 }
 
+// Inference on blocks of MLP_R rows: four threads per row, each computing 16
+// hidden units of both layers from activations staged in LDS (no per-thread
+// arrays, so nothing spills), then a 4-lane sum of the output layer.
 __global__ __launch_bounds__(kThreads) void k_mlp_forward(const float* __restrict__ X, uint64_t rows,
                                                           const uint16_t* __restrict__ wbf,
                                                           const float* __restrict__ norm,
                                                           float* __restrict__ out) {
+  static_assert(kThreads == 4 * MLP_R, "four threads per row");
   __shared__ float w[MLP_PARAMS];
   __shared__ float nm[2 * MLP_IN];
+  __shared__ float sX[MLP_R][MLP_IN + 1];
+  __shared__ float sH1[MLP_R][MLP_H + 1];
   load_weights(wbf, w);
   if (threadIdx.x < 2 * MLP_IN) nm[threadIdx.x] = norm[threadIdx.x];
-  __syncthreads();
-  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < rows;
-       r += (uint64_t)gridDim.x * blockDim.x) {
-    float x[MLP_IN], h1[MLP_H];
+  const int r = threadIdx.x >> 2, part = threadIdx.x & 3, c0 = part * 16;
+  for (uint64_t b0 = (uint64_t)blockIdx.x * MLP_R; b0 < rows; b0 += (uint64_t)gridDim.x * MLP_R) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < MLP_R * MLP_IN; e += kThreads) {
+      const int rr = e / MLP_IN, i = e % MLP_IN;
+      const uint64_t g = b0 + rr;
+      sX[rr][i] = g < rows ? (X[g * MLP_IN + i] - nm[i]) * nm[MLP_IN + i] : 0.f;
+    }
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < MLP_IN; ++i) x[i] = (X[r * MLP_IN + i] - nm[i]) * nm[MLP_IN + i];
-    out[r] = forward_row(w, x, h1, nullptr);
+    for (int j = 0; j < 16; ++j) {
+      float a = w[MLP_B1 + c0 + j];
+#pragma unroll
+      for (int i = 0; i < MLP_IN; ++i) a = fmaf(sX[r][i], w[MLP_W1 + i * MLP_H + c0 + j], a);
+      sH1[r][c0 + j] = fmaxf(a, 0.f);
+    }
+    __syncthreads();
+    float acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = w[MLP_B2 + c0 + j];
+    for (int i = 0; i < MLP_H; ++i) {
+      const float h = sH1[r][i];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j] = fmaf(h, w[MLP_W2 + i * MLP_H + c0 + j], acc[j]);
+    }
+    float o = 0.f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) o = fmaf(fmaxf(acc[j], 0.f), w[MLP_W3 + c0 + j], o);
+    o += __shfl_xor(o, 1);
+    o += __shfl_xor(o, 2);
+    const uint64_t g = b0 + r;
+    if (part == 0 && g < rows) out[g] = o + w[MLP_B3];
   }
 }
 
-// Gradient of sum_r (out_r - y_r)^2 * scale over a block of MLP_R rows:
-// per-row backpropagation by one wavefront, then the parameter sums over the
-// block's rows by all threads, added atomically into grad.
+// Gradient of scale * sum_r (out_r - y_r)^2 over rows [r0, r1): each workgroup
+// takes chunks of MLP_R rows (per-row backpropagation by one wavefront, then
+// the parameter sums over the chunk by all threads) and accumulates into its
+// own slot partial[blockIdx.x][0..MLP_PARAMS] (the last entry is the loss);
+// every slot entry has one owning thread, so there are no atomics and the
+// result does not depend on scheduling.
 __global__ __launch_bounds__(kThreads) void k_mlp_grad(const float* __restrict__ X,
                                                        const float* __restrict__ Y, uint64_t r0,
                                                        uint64_t r1, float scale,
                                                        const uint16_t* __restrict__ wbf,
                                                        const float* __restrict__ norm,
-                                                       float* __restrict__ grad,
-                                                       float* __restrict__ loss) {
+                                                       float* __restrict__ partial) {
   __shared__ float w[MLP_PARAMS];
   __shared__ float nm[2 * MLP_IN];
   __shared__ float sX[MLP_R][MLP_IN];
@@ -90,8 +123,10 @@ __global__ __launch_bounds__(kThreads) void k_mlp_grad(const float* __restrict__
   __shared__ float sD1[MLP_R][MLP_H + 1];  // padded: conflict-free per-row access
   __shared__ float sDo[MLP_R];
   __shared__ float sL[MLP_R];
+  float* slot = partial + (uint64_t)blockIdx.x * (MLP_PARAMS + 1);
   load_weights(wbf, w);
   if (threadIdx.x < 2 * MLP_IN) nm[threadIdx.x] = norm[threadIdx.x];
+  for (int p = threadIdx.x; p <= MLP_PARAMS; p += blockDim.x) slot[p] = 0.f;
   __syncthreads();
   for (uint64_t b0 = r0 + (uint64_t)blockIdx.x * MLP_R; b0 < r1; b0 += (uint64_t)gridDim.x * MLP_R) {
     const int nr = (int)min<uint64_t>(MLP_R, r1 - b0);
@@ -156,14 +191,37 @@ __global__ __launch_bounds__(kThreads) void k_mlp_grad(const float* __restrict__
       } else {  // b3
         for (int r = 0; r < MLP_R; ++r) g += sDo[r];
       }
-      if (g != 0.f) atomicAdd(&grad[p], g);
+      slot[p] += g;
     }
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == (MLP_PARAMS % kThreads)) {  // the owner of slot[MLP_PARAMS]
       float l = 0.f;
       for (int r = 0; r < MLP_R; ++r) l += sL[r];
-      atomicAdd(loss, l);
+      slot[MLP_PARAMS] += l;
     }
     __syncthreads();
+  }
+}
+
+// grad[p] = sum over workgroup slots in slot order; *loss += the summed loss.
+__global__ void k_mlp_reduce(const float* __restrict__ partial, uint32_t nslots,
+                             float* __restrict__ grad, float* __restrict__ loss) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p <= MLP_PARAMS; p += gridDim.x * blockDim.x) {
+    float g = 0.f;
+    for (uint32_t b = 0; b < nslots; ++b) g += partial[(uint64_t)b * (MLP_PARAMS + 1) + p];
+    if (p < MLP_PARAMS) grad[p] = g;
+    else *loss += g;
+  }
+}
+
+// Per-epoch bookkeeping on the device (so an epoch can be replayed as a graph):
+// losses[*epoch] = *acc / batches, then the epoch and Adam step counters advance.
+__global__ void k_mlp_epoch_end(float* __restrict__ acc, float* __restrict__ losses,
+                                uint32_t* __restrict__ ctr, uint32_t batches) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    losses[ctr[0]] = *acc / (float)batches;
+    ctr[0] += 1;
+    ctr[1] += batches;
+    *acc = 0.f;
   }
 }
 
@@ -175,9 +233,14 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
 }
 
 // Adam on the FP32 master copy, then the BF16 weights are rounded from it.
+// The step number is *step_base + step_add (a device counter, so replays of a
+// captured epoch use the right bias corrections).
 __global__ void k_mlp_adam(float* __restrict__ master, float* __restrict__ m, float* __restrict__ v,
                            const float* __restrict__ grad, uint16_t* __restrict__ wbf, float lr,
-                           float b1, float b2, float eps, float c1, float c2) {
+                           float b1, float b2, float eps, const uint32_t* __restrict__ step_base,
+                           uint32_t step_add) {
+  const float t = (float)(*step_base + step_add);
+  const float c1 = 1.f - powf(b1, t), c2 = 1.f - powf(b2, t);
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < MLP_PARAMS; p += gridDim.x * blockDim.x) {
     const float g = grad[p];
     const float mm = b1 * m[p] + (1.f - b1) * g;
@@ -200,24 +263,32 @@ __global__ void k_mlp_round(const float* __restrict__ master, uint16_t* __restri
 void launch_mlp_forward(const float* X, uint64_t rows, const uint16_t* wbf, const float* norm,
                         float* out, hipStream_t s) {
   if (rows == 0) return;
-  k_mlp_forward<<<grid_for(rows, kThreads, 4096), kThreads, 0, s>>>(X, rows, wbf, norm, out);
+  k_mlp_forward<<<grid_for(rows, MLP_R, 2048), kThreads, 0, s>>>(X, rows, wbf, norm, out);
   BM_LAUNCH_CHECK();
 }
 
+uint32_t mlp_grad_slots(uint64_t rows) { return grid_for(rows, MLP_R, 1024); }
+
 void launch_mlp_grad(const float* X, const float* Y, uint64_t r0, uint64_t r1, float scale,
-                     const uint16_t* wbf, const float* norm, float* grad, float* loss, hipStream_t s) {
+                     const uint16_t* wbf, const float* norm, float* partial, float* grad, float* loss,
+                     hipStream_t s) {
   if (r1 <= r0) return;
-  k_mlp_grad<<<grid_for(r1 - r0, MLP_R, 1024), kThreads, 0, s>>>(X, Y, r0, r1, scale, wbf, norm,
-                                                                  grad, loss);
+  const uint32_t g = mlp_grad_slots(r1 - r0);
+  k_mlp_grad<<<g, kThreads, 0, s>>>(X, Y, r0, r1, scale, wbf, norm, partial);
+  BM_LAUNCH_CHECK();
+  k_mlp_reduce<<<grid_for(MLP_PARAMS + 1, kThreads), kThreads, 0, s>>>(partial, g, grad, loss);
   BM_LAUNCH_CHECK();
 }
 
 void launch_mlp_adam(float* master, float* m, float* v, const float* grad, uint16_t* wbf, float lr,
-                     uint64_t step, hipStream_t s) {
-  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
-  k_mlp_adam<<<grid_for(MLP_PARAMS, kThreads), kThreads, 0, s>>>(master, m, v, grad, wbf, lr, b1, b2,
-                                                                  eps, c1, c2);
+                     const uint32_t* step_base, uint32_t step_add, hipStream_t s) {
+  k_mlp_adam<<<grid_for(MLP_PARAMS, kThreads), kThreads, 0, s>>>(master, m, v, grad, wbf, lr, 0.9f,
+                                                                  0.999f, 1e-8f, step_base, step_add);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_mlp_epoch_end(float* acc, float* losses, uint32_t* ctr, uint32_t batches, hipStream_t s) {
+  k_mlp_epoch_end<<<1, 64, 0, s>>>(acc, losses, ctr, batches);
   BM_LAUNCH_CHECK();
 }
 

@@ -341,6 +341,100 @@ bm_db* build_db(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n, ui
   return db.release();
 }
 
+// Batched construction: every database whose item count the tiled kernel
+// handles is validated and packed by two launches for the whole batch, with
+// one synchronisation; the others are built one by one.  All or nothing: on
+// any failure no handle is returned.
+std::vector<bm_db*> build_many(uint32_t count, const uint64_t* const* row_ptrs,
+                               const uint32_t* const* col_idxs, const uint64_t* ns,
+                               const uint32_t* ms, hipStream_t s) {
+  std::vector<std::unique_ptr<bm_db>> dbs(count);
+  {
+    CallScope scope(s);  // after dbs: on failure it synchronises before they are freed
+    std::vector<PackJob> jobs;
+    std::vector<uint32_t> job_db;
+    std::vector<uint64_t> blk_start(1, 0);
+    std::vector<uint32_t> single;
+    for (uint32_t d = 0; d < count; ++d) {
+      const uint64_t n = ns[d];
+      const uint32_t m = ms[d];
+      if (!row_ptrs[d]) fail(BM_ERR_INVALID_ARG, "database %u: row_ptr is NULL", d);
+      if (n >= (1ull << 31))
+        fail(BM_ERR_UNSUPPORTED, "database %u: n_tx = %llu >= 2^31", d, (unsigned long long)n);
+      const uint64_t Wp = padded_words(n);
+      if ((double)m * (double)Wp * 8.0 > 1.0e15)
+        fail(BM_ERR_UNSUPPORTED, "database %u: bitset matrix too large", d);
+      if (!pack_tiled_ok(m, Wp)) {
+        single.push_back(d);
+        continue;
+      }
+      auto db = std::make_unique<bm_db>();
+      BM_HIP(hipGetDevice(&db->device));
+      db->n = n;
+      db->m = m;
+      db->W = (n + 63) / 64;
+      db->Wp = Wp;
+      PackJob jb{};
+      jb.rp = row_ptrs[d];
+      jb.ci = col_idxs ? col_idxs[d] : nullptr;
+      if (!is_device_ptr(jb.rp)) {
+        const uint64_t nnz = row_ptrs[d][n];
+        TBuf<uint64_t> rp(n + 1, s);
+        BM_HIP(hipMemcpyAsync(rp.get(), row_ptrs[d], (n + 1) * 8, hipMemcpyHostToDevice, s));
+        jb.rp = rp.get();
+        if (nnz > 0 && jb.ci && !is_device_ptr(jb.ci)) {
+          TBuf<uint32_t> ci(nnz, s);
+          BM_HIP(hipMemcpyAsync(ci.get(), col_idxs[d], nnz * 4, hipMemcpyHostToDevice, s));
+          jb.ci = ci.get();
+        }
+      } else if (jb.ci && !is_device_ptr(jb.ci)) {
+        fail(BM_ERR_INVALID_ARG, "database %u: row_ptr on the device but col_idx on the host", d);
+      }
+      db->B.reset((size_t)m * Wp, s);
+      db->colsum.reset(m, s);
+      jb.n = n;
+      jb.m = m;
+      jb.B = db->B.get();
+      jb.Wp = Wp;
+      jb.colsum = db->colsum.get();
+      jobs.push_back(jb);
+      job_db.push_back(d);
+      blk_start.push_back(blk_start.back() + pack_blocks(Wp));
+      dbs[d] = std::move(db);
+    }
+    const uint32_t nj = (uint32_t)jobs.size();
+    if (nj) {
+      TBuf<PackJob> djobs(nj, s);
+      TBuf<uint64_t> dstart(nj + 1, s);
+      TBuf<uint32_t> derr(nj, s);
+      upload(djobs.get(), jobs, s);
+      upload(dstart.get(), blk_start, s);
+      launch_fill_u32(derr.get(), 0, nj, s);
+      launch_build_multi(djobs.get(), nj, dstart.get(), blk_start.back(), derr.get(), s);
+      std::vector<uint32_t> herr(nj);
+      BM_HIP(hipMemcpyAsync(herr.data(), derr.get(), nj * 4, hipMemcpyDeviceToHost, s));
+      BM_HIP(hipStreamSynchronize(s));
+      for (uint32_t j = 0; j < nj; ++j) {
+        const uint32_t e = herr[j], d = job_db[j];
+        if (e & 8u) fail(BM_ERR_CSR, "database %u: row_ptr[0] is not 0", d);
+        if (e & 4u) fail(BM_ERR_INVALID_ARG, "database %u: col_idx is NULL but row_ptr[n] > 0", d);
+        if (e & 1u) fail(BM_ERR_CSR, "database %u: row_ptr is not non-decreasing", d);
+        if (e & 2u) fail(BM_ERR_CSR, "database %u: an item id is >= n_items (%u)", d, ms[d]);
+      }
+    }
+    for (uint32_t d : single) {
+      try {
+        dbs[d].reset(build_db(row_ptrs[d], col_idxs ? col_idxs[d] : nullptr, ns[d], ms[d], s));
+      } catch (const Error& e) {
+        fail(e.status, "database %u: %s", d, e.msg.c_str());
+      }
+    }
+  }
+  std::vector<bm_db*> out(count);
+  for (uint32_t d = 0; d < count; ++d) out[d] = dbs[d].release();
+  return out;
+}
+
 // ------------------------------------------------------------------ pairs
 
 void pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* out,
@@ -753,12 +847,14 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
                         Kls >= 2 ? L[1].cstart.get() : nullptr, ls_first[1].get(),
                         ls_count[1].get(), FL[1].item.get(), FL[1].parent.get(), FL[1].supp.get(),
                         FL[1].db.get(), skind[1].get(), sfirst[1].get(), scount[1].get(), s);
+      // every level-synchronous node and every arena node is final, so the
+      // final level sizes are known without reading anything back
       for (uint32_t k = 1;; ++k) {
         const uint64_t nk = FL[k].n;
         FL[k].cstart.alloc(nk + 1, s);
         scan32(scount[k].get(), FL[k].cstart.get(), nk, s);
-        const uint64_t nn = read_back(FL[k].cstart.get() + nk, s);
-        st.host_syncs++;
+        const uint64_t nn = (k + 1 <= Kls ? L[k + 1].n : 0) +
+                            (k + 1 <= BM_MAX_LEVELS ? (uint64_t)hstat[BM_MAX_LEVELS + 1 + k + 1] : 0);
         if (nn == 0) break;
         if (k + 1 > BM_MAX_LEVELS)
           fail(BM_ERR_UNSUPPORTED, "frequent itemsets longer than %d items", BM_MAX_LEVELS);

@@ -112,34 +112,75 @@ void model_set_norm_from(bm_model* m, const float* feats, uint64_t rows, hipStre
   upload_norm(m, s);
 }
 
-float model_train(bm_model* m, const float* feats, const float* labels, uint64_t rows,
-                  uint32_t epochs, float lr, uint32_t batch, hipStream_t s) {
-  if (rows == 0) return 0.f;
-  if (!m->has_norm) model_set_norm_from(m, feats, rows, s);
-  DevData X = as_device(feats, rows * MLP_IN, s);
-  DevData Y = as_device(labels, rows, s);
-  DBuf<float> loss(1, s);
+std::vector<float> model_train(bm_model* m, const float* feats, const float* labels, uint64_t rows,
+                               uint32_t epochs, float lr, uint32_t batch, bool graph,
+                               hipStream_t caller) {
+  if (rows == 0 || epochs == 0) return {};
+  if (!m->has_norm) model_set_norm_from(m, feats, rows, caller);
   if (batch == 0) batch = 256;
-  float last = 0.f;
-  for (uint32_t e = 0; e < epochs; ++e) {
-    launch_fill_u32(reinterpret_cast<uint32_t*>(loss.get()), 0, 1, s);
-    for (uint64_t r0 = 0; r0 < rows; r0 += batch) {
-      const uint64_t r1 = std::min<uint64_t>(rows, r0 + batch);
-      launch_fill_u32(reinterpret_cast<uint32_t*>(m->grad.get()), 0, MLP_PARAMS, s);
-      launch_mlp_grad(X.p, Y.p, r0, r1, 1.f / (float)(r1 - r0), m->wbf.get(), m->norm.get(),
-                      m->grad.get(), loss.get(), s);
-      m->step += 1;
-      launch_mlp_adam(m->master.get(), m->m.get(), m->v.get(), m->grad.get(), m->wbf.get(), lr,
-                      m->step, s);
+  // training runs on a private stream (a graph cannot be captured on the null
+  // stream), ordered after the caller's stream
+  hipStream_t ts = nullptr;
+  hipEvent_t ev = nullptr;
+  BM_HIP(hipStreamCreateWithFlags(&ts, hipStreamNonBlocking));
+  struct Cleanup {
+    hipStream_t s;
+    hipEvent_t e;
+    ~Cleanup() {
+      if (e) (void)hipEventDestroy(e);
+      if (s) (void)hipStreamDestroy(s);
     }
-    float l = 0.f;
-    BM_HIP(hipMemcpyAsync(&l, loss.get(), 4, hipMemcpyDeviceToHost, s));
-    BM_HIP(hipStreamSynchronize(s));
-    // sum over batches of each batch's mean squared error -> mean per batch
-    last = l / (float)((rows + batch - 1) / batch);
+  } cleanup{ts, nullptr};
+  BM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  cleanup.e = ev;
+  BM_HIP(hipEventRecord(ev, caller));
+  BM_HIP(hipStreamWaitEvent(ts, ev, 0));
+  DevData X = as_device(feats, rows * MLP_IN, ts);
+  DevData Y = as_device(labels, rows, ts);
+  const uint32_t nb = (uint32_t)((rows + batch - 1) / batch);
+  DBuf<float> partial((uint64_t)mlp_grad_slots(std::min<uint64_t>(batch, rows)) * (MLP_PARAMS + 1), ts);
+  DBuf<float> acc(1, ts), losses(epochs, ts);
+  DBuf<uint32_t> ctr(2, ts);  // [0] epoch, [1] Adam steps taken before this epoch
+  launch_fill_u32(reinterpret_cast<uint32_t*>(acc.get()), 0, 1, ts);
+  launch_fill_u32(ctr.get(), 0, 1, ts);
+  launch_fill_u32(ctr.get() + 1, (uint32_t)m->step, 1, ts);
+  auto epoch = [&] {
+    for (uint32_t b = 0; b < nb; ++b) {
+      const uint64_t r0 = (uint64_t)b * batch, r1 = std::min<uint64_t>(rows, r0 + batch);
+      launch_mlp_grad(X.p, Y.p, r0, r1, 1.f / (float)(r1 - r0), m->wbf.get(), m->norm.get(),
+                      partial.get(), m->grad.get(), acc.get(), ts);
+      launch_mlp_adam(m->master.get(), m->m.get(), m->v.get(), m->grad.get(), m->wbf.get(), lr,
+                      ctr.get() + 1, b + 1, ts);
+    }
+    launch_mlp_epoch_end(acc.get(), losses.get(), ctr.get(), nb, ts);
+  };
+  if (graph && epochs > 1) {
+    // one epoch is 2 * batches + 1 small launches: capture it once, replay it
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    BM_HIP(hipStreamBeginCapture(ts, hipStreamCaptureModeThreadLocal));
+    try {
+      epoch();
+    } catch (...) {
+      (void)hipStreamEndCapture(ts, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    BM_HIP(hipStreamEndCapture(ts, &g));
+    hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    BM_HIP(e);
+    for (uint32_t i = 0; i < epochs && e == hipSuccess; ++i) e = hipGraphLaunch(ge, ts);
+    (void)hipGraphExecDestroy(ge);
+    BM_HIP(e);
+  } else {
+    for (uint32_t i = 0; i < epochs; ++i) epoch();
   }
-  BM_HIP(hipStreamSynchronize(s));
-  return last;
+  std::vector<float> out(epochs);
+  BM_HIP(hipMemcpyAsync(out.data(), losses.get(), epochs * 4, hipMemcpyDeviceToHost, ts));
+  BM_HIP(hipStreamSynchronize(ts));
+  m->step += (uint64_t)nb * epochs;
+  return out;
 }
 
 void model_predict(const bm_model* m, const float* feats, uint64_t rows, float* out,
@@ -167,9 +208,14 @@ float model_grad(bm_model* m, const float* feats, const float* labels, uint64_t 
   DevData Y = as_device(labels, rows, s);
   DBuf<float> loss(1, s);
   launch_fill_u32(reinterpret_cast<uint32_t*>(loss.get()), 0, 1, s);
-  launch_fill_u32(reinterpret_cast<uint32_t*>(m->grad.get()), 0, MLP_PARAMS, s);
-  if (rows) launch_mlp_grad(X.p, Y.p, 0, rows, 1.f / (float)rows, m->wbf.get(), m->norm.get(),
-                            m->grad.get(), loss.get(), s);
+  if (rows) {
+    DBuf<float> partial((uint64_t)mlp_grad_slots(rows) * (MLP_PARAMS + 1), s);
+    launch_mlp_grad(X.p, Y.p, 0, rows, 1.f / (float)rows, m->wbf.get(), m->norm.get(), partial.get(),
+                    m->grad.get(), loss.get(), s);
+    BM_HIP(hipStreamSynchronize(s));
+  } else {
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->grad.get()), 0, MLP_PARAMS, s);
+  }
   float l = 0.f;
   BM_HIP(hipMemcpyAsync(&l, loss.get(), 4, hipMemcpyDeviceToHost, s));
   if (grad_out)

@@ -314,3 +314,61 @@ def test_batch_device_tensor_copy(bm):
         want = ocpp.OracleDb(d.row_ptr, d.col_idx, d.n, d.m).mine_arrays(d.minsup)[:3]
         offs, items, supp = r.tensors("cuda")
         assert_same((offs.cpu().numpy(), items.cpu().numpy(), supp.cpu().numpy()), want)
+
+
+# ------------------------------------------------------------ batched build
+
+def _build_batch_inputs():
+    dbs = [gen.random_small(s, 200 + 97 * s, 40 + 13 * s, density=0.15, dup_rate=0.2, shuffle=True,
+                            empty_rate=0.1) for s in range(6)]
+    dbs.append(gen.from_rows([], 5))                       # no transactions
+    dbs.append(gen.from_rows([[0, 1], [1]], 2))            # tiny
+    dbs.append(gen.from_rows([[3], [], [7]], 20_000))      # too many items for the tiled kernel
+    dbs.append(gen.make_config(2, scale=0.3))
+    dbs.append(gen.random_small(99, 70_001, 64, density=0.05))  # ragged last block
+    return dbs
+
+
+def test_build_batch_matches_single_builds(bm):
+    import torch
+    dbs = _build_batch_inputs()
+    print(f"build batch of {len(dbs)}", flush=True)
+    items = []
+    for i, d in enumerate(dbs):
+        if i % 2:  # alternate host arrays and device tensors
+            rp = torch.from_numpy(d.row_ptr.astype(np.uint64)).cuda()
+            ci = torch.from_numpy(d.col_idx.astype(np.uint32)).cuda() if d.col_idx.size else None
+            items.append((rp, ci, d.n, d.m))
+        else:
+            items.append((d.row_ptr, d.col_idx, d.n, d.m))
+    hs = bm.bm_build_batch(items)
+    for d, h in zip(dbs, hs):
+        assert h.info()[:2] == (d.n, d.m)
+        want = pairs.column_sums(d.row_ptr, d.col_idx, d.n, d.m)
+        assert np.array_equal(bm.bm_item_support(h).astype(np.int64), want)
+    ms = [max(1, d.n // 20) for d in dbs]
+    got = bm.bm_mine_batch(hs, ms)
+    for d, m, r in zip(dbs, ms, got):
+        h1 = bm.bm_build(d.row_ptr, d.col_idx, d.n, d.m)
+        assert_same(r.arrays(), bm.bm_mine(h1, m).arrays())
+
+
+@pytest.mark.parametrize("case", ["bad_item", "decreasing", "nonzero_start"])
+def test_build_batch_errors_name_the_database(bm, case):
+    good = gen.random_small(1, 100, 10, density=0.3)
+    rp = good.row_ptr.copy()
+    ci = good.col_idx.copy()
+    if case == "bad_item":
+        ci[len(ci) // 2] = 10
+    elif case == "decreasing":
+        rp[50] = rp[52] + 1
+    else:  # every row shifted by one element: row_ptr[0] = 1, row_ptr[n] = len(col_idx)
+        rp = rp + 1
+        ci = np.concatenate([[0], ci]).astype(np.uint32)
+    items = [(good.row_ptr, good.col_idx, good.n, good.m), (rp, ci, good.n, good.m)]
+    with pytest.raises(bm.BmError, match="database 1"):
+        bm.bm_build_batch(items)
+    # the good database still builds on its own afterwards
+    h = bm.bm_build_batch(items[:1])[0]
+    assert np.array_equal(bm.bm_item_support(h).astype(np.int64),
+                          pairs.column_sums(good.row_ptr, good.col_idx, good.n, good.m))

@@ -248,3 +248,45 @@ def test_depth_first_forced_on_full_size(bm, k):
     r = bm.bm_mine_ex(h, db.minsup, bm.options(dfs_threads=1024, dfs_max_words=0xFFFFFFFF))
     assert r.stats()["dfs_tasks"] > 0
     assert _arrays_equal(r.arrays(), base.arrays())
+
+
+def test_training_is_deterministic_and_graph_replay_matches_eager(bm):
+    # every replayed epoch of the captured graph must give what the host-issued
+    # launches give: per-epoch losses and final parameters are compared exactly
+    # (the gradient has a fixed summation order, so training is deterministic)
+    print("graph vs eager training", flush=True)
+    X, _ = _model_data(9, 1500)
+    Y = (0.5 * X[:, 0] + X[:, 2] - 0.2 * X[:, 3]).astype(np.float32)
+    a, b, c = bm.Model(seed=2), bm.Model(seed=2), bm.Model(seed=2)
+    la = a.train(X, Y, epochs=6, lr=2e-3, batch=200, graph=False, all_losses=True)
+    lb = b.train(X, Y, epochs=6, lr=2e-3, batch=200, graph=True, all_losses=True)
+    lc = c.train(X, Y, epochs=6, lr=2e-3, batch=200, graph=True, all_losses=True)
+    assert np.all(np.isfinite(la)) and la[-1] < la[0]
+    assert np.array_equal(la, lb) and np.array_equal(lb, lc)
+    for x, y in zip(a.params(), b.params()):
+        assert np.array_equal(x, y)
+    # a second call continues the Adam step count in both modes
+    la2 = a.train(X, Y, epochs=3, lr=2e-3, batch=200, graph=True, all_losses=True)
+    lb2 = b.train(X, Y, epochs=3, lr=2e-3, batch=200, graph=False, all_losses=True)
+    assert np.array_equal(la2, lb2)
+    for x, y in zip(a.params(), b.params()):
+        assert np.array_equal(x, y)
+
+
+def test_autotune_picks_options_with_identical_output(bm, tmp_path):
+    print("autotune", flush=True)
+    dbs = [gen.batch_db(k, scale=0.05) for k in range(5)]
+    hs = [bm.bm_build(d.row_ptr, d.col_idx, d.n, d.m) for d in dbs]
+    ms = [d.minsup for d in dbs]
+    best, best_ms = bm.bm_autotune(hs, ms, reps=1)
+    assert best_ms > 0
+    assert best.dfs_threads in (0, 256, 512, 1024)
+    ref = bm.bm_mine_batch(hs, ms)
+    got = bm.bm_mine_batch(hs, ms, opts=best)
+    for a, b in zip(ref, got):
+        assert _arrays_equal(a.arrays(), b.arrays())
+    path = str(tmp_path / "tune.json")
+    o1, ms1, hit1 = bm.autotune_cached(hs, ms, path, reps=1)
+    o2, ms2, hit2 = bm.autotune_cached(hs, ms, path, reps=1)
+    assert not hit1 and hit2 and ms1 == ms2
+    assert bm.options_to_dict(o1) == bm.options_to_dict(o2)
