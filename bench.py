@@ -27,7 +27,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-INT8_PEAK_TOPS = 5000.0
+# dense MFMA peaks of MI355X by operand type (TOP/s)
+MFMA_PEAK_TOPS = {"int8": 5000.0, "fp4": 10100.0}
+# contractions priced against the MFMA peak of their operand type: algorithmic
+# ops = 2 n per candidate pair (one AND, one add per transaction)
+MFMA_KERNELS = {
+    "gram_mfma": "k_gram_mfma (MFMA Gram of a prefix class, 128x128 tiles)",
+    "gram_mfma_big": "k_gram_mfma_big (MFMA Gram of a prefix class, 256x256 tiles)",
+}
 # streaming kernels priced against HBM: algorithmic bytes = column words read
 HBM_KERNELS = {
     "andpop": "k_andpop (AND+popcount of a prefix class, LDS-blocked)",
@@ -45,18 +52,22 @@ WORKLOADS = {
 }
 
 
-def cpu_baseline(db, budget_s: float = 12.0) -> dict:
+def cpu_baseline(db, target_s: float = 12.0) -> dict:
     """The C++ oracle as it stands, on a bounded sample of the same workload:
     the subtrees of the first k frequent items (all itemsets whose smallest
-    item is one of them), k grown until the run takes about `budget_s`."""
+    item is one of them), k grown until one run takes about `target_s`
+    (at least 10 s of CPU work unless the whole workload finishes sooner)."""
     from oracle import cpp as ocpp
     threads = max(1, min(16, os.cpu_count() or 1))
     o = ocpp.OracleDb(db.row_ptr, db.col_idx, db.n, db.m)
     m1 = len(o.frequent_items(db.minsup))
-    k = max(1, threads)
+    k = max(1, min(m1, threads))
     dt, cands, sets_ = o.time_sample(db.minsup, 0, k, threads)
-    while dt < budget_s / 4 and k < m1:
-        k = min(m1, k * 2 if dt < budget_s / 8 else int(k * budget_s / max(dt, 1e-3) / 2) + 1)
+    for _ in range(8):
+        if dt >= 10.0 or k >= m1:
+            break
+        # subtree costs fall with the item index, so extrapolate generously
+        k = min(m1, max(k + 1, int(k * target_s / max(dt, 1e-3))))
         dt, cands, sets_ = o.time_sample(db.minsup, 0, k, threads)
     return {
         "value": cands / dt if dt > 0 else None,
@@ -82,7 +93,7 @@ def _kernel_table(stats, steps):
         op = sum(s["kernel_ops"][k] for s in stats) / launches[k]
         kernels[k] = {"ms_per_step": round(ms[k] / steps, 4), "launches_per_step":
                       launches[k] / steps, "avg_launch_ms": round(per, 4)}
-        if k == "gram_mfma":
+        if k in MFMA_KERNELS:
             kernels[k]["achieved_TOPs"] = round(op / (per * 1e-3) / 1e12, 2)
             kernels[k]["algorithmic_ops_per_launch"] = op
         if k in HBM_KERNELS:
@@ -91,18 +102,51 @@ def _kernel_table(stats, steps):
     return kernels, ms
 
 
-def _roofline(kernels, ms):
-    dom = max((k for k in kernels if k == "gram_mfma" or k in HBM_KERNELS), key=lambda k: ms[k],
+DTYPE = {"fp4": "u64 bitsets; fp4 (e2m1) MFMA, fp32 accumulate (exact: counts < 2^24 per task)",
+         "int8": "u64 bitsets; int8 MFMA, int32 accumulate"}
+
+# HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by
+# the copy calibration), valid only while the kernel's source is unchanged:
+# (workload, kernel, form) -> (sha256 of the source file, bytes per launch).
+TRAFFIC = {
+    # dense_planted 1M x 4,096 (profiles/dense_planted_1M_hbm_traffic.md)
+    (3, "gram_mfma", "fp4"): ("96571be43009de1e941f529bf1c1bbb87c0a8e30e5bef7b1bf0b3cedb988c2fd", 2812.7e6),
+    (3, "andpop_reg", "fp4"): ("c0555966d5ffedb8a7bc270f39fe9960f402066224424f67f9902b659f1d0f46", 543.0e6),
+    (3, "andpop", "fp4"): ("c0555966d5ffedb8a7bc270f39fe9960f402066224424f67f9902b659f1d0f46", 112.7e6),
+}
+KERNEL_SOURCE = {
+    "gram_mfma": "k_gram_mfma.hip", "gram_mfma_big": "k_gram_mfma.hip",
+    "andpop": "k_andpop.hip", "andpop_reg": "k_andpop.hip", "dfs": "k_dfs.hip",
+}
+WORKLOAD = None
+
+
+def traffic_of(kernel: str, form: str):
+    rec = TRAFFIC.get((WORKLOAD, kernel, form))
+    src = KERNEL_SOURCE.get(kernel)
+    if rec is None or src is None:
+        return None
+    import hashlib
+    path = os.path.join(ROOT, "paper_2412_19420_amd", "csrc", src)
+    with open(path, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec[0]:
+            return None
+    return rec[1]
+
+
+def _roofline(kernels, ms, form):
+    dom = max((k for k in kernels if k in MFMA_KERNELS or k in HBM_KERNELS), key=lambda k: ms[k],
               default=None)
-    if dom == "gram_mfma":
+    if dom in MFMA_KERNELS:
         a = kernels[dom]["achieved_TOPs"]
-        return {"bound": "mfma", "kernel": "k_gram_mfma (int8 MFMA Gram of a prefix class)",
-                "achieved": a, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
-                "frac": round(a / INT8_PEAK_TOPS, 4), "traffic": None}
+        peak = MFMA_PEAK_TOPS[form]
+        return {"bound": "mfma", "kernel": f"{MFMA_KERNELS[dom]}, {form} operands",
+                "achieved": a, "peak": peak, "unit": "TOP/s",
+                "frac": round(a / peak, 4), "traffic": traffic_of(dom, form)}
     if dom is not None:
         a = kernels[dom]["achieved_GBs"]
         return {"bound": "hbm", "kernel": HBM_KERNELS[dom], "achieved": a, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(a / HBM_PEAK_GBS, 4), "traffic": None}
+                "unit": "GB/s", "frac": round(a / HBM_PEAK_GBS, 4), "traffic": traffic_of(dom, form)}
     return None
 
 
@@ -205,7 +249,7 @@ def run_batched(args, bm, torch, dev):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": best["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u64 bitsets; int8 MFMA, int32 accumulate",
+        "dtype": DTYPE[st["mfma_form"]],
         "data": "synthetic (seeded generator, see DESIGN.md)",
         "config": {"workload": WORKLOADS[4], "databases": len(dbs), "candidates": best["candidates"],
                    "dfs_tasks": st["dfs_tasks"], "host_syncs": st["host_syncs"],
@@ -216,7 +260,7 @@ def run_batched(args, bm, torch, dev):
                    "learned_vs_batched_depth_first": round(res["batched_depth_first"]["mine_ms"] /
                                                            best["mine_ms"], 3),
                    "kernels": kernels},
-        "roofline": _roofline(kernels, kms) if kernels else None,
+        "roofline": _roofline(kernels, kms, st["mfma_form"]) if kernels else None,
     }
     print(json.dumps(out), flush=True)
 
@@ -232,6 +276,9 @@ def main():
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--mfma-min-children", type=int, default=0)
     ap.add_argument("--split-words", type=int, default=0)
+    ap.add_argument("--mfma", choices=["default", "int8", "fp4"], default="default",
+                    help="form of the Gram kernels' MFMA")
+    ap.add_argument("--mfma-big-children", type=int, default=0)
     ap.add_argument("--levelsync", action="store_true",
                     help="plain level-synchronous miner (no depth-first phase)")
     ap.add_argument("--dfs-threads", type=int, default=0)
@@ -266,6 +313,8 @@ def main():
     import gen
     import paper_2412_19420_amd as bm
 
+    global WORKLOAD
+    WORKLOAD = args.workload
     if args.workload == 4:
         run_batched(args, bm, torch, dev)
         return
@@ -282,7 +331,9 @@ def main():
         flags |= bm.FLAG_LEVELSYNC
     if args.shuffle:
         flags |= bm.FLAG_SHUFFLE
+    flags |= {"default": 0, "int8": bm.FLAG_INT8_MFMA, "fp4": bm.FLAG_FP4_MFMA}[args.mfma]
     opts = bm.options(flags=flags, mfma_min_children=args.mfma_min_children,
+                      mfma_big_children=args.mfma_big_children,
                       split_words=args.split_words, shuffle_seed=args.shuffle,
                       dfs_threads=args.dfs_threads, dfs_max_words=args.dfs_max_words)
     model = None
@@ -331,7 +382,8 @@ def main():
 
     # dominant kernel by total event time
     kernels, kms = _kernel_table(stats, args.steps)
-    roofline = _roofline(kernels, kms) if (not args.no_timing and kernels) else None
+    roofline = (_roofline(kernels, kms, st["mfma_form"]) if (not args.no_timing and kernels)
+                else None)
 
     out = {
         "metric": "candidate supports counted/s + mine wall time at minsup; % of HBM peak",
@@ -344,7 +396,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64 bitsets; int8 MFMA, int32 accumulate",
+        "dtype": DTYPE[st["mfma_form"]],
         "data": "synthetic (seeded generator, see DESIGN.md)",
         "config": {"workload": WORKLOADS[args.workload], "n_tx": db.n, "n_items": db.m,
                    "minsup": db.minsup, "frequent_itemsets": st["frequent_total"],

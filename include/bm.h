@@ -70,7 +70,8 @@ enum {
   BM_K_EMIT = 6,      /* canonical-order output (and the merge of depth-first output) */
   BM_K_DFS = 7,       /* persistent depth-first subtree kernel (small classes) */
   BM_K_SCHED = 8,     /* cost-model features, prediction and task ordering */
-  BM_K_COUNT = 9
+  BM_K_GRAM_MFMA_BIG = 9, /* as BM_K_GRAM_MFMA with 256 x 256 tiles (classes of >= 256 children) */
+  BM_K_COUNT = 10
 };
 
 /* Statistics of one mining call.  Kernel times are filled only when the call
@@ -93,6 +94,7 @@ typedef struct {
   double wall_ms;                              /* host wall time of the call */
   uint32_t host_syncs;                         /* device->host synchronisations */
   uint64_t dfs_tasks;                          /* subtree tasks run by the depth-first kernel */
+  uint32_t mfma_form;                          /* 1: Gram kernels ran in FP4 (e2m1) form, 0: int8 */
 } bm_stats;
 
 /* Tuning and behaviour switches for bm_mine_ex / bm_mine_batch.  Zero fields
@@ -105,6 +107,10 @@ typedef struct {
 #define BM_FLAG_TRACE 16u      /* keep per-class features and subtree costs (bm_result_trace) */
 #define BM_FLAG_SHUFFLE 32u    /* random subtree-task order (order-invariance tests) */
 #define BM_FLAG_LEVELSYNC 64u  /* evaluate small classes level by level too (no depth-first kernel) */
+#define BM_FLAG_FP4_MFMA 128u  /* Gram kernels on the FP4 (e2m1) MFMA form (the default): bits
+                                * as 0 / 0.5, FP32 sums, exact for counts < 2^24 per task (word
+                                * splits are capped to guarantee it) */
+#define BM_FLAG_INT8_MFMA 256u /* Gram kernels on int8 x int8 -> int32 MFMA (overrides FP4) */
 
 typedef struct {
   uint32_t flags;
@@ -115,7 +121,9 @@ typedef struct {
   uint32_t dfs_threads;       /* threads per workgroup of the depth-first kernel: 256, 512 or 1024 */
   uint32_t dfs_max_words;     /* depth-first phase only when every database has at most this many
                                * 64-bit words per column (0 = default; 0xffffffff = always) */
-  uint32_t reserved[5];
+  uint32_t mfma_big_children; /* MFMA classes with at least this many children use 256-wide
+                               * tiles (0 = default: never) */
+  uint32_t reserved[4];
 } bm_options;
 
 uint32_t bm_abi_version(void);
@@ -199,7 +207,8 @@ bm_status bm_mine_batch(const bm_db* const* dbs, const uint32_t* minsups, uint32
 /* Autotuner (batching design, word tiles and block shapes): times real calls of
  * bm_mine_batch on these databases over a coordinate search of the tuning
  * fields of bm_options -- depth-first phase off / default cut-off / always,
- * mfma_min_children, split_words, andpop_chunk_words, dfs_threads -- and writes
+ * mfma_min_children, mfma_big_children, split_words, andpop_chunk_words,
+ * dfs_threads -- and writes
  * the fastest combination to *best (base's other flags kept; NULL base =
  * defaults).  Each point is the minimum of `reps` calls (0 = 3); *best_ms
  * (optional) receives its wall time.  No tuning field changes the mined

@@ -20,14 +20,15 @@ import os
 import numpy as np
 
 from . import _bm
-from ._bm import (BM_K_NAMES, FLAG_ALL_MFMA, FLAG_GRAPH, FLAG_LEVELSYNC, FLAG_NO_MFMA,
+from ._bm import (BM_K_NAMES, FLAG_ALL_MFMA, FLAG_FP4_MFMA, FLAG_GRAPH, FLAG_INT8_MFMA,
+                  FLAG_LEVELSYNC, FLAG_NO_MFMA,
                   FLAG_SHUFFLE, FLAG_TIMING, FLAG_TRACE, MLP_PARAMS, BmError, BmOptions)
 
 __all__ = [
     "bm_abi_version", "bm_build", "bm_build_batch", "bm_item_support", "bm_pair_support", "bm_mine",
     "bm_mine_ex", "bm_mine_batch", "bm_set_allocator", "bm_release_cached_memory", "Db", "Result", "BmError",
     "options", "FLAG_TIMING", "FLAG_NO_MFMA", "FLAG_ALL_MFMA", "FLAG_GRAPH", "FLAG_TRACE",
-    "FLAG_SHUFFLE", "FLAG_LEVELSYNC", "LIB_PATH", "Model", "MLP_PARAMS", "bm_autotune",
+    "FLAG_SHUFFLE", "FLAG_LEVELSYNC", "FLAG_FP4_MFMA", "FLAG_INT8_MFMA", "LIB_PATH", "Model", "MLP_PARAMS", "bm_autotune",
     "autotune_cached", "options_to_dict", "options_from_dict", "shape_key",
 ]
 
@@ -136,6 +137,7 @@ class Result:
             "wall_ms": float(st.wall_ms),
             "host_syncs": int(st.host_syncs),
             "dfs_tasks": int(st.dfs_tasks),
+            "mfma_form": "fp4" if st.mfma_form else "int8",
         }
 
     def trace(self):
@@ -163,7 +165,7 @@ class Result:
 
 def options(flags: int = 0, mfma_min_children: int = 0, andpop_chunk_words: int = 0,
             split_words: int = 0, shuffle_seed: int = 0, dfs_threads: int = 0,
-            dfs_max_words: int = 0) -> BmOptions:
+            dfs_max_words: int = 0, mfma_big_children: int = 0) -> BmOptions:
     o = BmOptions()
     o.flags = flags
     o.mfma_min_children = mfma_min_children
@@ -172,6 +174,7 @@ def options(flags: int = 0, mfma_min_children: int = 0, andpop_chunk_words: int 
     o.shuffle_seed = shuffle_seed
     o.dfs_threads = dfs_threads
     o.dfs_max_words = dfs_max_words
+    o.mfma_big_children = mfma_big_children
     return o
 
 
@@ -293,7 +296,7 @@ def bm_autotune(dbs, minsups, model=None, base: BmOptions | None = None, reps: i
 
 
 _TUNE_FIELDS = ("flags", "mfma_min_children", "andpop_chunk_words", "split_words", "dfs_threads",
-                "dfs_max_words")
+                "dfs_max_words", "mfma_big_children")
 
 
 def options_to_dict(o: BmOptions) -> dict:

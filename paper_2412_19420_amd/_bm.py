@@ -23,7 +23,7 @@ lib = ctypes.CDLL(LIB_PATH)
 
 BM_MAX_LEVELS = 64
 BM_K_NAMES = ["build", "colsum", "gram_mfma", "andpop", "andpop_reg", "level", "emit", "dfs",
-              "sched"]
+              "sched", "gram_mfma_big"]
 BM_K_COUNT = len(BM_K_NAMES)
 
 FLAG_TIMING = 1
@@ -33,6 +33,8 @@ FLAG_GRAPH = 8
 FLAG_TRACE = 16
 FLAG_SHUFFLE = 32
 FLAG_LEVELSYNC = 64
+FLAG_FP4_MFMA = 128
+FLAG_INT8_MFMA = 256
 MLP_PARAMS = 4801
 
 STATUS = {0: "BM_OK", 1: "BM_ERR_INVALID_ARG", 2: "BM_ERR_CSR", 3: "BM_ERR_OOM",
@@ -56,6 +58,7 @@ class BmStats(ctypes.Structure):
         ("wall_ms", ctypes.c_double),
         ("host_syncs", ctypes.c_uint32),
         ("dfs_tasks", ctypes.c_uint64),
+        ("mfma_form", ctypes.c_uint32),
     ]
 
 
@@ -68,7 +71,8 @@ class BmOptions(ctypes.Structure):
         ("shuffle_seed", ctypes.c_uint32),
         ("dfs_threads", ctypes.c_uint32),
         ("dfs_max_words", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 5),
+        ("mfma_big_children", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 4),
     ]
 
 

@@ -3,7 +3,7 @@
 // Every tuning field changes only speed, never the result, so the tuner can
 // time real calls on the caller's own databases: a coordinate search over
 //   * the depth-first phase (on at any column length / off),
-//   * the MFMA routing threshold (children per class),
+//   * the MFMA routing thresholds (children per class, for 128- and 256-wide tiles),
 //   * the word-range length of one task (automatic or fixed),
 //   * the AND+popcount LDS chunk,
 //   * the depth-first workgroup size,
@@ -69,6 +69,7 @@ bm_options autotune(const bm_db* const* dbs, const uint32_t* minsups, uint32_t c
       },
       {0u, 4096u, 0xffffffffu});
   try_field([](bm_options& o, uint32_t v) { o.mfma_min_children = v; }, {24u, 32u, 48u, 64u, 96u, 128u});
+  try_field([](bm_options& o, uint32_t v) { o.mfma_big_children = v; }, {192u, 256u, 512u, 0xffffffffu});
   try_field([](bm_options& o, uint32_t v) { o.split_words = v; }, {0u, 512u, 1024u, 2048u, 4096u});
   try_field([](bm_options& o, uint32_t v) { o.andpop_chunk_words = v; }, {128u, 256u});
   if (!(cur.flags & BM_FLAG_LEVELSYNC))

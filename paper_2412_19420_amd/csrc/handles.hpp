@@ -62,9 +62,11 @@ const char* last_error();
 // Defaults of the tuning knobs (no knob changes the result).
 struct Tuning {
   uint32_t mfma_min_q = 64;     // classes with this many children or more go to MFMA
+  uint32_t mfma_big_q = 0xffffffffu;  // ... and with this many, to the 256-wide MFMA tiles
   uint32_t andpop_chunk = 256;  // AND+popcount LDS chunk (words)
   uint32_t split_words = 0;     // 0 = automatic word split
   bool dfs = true;              // small classes: depth-first subtree kernel
+  bool mfma_fp4 = true;         // MFMA kernels in the e2m1 form (else int8)
   uint32_t dfs_threads = 256;   // threads per depth-first workgroup
   uint32_t dfs_max_words = 4096;  // depth-first only when every column has <= this many words
 };

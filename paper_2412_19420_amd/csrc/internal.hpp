@@ -127,6 +127,7 @@ __host__ __device__ inline uint64_t tri_index(uint64_t i, uint64_t l, uint64_t q
 }
 
 constexpr int GRAM_TILE = 128;  // MFMA kernel output tile (children per block)
+constexpr int GRAM_TILE_BIG = 256;  // big-class MFMA kernel output tile
 constexpr int GRAM_KW = 16;     // MFMA kernel words per LDS stage
 constexpr int AP_BLOCK = 16;    // AND+popcount kernel children per block
 constexpr int TINY_Q = 8;       // classes up to this many children use the register kernel
@@ -227,7 +228,13 @@ void scan_ge_u32(const uint32_t* in, uint32_t thr, uint64_t* out, uint64_t n, ui
                  hipStream_t s);
 
 // class kernels
-void launch_gram_mfma(const ClassArgs& a, uint32_t grid, hipStream_t s);
+// fp4: the e2m1 MFMA form (64 transactions per instruction, exact FP32 sums of
+// quarters for counts below 2^24); else int8 x int8 -> int32.
+void launch_gram_mfma(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s);
+// Same contraction with 256 x 256 tiles (tasks index 256-wide blocks).
+void launch_gram_mfma_big(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s);
+// Longest word range one MFMA task may cover in the fp4 form (2^24 transactions).
+constexpr uint32_t GRAM_FP4_MAX_WORDS = 1u << 18;
 void launch_andpop(const ClassArgs& a, uint32_t chunk_words, uint32_t grid, hipStream_t s);
 void launch_andpop_reg(const ClassArgs& a, uint32_t grid, hipStream_t s);
 

@@ -23,6 +23,8 @@
 //     bit -> (lane, byte) map, so every transaction meets itself in the K sum;
 //   * the accumulated tile is added atomically into the class's triangle
 //     (integer adds: exact and independent of the order of word splits).
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace bm {
@@ -30,11 +32,10 @@ namespace bm {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
-constexpr int T = GRAM_TILE;     // 128
-constexpr int KW = GRAM_KW;      // 16 words per stage
-constexpr int LDW = 2 * KW + 1;  // dwords per column row in LDS (odd stride: conflict-free reads)
 
 __device__ __forceinline__ v4i expand4(uint32_t v, int d0) {
   v4i r;
@@ -45,14 +46,40 @@ __device__ __forceinline__ v4i expand4(uint32_t v, int d0) {
   return r;
 }
 
-__global__ __launch_bounds__(256) void k_gram_mfma(ClassArgs a) {
-  __shared__ uint32_t sA[T * LDW];
-  __shared__ uint32_t sB[T * LDW];
+// FP4 (e2m1) form: a lane's 32-bit half-word v becomes 32 nibbles, nibble j of
+// dword d = bit 4j + d of v, each 0 or 0x1 (the e2m1 value 0.5).  One
+// v_mfma_f32_32x32x64_f8f6f4 then sums 64 transactions; every product is 0 or
+// 0.25 and FP32 holds every multiple of 0.25 below 2^22 exactly, so a task's
+// sums are exact while its counts stay below 2^24 -- the task word split is
+// capped at GRAM_FP4_MAX_WORDS for that.
+__device__ __forceinline__ v8i expand_fp4(uint32_t v) {
+  v8i r;
+  r[0] = (int)((v >> 0) & 0x11111111u);
+  r[1] = (int)((v >> 1) & 0x11111111u);
+  r[2] = (int)((v >> 2) & 0x11111111u);
+  r[3] = (int)((v >> 3) & 0x11111111u);
+  r[4] = r[5] = r[6] = r[7] = 0;
+  return r;
+}
+
+// NB = 32x32 accumulator blocks per wave side: NB = 2 gives 64x64 per wave and
+// a 128x128 workgroup tile; NB = 4 gives 128x128 per wave (256 accumulator
+// registers, one wave per SIMD) and a 256x256 tile, which halves both the bit
+// expansions per MFMA and the column traffic per output for big classes.
+// KW = words per LDS stage (a divisor of GRAM_KW, so stages tile every task).
+template <int NB, int KW, bool F4>
+__device__ __forceinline__ void gram_tiles(const ClassArgs& a, uint32_t* sA, uint32_t* sB) {
+  static_assert(GRAM_KW % KW == 0, "stages must tile the task word ranges");
+  constexpr int T = 64 * NB;         // workgroup tile (children per side)
+  constexpr int LDW = 2 * KW + 1;    // dwords per column row in LDS (odd stride: conflict-free reads)
+  constexpr int SUBS = KW / 2;       // 16-byte slots per column per stage
+  constexpr int CSL = 256 / SUBS;    // columns staged per pass of the workgroup
+  constexpr int NS = T / CSL;        // column slots per side staged by each thread
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  const int sub = tid & 7;     // 16-byte slot of a column's 128-byte stage slice
-  const int cslot = tid >> 3;  // column slot 0..31
+  const int sub = tid % SUBS;   // 16-byte slot of a column's stage slice
+  const int cslot = tid / SUBS; // column slot 0..CSL-1
   const uint64_t ntasks = *a.ntasks;
 
   for (uint64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
@@ -63,13 +90,13 @@ __global__ __launch_bounds__(256) void k_gram_mfma(ClassArgs a) {
     const uint32_t q = cd.q;
     const uint32_t I0 = (uint32_t)task.bi * T, L0 = (uint32_t)task.bl * T;
     const bool diag = task.bi == task.bl;
-    const int nload = diag ? 4 : 8;
+    const int nload = diag ? NS : 2 * NS;
 
     // base pointers of the columns this thread stages (nullptr = zero column)
-    const uint64_t* colp[8];
+    const uint64_t* colp[2 * NS];
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
-      const uint32_t idx = ((p >> 2) ? L0 : I0) + cslot + 32 * (p & 3);
+    for (int p = 0; p < 2 * NS; ++p) {
+      const uint32_t idx = ((p >= NS) ? L0 : I0) + cslot + CSL * (p % NS);
       colp[p] = nullptr;
       if (p < nload && idx < q) {
         const uint32_t item = a.child_item[cd.child0 + idx];
@@ -80,7 +107,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(ClassArgs a) {
     const uint32_t* pre = a.pre_cols + cd.pre_off;
     const uint32_t pre_len = cd.pre_len;
 
-    uint4 reg[8];
+    uint4 reg[2 * NS];
     uint64_t m0 = ~0ull, m1 = ~0ull;
     auto load_stage = [&](uint32_t w) {
       m0 = ~0ull;
@@ -91,17 +118,18 @@ __global__ __launch_bounds__(256) void k_gram_mfma(ClassArgs a) {
         m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
       }
 #pragma unroll
-      for (int p = 0; p < 8; ++p) {
+      for (int p = 0; p < 2 * NS; ++p) {
         if (colp[p]) reg[p] = *reinterpret_cast<const uint4*>(colp[p] + w);
         else reg[p] = make_uint4(0, 0, 0, 0);
       }
     };
 
-    v16i acc[2][2];
+    using Acc = typename std::conditional<F4, v16f, v16i>::type;
+    Acc acc[NB][NB];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NB; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < NB; ++j)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
 
@@ -110,9 +138,9 @@ __global__ __launch_bounds__(256) void k_gram_mfma(ClassArgs a) {
     for (uint32_t s = 0; s < nst; ++s) {
       __syncthreads();  // previous stage (or task) finished reading LDS
 #pragma unroll
-      for (int p = 0; p < 8; ++p) {
+      for (int p = 0; p < 2 * NS; ++p) {
         if (p < nload) {
-          uint32_t* dst = ((p >> 2) ? sB : sA) + (cslot + 32 * (p & 3)) * LDW + 4 * sub;
+          uint32_t* dst = ((p >= NS) ? sB : sA) + (cslot + CSL * (p % NS)) * LDW + 4 * sub;
           const uint64_t x0 = ((uint64_t)reg[p].x | ((uint64_t)reg[p].y << 32)) & m0;
           const uint64_t x1 = ((uint64_t)reg[p].z | ((uint64_t)reg[p].w << 32)) & m1;
           dst[0] = (uint32_t)x0;
@@ -124,20 +152,44 @@ __global__ __launch_bounds__(256) void k_gram_mfma(ClassArgs a) {
       __syncthreads();
       if (s + 1 < nst) load_stage(task.w0 + (s + 1) * KW);
 
-      const uint32_t* pa = sA + (wr * 64 + (lane & 31)) * LDW + (lane >> 5);
-      const uint32_t* pb = (diag ? sA : sB) + (wc * 64 + (lane & 31)) * LDW + (lane >> 5);
-#pragma unroll 4
+      const uint32_t* pa = sA + (wr * (T / 2) + (lane & 31)) * LDW + (lane >> 5);
+      const uint32_t* pb = (diag ? sA : sB) + (wc * (T / 2) + (lane & 31)) * LDW + (lane >> 5);
+#pragma unroll(NB == 2 ? 2 : 1)
       for (int w = 0; w < KW; ++w) {
-        const uint32_t va0 = pa[2 * w], va1 = pa[32 * LDW + 2 * w];
-        const uint32_t vb0 = pb[2 * w], vb1 = pb[32 * LDW + 2 * w];
+        uint32_t va[NB], vb[NB];
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const v4i A0 = expand4(va0, 4 * e), A1 = expand4(va1, 4 * e);
-          const v4i B0 = expand4(vb0, 4 * e), B1 = expand4(vb1, 4 * e);
-          acc[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, B0, acc[0][0], 0, 0, 0);
-          acc[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, B1, acc[0][1], 0, 0, 0);
-          acc[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B0, acc[1][0], 0, 0, 0);
-          acc[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B1, acc[1][1], 0, 0, 0);
+        for (int i = 0; i < NB; ++i) {
+          va[i] = pa[i * 32 * LDW + 2 * w];
+          vb[i] = pb[i * 32 * LDW + 2 * w];
+        }
+        if constexpr (F4) {
+          v8i A[NB], B[NB];
+#pragma unroll
+          for (int i = 0; i < NB; ++i) {
+            A[i] = expand_fp4(va[i]);
+            B[i] = expand_fp4(vb[i]);
+          }
+#pragma unroll
+          for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)  // format 4 = e2m1 for both operands, no scaling
+              acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[i], B[j], acc[i][j], 4,
+                                                                          4, 0, 0, 0, 0);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            v4i A[NB], B[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+              A[i] = expand4(va[i], 4 * e);
+              B[i] = expand4(vb[i], 4 * e);
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+              for (int j = 0; j < NB; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i], B[j], acc[i][j], 0, 0, 0);
+          }
         }
       }
     }
@@ -146,24 +198,54 @@ __global__ __launch_bounds__(256) void k_gram_mfma(ClassArgs a) {
     // row 8*(r/4) + 4*(lane/32) + (r%4).
     uint32_t* tri = a.tri + cd.tri_off;
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < NB; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
+      for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const uint32_t gi = I0 + wr * 64 + rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-          const uint32_t gl = L0 + wc * 64 + cb * 32 + (lane & 31);
-          const int v = acc[rb][cb][r];
-          if (gi < gl && gl < q && v) atomicAdd(tri + tri_index(gi, gl, q), (uint32_t)v);
+          const uint32_t gi =
+              I0 + wr * (T / 2) + rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const uint32_t gl = L0 + wc * (T / 2) + cb * 32 + (lane & 31);
+          uint32_t v;
+          if constexpr (F4) v = __float2uint_rn(acc[rb][cb][r] * 4.0f);  // exact: quarters
+          else v = (uint32_t)acc[rb][cb][r];
+          if (gi < gl && gl < q && v) atomicAdd(tri + tri_index(gi, gl, q), v);
         }
   }
 }
 
+template <bool F4>
+__global__ __launch_bounds__(256) void k_gram_mfma(ClassArgs a) {
+  constexpr int KW = 16;
+  __shared__ uint32_t sA[GRAM_TILE * (2 * KW + 1)];
+  __shared__ uint32_t sB[GRAM_TILE * (2 * KW + 1)];
+  gram_tiles<2, KW, F4>(a, sA, sB);
+}
+
+// 8-word stages keep the staging registers at 8 x 16 bytes per thread next to
+// the 256 accumulator registers.
+template <bool F4>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_gram_mfma_big(ClassArgs a) {
+  constexpr int KW = 8;
+  __shared__ uint32_t sA[GRAM_TILE_BIG * (2 * KW + 1)];
+  __shared__ uint32_t sB[GRAM_TILE_BIG * (2 * KW + 1)];
+  gram_tiles<4, KW, F4>(a, sA, sB);
+}
+
 }  // namespace
 
-void launch_gram_mfma(const ClassArgs& a, uint32_t grid, hipStream_t s) {
+void launch_gram_mfma(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s) {
   if (grid == 0) return;
-  k_gram_mfma<<<grid, 256, 0, s>>>(a);
+  if (fp4) k_gram_mfma<true><<<grid, 256, 0, s>>>(a);
+  else k_gram_mfma<false><<<grid, 256, 0, s>>>(a);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_gram_mfma_big(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s) {
+  if (grid == 0) return;
+  if (fp4) k_gram_mfma_big<true><<<grid, 256, 0, s>>>(a);
+  else k_gram_mfma_big<false><<<grid, 256, 0, s>>>(a);
   BM_LAUNCH_CHECK();
 }
 

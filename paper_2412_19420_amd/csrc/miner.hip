@@ -128,6 +128,13 @@ TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_v, uint64_t c
   g.split_m = (uint32_t)pick(pairs_m, 256, GRAM_KW);
   g.split_v = (uint32_t)pick(pairs_v, 512, 1);
   g.split_t = (uint32_t)pick(classes_t, 2048, 64);
+  // a 256-wide tile holds about four 128-wide tiles: split its words further
+  g.split_b = (uint32_t)pick((pairs_m + 3) / 4, 256, GRAM_KW);
+  g.big_q = tu.mfma_big_q;
+  if (tu.mfma_fp4) {  // keep every MFMA task's counts below 2^24
+    g.split_m = std::min<uint32_t>(g.split_m, GRAM_FP4_MAX_WORDS);
+    g.split_b = std::min<uint32_t>(g.split_b, GRAM_FP4_MAX_WORDS);
+  }
   return g;
 }
 
@@ -136,9 +143,9 @@ struct StepWork {
   uint64_t ncls = 0;
   TBuf<ClassDesc> cls;
   TBuf<uint32_t> pre;
-  TBuf<Task> tm, tv, tt;
-  uint64_t ub_m = 0, ub_v = 0, ub_t = 0;  // task-count upper bounds (host)
-  TBuf<uint64_t> om, ov, ot;              // task offsets per class (+ total at [ncls])
+  TBuf<Task> tm, tv, tt, tb;
+  uint64_t ub_m = 0, ub_v = 0, ub_t = 0, ub_b = 0;  // task-count upper bounds (host)
+  TBuf<uint64_t> om, ov, ot, ob;                    // task offsets per class (+ total at [ncls])
   TBuf<uint32_t> tri;
   uint64_t T = 0;
   uint64_t st[ST_COUNT] = {};
@@ -155,39 +162,49 @@ void prepare_tasks(StepWork& w, const DbInfo* ddb, uint64_t Wmax, uint64_t pairs
   const TaskGeom g = make_geom(Wmax, pairs_m, pairs_v, classes_t, tu);
   const uint64_t Wm = round_up(std::max<uint64_t>(1, Wmax), GRAM_KW);
   w.ub_m = pairs_m * ceil_div(Wm, g.split_m);
+  w.ub_b = g.big_q < 0xffffffffu ? pairs_m * ceil_div(Wm, g.split_b) : 0;
   w.ub_v = pairs_v * ceil_div(std::max<uint64_t>(1, Wmax), g.split_v);
   w.ub_t = dfs ? 0 : classes_t * ceil_div(std::max<uint64_t>(1, Wmax), g.split_t);
   if (dfs) {
     w.ndt = classes_t;
     w.dt.alloc(classes_t, s);
   }
-  TBuf<uint32_t> cm(w.ncls, s), cv(w.ncls, s), ct(w.ncls, s);
+  TBuf<uint32_t> cm(w.ncls, s), cv(w.ncls, s), ct(w.ncls, s), cb(w.ncls, s);
   w.om.alloc(w.ncls + 1, s);
   w.ov.alloc(w.ncls + 1, s);
   w.ot.alloc(w.ncls + 1, s);
+  w.ob.alloc(w.ncls + 1, s);
   launch_class_task_counts(w.cls.get(), w.ncls, ddb, tu.mfma_min_q, g, dfs, cm.get(), cv.get(),
-                           ct.get(), s);
-  const void* in[3] = {cm.get(), cv.get(), ct.get()};
-  const bool is64[3] = {false, false, false};
-  uint64_t* out[3] = {w.om.get(), w.ov.get(), w.ot.get()};
-  scan_many(in, is64, out, 3, w.ncls, s);
+                           ct.get(), cb.get(), s);
+  const void* in[4] = {cm.get(), cv.get(), ct.get(), cb.get()};
+  const bool is64[4] = {false, false, false, false};
+  uint64_t* out[4] = {w.om.get(), w.ov.get(), w.ot.get(), w.ob.get()};
+  scan_many(in, is64, out, 4, w.ncls, s);
   w.tm.alloc(w.ub_m, s);
   w.tv.alloc(w.ub_v, s);
   w.tt.alloc(w.ub_t, s);
+  w.tb.alloc(w.ub_b, s);
   launch_write_class_tasks(w.cls.get(), w.ncls, ddb, tu.mfma_min_q, g, w.om.get(), w.ov.get(),
                            w.ot.get(), w.tm.get(), w.tv.get(), w.tt.get(), dfs ? w.dt.get() : nullptr,
-                           level, s);
+                           level, w.ob.get(), w.tb.get(), s);
 }
 
 void run_class_kernels(const DbInfo* ddb, const uint32_t* child_item, const StepWork& w,
                        const Tuning& tu, double nW, double nN, KTimer& tm, hipStream_t s) {
   ClassArgs a{ddb, child_item, w.cls.get(), w.pre.get(), nullptr, nullptr, w.tri.get()};
   const uint64_t ncu = (uint64_t)cu_count();
-  if (w.ub_m) {
+  if (w.ub_b && w.st[ST_CLS_B]) {
+    a.tasks = w.tb.get();
+    a.ntasks = w.ob.get() + w.ncls;
+    tm.begin(BM_K_GRAM_MFMA_BIG);
+    launch_gram_mfma_big(a, (uint32_t)std::min<uint64_t>(w.ub_b, ncu), tu.mfma_fp4, s);
+    tm.end(8.0 * nW * (double)w.st[ST_COLS_B], 2.0 * (double)w.st[ST_CAND_B] * nN);
+  }
+  if (w.ub_m && w.st[ST_CLS_M]) {
     a.tasks = w.tm.get();
     a.ntasks = w.om.get() + w.ncls;
     tm.begin(BM_K_GRAM_MFMA);
-    launch_gram_mfma(a, (uint32_t)std::min<uint64_t>(w.ub_m, ncu * 4), s);
+    launch_gram_mfma(a, (uint32_t)std::min<uint64_t>(w.ub_m, ncu * 4), tu.mfma_fp4, s);
     tm.end(8.0 * nW * (double)w.st[ST_COLS_M], 2.0 * (double)w.st[ST_CAND_M] * nN);
   }
   if (w.ub_v) {
@@ -220,8 +237,8 @@ void host_classes(StepWork& w, const std::vector<ClassDesc>& hc, const DbInfo* d
   for (const auto& c : hc) {
     const uint64_t tsz = (uint64_t)c.q * (c.q - 1) / 2;
     w.T += tsz;
-    const int kind = class_kind(c.q, tu.mfma_min_q);
-    if (kind == 0) pm += host_mfma_pairs(c.q);
+    const int kind = class_kind(c.q, tu.mfma_min_q, tu.mfma_big_q);
+    if (is_mfma_kind(kind)) pm += host_mfma_pairs(c.q);
     else if (kind == 1) pv += host_andpop_pairs(c.q);
     else ct += 1;
     w.st[ST_CAND_M + kind] += tsz;
@@ -264,7 +281,10 @@ Tuning tuning_from(const bm_options* opt) {
     t.dfs_threads = opt->dfs_threads;
   }
   if (opt->dfs_max_words) t.dfs_max_words = opt->dfs_max_words;
+  if (opt->mfma_big_children) t.mfma_big_q = std::max<uint32_t>(2, opt->mfma_big_children);
   if (opt->flags & BM_FLAG_LEVELSYNC) t.dfs = false;
+  if (opt->flags & BM_FLAG_FP4_MFMA) t.mfma_fp4 = true;
+  if (opt->flags & BM_FLAG_INT8_MFMA) t.mfma_fp4 = false;
   if (opt->flags & BM_FLAG_NO_MFMA) t.mfma_min_q = 0xffffffffu;
   if (opt->flags & BM_FLAG_ALL_MFMA) t.mfma_min_q = 2;
   return t;
@@ -500,6 +520,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
   BM_HIP(hipGetDevice(&device));
   auto store = std::make_shared<ResultStore>();
   bm_stats st{};
+  st.mfma_form = tu.mfma_fp4 ? 1u : 0u;
   KTimer tm((flags & BM_FLAG_TIMING) != 0, s);
   std::vector<uint64_t> Fs(N + 1, 0), Is(N + 1, 0);
   std::vector<std::vector<uint64_t>> per_level;  // [k] -> first node of each database (N+1)
@@ -612,7 +633,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         st.candidates_total += ls_cand;
         if (w->ndt) parts.push_back({w->dt.get(), w->ndt});
         step_pre[k] = w->pre.get();
-        st.classes_mfma += w->st[ST_CLS_M];
+        st.classes_mfma += w->st[ST_CLS_M] + w->st[ST_CLS_B];
         st.classes_andpop += w->st[ST_CLS_V] + w->st[ST_CLS_T];
         run_class_kernels(ddb.get(), L[k].item.get(), *w, tu, nW, nN, tm, s);
 
@@ -627,7 +648,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         TBuf<unsigned long long> dst(ST_COUNT, s);
         launch_fill_u64(reinterpret_cast<uint64_t*>(dst.get()), 0, ST_COUNT, s);
         launch_node_counts(nk, k, L[k].parent.get(), pcls_prev.get(), w->cls.get(), S.get(),
-                           tu.mfma_min_q, cnt.get(), iscls.get(), trisz.get(), pm.get(), pv.get(),
+                           tu.mfma_min_q, tu.mfma_big_q, cnt.get(), iscls.get(), trisz.get(), pm.get(), pv.get(),
                            pt.get(), dst.get(), s);
         L[k].cstart.alloc(nk + 1, s);
         TBuf<uint64_t> clspos(nk + 1, s), trioff(nk + 1, s), pmoff(nk + 1, s), pvoff(nk + 1, s),

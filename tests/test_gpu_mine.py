@@ -84,6 +84,7 @@ def test_build_from_device_pointers(bm):
     (10_000, 169, None, None),      # basket workload, all items (MFMA path)
     (5_000, 40, None, 0.3),         # few items (AND+popcount path)
     (3_001, 300, None, 0.1),        # three MFMA tiles, ragged in both dims
+    (2_433, 600, None, 0.08),       # three 256-wide MFMA tiles, ragged
     (65, 70, None, 0.5),            # one word plus one bit
 ])
 def test_pair_support_equals_gram(bm, n, m, k, density):
@@ -126,9 +127,14 @@ def test_mine_matches_brute_force(bm, seed):
     for minsup in sorted({1, 2, max(1, n // 5), max(1, n // 2), n, n + 1}):
         print(f"brute seed={seed} n={n} m={m} minsup={minsup}", flush=True)
         want = brute.mine(db.row_ptr, db.col_idx, db.n, db.m, minsup)
-        for flags in (0, bm.FLAG_NO_MFMA, bm.FLAG_ALL_MFMA):
-            r = bm.bm_mine_ex(h, minsup, bm.options(flags=flags))
-            assert r.to_list() == want, (flags, minsup)
+        routings = [bm.options(flags=0), bm.options(flags=bm.FLAG_NO_MFMA),
+                    bm.options(flags=bm.FLAG_ALL_MFMA | bm.FLAG_INT8_MFMA),
+                    bm.options(flags=bm.FLAG_ALL_MFMA | bm.FLAG_INT8_MFMA, mfma_big_children=2),
+                    bm.options(flags=bm.FLAG_ALL_MFMA | bm.FLAG_FP4_MFMA),
+                    bm.options(flags=bm.FLAG_ALL_MFMA | bm.FLAG_FP4_MFMA, mfma_big_children=2)]
+        for o in routings:
+            r = bm.bm_mine_ex(h, minsup, o)
+            assert r.to_list() == want, (o.flags, o.mfma_big_children, minsup)
 
 
 def test_hand_example(bm):
@@ -372,3 +378,45 @@ def test_build_batch_errors_name_the_database(bm, case):
     h = bm.bm_build_batch(items[:1])[0]
     assert np.array_equal(bm.bm_item_support(h).astype(np.int64),
                           pairs.column_sums(good.row_ptr, good.col_idx, good.n, good.m))
+
+
+@pytest.mark.parametrize("form", ["int8", "fp4"])
+@pytest.mark.parametrize("big", [2, 64, 300, 0xFFFFFFFF])
+def test_mine_quest_mfma_routings_exact(bm, big, form):
+    # every MFMA class on 256-wide tiles (2), a split at 64 and inside the root
+    # class's range, and none (0xFFFFFFFF), in both MFMA forms: the oracle's arrays
+    db = gen.make_config(2)
+    print(f"quest MFMA routing big={big} form={form}", flush=True)
+    flag = bm.FLAG_FP4_MFMA if form == "fp4" else bm.FLAG_INT8_MFMA
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    r = bm.bm_mine_ex(h, db.minsup, bm.options(flag, mfma_big_children=big))
+    _, want, _ = oracle_arrays(db, db.minsup)
+    assert_same(r.arrays(), want)
+
+
+def test_fp4_mfma_counts_beyond_fp32_quarter_range(bm):
+    # item 0 in every row, item 1 in 63 of every 64: each 64-transaction MFMA step
+    # adds 15.75 (63 quarters), so one FP32 accumulator over all 20M rows would
+    # lose quarters past 2^22; the capped word split keeps every task exact
+    n = 20_000_000
+    keep1 = (np.arange(n) % 64) != 0
+    lens = 1 + keep1.astype(np.uint64)
+    row_ptr = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(lens, out=row_ptr[1:])
+    col_idx = np.zeros(int(row_ptr[-1]), dtype=np.uint32)
+    col_idx[row_ptr[:-1][keep1].astype(np.int64) + 1] = 1
+    print("fp4 range test, 20M rows", flush=True)
+    h = bm.bm_build(row_ptr, col_idx, n, 2)
+    want = [((0,), n), ((0, 1), int(keep1.sum())), ((1,), int(keep1.sum()))]
+    for flags in (bm.FLAG_INT8_MFMA, bm.FLAG_FP4_MFMA):
+        r = bm.bm_mine_ex(h, 1, bm.options(flags | bm.FLAG_ALL_MFMA, split_words=1 << 19))
+        assert r.to_list() == want, flags
+
+
+def test_fp4_and_int8_identical_on_full_dense(bm):
+    db = gen.make_config(3)
+    print("fp4 vs int8, dense 1M", flush=True)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    a = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_INT8_MFMA)).arrays()
+    b = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_FP4_MFMA)).arrays()
+    assert_same(a, b)
