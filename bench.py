@@ -34,6 +34,7 @@ MFMA_PEAK_TOPS = {"int8": 5000.0, "fp4": 10100.0}
 MFMA_KERNELS = {
     "gram_mfma": "k_gram_mfma (MFMA Gram of a prefix class, 128x128 tiles)",
     "gram_mfma_big": "k_gram_mfma_big (MFMA Gram of a prefix class, 256x256 tiles)",
+    "gram_small": "k_gram_small (MFMA Gram of a mid-size class, 32x32 tiles, one wave per task)",
 }
 # streaming kernels priced against HBM: algorithmic bytes = column words read
 HBM_KERNELS = {
@@ -116,6 +117,7 @@ TRAFFIC = {
 }
 KERNEL_SOURCE = {
     "gram_mfma": "k_gram_mfma.hip", "gram_mfma_big": "k_gram_mfma.hip",
+    "gram_small": "k_gram_small.hip",
     "andpop": "k_andpop.hip", "andpop_reg": "k_andpop.hip", "dfs": "k_dfs.hip",
 }
 WORKLOAD = None

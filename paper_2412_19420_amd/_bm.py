@@ -23,7 +23,7 @@ lib = ctypes.CDLL(LIB_PATH)
 
 BM_MAX_LEVELS = 64
 BM_K_NAMES = ["build", "colsum", "gram_mfma", "andpop", "andpop_reg", "level", "emit", "dfs",
-              "sched", "gram_mfma_big"]
+              "sched", "gram_mfma_big", "gram_small"]
 BM_K_COUNT = len(BM_K_NAMES)
 
 FLAG_TIMING = 1

@@ -61,7 +61,8 @@ const char* last_error();
 
 // Defaults of the tuning knobs (no knob changes the result).
 struct Tuning {
-  uint32_t mfma_min_q = 64;     // classes with this many children or more go to MFMA
+  uint32_t mfma_min_q = 64;     // classes with this many children or more go to 128-wide MFMA tiles
+  bool mfma_small = true;       // classes of 9 .. mfma_min_q - 1 children: 32-wide MFMA tiles
   uint32_t mfma_big_q = 0xffffffffu;  // ... and with this many, to the 256-wide MFMA tiles
   uint32_t andpop_chunk = 256;  // AND+popcount LDS chunk (words)
   uint32_t split_words = 0;     // 0 = automatic word split

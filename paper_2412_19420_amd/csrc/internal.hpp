@@ -130,6 +130,8 @@ constexpr int GRAM_TILE = 128;  // MFMA kernel output tile (children per block)
 constexpr int GRAM_TILE_BIG = 256;  // big-class MFMA kernel output tile
 constexpr int GRAM_KW = 16;     // MFMA kernel words per LDS stage
 constexpr int AP_BLOCK = 16;    // AND+popcount kernel children per block
+constexpr int GRAM_SMALL_TILE = 32;  // mid-size-class MFMA kernel children per block
+constexpr int GRAM_SMALL_KW = 16;    // its task word ranges are multiples of this
 constexpr int TINY_Q = 8;       // classes up to this many children use the register kernel
 
 // Arguments shared by the class kernels.  They loop over the task list from
@@ -233,6 +235,8 @@ void scan_ge_u32(const uint32_t* in, uint32_t thr, uint64_t* out, uint64_t n, ui
 void launch_gram_mfma(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s);
 // Same contraction with 256 x 256 tiles (tasks index 256-wide blocks).
 void launch_gram_mfma_big(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s);
+// Mid-size classes: one wave per 32 x 32 block pair (tasks index 32-wide blocks).
+void launch_gram_small(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s);
 // Longest word range one MFMA task may cover in the fp4 form (2^24 transactions).
 constexpr uint32_t GRAM_FP4_MAX_WORDS = 1u << 18;
 void launch_andpop(const ClassArgs& a, uint32_t chunk_words, uint32_t grid, hipStream_t s);

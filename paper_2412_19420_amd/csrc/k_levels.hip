@@ -130,10 +130,10 @@ __device__ inline uint32_t mfma_pairs(uint32_t q, uint32_t tile = GRAM_TILE) {
   const uint32_t nb = (q + tile - 1) / tile;
   return nb * (nb + 1) / 2;
 }
-__device__ inline uint32_t andpop_pairs(uint32_t q) {
-  const uint32_t nb = (q + AP_BLOCK - 1) / AP_BLOCK;
+__device__ inline uint32_t andpop_pairs(uint32_t q, uint32_t block = AP_BLOCK) {
+  const uint32_t nb = (q + block - 1) / block;
   // the diagonal block of a lone last child holds no pair
-  return nb * (nb + 1) / 2 - ((q % AP_BLOCK) == 1 ? 1u : 0u);
+  return nb * (nb + 1) / 2 - ((q % block) == 1 ? 1u : 0u);
 }
 
 // Per node of level k: number of frequent children, and what it contributes
@@ -142,7 +142,7 @@ __device__ inline uint32_t andpop_pairs(uint32_t q) {
 __global__ __launch_bounds__(kThreads) void k_node_counts(
     uint64_t n, uint32_t k, const uint32_t* __restrict__ parent, const int32_t* __restrict__ pcls,
     const ClassDesc* __restrict__ cls, const uint64_t* __restrict__ S, uint32_t mfma_min_q,
-    uint32_t big_q, uint32_t* __restrict__ cnt, uint32_t* __restrict__ is_cls, uint64_t* __restrict__ tri_sz,
+    uint32_t big_q, uint32_t small_on, uint32_t* __restrict__ cnt, uint32_t* __restrict__ is_cls, uint64_t* __restrict__ tri_sz,
     uint32_t* __restrict__ pm, uint32_t* __restrict__ pv, uint32_t* __restrict__ pt,
     unsigned long long* __restrict__ st) {
   __shared__ unsigned long long s_st[ST_COUNT];
@@ -166,13 +166,14 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
     }
     cnt[i] = kc;
     const bool cl = kc >= 2;
-    const int kind = cl ? class_kind(kc, mfma_min_q, big_q) : -1;
+    const int kind = cl ? class_kind(kc, mfma_min_q, big_q, small_on) : -1;
     const uint64_t tsz = cl ? (uint64_t)kc * (kc - 1) / 2 : 0ull;
     is_cls[i] = cl ? 1u : 0u;
     tri_sz[i] = tsz;
     // 128-wide tile pairs: also an upper bound on a big class's 256-wide tile pairs
     pm[i] = (kind == 0 || kind == 3) ? mfma_pairs(kc) : 0u;
-    pv[i] = kind == 1 ? andpop_pairs(kc) : 0u;
+    // 16-wide block pairs: also an upper bound on a mid-size class's 32-wide ones
+    pv[i] = (kind == 1 || kind == 4) ? andpop_pairs(kc) : 0u;
     pt[i] = kind == 2 ? 1u : 0u;
     if (cl) {
       loc[ST_CAND_M + kind] += tsz;
@@ -247,7 +248,9 @@ __device__ void write_tasks(uint32_t ci, uint32_t q, uint32_t npairs, uint32_t b
 // Word range each kernel covers for a database: MFMA stages need multiples of 16.
 __device__ inline uint32_t wend_of(const DbInfo& d, int kind) {
   const uint64_t W = d.W ? d.W : 1;
-  return (uint32_t)(is_mfma_kind(kind) ? (W + GRAM_KW - 1) / GRAM_KW * GRAM_KW : W);
+  if (is_mfma_kind(kind)) return (uint32_t)((W + GRAM_KW - 1) / GRAM_KW * GRAM_KW);
+  if (kind == 4) return (uint32_t)((W + GRAM_SMALL_KW - 1) / GRAM_SMALL_KW * GRAM_SMALL_KW);
+  return (uint32_t)W;
 }
 
 struct ClassWork {
@@ -258,7 +261,7 @@ struct ClassWork {
 __device__ inline ClassWork class_work(const ClassDesc& cd, const DbInfo& d, uint32_t mfma_min_q,
                                        const TaskGeom& geo) {
   ClassWork w;
-  w.kind = class_kind(cd.q, mfma_min_q, geo.big_q);
+  w.kind = class_kind(cd.q, mfma_min_q, geo.big_q, geo.small_on);
   w.wend = wend_of(d, w.kind);
   if (w.kind == 0) {
     w.npairs = mfma_pairs(cd.q);
@@ -268,6 +271,10 @@ __device__ inline ClassWork class_work(const ClassDesc& cd, const DbInfo& d, uin
     w.npairs = mfma_pairs(cd.q, GRAM_TILE_BIG);
     w.split = geo.split_b;
     w.block = GRAM_TILE_BIG;
+  } else if (w.kind == 4) {
+    w.npairs = andpop_pairs(cd.q, GRAM_SMALL_TILE);
+    w.split = geo.split_s;
+    w.block = GRAM_SMALL_TILE;
   } else if (w.kind == 1) {
     w.npairs = andpop_pairs(cd.q);
     w.split = geo.split_v;
@@ -287,7 +294,7 @@ __global__ void k_class_task_counts(const ClassDesc* __restrict__ cls, uint64_t 
                                     const DbInfo* __restrict__ dbs, uint32_t mfma_min_q,
                                     TaskGeom geo, uint32_t dfs, uint32_t* __restrict__ cm,
                                     uint32_t* __restrict__ cv, uint32_t* __restrict__ ct,
-                                    uint32_t* __restrict__ cb) {
+                                    uint32_t* __restrict__ cb, uint32_t* __restrict__ cs) {
   for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < ncls;
        c += (uint64_t)gridDim.x * blockDim.x) {
     const ClassDesc cd = cls[c];
@@ -297,6 +304,7 @@ __global__ void k_class_task_counts(const ClassDesc* __restrict__ cls, uint64_t 
     cv[c] = w.kind == 1 ? nt : 0u;
     ct[c] = w.kind == 2 ? (dfs ? 1u : nt) : 0u;
     cb[c] = w.kind == 3 ? nt : 0u;
+    cs[c] = w.kind == 4 ? nt : 0u;
   }
 }
 
@@ -309,7 +317,8 @@ __global__ void k_write_class_tasks(const ClassDesc* __restrict__ cls, uint64_t 
                                     Task* __restrict__ tm, Task* __restrict__ tv,
                                     Task* __restrict__ tt, DfsTask* __restrict__ dt,
                                     uint32_t level, const uint64_t* __restrict__ ob,
-                                    Task* __restrict__ tb) {
+                                    Task* __restrict__ tb, const uint64_t* __restrict__ os,
+                                    Task* __restrict__ ts) {
   const int lane = threadIdx.x & 63;
   const uint64_t wave0 = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
@@ -332,7 +341,8 @@ __global__ void k_write_class_tasks(const ClassDesc* __restrict__ cls, uint64_t 
     Task* out = w.kind == 0 ? tm + om[c]
                 : w.kind == 1 ? tv + ov[c]
                 : w.kind == 2 ? tt + ot[c]
-                              : tb + ob[c];
+                : w.kind == 3 ? tb + ob[c]
+                              : ts + os[c];
     write_tasks((uint32_t)c, cd.q, w.npairs, w.block, w.nsplit, w.split, w.wend, out, lane, 64);
   }
 }
@@ -507,12 +517,13 @@ void launch_tri_flags(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs, co
 
 void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const int32_t* pcls,
                         const ClassDesc* cls, const uint64_t* S, uint32_t mfma_min_q, uint32_t big_q,
-                        uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz, uint32_t* pm,
-                        uint32_t* pv, uint32_t* pt, unsigned long long* st, hipStream_t s) {
+                        uint32_t small_on, uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz,
+                        uint32_t* pm, uint32_t* pv, uint32_t* pt, unsigned long long* st,
+                        hipStream_t s) {
   if (n == 0) return;
   k_node_counts<<<grid_for(n, kThreads, 2048), kThreads, 0, s>>>(n, k, parent, pcls, cls, S,
-                                                                  mfma_min_q, big_q, cnt, is_cls,
-                                                                  tri_sz, pm, pv, pt, st);
+                                                                  mfma_min_q, big_q, small_on, cnt,
+                                                                  is_cls, tri_sz, pm, pv, pt, st);
   BM_LAUNCH_CHECK();
 }
 
@@ -528,10 +539,11 @@ void launch_fill_level(uint64_t n, const uint32_t* parent, const int32_t* pcls,
 
 void launch_class_task_counts(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs,
                               uint32_t mfma_min_q, const TaskGeom& geo, bool dfs, uint32_t* cm,
-                              uint32_t* cv, uint32_t* ct, uint32_t* cb, hipStream_t s) {
+                              uint32_t* cv, uint32_t* ct, uint32_t* cb, uint32_t* cs, hipStream_t s) {
   if (ncls == 0) return;
   k_class_task_counts<<<grid_for(ncls, kThreads), kThreads, 0, s>>>(cls, ncls, dbs, mfma_min_q, geo,
-                                                                     dfs ? 1u : 0u, cm, cv, ct, cb);
+                                                                     dfs ? 1u : 0u, cm, cv, ct, cb,
+                                                                     cs);
   BM_LAUNCH_CHECK();
 }
 
@@ -539,10 +551,10 @@ void launch_write_class_tasks(const ClassDesc* cls, uint64_t ncls, const DbInfo*
                               uint32_t mfma_min_q, const TaskGeom& geo, const uint64_t* om,
                               const uint64_t* ov, const uint64_t* ot, Task* tm, Task* tv, Task* tt,
                               DfsTask* dt, uint32_t level, const uint64_t* ob, Task* tb,
-                              hipStream_t s) {
+                              const uint64_t* os, Task* ts, hipStream_t s) {
   if (ncls == 0) return;
   k_write_class_tasks<<<grid_for(ncls * 64, kThreads), kThreads, 0, s>>>(
-      cls, ncls, dbs, mfma_min_q, geo, om, ov, ot, tm, tv, tt, dt, level, ob, tb);
+      cls, ncls, dbs, mfma_min_q, geo, om, ov, ot, tm, tv, tt, dt, level, ob, tb, os, ts);
   BM_LAUNCH_CHECK();
 }
 

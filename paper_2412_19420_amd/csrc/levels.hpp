@@ -14,15 +14,16 @@ struct LevelPtrs {
 
 // Word-range length of one task, per kernel (MFMA splits are multiples of 16 words).
 struct TaskGeom {
-  uint32_t split_m, split_v, split_t, split_b;
-  uint32_t big_q;  // classes with at least this many children (and MFMA-routed) use 256-wide tiles
+  uint32_t split_m, split_v, split_t, split_b, split_s;
+  uint32_t big_q;     // classes with at least this many children (and MFMA-routed) use 256-wide tiles
+  uint32_t small_on;  // mid-size classes use the 32-wide MFMA kernel (else LDS AND+popcount)
 };
 
 // Per-step totals accumulated on the device for statistics.
 // Index = base + kernel type (0 = MFMA 128-wide tiles, 1 = LDS-blocked AND+popcount,
-// 2 = register AND+popcount, 3 = MFMA 256-wide tiles).
-enum { ST_CAND_M = 0, ST_CAND_V, ST_CAND_T, ST_CAND_B, ST_COLS_M, ST_COLS_V, ST_COLS_T, ST_COLS_B,
-       ST_CLS_M, ST_CLS_V, ST_CLS_T, ST_CLS_B, ST_COUNT };
+// 2 = register AND+popcount, 3 = MFMA 256-wide tiles, 4 = MFMA 32-wide tiles).
+enum { ST_CAND_M = 0, ST_CAND_V, ST_CAND_T, ST_CAND_B, ST_CAND_S, ST_COLS_M, ST_COLS_V, ST_COLS_T,
+       ST_COLS_B, ST_COLS_S, ST_CLS_M, ST_CLS_V, ST_CLS_T, ST_CLS_B, ST_CLS_S, ST_COUNT };
 
 void launch_f1_flags(const DbInfo* dbs, uint32_t ndb, const uint64_t* item_base, uint64_t total,
                      uint32_t* flags, hipStream_t s);
@@ -37,7 +38,7 @@ void launch_tri_flags(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs, co
                       uint64_t T, uint32_t uniform_thr, uint32_t* flags, hipStream_t s);
 void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const int32_t* pcls,
                         const ClassDesc* cls, const uint64_t* S, uint32_t mfma_min_q, uint32_t big_q,
-                        uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz, uint32_t* pm,
+                        uint32_t small_on, uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz, uint32_t* pm,
                         uint32_t* pv, uint32_t* pt, unsigned long long* st, hipStream_t s);
 void launch_fill_level(uint64_t n, const uint32_t* parent, const int32_t* pcls,
                        const ClassDesc* cls, const DbInfo* dbs, const uint32_t* child_item,
@@ -45,13 +46,13 @@ void launch_fill_level(uint64_t n, const uint32_t* parent, const int32_t* pcls,
                        uint32_t* nsupp, uint32_t* ndbv, hipStream_t s);
 void launch_class_task_counts(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs,
                               uint32_t mfma_min_q, const TaskGeom& geo, bool dfs, uint32_t* cm,
-                              uint32_t* cv, uint32_t* ct, uint32_t* cb, hipStream_t s);
+                              uint32_t* cv, uint32_t* ct, uint32_t* cb, uint32_t* cs, hipStream_t s);
 struct DfsTask;
 void launch_write_class_tasks(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs,
                               uint32_t mfma_min_q, const TaskGeom& geo, const uint64_t* om,
                               const uint64_t* ov, const uint64_t* ot, Task* tm, Task* tv, Task* tt,
                               DfsTask* dt, uint32_t level, const uint64_t* ob, Task* tb,
-                              hipStream_t s);
+                              const uint64_t* os, Task* ts, hipStream_t s);
 void launch_fill_classes(uint64_t n, uint32_t k, const uint32_t* cnt, const uint64_t* child_start,
                          const uint64_t* cls_pos, const uint64_t* tri_off, const LevelPtrs& lv,
                          const uint32_t* node_db, const DbInfo* dbs, ClassDesc* ocls,
@@ -78,11 +79,15 @@ inline uint32_t host_mfma_pairs(uint32_t q) {
   return nb * (nb + 1) / 2;
 }
 // Kernel that evaluates a class of q children: 0 = MFMA (128-wide tiles),
-// 1 = LDS-blocked AND+popcount, 2 = registers, 3 = MFMA (256-wide tiles).
-__host__ __device__ inline int class_kind(uint32_t q, uint32_t mfma_min_q, uint32_t big_q) {
+// 1 = LDS-blocked AND+popcount, 2 = registers, 3 = MFMA (256-wide tiles),
+// 4 = MFMA (32-wide tiles, one wave per block pair).
+__host__ __device__ inline int class_kind(uint32_t q, uint32_t mfma_min_q, uint32_t big_q,
+                                          uint32_t small_on) {
   if (q >= mfma_min_q) return q >= big_q ? 3 : 0;
-  return q <= (uint32_t)TINY_Q ? 2 : 1;
+  if (q <= (uint32_t)TINY_Q) return 2;
+  return small_on ? 4 : 1;
 }
+// Kinds whose task word ranges are rounded to GRAM_KW (LDS-staged MFMA kernels).
 __host__ __device__ inline bool is_mfma_kind(int kind) { return kind == 0 || kind == 3; }
 inline uint32_t host_andpop_pairs(uint32_t q) {
   const uint32_t nb = (q + AP_BLOCK - 1) / AP_BLOCK;

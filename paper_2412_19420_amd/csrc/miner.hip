@@ -119,9 +119,9 @@ TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_v, uint64_t c
   const uint64_t target = (uint64_t)cu_count() * 8;
   const uint64_t W = std::max<uint64_t>(1, Wmax);
   TaskGeom g{};
-  auto pick = [&](uint64_t units, uint64_t min_len, uint64_t align) {
+  auto pick = [&](uint64_t units, uint64_t min_len, uint64_t align, uint64_t per_wg = 1) {
     if (tu.split_words) return round_up(tu.split_words, align);
-    uint64_t ns = units ? ceil_div(target, units) : 1;
+    uint64_t ns = units ? ceil_div(target * per_wg, units) : 1;
     ns = std::min<uint64_t>(ns, std::max<uint64_t>(1, W / min_len));
     return round_up(ceil_div(W, ns), align);
   };
@@ -130,10 +130,15 @@ TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_v, uint64_t c
   g.split_t = (uint32_t)pick(classes_t, 2048, 64);
   // a 256-wide tile holds about four 128-wide tiles: split its words further
   g.split_b = (uint32_t)pick((pairs_m + 3) / 4, 256, GRAM_KW);
+  // 32-wide block pairs number about a quarter of the 16-wide ones, and each
+  // is one wave's task: four per workgroup
+  g.split_s = (uint32_t)pick((pairs_v + 3) / 4, 128, GRAM_SMALL_KW, 4);
   g.big_q = tu.mfma_big_q;
+  g.small_on = tu.mfma_small ? 1u : 0u;
   if (tu.mfma_fp4) {  // keep every MFMA task's counts below 2^24
     g.split_m = std::min<uint32_t>(g.split_m, GRAM_FP4_MAX_WORDS);
     g.split_b = std::min<uint32_t>(g.split_b, GRAM_FP4_MAX_WORDS);
+    g.split_s = std::min<uint32_t>(g.split_s, GRAM_FP4_MAX_WORDS);
   }
   return g;
 }
@@ -143,9 +148,9 @@ struct StepWork {
   uint64_t ncls = 0;
   TBuf<ClassDesc> cls;
   TBuf<uint32_t> pre;
-  TBuf<Task> tm, tv, tt, tb;
-  uint64_t ub_m = 0, ub_v = 0, ub_t = 0, ub_b = 0;  // task-count upper bounds (host)
-  TBuf<uint64_t> om, ov, ot, ob;                    // task offsets per class (+ total at [ncls])
+  TBuf<Task> tm, tv, tt, tb, ts;
+  uint64_t ub_m = 0, ub_v = 0, ub_t = 0, ub_b = 0, ub_s = 0;  // task-count upper bounds (host)
+  TBuf<uint64_t> om, ov, ot, ob, os;  // task offsets per class (+ total at [ncls])
   TBuf<uint32_t> tri;
   uint64_t T = 0;
   uint64_t st[ST_COUNT] = {};
@@ -163,30 +168,35 @@ void prepare_tasks(StepWork& w, const DbInfo* ddb, uint64_t Wmax, uint64_t pairs
   const uint64_t Wm = round_up(std::max<uint64_t>(1, Wmax), GRAM_KW);
   w.ub_m = pairs_m * ceil_div(Wm, g.split_m);
   w.ub_b = g.big_q < 0xffffffffu ? pairs_m * ceil_div(Wm, g.split_b) : 0;
-  w.ub_v = pairs_v * ceil_div(std::max<uint64_t>(1, Wmax), g.split_v);
+  w.ub_v = tu.mfma_small ? 0 : pairs_v * ceil_div(std::max<uint64_t>(1, Wmax), g.split_v);
+  w.ub_s = tu.mfma_small ? pairs_v * ceil_div(round_up(std::max<uint64_t>(1, Wmax), GRAM_SMALL_KW),
+                                              g.split_s)
+                         : 0;
   w.ub_t = dfs ? 0 : classes_t * ceil_div(std::max<uint64_t>(1, Wmax), g.split_t);
   if (dfs) {
     w.ndt = classes_t;
     w.dt.alloc(classes_t, s);
   }
-  TBuf<uint32_t> cm(w.ncls, s), cv(w.ncls, s), ct(w.ncls, s), cb(w.ncls, s);
+  TBuf<uint32_t> cm(w.ncls, s), cv(w.ncls, s), ct(w.ncls, s), cb(w.ncls, s), cs(w.ncls, s);
   w.om.alloc(w.ncls + 1, s);
   w.ov.alloc(w.ncls + 1, s);
   w.ot.alloc(w.ncls + 1, s);
   w.ob.alloc(w.ncls + 1, s);
+  w.os.alloc(w.ncls + 1, s);
   launch_class_task_counts(w.cls.get(), w.ncls, ddb, tu.mfma_min_q, g, dfs, cm.get(), cv.get(),
-                           ct.get(), cb.get(), s);
-  const void* in[4] = {cm.get(), cv.get(), ct.get(), cb.get()};
-  const bool is64[4] = {false, false, false, false};
-  uint64_t* out[4] = {w.om.get(), w.ov.get(), w.ot.get(), w.ob.get()};
-  scan_many(in, is64, out, 4, w.ncls, s);
+                           ct.get(), cb.get(), cs.get(), s);
+  const void* in[5] = {cm.get(), cv.get(), ct.get(), cb.get(), cs.get()};
+  const bool is64[5] = {false, false, false, false, false};
+  uint64_t* out[5] = {w.om.get(), w.ov.get(), w.ot.get(), w.ob.get(), w.os.get()};
+  scan_many(in, is64, out, 5, w.ncls, s);
   w.tm.alloc(w.ub_m, s);
   w.tv.alloc(w.ub_v, s);
   w.tt.alloc(w.ub_t, s);
   w.tb.alloc(w.ub_b, s);
+  w.ts.alloc(w.ub_s, s);
   launch_write_class_tasks(w.cls.get(), w.ncls, ddb, tu.mfma_min_q, g, w.om.get(), w.ov.get(),
                            w.ot.get(), w.tm.get(), w.tv.get(), w.tt.get(), dfs ? w.dt.get() : nullptr,
-                           level, w.ob.get(), w.tb.get(), s);
+                           level, w.ob.get(), w.tb.get(), w.os.get(), w.ts.get(), s);
 }
 
 void run_class_kernels(const DbInfo* ddb, const uint32_t* child_item, const StepWork& w,
@@ -207,7 +217,14 @@ void run_class_kernels(const DbInfo* ddb, const uint32_t* child_item, const Step
     launch_gram_mfma(a, (uint32_t)std::min<uint64_t>(w.ub_m, ncu * 4), tu.mfma_fp4, s);
     tm.end(8.0 * nW * (double)w.st[ST_COLS_M], 2.0 * (double)w.st[ST_CAND_M] * nN);
   }
-  if (w.ub_v) {
+  if (w.ub_s && w.st[ST_CLS_S]) {
+    a.tasks = w.ts.get();
+    a.ntasks = w.os.get() + w.ncls;
+    tm.begin(BM_K_GRAM_SMALL);
+    launch_gram_small(a, (uint32_t)std::min<uint64_t>((w.ub_s + 3) / 4, ncu * 8), tu.mfma_fp4, s);
+    tm.end(8.0 * nW * (double)w.st[ST_COLS_S], 2.0 * (double)w.st[ST_CAND_S] * nN);
+  }
+  if (w.ub_v && w.st[ST_CLS_V]) {
     a.tasks = w.tv.get();
     a.ntasks = w.ov.get() + w.ncls;
     tm.begin(BM_K_ANDPOP);
@@ -237,9 +254,9 @@ void host_classes(StepWork& w, const std::vector<ClassDesc>& hc, const DbInfo* d
   for (const auto& c : hc) {
     const uint64_t tsz = (uint64_t)c.q * (c.q - 1) / 2;
     w.T += tsz;
-    const int kind = class_kind(c.q, tu.mfma_min_q, tu.mfma_big_q);
+    const int kind = class_kind(c.q, tu.mfma_min_q, tu.mfma_big_q, tu.mfma_small ? 1u : 0u);
     if (is_mfma_kind(kind)) pm += host_mfma_pairs(c.q);
-    else if (kind == 1) pv += host_andpop_pairs(c.q);
+    else if (kind == 1 || kind == 4) pv += host_andpop_pairs(c.q);
     else ct += 1;
     w.st[ST_CAND_M + kind] += tsz;
     w.st[ST_COLS_M + kind] += c.q;
@@ -285,7 +302,10 @@ Tuning tuning_from(const bm_options* opt) {
   if (opt->flags & BM_FLAG_LEVELSYNC) t.dfs = false;
   if (opt->flags & BM_FLAG_FP4_MFMA) t.mfma_fp4 = true;
   if (opt->flags & BM_FLAG_INT8_MFMA) t.mfma_fp4 = false;
-  if (opt->flags & BM_FLAG_NO_MFMA) t.mfma_min_q = 0xffffffffu;
+  if (opt->flags & BM_FLAG_NO_MFMA) {
+    t.mfma_min_q = 0xffffffffu;
+    t.mfma_small = false;
+  }
   if (opt->flags & BM_FLAG_ALL_MFMA) t.mfma_min_q = 2;
   return t;
 }
@@ -633,7 +653,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         st.candidates_total += ls_cand;
         if (w->ndt) parts.push_back({w->dt.get(), w->ndt});
         step_pre[k] = w->pre.get();
-        st.classes_mfma += w->st[ST_CLS_M] + w->st[ST_CLS_B];
+        st.classes_mfma += w->st[ST_CLS_M] + w->st[ST_CLS_B] + w->st[ST_CLS_S];
         st.classes_andpop += w->st[ST_CLS_V] + w->st[ST_CLS_T];
         run_class_kernels(ddb.get(), L[k].item.get(), *w, tu, nW, nN, tm, s);
 
@@ -648,7 +668,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         TBuf<unsigned long long> dst(ST_COUNT, s);
         launch_fill_u64(reinterpret_cast<uint64_t*>(dst.get()), 0, ST_COUNT, s);
         launch_node_counts(nk, k, L[k].parent.get(), pcls_prev.get(), w->cls.get(), S.get(),
-                           tu.mfma_min_q, tu.mfma_big_q, cnt.get(), iscls.get(), trisz.get(), pm.get(), pv.get(),
+                           tu.mfma_min_q, tu.mfma_big_q, tu.mfma_small ? 1u : 0u, cnt.get(), iscls.get(), trisz.get(), pm.get(), pv.get(),
                            pt.get(), dst.get(), s);
         L[k].cstart.alloc(nk + 1, s);
         TBuf<uint64_t> clspos(nk + 1, s), trioff(nk + 1, s), pmoff(nk + 1, s), pvoff(nk + 1, s),

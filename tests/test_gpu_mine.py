@@ -394,6 +394,20 @@ def test_mine_quest_mfma_routings_exact(bm, big, form):
     assert_same(r.arrays(), want)
 
 
+@pytest.mark.parametrize("form", ["int8", "fp4"])
+@pytest.mark.parametrize("min_children", [9, 33, 0xFFFFFFFF])
+def test_mine_quest_small_mfma_routings_exact(bm, min_children, form):
+    # classes of 9 .. min_children - 1 children on the 32-wide one-wave MFMA
+    # kernel (0xFFFFFFFF: every class with more than 8 children, the root included)
+    db = gen.make_config(2)
+    print(f"quest small-MFMA routing min={min_children} form={form}", flush=True)
+    flag = bm.FLAG_FP4_MFMA if form == "fp4" else bm.FLAG_INT8_MFMA
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    r = bm.bm_mine_ex(h, db.minsup, bm.options(flag, mfma_min_children=min_children))
+    _, want, _ = oracle_arrays(db, db.minsup)
+    assert_same(r.arrays(), want)
+
+
 def test_fp4_mfma_counts_beyond_fp32_quarter_range(bm):
     # item 0 in every row, item 1 in 63 of every 64: each 64-transaction MFMA step
     # adds 15.75 (63 quarters), so one FP32 accumulator over all 20M rows would
