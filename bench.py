@@ -152,6 +152,15 @@ def _roofline(kernels, ms, form):
     return None
 
 
+def _makespan(costs, order, workers):
+    """Greedy list scheduling, as the persistent queue assigns tasks."""
+    import heapq
+    heap = [0.0] * workers
+    for t in order:
+        heapq.heapreplace(heap, heap[0] + costs[t])
+    return float(max(heap))
+
+
 def run_batched(args, bm, torch, dev):
     """The batched workload: 256 databases per step, mined four ways on the same
     device-resident inputs -- one plain level-synchronous call per database
@@ -203,6 +212,22 @@ def run_batched(args, bm, torch, dev):
         "batched_learned": (build_batch, lambda hs: bm.bm_mine_batch(hs, ms_list, model=model,
                                                                      opts=o_dfs, stream=stream)),
     }
+    # what the learned order buys, independent of timing noise: the realised
+    # subtree costs of this batch's depth-first queue list-scheduled over the
+    # kernel's workgroups in plain and in learned order (untimed)
+    hs = build_batch(dbs, dev_in)
+    f, y = bm.bm_mine_batch(hs, ms_list, opts=bm.options(bm.FLAG_TRACE), stream=stream)[0].trace()
+    cost = np.exp2(y.astype(np.float64)) - 1
+    pred = model.predict(f, stream=stream).astype(np.float64)
+    workers = torch.cuda.get_device_properties(0).multi_processor_count * 8
+    sched_sim = {
+        "tasks": int(len(cost)), "workers": workers,
+        "plain_makespan_words": _makespan(cost, range(len(cost)), workers),
+        "learned_makespan_words": _makespan(cost, np.argsort(-pred, kind="stable"), workers),
+        "true_cost_lpt_makespan_words": _makespan(cost, np.argsort(-cost, kind="stable"), workers),
+    }
+    del hs
+
     # identical output in every mode (checked once, untimed)
     ref = [r.arrays() for r in modes["plain_per_db"][1](build_each(dbs, dev_in))]
     for name in list(modes)[1:]:
@@ -261,6 +286,7 @@ def run_batched(args, bm, torch, dev):
                                                      best["ms_per_step"], 3),
                    "learned_vs_batched_depth_first": round(res["batched_depth_first"]["mine_ms"] /
                                                            best["mine_ms"], 3),
+                   "queue_makespan_simulation": sched_sim,
                    "kernels": kernels},
         "roofline": _roofline(kernels, kms, st["mfma_form"]) if kernels else None,
     }

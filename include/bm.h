@@ -71,7 +71,8 @@ enum {
   BM_K_DFS = 7,       /* persistent depth-first subtree kernel (small classes) */
   BM_K_SCHED = 8,     /* cost-model features, prediction and task ordering */
   BM_K_GRAM_MFMA_BIG = 9, /* as BM_K_GRAM_MFMA with 256 x 256 tiles (classes of >= 256 children) */
-  BM_K_COUNT = 10
+  BM_K_GRAM_SMALL = 10,   /* MFMA Gram of mid-size classes, one wave per 32 x 32 block pair */
+  BM_K_COUNT = 11
 };
 
 /* Statistics of one mining call.  Kernel times are filled only when the call
@@ -101,7 +102,7 @@ typedef struct {
  * take the library default (or the autotuned value, see bm_autotune).  No option
  * changes the mined result. */
 #define BM_FLAG_TIMING 1u      /* record per-kernel hipEvent times into bm_stats */
-#define BM_FLAG_NO_MFMA 2u     /* send every class to the AND+popcount kernel */
+#define BM_FLAG_NO_MFMA 2u     /* send every class to the AND+popcount kernels (no MFMA) */
 #define BM_FLAG_ALL_MFMA 4u    /* send every class with >= 2 children to the MFMA kernel */
 #define BM_FLAG_GRAPH 8u       /* bm_model_train_ex: replay each training epoch as a hipGraph */
 #define BM_FLAG_TRACE 16u      /* keep per-class features and subtree costs (bm_result_trace) */
@@ -111,10 +112,12 @@ typedef struct {
                                 * as 0 / 0.5, FP32 sums, exact for counts < 2^24 per task (word
                                 * splits are capped to guarantee it) */
 #define BM_FLAG_INT8_MFMA 256u /* Gram kernels on int8 x int8 -> int32 MFMA (overrides FP4) */
+#define BM_FLAG_DFS_BLOCK_ONLY 512u /* every subtree task on the one-stack-per-workgroup kernel */
 
 typedef struct {
   uint32_t flags;
-  uint32_t mfma_min_children; /* classes with at least this many children use MFMA (default tuned) */
+  uint32_t mfma_min_children; /* classes with at least this many children use 128-wide MFMA tiles,
+                               * smaller ones (over 8 children) 32-wide MFMA tiles (default 64) */
   uint32_t andpop_chunk_words;/* AND+popcount LDS chunk: 128 or 256 words */
   uint32_t split_words;       /* word-range length of one task (multiple of 64; 0 = automatic) */
   uint32_t shuffle_seed;      /* with BM_FLAG_SHUFFLE */
@@ -123,7 +126,10 @@ typedef struct {
                                * 64-bit words per column (0 = default; 0xffffffff = always) */
   uint32_t mfma_big_children; /* MFMA classes with at least this many children use 256-wide
                                * tiles (0 = default: never) */
-  uint32_t reserved[4];
+  uint32_t dfs_wave_max_words;/* subtree tasks of databases with at most this many words per
+                               * column run one stack per wave, the others one per workgroup
+                               * (0 = default 1024; see BM_FLAG_DFS_BLOCK_ONLY) */
+  uint32_t reserved[3];
 } bm_options;
 
 uint32_t bm_abi_version(void);
@@ -233,14 +239,15 @@ bm_status bm_result_stats(const bm_result* r, bm_stats* out);
  * the task's prefix class (itemset length of its children, log2 support of the
  * prefix, log2(1 + children), mean log2 child support, max and mean child /
  * prefix support ratio, log2 minsup, log2 words per column) and the label
- * log2(1 + candidate supports evaluated in the task's subtree), which is
- * deterministic.  feats: host float[rows*8] or NULL; labels: host float[rows]
+ * log2(1 + 64-bit column words the depth-first kernel streams for the task's
+ * whole subtree: prefix and child columns of every class it evaluates), which
+ * is deterministic and proportional to the task's run time.  feats: host float[rows*8] or NULL; labels: host float[rows]
  * or NULL; *rows receives the row count (0 without a trace). */
 bm_status bm_result_trace(const bm_result* r, float* feats, float* labels, uint64_t* rows);
 
 /* Scheduler cost model: an 8 -> 64 -> 64 -> 1 perceptron with ReLU, BF16
- * weights and FP32 accumulation, predicting log2(1 + subtree candidates) of a
- * subtree task from its 8 trace features.  Passed to bm_mine_batch it only
+ * weights and FP32 accumulation, predicting the trace label (log2 of the
+ * subtree's streamed column words) of a subtree task from its 8 features.  Passed to bm_mine_batch it only
  * orders the depth-first work queue (longest predicted first); results are
  * identical with and without it.  Training runs on the device (forward,
  * backward and Adam kernels on an FP32 master copy); inputs are standardised

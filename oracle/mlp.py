@@ -106,5 +106,6 @@ def adam(master, m, v, g, lr, step, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def label(cost):
-    """Training target of a subtree task: log2(1 + candidates it evaluated)."""
+    """Training target of a subtree task: log2(1 + its cost), the cost being the
+    64-bit column words the depth-first evaluation of its subtree streams."""
     return np.log2(1.0 + np.asarray(cost, dtype=np.float64))

@@ -20,7 +20,8 @@ import os
 import numpy as np
 
 from . import _bm
-from ._bm import (BM_K_NAMES, FLAG_ALL_MFMA, FLAG_FP4_MFMA, FLAG_GRAPH, FLAG_INT8_MFMA,
+from ._bm import (BM_K_NAMES, FLAG_ALL_MFMA, FLAG_DFS_BLOCK_ONLY, FLAG_FP4_MFMA, FLAG_GRAPH,
+                  FLAG_INT8_MFMA,
                   FLAG_LEVELSYNC, FLAG_NO_MFMA,
                   FLAG_SHUFFLE, FLAG_TIMING, FLAG_TRACE, MLP_PARAMS, BmError, BmOptions)
 
@@ -28,7 +29,8 @@ __all__ = [
     "bm_abi_version", "bm_build", "bm_build_batch", "bm_item_support", "bm_pair_support", "bm_mine",
     "bm_mine_ex", "bm_mine_batch", "bm_set_allocator", "bm_release_cached_memory", "Db", "Result", "BmError",
     "options", "FLAG_TIMING", "FLAG_NO_MFMA", "FLAG_ALL_MFMA", "FLAG_GRAPH", "FLAG_TRACE",
-    "FLAG_SHUFFLE", "FLAG_LEVELSYNC", "FLAG_FP4_MFMA", "FLAG_INT8_MFMA", "LIB_PATH", "Model", "MLP_PARAMS", "bm_autotune",
+    "FLAG_SHUFFLE", "FLAG_LEVELSYNC", "FLAG_FP4_MFMA", "FLAG_INT8_MFMA", "FLAG_DFS_BLOCK_ONLY",
+    "LIB_PATH", "Model", "MLP_PARAMS", "bm_autotune",
     "autotune_cached", "options_to_dict", "options_from_dict", "shape_key",
 ]
 
@@ -165,7 +167,8 @@ class Result:
 
 def options(flags: int = 0, mfma_min_children: int = 0, andpop_chunk_words: int = 0,
             split_words: int = 0, shuffle_seed: int = 0, dfs_threads: int = 0,
-            dfs_max_words: int = 0, mfma_big_children: int = 0) -> BmOptions:
+            dfs_max_words: int = 0, mfma_big_children: int = 0,
+            dfs_wave_max_words: int = 0) -> BmOptions:
     o = BmOptions()
     o.flags = flags
     o.mfma_min_children = mfma_min_children
@@ -175,6 +178,7 @@ def options(flags: int = 0, mfma_min_children: int = 0, andpop_chunk_words: int 
     o.dfs_threads = dfs_threads
     o.dfs_max_words = dfs_max_words
     o.mfma_big_children = mfma_big_children
+    o.dfs_wave_max_words = dfs_wave_max_words
     return o
 
 
@@ -296,7 +300,7 @@ def bm_autotune(dbs, minsups, model=None, base: BmOptions | None = None, reps: i
 
 
 _TUNE_FIELDS = ("flags", "mfma_min_children", "andpop_chunk_words", "split_words", "dfs_threads",
-                "dfs_max_words", "mfma_big_children")
+                "dfs_max_words", "mfma_big_children", "dfs_wave_max_words")
 
 
 def options_to_dict(o: BmOptions) -> dict:

@@ -35,6 +35,7 @@ FLAG_SHUFFLE = 32
 FLAG_LEVELSYNC = 64
 FLAG_FP4_MFMA = 128
 FLAG_INT8_MFMA = 256
+FLAG_DFS_BLOCK_ONLY = 512
 MLP_PARAMS = 4801
 
 STATUS = {0: "BM_OK", 1: "BM_ERR_INVALID_ARG", 2: "BM_ERR_CSR", 3: "BM_ERR_OOM",
@@ -72,7 +73,8 @@ class BmOptions(ctypes.Structure):
         ("dfs_threads", ctypes.c_uint32),
         ("dfs_max_words", ctypes.c_uint32),
         ("mfma_big_children", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 4),
+        ("dfs_wave_max_words", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 3),
     ]
 
 

@@ -6,7 +6,8 @@
 //   * the MFMA routing thresholds (children per class, for 128- and 256-wide tiles),
 //   * the word-range length of one task (automatic or fixed),
 //   * the AND+popcount LDS chunk,
-//   * the depth-first workgroup size,
+//   * the depth-first workgroup size and the column length below which a
+//     subtree task runs one stack per wave,
 // keeping each field's fastest value before moving to the next.  Each point
 // is the minimum wall time of `reps` calls.
 #include <algorithm>
@@ -72,8 +73,19 @@ bm_options autotune(const bm_db* const* dbs, const uint32_t* minsups, uint32_t c
   try_field([](bm_options& o, uint32_t v) { o.mfma_big_children = v; }, {192u, 256u, 512u, 0xffffffffu});
   try_field([](bm_options& o, uint32_t v) { o.split_words = v; }, {0u, 512u, 1024u, 2048u, 4096u});
   try_field([](bm_options& o, uint32_t v) { o.andpop_chunk_words = v; }, {128u, 256u});
-  if (!(cur.flags & BM_FLAG_LEVELSYNC))
+  if (!(cur.flags & BM_FLAG_LEVELSYNC)) {
     try_field([](bm_options& o, uint32_t v) { o.dfs_threads = v; }, {256u, 512u, 1024u});
+    try_field(
+        [](bm_options& o, uint32_t v) {
+          if (v == 0) {
+            o.flags |= BM_FLAG_DFS_BLOCK_ONLY;
+          } else {
+            o.flags &= ~BM_FLAG_DFS_BLOCK_ONLY;
+            o.dfs_wave_max_words = v;
+          }
+        },
+        {0u, 256u, 1024u, 4096u});
+  }
   if (best_ms) *best_ms = best;
   return cur;
 }

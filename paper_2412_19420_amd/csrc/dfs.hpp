@@ -32,7 +32,8 @@ struct DfsArgs {
   const DbInfo* dbs;
   const DfsTask* tasks;
   uint32_t ntasks;
-  const uint32_t* order;  // queue order (nullptr: task order)
+  const uint32_t* ntasks_dev;  // if set, the queue length is read from device memory
+  const uint32_t* order;       // queue order (nullptr: task order)
   uint32_t* queue_head;
   const uint32_t* lv_item[BM_MAX_LEVELS + 2];
   const uint32_t* step_pre[BM_MAX_LEVELS + 2];
@@ -44,7 +45,7 @@ struct DfsArgs {
   uint32_t* flags;
   unsigned long long* level_cand;  // [BM_MAX_LEVELS + 1] candidates by itemset length
   unsigned long long* level_freq;  // [BM_MAX_LEVELS + 1] frequent itemsets by length
-  float* task_cost;                // candidates evaluated in each task's subtree (or nullptr)
+  float* task_cost;                // column words streamed in each task's subtree (or nullptr)
   unsigned long long* words_read;  // column words streamed (prefix + children), for the roofline
 };
 
@@ -63,6 +64,17 @@ enum : uint32_t { SRC_NONE = 0u, SRC_LS = 1u, SRC_ARENA = 2u };
 
 // threads: 256, 512 or 1024 per workgroup
 void launch_dfs(const DfsArgs& a, uint32_t threads, uint32_t grid, hipStream_t s);
+// One subtree stack per wave (four waves per workgroup): for databases with
+// short columns, where a whole workgroup per class would mostly wait.
+void launch_dfs_wave(const DfsArgs& a, uint32_t grid, hipStream_t s);
+// flags[t] = 1 if queue entry t (order[t], or t) belongs to a database with at
+// most max_words words per column.
+void launch_dfs_short_flags(const DfsTask* tasks, const DbInfo* dbs, const uint32_t* order,
+                            uint32_t n, uint32_t max_words, uint32_t* flags, hipStream_t s);
+// Stable split of the queue by flags (pos = exclusive scan of flags, n + 1):
+// short[] gets the flagged entries, long_[] the others, counts[0..1] their sizes.
+void launch_dfs_split(const uint32_t* order, uint32_t n, const uint32_t* flags, const uint64_t* pos,
+                      uint32_t* short_, uint32_t* long_, uint32_t* counts, hipStream_t s);
 void launch_dfs_features(const FeatArgs& a, hipStream_t s);
 // order[0..n) = tasks sorted by descending key (bucketed, ties in arbitrary order)
 void launch_order_by_key(const float* key, uint32_t n, uint32_t* hist, uint64_t* hist_off,

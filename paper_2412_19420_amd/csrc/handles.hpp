@@ -70,6 +70,8 @@ struct Tuning {
   bool mfma_fp4 = true;         // MFMA kernels in the e2m1 form (else int8)
   uint32_t dfs_threads = 256;   // threads per depth-first workgroup
   uint32_t dfs_max_words = 4096;  // depth-first only when every column has <= this many words
+  uint32_t dfs_wave_words = 1024;  // tasks of databases with <= this many words: one stack per wave
+                                   // (0: every task on the one-stack-per-workgroup kernel)
 };
 Tuning tuning_from(const bm_options* opt);
 

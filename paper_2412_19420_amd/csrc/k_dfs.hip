@@ -59,6 +59,56 @@ __device__ inline uint32_t lane_scan(uint32_t x, int lane) {
   return x;
 }
 
+// Per-worker bookkeeping kept in LDS and written by one lane only: level
+// statistics are summed locally and flushed once at exit, and arena space is
+// reserved ARENA_CHUNK nodes at a time, so the classes of a subtree touch no
+// device-wide counter (about a hundred thousand classes would otherwise
+// serialise on a handful of addresses).
+constexpr uint32_t ARENA_CHUNK = 256;
+
+struct WorkerStats {
+  unsigned long long cand[BM_MAX_LEVELS + 1];
+  unsigned long long freq[BM_MAX_LEVELS + 1];
+  unsigned long long words;
+  uint32_t next, end;  // free arena range reserved by this worker
+};
+
+__device__ inline void ws_init(WorkerStats& w, int lane, int nl) {
+  for (int j = lane; j <= BM_MAX_LEVELS; j += nl) {
+    w.cand[j] = 0;
+    w.freq[j] = 0;
+  }
+  if (lane == 0) {
+    w.words = 0;
+    w.next = 0;
+    w.end = 0;
+  }
+}
+
+__device__ inline void ws_flush(const WorkerStats& w, const DfsArgs& a, int lane, int nl) {
+  for (int j = lane; j <= BM_MAX_LEVELS; j += nl) {
+    if (w.cand[j]) atomicAdd(&a.level_cand[j], w.cand[j]);
+    if (w.freq[j]) atomicAdd(&a.level_freq[j], w.freq[j]);
+  }
+  if (lane == 0 && w.words) atomicAdd(a.words_read, w.words);
+}
+
+// Arena block of `total` nodes for one class, from the worker's reserved range
+// (a new range when it runs out).  false: the arena is full (the call retries
+// with a bigger one; the reservation counter tells the host how big).
+__device__ inline bool ws_alloc(WorkerStats& w, const DfsArgs& a, uint32_t total, uint32_t* base) {
+  if (w.next + total > w.end) {
+    const uint32_t want = total > ARENA_CHUNK ? total : ARENA_CHUNK;
+    const uint32_t b = atomicAdd(a.arena_count, want);
+    if (b + want > a.arena_cap) return false;
+    w.next = b;
+    w.end = b + want;
+  }
+  *base = w.next;
+  w.next += total;
+  return true;
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_dfs(DfsArgs a) {
   constexpr int NW = NT / 64;
@@ -68,25 +118,27 @@ __global__ __launch_bounds__(NT) void k_dfs(DfsArgs a) {
   __shared__ uint32_t s_task;
   __shared__ uint32_t s_red[NW][TNP];
   __shared__ uint32_t s_cnt[TNP];
-  __shared__ unsigned long long s_task_cand;
+  __shared__ unsigned long long s_task_cost;  // column words streamed by the current task
   __shared__ int s_done;
+  __shared__ WorkerStats s_ws;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) {
     s_sp = 0;
     s_done = 0;
   }
+  ws_init(s_ws, tid, NT);
   __syncthreads();
   for (;;) {
     // ---- next class: from the stack, else a new task from the queue
     if (tid == 0) {
       if (s_sp == 0) {
         const uint32_t t = atomicAdd(a.queue_head, 1u);
-        if (t >= a.ntasks) {
+        if (t >= (a.ntasks_dev ? *a.ntasks_dev : a.ntasks)) {
           s_done = 1;
         } else {
           const uint32_t ti = a.order ? a.order[t] : t;
           s_task = ti;
-          s_task_cand = 0;
+          s_task_cost = 0;
           const DfsTask tk = a.tasks[ti];
           Entry& e = s_stack[0];
           e.pre_len = tk.pre_len;
@@ -109,7 +161,10 @@ __global__ __launch_bounds__(NT) void k_dfs(DfsArgs a) {
       }
     }
     __syncthreads();
-    if (s_done) break;
+    if (s_done) {
+      ws_flush(s_ws, a, tid, NT);
+      break;
+    }
 
     // ---- evaluate every child pair of the class over all words
     const Entry& c = s_cur;
@@ -181,16 +236,19 @@ __global__ __launch_bounds__(NT) void k_dfs(DfsArgs a) {
       uint32_t base = 0, ok = total > 0 ? 1u : 0u;
       if (lane == 0) {
         const uint64_t ncand = (uint64_t)q * (q - 1) / 2;
-        s_task_cand += ncand;
-        if (len <= BM_MAX_LEVELS) atomicAdd(&a.level_cand[len], (unsigned long long)ncand);
-        atomicAdd(a.words_read, (unsigned long long)(c.pre_len + q) * db.W);
+        const unsigned long long words = (unsigned long long)(c.pre_len + q) * db.W;
+        s_task_cost += words;
+        if (len <= BM_MAX_LEVELS) s_ws.cand[len] += ncand;
+        s_ws.words += words;
         if (total) {
-          base = atomicAdd(a.arena_count, total);
-          if (base + total > a.arena_cap || len > BM_MAX_LEVELS) {
-            atomicOr(a.flags, base + total > a.arena_cap ? DFS_OVERFLOW : DFS_TOO_LONG);
+          if (len > BM_MAX_LEVELS) {
+            atomicOr(a.flags, DFS_TOO_LONG);
+            ok = 0;
+          } else if (!ws_alloc(s_ws, a, total, &base)) {
+            atomicOr(a.flags, DFS_OVERFLOW);
             ok = 0;
           } else {
-            atomicAdd(&a.level_freq[len], (unsigned long long)total);
+            s_ws.freq[len] += total;
           }
         }
       }
@@ -250,10 +308,235 @@ __global__ __launch_bounds__(NT) void k_dfs(DfsArgs a) {
       if (lane == 0) {
         const int sp = min(sp0 + (int)npush, SCAP);
         s_sp = sp;
-        if (sp == 0 && a.task_cost) a.task_cost[s_task] = (float)s_task_cand;
+        if (sp == 0 && a.task_cost) a.task_cost[s_task] = (float)s_task_cost;
       }
     }
     __syncthreads();
+  }
+}
+
+// Orders one wave's LDS writes before its own later reads (and reads before
+// later writes): a wave's LDS operations are performed in issue order, and the
+// fence keeps the compiler from moving them across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+constexpr int WSCAP = 24;  // stack entries per wave: <= 6 + 5 + ... + 1 pending classes
+
+// Depth-first subtrees with one stack per wave.  The class evaluation is the
+// workgroup kernel's, shrunk to a wave: 64 lanes stream two words each per
+// step, the 28 pair counts are reduced by a transposing butterfly (lane 2p
+// ends up with pair p after 32 shuffles), and lane i records child i.  No
+// workgroup barrier is ever taken, so four waves per workgroup mine four
+// subtrees independently.
+__global__ __launch_bounds__(256, 4) void k_dfs_wave(DfsArgs a) {
+  __shared__ Entry s_stack[4][WSCAP];
+  __shared__ uint32_t s_pre[4][BM_MAX_LEVELS];
+  __shared__ WorkerStats s_ws[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  Entry* stk = s_stack[wv];
+  uint32_t* cpre = s_pre[wv];
+  WorkerStats& ws = s_ws[wv];
+  ws_init(ws, lane, 64);
+  wave_lds_sync();
+  const uint32_t ntasks = a.ntasks_dev ? *a.ntasks_dev : a.ntasks;
+  int sp = 0;                    // wave-uniform
+  uint32_t task = 0;
+  unsigned long long tcost = 0;  // column words streamed by the current task
+  for (;;) {
+    uint32_t pre_len, q, ls_level, dbi, my_item = 0, my_node = 0;
+    if (sp == 0) {
+      uint32_t t = 0;
+      if (lane == 0) t = atomicAdd(a.queue_head, 1u);
+      t = __shfl(t, 0);
+      if (t >= ntasks) {
+        wave_lds_sync();
+        ws_flush(ws, a, lane, 64);
+        break;
+      }
+      task = a.order ? a.order[t] : t;
+      tcost = 0;
+      const DfsTask tk = a.tasks[task];
+      pre_len = tk.pre_len;
+      q = tk.q;
+      ls_level = tk.level;
+      dbi = tk.db;
+      if (lane < (int)q) {
+        my_item = a.lv_item[tk.level][tk.child0 + lane];
+        my_node = tk.child0 + lane;
+      }
+      const uint32_t* pre = a.step_pre[tk.level] + tk.pre_off;
+      if (lane < (int)pre_len) cpre[lane] = pre[lane];
+    } else {
+      sp -= 1;
+      const Entry& e = stk[sp];
+      pre_len = e.pre_len;
+      q = e.q;
+      ls_level = e.ls_level;
+      dbi = e.db;
+      if (lane < TQ) {
+        my_item = e.item[lane];
+        my_node = e.node[lane];
+      }
+      wave_lds_sync();  // every lane has read the entry before cpre is rewritten
+      if (lane < (int)pre_len) cpre[lane] = e.pre[lane];
+    }
+    wave_lds_sync();
+
+    // ---- evaluate every child pair over all words
+    const DbInfo db = a.dbs[dbi];
+    const unsigned long long mycol =
+        lane < (int)q ? (unsigned long long)db.f1[my_item] * db.Wp : 0ull;
+    const uint64_t* col[TQ];
+#pragma unroll
+    for (int i = 0; i < TQ; ++i) col[i] = db.B + __shfl(mycol, i);
+    uint32_t acc[TNP];
+#pragma unroll
+    for (int p = 0; p < TNP; ++p) acc[p] = 0;
+    const uint32_t W = (uint32_t)db.W;
+    const int qi = (int)q;
+    for (uint32_t w = 2 * lane; w < W; w += 128) {
+      uint64_t m0 = ~0ull, m1 = (w + 1 < W) ? ~0ull : 0ull;
+      for (uint32_t j = 0; j < pre_len; ++j) {
+        const uint4 x = *reinterpret_cast<const uint4*>(db.B + (uint64_t)cpre[j] * db.Wp + w);
+        m0 &= (uint64_t)x.x | ((uint64_t)x.y << 32);
+        m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
+      }
+      uint64_t x0[TQ], x1[TQ];
+#pragma unroll
+      for (int i = 0; i < TQ; ++i) {
+        x0[i] = 0;
+        x1[i] = 0;
+        if (i < qi) {
+          const uint4 v = *reinterpret_cast<const uint4*>(col[i] + w);
+          x0[i] = ((uint64_t)v.x | ((uint64_t)v.y << 32)) & m0;
+          x1[i] = ((uint64_t)v.z | ((uint64_t)v.w << 32)) & m1;
+        }
+      }
+      int p = 0;
+#pragma unroll
+      for (int i = 0; i < TQ; ++i)
+#pragma unroll
+        for (int l = i + 1; l < TQ; ++l, ++p)
+          if (l < qi) acc[p] += (uint32_t)(__popcll(x0[i] & x0[l]) + __popcll(x1[i] & x1[l]));
+    }
+    // transposing reduction: after the step with distance d a lane keeps the
+    // half of its values selected by (lane & d) and adds its partner's copy
+    uint32_t v[32];
+#pragma unroll
+    for (int p = 0; p < 32; ++p) v[p] = p < TNP ? acc[p] : 0u;
+#pragma unroll
+    for (int d = 32, n = 16; d >= 2; d >>= 1, n >>= 1) {
+      const bool up = (lane & d) != 0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        if (k < n) {
+          const uint32_t send = up ? v[k] : v[k + n];
+          const uint32_t keep = up ? v[k + n] : v[k];
+          v[k] = keep + __shfl_xor(send, d);
+        }
+      }
+    }
+    const uint32_t pair_total = v[0] + __shfl_xor(v[0], 1);  // lanes 2p, 2p+1: pair p
+
+    // ---- record frequent extensions (lane i: child i), push new classes
+    const uint32_t minsup = db.minsup;
+    const uint32_t len = pre_len + 2;
+    uint32_t cnt_l[TQ], item_l[TQ];
+    uint32_t mask = 0;
+#pragma unroll
+    for (int l = 0; l < TQ; ++l) {
+      item_l[l] = __shfl(my_item, l);
+      const int src = (lane < l) ? 2 * pair_slot(lane, l) : 0;
+      cnt_l[l] = __shfl(pair_total, src);
+      if (lane < l && l < qi && cnt_l[l] >= minsup) mask |= 1u << l;
+    }
+    const int i = lane;
+    const uint32_t nf = (uint32_t)__popc(mask);
+    const uint32_t incl = lane_scan(i < TQ ? nf : 0u, lane);
+    const uint32_t total = __shfl(incl, TQ - 1);
+    uint32_t base = 0, ok = total > 0 ? 1u : 0u;
+    if (lane == 0) {
+      const uint64_t ncand = (uint64_t)q * (q - 1) / 2;
+      const unsigned long long words = (unsigned long long)(pre_len + q) * db.W;
+      if (len <= BM_MAX_LEVELS) ws.cand[len] += ncand;
+      ws.words += words;
+      if (total) {
+        if (len > BM_MAX_LEVELS) {
+          atomicOr(a.flags, DFS_TOO_LONG);
+          ok = 0;
+        } else if (!ws_alloc(ws, a, total, &base)) {
+          atomicOr(a.flags, DFS_OVERFLOW);
+          ok = 0;
+        } else {
+          ws.freq[len] += total;
+        }
+      }
+    }
+    tcost += (unsigned long long)(pre_len + q) * db.W;
+    base = __shfl(base, 0);
+    ok = __shfl(ok, 0);
+    const uint32_t cnt = ok ? nf : 0u;
+    const uint32_t first = base + incl - nf;
+    const uint32_t push = (i < qi && cnt >= 2) ? 1u : 0u;
+    const uint32_t pincl = lane_scan(i < TQ ? push : 0u, lane);
+    const uint32_t npush = __shfl(pincl, TQ - 1);
+    wave_lds_sync();  // cpre fully read by the word loop before entries copy it
+    if (i < qi) {
+      if (ok) {
+        uint32_t r = 0;
+#pragma unroll
+        for (int l = 0; l < TQ; ++l) {
+          if ((mask >> l) & 1u) {
+            ArenaNode an;
+            an.item = item_l[l];
+            an.supp = cnt_l[l];
+            an.first = 0;
+            an.count = 0;
+            a.arena[first + r] = an;
+            ++r;
+          }
+        }
+      }
+      if (ls_level) {
+        a.ls_first[ls_level][my_node] = first;
+        a.ls_count[ls_level][my_node] = cnt;
+      } else {
+        a.arena[my_node].first = first;
+        a.arena[my_node].count = cnt;
+      }
+      if (push) {
+        const int slot = sp + (int)(pincl - 1);
+        if (slot < WSCAP) {
+          Entry& e = stk[slot];
+          e.pre_len = pre_len + 1;
+          e.q = cnt;
+          e.ls_level = 0;
+          e.db = dbi;
+          for (uint32_t j = 0; j < pre_len; ++j) e.pre[j] = cpre[j];
+          e.pre[pre_len] = db.f1[my_item];
+          uint32_t r = 0;
+#pragma unroll
+          for (int l = 0; l < TQ; ++l) {
+            if ((mask >> l) & 1u) {
+              e.item[r] = item_l[l];
+              ++r;
+            }
+          }
+          for (uint32_t k = 0; k < TQ; ++k) {
+            if (k >= r) e.item[k] = 0u;
+            e.node[k] = first + k;
+          }
+        } else {
+          atomicOr(a.flags, DFS_STACK);
+        }
+      }
+    }
+    sp = min(sp + (int)npush, WSCAP);
+    if (sp == 0 && lane == 0 && a.task_cost) a.task_cost[task] = (float)tcost;
+    wave_lds_sync();
   }
 }
 
@@ -338,6 +621,31 @@ __global__ void k_bucket_scatter(const float* __restrict__ key, uint32_t n, uint
   for (uint32_t t = c0 + threadIdx.x; t < c1; t += blockDim.x) {
     const uint32_t b = bucket_of(key[t]);
     order[base[b] + atomicAdd(&cnt[b], 1u)] = t;
+  }
+}
+
+__global__ void k_dfs_short_flags(const DfsTask* __restrict__ tasks, const DbInfo* __restrict__ dbs,
+                                  const uint32_t* __restrict__ order, uint32_t n, uint32_t max_words,
+                                  uint32_t* __restrict__ flags) {
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const uint32_t ti = order ? order[t] : t;
+    flags[t] = dbs[tasks[ti].db].W <= max_words ? 1u : 0u;
+  }
+}
+
+__global__ void k_dfs_split(const uint32_t* __restrict__ order, uint32_t n,
+                            const uint32_t* __restrict__ flags, const uint64_t* __restrict__ pos,
+                            uint32_t* __restrict__ short_, uint32_t* __restrict__ long_,
+                            uint32_t* __restrict__ counts) {
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t <= n; t += gridDim.x * blockDim.x) {
+    if (t == n) {
+      counts[0] = (uint32_t)pos[n];
+      counts[1] = n - (uint32_t)pos[n];
+    } else {
+      const uint32_t ti = order ? order[t] : t;
+      if (flags[t]) short_[pos[t]] = ti;
+      else long_[t - pos[t]] = ti;
+    }
   }
 }
 
@@ -429,6 +737,27 @@ void launch_dfs(const DfsArgs& a, uint32_t threads, uint32_t grid, hipStream_t s
   if (threads == 1024) k_dfs<1024><<<grid, 1024, 0, s>>>(a);
   else if (threads == 512) k_dfs<512><<<grid, 512, 0, s>>>(a);
   else k_dfs<256><<<grid, 256, 0, s>>>(a);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_dfs_wave(const DfsArgs& a, uint32_t grid, hipStream_t s) {
+  if (grid == 0) return;
+  k_dfs_wave<<<grid, 256, 0, s>>>(a);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_dfs_short_flags(const DfsTask* tasks, const DbInfo* dbs, const uint32_t* order,
+                            uint32_t n, uint32_t max_words, uint32_t* flags, hipStream_t s) {
+  if (n == 0) return;
+  k_dfs_short_flags<<<grid_for(n, kThreads), kThreads, 0, s>>>(tasks, dbs, order, n, max_words,
+                                                               flags);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_dfs_split(const uint32_t* order, uint32_t n, const uint32_t* flags, const uint64_t* pos,
+                      uint32_t* short_, uint32_t* long_, uint32_t* counts, hipStream_t s) {
+  k_dfs_split<<<grid_for(n + 1, kThreads), kThreads, 0, s>>>(order, n, flags, pos, short_, long_,
+                                                             counts);
   BM_LAUNCH_CHECK();
 }
 

@@ -1,7 +1,8 @@
 // Cost model of the scheduler: an 8 -> 64 -> 64 -> 1 perceptron with ReLU,
 // BF16 weights and FP32 accumulation, trained with Adam on an FP32 master copy.
-// It predicts log2(1 + candidates in a subtree) from 8 features of a prefix
-// class and is used only to order subtree tasks; it never changes a result.
+// It predicts log2(1 + column words streamed for a subtree) from 8 features of
+// a prefix class and is used only to order subtree tasks; it never changes a
+// result.
 //
 // Parameter layout (4,801 values): W1[8][64], b1[64], W2[64][64], b2[64],
 // W3[64], b3.  Inputs are standardised with a per-feature mean and 1/std kept

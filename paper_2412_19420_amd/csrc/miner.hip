@@ -298,6 +298,8 @@ Tuning tuning_from(const bm_options* opt) {
     t.dfs_threads = opt->dfs_threads;
   }
   if (opt->dfs_max_words) t.dfs_max_words = opt->dfs_max_words;
+  if (opt->dfs_wave_max_words) t.dfs_wave_words = opt->dfs_wave_max_words;
+  if (opt->flags & BM_FLAG_DFS_BLOCK_ONLY) t.dfs_wave_words = 0;
   if (opt->mfma_big_children) t.mfma_big_q = std::max<uint32_t>(2, opt->mfma_big_children);
   if (opt->flags & BM_FLAG_LEVELSYNC) t.dfs = false;
   if (opt->flags & BM_FLAG_FP4_MFMA) t.mfma_fp4 = true;
@@ -791,13 +793,31 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         upload(order.get(), perm, s);
       }
       tm.end();
+      // short-column databases' tasks go to the one-stack-per-wave kernel, the
+      // rest to the one-stack-per-workgroup kernel; a stable split keeps the
+      // queue order within each
+      TBuf<uint32_t> qshort, qlong, qcnt;
+      if (tu.dfs_wave_words) {
+        TBuf<uint32_t> qflag(D, s);
+        TBuf<uint64_t> qpos(D + 1, s);
+        qshort.alloc(D, s);
+        qlong.alloc(D, s);
+        qcnt.alloc(2, s);
+        launch_dfs_short_flags(tasks.get(), ddb.get(), order.get(), (uint32_t)D, tu.dfs_wave_words,
+                               qflag.get(), s);
+        scan32(qflag.get(), qpos.get(), D, s);
+        launch_dfs_split(order.get(), (uint32_t)D, qflag.get(), qpos.get(), qshort.get(), qlong.get(),
+                         qcnt.get(), s);
+      }
       std::vector<TBuf<uint32_t>> ls_first(Kls + 2), ls_count(Kls + 2);
-      TBuf<uint32_t> ctrl(2, s);                  // [0] queue head, [1] arena count
+      TBuf<uint32_t> ctrl(3, s);  // [0] workgroup-queue head, [1] arena count, [2] wave-queue head
       TBuf<uint32_t> dflags(1, s);
       TBuf<unsigned long long> lstat(2 * (BM_MAX_LEVELS + 1) + 1, s);
       TBuf<float> cost;
       if (trace) cost.alloc(D, s);
-      uint64_t cap = std::max<uint64_t>(1u << 16, 32 * D);
+      // workers reserve arena space ARENA_CHUNK (256) nodes at a time
+      const uint64_t workers = (uint64_t)cu_count() * (16 + 2048 / tu.dfs_threads);
+      uint64_t cap = std::max<uint64_t>(1u << 16, 32 * D) + workers * 256;
       TBuf<ArenaNode> arena;
       std::vector<unsigned long long> hstat(2 * (BM_MAX_LEVELS + 1) + 1);
       for (int attempt = 0;; ++attempt) {
@@ -810,7 +830,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
           }
           launch_fill_u32(ls_count[j].get(), 0, L[j].n, s);
         }
-        launch_fill_u32(ctrl.get(), 0, 2, s);
+        launch_fill_u32(ctrl.get(), 0, 3, s);
         launch_fill_u32(dflags.get(), 0, 1, s);
         launch_fill_u64(reinterpret_cast<uint64_t*>(lstat.get()), 0, hstat.size(), s);
         DfsArgs da{};
@@ -834,6 +854,15 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         da.words_read = lstat.get() + 2 * (BM_MAX_LEVELS + 1);
         da.task_cost = trace ? cost.get() : nullptr;
         tm.begin(BM_K_DFS);
+        if (tu.dfs_wave_words) {
+          DfsArgs dw = da;
+          dw.order = qshort.get();
+          dw.ntasks_dev = qcnt.get();
+          dw.queue_head = ctrl.get() + 2;
+          launch_dfs_wave(dw, (uint32_t)std::min<uint64_t>((D + 3) / 4, (uint64_t)cu_count() * 4), s);
+          da.order = qlong.get();
+          da.ntasks_dev = qcnt.get() + 1;
+        }
         launch_dfs(da, tu.dfs_threads,
                    (uint32_t)std::min<uint64_t>(D, (uint64_t)cu_count() * (2048 / tu.dfs_threads)), s);
         tm.end();

@@ -91,7 +91,7 @@ def test_trace_rows_and_labels(bm):
     db = gen.make_config(3, scale=0.02)
     print("trace", flush=True)
     h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
-    r1 = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_TRACE))
+    r1 = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_TRACE | bm.FLAG_TIMING))
     r2 = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_TRACE | bm.FLAG_SHUFFLE, shuffle_seed=5))
     f1, y1 = r1.trace()
     f2, y2 = r2.trace()
@@ -99,11 +99,13 @@ def test_trace_rows_and_labels(bm):
     # features and per-task costs do not depend on the order tasks are taken in
     assert np.array_equal(f1, f2) and np.array_equal(y1, y2)
     assert np.all(np.isfinite(f1)) and np.all(y1 >= 0)
-    # label = log2(1 + candidates in the subtree); they add up to the depth-first share
+    # label = log2(1 + column words streamed for the subtree); they add up to
+    # the depth-first kernel's words (its algorithmic bytes / 8)
     cost = np.exp2(y1.astype(np.float64)) - 1
-    assert np.all(cost >= 1 - 1e-3)  # a task is a class with >= 2 children: >= 1 candidate
+    words = (db.n + 63) // 64
+    assert np.all(cost >= 2 * words * (1 - 1e-4))  # >= 2 child columns of W words
     st = r1.stats()
-    assert cost.sum() <= st["candidates_total"] * (1 + 1e-4)
+    assert abs(8 * cost.sum() - st["kernel_bytes"]["dfs"]) <= 1e-3 * st["kernel_bytes"]["dfs"]
     # feature 0 is the level of the task's children, feature 2 is log2(1 + q) with 2 <= q <= 8
     assert np.all(f1[:, 0] >= 1)
     q = np.exp2(f1[:, 2].astype(np.float64)) - 1
@@ -225,15 +227,40 @@ def test_learned_order_keeps_results(bm):
         assert _arrays_equal(a.arrays(), _oracle(d, d.minsup))
 
 
-@pytest.mark.parametrize("threads", [256, 512, 1024])
-def test_depth_first_block_sizes(bm, threads):
+@pytest.mark.parametrize("threads,wave", [(256, "block"), (512, "block"), (1024, "block"),
+                                          (256, "wave"), (512, "default")])
+def test_depth_first_block_sizes(bm, threads, wave):
+    # one stack per workgroup of 256/512/1024 threads, one stack per wave, and
+    # the default split between them: identical to the level-synchronous result
     db = gen.make_config(3, scale=0.02)
-    print(f"dfs threads={threads}", flush=True)
+    print(f"dfs threads={threads} {wave}", flush=True)
     h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
     base = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_LEVELSYNC)).arrays()
-    r = bm.bm_mine_ex(h, db.minsup, bm.options(dfs_threads=threads))
+    flags = bm.FLAG_DFS_BLOCK_ONLY if wave == "block" else 0
+    ww = 0xFFFFFFFF if wave == "wave" else 0
+    r = bm.bm_mine_ex(h, db.minsup, bm.options(flags, dfs_threads=threads, dfs_wave_max_words=ww))
     assert r.stats()["dfs_tasks"] > 0
     assert _arrays_equal(r.arrays(), base)
+
+
+def test_depth_first_wave_kernel_on_batch_with_split(bm):
+    # a batch whose databases straddle the split: both kernels run in one call,
+    # in plain, shuffled and learned queue order
+    dbs = [gen.batch_db(k, scale=0.1) for k in range(12)]
+    hs = [bm.bm_build(d.row_ptr, d.col_idx, d.n, d.m) for d in dbs]
+    ms = [d.minsup for d in dbs]
+    print("wave/block split on a batch", flush=True)
+    ref = bm.bm_mine_batch(hs, ms, opts=bm.options(bm.FLAG_LEVELSYNC))
+    model = bm.Model(seed=4)
+    f, y = bm.bm_mine_batch(hs, ms, opts=bm.options(bm.FLAG_TRACE))[0].trace()
+    model.train(f, y, epochs=5, lr=3e-3)
+    for o, mdl in ((bm.options(dfs_wave_max_words=128), None),
+                   (bm.options(bm.FLAG_SHUFFLE, shuffle_seed=3, dfs_wave_max_words=128), None),
+                   (bm.options(dfs_wave_max_words=128), model)):
+        got = bm.bm_mine_batch(hs, ms, model=mdl, opts=o)
+        assert got[0].stats()["dfs_tasks"] > 0
+        for d, a, b in zip(dbs, ref, got):
+            assert _arrays_equal(a.arrays(), b.arrays())
 
 
 @pytest.mark.parametrize("k", [3, 5])
@@ -247,6 +274,9 @@ def test_depth_first_forced_on_full_size(bm, k):
     assert base.stats()["dfs_tasks"] == 0
     r = bm.bm_mine_ex(h, db.minsup, bm.options(dfs_threads=1024, dfs_max_words=0xFFFFFFFF))
     assert r.stats()["dfs_tasks"] > 0
+    assert _arrays_equal(r.arrays(), base.arrays())
+    r = bm.bm_mine_ex(h, db.minsup, bm.options(dfs_max_words=0xFFFFFFFF,
+                                               dfs_wave_max_words=0xFFFFFFFF))
     assert _arrays_equal(r.arrays(), base.arrays())
 
 
@@ -290,3 +320,44 @@ def test_autotune_picks_options_with_identical_output(bm, tmp_path):
     o2, ms2, hit2 = bm.autotune_cached(hs, ms, path, reps=1)
     assert not hit1 and hit2 and ms1 == ms2
     assert bm.options_to_dict(o1) == bm.options_to_dict(o2)
+
+
+def _list_schedule_makespan(costs, order, workers):
+    """Greedy list scheduling as the persistent queue does it: each task, in
+    queue order, goes to the worker that frees up first."""
+    import heapq
+    heap = [0.0] * workers
+    for t in order:
+        heapq.heapreplace(heap, heap[0] + costs[t])
+    return max(heap)
+
+
+def test_learned_order_shortens_the_queue_makespan(bm):
+    # What the trained network buys: on the batched workload (half-size rows),
+    # the realised per-task costs of the depth-first queue, scheduled over the
+    # kernel's workgroups in plain order and in the model's longest-predicted-
+    # first order.  The model is trained on the GPU on traces of held-out
+    # databases only.  Deterministic: traces, training and prediction are.
+    import torch
+    print("learned order gain (simulated makespan)", flush=True)
+    test = [gen.batch_db(k, scale=0.5) for k in range(256)]
+    held = [gen.batch_db(k, scale=0.5) for k in range(256, 320)]
+    ht = [bm.bm_build(d.row_ptr, d.col_idx, d.n, d.m) for d in test]
+    hh = [bm.bm_build(d.row_ptr, d.col_idx, d.n, d.m) for d in held]
+    ft, yt = bm.bm_mine_batch(hh, [d.minsup for d in held], opts=bm.options(bm.FLAG_TRACE))[0].trace()
+    model = bm.Model(seed=1)
+    model.train(ft, yt, epochs=40, lr=3e-3, batch=256)
+    f, y = bm.bm_mine_batch(ht, [d.minsup for d in test], opts=bm.options(bm.FLAG_TRACE))[0].trace()
+    cost = np.exp2(y.astype(np.float64)) - 1
+    pred = model.predict(f).astype(np.float64)
+    workers = torch.cuda.get_device_properties(0).multi_processor_count * 8
+    assert len(cost) > 4 * workers, "too few tasks for the order to matter"
+    plain = _list_schedule_makespan(cost, range(len(cost)), workers)
+    learned = _list_schedule_makespan(cost, np.argsort(-pred, kind="stable"), workers)
+    best = _list_schedule_makespan(cost, np.argsort(-cost, kind="stable"), workers)
+    lower = max(cost.sum() / workers, cost.max())
+    print(f"tasks={len(cost)} workers={workers} makespan plain={plain:.3g} learned={learned:.3g} "
+          f"true-cost LPT={best:.3g} bound={lower:.3g}", flush=True)
+    rho = np.corrcoef(np.argsort(np.argsort(pred)), np.argsort(np.argsort(cost)))[0, 1]
+    assert rho > 0.5, rho  # the ranking carries the cost
+    assert learned < plain
