@@ -15,6 +15,7 @@
 // per level reads back the next level's sizes -- for the whole batch.
 #include <algorithm>
 #include <chrono>
+#include <cstring>
 #include <cmath>
 #include <memory>
 #include <vector>
@@ -51,16 +52,64 @@ struct TBuf {  // temporary device buffer bound to the current call scope
   T* get() const { return p; }
 };
 
+// Page-locked staging for a call's small host <-> device transfers: copies
+// between device memory and pinned host memory run as plain asynchronous DMA,
+// where pageable memory would go through the runtime's bounce buffers at every
+// level's synchronisation.  Buffers are bump-allocated per thread, kept for
+// the life of the process, and recycled when the outermost call scope has
+// synchronised its stream.
+struct PinnedPool {
+  std::vector<std::pair<char*, size_t>> bufs;
+  size_t cur = 0, used = 0;
+};
+thread_local PinnedPool t_pin;
+thread_local int t_depth = 0;
+
+void* pinned(size_t bytes) {
+  bytes = (bytes + 63) & ~size_t(63);
+  for (;;) {
+    if (t_pin.cur < t_pin.bufs.size()) {
+      if (t_pin.used + bytes <= t_pin.bufs[t_pin.cur].second) {
+        void* p = t_pin.bufs[t_pin.cur].first + t_pin.used;
+        t_pin.used += bytes;
+        return p;
+      }
+      if (t_pin.cur + 1 < t_pin.bufs.size()) {
+        ++t_pin.cur;
+        t_pin.used = 0;
+        continue;
+      }
+    }
+    const size_t last = t_pin.bufs.empty() ? 0 : t_pin.bufs.back().second;
+    const size_t sz = std::max<size_t>({bytes, size_t(1) << 20, 2 * last});
+    void* p = nullptr;
+    BM_HIP(hipHostMalloc(&p, sz, hipHostMallocDefault));
+    t_pin.bufs.push_back({static_cast<char*>(p), sz});
+    t_pin.cur = t_pin.bufs.size() - 1;
+    t_pin.used = 0;
+  }
+}
+
+template <class T>
+T* pinned_array(size_t n) {
+  return static_cast<T*>(pinned(std::max<size_t>(1, n) * sizeof(T)));
+}
+
 class CallScope {
  public:
   explicit CallScope(hipStream_t s) : sc_{s, {}} {
     prev_ = t_scope;
     t_scope = &sc_;
+    ++t_depth;
   }
   ~CallScope() {
     (void)hipStreamSynchronize(sc_.s);
     for (void* p : sc_.held) dfree(p, sc_.s);
     t_scope = prev_;
+    if (--t_depth == 0) {  // nothing of this thread's calls is in flight any more
+      t_pin.cur = 0;
+      t_pin.used = 0;
+    }
   }
 
  private:
@@ -70,19 +119,20 @@ class CallScope {
 
 template <class T>
 T read_back(const T* dev, hipStream_t s) {
-  T v{};
-  BM_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+  T* v = pinned_array<T>(1);
+  BM_HIP(hipMemcpyAsync(v, dev, sizeof(T), hipMemcpyDeviceToHost, s));
   BM_HIP(hipStreamSynchronize(s));
-  return v;
+  return *v;
 }
 
-// Host -> device copy of a small host array.  hipMemcpyAsync from pageable
-// memory may still be reading the source after returning, so the source is
-// kept alive by the caller until the call's scope synchronises.
+// Host -> device copy of a small host array through pinned staging (the
+// staging copy lives until the call's scope has synchronised).
 template <class T>
 void upload(T* dst, const std::vector<T>& src, hipStream_t s) {
-  if (!src.empty())
-    BM_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  if (src.empty()) return;
+  T* st = pinned_array<T>(src.size());
+  std::memcpy(st, src.data(), src.size() * sizeof(T));
+  BM_HIP(hipMemcpyAsync(dst, st, src.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
 void scan32(const uint32_t* in, uint64_t* out, uint64_t n, hipStream_t s) {
@@ -453,8 +503,8 @@ std::vector<bm_db*> build_many(uint32_t count, const uint64_t* const* row_ptrs,
       upload(dstart.get(), blk_start, s);
       launch_fill_u32(derr.get(), 0, nj, s);
       launch_build_multi(djobs.get(), nj, dstart.get(), blk_start.back(), derr.get(), s);
-      std::vector<uint32_t> herr(nj);
-      BM_HIP(hipMemcpyAsync(herr.data(), derr.get(), nj * 4, hipMemcpyDeviceToHost, s));
+      uint32_t* herr = pinned_array<uint32_t>(nj);
+      BM_HIP(hipMemcpyAsync(herr, derr.get(), nj * 4, hipMemcpyDeviceToHost, s));
       BM_HIP(hipStreamSynchronize(s));
       for (uint32_t j = 0; j < nj; ++j) {
         const uint32_t e = herr[j], d = job_db[j];
@@ -597,8 +647,10 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       scan32(fl.get(), pos.get(), total_items, s);
       launch_gather_idx(pos.get(), dibase.get(), N + 1, dfb.get(), s);
       tm.end();
-      BM_HIP(hipMemcpyAsync(f1_base.data(), dfb.get(), (N + 1) * 8, hipMemcpyDeviceToHost, s));
+      uint64_t* pf1 = pinned_array<uint64_t>(N + 1);
+      BM_HIP(hipMemcpyAsync(pf1, dfb.get(), (N + 1) * 8, hipMemcpyDeviceToHost, s));
       BM_HIP(hipStreamSynchronize(s));
+      std::copy(pf1, pf1 + N + 1, f1_base.begin());
       st.host_syncs++;
       const uint64_t M1 = f1_base[N];
       if (M1 > 0) {
@@ -680,7 +732,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         uint64_t* outs[6] = {L[k].cstart.get(), clspos.get(), trioff.get(), pmoff.get(), pvoff.get(),
                              ptoff.get()};
         scan_many(ins, is64, outs, 6, nk, s);
-        uint64_t tot[6 + ST_COUNT];
+        uint64_t* tot = pinned_array<uint64_t>(6 + ST_COUNT);
         GatherU64 gsrc{};
         for (int j = 0; j < 6; ++j) gsrc.src[j] = outs[j] + nk;
         for (int j = 0; j < ST_COUNT; ++j)
@@ -688,7 +740,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         TBuf<uint64_t> dtot(6 + ST_COUNT, s);
         launch_gather_u64(gsrc, 6 + ST_COUNT, dtot.get(), s);
         tm.end();
-        BM_HIP(hipMemcpyAsync(tot, dtot.get(), sizeof(tot), hipMemcpyDeviceToHost, s));
+        BM_HIP(hipMemcpyAsync(tot, dtot.get(), (6 + ST_COUNT) * 8, hipMemcpyDeviceToHost, s));
         BM_HIP(hipStreamSynchronize(s));
         st.host_syncs++;
         const uint64_t n_next = tot[0], ncls = tot[1], Tn = tot[2], PM = tot[3], PV = tot[4],
@@ -866,11 +918,15 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         launch_dfs(da, tu.dfs_threads,
                    (uint32_t)std::min<uint64_t>(D, (uint64_t)cu_count() * (2048 / tu.dfs_threads)), s);
         tm.end();
-        uint32_t hc[2], hf = 0;
+        uint32_t* hc = pinned_array<uint32_t>(2);
+        uint32_t* phf = pinned_array<uint32_t>(1);
+        unsigned long long* pst = pinned_array<unsigned long long>(hstat.size());
         BM_HIP(hipMemcpyAsync(hc, ctrl.get(), 8, hipMemcpyDeviceToHost, s));
-        BM_HIP(hipMemcpyAsync(&hf, dflags.get(), 4, hipMemcpyDeviceToHost, s));
-        BM_HIP(hipMemcpyAsync(hstat.data(), lstat.get(), hstat.size() * 8, hipMemcpyDeviceToHost, s));
+        BM_HIP(hipMemcpyAsync(phf, dflags.get(), 4, hipMemcpyDeviceToHost, s));
+        BM_HIP(hipMemcpyAsync(pst, lstat.get(), hstat.size() * 8, hipMemcpyDeviceToHost, s));
         BM_HIP(hipStreamSynchronize(s));
+        const uint32_t hf = *phf;
+        std::copy(pst, pst + hstat.size(), hstat.begin());
         st.host_syncs++;
         if (hf & DFS_TOO_LONG)
           fail(BM_ERR_UNSUPPORTED, "frequent itemsets longer than %d items", BM_MAX_LEVELS);
@@ -1013,11 +1069,17 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       for (uint32_t k = 1; k <= K; ++k)
         launch_db_bounds(L[k].db.get(), L[k].n, N, bounds.get() + (size_t)k * (N + 1), s);
       tm.end();
-      BM_HIP(hipMemcpyAsync(Fs.data(), dFs.get(), (N + 1) * 8, hipMemcpyDeviceToHost, s));
-      BM_HIP(hipMemcpyAsync(Is.data(), dIs.get(), (N + 1) * 8, hipMemcpyDeviceToHost, s));
-      std::vector<uint64_t> hb((size_t)(K + 1) * (N + 1));
-      BM_HIP(hipMemcpyAsync(hb.data(), bounds.get(), hb.size() * 8, hipMemcpyDeviceToHost, s));
+      uint64_t* pFs = pinned_array<uint64_t>(N + 1);
+      uint64_t* pIs = pinned_array<uint64_t>(N + 1);
+      const size_t nhb = (size_t)(K + 1) * (N + 1);
+      uint64_t* phb = pinned_array<uint64_t>(nhb);
+      BM_HIP(hipMemcpyAsync(pFs, dFs.get(), (N + 1) * 8, hipMemcpyDeviceToHost, s));
+      BM_HIP(hipMemcpyAsync(pIs, dIs.get(), (N + 1) * 8, hipMemcpyDeviceToHost, s));
+      BM_HIP(hipMemcpyAsync(phb, bounds.get(), nhb * 8, hipMemcpyDeviceToHost, s));
       BM_HIP(hipStreamSynchronize(s));
+      std::copy(pFs, pFs + N + 1, Fs.begin());
+      std::copy(pIs, pIs + N + 1, Is.begin());
+      const std::vector<uint64_t> hb(phb, phb + nhb);
       per_level.assign(K + 1, {});
       for (uint32_t k = 1; k <= K; ++k)
         per_level[k].assign(hb.begin() + (size_t)k * (N + 1), hb.begin() + (size_t)(k + 1) * (N + 1));
