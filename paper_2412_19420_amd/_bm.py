@@ -17,7 +17,15 @@ LIB_PATH = os.path.join(_PKG, "libbm.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build the HIP library first "
-        "(python -m paper_2412_19420_amd.build or __graft_entry__.build())")
+        "(python paper_2412_19420_amd/build.py or __graft_entry__.build())")
+
+# When PyTorch-ROCm is installed, its HIP runtime is loaded before the library
+# so that the library binds to that same runtime: the two then share one device
+# context, and torch streams and tensors can be passed across the boundary.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 
 lib = ctypes.CDLL(LIB_PATH)
 

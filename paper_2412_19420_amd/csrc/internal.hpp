@@ -181,10 +181,12 @@ void launch_validate(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_
 void launch_pack(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t* B, uint64_t Wp,
                  hipStream_t s);
 void launch_colsum(const uint64_t* B, uint64_t Wp, uint32_t m, uint32_t* colsum, hipStream_t s);
-// Tiled build of M and its column sums in one pass (colsum and err must be
-// zeroed); returns false when the shape needs the atomic path (m > 16384).
-bool launch_pack_tiled(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t nnz, uint32_t m,
-                       uint64_t* B, uint64_t Wp, uint32_t* colsum, uint32_t* err, hipStream_t s);
+// Tiled build of M and its column sums in one pass, with the CSR checks
+// (colsum and err must be zeroed; err gets the flags of launch_build_multi;
+// nnz is read on the device); returns false when the shape needs the atomic
+// path (m > 16384).
+bool launch_pack_tiled(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint32_t m, uint64_t* B,
+                       uint64_t Wp, uint32_t* colsum, uint32_t* err, hipStream_t s);
 // One database of a batched matrix construction (nnz is filled on the device).
 struct PackJob {
   const uint64_t* rp;
@@ -219,7 +221,7 @@ struct ScanMulti {
   uint64_t* out[8];
 };
 constexpr uint64_t kSingleMaxN = 1ull << 18;
-// dst[i] = *src[i] for i < count (count <= 32): one small D2H copy instead of many.
+// dst[i] = *src[i] for i < count (count <= 32); dst may be mapped host memory.
 struct GatherU64 {
   const uint64_t* src[32];
 };

@@ -134,10 +134,12 @@ __global__ __launch_bounds__(256) void k_andpop(ClassArgs a) {
 }
 
 // Classes with at most TINY_Q children: no LDS staging.  Each thread streams
-// two consecutive words of the prefix and of every child column with 16-byte
-// loads, ANDs them in registers and keeps one popcount accumulator per child
-// pair; the accumulators are reduced across the wavefront with shuffles and
-// across the workgroup through LDS once per task.
+// four consecutive words of the prefix and of every child column with two
+// independent 16-byte loads (task word ranges start at multiples of 64 and
+// columns are padded to 64 words, so the four words stay inside the column),
+// ANDs them in registers and keeps one popcount accumulator per child pair;
+// the accumulators are reduced across the wavefront with shuffles and across
+// the workgroup through LDS once per task.
 constexpr int TQ = TINY_Q;
 constexpr int TNP = TQ * (TQ - 1) / 2;
 
@@ -164,22 +166,31 @@ __global__ __launch_bounds__(256) void k_andpop_reg(ClassArgs a) {
     uint32_t acc[TNP];
 #pragma unroll
     for (int p = 0; p < TNP; ++p) acc[p] = 0;
-    for (uint32_t w = task.w0 + 2 * tid; w < task.w1; w += 512) {
-      uint64_t m0 = ~0ull, m1 = (w + 1 < task.w1) ? ~0ull : 0ull;
+    for (uint32_t w = task.w0 + 4 * tid; w < task.w1; w += 1024) {
+      uint64_t m[4];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) m[h] = (w + h < task.w1) ? ~0ull : 0ull;
       for (uint32_t j = 0; j < pre_len; ++j) {
-        const uint4 x = *reinterpret_cast<const uint4*>(db.B + (uint64_t)pre[j] * db.Wp + w);
-        m0 &= (uint64_t)x.x | ((uint64_t)x.y << 32);
-        m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
+        const uint64_t* pc = db.B + (uint64_t)pre[j] * db.Wp + w;
+        const uint4 x = *reinterpret_cast<const uint4*>(pc);
+        const uint4 y = *reinterpret_cast<const uint4*>(pc + 2);
+        m[0] &= (uint64_t)x.x | ((uint64_t)x.y << 32);
+        m[1] &= (uint64_t)x.z | ((uint64_t)x.w << 32);
+        m[2] &= (uint64_t)y.x | ((uint64_t)y.y << 32);
+        m[3] &= (uint64_t)y.z | ((uint64_t)y.w << 32);
       }
-      uint64_t x0[TQ], x1[TQ];
+      uint64_t xv[TQ][4];
 #pragma unroll
       for (int i = 0; i < TQ; ++i) {
-        x0[i] = 0;
-        x1[i] = 0;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) xv[i][h] = 0;
         if (i < q) {
           const uint4 v = *reinterpret_cast<const uint4*>(col[i] + w);
-          x0[i] = ((uint64_t)v.x | ((uint64_t)v.y << 32)) & m0;
-          x1[i] = ((uint64_t)v.z | ((uint64_t)v.w << 32)) & m1;
+          const uint4 u = *reinterpret_cast<const uint4*>(col[i] + w + 2);
+          xv[i][0] = ((uint64_t)v.x | ((uint64_t)v.y << 32)) & m[0];
+          xv[i][1] = ((uint64_t)v.z | ((uint64_t)v.w << 32)) & m[1];
+          xv[i][2] = ((uint64_t)u.x | ((uint64_t)u.y << 32)) & m[2];
+          xv[i][3] = ((uint64_t)u.z | ((uint64_t)u.w << 32)) & m[3];
         }
       }
       int p = 0;
@@ -187,7 +198,9 @@ __global__ __launch_bounds__(256) void k_andpop_reg(ClassArgs a) {
       for (int i = 0; i < TQ; ++i)
 #pragma unroll
         for (int l = i + 1; l < TQ; ++l, ++p)
-          if (l < q) acc[p] += (uint32_t)(__popcll(x0[i] & x0[l]) + __popcll(x1[i] & x1[l]));
+          if (l < q)
+            acc[p] += (uint32_t)(__popcll(xv[i][0] & xv[l][0]) + __popcll(xv[i][1] & xv[l][1]) +
+                                 __popcll(xv[i][2] & xv[l][2]) + __popcll(xv[i][3] & xv[l][3]));
     }
 #pragma unroll
     for (int p = 0; p < TNP; ++p) {

@@ -68,9 +68,9 @@ __global__ __launch_bounds__(kThreads) void k_pack(const uint64_t* __restrict__ 
 //     filled in row by row -- and every column window is then replayed from LDS;
 //   * bits are set with LDS atomic ORs (idempotent: duplicate ids collapse, as
 //     M is 0/1); ids >= m are flagged;
-//   * element ranges are clamped to [0, nnz] and local rows are masked, so a
-//     malformed row_ptr (flagged by the row validation kernel) cannot send any
-//     access out of bounds.
+//   * row_ptr is checked on the way in (non-decreasing: flag 1); element
+//     ranges are clamped to [0, nnz] and local rows are masked, so a malformed
+//     row_ptr cannot send any access out of bounds.
 constexpr int PK_KR = 8;                  // words per column per tile
 constexpr int PK_ROWS = PK_KR * 64;       // 512 rows
 constexpr int PK_RBITS = 9;               // bits of a local row
@@ -100,16 +100,22 @@ __device__ __forceinline__ void pack_tile(PackSmem& sm, const uint64_t* __restri
   const int tid = threadIdx.x;
   const uint64_t r0 = blk * PK_ROWS;
   const int nr = (int)(r0 < n ? min<uint64_t>(PK_ROWS, n - r0) : 0);
+  uint32_t bad = 0;
   if (nr == 0) {
     if (tid == 0) s_rp[0] = 0;
   } else {
-    for (int t = tid; t <= nr; t += PK_T) s_rp[t] = min(rp[r0 + t], nnz);
+    // the tile's rows r0 .. r0 + nr - 1 check row_ptr[r] <= row_ptr[r + 1], so
+    // the tiles together check every row
+    for (int t = tid; t <= nr; t += PK_T) {
+      const uint64_t v = rp[r0 + t];
+      s_rp[t] = min(v, nnz);
+      if (t < nr && rp[r0 + t + 1] < v) bad |= 1u;
+    }
   }
   __syncthreads();
   const uint64_t e0 = s_rp[0];
   const uint64_t e1 = max(e0, s_rp[nr]);
   const uint32_t nwin = (m + PK_CW - 1) / PK_CW;
-  uint32_t bad = 0;
   const bool single_chunk = e1 - e0 <= PK_ECAP;
   for (uint64_t ea = e0; ea < e1 || (ea == e0 && e0 == e1); ea += PK_ECAP) {
     const uint64_t eb = min<uint64_t>(e1, ea + PK_ECAP);
@@ -195,17 +201,26 @@ __device__ __forceinline__ void pack_tile(PackSmem& sm, const uint64_t* __restri
   if (bad) atomicOr(err, bad);
 }
 
+// One database: nnz = row_ptr[n] is read here, so the host needs no read-back
+// before the launch.  Flags row_ptr[0] != 0 (8) and a NULL col_idx with
+// nnz > 0 (4, nothing is packed).
 __global__ __launch_bounds__(PK_T) void k_pack_tiled(
-    const uint64_t* __restrict__ rp, const uint32_t* __restrict__ ci, uint64_t n, uint64_t nnz,
-    uint32_t m, unsigned long long* __restrict__ B, uint64_t Wp, uint32_t* __restrict__ colsum,
+    const uint64_t* __restrict__ rp, const uint32_t* __restrict__ ci, uint64_t n, uint32_t m,
+    unsigned long long* __restrict__ B, uint64_t Wp, uint32_t* __restrict__ colsum,
     uint32_t* __restrict__ err) {
   __shared__ PackSmem sm;
+  const uint64_t nnz = rp[n];
+  if (ci == nullptr && nnz > 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, 4u);
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && rp[0] != 0) atomicOr(err, 8u);
   pack_tile(sm, rp, ci, n, nnz, m, B, Wp, colsum, err, blockIdx.x);
 }
 
 // Batched construction, part 1 -- one workgroup per database: read nnz =
-// row_ptr[n] into the job, flag row_ptr[0] != 0 (8), a NULL col_idx with
-// nnz > 0 (4) and a decreasing row_ptr (1), and zero the column sums.
+// row_ptr[n] into the job, flag row_ptr[0] != 0 (8) and a NULL col_idx with
+// nnz > 0 (4), and zero the column sums.  The pack checks the rows.
 __global__ __launch_bounds__(kThreads) void k_build_multi_pre(PackJob* __restrict__ jobs,
                                                               uint32_t* __restrict__ err) {
   PackJob& j = jobs[blockIdx.x];
@@ -217,8 +232,6 @@ __global__ __launch_bounds__(kThreads) void k_build_multi_pre(PackJob* __restric
     if (j.rp[0] != 0) bad |= 8u;
     if (nnz > 0 && j.ci == nullptr) bad |= 4u;
   }
-  for (uint64_t i = threadIdx.x; i < n; i += kThreads)
-    if (j.rp[i + 1] < j.rp[i]) bad |= 1u;
   for (uint32_t c = threadIdx.x; c < j.m; c += kThreads) j.colsum[c] = 0u;
   if (bad) atomicOr(err + blockIdx.x, bad);
 }
@@ -488,14 +501,12 @@ void launch_pack(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t* B
   BM_LAUNCH_CHECK();
 }
 
-bool launch_pack_tiled(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t nnz, uint32_t m,
-                       uint64_t* B, uint64_t Wp, uint32_t* colsum, uint32_t* err, hipStream_t s) {
-  const uint64_t windows = (m + PK_CW - 1) / PK_CW;
-  (void)windows;
+bool launch_pack_tiled(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint32_t m, uint64_t* B,
+                       uint64_t Wp, uint32_t* colsum, uint32_t* err, hipStream_t s) {
   if (!pack_tiled_ok(m, Wp)) return false;
   dim3 grid((uint32_t)(Wp / PK_KR));
-  k_pack_tiled<<<grid, PK_T, 0, s>>>(rp, ci, n, nnz, m, reinterpret_cast<unsigned long long*>(B),
-                                         Wp, colsum, err);
+  k_pack_tiled<<<grid, PK_T, 0, s>>>(rp, ci, n, m, reinterpret_cast<unsigned long long*>(B), Wp,
+                                     colsum, err);
   BM_LAUNCH_CHECK();
   return true;
 }

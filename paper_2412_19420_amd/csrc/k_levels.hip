@@ -83,9 +83,12 @@ __global__ void k_init_level1(const DbInfo* __restrict__ dbs, uint32_t ndb,
 }
 
 __global__ void k_gather_idx(const uint64_t* __restrict__ arr, const uint64_t* __restrict__ idx,
-                             uint32_t k, uint64_t* __restrict__ out) {
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x)
-    out[i] = arr[idx[i]];
+                             uint32_t k, uint64_t* __restrict__ out, uint64_t* __restrict__ out2) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+    const uint64_t v = arr[idx[i]];
+    out[i] = v;
+    if (out2) out2[i] = v;
+  }
 }
 
 // Threshold of every candidate against its own database's minsup, one thread
@@ -385,61 +388,67 @@ __global__ void k_fill_classes(uint64_t n, uint32_t k, const uint32_t* __restric
 
 // ---------------------------------------------------------------- output
 
-// Subtree sizes (itemsets, item ids) of each level-k node from the next level's scans.
-__global__ void k_emit_sizes(uint64_t n, uint32_t k, const uint64_t* __restrict__ cstart,
-                             const uint64_t* __restrict__ SZn, const uint64_t* __restrict__ ISZn,
-                             uint64_t* __restrict__ sz, uint64_t* __restrict__ isz) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    uint64_t a = 1, b = k;
-    if (SZn) {
-      const uint64_t c0 = cstart[i], c1 = cstart[i + 1];
-      a += SZn[c1] - SZn[c0];
-      b += ISZn[c1] - ISZn[c0];
+// Canonical output in one pass.  Each level's nodes are stored in the
+// lexicographic order of their itemsets (children contiguous, in parent
+// order), so the depth-first rank of a level-k node v among all itemsets is a
+// sum over levels: for every shallower level j, the index of v's level-j
+// ancestor plus one (that ancestor and every node before it come first); at
+// level k, v's own index; for every deeper level, the index of v's first
+// level-j descendant slot (all level-j nodes below earlier level-k nodes come
+// first), found by following the child-start arrays down.  The item offset is
+// the same sum with each level's count weighted by its itemset length.  With
+// no scan over subtree sizes, every node is placed independently.
+//
+// Threads past the F itemsets compute, for each database d (and d = N), the
+// first level-k node of d on every level -- the descendants of d's first
+// frequent item, followed down the same way -- and from those the first
+// itemset and first item id of d's slice of the output.
+__global__ __launch_bounds__(kThreads) void k_emit_all(EmitArgs a, uint64_t F) {
+  const uint32_t K = a.K;
+  const uint64_t total = F + a.N + 1;
+  for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < total;
+       g += (uint64_t)gridDim.x * blockDim.x) {
+    if (g < F) {
+      uint32_t k = 1;
+      while (a.base[k + 1] <= g) ++k;
+      const uint64_t i = g - a.base[k];
+      uint64_t pos = i, ioff = (uint64_t)k * i, x = i;
+      for (uint32_t j = k; j < K; ++j) {
+        x = a.cstart[j][x];
+        pos += x;
+        ioff += (uint64_t)(j + 1) * x;
+      }
+      uint64_t y = i;
+      for (uint32_t j = k; j >= 2; --j) {
+        y = a.parent[j][y];
+        pos += y + 1;
+        ioff += (uint64_t)(j - 1) * (y + 1);
+      }
+      a.o_off[pos] = ioff;
+      a.o_supp[pos] = a.supp[k][i];
+      const uint32_t* f1 = a.dbs[a.node_db[k][i]].f1;
+      y = i;
+      for (uint32_t j = k; j >= 1; --j) {
+        a.o_items[ioff + j - 1] = f1[a.item[j][y]];
+        if (j > 1) y = a.parent[j][y];
+      }
+    } else {
+      const uint32_t d = (uint32_t)(g - F);
+      const uint64_t rows = (uint64_t)a.N + 1;
+      uint64_t x = a.first_root[d];
+      uint64_t fs = x, is = x;
+      a.bounds[rows + d] = x;
+      for (uint32_t j = 1; j < K; ++j) {
+        x = a.cstart[j][x];
+        a.bounds[(uint64_t)(j + 1) * rows + d] = x;
+        fs += x;
+        is += (uint64_t)(j + 1) * x;
+      }
+      a.slices[d] = fs;
+      a.slices[rows + d] = is;
+      if (d == a.N) a.o_off[F] = is;
     }
-    sz[i] = a;
-    isz[i] = b;
   }
-}
-
-// Preorder rank and item offset of each level-k node (k >= 2) from its parent's.
-__global__ void k_emit_pos(uint64_t n, uint32_t k, const uint32_t* __restrict__ parent,
-                           const uint64_t* __restrict__ ppre, const uint64_t* __restrict__ poff,
-                           const uint64_t* __restrict__ pcstart, const uint64_t* __restrict__ SZ,
-                           const uint64_t* __restrict__ ISZ, uint64_t* __restrict__ pre,
-                           uint64_t* __restrict__ off) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t p = parent[i];
-    const uint64_t first = pcstart[p];
-    pre[i] = ppre[p] + 1 + (SZ[i] - SZ[first]);
-    off[i] = poff[p] + (k - 1) + (ISZ[i] - ISZ[first]);
-  }
-}
-
-// Scatter every level-k itemset to its canonical position; item ids are mapped
-// back to the caller's ids through the node's database's frequent-item table.
-__global__ void k_emit_write(uint64_t n, uint32_t k, const uint64_t* __restrict__ pre,
-                             const uint64_t* __restrict__ off, const uint32_t* __restrict__ supp,
-                             const uint32_t* __restrict__ node_db, LevelPtrs lv,
-                             const DbInfo* __restrict__ dbs, uint64_t* __restrict__ o_off,
-                             uint32_t* __restrict__ o_items, uint32_t* __restrict__ o_supp) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t r = pre[i], o = off[i];
-    o_off[r] = o;
-    o_supp[r] = supp[i];
-    const uint32_t* f1 = dbs[node_db[i]].f1;
-    uint64_t x = i;
-    for (int lev = (int)k; lev >= 1; --lev) {
-      o_items[o + lev - 1] = f1[lv.item[lev][x]];
-      x = lv.parent[lev][x];
-    }
-  }
-}
-
-__global__ void k_put_u64(uint64_t* __restrict__ dst, const uint64_t* __restrict__ src) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
 }
 
 __global__ void k_rebase(const uint64_t* __restrict__ src, uint64_t n, uint64_t base,
@@ -447,19 +456,6 @@ __global__ void k_rebase(const uint64_t* __restrict__ src, uint64_t n, uint64_t 
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x)
     dst[i] = src[i] - base;
-}
-
-// first[d] = first node of a level whose database is >= d (nodes are sorted by database).
-__global__ void k_db_bounds(const uint32_t* __restrict__ node_db, uint64_t n, uint32_t ndb,
-                            uint64_t* __restrict__ first) {
-  for (uint32_t d = blockIdx.x * blockDim.x + threadIdx.x; d <= ndb; d += gridDim.x * blockDim.x) {
-    uint64_t lo = 0, hi = n;
-    while (lo < hi) {
-      const uint64_t mid = (lo + hi) >> 1;
-      if (node_db[mid] < d) lo = mid + 1; else hi = mid;
-    }
-    first[d] = lo;
-  }
 }
 
 __global__ void k_expand_pairs(uint32_t k, const uint32_t* __restrict__ items,
@@ -502,9 +498,9 @@ void launch_init_level1(const DbInfo* dbs, uint32_t ndb, const uint64_t* f1_base
 }
 
 void launch_gather_idx(const uint64_t* arr, const uint64_t* idx, uint32_t k, uint64_t* out,
-                       hipStream_t s) {
+                       uint64_t* out2, hipStream_t s) {
   if (k == 0) return;
-  k_gather_idx<<<grid_for(k, kThreads), kThreads, 0, s>>>(arr, idx, k, out);
+  k_gather_idx<<<grid_for(k, kThreads), kThreads, 0, s>>>(arr, idx, k, out, out2);
   BM_LAUNCH_CHECK();
 }
 
@@ -568,46 +564,14 @@ void launch_fill_classes(uint64_t n, uint32_t k, const uint32_t* cnt, const uint
   BM_LAUNCH_CHECK();
 }
 
-void launch_emit_sizes(uint64_t n, uint32_t k, const uint64_t* cstart, const uint64_t* SZn,
-                       const uint64_t* ISZn, uint64_t* sz, uint64_t* isz, hipStream_t s) {
-  if (n == 0) return;
-  k_emit_sizes<<<grid_for(n, kThreads), kThreads, 0, s>>>(n, k, cstart, SZn, ISZn, sz, isz);
-  BM_LAUNCH_CHECK();
-}
-
-void launch_emit_pos(uint64_t n, uint32_t k, const uint32_t* parent, const uint64_t* ppre,
-                     const uint64_t* poff, const uint64_t* pcstart, const uint64_t* SZ,
-                     const uint64_t* ISZ, uint64_t* pre, uint64_t* off, hipStream_t s) {
-  if (n == 0) return;
-  k_emit_pos<<<grid_for(n, kThreads), kThreads, 0, s>>>(n, k, parent, ppre, poff, pcstart, SZ, ISZ,
-                                                         pre, off);
-  BM_LAUNCH_CHECK();
-}
-
-void launch_emit_write(uint64_t n, uint32_t k, const uint64_t* pre, const uint64_t* off,
-                       const uint32_t* supp, const uint32_t* node_db, const LevelPtrs& lv,
-                       const DbInfo* dbs, uint64_t* o_off, uint32_t* o_items, uint32_t* o_supp,
-                       hipStream_t s) {
-  if (n == 0) return;
-  k_emit_write<<<grid_for(n, kThreads), kThreads, 0, s>>>(n, k, pre, off, supp, node_db, lv, dbs,
-                                                           o_off, o_items, o_supp);
-  BM_LAUNCH_CHECK();
-}
-
-void launch_put_u64(uint64_t* dst, const uint64_t* src, hipStream_t s) {
-  k_put_u64<<<1, 64, 0, s>>>(dst, src);
+void launch_emit_all(const EmitArgs& a, uint64_t F, hipStream_t s) {
+  k_emit_all<<<grid_for(F + a.N + 1, kThreads), kThreads, 0, s>>>(a, F);
   BM_LAUNCH_CHECK();
 }
 
 void launch_rebase(const uint64_t* src, uint64_t n, uint64_t base, uint64_t* dst, hipStream_t s) {
   if (n == 0) return;
   k_rebase<<<grid_for(n, kThreads), kThreads, 0, s>>>(src, n, base, dst);
-  BM_LAUNCH_CHECK();
-}
-
-void launch_db_bounds(const uint32_t* node_db, uint64_t n, uint32_t ndb, uint64_t* first,
-                      hipStream_t s) {
-  k_db_bounds<<<grid_for(ndb + 1, kThreads), kThreads, 0, s>>>(node_db, n, ndb, first);
   BM_LAUNCH_CHECK();
 }
 

@@ -12,6 +12,30 @@ struct LevelPtrs {
   const uint32_t* parent[BM_MAX_LEVELS + 2];
 };
 
+// Everything the one-pass output kernel reads and writes.  Per level k = 1..K:
+// the node arrays, the child-start array (k < K; n_k + 1 entries, the last
+// one n_{k+1}) and base[k] = nodes on levels below k (base[K + 1] = F).
+// first_root[d] = first level-1 node of database d (N + 1 entries).  bounds
+// is (K + 1) x (N + 1), row k = first level-k node of each database; slices
+// holds the first itemset (N + 1 entries) then the first item id (N + 1) of
+// each database's slice.  bounds and slices may be mapped host memory.
+struct EmitArgs {
+  const uint32_t* item[BM_MAX_LEVELS + 2];
+  const uint32_t* parent[BM_MAX_LEVELS + 2];
+  const uint64_t* cstart[BM_MAX_LEVELS + 2];
+  const uint32_t* supp[BM_MAX_LEVELS + 2];
+  const uint32_t* node_db[BM_MAX_LEVELS + 2];
+  uint64_t base[BM_MAX_LEVELS + 2];
+  const DbInfo* dbs;
+  const uint64_t* first_root;
+  uint64_t* o_off;
+  uint32_t* o_items;
+  uint32_t* o_supp;
+  uint64_t* bounds;
+  uint64_t* slices;
+  uint32_t K, N;
+};
+
 // Word-range length of one task, per kernel (MFMA splits are multiples of 16 words).
 struct TaskGeom {
   uint32_t split_m, split_v, split_t, split_b, split_s;
@@ -32,8 +56,9 @@ void launch_f1_fill(const uint32_t* flags, const uint64_t* pos, uint32_t ndb,
 void launch_init_level1(const DbInfo* dbs, uint32_t ndb, const uint64_t* f1_base, uint64_t n1,
                         const uint32_t* f1, uint32_t* item, uint32_t* parent, uint32_t* supp,
                         uint32_t* ndbv, hipStream_t s);
+// out[i] = arr[idx[i]], i < k; also into out2 (e.g. mapped host memory) when not NULL.
 void launch_gather_idx(const uint64_t* arr, const uint64_t* idx, uint32_t k, uint64_t* out,
-                       hipStream_t s);
+                       uint64_t* out2, hipStream_t s);
 void launch_tri_flags(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs, const uint32_t* tri,
                       uint64_t T, uint32_t uniform_thr, uint32_t* flags, hipStream_t s);
 void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const int32_t* pcls,
@@ -57,19 +82,8 @@ void launch_fill_classes(uint64_t n, uint32_t k, const uint32_t* cnt, const uint
                          const uint64_t* cls_pos, const uint64_t* tri_off, const LevelPtrs& lv,
                          const uint32_t* node_db, const DbInfo* dbs, ClassDesc* ocls,
                          uint32_t* opre, int32_t* pcls_out, hipStream_t s);
-void launch_emit_sizes(uint64_t n, uint32_t k, const uint64_t* cstart, const uint64_t* SZn,
-                       const uint64_t* ISZn, uint64_t* sz, uint64_t* isz, hipStream_t s);
-void launch_emit_pos(uint64_t n, uint32_t k, const uint32_t* parent, const uint64_t* ppre,
-                     const uint64_t* poff, const uint64_t* pcstart, const uint64_t* SZ,
-                     const uint64_t* ISZ, uint64_t* pre, uint64_t* off, hipStream_t s);
-void launch_emit_write(uint64_t n, uint32_t k, const uint64_t* pre, const uint64_t* off,
-                       const uint32_t* supp, const uint32_t* node_db, const LevelPtrs& lv,
-                       const DbInfo* dbs, uint64_t* o_off, uint32_t* o_items, uint32_t* o_supp,
-                       hipStream_t s);
-void launch_put_u64(uint64_t* dst, const uint64_t* src, hipStream_t s);
+void launch_emit_all(const EmitArgs& a, uint64_t F, hipStream_t s);
 void launch_rebase(const uint64_t* src, uint64_t n, uint64_t base, uint64_t* dst, hipStream_t s);
-void launch_db_bounds(const uint32_t* node_db, uint64_t n, uint32_t ndb, uint64_t* first,
-                      hipStream_t s);
 void launch_expand_pairs(uint32_t k, const uint32_t* items, const uint32_t* colsum,
                          const uint32_t* tri, uint32_t* out, hipStream_t s);
 

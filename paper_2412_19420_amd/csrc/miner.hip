@@ -60,6 +60,7 @@ struct TBuf {  // temporary device buffer bound to the current call scope
 // synchronised its stream.
 struct PinnedPool {
   std::vector<std::pair<char*, size_t>> bufs;
+  std::vector<char*> dev;  // device address of each buffer (kernels may write there)
   size_t cur = 0, used = 0;
 };
 thread_local PinnedPool t_pin;
@@ -84,7 +85,10 @@ void* pinned(size_t bytes) {
     const size_t sz = std::max<size_t>({bytes, size_t(1) << 20, 2 * last});
     void* p = nullptr;
     BM_HIP(hipHostMalloc(&p, sz, hipHostMallocDefault));
+    void* d = nullptr;
+    BM_HIP(hipHostGetDevicePointer(&d, p, 0));
     t_pin.bufs.push_back({static_cast<char*>(p), sz});
+    t_pin.dev.push_back(static_cast<char*>(d));
     t_pin.cur = t_pin.bufs.size() - 1;
     t_pin.used = 0;
   }
@@ -93,6 +97,20 @@ void* pinned(size_t bytes) {
 template <class T>
 T* pinned_array(size_t n) {
   return static_cast<T*>(pinned(std::max<size_t>(1, n) * sizeof(T)));
+}
+
+// Device address of a staging-pool pointer: a kernel writes its small results
+// straight into host memory, which the host reads after synchronising the
+// stream (no copy launch).
+template <class T>
+T* mapped(T* host) {
+  const char* h = reinterpret_cast<const char*>(host);
+  for (size_t b = 0; b < t_pin.bufs.size(); ++b) {
+    const char* base = t_pin.bufs[b].first;
+    if (h >= base && h < base + t_pin.bufs[b].second)
+      return reinterpret_cast<T*>(t_pin.dev[b] + (h - base));
+  }
+  fail(BM_ERR_DEVICE, "pointer outside the staging pool");
 }
 
 class CallScope {
@@ -135,11 +153,29 @@ void upload(T* dst, const std::vector<T>& src, hipStream_t s) {
   BM_HIP(hipMemcpyAsync(dst, st, src.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
+// Up to this length one workgroup scans an array in a single launch (a few
+// looped chunks) faster than the three-launch block scan.
+constexpr uint64_t kOneLaunchScan = 16384;
+
 void scan32(const uint32_t* in, uint64_t* out, uint64_t n, hipStream_t s) {
+  if (n <= kOneLaunchScan) {
+    ScanMulti sm{};
+    sm.in[0] = in;
+    sm.is64[0] = 0;
+    sm.out[0] = out;
+    if (scan_multi_single(sm, 1, n, s)) return;
+  }
   TBuf<uint64_t> tmp(scan_tmp_words(n), s);
   scan_u32_to_u64(in, out, n, tmp.get(), s);
 }
 void scan64(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s) {
+  if (n <= kOneLaunchScan) {
+    ScanMulti sm{};
+    sm.in[0] = in;
+    sm.is64[0] = 1;
+    sm.out[0] = out;
+    if (scan_multi_single(sm, 1, n, s)) return;
+  }
   TBuf<uint64_t> tmp(scan_tmp_words(n), s);
   scan_u64(in, out, n, tmp.get(), s);
 }
@@ -177,7 +213,7 @@ TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_v, uint64_t c
   };
   g.split_m = (uint32_t)pick(pairs_m, 256, GRAM_KW);
   g.split_v = (uint32_t)pick(pairs_v, 512, 1);
-  g.split_t = (uint32_t)pick(classes_t, 2048, 64);
+  g.split_t = (uint32_t)pick(classes_t, 2048, 64);  // tiny-class loads read 4-word groups
   // a 256-wide tile holds about four 128-wide tiles: split its words further
   g.split_b = (uint32_t)pick((pairs_m + 3) / 4, 256, GRAM_KW);
   // 32-wide block pairs number about a quarter of the 16-wide ones, and each
@@ -376,19 +412,30 @@ bm_db* build_db(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n, ui
   db->W = (n + 63) / 64;
   db->Wp = padded_words(n);
   const bool rp_dev = is_device_ptr(row_ptr);
-  uint64_t rp0 = 0, nnz = 0;
-  if (rp_dev) {
-    BM_HIP(hipMemcpy(&rp0, row_ptr, 8, hipMemcpyDeviceToHost));
-    BM_HIP(hipMemcpy(&nnz, row_ptr + n, 8, hipMemcpyDeviceToHost));
-  } else {
-    rp0 = row_ptr[0];
-    nnz = row_ptr[n];
-  }
-  if (rp0 != 0) fail(BM_ERR_CSR, "row_ptr[0] = %llu, expected 0", (unsigned long long)rp0);
-  if (nnz > 0 && !col_idx) fail(BM_ERR_INVALID_ARG, "col_idx is NULL but row_ptr[n] = %llu",
-                                (unsigned long long)nnz);
+  const bool ci_host = col_idx && !is_device_ptr(col_idx);
+  const bool tiled = pack_tiled_ok(m, db->Wp);
   const double words = (double)m * (double)db->Wp;
   if (words * 8.0 > 1.0e15) fail(BM_ERR_UNSUPPORTED, "bitset matrix too large");
+  // nnz is needed on the host only to copy host item ids or for the untiled
+  // path; the tiled kernel reads it, and checks row_ptr, on the device
+  uint64_t nnz = 0;
+  if (!rp_dev || !tiled || ci_host) {
+    uint64_t rp0 = 0;
+    if (rp_dev) {
+      uint64_t* h = pinned_array<uint64_t>(2);
+      BM_HIP(hipMemcpyAsync(h, row_ptr, 8, hipMemcpyDeviceToHost, s));
+      BM_HIP(hipMemcpyAsync(h + 1, row_ptr + n, 8, hipMemcpyDeviceToHost, s));
+      BM_HIP(hipStreamSynchronize(s));
+      rp0 = h[0];
+      nnz = h[1];
+    } else {
+      rp0 = row_ptr[0];
+      nnz = row_ptr[n];
+    }
+    if (rp0 != 0) fail(BM_ERR_CSR, "row_ptr[0] = %llu, expected 0", (unsigned long long)rp0);
+    if (nnz > 0 && !col_idx) fail(BM_ERR_INVALID_ARG, "col_idx is NULL but row_ptr[n] = %llu",
+                                  (unsigned long long)nnz);
+  }
 
   const uint64_t* d_rp = row_ptr;
   TBuf<uint64_t> rp_copy;
@@ -399,7 +446,7 @@ bm_db* build_db(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n, ui
   }
   const uint32_t* d_ci = col_idx;
   TBuf<uint32_t> ci_copy;
-  if (nnz > 0 && !is_device_ptr(col_idx)) {
+  if (nnz > 0 && ci_host) {
     ci_copy.alloc(nnz, s);
     BM_HIP(hipMemcpyAsync(ci_copy.get(), col_idx, nnz * 4, hipMemcpyHostToDevice, s));
     d_ci = ci_copy.get();
@@ -408,28 +455,26 @@ bm_db* build_db(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n, ui
   launch_fill_u32(err.get(), 0, 1, s);
   db->B.reset((size_t)m * db->Wp, s);
   db->colsum.reset(m, s);
-  if (m > 0) {
+  if (tiled) {
     launch_fill_u32(db->colsum.get(), 0, m, s);
-    // row_ptr monotonicity first (flag only); the tiled pack clamps element
-    // ranges, flags ids >= m and writes every word of M.
-    launch_validate(d_rp, nullptr, n, 0, m, err.get(), s);
-    if (!launch_pack_tiled(d_rp, d_ci, n, nnz, m, db->B.get(), db->Wp, db->colsum.get(), err.get(),
-                           s)) {
-      launch_validate(d_rp, d_ci, n, nnz, m, err.get(), s);
-      const uint32_t e0 = read_back(err.get(), s);
-      if (e0 & 1u) fail(BM_ERR_CSR, "row_ptr is not non-decreasing");
-      if (e0 & 2u) fail(BM_ERR_CSR, "an item id is >= n_items (%u)", m);
-      launch_fill_u64(db->B.get(), 0, (uint64_t)m * db->Wp, s);
-      launch_pack(d_rp, d_ci, n, db->B.get(), db->Wp, s);
-      launch_colsum(db->B.get(), db->Wp, m, db->colsum.get(), s);
-    }
+    launch_pack_tiled(d_rp, d_ci, n, m, db->B.get(), db->Wp, db->colsum.get(), err.get(), s);
+  } else if (m > 0) {
+    launch_fill_u32(db->colsum.get(), 0, m, s);
+    launch_validate(d_rp, d_ci, n, nnz, m, err.get(), s);
+    const uint32_t e0 = read_back(err.get(), s);
+    if (e0 & 1u) fail(BM_ERR_CSR, "row_ptr is not non-decreasing");
+    if (e0 & 2u) fail(BM_ERR_CSR, "an item id is >= n_items (%u)", m);
+    launch_fill_u64(db->B.get(), 0, (uint64_t)m * db->Wp, s);
+    launch_pack(d_rp, d_ci, n, db->B.get(), db->Wp, s);
+    launch_colsum(db->B.get(), db->Wp, m, db->colsum.get(), s);
   } else {
     launch_validate(d_rp, d_ci, n, nnz, m, err.get(), s);
   }
   const uint32_t e = read_back(err.get(), s);
+  if (e & 8u) fail(BM_ERR_CSR, "row_ptr[0] is not 0");
+  if (e & 4u) fail(BM_ERR_INVALID_ARG, "col_idx is NULL but row_ptr[n] > 0");
   if (e & 1u) fail(BM_ERR_CSR, "row_ptr is not non-decreasing");
   if (e & 2u) fail(BM_ERR_CSR, "an item id is >= n_items (%u)", m);
-  BM_HIP(hipStreamSynchronize(s));
   return db.release();
 }
 
@@ -645,10 +690,9 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       TBuf<uint64_t> pos(total_items + 1, s);
       launch_f1_flags(ddb.get(), N, dibase.get(), total_items, fl.get(), s);
       scan32(fl.get(), pos.get(), total_items, s);
-      launch_gather_idx(pos.get(), dibase.get(), N + 1, dfb.get(), s);
-      tm.end();
       uint64_t* pf1 = pinned_array<uint64_t>(N + 1);
-      BM_HIP(hipMemcpyAsync(pf1, dfb.get(), (N + 1) * 8, hipMemcpyDeviceToHost, s));
+      launch_gather_idx(pos.get(), dibase.get(), N + 1, dfb.get(), mapped(pf1), s);
+      tm.end();
       BM_HIP(hipStreamSynchronize(s));
       std::copy(pf1, pf1 + N + 1, f1_base.begin());
       st.host_syncs++;
@@ -737,10 +781,8 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         for (int j = 0; j < 6; ++j) gsrc.src[j] = outs[j] + nk;
         for (int j = 0; j < ST_COUNT; ++j)
           gsrc.src[6 + j] = reinterpret_cast<const uint64_t*>(dst.get()) + j;
-        TBuf<uint64_t> dtot(6 + ST_COUNT, s);
-        launch_gather_u64(gsrc, 6 + ST_COUNT, dtot.get(), s);
+        launch_gather_u64(gsrc, 6 + ST_COUNT, mapped(tot), s);
         tm.end();
-        BM_HIP(hipMemcpyAsync(tot, dtot.get(), (6 + ST_COUNT) * 8, hipMemcpyDeviceToHost, s));
         BM_HIP(hipStreamSynchronize(s));
         st.host_syncs++;
         const uint64_t n_next = tot[0], ncls = tot[1], Tn = tot[2], PM = tot[3], PV = tot[4],
@@ -1028,55 +1070,35 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       launch_fill_u64(store->offsets.get(), 0, 1, s);
     } else {
       tm.begin(BM_K_EMIT);
-      std::vector<TBuf<uint64_t>> SZ(K + 2), ISZ(K + 2), pre(K + 1), off(K + 1);
-      for (uint32_t k = K; k >= 1; --k) {
-        TBuf<uint64_t> sz(L[k].n, s), isz(L[k].n, s);
-        const bool last = k == K;
-        launch_emit_sizes(L[k].n, k, last ? nullptr : L[k].cstart.get(),
-                          last ? nullptr : SZ[k + 1].get(), last ? nullptr : ISZ[k + 1].get(),
-                          sz.get(), isz.get(), s);
-        SZ[k].alloc(L[k].n + 1, s);
-        ISZ[k].alloc(L[k].n + 1, s);
-        const void* in[2] = {sz.get(), isz.get()};
-        const bool is64[2] = {true, true};
-        uint64_t* out[2] = {SZ[k].get(), ISZ[k].get()};
-        scan_many(in, is64, out, 2, L[k].n, s);
-      }
-      LevelPtrs lv{};
+      EmitArgs ea{};
+      uint64_t acc = 0;
       for (uint32_t k = 1; k <= K; ++k) {
-        lv.item[k] = L[k].item.get();
-        lv.parent[k] = L[k].parent.get();
+        ea.item[k] = L[k].item.get();
+        ea.parent[k] = L[k].parent.get();
+        ea.cstart[k] = k < K ? L[k].cstart.get() : nullptr;
+        ea.supp[k] = L[k].supp.get();
+        ea.node_db[k] = L[k].db.get();
+        ea.base[k] = acc;
+        acc += L[k].n;
       }
-      for (uint32_t k = 2; k <= K; ++k) {
-        pre[k].alloc(L[k].n, s);
-        off[k].alloc(L[k].n, s);
-        launch_emit_pos(L[k].n, k, L[k].parent.get(), k == 2 ? SZ[1].get() : pre[k - 1].get(),
-                        k == 2 ? ISZ[1].get() : off[k - 1].get(), L[k - 1].cstart.get(),
-                        SZ[k].get(), ISZ[k].get(), pre[k].get(), off[k].get(), s);
-      }
-      for (uint32_t k = 1; k <= K; ++k) {
-        launch_emit_write(L[k].n, k, k == 1 ? SZ[1].get() : pre[k].get(),
-                          k == 1 ? ISZ[1].get() : off[k].get(), L[k].supp.get(), L[k].db.get(), lv,
-                          ddb.get(), store->offsets.get(), store->items.get(),
-                          store->supports.get(), s);
-      }
-      launch_put_u64(store->offsets.get() + F, ISZ[1].get() + L[1].n, s);
-      // where each database's slice starts, and its per-length counts
-      TBuf<uint64_t> dFs(N + 1, s), dIs(N + 1, s);
-      launch_gather_idx(SZ[1].get(), dfb.get(), N + 1, dFs.get(), s);
-      launch_gather_idx(ISZ[1].get(), dfb.get(), N + 1, dIs.get(), s);
-      TBuf<uint64_t> bounds((size_t)(K + 1) * (N + 1), s);
-      for (uint32_t k = 1; k <= K; ++k)
-        launch_db_bounds(L[k].db.get(), L[k].n, N, bounds.get() + (size_t)k * (N + 1), s);
+      ea.base[K + 1] = acc;
+      const size_t rows = (size_t)N + 1, nhb = (size_t)(K + 1) * rows;
+      uint64_t* phb = pinned_array<uint64_t>(nhb + 2 * rows);
+      ea.dbs = ddb.get();
+      ea.first_root = dfb.get();
+      ea.o_off = store->offsets.get();
+      ea.o_items = store->items.get();
+      ea.o_supp = store->supports.get();
+      ea.bounds = mapped(phb);
+      ea.slices = mapped(phb + nhb);
+      ea.K = K;
+      ea.N = N;
+      launch_emit_all(ea, F, s);
       tm.end();
-      uint64_t* pFs = pinned_array<uint64_t>(N + 1);
-      uint64_t* pIs = pinned_array<uint64_t>(N + 1);
-      const size_t nhb = (size_t)(K + 1) * (N + 1);
-      uint64_t* phb = pinned_array<uint64_t>(nhb);
-      BM_HIP(hipMemcpyAsync(pFs, dFs.get(), (N + 1) * 8, hipMemcpyDeviceToHost, s));
-      BM_HIP(hipMemcpyAsync(pIs, dIs.get(), (N + 1) * 8, hipMemcpyDeviceToHost, s));
-      BM_HIP(hipMemcpyAsync(phb, bounds.get(), nhb * 8, hipMemcpyDeviceToHost, s));
       BM_HIP(hipStreamSynchronize(s));
+      st.host_syncs++;
+      const uint64_t* pFs = phb + nhb;
+      const uint64_t* pIs = phb + nhb + rows;
       std::copy(pFs, pFs + N + 1, Fs.begin());
       std::copy(pIs, pIs + N + 1, Is.begin());
       const std::vector<uint64_t> hb(phb, phb + nhb);

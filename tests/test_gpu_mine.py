@@ -266,6 +266,41 @@ def test_errors(bm):
     assert_same(bm.bm_mine(h, db.minsup).arrays(), want)
 
 
+@pytest.mark.parametrize("case", ["bad_item", "decreasing", "decreasing_last", "nonzero_start",
+                                  "null_col_idx"])
+def test_build_errors_device_inputs(bm, case):
+    # device-resident CSR: the tiled pack reads nnz and checks row_ptr itself,
+    # so every malformed input must still be reported (and nothing else breaks)
+    import torch
+    db = gen.make_config(1)
+    assert db.n > 1100
+    rp = db.row_ptr.astype(np.uint64).copy()
+    ci = db.col_idx.astype(np.uint32).copy()
+    want = "BM_ERR_CSR"
+    if case == "bad_item":
+        ci[len(ci) - 1] = db.m
+    elif case == "decreasing":
+        rp[700] = rp[702] + 1  # inside one 512-row tile and across the next
+    elif case == "decreasing_last":
+        rp[db.n - 1] = rp[db.n] + 1  # only the last row's end is out of order
+    elif case == "nonzero_start":
+        rp = rp + 1
+        ci = np.concatenate([[0], ci]).astype(np.uint32)
+    else:
+        want = "BM_ERR_INVALID_ARG"
+    print(f"device build error {case}", flush=True)
+    drp = torch.from_numpy(rp).cuda()
+    dci = None if case == "null_col_idx" else torch.from_numpy(ci).cuda()
+    with pytest.raises(bm.BmError) as e:
+        bm.bm_build(drp, dci, db.n, db.m)
+    assert e.value.name == want
+    # the same arrays, well formed, on the device: exact supports
+    h = bm.bm_build(torch.from_numpy(db.row_ptr.astype(np.uint64)).cuda(),
+                    torch.from_numpy(db.col_idx.astype(np.uint32)).cuda(), db.n, db.m)
+    assert np.array_equal(bm.bm_item_support(h).astype(np.int64),
+                          pairs.column_sums(db.row_ptr, db.col_idx, db.n, db.m))
+
+
 def test_repeated_calls_reuse_pool(bm):
     db = gen.make_config(2, scale=0.1)
     h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
