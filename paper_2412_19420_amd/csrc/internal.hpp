@@ -219,6 +219,12 @@ struct ScanMulti {
   const void* in[8];
   uint32_t is64[8];
   uint64_t* out[8];
+  uint32_t ge[8];       // 32-bit input j scanned as (in[j][i] >= ge[j]) when ge[j] > 0
+  uint64_t* zero;       // nzero words zeroed before the scan (e.g. counters of a later kernel)
+  uint32_t nzero;
+  uint64_t* tot;        // if set: tot[j] = total of array j, then tot[count + e] = extra[e]
+  const uint64_t* extra;
+  uint32_t nextra;
 };
 constexpr uint64_t kSingleMaxN = 1ull << 18;
 // dst[i] = *src[i] for i < count (count <= 32); dst may be mapped host memory.

@@ -405,7 +405,14 @@ __global__ __launch_bounds__(kSingleThreads) void k_scan_single(ScanMulti sm, ui
   const int a = blockIdx.x;
   const void* in = sm.in[a];
   const bool is64 = sm.is64[a] != 0;
+  const uint32_t ge = sm.ge[a];
   uint64_t* out = sm.out[a];
+  if (a == 0) {
+    for (uint32_t j = threadIdx.x; j < sm.nzero; j += kSingleThreads) sm.zero[j] = 0;
+    if (sm.tot)
+      for (uint32_t j = threadIdx.x; j < sm.nextra; j += kSingleThreads)
+        sm.tot[gridDim.x + j] = sm.extra[j];
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint64_t base = 0;
   for (uint64_t c0 = 0; c0 < n; c0 += kSingleChunk) {
@@ -415,8 +422,16 @@ __global__ __launch_bounds__(kSingleThreads) void k_scan_single(ScanMulti sm, ui
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
       const uint64_t i = i0 + k;
-      v[k] = i < n ? (is64 ? static_cast<const uint64_t*>(in)[i] : static_cast<const uint32_t*>(in)[i])
-                   : 0ull;
+      uint64_t x = 0;
+      if (i < n) {
+        if (is64) {
+          x = static_cast<const uint64_t*>(in)[i];
+        } else {
+          const uint32_t y = static_cast<const uint32_t*>(in)[i];
+          x = ge ? (y >= ge ? 1u : 0u) : y;
+        }
+      }
+      v[k] = x;
       t += v[k];
     }
     uint64_t inc = t;
@@ -440,7 +455,10 @@ __global__ __launch_bounds__(kSingleThreads) void k_scan_single(ScanMulti sm, ui
     base += tot;
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[n] = base;
+  if (threadIdx.x == 0) {
+    out[n] = base;
+    if (sm.tot) sm.tot[a] = base;
+  }
 }
 
 __global__ void k_gather_u64(GatherU64 g, int count, uint64_t* __restrict__ dst) {

@@ -191,33 +191,28 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
 }
 
 // Wave per node: write the node's frequent extensions into the next level.
-__global__ void k_fill_level(uint64_t n, const uint32_t* __restrict__ parent,
-                             const int32_t* __restrict__ pcls, const ClassDesc* __restrict__ cls,
-                             const DbInfo* __restrict__ dbs,
-                             const uint32_t* __restrict__ child_item, const uint32_t* __restrict__ tri,
-                             const uint64_t* __restrict__ S, uint32_t* __restrict__ nitem,
-                             uint32_t* __restrict__ nparent, uint32_t* __restrict__ nsupp,
-                             uint32_t* __restrict__ ndbv) {
+// Threads [t0, t0 + nt) of a launch take part.
+__device__ inline void fill_level_body(const LevelPost& a, uint64_t t0, uint64_t nt) {
   const int lane = threadIdx.x & 63;
-  const uint64_t wave0 = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t i = wave0; i < n; i += nwaves) {
-    const int32_t c = pcls[parent[i]];
+  const uint64_t wave0 = t0 >> 6;
+  const uint64_t nwaves = nt >> 6;
+  for (uint64_t i = wave0; i < a.n; i += nwaves) {
+    const int32_t c = a.pcls[a.parent[i]];
     if (c < 0) continue;
-    const ClassDesc cd = cls[c];
+    const ClassDesc cd = a.cls[c];
     const uint64_t li = i - cd.child0;
     if (li + 1 >= cd.q) continue;
     const uint64_t rs = cd.tri_off + tri_index(li, li + 1, cd.q);
     const uint64_t len = cd.q - li - 1;
-    const uint32_t minsup = dbs[cd.db].minsup;
+    const uint32_t minsup = a.dbs[cd.db].minsup;
     for (uint64_t t = lane; t < len; t += 64) {
-      const uint32_t v = tri[rs + t];
+      const uint32_t v = a.tri[rs + t];
       if (v >= minsup) {
-        const uint64_t pos = S[rs + t];
-        nitem[pos] = child_item[cd.child0 + li + 1 + t];
-        nparent[pos] = (uint32_t)i;
-        nsupp[pos] = v;
-        ndbv[pos] = cd.db;
+        const uint64_t pos = a.S[rs + t];
+        a.nitem[pos] = a.child_item[cd.child0 + li + 1 + t];
+        a.nparent[pos] = (uint32_t)i;
+        a.nsupp[pos] = v;
+        a.ndbv[pos] = cd.db;
       }
     }
   }
@@ -352,37 +347,51 @@ __global__ void k_write_class_tasks(const ClassDesc* __restrict__ cls, uint64_t 
 
 // A node of level k with >= 2 frequent children becomes a class of the next
 // step, whose prefix is the node's itemset.
-__global__ void k_fill_classes(uint64_t n, uint32_t k, const uint32_t* __restrict__ cnt,
-                               const uint64_t* __restrict__ child_start,
-                               const uint64_t* __restrict__ cls_pos, const uint64_t* __restrict__ tri_off,
-                               LevelPtrs lv, const uint32_t* __restrict__ node_db,
-                               const DbInfo* __restrict__ dbs, ClassDesc* __restrict__ ocls,
-                               uint32_t* __restrict__ opre, int32_t* __restrict__ pcls_out) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t q = cnt[i];
+__device__ inline void fill_classes_body(const LevelPost& a, uint64_t t0, uint64_t nt) {
+  const uint32_t k = a.k;
+  for (uint64_t i = t0; i < a.n; i += nt) {
+    const uint32_t q = a.cnt[i];
     if (q < 2) {
-      pcls_out[i] = -1;
+      a.pcls_out[i] = -1;
       continue;
     }
-    const uint32_t ci = (uint32_t)cls_pos[i];
-    pcls_out[i] = (int32_t)ci;
-    const uint32_t d = node_db[i];
+    const uint32_t ci = (uint32_t)a.cls_pos[i];
+    a.pcls_out[i] = (int32_t)ci;
+    const uint32_t d = a.node_db[i];
     ClassDesc cd;
-    cd.tri_off = tri_off[i];
-    cd.child0 = (uint32_t)child_start[i];
+    cd.tri_off = a.tri_off[i];
+    cd.child0 = (uint32_t)a.child_start[i];
     cd.q = q;
     cd.pre_off = ci * k;
     cd.pre_len = k;
     cd.db = d;
     cd.pad = 0;
-    ocls[ci] = cd;
-    const uint32_t* f1 = dbs[d].f1;
+    a.ocls[ci] = cd;
+    const uint32_t* f1 = a.dbs[d].f1;
     uint64_t x = i;
     for (int lev = (int)k; lev >= 1; --lev) {
-      opre[(uint64_t)ci * k + (k - lev)] = f1[lv.item[lev][x]];
-      x = lv.parent[lev][x];
+      a.opre[(uint64_t)ci * k + (k - lev)] = f1[a.lv.item[lev][x]];
+      x = a.lv.parent[lev][x];
     }
+  }
+}
+
+// The work between two level steps that depends only on the finished counts,
+// in one launch: blocks [0, b_level) write the next level, blocks
+// [b_level, b_level + b_cls) the next step's classes (when ocls is set) and
+// the remaining blocks zero the next step's support triangle.
+__global__ __launch_bounds__(kThreads) void k_level_post(LevelPost a) {
+  const uint32_t b = blockIdx.x;
+  if (b < a.b_level) {
+    fill_level_body(a, (uint64_t)b * kThreads + threadIdx.x, (uint64_t)a.b_level * kThreads);
+  } else if (b < a.b_level + a.b_cls) {
+    fill_classes_body(a, (uint64_t)(b - a.b_level) * kThreads + threadIdx.x,
+                      (uint64_t)a.b_cls * kThreads);
+  } else {
+    const uint32_t nb = gridDim.x - a.b_level - a.b_cls;
+    for (uint64_t i = (uint64_t)(b - a.b_level - a.b_cls) * kThreads + threadIdx.x; i < a.nz;
+         i += (uint64_t)nb * kThreads)
+      a.ztri[i] = 0u;
   }
 }
 
@@ -523,13 +532,12 @@ void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const in
   BM_LAUNCH_CHECK();
 }
 
-void launch_fill_level(uint64_t n, const uint32_t* parent, const int32_t* pcls,
-                       const ClassDesc* cls, const DbInfo* dbs, const uint32_t* child_item,
-                       const uint32_t* tri, const uint64_t* S, uint32_t* nitem, uint32_t* nparent,
-                       uint32_t* nsupp, uint32_t* ndbv, hipStream_t s) {
-  if (n == 0) return;
-  k_fill_level<<<grid_for(n * 64, kThreads), kThreads, 0, s>>>(n, parent, pcls, cls, dbs, child_item,
-                                                                 tri, S, nitem, nparent, nsupp, ndbv);
+void launch_level_post(LevelPost a, hipStream_t s) {
+  if (a.n == 0) return;
+  a.b_level = grid_for(a.n * 64, kThreads);
+  a.b_cls = a.ocls ? grid_for(a.n, kThreads) : 0u;
+  const uint32_t bz = a.nz ? grid_for(a.nz, kThreads, 16384) : 0u;
+  k_level_post<<<a.b_level + a.b_cls + bz, kThreads, 0, s>>>(a);
   BM_LAUNCH_CHECK();
 }
 
@@ -551,16 +559,6 @@ void launch_write_class_tasks(const ClassDesc* cls, uint64_t ncls, const DbInfo*
   if (ncls == 0) return;
   k_write_class_tasks<<<grid_for(ncls * 64, kThreads), kThreads, 0, s>>>(
       cls, ncls, dbs, mfma_min_q, geo, om, ov, ot, tm, tv, tt, dt, level, ob, tb, os, ts);
-  BM_LAUNCH_CHECK();
-}
-
-void launch_fill_classes(uint64_t n, uint32_t k, const uint32_t* cnt, const uint64_t* child_start,
-                         const uint64_t* cls_pos, const uint64_t* tri_off, const LevelPtrs& lv,
-                         const uint32_t* node_db, const DbInfo* dbs, ClassDesc* ocls,
-                         uint32_t* opre, int32_t* pcls_out, hipStream_t s) {
-  if (n == 0) return;
-  k_fill_classes<<<grid_for(n, kThreads), kThreads, 0, s>>>(n, k, cnt, child_start, cls_pos, tri_off,
-                                                             lv, node_db, dbs, ocls, opre, pcls_out);
   BM_LAUNCH_CHECK();
 }
 

@@ -65,10 +65,38 @@ void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const in
                         const ClassDesc* cls, const uint64_t* S, uint32_t mfma_min_q, uint32_t big_q,
                         uint32_t small_on, uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz, uint32_t* pm,
                         uint32_t* pv, uint32_t* pt, unsigned long long* st, hipStream_t s);
-void launch_fill_level(uint64_t n, const uint32_t* parent, const int32_t* pcls,
-                       const ClassDesc* cls, const DbInfo* dbs, const uint32_t* child_item,
-                       const uint32_t* tri, const uint64_t* S, uint32_t* nitem, uint32_t* nparent,
-                       uint32_t* nsupp, uint32_t* ndbv, hipStream_t s);
+// Arguments of the launch between two level steps (k_level_post): node i < n
+// of level k writes its frequent extensions into the next level and, if it
+// has at least two, its class of the next step (skipped when ocls is NULL);
+// the next step's support triangle ztri[0, nz) is zeroed.
+struct LevelPost {
+  uint64_t n;
+  const uint32_t* parent;
+  const int32_t* pcls;
+  const ClassDesc* cls;
+  const DbInfo* dbs;
+  const uint32_t* child_item;
+  const uint32_t* tri;
+  const uint64_t* S;
+  uint32_t* nitem;
+  uint32_t* nparent;
+  uint32_t* nsupp;
+  uint32_t* ndbv;
+  uint32_t k;
+  const uint32_t* cnt;
+  const uint64_t* child_start;
+  const uint64_t* cls_pos;
+  const uint64_t* tri_off;
+  const uint32_t* node_db;
+  ClassDesc* ocls;
+  uint32_t* opre;
+  int32_t* pcls_out;
+  uint32_t* ztri;
+  uint64_t nz;
+  uint32_t b_level, b_cls;  // set by the launcher
+  LevelPtrs lv;
+};
+void launch_level_post(LevelPost a, hipStream_t s);
 void launch_class_task_counts(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs,
                               uint32_t mfma_min_q, const TaskGeom& geo, bool dfs, uint32_t* cm,
                               uint32_t* cv, uint32_t* ct, uint32_t* cb, uint32_t* cs, hipStream_t s);
@@ -78,10 +106,6 @@ void launch_write_class_tasks(const ClassDesc* cls, uint64_t ncls, const DbInfo*
                               const uint64_t* ov, const uint64_t* ot, Task* tm, Task* tv, Task* tt,
                               DfsTask* dt, uint32_t level, const uint64_t* ob, Task* tb,
                               const uint64_t* os, Task* ts, hipStream_t s);
-void launch_fill_classes(uint64_t n, uint32_t k, const uint32_t* cnt, const uint64_t* child_start,
-                         const uint64_t* cls_pos, const uint64_t* tri_off, const LevelPtrs& lv,
-                         const uint32_t* node_db, const DbInfo* dbs, ClassDesc* ocls,
-                         uint32_t* opre, int32_t* pcls_out, hipStream_t s);
 void launch_emit_all(const EmitArgs& a, uint64_t F, hipStream_t s);
 void launch_rebase(const uint64_t* src, uint64_t n, uint64_t base, uint64_t* dst, hipStream_t s);
 void launch_expand_pairs(uint32_t k, const uint32_t* items, const uint32_t* colsum,

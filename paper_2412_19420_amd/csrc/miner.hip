@@ -195,6 +195,28 @@ void scan_many(const void* const* in, const bool* is64, uint64_t* const* out, in
   }
 }
 
+// scan_many that also writes the totals to tot[0..count) and then
+// extra[0..nextra) to tot[count..] (tot may be mapped host memory).
+void scan_many_tot(const void* const* in, const bool* is64, uint64_t* const* out, int count,
+                   uint64_t n, uint64_t* tot, const uint64_t* extra, uint32_t nextra,
+                   hipStream_t s) {
+  ScanMulti sm{};
+  for (int j = 0; j < count; ++j) {
+    sm.in[j] = in[j];
+    sm.is64[j] = is64[j] ? 1u : 0u;
+    sm.out[j] = out[j];
+  }
+  sm.tot = tot;
+  sm.extra = extra;
+  sm.nextra = nextra;
+  if (scan_multi_single(sm, count, n, s)) return;
+  scan_many(in, is64, out, count, n, s);
+  GatherU64 g{};
+  for (int j = 0; j < count; ++j) g.src[j] = out[j] + n;
+  for (uint32_t e = 0; e < nextra; ++e) g.src[count + e] = extra + e;
+  launch_gather_u64(g, count + (int)nextra, tot, s);
+}
+
 uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 uint64_t round_up(uint64_t a, uint64_t b) { return ceil_div(a, b) * b; }
 
@@ -756,15 +778,33 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         run_class_kernels(ddb.get(), L[k].item.get(), *w, tu, nW, nN, tm, s);
 
         tm.begin(BM_K_LEVEL);
-        TBuf<uint32_t> tfl(w->T, s);
+        // S = exclusive scan of the frequent flags of this step's candidates;
+        // the step's statistics counters are zeroed on the way
         TBuf<uint64_t> S(w->T + 1, s);
-        launch_tri_flags(w->cls.get(), w->ncls, ddb.get(), w->tri.get(), w->T, uniform_thr, tfl.get(),
-                         s);
-        scan32(tfl.get(), S.get(), w->T, s);
+        TBuf<unsigned long long> dst(ST_COUNT, s);
+        uint64_t* dst64 = reinterpret_cast<uint64_t*>(dst.get());
+        if (uniform_thr && w->T <= kOneLaunchScan) {
+          ScanMulti sm{};
+          sm.in[0] = w->tri.get();
+          sm.out[0] = S.get();
+          sm.ge[0] = uniform_thr;
+          sm.zero = dst64;
+          sm.nzero = ST_COUNT;
+          if (!scan_multi_single(sm, 1, w->T, s)) fail(BM_ERR_DEVICE, "candidate scan");
+        } else {
+          launch_fill_u64(dst64, 0, ST_COUNT, s);
+          TBuf<uint64_t> tmp(scan_tmp_words(w->T), s);
+          if (uniform_thr) {
+            scan_ge_u32(w->tri.get(), uniform_thr, S.get(), w->T, tmp.get(), s);
+          } else {
+            TBuf<uint32_t> tfl(w->T, s);
+            launch_tri_flags(w->cls.get(), w->ncls, ddb.get(), w->tri.get(), w->T, uniform_thr,
+                             tfl.get(), s);
+            scan_u32_to_u64(tfl.get(), S.get(), w->T, tmp.get(), s);
+          }
+        }
         TBuf<uint32_t> cnt(nk, s), iscls(nk, s), pm(nk, s), pv(nk, s), pt(nk, s);
         TBuf<uint64_t> trisz(nk, s);
-        TBuf<unsigned long long> dst(ST_COUNT, s);
-        launch_fill_u64(reinterpret_cast<uint64_t*>(dst.get()), 0, ST_COUNT, s);
         launch_node_counts(nk, k, L[k].parent.get(), pcls_prev.get(), w->cls.get(), S.get(),
                            tu.mfma_min_q, tu.mfma_big_q, tu.mfma_small ? 1u : 0u, cnt.get(), iscls.get(), trisz.get(), pm.get(), pv.get(),
                            pt.get(), dst.get(), s);
@@ -775,13 +815,8 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         const bool is64[6] = {false, false, true, false, false, false};
         uint64_t* outs[6] = {L[k].cstart.get(), clspos.get(), trioff.get(), pmoff.get(), pvoff.get(),
                              ptoff.get()};
-        scan_many(ins, is64, outs, 6, nk, s);
         uint64_t* tot = pinned_array<uint64_t>(6 + ST_COUNT);
-        GatherU64 gsrc{};
-        for (int j = 0; j < 6; ++j) gsrc.src[j] = outs[j] + nk;
-        for (int j = 0; j < ST_COUNT; ++j)
-          gsrc.src[6 + j] = reinterpret_cast<const uint64_t*>(dst.get()) + j;
-        launch_gather_u64(gsrc, 6 + ST_COUNT, mapped(tot), s);
+        scan_many_tot(ins, is64, outs, 6, nk, mapped(tot), dst64, ST_COUNT, s);
         tm.end();
         BM_HIP(hipStreamSynchronize(s));
         st.host_syncs++;
@@ -799,11 +834,22 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         Ln.supp.alloc(n_next, s);
         Ln.db.alloc(n_next, s);
         tm.begin(BM_K_LEVEL);
-        launch_fill_level(nk, L[k].parent.get(), pcls_prev.get(), w->cls.get(), ddb.get(),
-                          L[k].item.get(), w->tri.get(), S.get(), Ln.item.get(), Ln.parent.get(),
-                          Ln.supp.get(), Ln.db.get(), s);
+        LevelPost lp{};
+        lp.n = nk;
+        lp.parent = L[k].parent.get();
+        lp.pcls = pcls_prev.get();
+        lp.cls = w->cls.get();
+        lp.dbs = ddb.get();
+        lp.child_item = L[k].item.get();
+        lp.tri = w->tri.get();
+        lp.S = S.get();
+        lp.nitem = Ln.item.get();
+        lp.nparent = Ln.parent.get();
+        lp.nsupp = Ln.supp.get();
+        lp.ndbv = Ln.db.get();
         st.frequent[k + 1] = n_next;
         if (ncls == 0) {
+          launch_level_post(lp, s);
           tm.end();
           k += 1;
           break;
@@ -815,15 +861,23 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         TBuf<int32_t> pcls_k(nk, s);
         nw->T = Tn;
         nw->tri.alloc(Tn, s);
-        launch_fill_u32(nw->tri.get(), 0, Tn, s);
         for (int j = 0; j < ST_COUNT; ++j) nw->st[j] = tot[6 + j];
-        LevelPtrs lv{};
+        lp.k = k;
+        lp.cnt = cnt.get();
+        lp.child_start = L[k].cstart.get();
+        lp.cls_pos = clspos.get();
+        lp.tri_off = trioff.get();
+        lp.node_db = L[k].db.get();
+        lp.ocls = nw->cls.get();
+        lp.opre = nw->pre.get();
+        lp.pcls_out = pcls_k.get();
+        lp.ztri = nw->tri.get();
+        lp.nz = Tn;
         for (uint32_t j = 1; j <= k; ++j) {
-          lv.item[j] = L[j].item.get();
-          lv.parent[j] = L[j].parent.get();
+          lp.lv.item[j] = L[j].item.get();
+          lp.lv.parent[j] = L[j].parent.get();
         }
-        launch_fill_classes(nk, k, cnt.get(), L[k].cstart.get(), clspos.get(), trioff.get(), lv,
-                            L[k].db.get(), ddb.get(), nw->cls.get(), nw->pre.get(), pcls_k.get(), s);
+        launch_level_post(lp, s);
         prepare_tasks(*nw, ddb.get(), Wmax, PM, PV, PT, tu, tu.dfs, k + 1, s);
         tm.end();
         w = std::move(nw);
