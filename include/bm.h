@@ -113,6 +113,9 @@ typedef struct {
                                 * splits are capped to guarantee it) */
 #define BM_FLAG_INT8_MFMA 256u /* Gram kernels on int8 x int8 -> int32 MFMA (overrides FP4) */
 #define BM_FLAG_DFS_BLOCK_ONLY 512u /* every subtree task on the one-stack-per-workgroup kernel */
+#define BM_FLAG_TIMING_MAIN 1024u   /* with BM_FLAG_TIMING: events only around the support-counting
+                                     * kernels (Gram, AND+popcount, depth-first), not around the
+                                     * level bookkeeping, output and scheduling launches */
 
 typedef struct {
   uint32_t flags;

@@ -152,7 +152,8 @@ struct ClassArgs {
 // Device timing of launches (hipEvents on the call's stream).
 class KTimer {
  public:
-  explicit KTimer(bool on, hipStream_t s) : on_(on), s_(s) {}
+  // Times the launch kinds whose bit is set in `kinds` (none: off).
+  KTimer(uint32_t kinds, hipStream_t s);
   ~KTimer();
   void begin(int kind);
   void end(double bytes = 0, double ops = 0);
@@ -169,7 +170,10 @@ class KTimer {
     double bytes, ops;
   };
   bool on_;
+  uint32_t kinds_;
+  bool skip_ = false;
   hipStream_t s_;
+  int dev_ = 0;
   std::vector<Rec> recs_;
   int cur_kind_ = -1;
   hipEvent_t cur_a_ = nullptr;

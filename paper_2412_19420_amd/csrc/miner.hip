@@ -630,7 +630,7 @@ void pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* 
   if (k >= 2) {
     hc.push_back(ClassDesc{0, 0, k, 0, 0, 0, 0});
     host_classes(w, hc, ddb.get(), db->W, tu, false, s);
-    KTimer tm(false, s);
+    KTimer tm(0u, s);
     run_class_kernels(ddb.get(), d_items.get(), w, tu, (double)db->W, (double)db->n, tm, s);
   }
   const bool out_dev = is_device_ptr(out);
@@ -660,7 +660,14 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
   auto store = std::make_shared<ResultStore>();
   bm_stats st{};
   st.mfma_form = tu.mfma_fp4 ? 1u : 0u;
-  KTimer tm((flags & BM_FLAG_TIMING) != 0, s);
+  // the support-counting kernels; the rest only without BM_FLAG_TIMING_MAIN
+  constexpr uint32_t kMainKinds = (1u << BM_K_BUILD) | (1u << BM_K_GRAM_MFMA) |
+                                  (1u << BM_K_GRAM_MFMA_BIG) | (1u << BM_K_GRAM_SMALL) |
+                                  (1u << BM_K_ANDPOP) | (1u << BM_K_ANDPOP_REG) | (1u << BM_K_DFS);
+  KTimer tm(!(flags & BM_FLAG_TIMING) ? 0u
+            : (flags & BM_FLAG_TIMING_MAIN) ? kMainKinds
+                                            : (1u << BM_K_COUNT) - 1u,
+            s);
   std::vector<uint64_t> Fs(N + 1, 0), Is(N + 1, 0);
   std::vector<std::vector<uint64_t>> per_level;  // [k] -> first node of each database (N+1)
   uint32_t K = 0;

@@ -136,32 +136,56 @@ void release_cached() {
 
 // ------------------------------------------------------------------ timing
 
-KTimer::~KTimer() {
-  for (auto& r : recs_) {
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+// Timing events are reused: creating one costs more host time than recording
+// it, and a call records a few dozen.  One pool per thread and device.
+namespace {
+thread_local std::map<int, std::vector<hipEvent_t>> t_events;
+
+hipEvent_t take_event(int dev) {
+  auto& v = t_events[dev];
+  if (!v.empty()) {
+    hipEvent_t e = v.back();
+    v.pop_back();
+    return e;
   }
-  if (cur_a_) (void)hipEventDestroy(cur_a_);
+  hipEvent_t e = nullptr;
+  BM_HIP(hipEventCreate(&e));
+  return e;
+}
+}  // namespace
+
+KTimer::KTimer(uint32_t kinds, hipStream_t s) : on_(kinds != 0), kinds_(kinds), s_(s) {
+  if (on_) BM_HIP(hipGetDevice(&dev_));
+}
+
+KTimer::~KTimer() {
+  auto& v = t_events[dev_];
+  for (auto& r : recs_) {
+    v.push_back(r.a);
+    v.push_back(r.b);
+  }
+  if (cur_a_) v.push_back(cur_a_);
 }
 
 void KTimer::begin(int kind) {
   if (!on_) return;
-  BM_HIP(hipEventCreate(&cur_a_));
+  skip_ = !(kinds_ & (1u << kind));
+  if (skip_) return;
+  if (!cur_a_) cur_a_ = take_event(dev_);
   BM_HIP(hipEventRecord(cur_a_, s_));
   cur_kind_ = kind;
 }
 
 void KTimer::end(double bytes, double ops) {
-  if (!on_) return;
-  hipEvent_t b;
-  BM_HIP(hipEventCreate(&b));
-  BM_HIP(hipEventRecord(b, s_));
+  if (!on_ || skip_) return;
+  hipEvent_t b = take_event(dev_);
   recs_.push_back(Rec{cur_kind_, cur_a_, b, bytes, ops});
   cur_a_ = nullptr;
+  BM_HIP(hipEventRecord(b, s_));
 }
 
 void KTimer::set_last(double bytes, double ops) {
-  if (!on_ || recs_.empty()) return;
+  if (!on_ || skip_ || recs_.empty()) return;
   recs_.back().bytes = bytes;
   recs_.back().ops = ops;
 }
@@ -175,8 +199,11 @@ void KTimer::collect(bm_stats* st) {
     st->kernel_launches[r.kind] += 1;
     st->kernel_bytes[r.kind] += r.bytes;
     st->kernel_ops[r.kind] += r.ops;
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+  }
+  auto& v = t_events[dev_];
+  for (auto& r : recs_) {
+    v.push_back(r.a);
+    v.push_back(r.b);
   }
   recs_.clear();
 }
