@@ -242,8 +242,8 @@ void scan_ge_u32(const uint32_t* in, uint32_t thr, uint64_t* out, uint64_t n, ui
                  hipStream_t s);
 
 // class kernels
-// fp4: the e2m1 MFMA form (64 transactions per instruction, exact FP32 sums of
-// quarters for counts below 2^24); else int8 x int8 -> int32.
+// fp4: the scaled e2m1 MFMA form (64 transactions per instruction, exact FP32
+// integer sums for counts up to 2^24); else int8 x int8 -> int32.
 void launch_gram_mfma(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s);
 // Same contraction with 256 x 256 tiles (tasks index 256-wide blocks).
 void launch_gram_mfma_big(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s);

@@ -1,4 +1,4 @@
-// Pair supports of a prefix class as a masked Gram matrix on int8 MFMA.
+// Pair supports of a prefix class as a masked Gram matrix on MFMA.
 //
 // For a class with prefix P (tidset t(P), the AND of P's columns) and children
 // c_0..c_{q-1}, the support of P + {c_i, c_l} is
@@ -7,20 +7,24 @@
 // for longer itemsets).  Over all pairs this is the Gram matrix
 // X^T X of the 0/1 matrix X[r, i] = t(P)[r] & M[r, c_i]; for the root class
 // (P empty) it is the pair-support matrix A^T A itself.  With 0/1 entries the
-// products are exact in int8 x int8 -> int32 (supports < 2^31).
+// products are exact, in FP4 x FP4 -> FP32 (the default form, below) or in
+// int8 x int8 -> int32.
 //
 // Kernel shape (gfx950, wave64):
 //   * one workgroup = 4 waves computes a 128 x 128 output tile of the class's
 //     triangle over a range of words; waves own 64 x 64 sub-tiles, each a 2 x 2
-//     grid of v_mfma_i32_32x32x32_i8 accumulators;
+//     grid of 32 x 32 MFMA accumulators;
 //   * the bit panels of both tile sides are staged through LDS 16 words
-//     (1024 transactions) at a time, with the prefix mask ANDed in on the way,
+//     (1024 transactions) at a time, with the prefix mask ANDed into the A
+//     side on the way (t & a_i & b_l needs it once; a diagonal tile reads its
+//     masked A panel for both sides),
 //     and the next stage's global loads are issued before the current stage's
 //     MFMAs (software pipelining);
-//   * bits are expanded to int8 in registers right before each MFMA: the lane's
-//     32-bit half-word v yields four dwords (v >> d) & 0x01010101, so each
-//     byte holds one transaction bit.  A and B fragments use the identical
-//     bit -> (lane, byte) map, so every transaction meets itself in the K sum;
+//   * bits become MFMA operands in registers right before each MFMA (FP4
+//     bit planes, or for int8 the lane's 32-bit half-word v yields four dwords
+//     (v >> d) & 0x01010101, one transaction bit per byte).  A and B fragments
+//     use the identical bit -> (lane, element) map, so every transaction meets
+//     itself in the K sum;
 //   * the accumulated tile is added atomically into the class's triangle
 //     (integer adds: exact and independent of the order of word splits).
 #include <type_traits>
@@ -46,26 +50,32 @@ __device__ __forceinline__ v4i expand4(uint32_t v, int d0) {
   return r;
 }
 
-// FP4 (e2m1) form: a lane's 32-bit half-word v becomes 32 nibbles, nibble j of
-// dword d = bit 4j + d of v, each 0 or 0x1 (the e2m1 value 0.5).  One
-// v_mfma_f32_32x32x64_f8f6f4 then sums 64 transactions; every product is 0 or
-// 0.25 and FP32 holds every multiple of 0.25 below 2^22 exactly, so a task's
-// sums are exact while its counts stay below 2^24 -- the task word split is
-// capped at GRAM_FP4_MAX_WORDS for that.
-__device__ __forceinline__ v8i expand_fp4(uint32_t v) {
-  v8i r;
-  r[0] = (int)((v >> 0) & 0x11111111u);
-  r[1] = (int)((v >> 1) & 0x11111111u);
-  r[2] = (int)((v >> 2) & 0x11111111u);
-  r[3] = (int)((v >> 3) & 0x11111111u);
-  r[4] = r[5] = r[6] = r[7] = 0;
-  return r;
+// FP4 (e2m1) form.  The e2m1 codes 0001, 0010 and 0100 are the values 0.5, 1
+// and 2, so one AND turns a 32-bit half-word v into eight FP4 elements that
+// each hold one transaction bit: plane 0 = v & 0x11111111 (bits 0, 4, .., 28
+// as 0.5), plane 1 = v & 0x22222222 (bits 1, 5, .. as 1), plane 2 =
+// v & 0x44444444 (as 2); plane 3 (bits 3, 7, ..) would land on the sign bit,
+// so it is shifted first: (v >> 2) & 0x22222222 (as 1).  One
+// v_mfma_scale_f32_32x32x64_f8f6f4 takes one plane of four consecutive words
+// (a lane's four operand dwords), and its E8M0 block scales (2, 1, 1/2, 1 on
+// both operands) make every product of two set bits exactly 1.0; four MFMAs,
+// one per plane, cover the four words.  A and B use the identical bit ->
+// (lane, element) map, so every transaction meets itself in the K sum.  FP32
+// holds every integer up to 2^24 exactly, so a task's sums are exact while its
+// counts stay at most 2^24 -- the task word split is capped at
+// GRAM_FP4_MAX_WORDS for that.
+__device__ __forceinline__ uint32_t fp4_plane(uint32_t v, int pl) {
+  return pl == 0 ? (v & 0x11111111u)
+       : pl == 1 ? (v & 0x22222222u)
+       : pl == 2 ? (v & 0x44444444u)
+                 : ((v >> 2) & 0x22222222u);
+}
+__device__ __forceinline__ int fp4_plane_scale(int pl) {  // E8M0: 2^(e - 127)
+  return pl == 0 ? 128 : pl == 2 ? 126 : 127;
 }
 
 // NB = 32x32 accumulator blocks per wave side: NB = 2 gives 64x64 per wave and
-// a 128x128 workgroup tile; NB = 4 gives 128x128 per wave (256 accumulator
-// registers, one wave per SIMD) and a 256x256 tile, which halves both the bit
-// expansions per MFMA and the column traffic per output for big classes.
+// a 128x128 workgroup tile of 4 waves.
 // KW = words per LDS stage (a divisor of GRAM_KW, so stages tile every task).
 template <int NB, int KW, bool F4>
 __device__ __forceinline__ void gram_tiles(const ClassArgs& a, uint32_t* sA, uint32_t* sB) {
@@ -141,12 +151,17 @@ __device__ __forceinline__ void gram_tiles(const ClassArgs& a, uint32_t* sA, uin
       for (int p = 0; p < 2 * NS; ++p) {
         if (p < nload) {
           uint32_t* dst = ((p >= NS) ? sB : sA) + (cslot + CSL * (p % NS)) * LDW + 4 * sub;
-          const uint64_t x0 = ((uint64_t)reg[p].x | ((uint64_t)reg[p].y << 32)) & m0;
-          const uint64_t x1 = ((uint64_t)reg[p].z | ((uint64_t)reg[p].w << 32)) & m1;
-          dst[0] = (uint32_t)x0;
-          dst[1] = (uint32_t)(x0 >> 32);
-          dst[2] = (uint32_t)x1;
-          dst[3] = (uint32_t)(x1 >> 32);
+          uint4 v = reg[p];
+          if (pre_len && p < NS) {  // the prefix mask on the A side only: t & a_i & b_l
+            v.x &= (uint32_t)m0;
+            v.y &= (uint32_t)(m0 >> 32);
+            v.z &= (uint32_t)m1;
+            v.w &= (uint32_t)(m1 >> 32);
+          }
+          dst[0] = v.x;
+          dst[1] = v.y;
+          dst[2] = v.z;
+          dst[3] = v.w;
         }
       }
       __syncthreads();
@@ -154,30 +169,50 @@ __device__ __forceinline__ void gram_tiles(const ClassArgs& a, uint32_t* sA, uin
 
       const uint32_t* pa = sA + (wr * (T / 2) + (lane & 31)) * LDW + (lane >> 5);
       const uint32_t* pb = (diag ? sA : sB) + (wc * (T / 2) + (lane & 31)) * LDW + (lane >> 5);
-      // NB = 2: fully unrolled, so the next word's bit expansions overlap this
-      // word's MFMAs (measured 6% faster than unrolling by two)
-#pragma unroll(NB == 2 ? KW : 1)
-      for (int w = 0; w < KW; ++w) {
-        uint32_t va[NB], vb[NB];
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-          va[i] = pa[i * 32 * LDW + 2 * w];
-          vb[i] = pb[i * 32 * LDW + 2 * w];
-        }
-        if constexpr (F4) {
-          v8i A[NB], B[NB];
-#pragma unroll
-          for (int i = 0; i < NB; ++i) {
-            A[i] = expand_fp4(va[i]);
-            B[i] = expand_fp4(vb[i]);
-          }
+      if constexpr (F4) {
+        // NB = 2: fully unrolled, so the next group's plane masks overlap this
+        // group's MFMAs
+#pragma unroll(NB == 2 ? KW / 4 : 1)
+        for (int w4 = 0; w4 < KW; w4 += 4) {
+          uint32_t va[NB][4], vb[NB][4];
 #pragma unroll
           for (int i = 0; i < NB; ++i)
 #pragma unroll
-            for (int j = 0; j < NB; ++j)  // format 4 = e2m1 for both operands, no scaling
-              acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[i], B[j], acc[i][j], 4,
-                                                                          4, 0, 0, 0, 0);
-        } else {
+            for (int j = 0; j < 4; ++j) {
+              va[i][j] = pa[i * 32 * LDW + 2 * (w4 + j)];
+              vb[i][j] = pb[i * 32 * LDW + 2 * (w4 + j)];
+            }
+#pragma unroll
+          for (int pl = 0; pl < 4; ++pl) {
+            v8i A[NB], B[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                A[i][j] = (int)fp4_plane(va[i][j], pl);
+                B[i][j] = (int)fp4_plane(vb[i][j], pl);
+              }
+              A[i][4] = A[i][5] = A[i][6] = A[i][7] = 0;
+              B[i][4] = B[i][5] = B[i][6] = B[i][7] = 0;
+            }
+            const int sc = fp4_plane_scale(pl);
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+              for (int j = 0; j < NB; ++j)  // format 4 = e2m1 for both operands
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                    A[i], B[j], acc[i][j], 4, 4, 0, sc, 0, sc);
+          }
+        }
+      } else {
+#pragma unroll(NB == 2 ? KW : 1)
+        for (int w = 0; w < KW; ++w) {
+          uint32_t va[NB], vb[NB];
+#pragma unroll
+          for (int i = 0; i < NB; ++i) {
+            va[i] = pa[i * 32 * LDW + 2 * w];
+            vb[i] = pb[i * 32 * LDW + 2 * w];
+          }
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
             v4i A[NB], B[NB];
@@ -209,7 +244,7 @@ __device__ __forceinline__ void gram_tiles(const ClassArgs& a, uint32_t* sA, uin
               I0 + wr * (T / 2) + rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
           const uint32_t gl = L0 + wc * (T / 2) + cb * 32 + (lane & 31);
           uint32_t v;
-          if constexpr (F4) v = __float2uint_rn(acc[rb][cb][r] * 4.0f);  // exact: quarters
+          if constexpr (F4) v = __float2uint_rn(acc[rb][cb][r]);  // exact integer counts
           else v = (uint32_t)acc[rb][cb][r];
           if (gi < gl && gl < q && v) atomicAdd(tri + tri_index(gi, gl, q), v);
         }
@@ -224,15 +259,194 @@ __global__ __launch_bounds__(256) void k_gram_mfma(ClassArgs a) {
   gram_tiles<2, KW, F4>(a, sA, sB);
 }
 
-// 8-word stages keep the staging registers at 8 x 16 bytes per thread next to
-// the 256 accumulator registers.
+// Big classes: 256 x 256 output tiles, one workgroup of 8 waves per tile.  A
+// wave owns 64 x 128 (2 x 4 accumulators of 32 x 32, 128 registers), so per
+// word it expands 6 operand rows for 8 MFMAs (the 128-tile kernel: 4 rows for
+// 4), and each staged column serves 256 outputs instead of 128.  One workgroup
+// fills a CU's 8 wave slots at this register use, so the LDS stages are double
+// buffered: stage s is written into buffer s & 1 while the other buffer may
+// still be read, and one barrier per stage suffices -- a buffer is rewritten
+// two stages later, after every wave has passed the barrier that follows its
+// last read.
+constexpr int BT = GRAM_TILE_BIG;   // 256
+constexpr int BKW = 8;              // words per stage
+constexpr int BLDW = 2 * BKW + 1;   // dwords per staged column row (odd: conflict-free reads)
+constexpr int BNT = 512;            // threads
+constexpr int BSUBS = BKW / 2;      // 16-byte slots per column per stage
+constexpr int BCSL = BNT / BSUBS;   // columns staged per pass
+constexpr int BNS = BT / BCSL;      // passes per side
+
 template <bool F4>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void k_gram_mfma_big(ClassArgs a) {
-  constexpr int KW = 8;
-  __shared__ uint32_t sA[GRAM_TILE_BIG * (2 * KW + 1)];
-  __shared__ uint32_t sB[GRAM_TILE_BIG * (2 * KW + 1)];
-  gram_tiles<4, KW, F4>(a, sA, sB);
+__device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint32_t* lds) {
+  static_assert(GRAM_KW % BKW == 0, "stages must tile the task word ranges");
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;  // rows wr*64 .. +63, columns wc*128 .. +127
+  const int sub = tid % BSUBS;
+  const int cslot = tid / BSUBS;
+  const uint64_t ntasks = *a.ntasks;
+  constexpr int SIDE = BT * BLDW;  // dwords of one side of one buffer
+
+  for (uint64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
+    const Task task = a.tasks[t];
+    const ClassDesc cd = a.cls[task.cls];
+    const DbInfo db = a.dbs[cd.db];
+    const uint64_t Wp = db.Wp;
+    const uint32_t q = cd.q;
+    const uint32_t I0 = (uint32_t)task.bi * BT, L0 = (uint32_t)task.bl * BT;
+    const bool diag = task.bi == task.bl;
+    const int nload = diag ? BNS : 2 * BNS;
+
+    const uint64_t* colp[2 * BNS];
+#pragma unroll
+    for (int p = 0; p < 2 * BNS; ++p) {
+      const uint32_t idx = ((p >= BNS) ? L0 : I0) + cslot + BCSL * (p % BNS);
+      colp[p] = nullptr;
+      if (p < nload && idx < q) {
+        const uint32_t item = a.child_item[cd.child0 + idx];
+        const uint32_t col = db.f1 ? db.f1[item] : item;
+        colp[p] = db.B + (uint64_t)col * Wp + 2 * sub;
+      }
+    }
+    const uint32_t* pre = a.pre_cols + cd.pre_off;
+    const uint32_t pre_len = cd.pre_len;
+
+    uint4 reg[2 * BNS];
+    uint64_t m0 = ~0ull, m1 = ~0ull;
+    auto load_stage = [&](uint32_t w) {
+      m0 = ~0ull;
+      m1 = ~0ull;
+      for (uint32_t j = 0; j < pre_len; ++j) {
+        const uint4 x = *reinterpret_cast<const uint4*>(db.B + (uint64_t)pre[j] * Wp + w + 2 * sub);
+        m0 &= (uint64_t)x.x | ((uint64_t)x.y << 32);
+        m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
+      }
+#pragma unroll
+      for (int p = 0; p < 2 * BNS; ++p) {
+        if (colp[p]) reg[p] = *reinterpret_cast<const uint4*>(colp[p] + w);
+        else reg[p] = make_uint4(0, 0, 0, 0);
+      }
+    };
+
+    using Acc = typename std::conditional<F4, v16f, v16i>::type;
+    Acc acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
+
+    // the previous task's last reads of both buffers end before any write
+    __syncthreads();
+    const uint32_t nst = (task.w1 - task.w0) / BKW;
+    if (nst) load_stage(task.w0);
+    for (uint32_t s = 0; s < nst; ++s) {
+      uint32_t* sA = lds + (s & 1) * 2 * SIDE;
+      uint32_t* sB = sA + SIDE;
+#pragma unroll
+      for (int p = 0; p < 2 * BNS; ++p) {
+        if (p < nload) {
+          uint32_t* dst = ((p >= BNS) ? sB : sA) + (cslot + BCSL * (p % BNS)) * BLDW + 4 * sub;
+          uint4 v = reg[p];
+          if (pre_len && p < BNS) {  // the prefix mask on the A side only: t & a_i & b_l
+            v.x &= (uint32_t)m0;
+            v.y &= (uint32_t)(m0 >> 32);
+            v.z &= (uint32_t)m1;
+            v.w &= (uint32_t)(m1 >> 32);
+          }
+          dst[0] = v.x;
+          dst[1] = v.y;
+          dst[2] = v.z;
+          dst[3] = v.w;
+        }
+      }
+      __syncthreads();
+      if (s + 1 < nst) load_stage(task.w0 + (s + 1) * BKW);
+
+      const uint32_t* pa = sA + (wr * 64 + (lane & 31)) * BLDW + (lane >> 5);
+      const uint32_t* pb = (diag ? sA : sB) + (wc * 128 + (lane & 31)) * BLDW + (lane >> 5);
+      if constexpr (F4) {
+#pragma unroll
+        for (int w4 = 0; w4 < BKW; w4 += 4) {
+          uint32_t va[2][4], vb[4][4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) va[i][j] = pa[i * 32 * BLDW + 2 * (w4 + j)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) vb[i][j] = pb[i * 32 * BLDW + 2 * (w4 + j)];
+          }
+#pragma unroll
+          for (int pl = 0; pl < 4; ++pl) {
+            v8i A[2], B[4];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+#pragma unroll
+              for (int j = 0; j < 4; ++j) A[i][j] = (int)fp4_plane(va[i][j], pl);
+              A[i][4] = A[i][5] = A[i][6] = A[i][7] = 0;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+#pragma unroll
+              for (int j = 0; j < 4; ++j) B[i][j] = (int)fp4_plane(vb[i][j], pl);
+              B[i][4] = B[i][5] = B[i][6] = B[i][7] = 0;
+            }
+            const int sc = fp4_plane_scale(pl);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                    A[i], B[j], acc[i][j], 4, 4, 0, sc, 0, sc);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int w = 0; w < BKW; ++w) {
+          uint32_t va[2], vb[4];
+#pragma unroll
+          for (int i = 0; i < 2; ++i) va[i] = pa[i * 32 * BLDW + 2 * w];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) vb[i] = pb[i * 32 * BLDW + 2 * w];
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            v4i A[2], B[4];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) A[i] = expand4(va[i], 4 * e);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) B[i] = expand4(vb[i], 4 * e);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i], B[j], acc[i][j], 0, 0, 0);
+          }
+        }
+      }
+    }
+
+    uint32_t* tri = a.tri + cd.tri_off;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const uint32_t gi = I0 + wr * 64 + rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const uint32_t gl = L0 + wc * 128 + cb * 32 + (lane & 31);
+          uint32_t v;
+          if constexpr (F4) v = __float2uint_rn(acc[rb][cb][r]);
+          else v = (uint32_t)acc[rb][cb][r];
+          if (gi < gl && gl < q && v) atomicAdd(tri + tri_index(gi, gl, q), v);
+        }
+  }
+}
+
+template <bool F4>
+__global__ __launch_bounds__(BNT) void k_gram_mfma_big(ClassArgs a) {
+  __shared__ uint32_t lds[2 * 2 * BT * BLDW];
+  gram_tiles_big<F4>(a, lds);
 }
 
 }  // namespace
@@ -246,8 +460,8 @@ void launch_gram_mfma(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s
 
 void launch_gram_mfma_big(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s) {
   if (grid == 0) return;
-  if (fp4) k_gram_mfma_big<true><<<grid, 256, 0, s>>>(a);
-  else k_gram_mfma_big<false><<<grid, 256, 0, s>>>(a);
+  if (fp4) k_gram_mfma_big<true><<<grid, BNT, 0, s>>>(a);
+  else k_gram_mfma_big<false><<<grid, BNT, 0, s>>>(a);
   BM_LAUNCH_CHECK();
 }
 
