@@ -111,8 +111,8 @@ DTYPE = {"fp4": "u64 bitsets; fp4 (e2m1) MFMA, fp32 accumulate (exact: counts < 
 # (workload, kernel, form) -> (sha256 of the source file, bytes per launch).
 TRAFFIC = {
     # dense_planted 1M x 4,096 (profiles/dense_planted_1M_hbm_traffic.md)
-    (3, "gram_mfma", "fp4"): ("d66279cae0f0c385038ef967550f07e491dd1be79a4250318ddc41589b7a22dc", 2773.3e6),
-    (3, "andpop_reg", "fp4"): ("c0555966d5ffedb8a7bc270f39fe9960f402066224424f67f9902b659f1d0f46", 542.6e6),
+    (3, "gram_mfma", "fp4"): ("516f0a7347803fe86ad3cae8bbf2c0b03d7b4a52d3b4d1d339465b2d9c4cf3e1", 2778.7e6),
+    (3, "andpop_reg", "fp4"): ("29d6103342951cee0aaee29ca2a37e34e3c93ca6b3f31f2840111dcbe41caa56", 551.7e6),
     (3, "gram_small", "fp4"): ("b72a42d014a78320b850165b51eb79887bf398287b88b7b726bb78c59dd610f0", 129.4e6),
 }
 KERNEL_SOURCE = {
