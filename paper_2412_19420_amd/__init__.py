@@ -185,7 +185,7 @@ def options(flags: int = 0, mfma_min_children: int = 0, andpop_chunk_words: int 
 
 def bm_build(row_ptr, col_idx, n_tx: int, n_items: int, stream=None) -> Db:
     rp, k1 = _bm._ptr(row_ptr, np.uint64)
-    ci, k2 = _bm._ptr(col_idx, np.uint32) if col_idx is not None and len(col_idx) else (ctypes.c_void_p(0), None)
+    ci, k2 = _bm._ptr(col_idx, np.uint32) if col_idx is not None and _bm._nelem(col_idx) else (ctypes.c_void_p(0), None)
     h = ctypes.c_void_p()
     _bm.check(_bm.lib.bm_build(rp, ci, n_tx, n_items, _bm._stream_ptr(stream), ctypes.byref(h)),
               "bm_build")
@@ -213,7 +213,7 @@ def bm_build_batch(items, stream=None) -> list:
         p, k = _bm._ptr(rp, np.uint64)
         rps[i] = p.value
         keep.append(k)
-        if ci is not None and len(ci):
+        if ci is not None and _bm._nelem(ci):
             p, k = _bm._ptr(ci, np.uint32)
             cis[i] = p.value
             keep.append(k)

@@ -23,9 +23,9 @@ if not os.path.exists(LIB_PATH):
 # so that the library binds to that same runtime: the two then share one device
 # context, and torch streams and tensors can be passed across the boundary.
 try:
-    import torch  # noqa: F401
+    import torch as _torch
 except ImportError:
-    pass
+    _torch = None
 
 lib = ctypes.CDLL(LIB_PATH)
 
@@ -182,20 +182,27 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+_TORCH_DTYPE = ({np.uint64: _torch.uint64, np.uint32: _torch.uint32, np.int64: _torch.int64}
+                if _torch is not None else {})
+
+
+def _nelem(a) -> int:
+    """Element count of a numpy array or torch tensor (numel: len() of a tensor is slow)."""
+    if _torch is not None and isinstance(a, _torch.Tensor):
+        return a.numel()
+    return len(a)
+
+
 def _ptr(a, dtype):
     """(pointer, keepalive) of a numpy array or torch tensor with the given element dtype."""
     if a is None:
         return ctypes.c_void_p(0), None
-    try:
-        import torch
-        if isinstance(a, torch.Tensor):
-            want = {np.uint64: torch.uint64, np.uint32: torch.uint32, np.int64: torch.int64}[dtype]
-            if a.dtype != want:
-                raise TypeError(f"tensor dtype {a.dtype}, expected {want}")
-            if not a.is_contiguous():
-                raise ValueError("tensor must be contiguous")
-            return ctypes.c_void_p(a.data_ptr()), a
-    except ImportError:
-        pass
+    if _torch is not None and isinstance(a, _torch.Tensor):
+        want = _TORCH_DTYPE[dtype]
+        if a.dtype != want:
+            raise TypeError(f"tensor dtype {a.dtype}, expected {want}")
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(a.data_ptr()), a
     arr = np.ascontiguousarray(a, dtype=dtype)
     return ctypes.c_void_p(arr.ctypes.data), arr

@@ -237,6 +237,10 @@ struct GatherU64 {
 };
 void launch_gather_u64(const GatherU64& g, int count, uint64_t* dst, hipStream_t s);
 bool scan_multi_single(const ScanMulti& sm, int count, uint64_t n, hipStream_t s);
+// The same (zero, ge, tot and extra included) for long arrays in three launches;
+// tmp holds scan_tiles_tmp_words(count, n) words.  False if n is 0 or too long.
+size_t scan_tiles_tmp_words(int count, uint64_t n);
+bool scan_multi_tiles(const ScanMulti& sm, int count, uint64_t n, uint64_t* tmp, hipStream_t s);
 // out[0..n]: exclusive scan of (in[i] >= thr)
 void scan_ge_u32(const uint32_t* in, uint32_t thr, uint64_t* out, uint64_t n, uint64_t* tmp,
                  hipStream_t s);

@@ -461,6 +461,102 @@ __global__ __launch_bounds__(kSingleThreads) void k_scan_single(ScanMulti sm, ui
   }
 }
 
+// Element i of array a of a ScanMulti: 64-bit, 32-bit, or a 32-bit threshold flag.
+__device__ __forceinline__ uint64_t scan_elem(const ScanMulti& sm, int a, uint64_t i) {
+  if (sm.is64[a]) return static_cast<const uint64_t*>(sm.in[a])[i];
+  const uint32_t y = static_cast<const uint32_t*>(sm.in[a])[i];
+  const uint32_t ge = sm.ge[a];
+  return ge ? (y >= ge ? 1u : 0u) : y;
+}
+
+// Three-launch scan of up to 8 arrays of any length (grid.y = array): tiles of
+// kTileScan elements are scanned locally and their totals kept (1), one
+// workgroup per array scans the totals (2, k_scan_single), and each tile adds
+// its offset and the totals are written (3).
+constexpr int kTilePer = 8;
+constexpr int kTileScan = kThreads * kTilePer;
+
+__global__ __launch_bounds__(kThreads) void k_scan_tiles(ScanMulti sm, uint64_t n,
+                                                          uint64_t* __restrict__ sums, uint32_t nb) {
+  __shared__ uint64_t s_wave[kThreads / 64];
+  const int a = blockIdx.y;
+  const uint32_t b = blockIdx.x;
+  if (a == 0 && b == 0)
+    for (uint32_t j = threadIdx.x; j < sm.nzero; j += kThreads) sm.zero[j] = 0;
+  const uint64_t i0 = (uint64_t)b * kTileScan + (uint64_t)threadIdx.x * kTilePer;
+  uint64_t* out = sm.out[a];
+  // a thread's 8 elements are contiguous: 16-byte accesses when the arrays
+  // are 16-byte aligned and the 8 are all inside
+  const bool vec = i0 + kTilePer <= n &&
+                   ((reinterpret_cast<uintptr_t>(sm.in[a]) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+  uint64_t v[kTilePer];
+  uint64_t t = 0;
+  if (vec) {
+    if (sm.is64[a]) {
+      const uint4* q = reinterpret_cast<const uint4*>(static_cast<const uint64_t*>(sm.in[a]) + i0);
+#pragma unroll
+      for (int k = 0; k < kTilePer / 2; ++k) {
+        const uint4 x = q[k];
+        v[2 * k] = (uint64_t)x.x | ((uint64_t)x.y << 32);
+        v[2 * k + 1] = (uint64_t)x.z | ((uint64_t)x.w << 32);
+      }
+    } else {
+      const uint4* q = reinterpret_cast<const uint4*>(static_cast<const uint32_t*>(sm.in[a]) + i0);
+      const uint32_t ge = sm.ge[a];
+#pragma unroll
+      for (int k = 0; k < kTilePer / 4; ++k) {
+        const uint4 x = q[k];
+        const uint32_t y[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[4 * k + e] = ge ? (y[e] >= ge ? 1u : 0u) : y[e];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kTilePer; ++k) v[k] = i0 + k < n ? scan_elem(sm, a, i0 + k) : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kTilePer; ++k) t += v[k];
+  uint64_t total;
+  uint64_t ex = block_exclusive_scan(t, s_wave, &total);
+  if (vec) {
+    uint4* q = reinterpret_cast<uint4*>(out + i0);
+#pragma unroll
+    for (int k = 0; k < kTilePer / 2; ++k) {
+      const uint64_t e0 = ex, e1 = ex + v[2 * k];
+      ex = e1 + v[2 * k + 1];
+      q[k] = make_uint4((uint32_t)e0, (uint32_t)(e0 >> 32), (uint32_t)e1, (uint32_t)(e1 >> 32));
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kTilePer; ++k) {
+      if (i0 + k < n) out[i0 + k] = ex;
+      ex += v[k];
+    }
+  }
+  if (threadIdx.x == 0) sums[(uint64_t)a * nb + b] = total;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_tiles_add(ScanMulti sm, uint64_t n,
+                                                              const uint64_t* __restrict__ soff,
+                                                              uint32_t nb) {
+  const int a = blockIdx.y;
+  const uint32_t b = blockIdx.x;
+  const uint64_t* so = soff + (uint64_t)a * (nb + 1);
+  const uint64_t add = so[b];
+  uint64_t* out = sm.out[a];
+  const uint64_t base = (uint64_t)b * kTileScan;
+  if (add)
+    for (int k = threadIdx.x; k < kTileScan; k += kThreads)
+      if (base + k < n) out[base + k] += add;
+  if (b == 0 && threadIdx.x == 0) {
+    out[n] = so[nb];
+    if (sm.tot) sm.tot[a] = so[nb];
+  }
+  if (a == 0 && b == 0 && sm.tot)
+    for (uint32_t j = threadIdx.x; j < sm.nextra; j += kThreads) sm.tot[gridDim.y + j] = sm.extra[j];
+}
+
 __global__ void k_gather_u64(GatherU64 g, int count, uint64_t* __restrict__ dst) {
   const int i = threadIdx.x;
   if (i < count) dst[i] = *g.src[i];
@@ -478,6 +574,31 @@ size_t scan_tmp_words(uint64_t n) {
   uint64_t nb = (n + kScanBlock - 1) / kScanBlock;
   if (nb == 1) return 2;
   return 2 * (nb + 1) + scan_tmp_words(nb);
+}
+
+size_t scan_tiles_tmp_words(int count, uint64_t n) {
+  const uint64_t nb = (n + kTileScan - 1) / kTileScan;
+  return (size_t)count * (2 * nb + 1);
+}
+
+bool scan_multi_tiles(const ScanMulti& sm, int count, uint64_t n, uint64_t* tmp, hipStream_t s) {
+  const uint64_t nb = (n + kTileScan - 1) / kTileScan;
+  if (n == 0 || nb > kSingleMaxN || count < 1 || count > 8) return false;
+  uint64_t* sums = tmp;
+  uint64_t* soff = tmp + (size_t)count * nb;
+  k_scan_tiles<<<dim3((uint32_t)nb, count), kThreads, 0, s>>>(sm, n, sums, (uint32_t)nb);
+  BM_LAUNCH_CHECK();
+  ScanMulti st{};
+  for (int a = 0; a < count; ++a) {
+    st.in[a] = sums + (size_t)a * nb;
+    st.is64[a] = 1;
+    st.out[a] = soff + (size_t)a * (nb + 1);
+  }
+  k_scan_single<<<count, kSingleThreads, 0, s>>>(st, nb);
+  BM_LAUNCH_CHECK();
+  k_scan_tiles_add<<<dim3((uint32_t)nb, count), kThreads, 0, s>>>(sm, n, soff, (uint32_t)nb);
+  BM_LAUNCH_CHECK();
+  return true;
 }
 
 bool scan_multi_single(const ScanMulti& sm, int count, uint64_t n, hipStream_t s) {

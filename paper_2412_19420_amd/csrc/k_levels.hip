@@ -16,6 +16,8 @@
 //     comes out already sorted;
 //   * a node with c >= 2 frequent children becomes a class of the next step.
 #include "internal.hpp"
+#include <algorithm>
+
 #include "levels.hpp"
 #include "dfs.hpp"
 
@@ -67,11 +69,16 @@ __global__ void k_f1_fill(const uint32_t* __restrict__ flags, const uint64_t* __
 }
 
 // Level 1: every frequent item is a node whose parent is its database's root.
-__global__ void k_init_level1(const DbInfo* __restrict__ dbs, uint32_t ndb,
+__global__ void k_init_level1(DbInfo* __restrict__ dbs, uint32_t ndb,
                               const uint64_t* __restrict__ f1_base, uint64_t n1,
                               const uint32_t* __restrict__ f1, uint32_t* __restrict__ item,
                               uint32_t* __restrict__ parent, uint32_t* __restrict__ supp,
                               uint32_t* __restrict__ ndbv) {
+  // each database's table entry gets its slice of the frequent-item list (no
+  // thread of this kernel reads that field)
+  for (uint64_t d = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; d < ndb;
+       d += (uint64_t)gridDim.x * blockDim.x)
+    dbs[d].f1 = f1 + f1_base[d];
   for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n1;
        x += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t d = db_of(f1_base, ndb, x);
@@ -306,7 +313,7 @@ __global__ void k_class_task_counts(const ClassDesc* __restrict__ cls, uint64_t 
   }
 }
 
-// Wave per class: write its tasks at the scanned offsets (with dfs set, small
+// Workgroup per class: write its tasks at the scanned offsets (with dfs set, small
 // classes become depth-first subtree tasks whose children are level `level`).
 __global__ void k_write_class_tasks(const ClassDesc* __restrict__ cls, uint64_t ncls,
                                     const DbInfo* __restrict__ dbs, uint32_t mfma_min_q,
@@ -317,10 +324,9 @@ __global__ void k_write_class_tasks(const ClassDesc* __restrict__ cls, uint64_t 
                                     uint32_t level, const uint64_t* __restrict__ ob,
                                     Task* __restrict__ tb, const uint64_t* __restrict__ os,
                                     Task* __restrict__ ts) {
-  const int lane = threadIdx.x & 63;
-  const uint64_t wave0 = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t c = wave0; c < ncls; c += nwaves) {
+  // a workgroup per class: a big class has thousands of tasks
+  const int lane = threadIdx.x;
+  for (uint64_t c = blockIdx.x; c < ncls; c += gridDim.x) {
     const ClassDesc cd = cls[c];
     const ClassWork w = class_work(cd, dbs[cd.db], mfma_min_q, geo);
     if (w.kind == 2 && dt) {
@@ -341,7 +347,8 @@ __global__ void k_write_class_tasks(const ClassDesc* __restrict__ cls, uint64_t 
                 : w.kind == 2 ? tt + ot[c]
                 : w.kind == 3 ? tb + ob[c]
                               : ts + os[c];
-    write_tasks((uint32_t)c, cd.q, w.npairs, w.block, w.nsplit, w.split, w.wend, out, lane, 64);
+    write_tasks((uint32_t)c, cd.q, w.npairs, w.block, w.nsplit, w.split, w.wend, out, lane,
+                (int)blockDim.x);
   }
 }
 
@@ -497,12 +504,12 @@ void launch_f1_fill(const uint32_t* flags, const uint64_t* pos, uint32_t ndb,
   BM_LAUNCH_CHECK();
 }
 
-void launch_init_level1(const DbInfo* dbs, uint32_t ndb, const uint64_t* f1_base, uint64_t n1,
+void launch_init_level1(DbInfo* dbs, uint32_t ndb, const uint64_t* f1_base, uint64_t n1,
                         const uint32_t* f1, uint32_t* item, uint32_t* parent, uint32_t* supp,
                         uint32_t* ndbv, hipStream_t s) {
-  if (n1 == 0) return;
-  k_init_level1<<<grid_for(n1, kThreads), kThreads, 0, s>>>(dbs, ndb, f1_base, n1, f1, item, parent,
-                                                             supp, ndbv);
+  if (n1 == 0 && ndb == 0) return;
+  k_init_level1<<<grid_for(std::max<uint64_t>(n1, ndb), kThreads), kThreads, 0, s>>>(
+      dbs, ndb, f1_base, n1, f1, item, parent, supp, ndbv);
   BM_LAUNCH_CHECK();
 }
 
@@ -557,7 +564,7 @@ void launch_write_class_tasks(const ClassDesc* cls, uint64_t ncls, const DbInfo*
                               DfsTask* dt, uint32_t level, const uint64_t* ob, Task* tb,
                               const uint64_t* os, Task* ts, hipStream_t s) {
   if (ncls == 0) return;
-  k_write_class_tasks<<<grid_for(ncls * 64, kThreads), kThreads, 0, s>>>(
+  k_write_class_tasks<<<grid_for(ncls, 1), kThreads, 0, s>>>(
       cls, ncls, dbs, mfma_min_q, geo, om, ov, ot, tm, tv, tt, dt, level, ob, tb, os, ts);
   BM_LAUNCH_CHECK();
 }

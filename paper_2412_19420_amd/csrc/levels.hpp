@@ -53,7 +53,8 @@ void launch_f1_flags(const DbInfo* dbs, uint32_t ndb, const uint64_t* item_base,
                      uint32_t* flags, hipStream_t s);
 void launch_f1_fill(const uint32_t* flags, const uint64_t* pos, uint32_t ndb,
                     const uint64_t* item_base, uint64_t total, uint32_t* f1, hipStream_t s);
-void launch_init_level1(const DbInfo* dbs, uint32_t ndb, const uint64_t* f1_base, uint64_t n1,
+// Level 1 of every database; also sets each table entry's f1 slice.
+void launch_init_level1(DbInfo* dbs, uint32_t ndb, const uint64_t* f1_base, uint64_t n1,
                         const uint32_t* f1, uint32_t* item, uint32_t* parent, uint32_t* supp,
                         uint32_t* ndbv, hipStream_t s);
 // out[i] = arr[idx[i]], i < k; also into out2 (e.g. mapped host memory) when not NULL.

@@ -154,30 +154,46 @@ void upload(T* dst, const std::vector<T>& src, hipStream_t s) {
 }
 
 // Up to this length one workgroup scans an array in a single launch (a few
-// looped chunks) faster than the three-launch block scan.
+// looped chunks); longer arrays take the three-launch tiled scan.
 constexpr uint64_t kOneLaunchScan = 16384;
 
-void scan32(const uint32_t* in, uint64_t* out, uint64_t n, hipStream_t s) {
-  if (n <= kOneLaunchScan) {
-    ScanMulti sm{};
-    sm.in[0] = in;
-    sm.is64[0] = 0;
-    sm.out[0] = out;
-    if (scan_multi_single(sm, 1, n, s)) return;
+// Exclusive scans of sm's count arrays of length n (out[j][n] = total), with
+// sm's zeroing, threshold and totals options.
+void scan_arrays(const ScanMulti& sm, int count, uint64_t n, hipStream_t s) {
+  if (n <= kOneLaunchScan && scan_multi_single(sm, count, n, s)) return;
+  {
+    TBuf<uint64_t> tmp(scan_tiles_tmp_words(count, n), s);
+    if (scan_multi_tiles(sm, count, n, tmp.get(), s)) return;
   }
+  // more than 2^18 tiles: one recursive block scan per array
+  if (sm.nzero) launch_fill_u64(sm.zero, 0, sm.nzero, s);
   TBuf<uint64_t> tmp(scan_tmp_words(n), s);
-  scan_u32_to_u64(in, out, n, tmp.get(), s);
+  for (int j = 0; j < count; ++j) {
+    if (sm.is64[j]) scan_u64(static_cast<const uint64_t*>(sm.in[j]), sm.out[j], n, tmp.get(), s);
+    else if (sm.ge[j])
+      scan_ge_u32(static_cast<const uint32_t*>(sm.in[j]), sm.ge[j], sm.out[j], n, tmp.get(), s);
+    else scan_u32_to_u64(static_cast<const uint32_t*>(sm.in[j]), sm.out[j], n, tmp.get(), s);
+  }
+  if (sm.tot) {
+    GatherU64 g{};
+    for (int j = 0; j < count; ++j) g.src[j] = sm.out[j] + n;
+    for (uint32_t e = 0; e < sm.nextra; ++e) g.src[count + e] = sm.extra + e;
+    launch_gather_u64(g, count + (int)sm.nextra, sm.tot, s);
+  }
+}
+
+void scan32(const uint32_t* in, uint64_t* out, uint64_t n, hipStream_t s) {
+  ScanMulti sm{};
+  sm.in[0] = in;
+  sm.out[0] = out;
+  scan_arrays(sm, 1, n, s);
 }
 void scan64(const uint64_t* in, uint64_t* out, uint64_t n, hipStream_t s) {
-  if (n <= kOneLaunchScan) {
-    ScanMulti sm{};
-    sm.in[0] = in;
-    sm.is64[0] = 1;
-    sm.out[0] = out;
-    if (scan_multi_single(sm, 1, n, s)) return;
-  }
-  TBuf<uint64_t> tmp(scan_tmp_words(n), s);
-  scan_u64(in, out, n, tmp.get(), s);
+  ScanMulti sm{};
+  sm.in[0] = in;
+  sm.is64[0] = 1;
+  sm.out[0] = out;
+  scan_arrays(sm, 1, n, s);
 }
 // Scan of up to 8 same-length arrays (is64[j]: element type of in[j]).
 void scan_many(const void* const* in, const bool* is64, uint64_t* const* out, int count, uint64_t n,
@@ -188,11 +204,7 @@ void scan_many(const void* const* in, const bool* is64, uint64_t* const* out, in
     sm.is64[j] = is64[j] ? 1u : 0u;
     sm.out[j] = out[j];
   }
-  if (scan_multi_single(sm, count, n, s)) return;
-  for (int j = 0; j < count; ++j) {
-    if (is64[j]) scan64(static_cast<const uint64_t*>(in[j]), out[j], n, s);
-    else scan32(static_cast<const uint32_t*>(in[j]), out[j], n, s);
-  }
+  scan_arrays(sm, count, n, s);
 }
 
 // scan_many that also writes the totals to tot[0..count) and then
@@ -209,12 +221,7 @@ void scan_many_tot(const void* const* in, const bool* is64, uint64_t* const* out
   sm.tot = tot;
   sm.extra = extra;
   sm.nextra = nextra;
-  if (scan_multi_single(sm, count, n, s)) return;
-  scan_many(in, is64, out, count, n, s);
-  GatherU64 g{};
-  for (int j = 0; j < count; ++j) g.src[j] = out[j] + n;
-  for (uint32_t e = 0; e < nextra; ++e) g.src[count + e] = extra + e;
-  launch_gather_u64(g, count + (int)nextra, tot, s);
+  scan_arrays(sm, count, n, s);
 }
 
 uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
@@ -674,7 +681,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
   {
     CallScope scope(s);
     // ---- database table
-    std::vector<DbInfo> hdb(N), hdb2(N);
+    std::vector<DbInfo> hdb(N);
     std::vector<uint64_t> item_base(N + 1, 0);
     uint64_t Wmax = 1;
     double sumW = 0, sumN = 0;
@@ -702,10 +709,18 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       else if (uniform_thr != minsups[d]) uniform_thr = 0xffffffffu;
     }
     if (uniform_thr == 0xffffffffu) uniform_thr = 0;
-    TBuf<DbInfo> ddb(std::max<uint32_t>(N, 1), s);
-    upload(ddb.get(), hdb, s);
-    TBuf<uint64_t> dibase(N + 1, s);
-    upload(dibase.get(), item_base, s);
+    // the database table and the item bases in one upload
+    static_assert(sizeof(DbInfo) % 8 == 0, "DbInfo is a whole number of words");
+    const size_t tab_words = std::max<uint32_t>(N, 1) * (sizeof(DbInfo) / 8);
+    TBuf<uint64_t> tables(tab_words + N + 1, s);
+    {
+      uint64_t* st_h = pinned_array<uint64_t>(tab_words + N + 1);
+      std::memcpy(st_h, hdb.data(), N * sizeof(DbInfo));
+      std::memcpy(st_h + tab_words, item_base.data(), (N + 1) * 8);
+      BM_HIP(hipMemcpyAsync(tables.get(), st_h, (tab_words + N + 1) * 8, hipMemcpyHostToDevice, s));
+    }
+    DbInfo* const ddb_p = reinterpret_cast<DbInfo*>(tables.get());
+    const uint64_t* const dibase_p = tables.get() + tab_words;
     const uint64_t total_items = item_base[N];
 
     // ---- frequent single items of every database
@@ -717,10 +732,10 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       tm.begin(BM_K_LEVEL);
       TBuf<uint32_t> fl(total_items, s);
       TBuf<uint64_t> pos(total_items + 1, s);
-      launch_f1_flags(ddb.get(), N, dibase.get(), total_items, fl.get(), s);
+      launch_f1_flags(ddb_p, N, dibase_p, total_items, fl.get(), s);
       scan32(fl.get(), pos.get(), total_items, s);
       uint64_t* pf1 = pinned_array<uint64_t>(N + 1);
-      launch_gather_idx(pos.get(), dibase.get(), N + 1, dfb.get(), mapped(pf1), s);
+      launch_gather_idx(pos.get(), dibase_p, N + 1, dfb.get(), mapped(pf1), s);
       tm.end();
       BM_HIP(hipStreamSynchronize(s));
       std::copy(pf1, pf1 + N + 1, f1_base.begin());
@@ -729,19 +744,14 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       if (M1 > 0) {
         tm.begin(BM_K_LEVEL);
         f1.alloc(M1, s);
-        launch_f1_fill(fl.get(), pos.get(), N, dibase.get(), total_items, f1.get(), s);
-        for (uint32_t d = 0; d < N; ++d) {
-          hdb2[d] = hdb[d];
-          hdb2[d].f1 = f1.get() + f1_base[d];
-        }
-        upload(ddb.get(), hdb2, s);
+        launch_f1_fill(fl.get(), pos.get(), N, dibase_p, total_items, f1.get(), s);
         L.emplace_back();
         L[1].n = M1;
         L[1].item.alloc(M1, s);
         L[1].parent.alloc(M1, s);
         L[1].supp.alloc(M1, s);
         L[1].db.alloc(M1, s);
-        launch_init_level1(ddb.get(), N, dfb.get(), M1, f1.get(), L[1].item.get(), L[1].parent.get(),
+        launch_init_level1(ddb_p, N, dfb.get(), M1, f1.get(), L[1].item.get(), L[1].parent.get(),
                            L[1].supp.get(), L[1].db.get(), s);
         tm.end();
       }
@@ -771,7 +781,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       TBuf<int32_t> pcls_prev(hpcls.size(), s);
       upload(pcls_prev.get(), hpcls, s);
       auto w = std::make_unique<StepWork>();
-      host_classes(*w, roots, ddb.get(), Wmax, tu, tu.dfs, s);
+      host_classes(*w, roots, ddb_p, Wmax, tu, tu.dfs, s);
       uint32_t k = 1;
       for (;;) {
         const uint64_t nk = L[k].n;
@@ -782,7 +792,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         step_pre[k] = w->pre.get();
         st.classes_mfma += w->st[ST_CLS_M] + w->st[ST_CLS_B] + w->st[ST_CLS_S];
         st.classes_andpop += w->st[ST_CLS_V] + w->st[ST_CLS_T];
-        run_class_kernels(ddb.get(), L[k].item.get(), *w, tu, nW, nN, tm, s);
+        run_class_kernels(ddb_p, L[k].item.get(), *w, tu, nW, nN, tm, s);
 
         tm.begin(BM_K_LEVEL);
         // S = exclusive scan of the frequent flags of this step's candidates;
@@ -790,25 +800,22 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         TBuf<uint64_t> S(w->T + 1, s);
         TBuf<unsigned long long> dst(ST_COUNT, s);
         uint64_t* dst64 = reinterpret_cast<uint64_t*>(dst.get());
-        if (uniform_thr && w->T <= kOneLaunchScan) {
+        {
           ScanMulti sm{};
-          sm.in[0] = w->tri.get();
           sm.out[0] = S.get();
-          sm.ge[0] = uniform_thr;
           sm.zero = dst64;
           sm.nzero = ST_COUNT;
-          if (!scan_multi_single(sm, 1, w->T, s)) fail(BM_ERR_DEVICE, "candidate scan");
-        } else {
-          launch_fill_u64(dst64, 0, ST_COUNT, s);
-          TBuf<uint64_t> tmp(scan_tmp_words(w->T), s);
+          TBuf<uint32_t> tfl;
           if (uniform_thr) {
-            scan_ge_u32(w->tri.get(), uniform_thr, S.get(), w->T, tmp.get(), s);
+            sm.in[0] = w->tri.get();
+            sm.ge[0] = uniform_thr;
           } else {
-            TBuf<uint32_t> tfl(w->T, s);
-            launch_tri_flags(w->cls.get(), w->ncls, ddb.get(), w->tri.get(), w->T, uniform_thr,
+            tfl.alloc(w->T, s);
+            launch_tri_flags(w->cls.get(), w->ncls, ddb_p, w->tri.get(), w->T, uniform_thr,
                              tfl.get(), s);
-            scan_u32_to_u64(tfl.get(), S.get(), w->T, tmp.get(), s);
+            sm.in[0] = tfl.get();
           }
+          scan_arrays(sm, 1, w->T, s);
         }
         TBuf<uint32_t> cnt(nk, s), iscls(nk, s), pm(nk, s), pv(nk, s), pt(nk, s);
         TBuf<uint64_t> trisz(nk, s);
@@ -846,7 +853,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         lp.parent = L[k].parent.get();
         lp.pcls = pcls_prev.get();
         lp.cls = w->cls.get();
-        lp.dbs = ddb.get();
+        lp.dbs = ddb_p;
         lp.child_item = L[k].item.get();
         lp.tri = w->tri.get();
         lp.S = S.get();
@@ -885,7 +892,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
           lp.lv.parent[j] = L[j].parent.get();
         }
         launch_level_post(lp, s);
-        prepare_tasks(*nw, ddb.get(), Wmax, PM, PV, PT, tu, tu.dfs, k + 1, s);
+        prepare_tasks(*nw, ddb_p, Wmax, PM, PV, PT, tu, tu.dfs, k + 1, s);
         tm.end();
         w = std::move(nw);
         pcls_prev = pcls_k;
@@ -914,7 +921,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       if (sched || trace) {
         feats.alloc(D * MLP_IN, s);
         FeatArgs fa{};
-        fa.dbs = ddb.get();
+        fa.dbs = ddb_p;
         fa.tasks = tasks.get();
         fa.ntasks = (uint32_t)D;
         for (uint32_t j = 1; j <= Kls; ++j) {
@@ -958,7 +965,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         qshort.alloc(D, s);
         qlong.alloc(D, s);
         qcnt.alloc(2, s);
-        launch_dfs_short_flags(tasks.get(), ddb.get(), order.get(), (uint32_t)D, tu.dfs_wave_words,
+        launch_dfs_short_flags(tasks.get(), ddb_p, order.get(), (uint32_t)D, tu.dfs_wave_words,
                                qflag.get(), s);
         scan32(qflag.get(), qpos.get(), D, s);
         launch_dfs_split(order.get(), (uint32_t)D, qflag.get(), qpos.get(), qshort.get(), qlong.get(),
@@ -989,7 +996,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         launch_fill_u32(dflags.get(), 0, 1, s);
         launch_fill_u64(reinterpret_cast<uint64_t*>(lstat.get()), 0, hstat.size(), s);
         DfsArgs da{};
-        da.dbs = ddb.get();
+        da.dbs = ddb_p;
         da.tasks = tasks.get();
         da.ntasks = (uint32_t)D;
         da.order = order.get();
@@ -1145,7 +1152,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       ea.base[K + 1] = acc;
       const size_t rows = (size_t)N + 1, nhb = (size_t)(K + 1) * rows;
       uint64_t* phb = pinned_array<uint64_t>(nhb + 2 * rows);
-      ea.dbs = ddb.get();
+      ea.dbs = ddb_p;
       ea.first_root = dfb.get();
       ea.o_off = store->offsets.get();
       ea.o_items = store->items.get();
