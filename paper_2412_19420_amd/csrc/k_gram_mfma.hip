@@ -259,25 +259,24 @@ __global__ __launch_bounds__(256) void k_gram_mfma(ClassArgs a) {
   gram_tiles<2, KW, F4>(a, sA, sB);
 }
 
-// Big classes: 256 x 256 output tiles, one workgroup of 8 waves per tile.  A
-// wave owns 64 x 128 (2 x 4 accumulators of 32 x 32, 128 registers), so per
-// word it expands 6 operand rows for 8 MFMAs (the 128-tile kernel: 4 rows for
-// 4), and each staged column serves 256 outputs instead of 128.  One workgroup
-// fills a CU's 8 wave slots at this register use, so the LDS stages are double
-// buffered: stage s is written into buffer s & 1 while the other buffer may
-// still be read, and one barrier per stage suffices -- a buffer is rewritten
-// two stages later, after every wave has passed the barrier that follows its
-// last read.
-constexpr int BT = GRAM_TILE_BIG;   // 256
-constexpr int BKW = 8;              // words per stage
-constexpr int BLDW = 2 * BKW + 1;   // dwords per staged column row (odd: conflict-free reads)
-constexpr int BNT = 512;            // threads
-constexpr int BSUBS = BKW / 2;      // 16-byte slots per column per stage
-constexpr int BCSL = BNT / BSUBS;   // columns staged per pass
-constexpr int BNS = BT / BCSL;      // passes per side
+// Big classes: 256 x 256 block pairs, each as two tasks of 128 rows x 256
+// columns, one workgroup of 4 waves per task.  A wave owns 64 x 128 (2 x 4
+// accumulators of 32 x 32, 128 registers), so per word it builds 6 operand
+// rows for 8 MFMAs (the 128-tile kernel: 4 rows for 4), and two workgroups
+// share a CU as in the 128-tile kernel.  On a diagonal block pair the 128 rows
+// are a slice of the 256 staged columns, so only the column side is staged,
+// and a wave whose block lies wholly below the diagonal skips its MFMAs.
+constexpr int BR = GRAM_TILE_BIG / 2;  // 128 rows per task
+constexpr int BC = GRAM_TILE_BIG;      // 256 columns
+constexpr int BKW = 8;                 // words per stage
+constexpr int BLDW = 2 * BKW + 1;      // dwords per staged column row (odd: conflict-free reads)
+constexpr int BSUBS = BKW / 2;         // 16-byte slots per column per stage
+constexpr int BCSL = 256 / BSUBS;      // columns staged per pass (64)
+constexpr int BNSC = BC / BCSL;        // passes for the columns (4)
+constexpr int BNSR = BR / BCSL;        // passes for the rows (2)
 
 template <bool F4>
-__device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint32_t* lds) {
+__device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint32_t* sR, uint32_t* sC) {
   static_assert(GRAM_KW % BKW == 0, "stages must tile the task word ranges");
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -285,7 +284,7 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint32_t* lds
   const int sub = tid % BSUBS;
   const int cslot = tid / BSUBS;
   const uint64_t ntasks = *a.ntasks;
-  constexpr int SIDE = BT * BLDW;  // dwords of one side of one buffer
+  constexpr int NP = BNSC + BNSR;
 
   for (uint64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
     const Task task = a.tasks[t];
@@ -293,16 +292,20 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint32_t* lds
     const DbInfo db = a.dbs[cd.db];
     const uint64_t Wp = db.Wp;
     const uint32_t q = cd.q;
-    const uint32_t I0 = (uint32_t)task.bi * BT, L0 = (uint32_t)task.bl * BT;
-    const bool diag = task.bi == task.bl;
-    const int nload = diag ? BNS : 2 * BNS;
+    const uint32_t half = task.bi & 1u;
+    const uint32_t I0 = (uint32_t)task.bi * BR, L0 = (uint32_t)task.bl * BC;
+    const bool diag = (uint32_t)(task.bi >> 1) == (uint32_t)task.bl;
+    // below the diagonal: every row of the wave's block exceeds every column
+    const bool skip = I0 + wr * 64 >= L0 + wc * 128 + 128;
 
-    const uint64_t* colp[2 * BNS];
+    // passes 0..3 stage the 256 columns, passes 4..5 the 128 rows (not on a
+    // diagonal block pair); nullptr = zero column
+    const uint64_t* colp[NP];
 #pragma unroll
-    for (int p = 0; p < 2 * BNS; ++p) {
-      const uint32_t idx = ((p >= BNS) ? L0 : I0) + cslot + BCSL * (p % BNS);
+    for (int p = 0; p < NP; ++p) {
+      const uint32_t idx = (p < BNSC ? L0 + BCSL * p : I0 + BCSL * (p - BNSC)) + cslot;
       colp[p] = nullptr;
-      if (p < nload && idx < q) {
+      if ((p < BNSC || !diag) && idx < q) {
         const uint32_t item = a.child_item[cd.child0 + idx];
         const uint32_t col = db.f1 ? db.f1[item] : item;
         colp[p] = db.B + (uint64_t)col * Wp + 2 * sub;
@@ -311,7 +314,7 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint32_t* lds
     const uint32_t* pre = a.pre_cols + cd.pre_off;
     const uint32_t pre_len = cd.pre_len;
 
-    uint4 reg[2 * BNS];
+    uint4 reg[NP];
     uint64_t m0 = ~0ull, m1 = ~0ull;
     auto load_stage = [&](uint32_t w) {
       m0 = ~0ull;
@@ -322,7 +325,7 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint32_t* lds
         m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
       }
 #pragma unroll
-      for (int p = 0; p < 2 * BNS; ++p) {
+      for (int p = 0; p < NP; ++p) {
         if (colp[p]) reg[p] = *reinterpret_cast<const uint4*>(colp[p] + w);
         else reg[p] = make_uint4(0, 0, 0, 0);
       }
@@ -337,19 +340,19 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint32_t* lds
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
 
-    // the previous task's last reads of both buffers end before any write
-    __syncthreads();
     const uint32_t nst = (task.w1 - task.w0) / BKW;
     if (nst) load_stage(task.w0);
     for (uint32_t s = 0; s < nst; ++s) {
-      uint32_t* sA = lds + (s & 1) * 2 * SIDE;
-      uint32_t* sB = sA + SIDE;
+      __syncthreads();  // previous stage (or task) finished reading LDS
 #pragma unroll
-      for (int p = 0; p < 2 * BNS; ++p) {
-        if (p < nload) {
-          uint32_t* dst = ((p >= BNS) ? sB : sA) + (cslot + BCSL * (p % BNS)) * BLDW + 4 * sub;
+      for (int p = 0; p < NP; ++p) {
+        if (p < BNSC || !diag) {
+          uint32_t* dst = (p < BNSC ? sC + (cslot + BCSL * p) * BLDW
+                                    : sR + (cslot + BCSL * (p - BNSC)) * BLDW) + 4 * sub;
           uint4 v = reg[p];
-          if (pre_len && p < BNS) {  // the prefix mask on the A side only: t & a_i & b_l
+          // the prefix mask once per pair: on the rows, or on the columns of a
+          // diagonal block pair (whose rows are read from them)
+          if (pre_len && (diag ? p < BNSC : p >= BNSC)) {
             v.x &= (uint32_t)m0;
             v.y &= (uint32_t)(m0 >> 32);
             v.z &= (uint32_t)m1;
@@ -363,9 +366,11 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint32_t* lds
       }
       __syncthreads();
       if (s + 1 < nst) load_stage(task.w0 + (s + 1) * BKW);
+      if (skip) continue;
 
-      const uint32_t* pa = sA + (wr * 64 + (lane & 31)) * BLDW + (lane >> 5);
-      const uint32_t* pb = (diag ? sA : sB) + (wc * 128 + (lane & 31)) * BLDW + (lane >> 5);
+      const uint32_t* pa = (diag ? sC + half * BR * BLDW : sR) + (wr * 64 + (lane & 31)) * BLDW +
+                           (lane >> 5);
+      const uint32_t* pb = sC + (wc * 128 + (lane & 31)) * BLDW + (lane >> 5);
       if constexpr (F4) {
 #pragma unroll
         for (int w4 = 0; w4 < BKW; w4 += 4) {
@@ -425,6 +430,7 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint32_t* lds
         }
       }
     }
+    if (skip) continue;
 
     uint32_t* tri = a.tri + cd.tri_off;
 #pragma unroll
@@ -443,10 +449,13 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint32_t* lds
   }
 }
 
+// two workgroups per CU: at most 256 registers per lane
 template <bool F4>
-__global__ __launch_bounds__(BNT) void k_gram_mfma_big(ClassArgs a) {
-  __shared__ uint32_t lds[2 * 2 * BT * BLDW];
-  gram_tiles_big<F4>(a, lds);
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_gram_mfma_big(ClassArgs a) {
+  __shared__ uint32_t sR[BR * BLDW];
+  __shared__ uint32_t sC[BC * BLDW];
+  gram_tiles_big<F4>(a, sR, sC);
 }
 
 }  // namespace
@@ -460,8 +469,8 @@ void launch_gram_mfma(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s
 
 void launch_gram_mfma_big(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s) {
   if (grid == 0) return;
-  if (fp4) k_gram_mfma_big<true><<<grid, BNT, 0, s>>>(a);
-  else k_gram_mfma_big<false><<<grid, BNT, 0, s>>>(a);
+  if (fp4) k_gram_mfma_big<true><<<grid, 256, 0, s>>>(a);
+  else k_gram_mfma_big<false><<<grid, 256, 0, s>>>(a);
   BM_LAUNCH_CHECK();
 }
 

@@ -226,15 +226,19 @@ __device__ inline void fill_level_body(const LevelPost& a, uint64_t t0, uint64_t
 }
 
 // Task records of one class: block pairs (bi <= bl, row-major) x word splits.
-// Lanes stride over the class's tasks.
+// With halves = 2 every block pair is two tasks, one per half of its rows:
+// bi then counts half blocks (bi = 2 * block + half).  Lanes stride over the
+// class's tasks.
 __device__ void write_tasks(uint32_t ci, uint32_t q, uint32_t npairs, uint32_t block,
                             uint32_t nsplit, uint32_t split_len, uint32_t wend, Task* out,
-                            int lane, int nl) {
+                            int lane, int nl, uint32_t halves = 1) {
   const uint32_t nb = (q + block - 1) / block;
   const uint64_t total = (uint64_t)npairs * nsplit;
   for (uint64_t t = lane; t < total; t += nl) {
     uint32_t tp = (uint32_t)(t / nsplit);
     const uint32_t sp = (uint32_t)(t % nsplit);
+    const uint32_t half = tp % halves;
+    tp /= halves;
     uint32_t bi = 0;
     while (tp >= nb - bi) {
       tp -= nb - bi;
@@ -242,7 +246,7 @@ __device__ void write_tasks(uint32_t ci, uint32_t q, uint32_t npairs, uint32_t b
     }
     Task k;
     k.cls = ci;
-    k.bi = (uint16_t)bi;
+    k.bi = (uint16_t)(bi * halves + half);
     k.bl = (uint16_t)(bi + tp);
     k.w0 = sp * split_len;
     k.w1 = min(wend, (sp + 1) * split_len);
@@ -272,8 +276,8 @@ __device__ inline ClassWork class_work(const ClassDesc& cd, const DbInfo& d, uin
     w.npairs = mfma_pairs(cd.q);
     w.split = geo.split_m;
     w.block = GRAM_TILE;
-  } else if (w.kind == 3) {
-    w.npairs = mfma_pairs(cd.q, GRAM_TILE_BIG);
+  } else if (w.kind == 3) {  // a task is one half (128 rows) of a 256 x 256 block pair
+    w.npairs = 2 * mfma_pairs(cd.q, GRAM_TILE_BIG);
     w.split = geo.split_b;
     w.block = GRAM_TILE_BIG;
   } else if (w.kind == 4) {
@@ -348,7 +352,7 @@ __global__ void k_write_class_tasks(const ClassDesc* __restrict__ cls, uint64_t 
                 : w.kind == 3 ? tb + ob[c]
                               : ts + os[c];
     write_tasks((uint32_t)c, cd.q, w.npairs, w.block, w.nsplit, w.split, w.wend, out, lane,
-                (int)blockDim.x);
+                (int)blockDim.x, w.kind == 3 ? 2u : 1u);
   }
 }
 

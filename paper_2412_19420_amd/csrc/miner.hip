@@ -243,8 +243,8 @@ TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_v, uint64_t c
   g.split_m = (uint32_t)pick(pairs_m, 256, GRAM_KW);
   g.split_v = (uint32_t)pick(pairs_v, 512, 1);
   g.split_t = (uint32_t)pick(classes_t, 2048, 64);  // tiny-class loads read 4-word groups
-  // a 256-wide tile holds about four 128-wide tiles: split its words further
-  g.split_b = (uint32_t)pick((pairs_m + 3) / 4, 256, GRAM_KW);
+  // a 128 x 256 task holds about two 128-wide tiles: split its words further
+  g.split_b = (uint32_t)pick((pairs_m + 1) / 2, 256, GRAM_KW);
   // 32-wide block pairs number about a quarter of the 16-wide ones, and each
   // is one wave's task: four per workgroup
   g.split_s = (uint32_t)pick((pairs_v + 3) / 4, 128, GRAM_SMALL_KW, 4);
@@ -322,7 +322,7 @@ void run_class_kernels(const DbInfo* ddb, const uint32_t* child_item, const Step
     a.tasks = w.tb.get();
     a.ntasks = w.ob.get() + w.ncls;
     tm.begin(BM_K_GRAM_MFMA_BIG);
-    launch_gram_mfma_big(a, (uint32_t)std::min<uint64_t>(w.ub_b, ncu), tu.mfma_fp4, s);
+    launch_gram_mfma_big(a, (uint32_t)std::min<uint64_t>(w.ub_b, ncu * 4), tu.mfma_fp4, s);
     tm.end(8.0 * nW * (double)w.st[ST_COLS_B], 2.0 * (double)w.st[ST_CAND_B] * nN);
   }
   if (w.ub_m && w.st[ST_CLS_M]) {
