@@ -33,7 +33,7 @@ MFMA_PEAK_TOPS = {"int8": 5000.0, "fp4": 10100.0}
 # ops = 2 n per candidate pair (one AND, one add per transaction)
 MFMA_KERNELS = {
     "gram_mfma": "k_gram_mfma (MFMA Gram of a prefix class, 128x128 tiles)",
-    "gram_mfma_big": "k_gram_mfma_big (MFMA Gram of a prefix class, 256x256 tiles)",
+    "gram_mfma_big": "k_gram_mfma_big (MFMA Gram of a big prefix class, 128 x 256 halves of 256 x 256 block pairs)",
     "gram_small": "k_gram_small (MFMA Gram of a mid-size class, 32x32 tiles, one wave per task)",
 }
 # streaming kernels priced against HBM: algorithmic bytes = column words read
@@ -111,12 +111,12 @@ DTYPE = {"fp4": "u64 bitsets; fp4 (e2m1) MFMA, fp32 accumulate (exact: counts < 
 # (workload, kernel, form) -> (sha256 of the source file, bytes per launch).
 TRAFFIC = {
     # dense_planted 1M x 4,096 (profiles/dense_planted_1M_hbm_traffic.md)
-    (3, "gram_mfma", "fp4"): ("516f0a7347803fe86ad3cae8bbf2c0b03d7b4a52d3b4d1d339465b2d9c4cf3e1", 2778.7e6),
-    (3, "andpop_reg", "fp4"): ("29d6103342951cee0aaee29ca2a37e34e3c93ca6b3f31f2840111dcbe41caa56", 551.7e6),
+    (3, "gram_mfma", "fp4"): ("d1e68fb44a162bdf8ce86a5d8a1bf9f059d6869a2aafe40275f87b9d92d07dc9", 2752.5e6),
+    (3, "andpop_reg", "fp4"): ("29d6103342951cee0aaee29ca2a37e34e3c93ca6b3f31f2840111dcbe41caa56", 551.5e6),
     (3, "gram_small", "fp4"): ("b72a42d014a78320b850165b51eb79887bf398287b88b7b726bb78c59dd610f0", 129.4e6),
 }
 KERNEL_SOURCE = {
-    "gram_mfma": "k_gram_mfma.hip", "gram_mfma_big": "k_gram_mfma.hip",
+    "gram_mfma": "k_gram_mfma.hip", "gram_mfma_big": "k_gram_big.hip",
     "gram_small": "k_gram_small.hip",
     "andpop": "k_andpop.hip", "andpop_reg": "k_andpop.hip", "dfs": "k_dfs.hip",
 }

@@ -27,7 +27,7 @@ CFLAGS = [
     "-Wall", "-Wno-unused-result",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
-SOURCES = ["runtime.hip", "k_build.hip", "k_gram_mfma.hip", "k_gram_small.hip", "k_andpop.hip",
+SOURCES = ["runtime.hip", "k_build.hip", "k_gram_mfma.hip", "k_gram_big.hip", "k_gram_small.hip", "k_andpop.hip",
            "k_levels.hip",
            "k_dfs.hip", "k_mlp.hip", "model.hip", "miner.hip", "autotune.hip", "api.hip"]
 
