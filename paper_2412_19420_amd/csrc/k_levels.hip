@@ -108,6 +108,8 @@ __global__ __launch_bounds__(kThreads) void k_tri_flags(
     const uint32_t* __restrict__ tri, uint64_t T, uint32_t uniform_thr,
     uint32_t* __restrict__ flags) {
   __shared__ uint64_t s_lo, s_hi;
+  __shared__ uint64_t s_off[kThreads + 1];
+  __shared__ uint32_t s_thr[kThreads + 1];
   for (uint64_t b0 = (uint64_t)blockIdx.x * kThreads; b0 < T; b0 += (uint64_t)gridDim.x * kThreads) {
     const uint64_t i = b0 + threadIdx.x;
     if (uniform_thr) {
@@ -125,13 +127,23 @@ __global__ __launch_bounds__(kThreads) void k_tri_flags(
       if (threadIdx.x == 0) s_lo = lo; else s_hi = lo + 1;
     }
     __syncthreads();
+    // the block's <= 256 classes (each has at least one candidate): offsets
+    // and thresholds into LDS, then each thread searches there
+    const uint64_t c0 = s_lo;
+    const uint32_t nc = (uint32_t)(s_hi - s_lo);
+    if (threadIdx.x < nc) {
+      const ClassDesc cd = cls[c0 + threadIdx.x];
+      s_off[threadIdx.x] = cd.tri_off;
+      s_thr[threadIdx.x] = dbs[cd.db].minsup;
+    }
+    __syncthreads();
     if (i < T) {
-      uint64_t lo = s_lo, hi = s_hi;
+      uint32_t lo = 0, hi = nc;  // s_off[lo] <= i < s_off[hi]
       while (hi - lo > 1) {
-        const uint64_t mid = (lo + hi) >> 1;
-        if (cls[mid].tri_off <= i) lo = mid; else hi = mid;
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_off[mid] <= i) lo = mid; else hi = mid;
       }
-      flags[i] = tri[i] >= dbs[cls[lo].db].minsup ? 1u : 0u;
+      flags[i] = tri[i] >= s_thr[lo] ? 1u : 0u;
     }
   }
 }
@@ -148,19 +160,19 @@ __device__ inline uint32_t andpop_pairs(uint32_t q, uint32_t block = AP_BLOCK) {
 
 // Per node of level k: number of frequent children, and what it contributes
 // to the next step if it becomes a class.  Also accumulates per-step totals
-// (candidates, columns read, classes per kernel) for the statistics.
+// (candidates, columns read, classes per kernel) for the statistics, and the
+// next step's task-count bounds.
 __global__ __launch_bounds__(kThreads) void k_node_counts(
     uint64_t n, uint32_t k, const uint32_t* __restrict__ parent, const int32_t* __restrict__ pcls,
     const ClassDesc* __restrict__ cls, const uint64_t* __restrict__ S, uint32_t mfma_min_q,
-    uint32_t big_q, uint32_t small_on, uint32_t* __restrict__ cnt, uint32_t* __restrict__ is_cls, uint64_t* __restrict__ tri_sz,
-    uint32_t* __restrict__ pm, uint32_t* __restrict__ pv, uint32_t* __restrict__ pt,
-    unsigned long long* __restrict__ st) {
-  __shared__ unsigned long long s_st[ST_COUNT];
-  if (threadIdx.x < ST_COUNT) s_st[threadIdx.x] = 0;
+    uint32_t big_q, uint32_t small_on, uint32_t* __restrict__ cnt, uint32_t* __restrict__ is_cls,
+    uint64_t* __restrict__ tri_sz, unsigned long long* __restrict__ st) {
+  __shared__ unsigned long long s_st[NC_COUNT];
+  if (threadIdx.x < NC_COUNT) s_st[threadIdx.x] = 0;
   __syncthreads();
-  unsigned long long loc[ST_COUNT];
+  unsigned long long loc[NC_COUNT];
 #pragma unroll
-  for (int j = 0; j < ST_COUNT; ++j) loc[j] = 0;
+  for (int j = 0; j < NC_COUNT; ++j) loc[j] = 0;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x) {
     const int32_t c = pcls[parent[i]];
@@ -180,21 +192,21 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
     const uint64_t tsz = cl ? (uint64_t)kc * (kc - 1) / 2 : 0ull;
     is_cls[i] = cl ? 1u : 0u;
     tri_sz[i] = tsz;
-    // 128-wide tile pairs: also an upper bound on a big class's 256-wide tile pairs
-    pm[i] = (kind == 0 || kind == 3) ? mfma_pairs(kc) : 0u;
-    // 16-wide block pairs: also an upper bound on a mid-size class's 32-wide ones
-    pv[i] = (kind == 1 || kind == 4) ? andpop_pairs(kc) : 0u;
-    pt[i] = kind == 2 ? 1u : 0u;
     if (cl) {
       loc[ST_CAND_M + kind] += tsz;
       loc[ST_COLS_M + kind] += kc + k;
       loc[ST_CLS_M + kind] += 1;
+      // 128-wide tile pairs: also a bound on a big class's 256-wide half tasks;
+      // 16-wide block pairs: also a bound on a mid-size class's 32-wide ones
+      if (kind == 0 || kind == 3) loc[NC_PAIRS_M] += mfma_pairs(kc);
+      else if (kind == 1 || kind == 4) loc[NC_PAIRS_V] += andpop_pairs(kc);
+      else loc[NC_TINY] += 1;
     }
   }
-  for (int j = 0; j < ST_COUNT; ++j)
+  for (int j = 0; j < NC_COUNT; ++j)
     if (loc[j]) atomicAdd(&s_st[j], loc[j]);
   __syncthreads();
-  if (threadIdx.x < ST_COUNT && s_st[threadIdx.x]) atomicAdd(&st[threadIdx.x], s_st[threadIdx.x]);
+  if (threadIdx.x < NC_COUNT && s_st[threadIdx.x]) atomicAdd(&st[threadIdx.x], s_st[threadIdx.x]);
 }
 
 // Wave per node: write the node's frequent extensions into the next level.
@@ -534,12 +546,11 @@ void launch_tri_flags(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs, co
 void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const int32_t* pcls,
                         const ClassDesc* cls, const uint64_t* S, uint32_t mfma_min_q, uint32_t big_q,
                         uint32_t small_on, uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz,
-                        uint32_t* pm, uint32_t* pv, uint32_t* pt, unsigned long long* st,
-                        hipStream_t s) {
+                        unsigned long long* st, hipStream_t s) {
   if (n == 0) return;
   k_node_counts<<<grid_for(n, kThreads, 2048), kThreads, 0, s>>>(n, k, parent, pcls, cls, S,
                                                                   mfma_min_q, big_q, small_on, cnt,
-                                                                  is_cls, tri_sz, pm, pv, pt, st);
+                                                                  is_cls, tri_sz, st);
   BM_LAUNCH_CHECK();
 }
 

@@ -48,6 +48,9 @@ struct TaskGeom {
 // 2 = register AND+popcount, 3 = MFMA 256-wide tiles, 4 = MFMA 32-wide tiles).
 enum { ST_CAND_M = 0, ST_CAND_V, ST_CAND_T, ST_CAND_B, ST_CAND_S, ST_COLS_M, ST_COLS_V, ST_COLS_T,
        ST_COLS_B, ST_COLS_S, ST_CLS_M, ST_CLS_V, ST_CLS_T, ST_CLS_B, ST_CLS_S, ST_COUNT };
+// The node-count kernel also sums the next step's task-count bounds: 128-wide
+// tile pairs, 16-wide block pairs and tiny classes (sizes for the task lists).
+enum { NC_PAIRS_M = ST_COUNT, NC_PAIRS_V, NC_TINY, NC_COUNT };
 
 void launch_f1_flags(const DbInfo* dbs, uint32_t ndb, const uint64_t* item_base, uint64_t total,
                      uint32_t* flags, hipStream_t s);
@@ -62,10 +65,13 @@ void launch_gather_idx(const uint64_t* arr, const uint64_t* idx, uint32_t k, uin
                        uint64_t* out2, hipStream_t s);
 void launch_tri_flags(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs, const uint32_t* tri,
                       uint64_t T, uint32_t uniform_thr, uint32_t* flags, hipStream_t s);
+// Per node of level k: frequent children (cnt), whether it becomes a class
+// (is_cls) and its candidate triangle size (tri_sz); sums the step statistics
+// and the task-count bounds into st[0, NC_COUNT) (zeroed by the caller).
 void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const int32_t* pcls,
                         const ClassDesc* cls, const uint64_t* S, uint32_t mfma_min_q, uint32_t big_q,
-                        uint32_t small_on, uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz, uint32_t* pm,
-                        uint32_t* pv, uint32_t* pt, unsigned long long* st, hipStream_t s);
+                        uint32_t small_on, uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz,
+                        unsigned long long* st, hipStream_t s);
 // Arguments of the launch between two level steps (k_level_post): node i < n
 // of level k writes its frequent extensions into the next level and, if it
 // has at least two, its class of the next step (skipped when ocls is NULL);

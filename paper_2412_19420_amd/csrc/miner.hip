@@ -798,13 +798,13 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         // S = exclusive scan of the frequent flags of this step's candidates;
         // the step's statistics counters are zeroed on the way
         TBuf<uint64_t> S(w->T + 1, s);
-        TBuf<unsigned long long> dst(ST_COUNT, s);
+        TBuf<unsigned long long> dst(NC_COUNT, s);
         uint64_t* dst64 = reinterpret_cast<uint64_t*>(dst.get());
         {
           ScanMulti sm{};
           sm.out[0] = S.get();
           sm.zero = dst64;
-          sm.nzero = ST_COUNT;
+          sm.nzero = NC_COUNT;
           TBuf<uint32_t> tfl;
           if (uniform_thr) {
             sm.in[0] = w->tri.get();
@@ -817,25 +817,24 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
           }
           scan_arrays(sm, 1, w->T, s);
         }
-        TBuf<uint32_t> cnt(nk, s), iscls(nk, s), pm(nk, s), pv(nk, s), pt(nk, s);
+        TBuf<uint32_t> cnt(nk, s), iscls(nk, s);
         TBuf<uint64_t> trisz(nk, s);
         launch_node_counts(nk, k, L[k].parent.get(), pcls_prev.get(), w->cls.get(), S.get(),
-                           tu.mfma_min_q, tu.mfma_big_q, tu.mfma_small ? 1u : 0u, cnt.get(), iscls.get(), trisz.get(), pm.get(), pv.get(),
-                           pt.get(), dst.get(), s);
+                           tu.mfma_min_q, tu.mfma_big_q, tu.mfma_small ? 1u : 0u, cnt.get(),
+                           iscls.get(), trisz.get(), dst.get(), s);
         L[k].cstart.alloc(nk + 1, s);
-        TBuf<uint64_t> clspos(nk + 1, s), trioff(nk + 1, s), pmoff(nk + 1, s), pvoff(nk + 1, s),
-            ptoff(nk + 1, s);
-        const void* ins[6] = {cnt.get(), iscls.get(), trisz.get(), pm.get(), pv.get(), pt.get()};
-        const bool is64[6] = {false, false, true, false, false, false};
-        uint64_t* outs[6] = {L[k].cstart.get(), clspos.get(), trioff.get(), pmoff.get(), pvoff.get(),
-                             ptoff.get()};
-        uint64_t* tot = pinned_array<uint64_t>(6 + ST_COUNT);
-        scan_many_tot(ins, is64, outs, 6, nk, mapped(tot), dst64, ST_COUNT, s);
+        TBuf<uint64_t> clspos(nk + 1, s), trioff(nk + 1, s);
+        const void* ins[3] = {cnt.get(), iscls.get(), trisz.get()};
+        const bool is64[3] = {false, false, true};
+        uint64_t* outs[3] = {L[k].cstart.get(), clspos.get(), trioff.get()};
+        // totals: next level size, classes, candidates; then the counters
+        uint64_t* tot = pinned_array<uint64_t>(3 + NC_COUNT);
+        scan_many_tot(ins, is64, outs, 3, nk, mapped(tot), dst64, NC_COUNT, s);
         tm.end();
         BM_HIP(hipStreamSynchronize(s));
         st.host_syncs++;
-        const uint64_t n_next = tot[0], ncls = tot[1], Tn = tot[2], PM = tot[3], PV = tot[4],
-                       PT = tot[5];
+        const uint64_t n_next = tot[0], ncls = tot[1], Tn = tot[2];
+        const uint64_t PM = tot[3 + NC_PAIRS_M], PV = tot[3 + NC_PAIRS_V], PT = tot[3 + NC_TINY];
         if (n_next == 0) break;
         if (k + 1 > BM_MAX_LEVELS)
           fail(BM_ERR_UNSUPPORTED, "frequent itemsets longer than %d items", BM_MAX_LEVELS);
@@ -875,7 +874,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         TBuf<int32_t> pcls_k(nk, s);
         nw->T = Tn;
         nw->tri.alloc(Tn, s);
-        for (int j = 0; j < ST_COUNT; ++j) nw->st[j] = tot[6 + j];
+        for (int j = 0; j < ST_COUNT; ++j) nw->st[j] = tot[3 + j];
         lp.k = k;
         lp.cnt = cnt.get();
         lp.child_start = L[k].cstart.get();
