@@ -99,23 +99,19 @@ __global__ void k_gather_idx(const uint64_t* __restrict__ arr, const uint64_t* _
 }
 
 // Threshold of every candidate against its own database's minsup, one thread
-// per candidate.  With one threshold for the whole call (uniform_thr > 0) no
-// lookup is needed; otherwise the candidate's class is found by binary search
-// over the classes' triangle offsets (ascending by construction), narrowed to
-// the classes of the workgroup's first and last candidates.
+// per candidate, for calls whose databases have different thresholds (with
+// one threshold the candidate scan tests it directly).  The candidate's class
+// is found by binary search over the classes' triangle offsets (ascending by
+// construction), narrowed to the classes of the workgroup's first and last
+// candidates.
 __global__ __launch_bounds__(kThreads) void k_tri_flags(
     const ClassDesc* __restrict__ cls, uint64_t ncls, const DbInfo* __restrict__ dbs,
-    const uint32_t* __restrict__ tri, uint64_t T, uint32_t uniform_thr,
-    uint32_t* __restrict__ flags) {
+    const uint32_t* __restrict__ tri, uint64_t T, uint32_t* __restrict__ flags) {
   __shared__ uint64_t s_lo, s_hi;
   __shared__ uint64_t s_off[kThreads + 1];
   __shared__ uint32_t s_thr[kThreads + 1];
   for (uint64_t b0 = (uint64_t)blockIdx.x * kThreads; b0 < T; b0 += (uint64_t)gridDim.x * kThreads) {
     const uint64_t i = b0 + threadIdx.x;
-    if (uniform_thr) {
-      if (i < T) flags[i] = tri[i] >= uniform_thr ? 1u : 0u;
-      continue;
-    }
     __syncthreads();
     if (threadIdx.x < 2) {
       const uint64_t e = threadIdx.x == 0 ? b0 : min<uint64_t>(T - 1, b0 + kThreads - 1);
@@ -537,9 +533,9 @@ void launch_gather_idx(const uint64_t* arr, const uint64_t* idx, uint32_t k, uin
 }
 
 void launch_tri_flags(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs, const uint32_t* tri,
-                      uint64_t T, uint32_t uniform_thr, uint32_t* flags, hipStream_t s) {
+                      uint64_t T, uint32_t* flags, hipStream_t s) {
   if (ncls == 0 || T == 0) return;
-  k_tri_flags<<<grid_for(T, kThreads), kThreads, 0, s>>>(cls, ncls, dbs, tri, T, uniform_thr, flags);
+  k_tri_flags<<<grid_for(T, kThreads), kThreads, 0, s>>>(cls, ncls, dbs, tri, T, flags);
   BM_LAUNCH_CHECK();
 }
 

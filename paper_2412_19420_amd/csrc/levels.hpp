@@ -64,7 +64,7 @@ void launch_init_level1(DbInfo* dbs, uint32_t ndb, const uint64_t* f1_base, uint
 void launch_gather_idx(const uint64_t* arr, const uint64_t* idx, uint32_t k, uint64_t* out,
                        uint64_t* out2, hipStream_t s);
 void launch_tri_flags(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs, const uint32_t* tri,
-                      uint64_t T, uint32_t uniform_thr, uint32_t* flags, hipStream_t s);
+                      uint64_t T, uint32_t* flags, hipStream_t s);
 // Per node of level k: frequent children (cnt), whether it becomes a class
 // (is_cls) and its candidate triangle size (tri_sz); sums the step statistics
 // and the task-count bounds into st[0, NC_COUNT) (zeroed by the caller).

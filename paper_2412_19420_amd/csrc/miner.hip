@@ -811,8 +811,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
             sm.ge[0] = uniform_thr;
           } else {
             tfl.alloc(w->T, s);
-            launch_tri_flags(w->cls.get(), w->ncls, ddb_p, w->tri.get(), w->T, uniform_thr,
-                             tfl.get(), s);
+            launch_tri_flags(w->cls.get(), w->ncls, ddb_p, w->tri.get(), w->T, tfl.get(), s);
             sm.in[0] = tfl.get();
           }
           scan_arrays(sm, 1, w->T, s);
