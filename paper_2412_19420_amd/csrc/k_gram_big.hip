@@ -86,8 +86,9 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint32_t* sR,
     const uint32_t half = task.bi & 1u;
     const uint32_t I0 = (uint32_t)task.bi * BR, L0 = (uint32_t)task.bl * BC;
     const bool diag = (uint32_t)(task.bi >> 1) == (uint32_t)task.bl;
-    // below the diagonal: every row of the wave's block exceeds every column
-    const bool skip = I0 + wr * 64 >= L0 + wc * 128 + 128;
+    // no pair to count: every row of the wave's block exceeds every column
+    // (below the diagonal), or its rows or columns lie past the last child
+    const bool skip = I0 + wr * 64 >= L0 + wc * 128 + 128 || I0 + wr * 64 >= q || L0 + wc * 128 >= q;
 
     // passes 0..3 stage the 256 columns, passes 4..5 the 128 rows (not on a
     // diagonal block pair); nullptr = zero column
