@@ -78,6 +78,33 @@ def test_build_from_device_pointers(bm):
     assert_same((offs.cpu().numpy(), items.cpu().numpy(), supp.cpu().numpy()), want)
 
 
+@pytest.mark.parametrize("m", [169, 20_000])  # tiled pack; more than 32 windows: untiled path
+@pytest.mark.parametrize("rp_dev,ci_dev", [(False, False), (False, True), (True, False),
+                                           (True, True)])
+def test_build_host_device_combinations(bm, m, rp_dev, ci_dev):
+    # every placement of row_ptr and col_idx gives the same matrix: item
+    # supports equal the column sums, and pair supports the Gram closed form
+    import torch
+    # unsorted rows of Poisson(40) uniform items (duplicates and empty rows included)
+    rng = np.random.default_rng(11)
+    n = 3_000
+    lens = rng.poisson(40, n)
+    lens[rng.random(n) < 0.05] = 0
+    row_ptr = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(lens, out=row_ptr[1:])
+    col_idx = rng.integers(0, m, int(row_ptr[-1])).astype(np.uint32)
+    print(f"build rp_dev={rp_dev} ci_dev={ci_dev} m={m} nnz={len(col_idx)}", flush=True)
+    rp = torch.from_numpy(row_ptr).cuda() if rp_dev else row_ptr
+    ci = torch.from_numpy(col_idx).cuda() if ci_dev else col_idx
+    h = bm.bm_build(rp, ci, n, m)
+    want = pairs.column_sums(row_ptr, col_idx, n, m)
+    assert np.array_equal(bm.bm_item_support(h).astype(np.int64), want)
+    items = np.argsort(-want, kind="stable")[:40].astype(np.uint32)
+    got = bm.bm_pair_support(h, items)
+    ref = pairs.pair_support(row_ptr, col_idx, n, m, cols=items)
+    assert np.array_equal(np.asarray(got).astype(np.int64), np.asarray(ref).astype(np.int64))
+
+
 # ------------------------------------------------------------ pair supports (Eq. 2)
 
 @pytest.mark.parametrize("n,m,k,density", [
