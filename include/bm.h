@@ -166,8 +166,8 @@ bm_status bm_build(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n_
 
 /* Batched bm_build: `count` databases (host arrays of per-database row_ptr
  * and col_idx pointers, each host or device, and of sizes; col_idxs may be
- * NULL when every database is empty) are validated and packed by two kernel
- * launches for the whole batch and one synchronisation, instead of one call
+ * NULL when every database is empty) are validated and packed by three kernel
+ * launches for the whole batch and two synchronisations, instead of one call
  * each.  out[i] equals what bm_build would return for database i.  All or
  * nothing: on failure every out[i] is NULL and bm_last_error names the first
  * failing database. */

@@ -52,7 +52,6 @@ struct bm_result {
 
 namespace bm {
 
-int cu_count();
 bool is_device_ptr(const void* p);
 bm_status set_allocator(void* (*alloc)(size_t, void*, void*), void (*free_fn)(void*, void*, void*),
                         void* ctx);

@@ -206,10 +206,22 @@ struct PackJob {
 // Whether the tiled construction handles m items (else the atomic one is used).
 bool pack_tiled_ok(uint32_t m, uint64_t Wp);
 uint64_t pack_blocks(uint64_t Wp);
-// Validate and pack njobs databases in two launches; err[j] gets database j's
-// flags (1 decreasing row_ptr, 2 item id >= m, 4 NULL col_idx, 8 row_ptr[0] != 0).
-void launch_build_multi(PackJob* jobs, uint32_t njobs, const uint64_t* blk_start, uint64_t total_blk,
-                        uint32_t* err, hipStream_t s);
+// Compute units of the current device (cached per device).
+int cu_count();
+
+// Batched build, step 1: one workgroup per database reads nnz into the job
+// and into hnnz (host memory), sets err[j] to the flags row_ptr[0] != 0 (8)
+// and NULL col_idx with nnz > 0 (4), and zeroes the column sums.
+void launch_build_multi_pre(PackJob* jobs, uint32_t njobs, uint32_t* err, uint64_t* hnnz,
+                            hipStream_t s);
+// Whether a database of nnz elements over n rows takes the sparse pack (small
+// LDS chunks, two workgroups per CU).
+bool pack_sparse(uint64_t nnz, uint64_t n);
+// Step 2, per kind: the tiles of databases kjob[0..nk) (tile offsets kstart,
+// nk + 1 entries; `blocks` tiles in all) packed in one grid; err[j] gets the
+// row flags (1 decreasing row_ptr, 2 item id >= m).
+void launch_pack_multi(const PackJob* jobs, bool sparse, const uint32_t* kjob, uint32_t nk,
+                       const uint64_t* kstart, uint64_t blocks, uint32_t* err, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
 

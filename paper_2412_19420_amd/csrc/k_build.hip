@@ -77,19 +77,27 @@ constexpr int PK_RBITS = 9;               // bits of a local row
 constexpr int PK_CW = 512;                // columns per window
 constexpr int PK_LD = PK_KR + 1;          // padded LDS row (conflict-free OR)
 constexpr int PK_ECAP = 20480;            // staged elements per chunk (80 KB)
+// Sparse databases (at most PK_SPARSE_ROW elements per row on average) are
+// packed with 8,192-element chunks: 73 KB of LDS lets two workgroups share a
+// CU, which outweighs the second chunk that a tile of more than 16 elements
+// per row needs (measured on the batch of 256 Quest-style databases).
+constexpr int PK_ECAP_SPARSE = 8192;
+constexpr int PK_SPARSE_ROW = 32;
 constexpr int PK_UNROLL = 8;
 // One workgroup fills a CU's LDS, so it brings all the waves the CU can hold:
 // 16 waves hide the latency of the staging loads and LDS atomics (measured
 // 2.1x faster than 4 waves on the dense 1M x 4,096 workload).
 constexpr int PK_T = 1024;
 
+template <int ECAP>
 struct PackSmem {
   unsigned long long X[PK_CW * PK_LD];
-  uint32_t s_e[PK_ECAP];
+  uint32_t s_e[ECAP];
   uint64_t s_rp[PK_ROWS + 1];
 };
 
-__device__ __forceinline__ void pack_tile(PackSmem& sm, const uint64_t* __restrict__ rp,
+template <int ECAP>
+__device__ __forceinline__ void pack_tile(PackSmem<ECAP>& sm, const uint64_t* __restrict__ rp,
                                           const uint32_t* __restrict__ ci, uint64_t n, uint64_t nnz,
                                           uint32_t m, unsigned long long* __restrict__ B, uint64_t Wp,
                                           uint32_t* __restrict__ colsum, uint32_t* __restrict__ err,
@@ -116,9 +124,9 @@ __device__ __forceinline__ void pack_tile(PackSmem& sm, const uint64_t* __restri
   const uint64_t e0 = s_rp[0];
   const uint64_t e1 = max(e0, s_rp[nr]);
   const uint32_t nwin = (m + PK_CW - 1) / PK_CW;
-  const bool single_chunk = e1 - e0 <= PK_ECAP;
-  for (uint64_t ea = e0; ea < e1 || (ea == e0 && e0 == e1); ea += PK_ECAP) {
-    const uint64_t eb = min<uint64_t>(e1, ea + PK_ECAP);
+  const bool single_chunk = e1 - e0 <= ECAP;
+  for (uint64_t ea = e0; ea < e1 || (ea == e0 && e0 == e1); ea += ECAP) {
+    const uint64_t eb = min<uint64_t>(e1, ea + ECAP);
     const int ne = (int)(eb - ea);
     __syncthreads();  // previous chunk fully consumed
     for (int base = 0; base < ne; base += PK_T * PK_UNROLL) {
@@ -208,7 +216,7 @@ __global__ __launch_bounds__(PK_T) void k_pack_tiled(
     const uint64_t* __restrict__ rp, const uint32_t* __restrict__ ci, uint64_t n, uint32_t m,
     unsigned long long* __restrict__ B, uint64_t Wp, uint32_t* __restrict__ colsum,
     uint32_t* __restrict__ err) {
-  __shared__ PackSmem sm;
+  __shared__ PackSmem<PK_ECAP> sm;
   const uint64_t nnz = rp[n];
   if (ci == nullptr && nnz > 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, 4u);
@@ -219,41 +227,46 @@ __global__ __launch_bounds__(PK_T) void k_pack_tiled(
 }
 
 // Batched construction, part 1 -- one workgroup per database: read nnz =
-// row_ptr[n] into the job, flag row_ptr[0] != 0 (8) and a NULL col_idx with
-// nnz > 0 (4), and zero the column sums.  The pack checks the rows.
+// row_ptr[n] into the job (and into hnnz, host memory the host reads to pick
+// each database's pack), set err to the flags row_ptr[0] != 0 (8) and NULL
+// col_idx with nnz > 0 (4), and zero the column sums.  The pack checks the rows.
 __global__ __launch_bounds__(kThreads) void k_build_multi_pre(PackJob* __restrict__ jobs,
-                                                              uint32_t* __restrict__ err) {
+                                                              uint32_t* __restrict__ err,
+                                                              uint64_t* __restrict__ hnnz) {
   PackJob& j = jobs[blockIdx.x];
   const uint64_t n = j.n;
-  uint32_t bad = 0;
   if (threadIdx.x == 0) {
     const uint64_t nnz = j.rp[n];
+    uint32_t bad = 0;
     j.nnz = nnz;
+    hnnz[blockIdx.x] = nnz;
     if (j.rp[0] != 0) bad |= 8u;
     if (nnz > 0 && j.ci == nullptr) bad |= 4u;
+    err[blockIdx.x] = bad;
   }
   for (uint32_t c = threadIdx.x; c < j.m; c += kThreads) j.colsum[c] = 0u;
-  if (bad) atomicOr(err + blockIdx.x, bad);
 }
 
-// Batched construction, part 2 -- every 512-row block of every database in one
-// grid: block b belongs to the job whose [blk_start[j], blk_start[j + 1])
-// holds it.  Jobs already flagged are skipped (the call fails as a whole).
+// Batched construction, part 2 -- the 512-row tiles of a list of databases in
+// one grid: block b belongs to list entry e with kstart[e] <= b < kstart[e + 1],
+// database kjob[e].
+template <int ECAP>
 __global__ __launch_bounds__(PK_T) void k_pack_tiled_multi(const PackJob* __restrict__ jobs,
-                                                               uint32_t njobs,
-                                                               const uint64_t* __restrict__ blk_start,
-                                                               uint32_t* __restrict__ err) {
-  __shared__ PackSmem sm;
+                                                           const uint32_t* __restrict__ kjob,
+                                                           uint32_t nk,
+                                                           const uint64_t* __restrict__ kstart,
+                                                           uint32_t* __restrict__ err) {
+  __shared__ PackSmem<ECAP> sm;
   const uint64_t b = blockIdx.x;
-  uint32_t lo = 0, hi = njobs;  // blk_start[lo] <= b < blk_start[hi]
+  uint32_t lo = 0, hi = nk;  // kstart[lo] <= b < kstart[hi]
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (blk_start[mid] <= b) lo = mid; else hi = mid;
+    if (kstart[mid] <= b) lo = mid; else hi = mid;
   }
-  if (err[lo] & (4u | 8u)) return;
-  const PackJob j = jobs[lo];
+  const uint32_t jd = kjob[lo];
+  const PackJob j = jobs[jd];
   pack_tile(sm, j.rp, j.ci, j.n, j.nnz, j.m, reinterpret_cast<unsigned long long*>(j.B), j.Wp,
-            j.colsum, err + lo, b - blk_start[lo]);
+            j.colsum, err + jd, b - kstart[lo]);
 }
 
 // Support of each single item: popcount of its column, one workgroup per column.
@@ -655,13 +668,23 @@ bool pack_tiled_ok(uint32_t m, uint64_t Wp) {
   return m > 0 && windows <= 32 && Wp % PK_KR == 0 && ((uint64_t)m << PK_RBITS) < 0xffffffffull;
 }
 
-void launch_build_multi(PackJob* jobs, uint32_t njobs, const uint64_t* blk_start, uint64_t total_blk,
-                        uint32_t* err, hipStream_t s) {
+void launch_build_multi_pre(PackJob* jobs, uint32_t njobs, uint32_t* err, uint64_t* hnnz,
+                            hipStream_t s) {
   if (njobs == 0) return;
-  if (total_blk > 0x7fffffffull) fail(BM_ERR_UNSUPPORTED, "batch too large for one build");
-  k_build_multi_pre<<<njobs, kThreads, 0, s>>>(jobs, err);
+  k_build_multi_pre<<<njobs, kThreads, 0, s>>>(jobs, err, hnnz);
   BM_LAUNCH_CHECK();
-  k_pack_tiled_multi<<<(uint32_t)total_blk, PK_T, 0, s>>>(jobs, njobs, blk_start, err);
+}
+
+bool pack_sparse(uint64_t nnz, uint64_t n) { return nnz <= n * (uint64_t)PK_SPARSE_ROW; }
+
+void launch_pack_multi(const PackJob* jobs, bool sparse, const uint32_t* kjob, uint32_t nk,
+                       const uint64_t* kstart, uint64_t blocks, uint32_t* err, hipStream_t s) {
+  if (nk == 0 || blocks == 0) return;
+  if (blocks > 0x7fffffffull) fail(BM_ERR_UNSUPPORTED, "batch too large for one build");
+  if (sparse)
+    k_pack_tiled_multi<PK_ECAP_SPARSE><<<(uint32_t)blocks, PK_T, 0, s>>>(jobs, kjob, nk, kstart, err);
+  else
+    k_pack_tiled_multi<PK_ECAP><<<(uint32_t)blocks, PK_T, 0, s>>>(jobs, kjob, nk, kstart, err);
   BM_LAUNCH_CHECK();
 }
 

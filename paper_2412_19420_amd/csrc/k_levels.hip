@@ -386,6 +386,15 @@ __device__ inline void fill_classes_body(const LevelPost& a, uint64_t t0, uint64
     cd.db = d;
     cd.pad = 0;
     a.ocls[ci] = cd;
+    {
+      const ClassWork w = class_work(cd, a.dbs[d], a.mfma_min_q, a.geo);
+      const uint32_t nt = w.npairs * w.nsplit;
+      a.cm[ci] = w.kind == 0 ? nt : 0u;
+      a.cv[ci] = w.kind == 1 ? nt : 0u;
+      a.ct[ci] = w.kind == 2 ? (a.dfs ? 1u : nt) : 0u;
+      a.cb[ci] = w.kind == 3 ? nt : 0u;
+      a.cs[ci] = w.kind == 4 ? nt : 0u;
+    }
     const uint32_t* f1 = a.dbs[d].f1;
     uint64_t x = i;
     for (int lev = (int)k; lev >= 1; --lev) {

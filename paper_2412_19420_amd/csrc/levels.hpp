@@ -74,8 +74,9 @@ void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const in
                         unsigned long long* st, hipStream_t s);
 // Arguments of the launch between two level steps (k_level_post): node i < n
 // of level k writes its frequent extensions into the next level and, if it
-// has at least two, its class of the next step (skipped when ocls is NULL);
-// the next step's support triangle ztri[0, nz) is zeroed.
+// has at least two, its class of the next step and that class's task counts
+// (skipped when ocls is NULL); the next step's support triangle ztri[0, nz)
+// is zeroed.
 struct LevelPost {
   uint64_t n;
   const uint32_t* parent;
@@ -101,6 +102,10 @@ struct LevelPost {
   uint32_t* ztri;
   uint64_t nz;
   uint32_t b_level, b_cls;  // set by the launcher
+  // the next step's per-class task counts (as k_class_task_counts writes them)
+  TaskGeom geo;
+  uint32_t mfma_min_q, dfs;
+  uint32_t *cm, *cv, *ct, *cb, *cs;
   LevelPtrs lv;
 };
 void launch_level_post(LevelPost a, hipStream_t s);

@@ -271,6 +271,8 @@ struct StepWork {
   uint64_t st[ST_COUNT] = {};
   TBuf<DfsTask> dt;  // small classes handed to the depth-first kernel
   uint64_t ndt = 0;
+  TBuf<uint32_t> ccount[5];   // tasks per class per kind (128, LDS, tiny, 256, 32-wide)
+  bool counts_ready = false;  // ccount already written (by the previous step's post kernel)
 };
 
 // Task lists of a step's classes: counts per class on the device, scanned
@@ -292,15 +294,19 @@ void prepare_tasks(StepWork& w, const DbInfo* ddb, uint64_t Wmax, uint64_t pairs
     w.ndt = classes_t;
     w.dt.alloc(classes_t, s);
   }
-  TBuf<uint32_t> cm(w.ncls, s), cv(w.ncls, s), ct(w.ncls, s), cb(w.ncls, s), cs(w.ncls, s);
+  if (!w.counts_ready) {  // else the previous step's k_level_post wrote them
+    for (auto& c : w.ccount) c.alloc(w.ncls, s);
+    launch_class_task_counts(w.cls.get(), w.ncls, ddb, tu.mfma_min_q, g, dfs, w.ccount[0].get(),
+                             w.ccount[1].get(), w.ccount[2].get(), w.ccount[3].get(),
+                             w.ccount[4].get(), s);
+  }
   w.om.alloc(w.ncls + 1, s);
   w.ov.alloc(w.ncls + 1, s);
   w.ot.alloc(w.ncls + 1, s);
   w.ob.alloc(w.ncls + 1, s);
   w.os.alloc(w.ncls + 1, s);
-  launch_class_task_counts(w.cls.get(), w.ncls, ddb, tu.mfma_min_q, g, dfs, cm.get(), cv.get(),
-                           ct.get(), cb.get(), cs.get(), s);
-  const void* in[5] = {cm.get(), cv.get(), ct.get(), cb.get(), cs.get()};
+  const void* in[5] = {w.ccount[0].get(), w.ccount[1].get(), w.ccount[2].get(), w.ccount[3].get(),
+                       w.ccount[4].get()};
   const bool is64[5] = {false, false, false, false, false};
   uint64_t* out[5] = {w.om.get(), w.ov.get(), w.ot.get(), w.ob.get(), w.os.get()};
   scan_many(in, is64, out, 5, w.ncls, s);
@@ -508,9 +514,11 @@ bm_db* build_db(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n, ui
 }
 
 // Batched construction: every database whose item count the tiled kernel
-// handles is validated and packed by two launches for the whole batch, with
-// one synchronisation; the others are built one by one.  All or nothing: on
-// any failure no handle is returned.
+// handles is validated and packed for the whole batch at once: a pre-pass
+// reads each nnz into host memory, then one grid packs the tiles of the
+// sparse databases and one those of the dense (two synchronisations in all);
+// the others are built one by one.  All or nothing: on any failure no handle
+// is returned.
 std::vector<bm_db*> build_many(uint32_t count, const uint64_t* const* row_ptrs,
                                const uint32_t* const* col_idxs, const uint64_t* ns,
                                const uint32_t* ms, hipStream_t s) {
@@ -519,7 +527,6 @@ std::vector<bm_db*> build_many(uint32_t count, const uint64_t* const* row_ptrs,
     CallScope scope(s);  // after dbs: on failure it synchronises before they are freed
     std::vector<PackJob> jobs;
     std::vector<uint32_t> job_db;
-    std::vector<uint64_t> blk_start(1, 0);
     std::vector<uint32_t> single;
     for (uint32_t d = 0; d < count; ++d) {
       const uint64_t n = ns[d];
@@ -565,18 +572,38 @@ std::vector<bm_db*> build_many(uint32_t count, const uint64_t* const* row_ptrs,
       jb.colsum = db->colsum.get();
       jobs.push_back(jb);
       job_db.push_back(d);
-      blk_start.push_back(blk_start.back() + pack_blocks(Wp));
       dbs[d] = std::move(db);
     }
     const uint32_t nj = (uint32_t)jobs.size();
     if (nj) {
       TBuf<PackJob> djobs(nj, s);
-      TBuf<uint64_t> dstart(nj + 1, s);
       TBuf<uint32_t> derr(nj, s);
       upload(djobs.get(), jobs, s);
-      upload(dstart.get(), blk_start, s);
-      launch_fill_u32(derr.get(), 0, nj, s);
-      launch_build_multi(djobs.get(), nj, dstart.get(), blk_start.back(), derr.get(), s);
+      uint64_t* hnnz = pinned_array<uint64_t>(nj);
+      launch_build_multi_pre(djobs.get(), nj, derr.get(), mapped(hnnz), s);
+      BM_HIP(hipStreamSynchronize(s));
+      // Split the tiles by kind: [sparse starts | dense starts | sparse ids | dense ids].
+      std::vector<uint32_t> kid[2];
+      std::vector<uint64_t> kst[2] = {{0}, {0}};
+      for (uint32_t j = 0; j < nj; ++j) {
+        const int k = pack_sparse(hnnz[j], jobs[j].n) ? 0 : 1;
+        kid[k].push_back(j);
+        kst[k].push_back(kst[k].back() + pack_blocks(jobs[j].Wp));
+      }
+      std::vector<uint64_t> tab(kst[0]);
+      tab.insert(tab.end(), kst[1].begin(), kst[1].end());
+      const size_t id_at = tab.size();
+      tab.resize(id_at + (nj + 1) / 2, 0);
+      uint32_t* ids = reinterpret_cast<uint32_t*>(tab.data() + id_at);
+      std::copy(kid[0].begin(), kid[0].end(), ids);
+      std::copy(kid[1].begin(), kid[1].end(), ids + kid[0].size());
+      TBuf<uint64_t> dtab(tab.size(), s);
+      upload(dtab.get(), tab, s);
+      const uint32_t* did = reinterpret_cast<const uint32_t*>(dtab.get() + id_at);
+      launch_pack_multi(djobs.get(), true, did, (uint32_t)kid[0].size(), dtab.get(),
+                        kst[0].back(), derr.get(), s);
+      launch_pack_multi(djobs.get(), false, did + kid[0].size(), (uint32_t)kid[1].size(),
+                        dtab.get() + kst[0].size(), kst[1].back(), derr.get(), s);
       uint32_t* herr = pinned_array<uint32_t>(nj);
       BM_HIP(hipMemcpyAsync(herr, derr.get(), nj * 4, hipMemcpyDeviceToHost, s));
       BM_HIP(hipStreamSynchronize(s));
@@ -885,6 +912,16 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         lp.pcls_out = pcls_k.get();
         lp.ztri = nw->tri.get();
         lp.nz = Tn;
+        lp.geo = make_geom(Wmax, PM, PV, PT, tu);
+        lp.mfma_min_q = tu.mfma_min_q;
+        lp.dfs = tu.dfs ? 1u : 0u;
+        for (auto& c : nw->ccount) c.alloc(ncls, s);
+        lp.cm = nw->ccount[0].get();
+        lp.cv = nw->ccount[1].get();
+        lp.ct = nw->ccount[2].get();
+        lp.cb = nw->ccount[3].get();
+        lp.cs = nw->ccount[4].get();
+        nw->counts_ready = true;
         for (uint32_t j = 1; j <= k; ++j) {
           lp.lv.item[j] = L[j].item.get();
           lp.lv.parent[j] = L[j].parent.get();

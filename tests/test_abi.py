@@ -66,3 +66,24 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     mod = importlib.util.module_from_spec(spec)
     with pytest.raises(ImportError):
         spec.loader.exec_module(mod)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libbm.so not built")
+def test_binding_marshalling_checks():
+    """Argument marshalling only: element types and contiguity are checked
+    before any pointer reaches the library (host tensors suffice here)."""
+    import numpy as np
+    import torch
+    from paper_2412_19420_amd import _bm
+    t = torch.arange(10, dtype=torch.int64).to(torch.uint64)
+    p, keep = _bm._ptr(t, np.uint64)
+    assert p.value == t.data_ptr() and keep is t
+    with pytest.raises(TypeError):
+        _bm._ptr(t, np.uint32)
+    with pytest.raises(ValueError):
+        _bm._ptr(torch.zeros((4, 4), dtype=torch.uint32).t(), np.uint32)
+    a = np.arange(5, dtype=np.int32)  # converted to the requested element type
+    p, keep = _bm._ptr(a, np.uint32)
+    assert keep.dtype == np.uint32 and p.value == keep.ctypes.data
+    assert _bm._nelem(t) == 10 and _bm._nelem(a) == 5
+    assert _bm._ptr(None, np.uint32)[0].value is None
