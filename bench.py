@@ -40,7 +40,9 @@ MFMA_KERNELS = {
 HBM_KERNELS = {
     "andpop": "k_andpop (AND+popcount of a prefix class, LDS-blocked)",
     "andpop_reg": "k_andpop_reg (AND+popcount of a small prefix class in registers)",
-    "dfs": "k_dfs (persistent depth-first subtree mining from a work queue)",
+    "dfs": "small-class subtrees: k_subset_count + k_subset_emit (every subset of a class's "
+           "children counted over word ranges; long columns) or k_dfs (depth-first from a work "
+           "queue; short columns)",
 }
 
 WORKLOADS = {
@@ -462,7 +464,7 @@ def main():
                    "candidates": cands, "frequent_items": st["n_frequent_items"],
                    "mine_ms": round(sum(s["wall_ms"] for s in stats) / len(stats), 3),
                    "dfs_tasks": st["dfs_tasks"], "host_syncs": st["host_syncs"],
-                   "mode": ("levelsync" if args.levelsync else "depth-first") +
+                   "mode": ("levelsync" if args.levelsync else "subtrees") +
                            ("+learned" if model is not None else "") +
                            (f"+shuffle{args.shuffle}" if args.shuffle else ""),
                    "kernels": kernels},

@@ -132,7 +132,12 @@ typedef struct {
   uint32_t dfs_wave_max_words;/* subtree tasks of databases with at most this many words per
                                * column run one stack per wave, the others one per workgroup
                                * (0 = default 1024; see BM_FLAG_DFS_BLOCK_ONLY) */
-  uint32_t reserved[3];
+  uint32_t subset_max_children;/* when columns are too long for the depth-first phase, classes of
+                               * at most this many children (2..6) are mined whole: every subset
+                               * of their children is counted in one pass over word ranges, and
+                               * the rest of such a subtree needs no further level step
+                               * (0 = default 6; 1 = never, level by level instead) */
+  uint32_t reserved[2];
 } bm_options;
 
 uint32_t bm_abi_version(void);

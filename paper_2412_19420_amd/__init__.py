@@ -169,7 +169,7 @@ class Result:
 def options(flags: int = 0, mfma_min_children: int = 0, andpop_chunk_words: int = 0,
             split_words: int = 0, shuffle_seed: int = 0, dfs_threads: int = 0,
             dfs_max_words: int = 0, mfma_big_children: int = 0,
-            dfs_wave_max_words: int = 0) -> BmOptions:
+            dfs_wave_max_words: int = 0, subset_max_children: int = 0) -> BmOptions:
     o = BmOptions()
     o.flags = flags
     o.mfma_min_children = mfma_min_children
@@ -180,6 +180,7 @@ def options(flags: int = 0, mfma_min_children: int = 0, andpop_chunk_words: int 
     o.dfs_max_words = dfs_max_words
     o.mfma_big_children = mfma_big_children
     o.dfs_wave_max_words = dfs_wave_max_words
+    o.subset_max_children = subset_max_children
     return o
 
 
@@ -301,7 +302,7 @@ def bm_autotune(dbs, minsups, model=None, base: BmOptions | None = None, reps: i
 
 
 _TUNE_FIELDS = ("flags", "mfma_min_children", "andpop_chunk_words", "split_words", "dfs_threads",
-                "dfs_max_words", "mfma_big_children", "dfs_wave_max_words")
+                "dfs_max_words", "mfma_big_children", "dfs_wave_max_words", "subset_max_children")
 
 
 def options_to_dict(o: BmOptions) -> dict:

@@ -83,7 +83,8 @@ class BmOptions(ctypes.Structure):
         ("dfs_max_words", ctypes.c_uint32),
         ("mfma_big_children", ctypes.c_uint32),
         ("dfs_wave_max_words", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 3),
+        ("subset_max_children", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 2),
     ]
 
 

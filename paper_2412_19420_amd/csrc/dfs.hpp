@@ -67,6 +67,14 @@ void launch_dfs(const DfsArgs& a, uint32_t threads, uint32_t grid, hipStream_t s
 // One subtree stack per wave (four waves per workgroup): for databases with
 // short columns, where a whole workgroup per class would mostly wait.
 void launch_dfs_wave(const DfsArgs& a, uint32_t grid, hipStream_t s);
+// Subset counting (k_subsets.hip), for tasks of at most SUBSET_Q children:
+// counts[t << SUBSET_Q | mask] (zeroed by the caller) receives the support of
+// task t's prefix plus the children in mask, for every mask of two or more
+// children, from `splits` word ranges per task.  Then one thread per task
+// writes the subtree's frequent itemsets into the arena and links them as the
+// depth-first kernel does (same flags and statistics; queue fields unused).
+void launch_subset_count(const DfsArgs& a, uint32_t* counts, uint32_t splits, hipStream_t s);
+void launch_subset_emit(const DfsArgs& a, const uint32_t* counts, hipStream_t s);
 // flags[t] = 1 if queue entry t (order[t], or t) belongs to a database with at
 // most max_words words per column.
 void launch_dfs_short_flags(const DfsTask* tasks, const DbInfo* dbs, const uint32_t* order,

@@ -71,6 +71,11 @@ struct Tuning {
   uint32_t dfs_max_words = 4096;  // depth-first only when every column has <= this many words
   uint32_t dfs_wave_words = 1024;  // tasks of databases with <= this many words: one stack per wave
                                    // (0: every task on the one-stack-per-workgroup kernel)
+  // Longer columns: classes of at most subset_q children (0: none) are mined
+  // whole by counting every subset of their children over word ranges
+  uint32_t subset_q = SUBSET_Q;
+  bool subsets = false;            // this call mines small subtrees by subset counting
+  uint32_t tiny_q = TINY_Q;        // small-class threshold of this call
 };
 Tuning tuning_from(const bm_options* opt);
 

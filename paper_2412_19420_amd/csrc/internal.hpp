@@ -133,6 +133,7 @@ constexpr int AP_BLOCK = 16;    // AND+popcount kernel children per block
 constexpr int GRAM_SMALL_TILE = 32;  // mid-size-class MFMA kernel children per block
 constexpr int GRAM_SMALL_KW = 16;    // its task word ranges are multiples of this
 constexpr int TINY_Q = 8;       // classes up to this many children use the register kernel
+constexpr int SUBSET_Q = 6;     // largest class mined whole by subset counting (2^6 counters)
 
 // Arguments shared by the class kernels.  They loop over the task list from
 // the launched workgroups (persistent, grid-stride); the task count is read

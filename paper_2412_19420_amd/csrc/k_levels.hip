@@ -161,7 +161,8 @@ __device__ inline uint32_t andpop_pairs(uint32_t q, uint32_t block = AP_BLOCK) {
 __global__ __launch_bounds__(kThreads) void k_node_counts(
     uint64_t n, uint32_t k, const uint32_t* __restrict__ parent, const int32_t* __restrict__ pcls,
     const ClassDesc* __restrict__ cls, const uint64_t* __restrict__ S, uint32_t mfma_min_q,
-    uint32_t big_q, uint32_t small_on, uint32_t* __restrict__ cnt, uint32_t* __restrict__ is_cls,
+    uint32_t big_q, uint32_t small_on, uint32_t tiny_q, uint32_t* __restrict__ cnt,
+    uint32_t* __restrict__ is_cls,
     uint64_t* __restrict__ tri_sz, unsigned long long* __restrict__ st) {
   __shared__ unsigned long long s_st[NC_COUNT];
   if (threadIdx.x < NC_COUNT) s_st[threadIdx.x] = 0;
@@ -184,7 +185,7 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
     }
     cnt[i] = kc;
     const bool cl = kc >= 2;
-    const int kind = cl ? class_kind(kc, mfma_min_q, big_q, small_on) : -1;
+    const int kind = cl ? class_kind(kc, mfma_min_q, big_q, small_on, tiny_q) : -1;
     const uint64_t tsz = cl ? (uint64_t)kc * (kc - 1) / 2 : 0ull;
     is_cls[i] = cl ? 1u : 0u;
     tri_sz[i] = tsz;
@@ -278,7 +279,7 @@ struct ClassWork {
 __device__ inline ClassWork class_work(const ClassDesc& cd, const DbInfo& d, uint32_t mfma_min_q,
                                        const TaskGeom& geo) {
   ClassWork w;
-  w.kind = class_kind(cd.q, mfma_min_q, geo.big_q, geo.small_on);
+  w.kind = class_kind(cd.q, mfma_min_q, geo.big_q, geo.small_on, geo.tiny_q);
   w.wend = wend_of(d, w.kind);
   if (w.kind == 0) {
     w.npairs = mfma_pairs(cd.q);
@@ -550,12 +551,12 @@ void launch_tri_flags(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs, co
 
 void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const int32_t* pcls,
                         const ClassDesc* cls, const uint64_t* S, uint32_t mfma_min_q, uint32_t big_q,
-                        uint32_t small_on, uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz,
-                        unsigned long long* st, hipStream_t s) {
+                        uint32_t small_on, uint32_t tiny_q, uint32_t* cnt, uint32_t* is_cls,
+                        uint64_t* tri_sz, unsigned long long* st, hipStream_t s) {
   if (n == 0) return;
   k_node_counts<<<grid_for(n, kThreads, 2048), kThreads, 0, s>>>(n, k, parent, pcls, cls, S,
-                                                                  mfma_min_q, big_q, small_on, cnt,
-                                                                  is_cls, tri_sz, st);
+                                                                  mfma_min_q, big_q, small_on, tiny_q,
+                                                                  cnt, is_cls, tri_sz, st);
   BM_LAUNCH_CHECK();
 }
 

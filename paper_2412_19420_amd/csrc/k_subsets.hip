@@ -1,0 +1,252 @@
+// Whole subtrees of small prefix classes by subset counting, for databases
+// whose columns are too long for one workgroup to walk a subtree.
+//
+// The supports the recursion of the method needs below a class with prefix P
+// and children c_0..c_{q-1} are all of the form
+//     supp(P + {c_i : i in S}) = sum_words popcount(t(P) & AND_{i in S} col(c_i))
+// for subsets S of the children (Eq. 2 with the prefix columns ANDed in first,
+// applied to longer itemsets).  With q <= SUBSET_Q every such subset fits in
+// 2^q counters, so one pass over the columns counts them all:
+//   * k_subset_count: a workgroup takes one word range of one class; each
+//     thread ANDs its words of the prefix and child columns along a
+//     depth-first walk of the subset lattice (one AND per subset, from its
+//     parent's value) and popcounts every subset of two or more children into
+//     its own register counter; the counters are reduced over the workgroup
+//     and added atomically into the class's counter block;
+//   * k_subset_emit: one thread per class turns the counters into the
+//     subtree's frequent itemsets.  A subset is frequent when its count meets
+//     the threshold (every subset of a frequent set is frequent, so this is
+//     exactly the set the class-by-class recursion reaches).  The nodes are
+//     written to the subtree arena with each node's frequent extensions as one
+//     contiguous block, the format the depth-first kernel writes, so the same
+//     merge produces the canonical output.  Candidate and frequent counts per
+//     length are those of the recursion: a node with e >= 2 frequent
+//     extensions forms a class of e(e-1)/2 candidates.
+#include "internal.hpp"
+#include "levels.hpp"
+#include "dfs.hpp"
+
+namespace bm {
+
+namespace {
+
+constexpr int SQ = SUBSET_Q;
+constexpr int SN = 1 << SQ;
+constexpr int kCountThreads = 256;
+constexpr int kEmitThreads = 64;
+
+// Visits every subset that extends MASK by columns L.. (each exactly once, by
+// the step that adds its highest child); x = t(P) & the columns of MASK.
+template <int L, int MASK>
+__device__ __forceinline__ void subsets_from(const uint64_t (&c0)[SQ], const uint64_t (&c1)[SQ],
+                                             uint64_t x0, uint64_t x1, int q,
+                                             uint32_t (&acc)[SN]) {
+  if constexpr (L < SQ) {
+    if (L < q) {
+      constexpr int M2 = MASK | (1 << L);
+      const uint64_t y0 = x0 & c0[L], y1 = x1 & c1[L];
+      if constexpr (MASK != 0) acc[M2] += (uint32_t)(__popcll(y0) + __popcll(y1));
+      subsets_from<L + 1, M2>(c0, c1, y0, y1, q, acc);
+      subsets_from<L + 1, MASK>(c0, c1, x0, x1, q, acc);
+    }
+  }
+}
+
+// Block b counts word range b % splits of task b / splits.
+__global__ __launch_bounds__(kCountThreads) void k_subset_count(DfsArgs a,
+                                                                uint32_t* __restrict__ counts,
+                                                                uint32_t splits) {
+  __shared__ uint32_t s_red[kCountThreads / 64][SN];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t t = blockIdx.x / splits, sp = blockIdx.x % splits;
+  const DfsTask tk = a.tasks[t];
+  const DbInfo db = a.dbs[tk.db];
+  const int q = (int)tk.q;  // 2 <= q <= SQ
+  const uint32_t W = (uint32_t)db.W;
+  // even word ranges: the 16-byte loads at even words stay inside the padded column
+  const uint32_t len = ((W + splits - 1) / splits + 1) & ~1u;
+  const uint32_t w0 = sp * len;
+  const uint32_t w1 = min(W, w0 + len);
+  const uint32_t* lit = a.lv_item[tk.level];
+  const uint64_t* col[SQ];
+#pragma unroll
+  for (int i = 0; i < SQ; ++i) {
+    uint32_t c = 0;
+    if (i < q) {
+      const uint32_t it = lit[tk.child0 + i];
+      c = db.f1 ? db.f1[it] : it;
+    }
+    col[i] = db.B + (uint64_t)c * db.Wp;
+  }
+  const uint32_t* pre = a.step_pre[tk.level] + tk.pre_off;
+  const uint32_t pre_len = tk.pre_len;
+  uint32_t acc[SN];
+#pragma unroll
+  for (int j = 0; j < SN; ++j) acc[j] = 0;
+  for (uint32_t w = w0 + 2 * tid; w < w1; w += 2 * kCountThreads) {
+    uint64_t m0 = ~0ull, m1 = (w + 1 < w1) ? ~0ull : 0ull;
+    for (uint32_t j = 0; j < pre_len; ++j) {
+      const uint4 x = *reinterpret_cast<const uint4*>(db.B + (uint64_t)pre[j] * db.Wp + w);
+      m0 &= (uint64_t)x.x | ((uint64_t)x.y << 32);
+      m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
+    }
+    uint64_t c0[SQ], c1[SQ];
+#pragma unroll
+    for (int i = 0; i < SQ; ++i) {
+      c0[i] = 0;
+      c1[i] = 0;
+      if (i < q) {
+        const uint4 v = *reinterpret_cast<const uint4*>(col[i] + w);
+        c0[i] = (uint64_t)v.x | ((uint64_t)v.y << 32);
+        c1[i] = (uint64_t)v.z | ((uint64_t)v.w << 32);
+      }
+    }
+    subsets_from<0, 0>(c0, c1, m0, m1, q, acc);
+  }
+#pragma unroll
+  for (int mask = 3; mask < SN; ++mask) {
+    if (__builtin_popcount(mask) < 2 || mask >= (1 << q)) continue;
+    uint32_t v = acc[mask];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) s_red[wave][mask] = v;
+  }
+  __syncthreads();
+  if (tid < (1 << q) && __popc(tid) >= 2) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < kCountThreads / 64; ++j) v += s_red[j][tid];
+    if (v) atomicAdd(counts + (uint64_t)t * SN + tid, v);
+  }
+}
+
+// Thread per task: frequent subsets -> arena nodes, links and statistics.  A
+// thread's counter block, queue and node slots live in LDS (odd row stride:
+// the threads of a wave hit different banks).
+__global__ __launch_bounds__(kEmitThreads) void k_subset_emit(DfsArgs a,
+                                                              const uint32_t* __restrict__ counts) {
+  __shared__ uint32_t s_cnt[kEmitThreads][SN + 1];
+  __shared__ uint32_t s_pos[kEmitThreads][SN + 1];
+  __shared__ uint32_t s_queue[kEmitThreads][SN + 1];
+  __shared__ unsigned long long s_cand[BM_MAX_LEVELS + 1], s_freq[BM_MAX_LEVELS + 1];
+  __shared__ unsigned long long s_words;
+  const int tid = threadIdx.x;
+  for (int j = tid; j <= BM_MAX_LEVELS; j += kEmitThreads) {
+    s_cand[j] = 0;
+    s_freq[j] = 0;
+  }
+  if (tid == 0) s_words = 0;
+  __syncthreads();
+  const uint32_t t = blockIdx.x * kEmitThreads + tid;
+  if (t < a.ntasks) {
+    const DfsTask tk = a.tasks[t];
+    const DbInfo db = a.dbs[tk.db];
+    const uint32_t q = tk.q, level = tk.level, minsup = db.minsup;
+    const uint32_t nsub = 1u << q;
+    uint32_t* cnt = s_cnt[tid];
+    uint32_t* pos = s_pos[tid];
+    uint32_t* queue = s_queue[tid];
+    const uint4* src = reinterpret_cast<const uint4*>(counts + (uint64_t)t * SN);
+    for (uint32_t k = 0; k < (nsub + 3) / 4; ++k) {
+      const uint4 v = src[k];
+      cnt[4 * k] = v.x;
+      cnt[4 * k + 1] = v.y;
+      cnt[4 * k + 2] = v.z;
+      cnt[4 * k + 3] = v.w;
+    }
+    uint32_t item[SQ];
+    const uint32_t* lit = a.lv_item[tk.level] + tk.child0;
+#pragma unroll
+    for (int i = 0; i < SQ; ++i) item[i] = i < (int)q ? lit[i] : 0u;
+    uint32_t total = 0, maxj = 1;  // arena nodes; most children in a frequent subset
+    for (uint32_t m = 3; m < nsub; ++m)
+      if (__popc(m) >= 2 && cnt[m] >= minsup) {
+        total += 1;
+        maxj = max(maxj, (uint32_t)__popc(m));
+      }
+    bool ok = true;
+    if (level + maxj - 1 > BM_MAX_LEVELS) {  // itemsets of level + j - 1 items
+      atomicOr(a.flags, DFS_TOO_LONG);
+      ok = false;
+    }
+    uint32_t base = 0;
+    if (ok && total) {
+      base = atomicAdd(a.arena_count, total);
+      if (base + total > a.arena_cap) {
+        atomicOr(a.flags, DFS_OVERFLOW);
+        ok = false;
+      }
+    }
+    // breadth-first over the frequent subsets: each node's extensions get
+    // consecutive arena slots, and a node's own slot is known before its turn
+    uint32_t qn = 0;
+    for (uint32_t i = 0; i < q; ++i) queue[qn++] = 1u << i;
+    uint32_t next = base;
+    unsigned long long words = (unsigned long long)(tk.pre_len + q) * db.W;
+    if (ok && level + 1 <= BM_MAX_LEVELS)
+      atomicAdd(&s_cand[level + 1], (unsigned long long)q * (q - 1) / 2);
+    for (uint32_t h = 0; h < qn && ok; ++h) {
+      const uint32_t m = queue[h];
+      const uint32_t j = (uint32_t)__popc(m);
+      const uint32_t hb = 31u - (uint32_t)__clz(m);
+      uint32_t ext = 0;
+      for (uint32_t l = hb + 1; l < q; ++l)
+        if (cnt[m | (1u << l)] >= minsup) ext |= 1u << l;
+      const uint32_t ne = (uint32_t)__popc(ext), first = next;
+      next += ne;
+      if (j == 1) {
+        a.ls_first[level][tk.child0 + hb] = first;
+        a.ls_count[level][tk.child0 + hb] = ne;
+      } else {
+        a.arena[pos[m]].first = first;
+        a.arena[pos[m]].count = ne;
+      }
+      uint32_t r = 0;
+      for (uint32_t e = ext; e; e &= e - 1, ++r) {
+        const uint32_t l = (uint32_t)__ffs(e) - 1, m2 = m | (1u << l);
+        pos[m2] = first + r;
+        ArenaNode an;
+        an.item = item[0];
+#pragma unroll
+        for (int i = 1; i < SQ; ++i)
+          if ((int)l == i) an.item = item[i];
+        an.supp = cnt[m2];
+        an.first = 0;
+        an.count = 0;
+        a.arena[first + r] = an;
+        queue[qn++] = m2;
+      }
+      if (ne) atomicAdd(&s_freq[level + j], (unsigned long long)ne);
+      if (ne >= 2) {  // this node's class: its extensions paired
+        if (level + j + 1 <= BM_MAX_LEVELS)
+          atomicAdd(&s_cand[level + j + 1], (unsigned long long)ne * (ne - 1) / 2);
+        words += (unsigned long long)(tk.pre_len + j + ne) * db.W;
+      }
+    }
+    if (a.task_cost) a.task_cost[t] = (float)words;
+    atomicAdd(&s_words, (unsigned long long)(tk.pre_len + q) * db.W);
+  }
+  __syncthreads();
+  for (int j = tid; j <= BM_MAX_LEVELS; j += kEmitThreads) {
+    if (s_cand[j]) atomicAdd(&a.level_cand[j], s_cand[j]);
+    if (s_freq[j]) atomicAdd(&a.level_freq[j], s_freq[j]);
+  }
+  if (tid == 0 && s_words) atomicAdd(a.words_read, s_words);
+}
+
+}  // namespace
+
+void launch_subset_count(const DfsArgs& a, uint32_t* counts, uint32_t splits, hipStream_t s) {
+  if (a.ntasks == 0) return;
+  const uint64_t grid = (uint64_t)a.ntasks * splits;
+  if (splits == 0 || grid > 0x7fffffffull) fail(BM_ERR_UNSUPPORTED, "too many subset-count blocks");
+  k_subset_count<<<(uint32_t)grid, kCountThreads, 0, s>>>(a, counts, splits);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_subset_emit(const DfsArgs& a, const uint32_t* counts, hipStream_t s) {
+  if (a.ntasks == 0) return;
+  k_subset_emit<<<(a.ntasks + kEmitThreads - 1) / kEmitThreads, kEmitThreads, 0, s>>>(a, counts);
+  BM_LAUNCH_CHECK();
+}
+
+}  // namespace bm

@@ -41,6 +41,7 @@ struct TaskGeom {
   uint32_t split_m, split_v, split_t, split_b, split_s;
   uint32_t big_q;     // classes with at least this many children (and MFMA-routed) use 256-wide tiles
   uint32_t small_on;  // mid-size classes use the 32-wide MFMA kernel (else LDS AND+popcount)
+  uint32_t tiny_q;    // classes with at most this many children are small (registers / subtrees)
 };
 
 // Per-step totals accumulated on the device for statistics.
@@ -70,7 +71,8 @@ void launch_tri_flags(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs, co
 // and the task-count bounds into st[0, NC_COUNT) (zeroed by the caller).
 void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const int32_t* pcls,
                         const ClassDesc* cls, const uint64_t* S, uint32_t mfma_min_q, uint32_t big_q,
-                        uint32_t small_on, uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz,
+                        uint32_t small_on, uint32_t tiny_q, uint32_t* cnt, uint32_t* is_cls,
+                        uint64_t* tri_sz,
                         unsigned long long* st, hipStream_t s);
 // Arguments of the launch between two level steps (k_level_post): node i < n
 // of level k writes its frequent extensions into the next level and, if it
@@ -132,9 +134,9 @@ inline uint32_t host_mfma_pairs(uint32_t q) {
 // 1 = LDS-blocked AND+popcount, 2 = registers, 3 = MFMA (256-wide tiles),
 // 4 = MFMA (32-wide tiles, one wave per block pair).
 __host__ __device__ inline int class_kind(uint32_t q, uint32_t mfma_min_q, uint32_t big_q,
-                                          uint32_t small_on) {
+                                          uint32_t small_on, uint32_t tiny_q) {
   if (q >= mfma_min_q) return q >= big_q ? 3 : 0;
-  if (q <= (uint32_t)TINY_Q) return 2;
+  if (q <= tiny_q) return 2;
   return small_on ? 4 : 1;
 }
 // Kinds whose task word ranges are rounded to GRAM_KW (LDS-staged MFMA kernels).

@@ -250,6 +250,7 @@ TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_v, uint64_t c
   g.split_s = (uint32_t)pick((pairs_v + 3) / 4, 128, GRAM_SMALL_KW, 4);
   g.big_q = tu.mfma_big_q;
   g.small_on = tu.mfma_small ? 1u : 0u;
+  g.tiny_q = tu.tiny_q;
   if (tu.mfma_fp4) {  // keep every MFMA task's counts below 2^24
     g.split_m = std::min<uint32_t>(g.split_m, GRAM_FP4_MAX_WORDS);
     g.split_b = std::min<uint32_t>(g.split_b, GRAM_FP4_MAX_WORDS);
@@ -375,7 +376,8 @@ void host_classes(StepWork& w, const std::vector<ClassDesc>& hc, const DbInfo* d
   for (const auto& c : hc) {
     const uint64_t tsz = (uint64_t)c.q * (c.q - 1) / 2;
     w.T += tsz;
-    const int kind = class_kind(c.q, tu.mfma_min_q, tu.mfma_big_q, tu.mfma_small ? 1u : 0u);
+    const int kind =
+        class_kind(c.q, tu.mfma_min_q, tu.mfma_big_q, tu.mfma_small ? 1u : 0u, tu.tiny_q);
     if (is_mfma_kind(kind)) pm += host_mfma_pairs(c.q);
     else if (kind == 1 || kind == 4) pv += host_andpop_pairs(c.q);
     else ct += 1;
@@ -423,6 +425,11 @@ Tuning tuning_from(const bm_options* opt) {
   if (opt->flags & BM_FLAG_DFS_BLOCK_ONLY) t.dfs_wave_words = 0;
   if (opt->mfma_big_children) t.mfma_big_q = std::max<uint32_t>(2, opt->mfma_big_children);
   if (opt->flags & BM_FLAG_LEVELSYNC) t.dfs = false;
+  if (opt->subset_max_children) {
+    if (opt->subset_max_children > (uint32_t)SUBSET_Q)
+      fail(BM_ERR_INVALID_ARG, "subset_max_children must be at most %d", SUBSET_Q);
+    t.subset_q = opt->subset_max_children == 1 ? 0u : opt->subset_max_children;
+  }
   if (opt->flags & BM_FLAG_FP4_MFMA) t.mfma_fp4 = true;
   if (opt->flags & BM_FLAG_INT8_MFMA) t.mfma_fp4 = false;
   if (opt->flags & BM_FLAG_NO_MFMA) {
@@ -726,8 +733,13 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       }
     }
     const double nW = N ? sumW / N : 0, nN = N ? sumN / N : 0;  // per-database means for work counts
-    // one workgroup walks a whole subtree, so long columns favour the level-synchronous path
-    if (Wmax > tu.dfs_max_words) tu.dfs = false;
+    // one workgroup walks a whole subtree, so long columns take the subset-counting
+    // subtrees instead (word ranges spread over the chip), or the level-synchronous path
+    if (tu.dfs && Wmax > tu.dfs_max_words) {
+      tu.dfs = tu.subset_q >= 2;
+      tu.subsets = tu.dfs;
+      if (tu.subsets) tu.tiny_q = tu.subset_q;
+    }
     // one threshold for every live database lets the candidate threshold skip the class lookup
     uint32_t uniform_thr = 0;
     for (uint32_t d = 0; d < N; ++d) {
@@ -846,8 +858,8 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         TBuf<uint32_t> cnt(nk, s), iscls(nk, s);
         TBuf<uint64_t> trisz(nk, s);
         launch_node_counts(nk, k, L[k].parent.get(), pcls_prev.get(), w->cls.get(), S.get(),
-                           tu.mfma_min_q, tu.mfma_big_q, tu.mfma_small ? 1u : 0u, cnt.get(),
-                           iscls.get(), trisz.get(), dst.get(), s);
+                           tu.mfma_min_q, tu.mfma_big_q, tu.mfma_small ? 1u : 0u, tu.tiny_q,
+                           cnt.get(), iscls.get(), trisz.get(), dst.get(), s);
         L[k].cstart.alloc(nk + 1, s);
         TBuf<uint64_t> clspos(nk + 1, s), trioff(nk + 1, s);
         const void* ins[3] = {cnt.get(), iscls.get(), trisz.get()};
@@ -952,8 +964,10 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       const bool trace = (flags & BM_FLAG_TRACE) != 0;
       TBuf<uint32_t> order;
       TBuf<float> feats;
+      // subset counting needs no queue order: the model is not consulted
+      const bool ordered = sched && !tu.subsets;
       tm.begin(BM_K_SCHED);
-      if (sched || trace) {
+      if (ordered || trace) {
         feats.alloc(D * MLP_IN, s);
         FeatArgs fa{};
         fa.dbs = ddb_p;
@@ -967,14 +981,14 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         launch_dfs_features(fa, s);
       }
       std::vector<uint32_t> perm;
-      if (sched) {
+      if (ordered) {
         TBuf<float> pred(D, s);
         TBuf<uint32_t> hist(256, s);
         TBuf<uint64_t> hoff(257, s);
         order.alloc(D, s);
         model_predict_device(sched, feats.get(), D, pred.get(), s);
         launch_order_by_key(pred.get(), (uint32_t)D, hist.get(), hoff.get(), order.get(), s);
-      } else if (flags & BM_FLAG_SHUFFLE) {
+      } else if ((flags & BM_FLAG_SHUFFLE) && !tu.subsets) {
         perm.resize(D);
         for (uint64_t i = 0; i < D; ++i) perm[i] = (uint32_t)i;
         uint64_t x = 0x243F6A8885A308D3ull ^ (opt ? opt->shuffle_seed : 0u);
@@ -994,7 +1008,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       // rest to the one-stack-per-workgroup kernel; a stable split keeps the
       // queue order within each
       TBuf<uint32_t> qshort, qlong, qcnt;
-      if (tu.dfs_wave_words) {
+      if (tu.dfs_wave_words && !tu.subsets) {
         TBuf<uint32_t> qflag(D, s);
         TBuf<uint64_t> qpos(D + 1, s);
         qshort.alloc(D, s);
@@ -1012,6 +1026,15 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       TBuf<unsigned long long> lstat(2 * (BM_MAX_LEVELS + 1) + 1, s);
       TBuf<float> cost;
       if (trace) cost.alloc(D, s);
+      // subset counting: a counter block per task, and word ranges per task
+      // enough for about eight workgroups per CU (ranges of >= 1,024 words)
+      TBuf<uint32_t> scnt;
+      uint32_t splits = 1;
+      if (tu.subsets) {
+        scnt.alloc(D << SUBSET_Q, s);
+        const uint64_t want = ceil_div((uint64_t)cu_count() * 8, D);
+        splits = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, Wmax / 1024));
+      }
       // workers reserve arena space ARENA_CHUNK (256) nodes at a time
       const uint64_t workers = (uint64_t)cu_count() * (16 + 2048 / tu.dfs_threads);
       uint64_t cap = std::max<uint64_t>(1u << 16, 32 * D) + workers * 256;
@@ -1030,6 +1053,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         launch_fill_u32(ctrl.get(), 0, 3, s);
         launch_fill_u32(dflags.get(), 0, 1, s);
         launch_fill_u64(reinterpret_cast<uint64_t*>(lstat.get()), 0, hstat.size(), s);
+        if (tu.subsets) launch_fill_u32(scnt.get(), 0, D << SUBSET_Q, s);
         DfsArgs da{};
         da.dbs = ddb_p;
         da.tasks = tasks.get();
@@ -1051,7 +1075,10 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         da.words_read = lstat.get() + 2 * (BM_MAX_LEVELS + 1);
         da.task_cost = trace ? cost.get() : nullptr;
         tm.begin(BM_K_DFS);
-        if (tu.dfs_wave_words) {
+        if (tu.subsets) {
+          launch_subset_count(da, scnt.get(), splits, s);
+          launch_subset_emit(da, scnt.get(), s);
+        } else if (tu.dfs_wave_words) {
           DfsArgs dw = da;
           dw.order = qshort.get();
           dw.ntasks_dev = qcnt.get();
@@ -1060,8 +1087,10 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
           da.order = qlong.get();
           da.ntasks_dev = qcnt.get() + 1;
         }
-        launch_dfs(da, tu.dfs_threads,
-                   (uint32_t)std::min<uint64_t>(D, (uint64_t)cu_count() * (2048 / tu.dfs_threads)), s);
+        if (!tu.subsets)
+          launch_dfs(da, tu.dfs_threads,
+                     (uint32_t)std::min<uint64_t>(D, (uint64_t)cu_count() * (2048 / tu.dfs_threads)),
+                     s);
         tm.end();
         uint32_t* hc = pinned_array<uint32_t>(2);
         uint32_t* phf = pinned_array<uint32_t>(1);

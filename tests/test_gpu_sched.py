@@ -68,6 +68,43 @@ def test_depth_first_equals_level_sync_and_oracle(bm, name, db, minsup):
     assert s1["frequent"] == s2["frequent"]
 
 
+@pytest.mark.parametrize("qs", [2, 4, 6])
+@pytest.mark.parametrize("name,db,minsup", _cases(), ids=[c[0] for c in _cases()])
+def test_subset_counting_equals_level_sync_and_oracle(bm, name, db, minsup, qs):
+    # dfs_max_words=1 sends every database with more than one word per column
+    # to subset counting; classes of at most qs children are mined whole
+    minsup = db.minsup if minsup is None else minsup
+    print(f"subsets qs={qs} vs levelsync {name} n={db.n} m={db.m} minsup={minsup}", flush=True)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    r = bm.bm_mine_ex(h, minsup, bm.options(dfs_max_words=1, subset_max_children=qs))
+    r_ls = bm.bm_mine_ex(h, minsup, bm.options(bm.FLAG_LEVELSYNC))
+    assert _arrays_equal(r.arrays(), _oracle(db, minsup))
+    s1, s2 = r.stats(), r_ls.stats()
+    assert s1["candidates"] == s2["candidates"]
+    assert s1["frequent"] == s2["frequent"]
+
+
+def test_subset_counting_batch_trace_and_bad_option(bm):
+    # a batch in one call (per-database thresholds and word counts), with the
+    # trace on and a shuffled order (ignored: subset counting keeps no queue)
+    dbs = [gen.batch_db(k, scale=0.1) for k in range(6)]
+    hs = [bm.bm_build(d.row_ptr, d.col_idx, d.n, d.m) for d in dbs]
+    ms = [d.minsup for d in dbs]
+    print("subsets on a batch", flush=True)
+    ref = bm.bm_mine_batch(hs, ms, opts=bm.options(bm.FLAG_LEVELSYNC))
+    got = bm.bm_mine_batch(hs, ms, opts=bm.options(bm.FLAG_TRACE | bm.FLAG_SHUFFLE, shuffle_seed=2,
+                                                   dfs_max_words=1))
+    st = got[0].stats()
+    assert st["dfs_tasks"] > 0
+    f, y = got[0].trace()
+    assert f.shape == (st["dfs_tasks"], 8) and np.all(y > 0)
+    for d, a, b in zip(dbs, ref, got):
+        assert _arrays_equal(a.arrays(), b.arrays())
+        assert _arrays_equal(b.arrays(), _oracle(d, d.minsup))
+    with pytest.raises(bm.BmError):
+        bm.bm_mine_ex(hs[0], ms[0], bm.options(subset_max_children=7))
+
+
 @pytest.mark.parametrize("mmc", [2, 9, 16, 64])
 def test_depth_first_under_class_routings(bm, mmc):
     db = gen.make_config(2)
@@ -265,13 +302,23 @@ def test_depth_first_wave_kernel_on_batch_with_split(bm):
 
 @pytest.mark.parametrize("k", [3, 5])
 def test_depth_first_forced_on_full_size(bm, k):
-    # full-size columns (15,625 words) exceed the default depth-first cut-off;
-    # forcing the depth-first phase must still give the level-synchronous result
+    # full-size columns (15,625 words) exceed the default depth-first cut-off:
+    # by default small subtrees are mined by subset counting; that and the
+    # forced depth-first phase must both give the level-synchronous result,
+    # with the same candidate and frequent counts per length
     db = gen.make_config(k)
-    print(f"forced dfs on workload {k} n={db.n}", flush=True)
+    print(f"subsets / forced dfs on workload {k} n={db.n}", flush=True)
     h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
-    base = bm.bm_mine(h, db.minsup)
+    base = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_LEVELSYNC))
     assert base.stats()["dfs_tasks"] == 0
+    sub = bm.bm_mine(h, db.minsup)
+    assert sub.stats()["dfs_tasks"] > 0
+    assert _arrays_equal(sub.arrays(), base.arrays())
+    for key in ("candidates", "frequent"):
+        assert sub.stats()[key] == base.stats()[key], key
+    off = bm.bm_mine_ex(h, db.minsup, bm.options(subset_max_children=1))
+    assert off.stats()["dfs_tasks"] == 0
+    assert _arrays_equal(off.arrays(), base.arrays())
     r = bm.bm_mine_ex(h, db.minsup, bm.options(dfs_threads=1024, dfs_max_words=0xFFFFFFFF))
     assert r.stats()["dfs_tasks"] > 0
     assert _arrays_equal(r.arrays(), base.arrays())
