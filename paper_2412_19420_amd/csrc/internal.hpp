@@ -131,7 +131,7 @@ constexpr int GRAM_TILE_BIG = 256;  // big-class MFMA kernel output tile
 constexpr int GRAM_KW = 16;     // MFMA kernel words per LDS stage
 constexpr int AP_BLOCK = 16;    // AND+popcount kernel children per block
 constexpr int GRAM_SMALL_TILE = 32;  // mid-size-class MFMA kernel children per block
-constexpr int GRAM_SMALL_KW = 16;    // its task word ranges are multiples of this
+constexpr int GRAM_SMALL_KW = 32;    // its task word ranges are multiples of this
 constexpr int TINY_Q = 8;       // classes up to this many children use the register kernel
 constexpr int SUBSET_Q = 6;     // largest class mined whole by subset counting (2^6 counters)
 
