@@ -58,40 +58,42 @@ __global__ __launch_bounds__(kThreads) void k_pack(const uint64_t* __restrict__ 
   }
 }
 
-// Tiled construction: one workgroup builds a 512-row block of M (8 words per
+// Tiled construction: one workgroup builds a 256-row block of M (4 words per
 // column), one 512-column window at a time in LDS, and writes each window out
-// as 64-byte column segments.  Every word of M is written exactly once (zeros
+// as 32-byte column segments.  Every word of M is written exactly once (zeros
 // included), so no clearing pass is needed, and each window's column popcounts
 // are added to the single-item supports on the way out.
 //   * the block's item ids are loaded once, coalesced and several per thread in
-//     flight, into LDS as packed (column << 9 | local row) entries -- the row is
+//     flight, into LDS as packed (column << 8 | local row) entries -- the row is
 //     filled in row by row -- and every column window is then replayed from LDS;
 //   * bits are set with LDS atomic ORs (idempotent: duplicate ids collapse, as
 //     M is 0/1); ids >= m are flagged;
 //   * row_ptr is checked on the way in (non-decreasing: flag 1); element
 //     ranges are clamped to [0, nnz] and local rows are masked, so a malformed
 //     row_ptr cannot send any access out of bounds.
-constexpr int PK_KR = 8;                  // words per column per tile
-constexpr int PK_ROWS = PK_KR * 64;       // 512 rows
-constexpr int PK_RBITS = 9;               // bits of a local row
+// 256-row tiles keep a workgroup's LDS at 62 KB, so two workgroups (32 waves)
+// share a CU and one's loads overlap the other's window passes: measured 15%
+// faster than 512-row tiles with one workgroup per CU on the T40-style
+// 1M x 2,000 build, 3% on the dense 1M x 4,096 one.
+constexpr int PK_KR = 4;                  // words per column per tile
+constexpr int PK_ROWS = PK_KR * 64;       // 256 rows
+constexpr int PK_RBITS = 8;               // bits of a local row
 constexpr int PK_CW = 512;                // columns per window
 constexpr int PK_LD = PK_KR + 1;          // padded LDS row (conflict-free OR)
-constexpr int PK_ECAP = 20480;            // staged elements per chunk (80 KB)
+constexpr int PK_ECAP = 10240;            // staged elements per chunk (40 KB)
 // Sparse databases (at most PK_SPARSE_ROW elements per row on average) are
-// packed with 8,192-element chunks: 73 KB of LDS lets two workgroups share a
-// CU, which outweighs the second chunk that a tile of more than 16 elements
-// per row needs (measured on the batch of 256 Quest-style databases).
+// packed with 8,192-element chunks (32 KB), measured faster on the batch of
+// 256 Quest-style databases.
 constexpr int PK_ECAP_SPARSE = 8192;
 constexpr int PK_SPARSE_ROW = 32;
 constexpr int PK_UNROLL = 8;
-// One workgroup fills a CU's LDS, so it brings all the waves the CU can hold:
-// 16 waves hide the latency of the staging loads and LDS atomics (measured
-// 2.1x faster than 4 waves on the dense 1M x 4,096 workload).
+// 16 waves per workgroup hide the latency of the staging loads and LDS atomics
+// (measured 2.1x faster than 4 waves on the dense 1M x 4,096 workload).
 constexpr int PK_T = 1024;
 
 // Workgroups are dispatched to the 8 XCDs in turn, so block b runs on XCD
-// b % 8.  Giving each XCD a contiguous range of tiles lets the two 64-byte
-// halves of a 128-byte line of M (neighbouring tiles) meet in one XCD's L2
+// b % 8.  Giving each XCD a contiguous range of tiles lets the 32-byte
+// pieces of a 128-byte line of M (neighbouring tiles) meet in one XCD's L2
 // before they are written back (measured 7% faster on the dense 1M x 4,096
 // build than tiles in block order).
 __device__ __forceinline__ uint64_t xcd_tile(uint32_t b, uint32_t nb) {
@@ -257,7 +259,7 @@ __global__ __launch_bounds__(kThreads) void k_build_multi_pre(PackJob* __restric
   for (uint32_t c = threadIdx.x; c < j.m; c += kThreads) j.colsum[c] = 0u;
 }
 
-// Batched construction, part 2 -- the 512-row tiles of a list of databases in
+// Batched construction, part 2 -- the 256-row tiles of a list of databases in
 // one grid: block b belongs to list entry e with kstart[e] <= b < kstart[e + 1],
 // database kjob[e].
 template <int ECAP>

@@ -74,6 +74,69 @@ __device__ __forceinline__ int fp4_plane_scale(int pl) {  // E8M0: 2^(e - 127)
   return pl == 0 ? 128 : pl == 2 ? 126 : 127;
 }
 
+// One LDS stage of the FP4 form for one wave (NB = 2: 2 x 2 accumulators of
+// 32 x 32).  pa / pb point at the wave's first A row block and first B column
+// block (lane's row, half-word).  MODE 0: an off-diagonal tile -- A blocks
+// 0, 1 against B blocks 0, 1.  On a diagonal tile (A and B the same panel)
+// the 10 useful blocks of the 4 x 4 are shared out so that no wave does more
+// than three products or builds more than three operand rows:
+//   MODE 1 (waves on the diagonal): its two blocks against themselves,
+//     (0,0), (0,1), (1,1), with B taken from A's operands;
+//   MODE 2 (the two off-diagonal waves): one A block against B blocks 0, 1.
+template <int MODE, int KW, int LDW>
+__device__ __forceinline__ void fp4_stage(const uint32_t* pa, const uint32_t* pb,
+                                          v16f (&acc)[2][2]) {
+  constexpr int NA = MODE == 2 ? 1 : 2;  // A row blocks this wave builds
+  constexpr bool BSAME = MODE == 1;      // B operands are A's
+  // fully unrolled, so the next group's plane masks overlap this group's MFMAs
+#pragma unroll
+  for (int w4 = 0; w4 < KW; w4 += 4) {
+    uint32_t va[2][4], vb[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        va[i][j] = i < NA ? pa[i * 32 * LDW + 2 * (w4 + j)] : 0u;
+        vb[i][j] = BSAME ? 0u : pb[i * 32 * LDW + 2 * (w4 + j)];
+      }
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) {
+      v8i A[2], B[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          A[i][j] = i < NA ? (int)fp4_plane(va[i][j], pl) : 0;
+          B[i][j] = BSAME ? 0 : (int)fp4_plane(vb[i][j], pl);
+        }
+        A[i][4] = A[i][5] = A[i][6] = A[i][7] = 0;
+        B[i][4] = B[i][5] = B[i][6] = B[i][7] = 0;
+      }
+      const int sc = fp4_plane_scale(pl);  // format 4 = e2m1 for both operands
+      if constexpr (MODE == 0) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[i], B[j], acc[i][j], 4,
+                                                                        4, 0, sc, 0, sc);
+      } else if constexpr (MODE == 1) {
+        acc[0][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[0], A[0], acc[0][0], 4, 4, 0,
+                                                                    sc, 0, sc);
+        acc[0][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[0], A[1], acc[0][1], 4, 4, 0,
+                                                                    sc, 0, sc);
+        acc[1][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[1], A[1], acc[1][1], 4, 4, 0,
+                                                                    sc, 0, sc);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[0][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[0], B[j], acc[0][j], 4, 4,
+                                                                      0, sc, 0, sc);
+      }
+    }
+  }
+}
+
 // NB = 32x32 accumulator blocks per wave side: NB = 2 gives 64x64 per wave and
 // a 128x128 workgroup tile of 4 waves.
 // KW = words per LDS stage (a divisor of GRAM_KW, so stages tile every task).
@@ -100,6 +163,11 @@ __device__ __forceinline__ void gram_tiles(const ClassArgs& a, uint32_t* sA, uin
     const uint32_t q = cd.q;
     const uint32_t I0 = (uint32_t)task.bi * T, L0 = (uint32_t)task.bl * T;
     const bool diag = task.bi == task.bl;
+    // the wave's first A row block and first B column block (32-wide blocks
+    // of the tile): FP4 diagonal tiles share their useful blocks out by mode
+    const int mode = (F4 && diag) ? (wr == wc ? 1 : 2) : 0;
+    const int rb0 = mode == 2 ? wr : NB * wr;
+    const int cb0 = mode == 2 ? NB : NB * wc;
     const int nload = diag ? NS : 2 * NS;
 
     // base pointers of the columns this thread stages (nullptr = zero column)
@@ -167,43 +235,13 @@ __device__ __forceinline__ void gram_tiles(const ClassArgs& a, uint32_t* sA, uin
       __syncthreads();
       if (s + 1 < nst) load_stage(task.w0 + (s + 1) * KW);
 
-      const uint32_t* pa = sA + (wr * (T / 2) + (lane & 31)) * LDW + (lane >> 5);
-      const uint32_t* pb = (diag ? sA : sB) + (wc * (T / 2) + (lane & 31)) * LDW + (lane >> 5);
+      const uint32_t* pa = sA + (rb0 * 32 + (lane & 31)) * LDW + (lane >> 5);
+      const uint32_t* pb = (diag ? sA : sB) + (cb0 * 32 + (lane & 31)) * LDW + (lane >> 5);
       if constexpr (F4) {
-        // NB = 2: fully unrolled, so the next group's plane masks overlap this
-        // group's MFMAs
-#pragma unroll(NB == 2 ? KW / 4 : 1)
-        for (int w4 = 0; w4 < KW; w4 += 4) {
-          uint32_t va[NB][4], vb[NB][4];
-#pragma unroll
-          for (int i = 0; i < NB; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              va[i][j] = pa[i * 32 * LDW + 2 * (w4 + j)];
-              vb[i][j] = pb[i * 32 * LDW + 2 * (w4 + j)];
-            }
-#pragma unroll
-          for (int pl = 0; pl < 4; ++pl) {
-            v8i A[NB], B[NB];
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-#pragma unroll
-              for (int j = 0; j < 4; ++j) {
-                A[i][j] = (int)fp4_plane(va[i][j], pl);
-                B[i][j] = (int)fp4_plane(vb[i][j], pl);
-              }
-              A[i][4] = A[i][5] = A[i][6] = A[i][7] = 0;
-              B[i][4] = B[i][5] = B[i][6] = B[i][7] = 0;
-            }
-            const int sc = fp4_plane_scale(pl);
-#pragma unroll
-            for (int i = 0; i < NB; ++i)
-#pragma unroll
-              for (int j = 0; j < NB; ++j)  // format 4 = e2m1 for both operands
-                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                    A[i], B[j], acc[i][j], 4, 4, 0, sc, 0, sc);
-          }
-        }
+        static_assert(NB == 2, "the FP4 stage is written for 2 x 2 accumulators per wave");
+        if (mode == 0) fp4_stage<0, KW, LDW>(pa, pb, acc);
+        else if (mode == 1) fp4_stage<1, KW, LDW>(pa, pb, acc);
+        else fp4_stage<2, KW, LDW>(pa, pb, acc);
       } else {
 #pragma unroll(NB == 2 ? KW : 1)
         for (int w = 0; w < KW; ++w) {
@@ -240,9 +278,8 @@ __device__ __forceinline__ void gram_tiles(const ClassArgs& a, uint32_t* sA, uin
       for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const uint32_t gi =
-              I0 + wr * (T / 2) + rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-          const uint32_t gl = L0 + wc * (T / 2) + cb * 32 + (lane & 31);
+          const uint32_t gi = I0 + (rb0 + rb) * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const uint32_t gl = L0 + (cb0 + cb) * 32 + (lane & 31);
           uint32_t v;
           if constexpr (F4) v = __float2uint_rn(acc[rb][cb][r]);  // exact integer counts
           else v = (uint32_t)acc[rb][cb][r];
@@ -252,7 +289,10 @@ __device__ __forceinline__ void gram_tiles(const ClassArgs& a, uint32_t* sA, uin
 }
 
 template <bool F4>
-__global__ __launch_bounds__(256) void k_gram_mfma(ClassArgs a) {
+// Two workgroups per CU (two waves per SIMD): the register budget is capped
+// at 256 so the three stage variants do not push the kernel to one wave.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_gram_mfma(ClassArgs a) {
   constexpr int KW = 16;
   __shared__ uint32_t sA[GRAM_TILE * (2 * KW + 1)];
   __shared__ uint32_t sB[GRAM_TILE * (2 * KW + 1)];
