@@ -110,32 +110,26 @@ DTYPE = {"fp4": "u64 bitsets; fp4 (e2m1) MFMA, fp32 accumulate (exact: counts < 
 
 # HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by
 # the copy calibration), valid only while the kernel's source is unchanged:
-# (workload, kernel, form) -> (sha256 of the source file, bytes per launch).
+# (workload, kernel, form) -> (source file, its sha256, bytes per launch).
 TRAFFIC = {
     # dense_planted 1M x 4,096 (profiles/dense_planted_1M_hbm_traffic.md)
-    (3, "gram_mfma", "fp4"): ("d1e68fb44a162bdf8ce86a5d8a1bf9f059d6869a2aafe40275f87b9d92d07dc9", 2752.5e6),
-    (3, "andpop_reg", "fp4"): ("29d6103342951cee0aaee29ca2a37e34e3c93ca6b3f31f2840111dcbe41caa56", 551.5e6),
-    (3, "gram_small", "fp4"): ("b72a42d014a78320b850165b51eb79887bf398287b88b7b726bb78c59dd610f0", 129.4e6),
-}
-KERNEL_SOURCE = {
-    "gram_mfma": "k_gram_mfma.hip", "gram_mfma_big": "k_gram_big.hip",
-    "gram_small": "k_gram_small.hip",
-    "andpop": "k_andpop.hip", "andpop_reg": "k_andpop.hip", "dfs": "k_dfs.hip",
+    (3, "gram_mfma", "fp4"): ("k_gram_mfma.hip", "d494831ca8b34b3bc89b3e03712ceba98f8a302952b66bece8d5e39e52326447", 3194.5e6),
+    (3, "gram_small", "fp4"): ("k_gram_small.hip", "f5838556e51a593149d221a8305e3fde2e735c73c0970d0a561de7f91139de72", 226.7e6),
+    (3, "dfs", "fp4"): ("k_subsets.hip", "42d527853ef18480d13f15b0a89d4522100279a01881645dcebff148ed099b25", 774.5e6),
 }
 WORKLOAD = None
 
 
 def traffic_of(kernel: str, form: str):
     rec = TRAFFIC.get((WORKLOAD, kernel, form))
-    src = KERNEL_SOURCE.get(kernel)
-    if rec is None or src is None:
+    if rec is None:
         return None
     import hashlib
-    path = os.path.join(ROOT, "paper_2412_19420_amd", "csrc", src)
+    path = os.path.join(ROOT, "paper_2412_19420_amd", "csrc", rec[0])
     with open(path, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec[0]:
+        if hashlib.sha256(f.read()).hexdigest() != rec[1]:
             return None
-    return rec[1]
+    return rec[2]
 
 
 def _roofline(kernels, ms, form):
