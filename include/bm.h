@@ -133,7 +133,7 @@ typedef struct {
                                * column run one stack per wave, the others one per workgroup
                                * (0 = default 1024; see BM_FLAG_DFS_BLOCK_ONLY) */
   uint32_t subset_max_children;/* when columns are too long for the depth-first phase, classes of
-                               * at most this many children (2..6) are mined whole: every subset
+                               * at most this many children (2..8) are mined whole: every subset
                                * of their children is counted in one pass over word ranges, and
                                * the rest of such a subtree needs no further level step
                                * (0 = default 6; 1 = never, level by level instead) */

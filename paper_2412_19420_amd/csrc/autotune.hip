@@ -74,6 +74,8 @@ bm_options autotune(const bm_db* const* dbs, const uint32_t* minsups, uint32_t c
   try_field([](bm_options& o, uint32_t v) { o.split_words = v; }, {0u, 512u, 1024u, 2048u, 4096u});
   try_field([](bm_options& o, uint32_t v) { o.andpop_chunk_words = v; }, {128u, 256u});
   if (!(cur.flags & BM_FLAG_LEVELSYNC)) {
+    // long columns: small subtrees by subset counting, up to 4, 6 or 8 children, or not at all
+    try_field([](bm_options& o, uint32_t v) { o.subset_max_children = v; }, {1u, 4u, 6u, 8u});
     try_field([](bm_options& o, uint32_t v) { o.dfs_threads = v; }, {256u, 512u, 1024u});
     try_field(
         [](bm_options& o, uint32_t v) {

@@ -73,7 +73,7 @@ struct Tuning {
                                    // (0: every task on the one-stack-per-workgroup kernel)
   // Longer columns: classes of at most subset_q children (0: none) are mined
   // whole by counting every subset of their children over word ranges
-  uint32_t subset_q = SUBSET_Q;
+  uint32_t subset_q = SUBSET_DEFAULT_Q;
   bool subsets = false;            // this call mines small subtrees by subset counting
   uint32_t tiny_q = TINY_Q;        // small-class threshold of this call
 };

@@ -133,7 +133,12 @@ constexpr int AP_BLOCK = 16;    // AND+popcount kernel children per block
 constexpr int GRAM_SMALL_TILE = 32;  // mid-size-class MFMA kernel children per block
 constexpr int GRAM_SMALL_KW = 32;    // its task word ranges are multiples of this
 constexpr int TINY_Q = 8;       // classes up to this many children use the register kernel
-constexpr int SUBSET_Q = 6;     // largest class mined whole by subset counting (2^6 counters)
+constexpr int SUBSET_Q = 8;     // largest class mined whole by subset counting (2^8 counters)
+constexpr int SUBSET_LAT = 6;   // children walked in registers per subset-counting pass
+// Default limit: classes of 7-8 children need 2-4 passes, which measured
+// slower than evaluating them level by level (dense 1M x 4,096: 1.79 against
+// 1.64 ms per mine call; T40-style: 4.77 against 4.45 ms).
+constexpr int SUBSET_DEFAULT_Q = 6;
 
 // Arguments shared by the class kernels.  They loop over the task list from
 // the launched workgroups (persistent, grid-stride); the task count is read
@@ -225,6 +230,15 @@ void launch_pack_multi(const PackJob* jobs, bool sparse, const uint32_t* kjob, u
                        const uint64_t* kstart, uint64_t blocks, uint32_t* err, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s);
+// Zero up to kZeroSegs arrays of 32-bit words in one launch (segments with
+// p == nullptr or n == 0 are skipped).
+constexpr int kZeroSegs = 16;
+struct ZeroSegs {
+  uint32_t* p[kZeroSegs];
+  uint64_t n[kZeroSegs];
+  int count;
+};
+void launch_zero_segs(const ZeroSegs& z, hipStream_t s);
 
 // scans: out[0..n] exclusive, out[n] = total.  tmp sized by scan_tmp_words(n).
 size_t scan_tmp_words(uint64_t n);

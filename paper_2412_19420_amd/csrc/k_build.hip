@@ -714,6 +714,33 @@ void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   BM_LAUNCH_CHECK();
 }
 
+__global__ void k_zero_segs(ZeroSegs z) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint64_t base = 0;
+  for (int k = 0; k < z.count; ++k) {
+    const uint64_t end = base + z.n[k];
+    for (; i < end; i += stride) z.p[k][i - base] = 0u;
+    base = end;
+  }
+}
+
+void launch_zero_segs(const ZeroSegs& z, hipStream_t s) {
+  if (z.count < 0 || z.count > kZeroSegs) fail(BM_ERR_DEVICE, "too many zero segments");
+  uint64_t total = 0;
+  ZeroSegs c{};
+  for (int k = 0; k < z.count; ++k)
+    if (z.p[k] && z.n[k]) {
+      c.p[c.count] = z.p[k];
+      c.n[c.count] = z.n[k];
+      total += z.n[k];
+      ++c.count;
+    }
+  if (total == 0) return;
+  k_zero_segs<<<grid_for(total, kThreads, 16384), kThreads, 0, s>>>(c);
+  BM_LAUNCH_CHECK();
+}
+
 void launch_fill_u64(uint64_t* p, uint64_t v, uint64_t n, hipStream_t s) {
   if (n == 0) return;
   k_fill<uint64_t><<<grid_for(n, kThreads, 16384), kThreads, 0, s>>>(p, v, n);

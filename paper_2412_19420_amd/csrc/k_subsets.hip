@@ -6,7 +6,8 @@
 //     supp(P + {c_i : i in S}) = sum_words popcount(t(P) & AND_{i in S} col(c_i))
 // for subsets S of the children (Eq. 2 with the prefix columns ANDed in first,
 // applied to longer itemsets).  With q <= SUBSET_Q every such subset fits in
-// 2^q counters, so one pass over the columns counts them all:
+// 2^q counters, so one pass over the columns (two or four for q = 7, 8, the
+// repeats served from L2) counts them all:
 //   * k_subset_count: a workgroup takes one word range of one class; each
 //     thread ANDs its words of the prefix and child columns along a
 //     depth-first walk of the subset lattice (one AND per subset, from its
@@ -30,38 +31,47 @@ namespace bm {
 
 namespace {
 
-constexpr int SQ = SUBSET_Q;
-constexpr int SN = 1 << SQ;
+constexpr int LQ = SUBSET_LAT;  // children walked in registers per pass
+constexpr int LN = 1 << LQ;     // counters per pass
+constexpr int SQ = SUBSET_Q;    // most children of a task
+constexpr int SN = 1 << SQ;     // counters per task
 constexpr int kCountThreads = 256;
-constexpr int kEmitThreads = 64;
+constexpr int kEmitThreads = 16;
 
 // Visits every subset that extends MASK by columns L.. (each exactly once, by
-// the step that adds its highest child); x = t(P) & the columns of MASK.
+// the step that adds its highest child); x = t(P) & the pass's fixed columns &
+// the columns of MASK.  all: count single children too (the pass's fixed
+// children already make them sets of two or more).
 template <int L, int MASK>
-__device__ __forceinline__ void subsets_from(const uint64_t (&c0)[SQ], const uint64_t (&c1)[SQ],
-                                             uint64_t x0, uint64_t x1, int q,
-                                             uint32_t (&acc)[SN]) {
-  if constexpr (L < SQ) {
+__device__ __forceinline__ void subsets_from(const uint64_t (&c0)[LQ], const uint64_t (&c1)[LQ],
+                                             uint64_t x0, uint64_t x1, int q, bool all,
+                                             uint32_t (&acc)[LN]) {
+  if constexpr (L < LQ) {
     if (L < q) {
       constexpr int M2 = MASK | (1 << L);
       const uint64_t y0 = x0 & c0[L], y1 = x1 & c1[L];
-      if constexpr (MASK != 0) acc[M2] += (uint32_t)(__popcll(y0) + __popcll(y1));
-      subsets_from<L + 1, M2>(c0, c1, y0, y1, q, acc);
-      subsets_from<L + 1, MASK>(c0, c1, x0, x1, q, acc);
+      if (MASK != 0 || all) acc[M2] += (uint32_t)(__popcll(y0) + __popcll(y1));
+      subsets_from<L + 1, M2>(c0, c1, y0, y1, q, all, acc);
+      subsets_from<L + 1, MASK>(c0, c1, x0, x1, q, all, acc);
     }
   }
 }
 
-// Block b counts word range b % splits of task b / splits.
+// Block b counts word range b % splits of task b / splits.  A task of more
+// than LQ children runs one pass per subset g of its children LQ.. ("fixed"
+// in that pass): the pass ANDs them into the prefix mask and walks the first
+// LQ children, so counter g << LQ | mask holds the set g + mask.  Later passes
+// re-read the block's word range from L2.
 __global__ __launch_bounds__(kCountThreads) void k_subset_count(DfsArgs a,
                                                                 uint32_t* __restrict__ counts,
                                                                 uint32_t splits) {
-  __shared__ uint32_t s_red[kCountThreads / 64][SN];
+  __shared__ uint32_t s_red[kCountThreads / 64][LN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t t = blockIdx.x / splits, sp = blockIdx.x % splits;
   const DfsTask tk = a.tasks[t];
   const DbInfo db = a.dbs[tk.db];
   const int q = (int)tk.q;  // 2 <= q <= SQ
+  const int ql = min(q, LQ), nfix = q - ql;
   const uint32_t W = (uint32_t)db.W;
   // even word ranges: the 16-byte loads at even words stay inside the padded column
   const uint32_t len = ((W + splits - 1) / splits + 1) & ~1u;
@@ -80,42 +90,56 @@ __global__ __launch_bounds__(kCountThreads) void k_subset_count(DfsArgs a,
   }
   const uint32_t* pre = a.step_pre[tk.level] + tk.pre_off;
   const uint32_t pre_len = tk.pre_len;
-  uint32_t acc[SN];
+  for (int g = 0; g < (1 << nfix); ++g) {
+    const int gpop = __popc(g);
+    uint32_t acc[LN];
 #pragma unroll
-  for (int j = 0; j < SN; ++j) acc[j] = 0;
-  for (uint32_t w = w0 + 2 * tid; w < w1; w += 2 * kCountThreads) {
-    uint64_t m0 = ~0ull, m1 = (w + 1 < w1) ? ~0ull : 0ull;
-    for (uint32_t j = 0; j < pre_len; ++j) {
-      const uint4 x = *reinterpret_cast<const uint4*>(db.B + (uint64_t)pre[j] * db.Wp + w);
-      m0 &= (uint64_t)x.x | ((uint64_t)x.y << 32);
-      m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
-    }
-    uint64_t c0[SQ], c1[SQ];
-#pragma unroll
-    for (int i = 0; i < SQ; ++i) {
-      c0[i] = 0;
-      c1[i] = 0;
-      if (i < q) {
-        const uint4 v = *reinterpret_cast<const uint4*>(col[i] + w);
-        c0[i] = (uint64_t)v.x | ((uint64_t)v.y << 32);
-        c1[i] = (uint64_t)v.z | ((uint64_t)v.w << 32);
+    for (int j = 0; j < LN; ++j) acc[j] = 0;
+    uint32_t acc0 = 0;  // the fixed children alone (a set of two when gpop == 2)
+    for (uint32_t w = w0 + 2 * tid; w < w1; w += 2 * kCountThreads) {
+      uint64_t m0 = ~0ull, m1 = (w + 1 < w1) ? ~0ull : 0ull;
+      for (uint32_t j = 0; j < pre_len; ++j) {
+        const uint4 x = *reinterpret_cast<const uint4*>(db.B + (uint64_t)pre[j] * db.Wp + w);
+        m0 &= (uint64_t)x.x | ((uint64_t)x.y << 32);
+        m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
       }
+#pragma unroll
+      for (int i = 0; i < SQ - LQ; ++i)
+        if ((g >> i) & 1) {
+          const uint4 x = *reinterpret_cast<const uint4*>(col[LQ + i] + w);
+          m0 &= (uint64_t)x.x | ((uint64_t)x.y << 32);
+          m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
+        }
+      uint64_t c0[LQ], c1[LQ];
+#pragma unroll
+      for (int i = 0; i < LQ; ++i) {
+        c0[i] = 0;
+        c1[i] = 0;
+        if (i < ql) {
+          const uint4 v = *reinterpret_cast<const uint4*>(col[i] + w);
+          c0[i] = (uint64_t)v.x | ((uint64_t)v.y << 32);
+          c1[i] = (uint64_t)v.z | ((uint64_t)v.w << 32);
+        }
+      }
+      subsets_from<0, 0>(c0, c1, m0, m1, ql, gpop > 0, acc);
+      if (gpop >= 2) acc0 += (uint32_t)(__popcll(m0) + __popcll(m1));
     }
-    subsets_from<0, 0>(c0, c1, m0, m1, q, acc);
-  }
+    acc[0] = acc0;
 #pragma unroll
-  for (int mask = 3; mask < SN; ++mask) {
-    if (__builtin_popcount(mask) < 2 || mask >= (1 << q)) continue;
-    uint32_t v = acc[mask];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) s_red[wave][mask] = v;
-  }
-  __syncthreads();
-  if (tid < (1 << q) && __popc(tid) >= 2) {
-    uint32_t v = 0;
+    for (int mask = 0; mask < LN; ++mask) {
+      if (__builtin_popcount(mask) + gpop < 2 || mask >= (1 << ql)) continue;
+      uint32_t v = acc[mask];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) s_red[wave][mask] = v;
+    }
+    __syncthreads();
+    if (tid < (1 << ql) && __popc(tid) + gpop >= 2) {
+      uint32_t v = 0;
 #pragma unroll
-    for (int j = 0; j < kCountThreads / 64; ++j) v += s_red[j][tid];
-    if (v) atomicAdd(counts + (uint64_t)t * SN + tid, v);
+      for (int j = 0; j < kCountThreads / 64; ++j) v += s_red[j][tid];
+      if (v) atomicAdd(counts + (uint64_t)t * SN + ((uint32_t)g << LQ | tid), v);
+    }
+    __syncthreads();  // s_red is reused by the next pass
   }
 }
 

@@ -1022,9 +1022,15 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
                          qcnt.get(), s);
       }
       std::vector<TBuf<uint32_t>> ls_first(Kls + 2), ls_count(Kls + 2);
-      TBuf<uint32_t> ctrl(3, s);  // [0] workgroup-queue head, [1] arena count, [2] wave-queue head
-      TBuf<uint32_t> dflags(1, s);
-      TBuf<unsigned long long> lstat(2 * (BM_MAX_LEVELS + 1) + 1, s);
+      // one status block, zeroed and read back whole: statistics (candidates and
+      // frequent sets by length, words read), then the queue heads and arena
+      // count ([0] workgroup-queue head, [1] arena count, [2] wave-queue head)
+      // and the flags
+      constexpr size_t kStatWords = 2 * (BM_MAX_LEVELS + 1) + 1;
+      TBuf<unsigned long long> status(kStatWords + 2, s);
+      unsigned long long* lstat = status.get();
+      uint32_t* ctrl = reinterpret_cast<uint32_t*>(status.get() + kStatWords);
+      uint32_t* dflags = ctrl + 3;
       TBuf<float> cost;
       if (trace) cost.alloc(D, s);
       // subset counting: a counter block per task, and word ranges per task
@@ -1040,27 +1046,36 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       const uint64_t workers = (uint64_t)cu_count() * (16 + 2048 / tu.dfs_threads);
       uint64_t cap = std::max<uint64_t>(1u << 16, 32 * D) + workers * 256;
       TBuf<ArenaNode> arena;
-      std::vector<unsigned long long> hstat(2 * (BM_MAX_LEVELS + 1) + 1);
+      std::vector<unsigned long long> hstat(kStatWords);
       for (int attempt = 0;; ++attempt) {
         if (cap > 0xffffffffull) fail(BM_ERR_UNSUPPORTED, "depth-first output too large");
         arena.alloc(cap, s);
+        ZeroSegs z{};
+        auto zero = [&](uint32_t* p, uint64_t n) {
+          if (z.count == kZeroSegs) {
+            launch_zero_segs(z, s);
+            z = ZeroSegs{};
+          }
+          z.p[z.count] = p;
+          z.n[z.count] = n;
+          ++z.count;
+        };
         for (uint32_t j = 1; j <= Kls; ++j) {
           if (!ls_first[j].p) {
             ls_first[j].alloc(L[j].n, s);
             ls_count[j].alloc(L[j].n, s);
           }
-          launch_fill_u32(ls_count[j].get(), 0, L[j].n, s);
+          zero(ls_count[j].get(), L[j].n);
         }
-        launch_fill_u32(ctrl.get(), 0, 3, s);
-        launch_fill_u32(dflags.get(), 0, 1, s);
-        launch_fill_u64(reinterpret_cast<uint64_t*>(lstat.get()), 0, hstat.size(), s);
-        if (tu.subsets) launch_fill_u32(scnt.get(), 0, D << SUBSET_Q, s);
+        zero(reinterpret_cast<uint32_t*>(status.get()), 2 * (kStatWords + 2));
+        if (tu.subsets) zero(scnt.get(), D << SUBSET_Q);
+        launch_zero_segs(z, s);
         DfsArgs da{};
         da.dbs = ddb_p;
         da.tasks = tasks.get();
         da.ntasks = (uint32_t)D;
         da.order = order.get();
-        da.queue_head = ctrl.get();
+        da.queue_head = ctrl;
         for (uint32_t j = 1; j <= Kls; ++j) {
           da.lv_item[j] = L[j].item.get();
           da.step_pre[j] = step_pre[j];
@@ -1068,12 +1083,12 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
           da.ls_count[j] = ls_count[j].get();
         }
         da.arena = arena.get();
-        da.arena_count = ctrl.get() + 1;
+        da.arena_count = ctrl + 1;
         da.arena_cap = (uint32_t)cap;
-        da.flags = dflags.get();
-        da.level_cand = lstat.get();
-        da.level_freq = lstat.get() + (BM_MAX_LEVELS + 1);
-        da.words_read = lstat.get() + 2 * (BM_MAX_LEVELS + 1);
+        da.flags = dflags;
+        da.level_cand = lstat;
+        da.level_freq = lstat + (BM_MAX_LEVELS + 1);
+        da.words_read = lstat + 2 * (BM_MAX_LEVELS + 1);
         da.task_cost = trace ? cost.get() : nullptr;
         tm.begin(BM_K_DFS);
         if (tu.subsets) {
@@ -1083,7 +1098,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
           DfsArgs dw = da;
           dw.order = qshort.get();
           dw.ntasks_dev = qcnt.get();
-          dw.queue_head = ctrl.get() + 2;
+          dw.queue_head = ctrl + 2;
           launch_dfs_wave(dw, (uint32_t)std::min<uint64_t>((D + 3) / 4, (uint64_t)cu_count() * 4), s);
           da.order = qlong.get();
           da.ntasks_dev = qcnt.get() + 1;
@@ -1093,15 +1108,12 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
                      (uint32_t)std::min<uint64_t>(D, (uint64_t)cu_count() * (2048 / tu.dfs_threads)),
                      s);
         tm.end();
-        uint32_t* hc = pinned_array<uint32_t>(2);
-        uint32_t* phf = pinned_array<uint32_t>(1);
-        unsigned long long* pst = pinned_array<unsigned long long>(hstat.size());
-        BM_HIP(hipMemcpyAsync(hc, ctrl.get(), 8, hipMemcpyDeviceToHost, s));
-        BM_HIP(hipMemcpyAsync(phf, dflags.get(), 4, hipMemcpyDeviceToHost, s));
-        BM_HIP(hipMemcpyAsync(pst, lstat.get(), hstat.size() * 8, hipMemcpyDeviceToHost, s));
+        unsigned long long* pst = pinned_array<unsigned long long>(kStatWords + 2);
+        BM_HIP(hipMemcpyAsync(pst, status.get(), (kStatWords + 2) * 8, hipMemcpyDeviceToHost, s));
         BM_HIP(hipStreamSynchronize(s));
-        const uint32_t hf = *phf;
-        std::copy(pst, pst + hstat.size(), hstat.begin());
+        const uint32_t* hc = reinterpret_cast<const uint32_t*>(pst + kStatWords);
+        const uint32_t hf = hc[3];
+        std::copy(pst, pst + kStatWords, hstat.begin());
         st.host_syncs++;
         if (hf & DFS_TOO_LONG)
           fail(BM_ERR_UNSUPPORTED, "frequent itemsets longer than %d items", BM_MAX_LEVELS);

@@ -68,7 +68,7 @@ def test_depth_first_equals_level_sync_and_oracle(bm, name, db, minsup):
     assert s1["frequent"] == s2["frequent"]
 
 
-@pytest.mark.parametrize("qs", [2, 4, 6])
+@pytest.mark.parametrize("qs", [2, 6, 7, 8])
 @pytest.mark.parametrize("name,db,minsup", _cases(), ids=[c[0] for c in _cases()])
 def test_subset_counting_equals_level_sync_and_oracle(bm, name, db, minsup, qs):
     # dfs_max_words=1 sends every database with more than one word per column
@@ -102,7 +102,7 @@ def test_subset_counting_batch_trace_and_bad_option(bm):
         assert _arrays_equal(a.arrays(), b.arrays())
         assert _arrays_equal(b.arrays(), _oracle(d, d.minsup))
     with pytest.raises(bm.BmError):
-        bm.bm_mine_ex(hs[0], ms[0], bm.options(subset_max_children=7))
+        bm.bm_mine_ex(hs[0], ms[0], bm.options(subset_max_children=9))
 
 
 @pytest.mark.parametrize("mmc", [2, 9, 16, 64])
