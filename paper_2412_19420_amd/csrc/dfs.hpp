@@ -70,7 +70,7 @@ void launch_dfs_wave(const DfsArgs& a, uint32_t grid, hipStream_t s);
 // Subset counting (k_subsets.hip), for tasks of at most SUBSET_Q children:
 // counts[t << SUBSET_Q | mask] (zeroed by the caller) receives the support of
 // task t's prefix plus the children in mask, for every mask of two or more
-// children, from `splits` word ranges per task.  Then one thread per task
+// children, from `splits` word ranges per task.  Then one wave per task
 // writes the subtree's frequent itemsets into the arena and links them as the
 // depth-first kernel does (same flags and statistics; queue fields unused).
 void launch_subset_count(const DfsArgs& a, uint32_t* counts, uint32_t splits, hipStream_t s);

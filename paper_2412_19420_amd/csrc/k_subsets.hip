@@ -14,7 +14,7 @@
 //     parent's value) and popcounts every subset of two or more children into
 //     its own register counter; the counters are reduced over the workgroup
 //     and added atomically into the class's counter block;
-//   * k_subset_emit: one thread per class turns the counters into the
+//   * k_subset_emit: one wave per class turns the counters into the
 //     subtree's frequent itemsets.  A subset is frequent when its count meets
 //     the threshold (every subset of a frequent set is frequent, so this is
 //     exactly the set the class-by-class recursion reaches).  The nodes are
@@ -36,7 +36,7 @@ constexpr int LN = 1 << LQ;     // counters per pass
 constexpr int SQ = SUBSET_Q;    // most children of a task
 constexpr int SN = 1 << SQ;     // counters per task
 constexpr int kCountThreads = 256;
-constexpr int kEmitThreads = 16;
+constexpr int kEmitWaves = 4;  // tasks per emit workgroup
 
 // Visits every subset that extends MASK by columns L.. (each exactly once, by
 // the step that adds its highest child); x = t(P) & the pass's fixed columns &
@@ -143,114 +143,137 @@ __global__ __launch_bounds__(kCountThreads) void k_subset_count(DfsArgs a,
   }
 }
 
-// Thread per task: frequent subsets -> arena nodes, links and statistics.  A
-// thread's counter block, queue and node slots live in LDS (odd row stride:
-// the threads of a wave hit different banks).
-__global__ __launch_bounds__(kEmitThreads) void k_subset_emit(DfsArgs a,
-                                                              const uint32_t* __restrict__ counts) {
-  __shared__ uint32_t s_cnt[kEmitThreads][SN + 1];
-  __shared__ uint32_t s_pos[kEmitThreads][SN + 1];
-  __shared__ uint32_t s_queue[kEmitThreads][SN + 1];
+// Orders one wave's LDS writes before its own later reads: a wave's LDS
+// operations complete in issue order, and the fence keeps the compiler from
+// moving them across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Wave per task: frequent subsets -> arena nodes, links and statistics.
+// Lane l owns masks l, l + 64, ...  The arena order is breadth-first: by
+// number of children, then lexicographically by child tuple, which for masks
+// of one size is descending order of the bit-reversed mask.  In that order a
+// node's frequent extensions are consecutive, so every node's children form
+// one block, the format the depth-first kernel writes.
+__global__ __launch_bounds__(64 * kEmitWaves) void k_subset_emit(DfsArgs a,
+                                                                 const uint32_t* __restrict__ counts) {
+  constexpr int MPL = SN / 64;  // masks per lane
+  __shared__ uint32_t s_cnt[kEmitWaves][SN];
+  __shared__ uint32_t s_fr[kEmitWaves][SN];   // mask is a frequent set (single children: 1)
+  __shared__ uint32_t s_pos[kEmitWaves][SN];  // arena slot of a frequent mask of >= 2 children
   __shared__ unsigned long long s_cand[BM_MAX_LEVELS + 1], s_freq[BM_MAX_LEVELS + 1];
   __shared__ unsigned long long s_words;
-  const int tid = threadIdx.x;
-  for (int j = tid; j <= BM_MAX_LEVELS; j += kEmitThreads) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = tid; j <= BM_MAX_LEVELS; j += 64 * kEmitWaves) {
     s_cand[j] = 0;
     s_freq[j] = 0;
   }
   if (tid == 0) s_words = 0;
   __syncthreads();
-  const uint32_t t = blockIdx.x * kEmitThreads + tid;
-  if (t < a.ntasks) {
+  const uint32_t t = blockIdx.x * kEmitWaves + wave;
+  if (t < a.ntasks) {  // uniform over the wave
     const DfsTask tk = a.tasks[t];
     const DbInfo db = a.dbs[tk.db];
     const uint32_t q = tk.q, level = tk.level, minsup = db.minsup;
     const uint32_t nsub = 1u << q;
-    uint32_t* cnt = s_cnt[tid];
-    uint32_t* pos = s_pos[tid];
-    uint32_t* queue = s_queue[tid];
-    const uint4* src = reinterpret_cast<const uint4*>(counts + (uint64_t)t * SN);
-    for (uint32_t k = 0; k < (nsub + 3) / 4; ++k) {
-      const uint4 v = src[k];
-      cnt[4 * k] = v.x;
-      cnt[4 * k + 1] = v.y;
-      cnt[4 * k + 2] = v.z;
-      cnt[4 * k + 3] = v.w;
-    }
-    uint32_t item[SQ];
-    const uint32_t* lit = a.lv_item[tk.level] + tk.child0;
+    uint32_t* cnt = s_cnt[wave];
+    uint32_t* fr = s_fr[wave];
+    uint32_t* pos = s_pos[wave];
 #pragma unroll
-    for (int i = 0; i < SQ; ++i) item[i] = i < (int)q ? lit[i] : 0u;
-    uint32_t total = 0, maxj = 1;  // arena nodes; most children in a frequent subset
-    for (uint32_t m = 3; m < nsub; ++m)
-      if (__popc(m) >= 2 && cnt[m] >= minsup) {
-        total += 1;
-        maxj = max(maxj, (uint32_t)__popc(m));
-      }
-    bool ok = true;
-    if (level + maxj - 1 > BM_MAX_LEVELS) {  // itemsets of level + j - 1 items
-      atomicOr(a.flags, DFS_TOO_LONG);
-      ok = false;
+    for (int k = 0; k < MPL; ++k) {
+      const uint32_t m = lane + 64 * k;
+      const uint32_t c = m < nsub ? counts[(uint64_t)t * SN + m] : 0u;
+      const int j = __popc(m);
+      cnt[m] = c;
+      fr[m] = (m < nsub && (j == 1 || (j >= 2 && c >= minsup))) ? 1u : 0u;
     }
+    wave_lds_sync();
+    // per owned mask: frequent sets of 2..j-1 children before it, and of j
+    // children ordered before it; also the totals
+    uint32_t before[MPL], rank[MPL], mj[MPL], mbr[MPL];
+#pragma unroll
+    for (int k = 0; k < MPL; ++k) {
+      const uint32_t m = lane + 64 * k;
+      before[k] = 0;
+      rank[k] = 0;
+      mj[k] = (uint32_t)__popc(m);
+      mbr[k] = __brev(m) >> (32 - q);
+    }
+    uint32_t total = 0, maxj = 1;
+    for (uint32_t m2 = 3; m2 < nsub; ++m2) {
+      const uint32_t j2 = (uint32_t)__popc(m2);
+      if (j2 < 2 || !fr[m2]) continue;
+      total += 1;
+      maxj = max(maxj, j2);
+      const uint32_t br2 = __brev(m2) >> (32 - q);
+#pragma unroll
+      for (int k = 0; k < MPL; ++k) {
+        before[k] += j2 < mj[k] ? 1u : 0u;
+        rank[k] += (j2 == mj[k] && br2 > mbr[k]) ? 1u : 0u;
+      }
+    }
+    bool ok = level + maxj - 1 <= BM_MAX_LEVELS;  // itemsets of level + j - 1 items
+    if (!ok && lane == 0) atomicOr(a.flags, DFS_TOO_LONG);
     uint32_t base = 0;
     if (ok && total) {
-      base = atomicAdd(a.arena_count, total);
+      if (lane == 0) base = atomicAdd(a.arena_count, total);
+      base = __shfl(base, 0);
       if (base + total > a.arena_cap) {
-        atomicOr(a.flags, DFS_OVERFLOW);
+        if (lane == 0) atomicOr(a.flags, DFS_OVERFLOW);
         ok = false;
       }
     }
-    // breadth-first over the frequent subsets: each node's extensions get
-    // consecutive arena slots, and a node's own slot is known before its turn
-    uint32_t qn = 0;
-    for (uint32_t i = 0; i < q; ++i) queue[qn++] = 1u << i;
-    uint32_t next = base;
-    unsigned long long words = (unsigned long long)(tk.pre_len + q) * db.W;
-    if (ok && level + 1 <= BM_MAX_LEVELS)
-      atomicAdd(&s_cand[level + 1], (unsigned long long)q * (q - 1) / 2);
-    for (uint32_t h = 0; h < qn && ok; ++h) {
-      const uint32_t m = queue[h];
-      const uint32_t j = (uint32_t)__popc(m);
-      const uint32_t hb = 31u - (uint32_t)__clz(m);
-      uint32_t ext = 0;
-      for (uint32_t l = hb + 1; l < q; ++l)
-        if (cnt[m | (1u << l)] >= minsup) ext |= 1u << l;
-      const uint32_t ne = (uint32_t)__popc(ext), first = next;
-      next += ne;
-      if (j == 1) {
-        a.ls_first[level][tk.child0 + hb] = first;
-        a.ls_count[level][tk.child0 + hb] = ne;
-      } else {
-        a.arena[pos[m]].first = first;
-        a.arena[pos[m]].count = ne;
-      }
-      uint32_t r = 0;
-      for (uint32_t e = ext; e; e &= e - 1, ++r) {
-        const uint32_t l = (uint32_t)__ffs(e) - 1, m2 = m | (1u << l);
-        pos[m2] = first + r;
-        ArenaNode an;
-        an.item = item[0];
+    if (ok) {
 #pragma unroll
-        for (int i = 1; i < SQ; ++i)
-          if ((int)l == i) an.item = item[i];
-        an.supp = cnt[m2];
-        an.first = 0;
-        an.count = 0;
-        a.arena[first + r] = an;
-        queue[qn++] = m2;
+      for (int k = 0; k < MPL; ++k) {
+        const uint32_t m = lane + 64 * k;
+        if (m < nsub && mj[k] >= 2 && fr[m]) pos[m] = base + before[k] + rank[k];
       }
-      if (ne) atomicAdd(&s_freq[level + j], (unsigned long long)ne);
-      if (ne >= 2) {  // this node's class: its extensions paired
-        if (level + j + 1 <= BM_MAX_LEVELS)
-          atomicAdd(&s_cand[level + j + 1], (unsigned long long)ne * (ne - 1) / 2);
-        words += (unsigned long long)(tk.pre_len + j + ne) * db.W;
+      wave_lds_sync();
+      const uint32_t* lit = a.lv_item[tk.level] + tk.child0;
+      unsigned long long words = 0;
+#pragma unroll
+      for (int k = 0; k < MPL; ++k) {
+        const uint32_t m = lane + 64 * k;
+        if (m == 0 || m >= nsub || !fr[m]) continue;
+        const uint32_t j = mj[k], hb = 31u - (uint32_t)__clz(m);
+        uint32_t ext = 0;
+        for (uint32_t l = hb + 1; l < q; ++l)
+          if (fr[m | (1u << l)]) ext |= 1u << l;
+        const uint32_t ne = (uint32_t)__popc(ext);
+        const uint32_t first = ne ? pos[m | (1u << (__ffs(ext) - 1))] : 0u;
+        if (j == 1) {
+          a.ls_first[level][tk.child0 + hb] = first;
+          a.ls_count[level][tk.child0 + hb] = ne;
+        } else {
+          ArenaNode an;
+          an.item = lit[hb];
+          an.supp = cnt[m];
+          an.first = first;
+          an.count = ne;
+          a.arena[pos[m]] = an;
+          atomicAdd(&s_freq[level + j - 1], 1ull);
+        }
+        if (ne >= 2) {  // this node's class: its extensions paired
+          if (level + j + 1 <= BM_MAX_LEVELS)
+            atomicAdd(&s_cand[level + j + 1], (unsigned long long)ne * (ne - 1) / 2);
+          words += (unsigned long long)(tk.pre_len + j + ne) * db.W;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) words += __shfl_xor(words, off);
+      if (lane == 0) {
+        const unsigned long long read = (unsigned long long)(tk.pre_len + q) * db.W;
+        if (level + 1 <= BM_MAX_LEVELS)
+          atomicAdd(&s_cand[level + 1], (unsigned long long)q * (q - 1) / 2);
+        if (a.task_cost) a.task_cost[t] = (float)(words + read);
+        atomicAdd(&s_words, read);
       }
     }
-    if (a.task_cost) a.task_cost[t] = (float)words;
-    atomicAdd(&s_words, (unsigned long long)(tk.pre_len + q) * db.W);
   }
   __syncthreads();
-  for (int j = tid; j <= BM_MAX_LEVELS; j += kEmitThreads) {
+  for (int j = tid; j <= BM_MAX_LEVELS; j += 64 * kEmitWaves) {
     if (s_cand[j]) atomicAdd(&a.level_cand[j], s_cand[j]);
     if (s_freq[j]) atomicAdd(&a.level_freq[j], s_freq[j]);
   }
@@ -269,7 +292,7 @@ void launch_subset_count(const DfsArgs& a, uint32_t* counts, uint32_t splits, hi
 
 void launch_subset_emit(const DfsArgs& a, const uint32_t* counts, hipStream_t s) {
   if (a.ntasks == 0) return;
-  k_subset_emit<<<(a.ntasks + kEmitThreads - 1) / kEmitThreads, kEmitThreads, 0, s>>>(a, counts);
+  k_subset_emit<<<(a.ntasks + kEmitWaves - 1) / kEmitWaves, 64 * kEmitWaves, 0, s>>>(a, counts);
   BM_LAUNCH_CHECK();
 }
 
