@@ -74,6 +74,9 @@ void launch_dfs_wave(const DfsArgs& a, uint32_t grid, hipStream_t s);
 // writes the subtree's frequent itemsets into the arena and links them as the
 // depth-first kernel does (same flags and statistics; queue fields unused).
 void launch_subset_count(const DfsArgs& a, uint32_t* counts, uint32_t splits, hipStream_t s);
+// Fewest word ranges per task for columns of W words (the counting kernel's
+// per-thread counters are 16 bits wide).
+uint32_t subset_min_splits(uint64_t W);
 void launch_subset_emit(const DfsArgs& a, const uint32_t* counts, hipStream_t s);
 // flags[t] = 1 if queue entry t (order[t], or t) belongs to a database with at
 // most max_words words per column.

@@ -36,28 +36,34 @@ constexpr int LN = 1 << LQ;     // counters per pass
 constexpr int SQ = SUBSET_Q;    // most children of a task
 constexpr int SN = 1 << SQ;     // counters per task
 constexpr int kCountThreads = 256;
+constexpr uint32_t kMaxPairs = 511;  // word pairs per thread: 16-bit counters hold 511 * 128
 constexpr int kEmitWaves = 4;  // tasks per emit workgroup
 
 // Visits every subset that extends MASK by columns L.. (each exactly once, by
 // the step that adds its highest child); x = t(P) & the pass's fixed columns &
 // the columns of MASK.  all: count single children too (the pass's fixed
-// children already make them sets of two or more).
+// children already make them sets of two or more).  Counters are 16-bit
+// halves of acc (mask m in half m & 1 of acc[m >> 1]), which frees registers
+// for a fourth wave per SIMD; a thread adds at most 128 per word pair, and
+// the host keeps a task's word range to at most kMaxPairs pairs per thread.
 template <int L, int MASK>
 __device__ __forceinline__ void subsets_from(const uint64_t (&c0)[LQ], const uint64_t (&c1)[LQ],
                                              uint64_t x0, uint64_t x1, int q, bool all,
-                                             uint32_t (&acc)[LN]) {
+                                             uint32_t (&acc)[LN / 2]) {
   if constexpr (L < LQ) {
     if (L < q) {
       constexpr int M2 = MASK | (1 << L);
       const uint64_t y0 = x0 & c0[L], y1 = x1 & c1[L];
-      if (MASK != 0 || all) acc[M2] += (uint32_t)(__popcll(y0) + __popcll(y1));
+      if (MASK != 0 || all)
+        acc[M2 >> 1] += (uint32_t)(__popcll(y0) + __popcll(y1)) << (16 * (M2 & 1));
       subsets_from<L + 1, M2>(c0, c1, y0, y1, q, all, acc);
       subsets_from<L + 1, MASK>(c0, c1, x0, x1, q, all, acc);
     }
   }
 }
 
-// Block b counts word range b % splits of task b / splits.  A task of more
+// Block b counts word range b % splits of task b / splits (the host picks
+// splits so that a range holds at most kCountThreads * kMaxPairs word pairs).  A task of more
 // than LQ children runs one pass per subset g of its children LQ.. ("fixed"
 // in that pass): the pass ANDs them into the prefix mask and walks the first
 // LQ children, so counter g << LQ | mask holds the set g + mask.  Later passes
@@ -92,9 +98,9 @@ __global__ __launch_bounds__(kCountThreads) void k_subset_count(DfsArgs a,
   const uint32_t pre_len = tk.pre_len;
   for (int g = 0; g < (1 << nfix); ++g) {
     const int gpop = __popc(g);
-    uint32_t acc[LN];
+    uint32_t acc[LN / 2];
 #pragma unroll
-    for (int j = 0; j < LN; ++j) acc[j] = 0;
+    for (int j = 0; j < LN / 2; ++j) acc[j] = 0;
     uint32_t acc0 = 0;  // the fixed children alone (a set of two when gpop == 2)
     for (uint32_t w = w0 + 2 * tid; w < w1; w += 2 * kCountThreads) {
       uint64_t m0 = ~0ull, m1 = (w + 1 < w1) ? ~0ull : 0ull;
@@ -124,11 +130,10 @@ __global__ __launch_bounds__(kCountThreads) void k_subset_count(DfsArgs a,
       subsets_from<0, 0>(c0, c1, m0, m1, ql, gpop > 0, acc);
       if (gpop >= 2) acc0 += (uint32_t)(__popcll(m0) + __popcll(m1));
     }
-    acc[0] = acc0;
 #pragma unroll
     for (int mask = 0; mask < LN; ++mask) {
       if (__builtin_popcount(mask) + gpop < 2 || mask >= (1 << ql)) continue;
-      uint32_t v = acc[mask];
+      uint32_t v = mask == 0 ? acc0 : (acc[mask >> 1] >> (16 * (mask & 1))) & 0xffffu;
       for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
       if (lane == 0) s_red[wave][mask] = v;
     }
@@ -281,6 +286,11 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_subset_emit(DfsArgs a,
 }
 
 }  // namespace
+
+uint32_t subset_min_splits(uint64_t W) {
+  const uint64_t per = 2ull * kCountThreads * kMaxPairs;  // words per range at most
+  return (uint32_t)((W + per - 1) / per);
+}
 
 void launch_subset_count(const DfsArgs& a, uint32_t* counts, uint32_t splits, hipStream_t s) {
   if (a.ntasks == 0) return;

@@ -1041,6 +1041,8 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         scnt.alloc(D << SUBSET_Q, s);
         const uint64_t want = ceil_div((uint64_t)cu_count() * 8, D);
         splits = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, Wmax / 1024));
+        if (tu.split_words) splits = (uint32_t)ceil_div(std::max<uint64_t>(1, Wmax), tu.split_words);
+        splits = std::max(splits, subset_min_splits(Wmax));
       }
       // workers reserve arena space ARENA_CHUNK (256) nodes at a time
       const uint64_t workers = (uint64_t)cu_count() * (16 + 2048 / tu.dfs_threads);

@@ -489,6 +489,21 @@ def test_fp4_mfma_counts_beyond_fp32_quarter_range(bm):
         assert r.to_list() == want, flags
 
 
+def test_subset_counters_at_their_16_bit_limit(bm):
+    # two items in every one of 16,744,448 rows: 261,632 words, one word range
+    # (split_words above it), so each thread walks 511 word pairs and its
+    # 16-bit counter of the pair ends at 511 * 128 = 65,408 -- the most the
+    # range floor allows; one range more and the counter would wrap
+    n = 261_632 * 64
+    row_ptr = np.arange(0, 2 * n + 1, 2, dtype=np.uint64)
+    col_idx = np.tile(np.array([0, 1], dtype=np.uint32), n)
+    print("subset counter range test, 16.7M rows", flush=True)
+    h = bm.bm_build(row_ptr, col_idx, n, 2)
+    r = bm.bm_mine_ex(h, 1, bm.options(split_words=1 << 19))
+    assert r.stats()["dfs_tasks"] == 1
+    assert r.to_list() == [((0,), n), ((0, 1), n), ((1,), n)]
+
+
 def test_fp4_and_int8_identical_on_full_dense(bm):
     db = gen.make_config(3)
     print("fp4 vs int8, dense 1M", flush=True)
