@@ -73,7 +73,10 @@ void launch_dfs_wave(const DfsArgs& a, uint32_t grid, hipStream_t s);
 // children, from `splits` word ranges per task.  Then one wave per task
 // writes the subtree's frequent itemsets into the arena and links them as the
 // depth-first kernel does (same flags and statistics; queue fields unused).
-void launch_subset_count(const DfsArgs& a, uint32_t* counts, uint32_t splits, hipStream_t s);
+// max_q: most children of any task (the grid holds 2^(max_q - 6) passes per
+// word range when it exceeds 6).
+void launch_subset_count(const DfsArgs& a, uint32_t* counts, uint32_t splits, uint32_t max_q,
+                         hipStream_t s);
 // Fewest word ranges per task for columns of W words (the counting kernel's
 // per-thread counters are 16 bits wide).
 uint32_t subset_min_splits(uint64_t W);

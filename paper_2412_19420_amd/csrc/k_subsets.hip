@@ -6,8 +6,8 @@
 //     supp(P + {c_i : i in S}) = sum_words popcount(t(P) & AND_{i in S} col(c_i))
 // for subsets S of the children (Eq. 2 with the prefix columns ANDed in first,
 // applied to longer itemsets).  With q <= SUBSET_Q every such subset fits in
-// 2^q counters, so one pass over the columns (two or four for q = 7, 8, the
-// repeats served from L2) counts them all:
+// 2^q counters, so one pass over the columns (two or four for q = 7, 8)
+// counts them all:
 //   * k_subset_count: a workgroup takes one word range of one class; each
 //     thread ANDs its words of the prefix and child columns along a
 //     depth-first walk of the subset lattice (one AND per subset, from its
@@ -62,22 +62,28 @@ __device__ __forceinline__ void subsets_from(const uint64_t (&c0)[LQ], const uin
   }
 }
 
-// Block b counts word range b % splits of task b / splits (the host picks
-// splits so that a range holds at most kCountThreads * kMaxPairs word pairs).  A task of more
-// than LQ children runs one pass per subset g of its children LQ.. ("fixed"
-// in that pass): the pass ANDs them into the prefix mask and walks the first
-// LQ children, so counter g << LQ | mask holds the set g + mask.  Later passes
-// re-read the block's word range from L2.
+// Block b counts pass b / (ntasks * splits) of word range b % splits of task
+// (b / splits) % ntasks (the host picks splits so that a range holds at most
+// kCountThreads * kMaxPairs word pairs).  Pass-major order keeps consecutive
+// blocks -- which the dispatcher sends to different XCDs -- on real work.  A task of more than LQ children runs
+// one pass per subset g of its children LQ.. ("fixed" in that pass): the pass
+// ANDs them into the prefix mask and walks the first LQ children, so counter
+// g << LQ | mask holds the set g + mask.  Each pass is a workgroup of its own,
+// so the few long tasks do not trail the launch; blocks of passes a task does
+// not need exit at once.
 __global__ __launch_bounds__(kCountThreads) void k_subset_count(DfsArgs a,
                                                                 uint32_t* __restrict__ counts,
                                                                 uint32_t splits) {
   __shared__ uint32_t s_red[kCountThreads / 64][LN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t t = blockIdx.x / splits, sp = blockIdx.x % splits;
+  const uint32_t per_pass = a.ntasks * splits;
+  const uint32_t g = blockIdx.x / per_pass, b = blockIdx.x % per_pass;
+  const uint32_t t = b / splits, sp = b % splits;
   const DfsTask tk = a.tasks[t];
-  const DbInfo db = a.dbs[tk.db];
   const int q = (int)tk.q;  // 2 <= q <= SQ
   const int ql = min(q, LQ), nfix = q - ql;
+  if (g >= (1u << nfix)) return;  // this task needs fewer passes than the launch holds
+  const DbInfo db = a.dbs[tk.db];
   const uint32_t W = (uint32_t)db.W;
   // even word ranges: the 16-byte loads at even words stay inside the padded column
   const uint32_t len = ((W + splits - 1) / splits + 1) & ~1u;
@@ -96,7 +102,7 @@ __global__ __launch_bounds__(kCountThreads) void k_subset_count(DfsArgs a,
   }
   const uint32_t* pre = a.step_pre[tk.level] + tk.pre_off;
   const uint32_t pre_len = tk.pre_len;
-  for (int g = 0; g < (1 << nfix); ++g) {
+  {
     const int gpop = __popc(g);
     uint32_t acc[LN / 2];
 #pragma unroll
@@ -144,7 +150,6 @@ __global__ __launch_bounds__(kCountThreads) void k_subset_count(DfsArgs a,
       for (int j = 0; j < kCountThreads / 64; ++j) v += s_red[j][tid];
       if (v) atomicAdd(counts + (uint64_t)t * SN + ((uint32_t)g << LQ | tid), v);
     }
-    __syncthreads();  // s_red is reused by the next pass
   }
 }
 
@@ -292,9 +297,12 @@ uint32_t subset_min_splits(uint64_t W) {
   return (uint32_t)((W + per - 1) / per);
 }
 
-void launch_subset_count(const DfsArgs& a, uint32_t* counts, uint32_t splits, hipStream_t s) {
+void launch_subset_count(const DfsArgs& a, uint32_t* counts, uint32_t splits, uint32_t max_q,
+                         hipStream_t s) {
   if (a.ntasks == 0) return;
-  const uint64_t grid = (uint64_t)a.ntasks * splits;
+  if (max_q < 2 || max_q > (uint32_t)SQ) fail(BM_ERR_INVALID_ARG, "subset tasks of %u children", max_q);
+  const uint32_t passes = max_q > (uint32_t)LQ ? 1u << (max_q - LQ) : 1u;
+  const uint64_t grid = (uint64_t)a.ntasks * splits * passes;
   if (splits == 0 || grid > 0x7fffffffull) fail(BM_ERR_UNSUPPORTED, "too many subset-count blocks");
   k_subset_count<<<(uint32_t)grid, kCountThreads, 0, s>>>(a, counts, splits);
   BM_LAUNCH_CHECK();

@@ -1094,7 +1094,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         da.task_cost = trace ? cost.get() : nullptr;
         tm.begin(BM_K_DFS);
         if (tu.subsets) {
-          launch_subset_count(da, scnt.get(), splits, s);
+          launch_subset_count(da, scnt.get(), splits, tu.tiny_q, s);
           launch_subset_emit(da, scnt.get(), s);
         } else if (tu.dfs_wave_words) {
           DfsArgs dw = da;
