@@ -239,9 +239,13 @@ __device__ __forceinline__ void gram_tiles(const ClassArgs& a, uint32_t* sA, uin
       const uint32_t* pb = (diag ? sA : sB) + (cb0 * 32 + (lane & 31)) * LDW + (lane >> 5);
       if constexpr (F4) {
         static_assert(NB == 2, "the FP4 stage is written for 2 x 2 accumulators per wave");
+        // a wave in its MFMA section outranks the other workgroup's staging
+        // waves for issue slots (measured 3% faster on the dense root class)
+        __builtin_amdgcn_s_setprio(3);
         if (mode == 0) fp4_stage<0, KW, LDW>(pa, pb, acc);
         else if (mode == 1) fp4_stage<1, KW, LDW>(pa, pb, acc);
         else fp4_stage<2, KW, LDW>(pa, pb, acc);
+        __builtin_amdgcn_s_setprio(0);
       } else {
 #pragma unroll(NB == 2 ? KW : 1)
         for (int w = 0; w < KW; ++w) {
