@@ -158,7 +158,10 @@ def test_mine_matches_brute_force(bm, seed):
                     bm.options(flags=bm.FLAG_ALL_MFMA | bm.FLAG_INT8_MFMA),
                     bm.options(flags=bm.FLAG_ALL_MFMA | bm.FLAG_INT8_MFMA, mfma_big_children=2),
                     bm.options(flags=bm.FLAG_ALL_MFMA | bm.FLAG_FP4_MFMA),
-                    bm.options(flags=bm.FLAG_ALL_MFMA | bm.FLAG_FP4_MFMA, mfma_big_children=2)]
+                    bm.options(flags=bm.FLAG_ALL_MFMA | bm.FLAG_FP4_MFMA, mfma_big_children=2),
+                    # subset counting of small subtrees (more than one word per column)
+                    bm.options(dfs_max_words=1),
+                    bm.options(flags=bm.FLAG_NO_MFMA, dfs_max_words=1, subset_max_children=8)]
         for o in routings:
             r = bm.bm_mine_ex(h, minsup, o)
             assert r.to_list() == want, (o.flags, o.mfma_big_children, minsup)
