@@ -98,52 +98,6 @@ __global__ void k_gather_idx(const uint64_t* __restrict__ arr, const uint64_t* _
   }
 }
 
-// Threshold of every candidate against its own database's minsup, one thread
-// per candidate, for calls whose databases have different thresholds (with
-// one threshold the candidate scan tests it directly).  The candidate's class
-// is found by binary search over the classes' triangle offsets (ascending by
-// construction), narrowed to the classes of the workgroup's first and last
-// candidates.
-__global__ __launch_bounds__(kThreads) void k_tri_flags(
-    const ClassDesc* __restrict__ cls, uint64_t ncls, const DbInfo* __restrict__ dbs,
-    const uint32_t* __restrict__ tri, uint64_t T, uint32_t* __restrict__ flags) {
-  __shared__ uint64_t s_lo, s_hi;
-  __shared__ uint64_t s_off[kThreads + 1];
-  __shared__ uint32_t s_thr[kThreads + 1];
-  for (uint64_t b0 = (uint64_t)blockIdx.x * kThreads; b0 < T; b0 += (uint64_t)gridDim.x * kThreads) {
-    const uint64_t i = b0 + threadIdx.x;
-    __syncthreads();
-    if (threadIdx.x < 2) {
-      const uint64_t e = threadIdx.x == 0 ? b0 : min<uint64_t>(T - 1, b0 + kThreads - 1);
-      uint64_t lo = 0, hi = ncls;  // tri_off[lo] <= e < tri_off[hi]
-      while (hi - lo > 1) {
-        const uint64_t mid = (lo + hi) >> 1;
-        if (cls[mid].tri_off <= e) lo = mid; else hi = mid;
-      }
-      if (threadIdx.x == 0) s_lo = lo; else s_hi = lo + 1;
-    }
-    __syncthreads();
-    // the block's <= 256 classes (each has at least one candidate): offsets
-    // and thresholds into LDS, then each thread searches there
-    const uint64_t c0 = s_lo;
-    const uint32_t nc = (uint32_t)(s_hi - s_lo);
-    if (threadIdx.x < nc) {
-      const ClassDesc cd = cls[c0 + threadIdx.x];
-      s_off[threadIdx.x] = cd.tri_off;
-      s_thr[threadIdx.x] = dbs[cd.db].minsup;
-    }
-    __syncthreads();
-    if (i < T) {
-      uint32_t lo = 0, hi = nc;  // s_off[lo] <= i < s_off[hi]
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_off[mid] <= i) lo = mid; else hi = mid;
-      }
-      flags[i] = tri[i] >= s_thr[lo] ? 1u : 0u;
-    }
-  }
-}
-
 __device__ inline uint32_t mfma_pairs(uint32_t q, uint32_t tile = GRAM_TILE) {
   const uint32_t nb = (q + tile - 1) / tile;
   return nb * (nb + 1) / 2;
@@ -160,18 +114,21 @@ __device__ inline uint32_t andpop_pairs(uint32_t q, uint32_t block = AP_BLOCK) {
 // next step's task-count bounds.
 __global__ __launch_bounds__(kThreads) void k_node_counts(
     uint64_t n, uint32_t k, const uint32_t* __restrict__ parent, const int32_t* __restrict__ pcls,
-    const ClassDesc* __restrict__ cls, const uint64_t* __restrict__ S, uint32_t mfma_min_q,
-    uint32_t big_q, uint32_t small_on, uint32_t tiny_q, uint32_t* __restrict__ cnt,
-    uint32_t* __restrict__ is_cls,
+    const ClassDesc* __restrict__ cls, const DbInfo* __restrict__ dbs,
+    const uint32_t* __restrict__ tri, uint32_t mfma_min_q, uint32_t big_q, uint32_t small_on,
+    uint32_t tiny_q, uint32_t* __restrict__ cnt, uint32_t* __restrict__ is_cls,
     uint64_t* __restrict__ tri_sz, unsigned long long* __restrict__ st) {
   __shared__ unsigned long long s_st[NC_COUNT];
   if (threadIdx.x < NC_COUNT) s_st[threadIdx.x] = 0;
   __syncthreads();
+  const int lane = threadIdx.x & 63;
   unsigned long long loc[NC_COUNT];
 #pragma unroll
   for (int j = 0; j < NC_COUNT; ++j) loc[j] = 0;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
+  // wave per node: its frequent extensions are the entries of its row of its
+  // class's triangle that meet the class's threshold
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t i = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6; i < n; i += nwaves) {
     const int32_t c = pcls[parent[i]];
     uint32_t kc = 0;
     if (c >= 0) {
@@ -180,24 +137,31 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
       if (li + 1 < cd.q) {
         const uint64_t rs = cd.tri_off + tri_index(li, li + 1, cd.q);
         const uint64_t len = cd.q - li - 1;
-        kc = (uint32_t)(S[rs + len] - S[rs]);
+        const uint32_t minsup = dbs[cd.db].minsup;
+        for (uint64_t t0 = 0; t0 < len; t0 += 64) {
+          const uint64_t t = t0 + lane;
+          const bool f = t < len && tri[rs + t] >= minsup;
+          kc += (uint32_t)__popcll(__ballot(f));
+        }
       }
     }
-    cnt[i] = kc;
-    const bool cl = kc >= 2;
-    const int kind = cl ? class_kind(kc, mfma_min_q, big_q, small_on, tiny_q) : -1;
-    const uint64_t tsz = cl ? (uint64_t)kc * (kc - 1) / 2 : 0ull;
-    is_cls[i] = cl ? 1u : 0u;
-    tri_sz[i] = tsz;
-    if (cl) {
-      loc[ST_CAND_M + kind] += tsz;
-      loc[ST_COLS_M + kind] += kc + k;
-      loc[ST_CLS_M + kind] += 1;
-      // 128-wide tile pairs: also a bound on a big class's 256-wide half tasks;
-      // 16-wide block pairs: also a bound on a mid-size class's 32-wide ones
-      if (kind == 0 || kind == 3) loc[NC_PAIRS_M] += mfma_pairs(kc);
-      else if (kind == 1 || kind == 4) loc[NC_PAIRS_V] += andpop_pairs(kc);
-      else loc[NC_TINY] += 1;
+    if (lane == 0) {
+      cnt[i] = kc;
+      const bool cl = kc >= 2;
+      const int kind = cl ? class_kind(kc, mfma_min_q, big_q, small_on, tiny_q) : -1;
+      const uint64_t tsz = cl ? (uint64_t)kc * (kc - 1) / 2 : 0ull;
+      is_cls[i] = cl ? 1u : 0u;
+      tri_sz[i] = tsz;
+      if (cl) {
+        loc[ST_CAND_M + kind] += tsz;
+        loc[ST_COLS_M + kind] += kc + k;
+        loc[ST_CLS_M + kind] += 1;
+        // 128-wide tile pairs: also a bound on a big class's 256-wide half tasks;
+        // 16-wide block pairs: also a bound on a mid-size class's 32-wide ones
+        if (kind == 0 || kind == 3) loc[NC_PAIRS_M] += mfma_pairs(kc);
+        else if (kind == 1 || kind == 4) loc[NC_PAIRS_V] += andpop_pairs(kc);
+        else loc[NC_TINY] += 1;
+      }
     }
   }
   for (int j = 0; j < NC_COUNT; ++j)
@@ -221,15 +185,21 @@ __device__ inline void fill_level_body(const LevelPost& a, uint64_t t0, uint64_t
     const uint64_t rs = cd.tri_off + tri_index(li, li + 1, cd.q);
     const uint64_t len = cd.q - li - 1;
     const uint32_t minsup = a.dbs[cd.db].minsup;
-    for (uint64_t t = lane; t < len; t += 64) {
-      const uint32_t v = a.tri[rs + t];
-      if (v >= minsup) {
-        const uint64_t pos = a.S[rs + t];
+    // the node's children start at child_start[i], in row order
+    uint64_t base = a.child_start[i];
+    for (uint64_t t0 = 0; t0 < len; t0 += 64) {
+      const uint64_t t = t0 + lane;
+      const uint32_t v = t < len ? a.tri[rs + t] : 0u;
+      const bool f = t < len && v >= minsup;
+      const uint64_t m = __ballot(f);
+      if (f) {
+        const uint64_t pos = base + (uint64_t)__popcll(m & ((1ull << lane) - 1));
         a.nitem[pos] = a.child_item[cd.child0 + li + 1 + t];
         a.nparent[pos] = (uint32_t)i;
         a.nsupp[pos] = v;
         a.ndbv[pos] = cd.db;
       }
+      base += (uint64_t)__popcll(m);
     }
   }
 }
@@ -542,21 +512,16 @@ void launch_gather_idx(const uint64_t* arr, const uint64_t* idx, uint32_t k, uin
   BM_LAUNCH_CHECK();
 }
 
-void launch_tri_flags(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs, const uint32_t* tri,
-                      uint64_t T, uint32_t* flags, hipStream_t s) {
-  if (ncls == 0 || T == 0) return;
-  k_tri_flags<<<grid_for(T, kThreads), kThreads, 0, s>>>(cls, ncls, dbs, tri, T, flags);
-  BM_LAUNCH_CHECK();
-}
 
 void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const int32_t* pcls,
-                        const ClassDesc* cls, const uint64_t* S, uint32_t mfma_min_q, uint32_t big_q,
-                        uint32_t small_on, uint32_t tiny_q, uint32_t* cnt, uint32_t* is_cls,
-                        uint64_t* tri_sz, unsigned long long* st, hipStream_t s) {
+                        const ClassDesc* cls, const DbInfo* dbs, const uint32_t* tri,
+                        uint32_t mfma_min_q, uint32_t big_q, uint32_t small_on, uint32_t tiny_q,
+                        uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz, unsigned long long* st,
+                        hipStream_t s) {
   if (n == 0) return;
-  k_node_counts<<<grid_for(n, kThreads, 2048), kThreads, 0, s>>>(n, k, parent, pcls, cls, S,
-                                                                  mfma_min_q, big_q, small_on, tiny_q,
-                                                                  cnt, is_cls, tri_sz, st);
+  k_node_counts<<<grid_for(n, kThreads / 64, 4096), kThreads, 0, s>>>(
+      n, k, parent, pcls, cls, dbs, tri, mfma_min_q, big_q, small_on, tiny_q, cnt, is_cls, tri_sz,
+      st);
   BM_LAUNCH_CHECK();
 }
 

@@ -64,16 +64,16 @@ void launch_init_level1(DbInfo* dbs, uint32_t ndb, const uint64_t* f1_base, uint
 // out[i] = arr[idx[i]], i < k; also into out2 (e.g. mapped host memory) when not NULL.
 void launch_gather_idx(const uint64_t* arr, const uint64_t* idx, uint32_t k, uint64_t* out,
                        uint64_t* out2, hipStream_t s);
-void launch_tri_flags(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs, const uint32_t* tri,
-                      uint64_t T, uint32_t* flags, hipStream_t s);
-// Per node of level k: frequent children (cnt), whether it becomes a class
-// (is_cls) and its candidate triangle size (tri_sz); sums the step statistics
-// and the task-count bounds into st[0, NC_COUNT) (zeroed by the caller).
+// Per node of level k (a wave each): frequent children (cnt: the entries of
+// its row of its class's triangle tri that meet the class's threshold),
+// whether it becomes a class (is_cls) and its candidate triangle size
+// (tri_sz); sums the step statistics and the task-count bounds into
+// st[0, NC_COUNT) (zeroed by the caller).
 void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const int32_t* pcls,
-                        const ClassDesc* cls, const uint64_t* S, uint32_t mfma_min_q, uint32_t big_q,
-                        uint32_t small_on, uint32_t tiny_q, uint32_t* cnt, uint32_t* is_cls,
-                        uint64_t* tri_sz,
-                        unsigned long long* st, hipStream_t s);
+                        const ClassDesc* cls, const DbInfo* dbs, const uint32_t* tri,
+                        uint32_t mfma_min_q, uint32_t big_q, uint32_t small_on, uint32_t tiny_q,
+                        uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz, unsigned long long* st,
+                        hipStream_t s);
 // Arguments of the launch between two level steps (k_level_post): node i < n
 // of level k writes its frequent extensions into the next level and, if it
 // has at least two, its class of the next step and that class's task counts
@@ -87,7 +87,6 @@ struct LevelPost {
   const DbInfo* dbs;
   const uint32_t* child_item;
   const uint32_t* tri;
-  const uint64_t* S;
   uint32_t* nitem;
   uint32_t* nparent;
   uint32_t* nsupp;

@@ -741,14 +741,6 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       tu.subsets = tu.dfs;
       if (tu.subsets) tu.tiny_q = tu.subset_q;
     }
-    // one threshold for every live database lets the candidate threshold skip the class lookup
-    uint32_t uniform_thr = 0;
-    for (uint32_t d = 0; d < N; ++d) {
-      if (!hdb[d].m) continue;
-      if (uniform_thr == 0) uniform_thr = minsups[d];
-      else if (uniform_thr != minsups[d]) uniform_thr = 0xffffffffu;
-    }
-    if (uniform_thr == 0xffffffffu) uniform_thr = 0;
     // the database table and the item bases in one upload
     static_assert(sizeof(DbInfo) % 8 == 0, "DbInfo is a whole number of words");
     const size_t tab_words = std::max<uint32_t>(N, 1) * (sizeof(DbInfo) / 8);
@@ -818,6 +810,10 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       }
     }
     if (!roots.empty()) {
+      // per-step statistics counters of every level step, zeroed once
+      TBuf<unsigned long long> step_stats((size_t)(BM_MAX_LEVELS + 2) * NC_COUNT, s);
+      launch_fill_u64(reinterpret_cast<uint64_t*>(step_stats.get()), 0,
+                      (uint64_t)(BM_MAX_LEVELS + 2) * NC_COUNT, s);
       TBuf<int32_t> pcls_prev(hpcls.size(), s);
       upload(pcls_prev.get(), hpcls, s);
       auto w = std::make_unique<StepWork>();
@@ -835,32 +831,15 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         run_class_kernels(ddb_p, L[k].item.get(), *w, tu, nW, nN, tm, s);
 
         tm.begin(BM_K_LEVEL);
-        // S = exclusive scan of the frequent flags of this step's candidates;
-        // the step's statistics counters are zeroed on the way
-        TBuf<uint64_t> S(w->T + 1, s);
-        TBuf<unsigned long long> dst(NC_COUNT, s);
-        uint64_t* dst64 = reinterpret_cast<uint64_t*>(dst.get());
-        {
-          ScanMulti sm{};
-          sm.out[0] = S.get();
-          sm.zero = dst64;
-          sm.nzero = NC_COUNT;
-          TBuf<uint32_t> tfl;
-          if (uniform_thr) {
-            sm.in[0] = w->tri.get();
-            sm.ge[0] = uniform_thr;
-          } else {
-            tfl.alloc(w->T, s);
-            launch_tri_flags(w->cls.get(), w->ncls, ddb_p, w->tri.get(), w->T, tfl.get(), s);
-            sm.in[0] = tfl.get();
-          }
-          scan_arrays(sm, 1, w->T, s);
-        }
+        // each node counts the frequent entries of its triangle row (the
+        // step's statistics counters were zeroed at the start of the call)
+        unsigned long long* dst = step_stats.get() + (size_t)k * NC_COUNT;
+        uint64_t* dst64 = reinterpret_cast<uint64_t*>(dst);
         TBuf<uint32_t> cnt(nk, s), iscls(nk, s);
         TBuf<uint64_t> trisz(nk, s);
-        launch_node_counts(nk, k, L[k].parent.get(), pcls_prev.get(), w->cls.get(), S.get(),
-                           tu.mfma_min_q, tu.mfma_big_q, tu.mfma_small ? 1u : 0u, tu.tiny_q,
-                           cnt.get(), iscls.get(), trisz.get(), dst.get(), s);
+        launch_node_counts(nk, k, L[k].parent.get(), pcls_prev.get(), w->cls.get(), ddb_p,
+                           w->tri.get(), tu.mfma_min_q, tu.mfma_big_q, tu.mfma_small ? 1u : 0u,
+                           tu.tiny_q, cnt.get(), iscls.get(), trisz.get(), dst, s);
         L[k].cstart.alloc(nk + 1, s);
         TBuf<uint64_t> clspos(nk + 1, s), trioff(nk + 1, s);
         const void* ins[3] = {cnt.get(), iscls.get(), trisz.get()};
@@ -894,7 +873,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         lp.dbs = ddb_p;
         lp.child_item = L[k].item.get();
         lp.tri = w->tri.get();
-        lp.S = S.get();
+        lp.child_start = L[k].cstart.get();
         lp.nitem = Ln.item.get();
         lp.nparent = Ln.parent.get();
         lp.nsupp = Ln.supp.get();
@@ -916,7 +895,6 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         for (int j = 0; j < ST_COUNT; ++j) nw->st[j] = tot[3 + j];
         lp.k = k;
         lp.cnt = cnt.get();
-        lp.child_start = L[k].cstart.get();
         lp.cls_pos = clspos.get();
         lp.tri_off = trioff.get();
         lp.node_db = L[k].db.get();
