@@ -828,6 +828,9 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         step_pre[k] = w->pre.get();
         st.classes_mfma += w->st[ST_CLS_M] + w->st[ST_CLS_B] + w->st[ST_CLS_S];
         st.classes_andpop += w->st[ST_CLS_V] + w->st[ST_CLS_T];
+        // every class of this step is a deferred subtree: no level-synchronous
+        // level k + 1, so neither node counts nor a synchronisation are needed
+        if (ls_cand == 0) break;
         run_class_kernels(ddb_p, L[k].item.get(), *w, tu, nW, nN, tm, s);
 
         tm.begin(BM_K_LEVEL);
