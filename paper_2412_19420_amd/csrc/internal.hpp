@@ -250,9 +250,6 @@ struct ScanMulti {
   const void* in[8];
   uint32_t is64[8];
   uint64_t* out[8];
-  uint32_t ge[8];       // 32-bit input j scanned as (in[j][i] >= ge[j]) when ge[j] > 0
-  uint64_t* zero;       // nzero words zeroed before the scan (e.g. counters of a later kernel)
-  uint32_t nzero;
   uint64_t* tot;        // if set: tot[j] = total of array j, then tot[count + e] = extra[e]
   const uint64_t* extra;
   uint32_t nextra;
@@ -264,13 +261,10 @@ struct GatherU64 {
 };
 void launch_gather_u64(const GatherU64& g, int count, uint64_t* dst, hipStream_t s);
 bool scan_multi_single(const ScanMulti& sm, int count, uint64_t n, hipStream_t s);
-// The same (zero, ge, tot and extra included) for long arrays in three launches;
+// The same (tot and extra included) for long arrays in three launches;
 // tmp holds scan_tiles_tmp_words(count, n) words.  False if n is 0 or too long.
 size_t scan_tiles_tmp_words(int count, uint64_t n);
 bool scan_multi_tiles(const ScanMulti& sm, int count, uint64_t n, uint64_t* tmp, hipStream_t s);
-// out[0..n]: exclusive scan of (in[i] >= thr)
-void scan_ge_u32(const uint32_t* in, uint32_t thr, uint64_t* out, uint64_t n, uint64_t* tmp,
-                 hipStream_t s);
 
 // class kernels
 // fp4: the scaled e2m1 MFMA form (64 transactions per instruction, exact FP32

@@ -330,11 +330,6 @@ struct InU32 {
   const uint32_t* p;
   __device__ uint64_t operator()(uint64_t i) const { return p[i]; }
 };
-struct InGe {
-  const uint32_t* p;
-  uint32_t thr;
-  __device__ uint64_t operator()(uint64_t i) const { return p[i] >= thr ? 1u : 0u; }
-};
 
 __device__ inline uint64_t block_exclusive_scan(uint64_t v, uint64_t* s_wave, uint64_t* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -430,14 +425,10 @@ __global__ __launch_bounds__(kSingleThreads) void k_scan_single(ScanMulti sm, ui
   const int a = blockIdx.x;
   const void* in = sm.in[a];
   const bool is64 = sm.is64[a] != 0;
-  const uint32_t ge = sm.ge[a];
   uint64_t* out = sm.out[a];
-  if (a == 0) {
-    for (uint32_t j = threadIdx.x; j < sm.nzero; j += kSingleThreads) sm.zero[j] = 0;
-    if (sm.tot)
-      for (uint32_t j = threadIdx.x; j < sm.nextra; j += kSingleThreads)
-        sm.tot[gridDim.x + j] = sm.extra[j];
-  }
+  if (a == 0 && sm.tot)
+    for (uint32_t j = threadIdx.x; j < sm.nextra; j += kSingleThreads)
+      sm.tot[gridDim.x + j] = sm.extra[j];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint64_t base = 0;
   for (uint64_t c0 = 0; c0 < n; c0 += kSingleChunk) {
@@ -449,12 +440,7 @@ __global__ __launch_bounds__(kSingleThreads) void k_scan_single(ScanMulti sm, ui
       const uint64_t i = i0 + k;
       uint64_t x = 0;
       if (i < n) {
-        if (is64) {
-          x = static_cast<const uint64_t*>(in)[i];
-        } else {
-          const uint32_t y = static_cast<const uint32_t*>(in)[i];
-          x = ge ? (y >= ge ? 1u : 0u) : y;
-        }
+        x = is64 ? static_cast<const uint64_t*>(in)[i] : static_cast<const uint32_t*>(in)[i];
       }
       v[k] = x;
       t += v[k];
@@ -486,12 +472,10 @@ __global__ __launch_bounds__(kSingleThreads) void k_scan_single(ScanMulti sm, ui
   }
 }
 
-// Element i of array a of a ScanMulti: 64-bit, 32-bit, or a 32-bit threshold flag.
+// Element i of array a of a ScanMulti: 64-bit or 32-bit.
 __device__ __forceinline__ uint64_t scan_elem(const ScanMulti& sm, int a, uint64_t i) {
   if (sm.is64[a]) return static_cast<const uint64_t*>(sm.in[a])[i];
-  const uint32_t y = static_cast<const uint32_t*>(sm.in[a])[i];
-  const uint32_t ge = sm.ge[a];
-  return ge ? (y >= ge ? 1u : 0u) : y;
+  return static_cast<const uint32_t*>(sm.in[a])[i];
 }
 
 // Three-launch scan of up to 8 arrays of any length (grid.y = array): tiles of
@@ -506,8 +490,6 @@ __global__ __launch_bounds__(kThreads) void k_scan_tiles(ScanMulti sm, uint64_t 
   __shared__ uint64_t s_wave[kThreads / 64];
   const int a = blockIdx.y;
   const uint32_t b = blockIdx.x;
-  if (a == 0 && b == 0)
-    for (uint32_t j = threadIdx.x; j < sm.nzero; j += kThreads) sm.zero[j] = 0;
   const uint64_t i0 = (uint64_t)b * kTileScan + (uint64_t)threadIdx.x * kTilePer;
   uint64_t* out = sm.out[a];
   // a thread's 8 elements are contiguous: 16-byte accesses when the arrays
@@ -527,13 +509,13 @@ __global__ __launch_bounds__(kThreads) void k_scan_tiles(ScanMulti sm, uint64_t 
       }
     } else {
       const uint4* q = reinterpret_cast<const uint4*>(static_cast<const uint32_t*>(sm.in[a]) + i0);
-      const uint32_t ge = sm.ge[a];
 #pragma unroll
       for (int k = 0; k < kTilePer / 4; ++k) {
         const uint4 x = q[k];
-        const uint32_t y[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) v[4 * k + e] = ge ? (y[e] >= ge ? 1u : 0u) : y[e];
+        v[4 * k] = x.x;
+        v[4 * k + 1] = x.y;
+        v[4 * k + 2] = x.z;
+        v[4 * k + 3] = x.w;
       }
     }
   } else {
@@ -638,10 +620,6 @@ void scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipS
 }
 void scan_u32_to_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, hipStream_t s) {
   scan_impl(InU32{in}, out, n, tmp, s);
-}
-void scan_ge_u32(const uint32_t* in, uint32_t thr, uint64_t* out, uint64_t n, uint64_t* tmp,
-                 hipStream_t s) {
-  scan_impl(InGe{in, thr}, out, n, tmp, s);
 }
 
 void launch_validate(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t nnz, uint32_t m,

@@ -158,7 +158,7 @@ void upload(T* dst, const std::vector<T>& src, hipStream_t s) {
 constexpr uint64_t kOneLaunchScan = 16384;
 
 // Exclusive scans of sm's count arrays of length n (out[j][n] = total), with
-// sm's zeroing, threshold and totals options.
+// sm's totals option.
 void scan_arrays(const ScanMulti& sm, int count, uint64_t n, hipStream_t s) {
   if (n <= kOneLaunchScan && scan_multi_single(sm, count, n, s)) return;
   {
@@ -166,12 +166,9 @@ void scan_arrays(const ScanMulti& sm, int count, uint64_t n, hipStream_t s) {
     if (scan_multi_tiles(sm, count, n, tmp.get(), s)) return;
   }
   // more than 2^18 tiles: one recursive block scan per array
-  if (sm.nzero) launch_fill_u64(sm.zero, 0, sm.nzero, s);
   TBuf<uint64_t> tmp(scan_tmp_words(n), s);
   for (int j = 0; j < count; ++j) {
     if (sm.is64[j]) scan_u64(static_cast<const uint64_t*>(sm.in[j]), sm.out[j], n, tmp.get(), s);
-    else if (sm.ge[j])
-      scan_ge_u32(static_cast<const uint32_t*>(sm.in[j]), sm.ge[j], sm.out[j], n, tmp.get(), s);
     else scan_u32_to_u64(static_cast<const uint32_t*>(sm.in[j]), sm.out[j], n, tmp.get(), s);
   }
   if (sm.tot) {
