@@ -87,3 +87,31 @@ def test_binding_marshalling_checks():
     assert keep.dtype == np.uint32 and p.value == keep.ctypes.data
     assert _bm._nelem(t) == 10 and _bm._nelem(a) == 5
     assert _bm._ptr(None, np.uint32)[0].value is None
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of bm_options and bm_stats have the header's size and
+    field offsets (a C program built with gcc against include/bm.h prints them)."""
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    from paper_2412_19420_amd import _bm
+    ns = {"BmOptions": _bm.BmOptions, "BmStats": _bm.BmStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bm.h"', 'int main(void) {']
+    checks = []
+    for cname, pyname in (("bm_options", "BmOptions"), ("bm_stats", "BmStats")):
+        cls = ns[pyname]
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        checks.append((f"{cname} size", ctypes.sizeof(cls)))
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+            checks.append((f"{cname} {field}", getattr(cls, field).offset))
+    lines += ["  return 0;", "}"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {" ".join(l.split()[:-1]): int(l.split()[-1]) for l in out.splitlines()}
+    for key, want in checks:
+        assert got[key] == want, (key, got[key], want)
