@@ -237,7 +237,9 @@ TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_v, uint64_t c
     ns = std::min<uint64_t>(ns, std::max<uint64_t>(1, W / min_len));
     return round_up(ceil_div(W, ns), align);
   };
-  g.split_m = (uint32_t)pick(pairs_m, 256, GRAM_KW);
+  // at least 1,024 words: each task ends in 16K atomic adds of its tile, so
+  // short ones (the T40-style level 4 got 489 words) pay for them twice over
+  g.split_m = (uint32_t)pick(pairs_m, 1024, GRAM_KW);
   g.split_v = (uint32_t)pick(pairs_v, 512, 1);
   g.split_t = (uint32_t)pick(classes_t, 2048, 64);  // tiny-class loads read 4-word groups
   // a 128 x 256 task holds about two 128-wide tiles: split its words further
