@@ -196,7 +196,7 @@ def run_batched(args, bm, torch, dev):
 
     timing = 0 if args.no_timing else bm.FLAG_TIMING | bm.FLAG_TIMING_MAIN
     o_ls = bm.options(timing | bm.FLAG_LEVELSYNC)
-    o_dfs = bm.options(timing)
+    o_dfs = bm.options(timing | bm.FLAG_DEPTH_FIRST)
     # mode: (build, mine); the plain miner builds and mines one database per call
     modes = {
         "plain_per_db": (build_each, lambda hs: [bm.bm_mine_ex(h, m, o_ls, stream=stream)
@@ -458,7 +458,7 @@ def main():
                    "candidates": cands, "frequent_items": st["n_frequent_items"],
                    "mine_ms": round(sum(s["wall_ms"] for s in stats) / len(stats), 3),
                    "dfs_tasks": st["dfs_tasks"], "host_syncs": st["host_syncs"],
-                   "mode": ("levelsync" if args.levelsync else "subtrees") +
+                   "mode": ("levelsync" if args.levelsync or not st["dfs_tasks"] else "subtrees") +
                            ("+learned" if model is not None else "") +
                            (f"+shuffle{args.shuffle}" if args.shuffle else ""),
                    "kernels": kernels},

@@ -107,7 +107,8 @@ typedef struct {
 #define BM_FLAG_GRAPH 8u       /* bm_model_train_ex: replay each training epoch as a hipGraph */
 #define BM_FLAG_TRACE 16u      /* keep per-class features and subtree costs (bm_result_trace) */
 #define BM_FLAG_SHUFFLE 32u    /* random subtree-task order (order-invariance tests) */
-#define BM_FLAG_LEVELSYNC 64u  /* evaluate small classes level by level too (no depth-first kernel) */
+#define BM_FLAG_LEVELSYNC 64u  /* evaluate small classes level by level too (no depth-first kernel
+                                * and no subset counting) */
 #define BM_FLAG_FP4_MFMA 128u  /* Gram kernels on the FP4 (e2m1) MFMA form (the default): bits
                                 * as 0 / 0.5, FP32 sums, exact for counts < 2^24 per task (word
                                 * splits are capped to guarantee it) */
@@ -116,6 +117,11 @@ typedef struct {
 #define BM_FLAG_TIMING_MAIN 1024u   /* with BM_FLAG_TIMING: events only around the support-counting
                                      * kernels (Gram, AND+popcount, depth-first), not around the
                                      * level bookkeeping, output and scheduling launches */
+#define BM_FLAG_DEPTH_FIRST 2048u   /* databases with short columns (<= dfs_max_words words): mine
+                                     * small subtrees with the depth-first kernel from a work queue.
+                                     * Off by default (level by level measured faster there); also
+                                     * on when bm_mine_batch gets a cost model to order that queue,
+                                     * or with BM_FLAG_TRACE (whose rows are its tasks) */
 
 typedef struct {
   uint32_t flags;
@@ -125,8 +131,10 @@ typedef struct {
   uint32_t split_words;       /* word-range length of one task (multiple of 64; 0 = automatic) */
   uint32_t shuffle_seed;      /* with BM_FLAG_SHUFFLE */
   uint32_t dfs_threads;       /* threads per workgroup of the depth-first kernel: 256, 512 or 1024 */
-  uint32_t dfs_max_words;     /* depth-first phase only when every database has at most this many
-                               * 64-bit words per column (0 = default; 0xffffffff = always) */
+  uint32_t dfs_max_words;     /* columns of at most this many 64-bit words are short: the
+                               * depth-first phase may run (see BM_FLAG_DEPTH_FIRST); longer ones
+                               * take subset counting (0 = default 4,096; 0xffffffff = always
+                               * short) */
   uint32_t mfma_big_children; /* MFMA classes with at least this many children use 256-wide
                                * tiles (0 = default: never) */
   uint32_t dfs_wave_max_words;/* subtree tasks of databases with at most this many words per

@@ -20,7 +20,8 @@ import os
 import numpy as np
 
 from . import _bm
-from ._bm import (BM_K_NAMES, FLAG_ALL_MFMA, FLAG_DFS_BLOCK_ONLY, FLAG_FP4_MFMA, FLAG_GRAPH,
+from ._bm import (BM_K_NAMES, FLAG_ALL_MFMA, FLAG_DEPTH_FIRST, FLAG_DFS_BLOCK_ONLY, FLAG_FP4_MFMA,
+                  FLAG_GRAPH,
                   FLAG_INT8_MFMA,
                   FLAG_LEVELSYNC, FLAG_NO_MFMA,
                   FLAG_SHUFFLE, FLAG_TIMING, FLAG_TIMING_MAIN, FLAG_TRACE, MLP_PARAMS, BmError, BmOptions)
@@ -30,7 +31,7 @@ __all__ = [
     "bm_mine_ex", "bm_mine_batch", "bm_set_allocator", "bm_release_cached_memory", "Db", "Result", "BmError",
     "options", "FLAG_TIMING", "FLAG_NO_MFMA", "FLAG_ALL_MFMA", "FLAG_GRAPH", "FLAG_TRACE",
     "FLAG_SHUFFLE", "FLAG_LEVELSYNC", "FLAG_FP4_MFMA", "FLAG_INT8_MFMA", "FLAG_DFS_BLOCK_ONLY",
-    "FLAG_TIMING_MAIN",
+    "FLAG_TIMING_MAIN", "FLAG_DEPTH_FIRST",
     "LIB_PATH", "Model", "MLP_PARAMS", "bm_autotune",
     "autotune_cached", "options_to_dict", "options_from_dict", "shape_key",
 ]

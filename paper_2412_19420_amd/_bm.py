@@ -45,6 +45,7 @@ FLAG_FP4_MFMA = 128
 FLAG_INT8_MFMA = 256
 FLAG_DFS_BLOCK_ONLY = 512
 FLAG_TIMING_MAIN = 1024
+FLAG_DEPTH_FIRST = 2048
 MLP_PARAMS = 4801
 
 STATUS = {0: "BM_OK", 1: "BM_ERR_INVALID_ARG", 2: "BM_ERR_CSR", 3: "BM_ERR_OOM",

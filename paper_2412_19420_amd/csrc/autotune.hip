@@ -58,17 +58,17 @@ bm_options autotune(const bm_db* const* dbs, const uint32_t* minsups, uint32_t c
       }
     }
   };
-  // depth-first phase: off, default cut-off, always
+  // small subtrees: level by level throughout (0), the defaults (1), the
+  // depth-first kernel on short columns (2) or on every column (3)
   try_field(
       [](bm_options& o, uint32_t v) {
-        if (v == 0) {
-          o.flags |= BM_FLAG_LEVELSYNC;
-        } else {
-          o.flags &= ~BM_FLAG_LEVELSYNC;
-          o.dfs_max_words = v;
-        }
+        o.flags &= ~(BM_FLAG_LEVELSYNC | BM_FLAG_DEPTH_FIRST);
+        o.dfs_max_words = 0;
+        if (v == 0) o.flags |= BM_FLAG_LEVELSYNC;
+        if (v >= 2) o.flags |= BM_FLAG_DEPTH_FIRST;
+        if (v == 3) o.dfs_max_words = 0xffffffffu;
       },
-      {0u, 4096u, 0xffffffffu});
+      {0u, 1u, 2u, 3u});
   try_field([](bm_options& o, uint32_t v) { o.mfma_min_children = v; }, {24u, 32u, 48u, 64u, 96u, 128u});
   try_field([](bm_options& o, uint32_t v) { o.mfma_big_children = v; }, {192u, 256u, 512u, 0xffffffffu});
   try_field([](bm_options& o, uint32_t v) { o.split_words = v; }, {0u, 512u, 1024u, 2048u, 4096u});

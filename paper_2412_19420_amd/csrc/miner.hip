@@ -733,12 +733,18 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       }
     }
     const double nW = N ? sumW / N : 0, nN = N ? sumN / N : 0;  // per-database means for work counts
-    // one workgroup walks a whole subtree, so long columns take the subset-counting
-    // subtrees instead (word ranges spread over the chip), or the level-synchronous path
+    // Long columns: small subtrees by subset counting (one workgroup would walk
+    // a whole subtree, so the depth-first kernel is slow there).  Short
+    // columns: level by level, where the subtree phase's fixed costs (merge,
+    // read-back) measured more than it saves, unless the depth-first phase is
+    // asked for -- by the flag, a cost model to order its queue, or a trace
+    // of its tasks.
     if (tu.dfs && Wmax > tu.dfs_max_words) {
       tu.dfs = tu.subset_q >= 2;
       tu.subsets = tu.dfs;
       if (tu.subsets) tu.tiny_q = tu.subset_q;
+    } else if (tu.dfs) {
+      tu.dfs = sched != nullptr || (flags & (BM_FLAG_DEPTH_FIRST | BM_FLAG_TRACE)) != 0;
     }
     // the database table and the item bases in one upload
     static_assert(sizeof(DbInfo) % 8 == 0, "DbInfo is a whole number of words");

@@ -58,7 +58,7 @@ def test_depth_first_equals_level_sync_and_oracle(bm, name, db, minsup):
     minsup = db.minsup if minsup is None else minsup
     print(f"dfs vs levelsync {name} n={db.n} m={db.m} minsup={minsup}", flush=True)
     h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
-    r_dfs = bm.bm_mine(h, minsup)
+    r_dfs = bm.bm_mine_ex(h, minsup, bm.options(bm.FLAG_DEPTH_FIRST))
     r_ls = bm.bm_mine_ex(h, minsup, bm.options(bm.FLAG_LEVELSYNC))
     want = _oracle(db, minsup)
     assert _arrays_equal(r_dfs.arrays(), want)
@@ -105,12 +105,20 @@ def test_subset_counting_batch_trace_and_bad_option(bm):
         bm.bm_mine_ex(hs[0], ms[0], bm.options(subset_max_children=9))
 
 
+def test_short_columns_default_to_level_sync(bm):
+    # short columns: level by level unless the depth-first phase is asked for
+    db = gen.make_config(2)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    assert bm.bm_mine(h, db.minsup).stats()["dfs_tasks"] == 0
+    assert bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_DEPTH_FIRST)).stats()["dfs_tasks"] > 0
+
+
 @pytest.mark.parametrize("mmc", [2, 9, 16, 64])
 def test_depth_first_under_class_routings(bm, mmc):
     db = gen.make_config(2)
     print(f"dfs routing mfma_min_children={mmc}", flush=True)
     h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
-    r = bm.bm_mine_ex(h, db.minsup, bm.options(mfma_min_children=mmc))
+    r = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_DEPTH_FIRST, mfma_min_children=mmc))
     assert _arrays_equal(r.arrays(), _oracle(db, db.minsup))
 
 
@@ -118,9 +126,10 @@ def test_queue_order_does_not_change_result(bm):
     db = gen.make_config(3, scale=0.02)
     print("shuffled queues", flush=True)
     h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
-    base = bm.bm_mine(h, db.minsup).arrays()
+    base = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_DEPTH_FIRST)).arrays()
     for seed in (1, 2, 3):
-        r = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_SHUFFLE, shuffle_seed=seed))
+        r = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_SHUFFLE | bm.FLAG_DEPTH_FIRST,
+                                                   shuffle_seed=seed))
         assert _arrays_equal(r.arrays(), base), seed
 
 
@@ -275,7 +284,8 @@ def test_depth_first_block_sizes(bm, threads, wave):
     base = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_LEVELSYNC)).arrays()
     flags = bm.FLAG_DFS_BLOCK_ONLY if wave == "block" else 0
     ww = 0xFFFFFFFF if wave == "wave" else 0
-    r = bm.bm_mine_ex(h, db.minsup, bm.options(flags, dfs_threads=threads, dfs_wave_max_words=ww))
+    r = bm.bm_mine_ex(h, db.minsup, bm.options(flags | bm.FLAG_DEPTH_FIRST, dfs_threads=threads,
+                                               dfs_wave_max_words=ww))
     assert r.stats()["dfs_tasks"] > 0
     assert _arrays_equal(r.arrays(), base)
 
@@ -291,8 +301,9 @@ def test_depth_first_wave_kernel_on_batch_with_split(bm):
     model = bm.Model(seed=4)
     f, y = bm.bm_mine_batch(hs, ms, opts=bm.options(bm.FLAG_TRACE))[0].trace()
     model.train(f, y, epochs=5, lr=3e-3)
-    for o, mdl in ((bm.options(dfs_wave_max_words=128), None),
-                   (bm.options(bm.FLAG_SHUFFLE, shuffle_seed=3, dfs_wave_max_words=128), None),
+    for o, mdl in ((bm.options(bm.FLAG_DEPTH_FIRST, dfs_wave_max_words=128), None),
+                   (bm.options(bm.FLAG_SHUFFLE | bm.FLAG_DEPTH_FIRST, shuffle_seed=3,
+                               dfs_wave_max_words=128), None),
                    (bm.options(dfs_wave_max_words=128), model)):
         got = bm.bm_mine_batch(hs, ms, model=mdl, opts=o)
         assert got[0].stats()["dfs_tasks"] > 0
@@ -319,10 +330,11 @@ def test_depth_first_forced_on_full_size(bm, k):
     off = bm.bm_mine_ex(h, db.minsup, bm.options(subset_max_children=1))
     assert off.stats()["dfs_tasks"] == 0
     assert _arrays_equal(off.arrays(), base.arrays())
-    r = bm.bm_mine_ex(h, db.minsup, bm.options(dfs_threads=1024, dfs_max_words=0xFFFFFFFF))
+    r = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_DEPTH_FIRST, dfs_threads=1024,
+                                               dfs_max_words=0xFFFFFFFF))
     assert r.stats()["dfs_tasks"] > 0
     assert _arrays_equal(r.arrays(), base.arrays())
-    r = bm.bm_mine_ex(h, db.minsup, bm.options(dfs_max_words=0xFFFFFFFF,
+    r = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_DEPTH_FIRST, dfs_max_words=0xFFFFFFFF,
                                                dfs_wave_max_words=0xFFFFFFFF))
     assert _arrays_equal(r.arrays(), base.arrays())
 
