@@ -228,9 +228,10 @@ bm_status bm_mine_batch(const bm_db* const* dbs, const uint32_t* minsups, uint32
 
 /* Autotuner (batching design, word tiles and block shapes): times real calls of
  * bm_mine_batch on these databases over a coordinate search of the tuning
- * fields of bm_options -- depth-first phase off / default cut-off / always,
- * mfma_min_children, mfma_big_children, split_words, andpop_chunk_words,
- * dfs_threads -- and writes
+ * fields of bm_options -- small subtrees level by level / defaults /
+ * depth-first on short columns / depth-first everywhere, mfma_min_children,
+ * mfma_big_children, split_words, andpop_chunk_words, subset_max_children,
+ * dfs_threads, dfs_wave_max_words -- and writes
  * the fastest combination to *best (base's other flags kept; NULL base =
  * defaults).  Each point is the minimum of `reps` calls (0 = 3); *best_ms
  * (optional) receives its wall time.  No tuning field changes the mined

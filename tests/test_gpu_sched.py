@@ -1,6 +1,6 @@
 """GPU tests of the depth-first subtree phase and the learned scheduler.
 
-* The depth-first path (default) must give the same canonical result, byte for
+* The depth-first path (BM_FLAG_DEPTH_FIRST) must give the same canonical result, byte for
   byte, as the purely level-synchronous path and as the oracle, whatever order
   the subtree tasks are taken in (shuffled queues, learned order).
 * The cost model's forward pass, backward pass and Adam step on the device
@@ -313,7 +313,7 @@ def test_depth_first_wave_kernel_on_batch_with_split(bm):
 
 @pytest.mark.parametrize("k", [3, 5])
 def test_depth_first_forced_on_full_size(bm, k):
-    # full-size columns (15,625 words) exceed the default depth-first cut-off:
+    # full-size columns (15,625 words) exceed the default short-column cut-off:
     # by default small subtrees are mined by subset counting; that and the
     # forced depth-first phase must both give the level-synchronous result,
     # with the same candidate and frequent counts per length
