@@ -197,8 +197,10 @@ bm_status bm_item_support(const bm_db* db, uint32_t* out, void* stream);
  * n_items, repeats allowed; NULL means all n_items items in id order, k must then
  * equal n_items).  out: host or device uint32[k*k], row-major and symmetric,
  * out[a*k+b] = S({items[a], items[b]}), diagonal = single-item supports.
- * Computed as the Gram matrix A^T A of the selected columns on int8 MFMA with
- * int32 accumulation (exact).  k == 0 is a no-op. */
+ * Computed as the Gram matrix A^T A of the selected columns with the mining
+ * path's class kernels: MFMA in the FP4 (e2m1) form with FP32 sums, exact
+ * because every task's counts stay below 2^24 (small k: AND+popcount).  k == 0
+ * is a no-op. */
 bm_status bm_pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* out,
                           void* stream);
 

@@ -4,7 +4,7 @@ Python binding of libbm.so with the names of its C ABI (include/bm.h):
 
     db  = bm_build(row_ptr, col_idx, n_tx, n_items)      # Eq. 1: column bitsets on the GPU
     sup = bm_item_support(db)                             # Eq. 3: single-item supports
-    C   = bm_pair_support(db, items)                      # Eq. 2: pair supports (int8 MFMA Gram)
+    C   = bm_pair_support(db, items)                      # Eq. 2: pair supports (MFMA Gram)
     res = bm_mine(db, minsup)                             # all frequent itemsets, canonical order
     offsets, items, supports = res.arrays()
 

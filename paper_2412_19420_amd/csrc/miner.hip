@@ -6,13 +6,18 @@
 // paper's recursive mining by sequential column ANDs), for one database or a
 // whole batch at once:
 //   level 1: frequent single items (column popcounts >= minsup);
-//   level 2: all pairs of frequent items -- the Gram matrix A^T A on int8 MFMA
-//            (or AND+popcount when there are few items);
+//   level 2: all pairs of frequent items -- the Gram matrix A^T A on MFMA
+//            (FP4 form by default, int8 on request; AND+popcount when there
+//            are few items);
 //   level k+1: every prefix class of level k (nodes sharing a parent) evaluates
 //            its q(q-1)/2 sibling pairs, big classes as a masked Gram matrix on
-//            MFMA, small ones with AND+popcount;
-// and finally writes the frequent itemsets in canonical order.  One host sync
-// per level reads back the next level's sizes -- for the whole batch.
+//            128- or 256-wide MFMA tiles, mid-size ones on 32-wide MFMA tiles,
+//            small ones with AND+popcount;
+// small classes can instead be finished whole: by subset counting when columns
+// are long, or by the depth-first kernel from a work queue when asked for; the
+// output of those subtrees is merged into the canonical order with the rest.
+// One host sync per level reads back the next level's sizes -- for the whole
+// batch.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
