@@ -113,9 +113,9 @@ DTYPE = {"fp4": "u64 bitsets; fp4 (e2m1) MFMA, fp32 accumulate (exact: counts < 
 # (workload, kernel, form) -> (source file, its sha256, bytes per launch).
 TRAFFIC = {
     # dense_planted 1M x 4,096 (profiles/dense_planted_1M_hbm_traffic.md)
-    (3, "gram_mfma", "fp4"): ("k_gram_mfma.hip", "21074a5da110ee20db3c6c781868b7272afaa501a05745e03e163ca8fe03876e", 3275.8e6),
-    (3, "gram_small", "fp4"): ("k_gram_small.hip", "f5838556e51a593149d221a8305e3fde2e735c73c0970d0a561de7f91139de72", 226.8e6),
-    (3, "dfs", "fp4"): ("k_subsets.hip", "2109e75ca138125ad95a1d2f12b68e6102d64a5d0421e9effe55855d65b95f7e", 771.4e6),
+    (3, "gram_mfma", "fp4"): ("k_gram_mfma.hip", "21074a5da110ee20db3c6c781868b7272afaa501a05745e03e163ca8fe03876e", 3267.4e6),
+    (3, "gram_small", "fp4"): ("k_gram_small.hip", "f5838556e51a593149d221a8305e3fde2e735c73c0970d0a561de7f91139de72", 226.9e6),
+    (3, "dfs", "fp4"): ("k_subsets.hip", "2109e75ca138125ad95a1d2f12b68e6102d64a5d0421e9effe55855d65b95f7e", 769.8e6),
 }
 WORKLOAD = None
 
