@@ -2,16 +2,25 @@
 
 One step = the whole hot path on one synthetic database already resident in
 HBM: matrix construction from the CSR transaction list (bm_build), single-item
-supports, pair supports (A^T A on int8 MFMA), the recursive extension of
-frequent prefixes (masked Gram on MFMA for large prefix classes, AND+popcount
-for small ones), and the canonical-order result (bm_mine).  Prints one JSON line.
+supports, pair supports (A^T A on MFMA: scaled FP4 (e2m1) operands with exact
+FP32 sums by default, int8 on request), the recursive extension of frequent
+prefixes (masked Gram on MFMA for large prefix classes, subset counting or
+AND+popcount for small ones), and the canonical-order result (bm_mine).
+Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--workload 3]
 
 value = candidate supports counted per second of step wall time (pairs of
-frequent items plus every longer candidate), with the step's wall time in
-ms_per_step.  `roofline` describes the kernel with the largest total time,
-measured with hipEvents recorded by the library on the call's stream.
+frequent items plus every longer candidate; the two parts are reported
+separately in config), with the step's wall time in ms_per_step.  `roofline`
+describes the kernel with the largest total time, measured with hipEvents
+recorded by the library on the call's stream.  After the timed steps, more
+steps write a 2 GiB scratch buffer between build and mine so that the mine
+call starts with L2 and the Infinity Cache holding none of the matrix; their
+kernel rates are reported as `cache_cold`.  By default the batched workload
+(256 databases: plain per-database, batched, batched + learned order) and
+the T40-style workload (plain and learned subtree order) are also run and
+reported under `secondary`.
 """
 from __future__ import annotations
 
@@ -55,23 +64,50 @@ WORKLOADS = {
 }
 
 
-def cpu_baseline(db, target_s: float = 12.0) -> dict:
+def _host_cpu():
+    """Host cores available to this process and the CPU model (from /proc/cpuinfo)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return avail, os.cpu_count() or avail, model
+
+
+def cpu_baseline(db, target_s: float = 12.0, single_s: float = 4.0) -> dict:
     """The C++ oracle as it stands, on a bounded sample of the same workload:
     the subtrees of the first k frequent items (all itemsets whose smallest
     item is one of them), k grown until one run takes about `target_s`
-    (at least 10 s of CPU work unless the whole workload finishes sooner)."""
+    (at least 10 s of CPU work unless the whole workload finishes sooner),
+    on every available host core up to 16; then a smaller sample on one
+    thread (about `single_s`)."""
     from oracle import cpp as ocpp
-    threads = max(1, min(16, os.cpu_count() or 1))
+    avail, online, model = _host_cpu()
+    threads = max(1, min(16, avail))
     o = ocpp.OracleDb(db.row_ptr, db.col_idx, db.n, db.m)
     m1 = len(o.frequent_items(db.minsup))
-    k = max(1, min(m1, threads))
-    dt, cands, sets_ = o.time_sample(db.minsup, 0, k, threads)
-    for _ in range(8):
-        if dt >= 10.0 or k >= m1:
-            break
-        # subtree costs fall with the item index, so extrapolate generously
-        k = min(m1, max(k + 1, int(k * target_s / max(dt, 1e-3))))
-        dt, cands, sets_ = o.time_sample(db.minsup, 0, k, threads)
+
+    def grow(nthreads, goal, floor):
+        k = max(1, min(m1, nthreads))
+        dt, cands, sets_ = o.time_sample(db.minsup, 0, k, nthreads)
+        for _ in range(8):
+            if dt >= floor or k >= m1:
+                break
+            # subtree costs fall with the item index, so extrapolate generously
+            k = min(m1, max(k + 1, int(k * goal / max(dt, 1e-3))))
+            dt, cands, sets_ = o.time_sample(db.minsup, 0, k, nthreads)
+        return k, dt, cands, sets_
+
+    k, dt, cands, sets_ = grow(threads, target_s, 10.0)
+    k1, dt1, cands1, _ = grow(1, single_s, 3.0)
     return {
         "value": cands / dt if dt > 0 else None,
         "unit": "candidate supports/s",
@@ -80,6 +116,10 @@ def cpu_baseline(db, target_s: float = 12.0) -> dict:
         "sample": f"C++ sorted-tid-vector oracle, {threads} threads, subtrees of the first {k} of "
                   f"{m1} frequent items: {cands} candidate supports, {sets_} frequent sets in {dt:.2f} s",
         "seconds": round(dt, 3),
+        "host": {"cpu_model": model, "cores_available": avail, "cores_online": online},
+        "single_thread": {"value": cands1 / dt1 if dt1 > 0 else None, "seconds": round(dt1, 3),
+                          "sample": f"1 thread, subtrees of the first {k1} frequent items: "
+                                    f"{cands1} candidate supports"},
     }
 
 
@@ -157,7 +197,7 @@ def _makespan(costs, order, workers):
     return float(max(heap))
 
 
-def run_batched(args, bm, torch, dev):
+def run_batched(args, bm, torch, dev, steps=None, warmup=None):
     """The batched workload: 256 databases per step, mined four ways on the same
     device-resident inputs -- one plain level-synchronous call per database
     (the plain GPU miner), one batched level-synchronous call, one batched call
@@ -165,6 +205,8 @@ def run_batched(args, bm, torch, dev):
     subtree queue is ordered by the cost model.  The model is trained first, on
     the GPU, on traces of 64 held-out databases of the same distribution."""
     import gen
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     t0 = time.time()
     dbs = gen.make_config(4)
     held = [gen.batch_db(k) for k in range(256, 320)]
@@ -235,14 +277,14 @@ def run_batched(args, bm, torch, dev):
 
     res = {}
     for name, (build, fn) in modes.items():
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             fn(build(dbs, dev_in))
         torch.cuda.synchronize()
         stats = []
         t_start = time.perf_counter()
         build_s = 0.0
         kept = []
-        for i in range(args.steps):
+        for i in range(steps):
             tb = time.perf_counter()
             hs = build(dbs, dev_in)
             torch.cuda.synchronize()
@@ -260,21 +302,21 @@ def run_batched(args, bm, torch, dev):
             else:
                 cand = rs[0].stats()["candidates_total"]
         del kept
-        res[name] = {"ms_per_step": round(1e3 * total / args.steps, 3),
-                     "build_ms": round(1e3 * build_s / args.steps, 3),
-                     "mine_ms": round(1e3 * (total - build_s) / args.steps, 3),
+        res[name] = {"ms_per_step": round(1e3 * total / steps, 3),
+                     "build_ms": round(1e3 * build_s / steps, 3),
+                     "mine_ms": round(1e3 * (total - build_s) / steps, 3),
                      "candidates": cand, "stats": stats}
         print(f"# {name}: {res[name]['ms_per_step']} ms/step (mine {res[name]['mine_ms']} ms)",
               file=sys.stderr, flush=True)
 
     best = res["batched_learned"]
-    kernels, kms = (_kernel_table(best["stats"], args.steps) if not args.no_timing else ({}, {}))
+    kernels, kms = (_kernel_table(best["stats"], steps) if not args.no_timing else ({}, {}))
     st = best["stats"][-1]
     out = {
         "metric": "candidate supports counted/s + mine wall time at minsup; % of HBM peak",
         "value": round(best["candidates"] / (best["ms_per_step"] * 1e-3), 1),
         "unit": "candidate supports/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": best["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE[st["mfma_form"]],
@@ -291,7 +333,198 @@ def run_batched(args, bm, torch, dev):
                    "kernels": kernels},
         "roofline": _roofline(kernels, kms, st["mfma_form"]) if kernels else None,
     }
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def _single_opts(bm, args, flags, **over):
+    kw = dict(mfma_min_children=args.mfma_min_children, mfma_big_children=args.mfma_big_children,
+              split_words=args.split_words, shuffle_seed=args.shuffle, dfs_threads=args.dfs_threads,
+              dfs_max_words=args.dfs_max_words)
+    kw.update(over)
+    return bm.options(flags=flags, **kw)
+
+
+def run_single(args, bm, torch, dev, workload, steps, warmup, sched="none", extra_flags=0,
+               dfs_max_words=None, cold_steps=3, quiet=False):
+    """One database per step: bm_build + bm_mine on device-resident CSR.
+    Returns the bench record (without the CPU baseline)."""
+    import gen
+    t0 = time.time()
+    db = gen.make_config(workload)
+    print(f"# workload {workload}: {db.name} n={db.n} m={db.m} nnz={db.nnz} minsup={db.minsup} "
+          f"(generated in {time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
+    rp = torch.from_numpy(db.row_ptr.astype(np.uint64)).to(dev)
+    ci = torch.from_numpy(db.col_idx.astype(np.uint32)).to(dev)
+    stream = torch.cuda.current_stream()
+    # timed steps record events only around the support-counting kernels; the
+    # bookkeeping launches are timed in separate steps after the timed region
+    flags = (0 if args.no_timing else bm.FLAG_TIMING | bm.FLAG_TIMING_MAIN) | extra_flags
+    if args.levelsync:
+        flags |= bm.FLAG_LEVELSYNC
+    if args.shuffle:
+        flags |= bm.FLAG_SHUFFLE
+    flags |= {"default": 0, "int8": bm.FLAG_INT8_MFMA, "fp4": bm.FLAG_FP4_MFMA}[args.mfma]
+    dmw = args.dfs_max_words if dfs_max_words is None else dfs_max_words
+    opts = _single_opts(bm, args, flags, dfs_max_words=dmw)
+    model = None
+    if sched == "learned":
+        h = bm.bm_build(rp, ci, db.n, db.m, stream=stream)
+        topts = bm.options(flags=bm.FLAG_TRACE, dfs_max_words=dmw)
+        f, y = bm.bm_mine_ex(h, db.minsup, topts, stream=stream).trace()
+        model = bm.Model(seed=1)
+        loss = model.train(f, y, epochs=30, lr=3e-3, batch=256, stream=stream)
+        print(f"# cost model trained on {len(y)} traced tasks, loss {loss:.4f}", file=sys.stderr,
+              flush=True)
+        del h
+
+    def mine(h, o):
+        if model is not None:
+            return bm.bm_mine_batch([h], [db.minsup], model=model, opts=o, stream=stream)[0]
+        return bm.bm_mine_ex(h, db.minsup, o, stream=stream)
+
+    def step():
+        h = bm.bm_build(rp, ci, db.n, db.m, stream=stream)
+        return h, mine(h, opts)
+
+    for i in range(warmup):
+        h, r = step()
+        if not quiet:
+            print(f"# warmup {i}: {r.stats()['wall_ms']:.2f} ms mine", file=sys.stderr, flush=True)
+        del h, r
+    torch.cuda.synchronize()
+    stats = []
+    times = []
+    results = []
+    t_start = time.perf_counter()
+    kept = []
+    for i in range(steps):
+        t1 = time.perf_counter()
+        h, r = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        kept.append(r)
+        del h, r
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    ms_per_step = 1e3 * total / steps
+    for i, r in enumerate(kept):
+        stats.append(r.stats())
+        results.append(r.info())
+        if not quiet:
+            print(f"# step {i}: {times[i] * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    del kept
+    st = stats[-1]
+    cands = st["candidates_total"]
+    assert all(x == results[0] for x in results), "result changed between steps"
+
+    # dominant kernel by total event time
+    kernels, kms = _kernel_table(stats, steps)
+    roofline = (_roofline(kernels, kms, st["mfma_form"]) if (not args.no_timing and kernels)
+                else None)
+    cold = None
+    if not args.no_timing:
+        # every launch kind, events around all of them, outside the timed region
+        full = []
+        fopts = _single_opts(bm, args, flags & ~bm.FLAG_TIMING_MAIN, dfs_max_words=dmw)
+        for _ in range(3):
+            h = bm.bm_build(rp, ci, db.n, db.m, stream=stream)
+            full.append(mine(h, fopts).stats())
+            del h
+        fk, _ = _kernel_table(full, len(full))
+        for k, v in fk.items():
+            if k not in kernels:
+                kernels[k] = dict(v, timed="separate steps with every launch timed")
+        if cold_steps:
+            # cache-cold mining: a 2 GiB scratch write on the same stream between
+            # build and mine leaves none of the matrix in L2 or the Infinity Cache
+            # (256 MB); a fill kernel, not a memset
+            scratch = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
+            cst = []
+            for i in range(cold_steps):
+                h = bm.bm_build(rp, ci, db.n, db.m, stream=stream)
+                scratch.fill_(i + 1)
+                cst.append(mine(h, opts).stats())
+                del h
+            torch.cuda.synchronize()
+            del scratch
+            ck, _ = _kernel_table(cst, len(cst))
+            cold = {"protocol": "2 GiB scratch fill between build and mine, "
+                                f"{cold_steps} steps, events around the support-counting kernels",
+                    "mine_ms": round(sum(s["wall_ms"] for s in cst) / len(cst), 3)}
+            for k, v in ck.items():
+                e = {"avg_launch_ms": v["avg_launch_ms"]}
+                if "achieved_GBs" in v:
+                    e["achieved_GBs"] = v["achieved_GBs"]
+                    e["frac_of_hbm"] = round(v["achieved_GBs"] / HBM_PEAK_GBS, 4)
+                if "achieved_TOPs" in v:
+                    e["achieved_TOPs"] = v["achieved_TOPs"]
+                    e["frac_of_mfma"] = round(v["achieved_TOPs"] / MFMA_PEAK_TOPS[st["mfma_form"]],
+                                              4)
+                cold[k] = e
+
+    pairs = int(st["candidates"].get(2, 0))
+    out = {
+        "metric": "candidate supports counted/s + mine wall time at minsup; % of HBM peak",
+        "value": round(cands / (ms_per_step * 1e-3), 1),
+        "unit": "candidate supports/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[st["mfma_form"]],
+        "data": "synthetic (seeded generator, see DESIGN.md)",
+        "config": {"workload": WORKLOADS[workload], "n_tx": db.n, "n_items": db.m,
+                   "minsup": db.minsup, "frequent_itemsets": st["frequent_total"],
+                   "candidates": cands, "pair_candidates": pairs,
+                   "longer_candidates": cands - pairs,
+                   "pair_supports_per_s": round(pairs / (ms_per_step * 1e-3), 1),
+                   "longer_supports_per_s": round((cands - pairs) / (ms_per_step * 1e-3), 1),
+                   "frequent_items": st["n_frequent_items"],
+                   "mine_ms": round(sum(s["wall_ms"] for s in stats) / len(stats), 3),
+                   "dfs_tasks": st["dfs_tasks"], "host_syncs": st["host_syncs"],
+                   "mode": ("levelsync" if args.levelsync or not st["dfs_tasks"] else "subtrees") +
+                           ("+learned" if model is not None else "") +
+                           (f"+shuffle{args.shuffle}" if args.shuffle else ""),
+                   "kernels": kernels},
+        "roofline": roofline,
+    }
+    if cold is not None:
+        out["config"]["cache_cold"] = cold
+    out["_db"] = db
+    return out
+
+
+def _secondary(args, bm, torch, dev):
+    """Shorter runs of the batched and the T40-style workloads, for the record."""
+    sec = {}
+    b = run_batched(args, bm, torch, dev, steps=3, warmup=1)
+    sec["batch_256"] = {"ms_per_step_by_mode": {k: v["ms_per_step"]
+                                                for k, v in b["config"]["modes"].items()},
+                        "mine_ms_by_mode": {k: v["mine_ms"] for k, v in b["config"]["modes"].items()},
+                        "candidates": b["config"]["candidates"],
+                        "value_learned": b["value"], "roofline": b["roofline"]}
+    t40 = {}
+    for name, kw in (("default", {}),
+                     ("depth_first_plain", {"extra_flags": bm.FLAG_DEPTH_FIRST,
+                                            "dfs_max_words": 0xFFFFFFFF}),
+                     ("depth_first_learned", {"extra_flags": bm.FLAG_DEPTH_FIRST,
+                                              "dfs_max_words": 0xFFFFFFFF, "sched": "learned"})):
+        r = run_single(args, bm, torch, dev, 5, 3, 1, cold_steps=3 if name == "default" else 0,
+                       quiet=True, **kw)
+        e = {"ms_per_step": r["ms_per_step"], "mine_ms": r["config"]["mine_ms"],
+             "candidates": r["config"]["candidates"], "value": r["value"]}
+        if name == "default":
+            e["roofline"] = r["roofline"]
+            e["cache_cold"] = r["config"].get("cache_cold")
+            e["pair_candidates"] = r["config"]["pair_candidates"]
+            e["longer_candidates"] = r["config"]["longer_candidates"]
+        t40[name] = e
+        print(f"# T40 {name}: {r['ms_per_step']} ms/step", file=sys.stderr, flush=True)
+    sec["quest_t40_1M"] = t40
+    return sec
 
 
 def main():
@@ -302,6 +535,8 @@ def main():
     ap.add_argument("--workload", type=int, default=3, choices=sorted(WORKLOADS),
                     help="1-3, 5: one database; 4: the batch of 256 (mode comparison)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the shorter batched and T40-style runs after the headline")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--mfma-min-children", type=int, default=0)
     ap.add_argument("--split-words", type=int, default=0)
@@ -339,131 +574,20 @@ def main():
         print(json.dumps({"copy_probe_bytes": n * 4}), flush=True)
         return
 
-    import gen
     import paper_2412_19420_amd as bm
 
     global WORKLOAD
     WORKLOAD = args.workload
     if args.workload == 4:
-        run_batched(args, bm, torch, dev)
+        print(json.dumps(run_batched(args, bm, torch, dev)), flush=True)
         return
 
-    t0 = time.time()
-    db = gen.make_config(args.workload)
-    print(f"# workload {args.workload}: {db.name} n={db.n} m={db.m} nnz={db.nnz} minsup={db.minsup} "
-          f"(generated in {time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
-    rp = torch.from_numpy(db.row_ptr.astype(np.uint64)).to(dev)
-    ci = torch.from_numpy(db.col_idx.astype(np.uint32)).to(dev)
-    stream = torch.cuda.current_stream()
-    # timed steps record events only around the support-counting kernels; the
-    # bookkeeping launches are timed in separate steps after the timed region
-    flags = 0 if args.no_timing else bm.FLAG_TIMING | bm.FLAG_TIMING_MAIN
-    if args.levelsync:
-        flags |= bm.FLAG_LEVELSYNC
-    if args.shuffle:
-        flags |= bm.FLAG_SHUFFLE
-    flags |= {"default": 0, "int8": bm.FLAG_INT8_MFMA, "fp4": bm.FLAG_FP4_MFMA}[args.mfma]
-    opts = bm.options(flags=flags, mfma_min_children=args.mfma_min_children,
-                      mfma_big_children=args.mfma_big_children,
-                      split_words=args.split_words, shuffle_seed=args.shuffle,
-                      dfs_threads=args.dfs_threads, dfs_max_words=args.dfs_max_words)
-    model = None
-    if args.sched == "learned":
-        h = bm.bm_build(rp, ci, db.n, db.m, stream=stream)
-        topts = bm.options(flags=bm.FLAG_TRACE, dfs_max_words=args.dfs_max_words)
-        f, y = bm.bm_mine_ex(h, db.minsup, topts, stream=stream).trace()
-        model = bm.Model(seed=1)
-        loss = model.train(f, y, epochs=30, lr=3e-3, batch=256, stream=stream)
-        print(f"# cost model trained on {len(y)} traced tasks, loss {loss:.4f}", file=sys.stderr,
-              flush=True)
-        del h
-
-    def step():
-        h = bm.bm_build(rp, ci, db.n, db.m, stream=stream)
-        if model is not None:
-            r = bm.bm_mine_batch([h], [db.minsup], model=model, opts=opts, stream=stream)[0]
-        else:
-            r = bm.bm_mine_ex(h, db.minsup, opts, stream=stream)
-        return h, r
-
-    for i in range(args.warmup):
-        h, r = step()
-        print(f"# warmup {i}: {r.stats()['wall_ms']:.2f} ms mine", file=sys.stderr, flush=True)
-        del h, r
-    torch.cuda.synchronize()
-    stats = []
-    times = []
-    results = []
-    t_start = time.perf_counter()
-    kept = []
-    for i in range(args.steps):
-        t1 = time.perf_counter()
-        h, r = step()
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t1)
-        kept.append(r)
-        del h, r
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-    ms_per_step = 1e3 * total / args.steps
-    for i, r in enumerate(kept):
-        stats.append(r.stats())
-        results.append(r.info())
-        print(f"# step {i}: {times[i] * 1e3:.2f} ms", file=sys.stderr, flush=True)
-    del kept
-    st = stats[-1]
-    cands = st["candidates_total"]
-    assert all(x == results[0] for x in results), "result changed between steps"
-
-    # dominant kernel by total event time
-    kernels, kms = _kernel_table(stats, args.steps)
-    roofline = (_roofline(kernels, kms, st["mfma_form"]) if (not args.no_timing and kernels)
-                else None)
-    if not args.no_timing:
-        # every launch kind, events around all of them, outside the timed region
-        full = []
-        for _ in range(3):
-            h = bm.bm_build(rp, ci, db.n, db.m, stream=stream)
-            fopts = bm.options(flags=flags & ~bm.FLAG_TIMING_MAIN,
-                               mfma_min_children=args.mfma_min_children,
-                               mfma_big_children=args.mfma_big_children,
-                               split_words=args.split_words, shuffle_seed=args.shuffle,
-                               dfs_threads=args.dfs_threads, dfs_max_words=args.dfs_max_words)
-            if model is not None:
-                r = bm.bm_mine_batch([h], [db.minsup], model=model, opts=fopts, stream=stream)[0]
-            else:
-                r = bm.bm_mine_ex(h, db.minsup, fopts, stream=stream)
-            full.append(r.stats())
-            del h, r
-        fk, _ = _kernel_table(full, len(full))
-        for k, v in fk.items():
-            if k not in kernels:
-                kernels[k] = dict(v, timed="separate steps with every launch timed")
-
-    out = {
-        "metric": "candidate supports counted/s + mine wall time at minsup; % of HBM peak",
-        "value": round(cands / (ms_per_step * 1e-3), 1),
-        "unit": "candidate supports/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": DTYPE[st["mfma_form"]],
-        "data": "synthetic (seeded generator, see DESIGN.md)",
-        "config": {"workload": WORKLOADS[args.workload], "n_tx": db.n, "n_items": db.m,
-                   "minsup": db.minsup, "frequent_itemsets": st["frequent_total"],
-                   "candidates": cands, "frequent_items": st["n_frequent_items"],
-                   "mine_ms": round(sum(s["wall_ms"] for s in stats) / len(stats), 3),
-                   "dfs_tasks": st["dfs_tasks"], "host_syncs": st["host_syncs"],
-                   "mode": ("levelsync" if args.levelsync or not st["dfs_tasks"] else "subtrees") +
-                           ("+learned" if model is not None else "") +
-                           (f"+shuffle{args.shuffle}" if args.shuffle else ""),
-                   "kernels": kernels},
-        "roofline": roofline,
-    }
+    out = run_single(args, bm, torch, dev, args.workload, args.steps, args.warmup, sched=args.sched)
+    db = out.pop("_db")
+    if not args.no_secondary and args.workload == 3:
+        WORKLOAD = None  # traffic records belong to the headline workload
+        out["config"]["secondary"] = _secondary(args, bm, torch, dev)
+        WORKLOAD = args.workload
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(db)
     print(json.dumps(out), flush=True)

@@ -63,7 +63,8 @@ typedef enum {
 enum {
   BM_K_BUILD = 0,     /* CSR validation + packing of column bitsets */
   BM_K_COLSUM = 1,    /* column popcount: single-item supports */
-  BM_K_GRAM_MFMA = 2, /* int8-MFMA (masked) Gram matrix: pair supports of a class */
+  BM_K_GRAM_MFMA = 2, /* MFMA (masked) Gram matrix of a class, 128 x 128 tiles: pair supports
+                       * (scaled FP4 operands by default, int8 with BM_FLAG_INT8_MFMA) */
   BM_K_ANDPOP = 3,    /* AND + popcount of a prefix class's columns, LDS-blocked (VALU) */
   BM_K_ANDPOP_REG = 4,/* AND + popcount of a small prefix class held in registers (VALU) */
   BM_K_LEVEL = 5,     /* candidate/level bookkeeping: thresholds, scans, compaction */
@@ -77,8 +78,9 @@ enum {
 
 /* Statistics of one mining call.  Kernel times are filled only when the call
  * ran with BM_FLAG_TIMING (hipEvents recorded around every launch on the call's
- * stream); `ops` counts algorithmic work: int8 multiply-adds x2 for
- * BM_K_GRAM_MFMA, AND+popcount word operations for BM_K_ANDPOP; `bytes` counts
+ * stream); `ops` counts algorithmic work: 2 n per candidate pair (one AND and
+ * one add per transaction) for the Gram kernels, AND+popcount word operations
+ * for the AND+popcount kernels; `bytes` counts
  * algorithmic bytes (see the library's design notes for each kernel). */
 typedef struct {
   uint32_t max_len;                            /* longest frequent itemset */
@@ -109,9 +111,13 @@ typedef struct {
 #define BM_FLAG_SHUFFLE 32u    /* random subtree-task order (order-invariance tests) */
 #define BM_FLAG_LEVELSYNC 64u  /* evaluate small classes level by level too (no depth-first kernel
                                 * and no subset counting) */
-#define BM_FLAG_FP4_MFMA 128u  /* Gram kernels on the FP4 (e2m1) MFMA form (the default): bits
-                                * as 0 / 0.5, FP32 sums, exact for counts < 2^24 per task (word
-                                * splits are capped to guarantee it) */
+#define BM_FLAG_FP4_MFMA 128u  /* Gram kernels on the block-scaled FP4 (e2m1) MFMA form (the
+                                * default): each transaction bit sits in one e2m1 element of a
+                                * bit plane, coded 0.5, 1 or 2 by plane, and the planes' E8M0
+                                * scales (2, 1, 1/2, 1) make every product of two set bits
+                                * exactly 1.0; FP32 sums are exact while a task's counts stay
+                                * below 2^24, which the word-range cap of 2^18 words per task
+                                * guarantees */
 #define BM_FLAG_INT8_MFMA 256u /* Gram kernels on int8 x int8 -> int32 MFMA (overrides FP4) */
 #define BM_FLAG_DFS_BLOCK_ONLY 512u /* every subtree task on the one-stack-per-workgroup kernel */
 #define BM_FLAG_TIMING_MAIN 1024u   /* with BM_FLAG_TIMING: events only around the support-counting
@@ -145,7 +151,11 @@ typedef struct {
                                * of their children is counted in one pass over word ranges, and
                                * the rest of such a subtree needs no further level step
                                * (0 = default 6; 1 = never, level by level instead) */
-  uint32_t reserved[2];
+  uint32_t dfs_arena_nodes;   /* initial capacity, in nodes, of the output arena that the subtree
+                               * kernels write (0 = automatic).  When it overflows the subtree
+                               * phase runs again with at least four times the room; a small value
+                               * exercises that path and never changes the result */
+  uint32_t reserved[1];
 } bm_options;
 
 uint32_t bm_abi_version(void);

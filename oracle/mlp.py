@@ -2,9 +2,10 @@
 
 TEST INFRASTRUCTURE ONLY: used by tests/, never by the library.
 
-The paper's scheduler (Section IV, learned scheduling) is a small perceptron
-that maps per-task features to a predicted cost; its weights are stored in
-BF16 and it is trained on the device.  This module restates that network in
+The paper describes no scheduler: this cost model is a project addition that
+orders the miner's work, never its results.  It is a small perceptron that
+maps per-task features to a predicted cost; its weights are stored in BF16 and
+it is trained on the device.  This module restates that network in
 plain numpy float64 so the device forward pass, the hand-written backward pass
 and the Adam update can be compared against it:
 
@@ -19,11 +20,13 @@ W2, b2, W3, b3 -- 4,801 values.  The device keeps an FP32 master copy and
 computes with the master rounded to BF16 (round to nearest, ties to even on
 the upper 16 bits of the FP32 pattern); `bf16_round` is that rounding.
 
-Pins (tests/test_oracle.py): the backward pass against central finite
+Pins (tests/test_oracle_mlp.py): the backward pass against central finite
 differences of the forward pass; the forward pass of an all-active network
 against the product of its weight matrices (it is then affine); a dead first
 layer against its constant output; BF16 rounding against values fixed by the
-format's definition; Adam against its closed form on the first step.
+format's definition; Adam against closed forms: the first step is -lr sign(g),
+a constant gradient moves every step by -lr sign(g), and a hand-computed
+two-step sequence with a sign change (tests/test_oracle_mlp.py).
 """
 from __future__ import annotations
 

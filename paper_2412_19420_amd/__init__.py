@@ -170,7 +170,8 @@ class Result:
 def options(flags: int = 0, mfma_min_children: int = 0, andpop_chunk_words: int = 0,
             split_words: int = 0, shuffle_seed: int = 0, dfs_threads: int = 0,
             dfs_max_words: int = 0, mfma_big_children: int = 0,
-            dfs_wave_max_words: int = 0, subset_max_children: int = 0) -> BmOptions:
+            dfs_wave_max_words: int = 0, subset_max_children: int = 0,
+            dfs_arena_nodes: int = 0) -> BmOptions:
     o = BmOptions()
     o.flags = flags
     o.mfma_min_children = mfma_min_children
@@ -182,6 +183,7 @@ def options(flags: int = 0, mfma_min_children: int = 0, andpop_chunk_words: int 
     o.mfma_big_children = mfma_big_children
     o.dfs_wave_max_words = dfs_wave_max_words
     o.subset_max_children = subset_max_children
+    o.dfs_arena_nodes = dfs_arena_nodes
     return o
 
 

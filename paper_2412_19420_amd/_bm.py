@@ -85,7 +85,8 @@ class BmOptions(ctypes.Structure):
         ("mfma_big_children", ctypes.c_uint32),
         ("dfs_wave_max_words", ctypes.c_uint32),
         ("subset_max_children", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 2),
+        ("dfs_arena_nodes", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 1),
     ]
 
 

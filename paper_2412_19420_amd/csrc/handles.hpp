@@ -76,6 +76,7 @@ struct Tuning {
   uint32_t subset_q = SUBSET_DEFAULT_Q;
   bool subsets = false;            // this call mines small subtrees by subset counting
   uint32_t tiny_q = TINY_Q;        // small-class threshold of this call
+  uint32_t arena_nodes = 0;        // initial subtree-output arena (0: sized from the task count)
 };
 Tuning tuning_from(const bm_options* opt);
 

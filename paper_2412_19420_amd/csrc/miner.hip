@@ -435,6 +435,7 @@ Tuning tuning_from(const bm_options* opt) {
       fail(BM_ERR_INVALID_ARG, "subset_max_children must be at most %d", SUBSET_Q);
     t.subset_q = opt->subset_max_children == 1 ? 0u : opt->subset_max_children;
   }
+  t.arena_nodes = opt->dfs_arena_nodes;
   if (opt->flags & BM_FLAG_FP4_MFMA) t.mfma_fp4 = true;
   if (opt->flags & BM_FLAG_INT8_MFMA) t.mfma_fp4 = false;
   if (opt->flags & BM_FLAG_NO_MFMA) {
@@ -1037,7 +1038,8 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       }
       // workers reserve arena space ARENA_CHUNK (256) nodes at a time
       const uint64_t workers = (uint64_t)cu_count() * (16 + 2048 / tu.dfs_threads);
-      uint64_t cap = std::max<uint64_t>(1u << 16, 32 * D) + workers * 256;
+      uint64_t cap = tu.arena_nodes ? (uint64_t)tu.arena_nodes
+                                    : std::max<uint64_t>(1u << 16, 32 * D) + workers * 256;
       TBuf<ArenaNode> arena;
       std::vector<unsigned long long> hstat(kStatWords);
       for (int attempt = 0;; ++attempt) {

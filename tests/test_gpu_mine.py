@@ -2,9 +2,12 @@
 
 Integer work, so the bar is bit-exact: the canonical result arrays (offsets,
 items, supports) must equal the oracle's byte for byte.  Small and mid-size
-inputs are compared with the full oracle result; the full-size dense
-workloads are checked with the certificate (every reported support recomputed
-by the oracle, downward closure, and a sample of the negative border).
+inputs are compared with the full oracle result computed in the test; the
+full-size workloads (dense 1M x 4,096, T40-style 1M x 2,000 and the batch of
+256 databases) with the oracle's complete results stored under tests/golden/
+(written by tests/golden/make_full_fixtures.py, which calls only the oracle),
+plus the certificate (every reported support recomputed from tidsets,
+downward closure, a sample of the negative border) as an extra check.
 """
 import os
 
@@ -221,31 +224,77 @@ def test_mine_dense_planted_reduced_exact(bm):
     assert r.stats()["candidates_total"] == cands
 
 
-def _certify_full(bm, k, border_sample):
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _load_full_fixture(name):
+    """Expected canonical arrays of a full-size workload, written by
+    tests/golden/make_full_fixtures.py from the CPU oracle run to completion."""
+    z = np.load(os.path.join(GOLDEN, name), allow_pickle=False)
+    lens = z["lengths"].astype(np.uint64)
+    offs = np.zeros(len(lens) + 1, dtype=np.uint64)
+    np.cumsum(lens, out=offs[1:])
+    return ((offs, z["items"].astype(np.uint32), z["supports"].astype(np.uint32)),
+            int(z["candidates"][0]), str(z["input_sha256"][0]))
+
+
+def _full_exact(bm, k, fixture, certify_sample):
+    from golden.make_full_fixtures import input_digest
     db = gen.make_config(k)
+    want, cands, in_sha = _load_full_fixture(fixture)
+    assert input_digest(db) == in_sha, "the generator no longer yields the fixture's input"
     print(f"workload {k} full size: n={db.n} m={db.m} nnz={db.nnz}", flush=True)
     h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
     r = bm.bm_mine_ex(h, db.minsup, bm.options(flags=bm.FLAG_TIMING))
-    offs, items, supp = r.arrays()
+    got = r.arrays()
     st = r.stats()
-    print(f"mined {len(supp)} sets, {st['candidates_total']} candidates, {st['wall_ms']:.1f} ms",
+    print(f"mined {len(got[2])} sets, {st['candidates_total']} candidates, {st['wall_ms']:.1f} ms",
           flush=True)
+    # the bar: every array equal to the oracle's, element for element
+    assert_same(got, want)
+    assert st["candidates_total"] == cands
+    # and, independently of the stored arrays, the certificate: every reported
+    # support recomputed from tidsets, downward closure, a border sample
     o = ocpp.OracleDb(db.row_ptr, db.col_idx, db.n, db.m)
-    info = certify.certify(o, (offs, items, supp), db.minsup, border_sample=border_sample)
+    info = certify.certify(o, got, db.minsup, border_sample=certify_sample)
     print("certificate", info, flush=True)
-    # level-2 border in full from the closed-form pair matrix on the GPU's own
-    # frequent items is too slow on the host; the single-item border is complete.
-    return st
+    return h, db, st
 
 
-def test_mine_dense_planted_full_certified(bm):
-    st = _certify_full(bm, 3, border_sample=3000)
+def test_mine_dense_planted_full_exact(bm):
+    _, _, st = _full_exact(bm, 3, "full_dense_planted_1M.npz", 3000)
     assert st["n_frequent_items"] > 2000
 
 
-def test_mine_quest_long_full_certified(bm):
-    st = _certify_full(bm, 5, border_sample=2000)
+def test_mine_quest_long_full_exact(bm):
+    _, _, st = _full_exact(bm, 5, "full_quest_t40_1M.npz", 2000)
     assert st["frequent_total"] > 10_000
+
+
+def test_mine_batch_256_full_exact(bm):
+    # the full batched workload (256 databases, one batched build and one batched
+    # mining call) against the oracle's per-database results, compared through
+    # SHA-256 digests of the canonical arrays
+    import json
+    from golden.make_full_fixtures import input_digest, result_digest
+    with open(os.path.join(GOLDEN, "full_batch_256.json")) as f:
+        rows = json.load(f)["databases"]
+    dbs = gen.batch_dbs(256)
+    assert len(rows) == len(dbs) == 256
+    for d, row in zip(dbs, rows):
+        assert input_digest(d) == row["input_sha256"], f"generator changed for database {row['k']}"
+    print("batch of 256 databases, full size", flush=True)
+    hs = bm.bm_build_batch([(d.row_ptr, d.col_idx, d.n, d.m) for d in dbs])
+    rs = bm.bm_mine_batch(hs, [d.minsup for d in dbs])
+    bad = []
+    for d, row, r in zip(dbs, rows, rs):
+        offs, items, supp = r.arrays()
+        if (len(supp), len(items)) != (row["sets"], row["items"]) or \
+                result_digest(offs, items, supp) != row["result_sha256"]:
+            bad.append(row["k"])
+    assert not bad, f"databases differing from the oracle: {bad[:20]}"
+    cands = sum(row["candidates"] for row in rows)
+    assert rs[0].stats()["candidates_total"] == cands
 
 
 # ------------------------------------------------------------ edge cases / errors
@@ -473,10 +522,12 @@ def test_mine_quest_small_mfma_routings_exact(bm, min_children, form):
     assert_same(r.arrays(), want)
 
 
-def test_fp4_mfma_counts_beyond_fp32_quarter_range(bm):
-    # item 0 in every row, item 1 in 63 of every 64: each 64-transaction MFMA step
-    # adds 15.75 (63 quarters), so one FP32 accumulator over all 20M rows would
-    # lose quarters past 2^22; the capped word split keeps every task exact
+def test_fp4_mfma_counts_beyond_fp32_integer_range(bm):
+    # item 0 in every row, item 1 in 63 of every 64: each product of two set bits
+    # is exactly 1.0, so one 64-transaction MFMA step adds 63 and one FP32
+    # accumulator over all 20M rows (19.7M hits) would pass 2^24, where FP32
+    # stops holding every integer; the word split capped at 2^18 words (2^24
+    # transactions) per task keeps every partial sum exact
     n = 20_000_000
     keep1 = (np.arange(n) % 64) != 0
     lens = 1 + keep1.astype(np.uint64)

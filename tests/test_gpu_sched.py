@@ -237,6 +237,83 @@ def test_model_adam_step_matches_oracle(bm):
     assert np.array_equal(wbf_new, omlp.bf16_round(got))
 
 
+def _adam_mask(grads):
+    # components whose gradient stays clearly away from zero at every step: there
+    # the bias-corrected ratio m / sqrt(v) is well conditioned, so FP32 and
+    # float64 gradients give the same update to ~1e-5 of lr
+    gs = np.abs(np.stack(grads))
+    return gs.min(axis=0) > 1e-2 * gs.max()
+
+
+def test_model_adam_steps_match_oracle_one_step_per_call(bm):
+    # one Adam step per call (batch = all rows), four calls: step t of the
+    # device must be the oracle's step t from the device's own weights before
+    # it, with the oracle's moments carried over from its own gradients on those
+    # weights -- pins the step counter across calls and the bias correction at
+    # t = 2..4 (a correction one step off moves the update by >= 4% of lr)
+    print("model adam, four single-step calls", flush=True)
+    m, X, Y, master, wbf, nrm = _setup_model(bm, 14, 256)
+    lr = 1e-2
+    mo = np.zeros(omlp.PARAMS)
+    vo = np.zeros(omlp.PARAMS)
+    prev_master, prev_w = master.astype(np.float64), wbf.astype(np.float64)
+    wants, gots, grads = [], [], []
+    for t in range(1, 5):
+        m.train(X, Y, epochs=1, lr=lr, batch=len(Y), graph=False)
+        got, wbf_new, _ = m.params()
+        g = omlp.grad(prev_w, nrm, X, Y, 1.0 / len(Y))
+        want, mo, vo = omlp.adam(prev_master, mo, vo, g, lr, t)
+        wants.append(want)
+        gots.append(got.astype(np.float64))
+        grads.append(g)
+        assert np.array_equal(wbf_new, omlp.bf16_round(got))
+        prev_master, prev_w = got.astype(np.float64), wbf_new.astype(np.float64)
+    mask = _adam_mask(grads)
+    assert mask.sum() > 500
+    for t, (got, want) in enumerate(zip(gots, wants), start=1):
+        err = np.abs(got - want)[mask].max()
+        assert err <= 1e-3 * lr, (t, err)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_model_adam_two_epochs_of_two_batches_match_oracle(bm, graph):
+    # two batches per epoch, two epochs in one call (replayed as a hipGraph or
+    # issued from the host), after one single-step call: steps 2..5 with the
+    # in-epoch step offset.  The oracle replays the four steps from the device's
+    # weights, rounding its own master copy to BF16 between steps; a rare
+    # rounding tie broken differently moves a gradient by far less than the
+    # tolerance, which is 1e-2 of lr against a >= 4% shift for a step count off
+    # by one
+    print(f"model adam, 2 x 2 steps graph={graph}", flush=True)
+    m, X, Y, master, wbf, nrm = _setup_model(bm, 15, 512)
+    lr = 1e-2
+    m.train(X, Y, epochs=1, lr=lr, batch=len(Y), graph=False)
+    g1 = omlp.grad(wbf.astype(np.float64), nrm, X, Y, 1.0 / len(Y))
+    _, mo, vo = omlp.adam(master.astype(np.float64), np.zeros(omlp.PARAMS), np.zeros(omlp.PARAMS),
+                          g1, lr, 1)
+    start, wstart, _ = m.params()
+    m.train(X, Y, epochs=2, lr=lr, batch=len(Y) // 2, graph=graph)
+    got, wbf_new, _ = m.params()
+    w = start.astype(np.float64)
+    wb = wstart.astype(np.float64)
+    half = len(Y) // 2
+    grads = [g1]
+    t = 2
+    for _epoch in range(2):
+        for b in range(2):
+            Xb, Yb = X[b * half:(b + 1) * half], Y[b * half:(b + 1) * half]
+            g = omlp.grad(wb, nrm, Xb, Yb, 1.0 / half)
+            grads.append(g)
+            w, mo, vo = omlp.adam(w, mo, vo, g, lr, t)
+            wb = omlp.bf16_round(w.astype(np.float32)).astype(np.float64)
+            t += 1
+    mask = _adam_mask(grads)
+    assert mask.sum() > 300
+    err = np.abs(got.astype(np.float64) - w)[mask].max()
+    assert err <= 1e-2 * lr, err
+    assert np.array_equal(wbf_new, omlp.bf16_round(got))
+
+
 def test_model_training_reduces_loss_and_roundtrips(bm, tmp_path):
     print("model training", flush=True)
     rng = np.random.default_rng(5)
@@ -420,3 +497,25 @@ def test_learned_order_shortens_the_queue_makespan(bm):
     rho = np.corrcoef(np.argsort(np.argsort(pred)), np.argsort(np.argsort(cost)))[0, 1]
     assert rho > 0.5, rho  # the ranking carries the cost
     assert learned < plain
+
+
+@pytest.mark.parametrize("arena", [1, 64, 300])
+def test_small_arena_overflow_retry_is_exact(bm, arena):
+    # a subtree-output arena far too small for the first attempt: the kernels
+    # flag the overflow, the call runs the subtree phase again with a larger
+    # arena (at least fourfold each time), and the result is the oracle's --
+    # for the depth-first kernels (short columns) and for subset counting
+    # (long columns forced by a one-word column limit)
+    dbs = [gen.batch_db(k, scale=0.05) for k in range(4)] + [gen.make_config(3, scale=0.02)]
+    hs = [bm.bm_build(d.row_ptr, d.col_idx, d.n, d.m) for d in dbs]
+    ms = [d.minsup for d in dbs]
+    want = [_oracle(d, d.minsup) for d in dbs]
+    print(f"arena {arena}: depth-first batch", flush=True)
+    got = bm.bm_mine_batch(hs, ms, opts=bm.options(bm.FLAG_DEPTH_FIRST, dfs_arena_nodes=arena))
+    assert got[0].stats()["dfs_tasks"] > 0
+    for w, r in zip(want, got):
+        assert _arrays_equal(r.arrays(), w)
+    print(f"arena {arena}: subset counting", flush=True)
+    for d, h, w in zip(dbs, hs, want):
+        r = bm.bm_mine_ex(h, d.minsup, bm.options(dfs_max_words=1, dfs_arena_nodes=arena))
+        assert _arrays_equal(r.arrays(), w)

@@ -2,7 +2,8 @@
 
 Each pin fixes the oracle by something other than itself: finite differences
 of the forward pass, the closed form of an all-active (affine) network, a dead
-layer's constant output, the BF16 format's definition and Adam's first step.
+layer's constant output, the BF16 format's definition and Adam's closed forms
+(first step, constant gradient, a hand-worked two-step sequence).
 Planted mistakes in the backward pass must fail at least one of them.
 """
 import numpy as np
@@ -144,3 +145,65 @@ def test_pins_catch_planted_backward_mistakes(name, old, new):
             caught = True
             break
     assert caught, f"mutation '{name}' escaped the pins"
+
+
+def test_adam_constant_gradient_moves_by_signed_lr_every_step():
+    # with g_t = g for all t the moments are m_t = (1 - b1^t) g and
+    # v_t = (1 - b2^t) g^2, so the bias-corrected ratio is g / |g| at every
+    # step t and each update is exactly -lr * sign(g)
+    rng = np.random.default_rng(1)
+    g = rng.normal(size=40)
+    w0 = rng.normal(size=40)
+    w, m, v = w0.copy(), np.zeros(40), np.zeros(40)
+    for t in range(1, 6):
+        w, m, v = mlp.adam(w, m, v, g, 0.01, t, eps=0.0)
+        assert np.allclose(w, w0 - 0.01 * t * np.sign(g), rtol=0, atol=1e-12), t
+        assert np.allclose(m, (1 - 0.9 ** t) * g, rtol=1e-12)
+        assert np.allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-12)
+
+
+def test_adam_two_steps_with_sign_change_by_hand():
+    # g_1 = +1, g_2 = -1 (eps = 0), worked by hand:
+    #   step 1: m = 0.1, v = 0.001, m/(1-0.9) = 1, v/(1-0.999) = 1 -> w -= lr
+    #   step 2: m = 0.09 - 0.1 = -0.01, v = 0.000999 + 0.001 = 0.001999,
+    #           m/(1-0.81) = -1/19, v/(1-0.998001) = 1              -> w += lr/19
+    lr = 0.5
+    w, m, v = mlp.adam(np.array([2.0]), np.zeros(1), np.zeros(1), np.array([1.0]), lr, 1, eps=0.0)
+    assert np.allclose(w, [2.0 - lr], rtol=0, atol=1e-15)
+    w, m, v = mlp.adam(w, m, v, np.array([-1.0]), lr, 2, eps=0.0)
+    assert np.allclose(m, [-0.01], rtol=0, atol=1e-15)
+    assert np.allclose(v, [0.001999], rtol=0, atol=1e-15)
+    assert np.allclose(w, [2.0 - lr + lr / 19.0], rtol=0, atol=1e-12)
+
+
+_ADAM_MUTATIONS = [
+    ("first moment not bias-corrected by step", "mh = m / (1 - b1 ** step)", "mh = m / (1 - b1)"),
+    ("second moment exponent off by one", "vh = v / (1 - b2 ** step)",
+     "vh = v / (1 - b2 ** (step + 1))"),
+    ("second moment from the raw gradient", "v = b2 * v + (1 - b2) * g * g",
+     "v = b2 * v + (1 - b2) * np.abs(g)"),
+    ("moment decay swapped", "m = b1 * m + (1 - b1) * g", "m = (1 - b1) * m + b1 * g"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", _ADAM_MUTATIONS, ids=[m[0] for m in _ADAM_MUTATIONS])
+def test_adam_pins_catch_planted_mistakes(name, old, new):
+    src = open(mlp.__file__).read()
+    assert old in src, name
+    ns = {"__name__": "mutant"}
+    exec(compile(src.replace(old, new), "mutant_mlp.py", "exec"), ns)
+    caught = False
+    for pin in (test_adam_first_step_is_signed_lr,
+                test_adam_constant_gradient_moves_by_signed_lr_every_step,
+                test_adam_two_steps_with_sign_change_by_hand):
+        saved = mlp.adam
+        mlp.adam = ns["adam"]
+        try:
+            pin()
+        except AssertionError:
+            caught = True
+        finally:
+            mlp.adam = saved
+        if caught:
+            break
+    assert caught, f"mutation '{name}' escaped the Adam pins"
