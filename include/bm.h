@@ -49,6 +49,7 @@ extern "C" {
 typedef struct bm_db bm_db;
 typedef struct bm_result bm_result;
 typedef struct bm_model bm_model;
+typedef struct bm_rules bm_rules;
 
 typedef enum {
   BM_OK = 0,
@@ -309,8 +310,35 @@ bm_status bm_model_grad(bm_model* m, const float* feats, const float* labels, ui
 bm_status bm_model_params(const bm_model* m, float* master, float* weights_bf16, float* norm);
 bm_status bm_model_set_params(bm_model* m, const float* master, const float* norm);
 
+/* Association rules (the paper's use of frequent itemsets: abstract and
+ * Section I; support, confidence and lift are its indicators, Section IV-A).
+ * From every itemset Z of a mining result with 2 <= |Z| <= max_len and every
+ * split Z = X + Y into non-empty disjoint X (antecedent) and Y (consequent):
+ *   conf(X => Y) = supp(Z) / supp(X),
+ *   lift(X => Y) = supp(Z) * n / (supp(X) * supp(Y)),  n = transactions,
+ * keeping the rule iff supp(Z) * 10^6 >= min_conf_ppm * supp(X) (exact integer
+ * test; min_conf_ppm <= 10^6, 0 keeps all 2^|Z| - 2 rules of each Z).  Both
+ * supports are looked up in the result itself (every subset of a frequent
+ * set is frequent) by a device join of the canonical list with itself.
+ * max_len: 0 = 20; at most 24 (BM_ERR_UNSUPPORTED beyond), itemsets longer
+ * than max_len give no rules.  conf and lift are IEEE double quotients of the
+ * integers (exact operands while supp(Z) * n < 2^53).  Rules are ordered by
+ * Z's position in the result, then by X as an ascending tuple
+ * (lexicographically, a prefix first).  The result may be freed afterwards. */
+bm_status bm_rules_mine(const bm_result* r, uint32_t min_conf_ppm, uint32_t max_len, void* stream,
+                        bm_rules** out);
+bm_status bm_rules_info(const bm_rules* rs, uint64_t* n_rules);
+/* Copy the rules (host or device arrays of n_rules entries; any may be NULL):
+ *   z_index   uint64: position of Z in the result's itemset list
+ *   ante_mask uint32: X as a mask over Z's items, bit p = p-th (ascending) item
+ *   supp_x, supp_y, supp_z uint32; conf, lift double */
+bm_status bm_rules_copy(const bm_rules* rs, uint64_t* z_index, uint32_t* ante_mask, uint32_t* supp_x,
+                        uint32_t* supp_y, uint32_t* supp_z, double* conf, double* lift,
+                        void* stream);
+
 void bm_db_free(bm_db* db);
 void bm_result_free(bm_result* r);
+void bm_rules_free(bm_rules* rs);
 void bm_model_free(bm_model* m);
 
 #ifdef __cplusplus

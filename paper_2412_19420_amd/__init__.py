@@ -7,6 +7,7 @@ Python binding of libbm.so with the names of its C ABI (include/bm.h):
     C   = bm_pair_support(db, items)                      # Eq. 2: pair supports (MFMA Gram)
     res = bm_mine(db, minsup)                             # all frequent itemsets, canonical order
     offsets, items, supports = res.arrays()
+    rules = bm_rules_mine(res, min_conf_ppm)              # association rules, confidence and lift
 
 Arrays may be numpy arrays or torch tensors (host or device).  Work runs on
 torch's current HIP stream unless `stream` is given.  The package has no CPU
@@ -33,7 +34,7 @@ __all__ = [
     "FLAG_SHUFFLE", "FLAG_LEVELSYNC", "FLAG_FP4_MFMA", "FLAG_INT8_MFMA", "FLAG_DFS_BLOCK_ONLY",
     "FLAG_TIMING_MAIN", "FLAG_DEPTH_FIRST",
     "LIB_PATH", "Model", "MLP_PARAMS", "bm_autotune",
-    "autotune_cached", "options_to_dict", "options_from_dict", "shape_key",
+    "autotune_cached", "options_to_dict", "options_from_dict", "shape_key", "bm_rules_mine", "Rules",
 ]
 
 LIB_PATH = _bm.LIB_PATH
@@ -165,6 +166,71 @@ class Result:
             self.free()
         except Exception:
             pass
+
+
+class Rules:
+    """Association rules of a mining result, held on the GPU until copied out."""
+
+    def __init__(self, handle, result):
+        self._h = handle
+        self._result = result
+
+    def __len__(self):
+        n = ctypes.c_uint64()
+        _bm.check(_bm.lib.bm_rules_info(self._h, ctypes.byref(n)), "bm_rules_info")
+        return int(n.value)
+
+    def arrays(self, stream=None):
+        """dict of host arrays: z (u64 position of Z in the result), mask (u32
+        antecedent over Z's items), supp_x, supp_y, supp_z (u32), conf, lift (f64)."""
+        R = len(self)
+        out = {"z": np.zeros(max(R, 1), dtype=np.uint64), "mask": np.zeros(max(R, 1), dtype=np.uint32),
+               "supp_x": np.zeros(max(R, 1), dtype=np.uint32),
+               "supp_y": np.zeros(max(R, 1), dtype=np.uint32),
+               "supp_z": np.zeros(max(R, 1), dtype=np.uint32),
+               "conf": np.zeros(max(R, 1), dtype=np.float64),
+               "lift": np.zeros(max(R, 1), dtype=np.float64)}
+        _bm.check(_bm.lib.bm_rules_copy(self._h, *(out[k].ctypes.data for k in
+                                                   ("z", "mask", "supp_x", "supp_y", "supp_z",
+                                                    "conf", "lift")),
+                                        _bm._stream_ptr(stream)), "bm_rules_copy")
+        return {k: v[:R] for k, v in out.items()}
+
+    def to_list(self, itemsets=None):
+        """[(z, X, Y, supp_x, supp_y, supp_z, conf, lift)] with X and Y as item tuples;
+        itemsets: the result's to_list() (fetched when not given)."""
+        a = self.arrays()
+        F = itemsets if itemsets is not None else self._result.to_list()
+        out = []
+        for i in range(len(a["z"])):
+            zi = int(a["z"][i])
+            Z = F[zi][0]
+            m = int(a["mask"][i])
+            X = tuple(Z[p] for p in range(len(Z)) if m >> p & 1)
+            Y = tuple(Z[p] for p in range(len(Z)) if not m >> p & 1)
+            out.append((zi, X, Y, int(a["supp_x"][i]), int(a["supp_y"][i]), int(a["supp_z"][i]),
+                        float(a["conf"][i]), float(a["lift"][i])))
+        return out
+
+    def free(self):
+        if self._h:
+            _bm.lib.bm_rules_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def bm_rules_mine(result: Result, min_conf_ppm: int, max_len: int = 0, stream=None) -> Rules:
+    """Association rules X => Y of every itemset of `result` with
+    confidence >= min_conf_ppm / 10^6 (exact integer test)."""
+    h = ctypes.c_void_p()
+    _bm.check(_bm.lib.bm_rules_mine(result._h, min_conf_ppm, max_len, _bm._stream_ptr(stream),
+                                    ctypes.byref(h)), "bm_rules_mine")
+    return Rules(h, result)
 
 
 def options(flags: int = 0, mfma_min_children: int = 0, andpop_chunk_words: int = 0,

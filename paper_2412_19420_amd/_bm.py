@@ -158,6 +158,14 @@ lib.bm_db_free.restype = None
 lib.bm_db_free.argtypes = [_vp]
 lib.bm_result_free.restype = None
 lib.bm_result_free.argtypes = [_vp]
+lib.bm_rules_mine.restype = ctypes.c_int
+lib.bm_rules_mine.argtypes = [_vp, ctypes.c_uint32, ctypes.c_uint32, _vp, ctypes.POINTER(_vp)]
+lib.bm_rules_info.restype = ctypes.c_int
+lib.bm_rules_info.argtypes = [_vp, _u64p]
+lib.bm_rules_copy.restype = ctypes.c_int
+lib.bm_rules_copy.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+lib.bm_rules_free.restype = None
+lib.bm_rules_free.argtypes = [_vp]
 
 
 class BmError(RuntimeError):

@@ -176,6 +176,31 @@ bm_status bm_result_trace(const bm_result* r, float* feats, float* labels, uint6
   });
 }
 
+bm_status bm_rules_mine(const bm_result* r, uint32_t min_conf_ppm, uint32_t max_len, void* stream,
+                        bm_rules** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!r || !out) bm::fail(BM_ERR_INVALID_ARG, "result or out is NULL");
+    *out = bm::rules_mine(r, min_conf_ppm, max_len, as_stream(stream));
+  });
+}
+
+bm_status bm_rules_info(const bm_rules* rs, uint64_t* n_rules) {
+  return guarded([&] {
+    if (!rs) bm::fail(BM_ERR_INVALID_ARG, "rules is NULL");
+    if (n_rules) *n_rules = rs->n;
+  });
+}
+
+bm_status bm_rules_copy(const bm_rules* rs, uint64_t* z_index, uint32_t* ante_mask, uint32_t* supp_x,
+                        uint32_t* supp_y, uint32_t* supp_z, double* conf, double* lift,
+                        void* stream) {
+  return guarded([&] {
+    if (!rs) bm::fail(BM_ERR_INVALID_ARG, "rules is NULL");
+    bm::rules_copy(rs, z_index, ante_mask, supp_x, supp_y, supp_z, conf, lift, as_stream(stream));
+  });
+}
+
 bm_status bm_model_create(uint32_t seed, bm_model** out) {
   if (out) *out = nullptr;
   return guarded([&] {
@@ -259,5 +284,6 @@ void bm_model_free(bm_model* m) { delete m; }
 
 void bm_db_free(bm_db* db) { delete db; }
 void bm_result_free(bm_result* r) { delete r; }
+void bm_rules_free(bm_rules* r) { delete r; }
 
 }  // extern "C"

