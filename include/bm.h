@@ -215,6 +215,21 @@ bm_status bm_item_support(const bm_db* db, uint32_t* out, void* stream);
 bm_status bm_pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* out,
                           void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): bm_pair_support
+ * with every temporary buffer (item list, task lists, the support triangle)
+ * carved from a static 16 MiB scratch array that the library holds on each GPU
+ * it runs on until the process ends; the call makes no hipMalloc, hipFree or
+ * other allocating call.  items (or NULL, meaning all n_items items) and out
+ * (uint32[k*k], as bm_pair_support) must be device memory (else
+ * BM_ERR_INVALID_ARG).  k <= 2048 (BM_ERR_UNSUPPORTED beyond, or if the
+ * database's shape would need more scratch than the array holds).  Results are
+ * those of bm_pair_support.  All calls on one GPU share its scratch array, which
+ * keeps the last call's contents: calls that overlap on one GPU (from several
+ * threads or streams) race and must be serialised by the caller. */
+bm_status bm_pair_support_noalloc(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* out,
+                                  void* stream);
+
 /* Frequent-itemset mining (Section III, Eqs. 1-3 and the recursive extension of
  * frequent prefixes by further column ANDs).  Reports every non-empty itemset X
  * with S(X) >= minsup.  minsup == 0 gives BM_ERR_INVALID_ARG; minsup > n_tx or an

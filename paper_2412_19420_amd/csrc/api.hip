@@ -93,6 +93,14 @@ bm_status bm_pair_support(const bm_db* db, const uint32_t* items, uint32_t k, ui
   });
 }
 
+bm_status bm_pair_support_noalloc(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* out,
+                                  void* stream) {
+  return guarded([&] {
+    if (!db) bm::fail(BM_ERR_INVALID_ARG, "db is NULL");
+    bm::pair_support_noalloc(db, items, k, out, as_stream(stream));
+  });
+}
+
 bm_status bm_mine_ex(const bm_db* db, uint32_t minsup, const bm_options* opt, void* stream,
                      bm_result** out) {
   if (out) *out = nullptr;

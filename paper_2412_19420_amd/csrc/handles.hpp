@@ -98,6 +98,11 @@ std::vector<bm_db*> build_many(uint32_t count, const uint64_t* const* row_ptrs,
                                const uint32_t* const* col_idxs, const uint64_t* ns,
                                const uint32_t* ms, hipStream_t s);
 void pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* out, hipStream_t s);
+// The same with every temporary in the library's static per-device scratch
+// (16 MiB): no allocation; items (or NULL) and out in device memory.
+constexpr uint32_t kNoAllocMaxItems = 2048;
+void pair_support_noalloc(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* out,
+                          hipStream_t s);
 // Mine `count` databases in one level-synchronous pass; one result per database.
 bm_options autotune(const bm_db* const* dbs, const uint32_t* minsups, uint32_t count,
                     const bm_model* sched, const bm_options* base, uint32_t reps, hipStream_t s,

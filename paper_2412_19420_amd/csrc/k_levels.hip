@@ -491,7 +491,35 @@ __global__ void k_expand_pairs(uint32_t k, const uint32_t* __restrict__ items,
   }
 }
 
+struct Words64 {
+  uint32_t w[kWriteWordsMax];
+};
+
+__global__ void k_write_words(uint32_t* __restrict__ dst, Words64 v, uint32_t n) {
+  const uint32_t i = threadIdx.x;
+  if (i < n) dst[i] = v.w[i];
+}
+
+__global__ void k_iota_u32(uint32_t* __restrict__ dst, uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    dst[i] = i;
+}
+
 }  // namespace
+
+void launch_write_words(uint32_t* dst, const uint32_t* words, uint32_t n, hipStream_t s) {
+  if (n == 0) return;
+  Words64 v{};
+  for (uint32_t i = 0; i < n; ++i) v.w[i] = words[i];
+  k_write_words<<<1, kWriteWordsMax, 0, s>>>(dst, v, n);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_iota_u32(uint32_t* dst, uint32_t n, hipStream_t s) {
+  if (n == 0) return;
+  k_iota_u32<<<grid_for(n, kThreads), kThreads, 0, s>>>(dst, n);
+  BM_LAUNCH_CHECK();
+}
 
 void launch_f1_flags(const DbInfo* dbs, uint32_t ndb, const uint64_t* item_base, uint64_t total,
                      uint32_t* flags, hipStream_t s) {

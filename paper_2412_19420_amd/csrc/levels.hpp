@@ -120,6 +120,12 @@ void launch_write_class_tasks(const ClassDesc* cls, uint64_t ncls, const DbInfo*
                               DfsTask* dt, uint32_t level, const uint64_t* ob, Task* tb,
                               const uint64_t* os, Task* ts, hipStream_t s);
 void launch_emit_all(const EmitArgs& a, uint64_t F, hipStream_t s);
+// dst[i] = words[i] for i < n <= kWriteWordsMax; the words travel as a kernel
+// argument (no staging copy).
+constexpr uint32_t kWriteWordsMax = 64;
+void launch_write_words(uint32_t* dst, const uint32_t* words, uint32_t n, hipStream_t s);
+// dst[i] = i for i < n.
+void launch_iota_u32(uint32_t* dst, uint32_t n, hipStream_t s);
 void launch_rebase(const uint64_t* src, uint64_t n, uint64_t base, uint64_t* dst, hipStream_t s);
 void launch_expand_pairs(uint32_t k, const uint32_t* items, const uint32_t* colsum,
                          const uint32_t* tri, uint32_t* out, hipStream_t s);

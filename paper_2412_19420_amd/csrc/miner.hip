@@ -23,6 +23,7 @@
 #include <cstring>
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "dfs.hpp"
@@ -44,6 +45,25 @@ struct Scope {
 };
 thread_local Scope* t_scope = nullptr;
 
+// While set, temporaries are carved from a fixed device region instead of the
+// pool (the allocation-free entry point): bump allocation, 256-byte aligned,
+// nothing returned, a request past the end is an error.
+struct StaticArena {
+  char* base;
+  size_t cap;
+  size_t used;
+};
+thread_local StaticArena* t_arena = nullptr;
+
+void* arena_take(size_t bytes) {
+  StaticArena& a = *t_arena;
+  const size_t at = (a.used + 255) & ~size_t(255);
+  if (at + bytes > a.cap)
+    fail(BM_ERR_UNSUPPORTED, "the call needs more than the %zu bytes of static scratch", a.cap);
+  a.used = at + bytes;
+  return a.base + at;
+}
+
 template <class T>
 struct TBuf {  // temporary device buffer bound to the current call scope
   T* p = nullptr;
@@ -52,6 +72,10 @@ struct TBuf {  // temporary device buffer bound to the current call scope
   TBuf(size_t count, hipStream_t s) { alloc(count, s); }
   void alloc(size_t count, hipStream_t s) {
     n = count;
+    if (t_arena) {
+      p = count ? static_cast<T*>(arena_take(count * sizeof(T))) : nullptr;
+      return;
+    }
     p = count ? static_cast<T*>(dalloc(count * sizeof(T), s)) : nullptr;
     if (p) t_scope->held.push_back(p);
   }
@@ -143,6 +167,12 @@ class CallScope {
 
 template <class T>
 T read_back(const T* dev, hipStream_t s) {
+  if (t_arena) {  // no staging pool: one small copy into the caller's stack
+    T v{};
+    BM_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+    BM_HIP(hipStreamSynchronize(s));
+    return v;
+  }
   T* v = pinned_array<T>(1);
   BM_HIP(hipMemcpyAsync(v, dev, sizeof(T), hipMemcpyDeviceToHost, s));
   BM_HIP(hipStreamSynchronize(s));
@@ -154,6 +184,14 @@ T read_back(const T* dev, hipStream_t s) {
 template <class T>
 void upload(T* dst, const std::vector<T>& src, hipStream_t s) {
   if (src.empty()) return;
+  if (t_arena) {  // no staging pool: small tables travel as kernel arguments
+    static_assert(sizeof(T) % 4 == 0, "tables are whole 32-bit words");
+    const size_t words = src.size() * sizeof(T) / 4;
+    if (words > kWriteWordsMax) fail(BM_ERR_UNSUPPORTED, "table too large for static scratch mode");
+    launch_write_words(reinterpret_cast<uint32_t*>(dst),
+                       reinterpret_cast<const uint32_t*>(src.data()), (uint32_t)words, s);
+    return;
+  }
   T* st = pinned_array<T>(src.size());
   std::memcpy(st, src.data(), src.size() * sizeof(T));
   BM_HIP(hipMemcpyAsync(dst, st, src.size() * sizeof(T), hipMemcpyHostToDevice, s));
@@ -644,8 +682,13 @@ std::vector<bm_db*> build_many(uint32_t count, const uint64_t* const* row_ptrs,
 
 // ------------------------------------------------------------------ pairs
 
-void pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* out,
-                  hipStream_t s) {
+namespace {
+
+// Pair supports of k items.  static_scratch: every temporary comes from the
+// static region (items and out must then be device memory, and nothing is
+// allocated).
+void pair_support_impl(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* out,
+                       hipStream_t s, bool static_scratch) {
   if (k == 0) return;
   if (!out) fail(BM_ERR_INVALID_ARG, "out is NULL");
   if (!items && k != db->m) fail(BM_ERR_INVALID_ARG, "items == NULL requires k == n_items");
@@ -653,9 +696,13 @@ void pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* 
   TBuf<uint32_t> d_items(k, s);
   std::vector<uint32_t> h_items;
   if (!items) {
-    h_items.resize(k);
-    for (uint32_t i = 0; i < k; ++i) h_items[i] = i;
-    upload(d_items.get(), h_items, s);
+    if (static_scratch) {
+      launch_iota_u32(d_items.get(), k, s);
+    } else {
+      h_items.resize(k);
+      for (uint32_t i = 0; i < k; ++i) h_items[i] = i;
+      upload(d_items.get(), h_items, s);
+    }
   } else if (is_device_ptr(items)) {
     BM_HIP(hipMemcpyAsync(d_items.get(), items, (size_t)k * 4, hipMemcpyDeviceToDevice, s));
     TBuf<uint32_t> err(1, s);
@@ -692,6 +739,56 @@ void pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* 
   if (!out_dev)
     BM_HIP(hipMemcpyAsync(out, dst, (size_t)k * k * 4, hipMemcpyDeviceToHost, s));
   BM_HIP(hipStreamSynchronize(s));
+}
+
+// The allocation-free variant's scratch: one copy per GPU, held until the
+// process ends.  Its host-side name is a stand-in, not a device address: host
+// code only ever uses the address hipGetSymbolAddress returns for the current
+// device.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* scratch_of_current_device() {
+  int dev = 0;
+  BM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(BM_ERR_UNSUPPORTED, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    BM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(BM_ERR_DEVICE, "no device address for the static scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+void pair_support(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* out,
+                  hipStream_t s) {
+  pair_support_impl(db, items, k, out, s, false);
+}
+
+void pair_support_noalloc(const bm_db* db, const uint32_t* items, uint32_t k, uint32_t* out,
+                          hipStream_t s) {
+  if (k > kNoAllocMaxItems)
+    fail(BM_ERR_UNSUPPORTED, "k = %u exceeds the allocation-free limit of %u items", k,
+         kNoAllocMaxItems);
+  if (k == 0) return;
+  if (!out || !is_device_ptr(out))
+    fail(BM_ERR_INVALID_ARG, "out must be device memory in the allocation-free call");
+  if (items && !is_device_ptr(items))
+    fail(BM_ERR_INVALID_ARG, "items must be device memory (or NULL) in the allocation-free call");
+  StaticArena arena{static_cast<char*>(scratch_of_current_device()), kScratchBytes, 0};
+  struct Restore {
+    ~Restore() { t_arena = nullptr; }
+  } restore;
+  t_arena = &arena;
+  pair_support_impl(db, items, k, out, s, true);
 }
 
 // ------------------------------------------------------------------ mining
