@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define BM_ABI_VERSION 1u
+#define BM_ABI_VERSION 2u
 #define BM_MAX_LEVELS 64
 
 typedef struct bm_db bm_db;
@@ -74,7 +74,9 @@ enum {
   BM_K_SCHED = 8,     /* cost-model features, prediction and task ordering */
   BM_K_GRAM_MFMA_BIG = 9, /* as BM_K_GRAM_MFMA with 256 x 256 tiles (classes of >= 256 children) */
   BM_K_GRAM_SMALL = 10,   /* MFMA Gram of mid-size classes, one wave per 32 x 32 block pair */
-  BM_K_COUNT = 11
+  BM_K_PROJECT = 11,      /* projected views of big deep classes: prefix row lists and the
+                           * children's columns gathered over them */
+  BM_K_COUNT = 12
 };
 
 /* Statistics of one mining call.  Kernel times are filled only when the call
@@ -124,6 +126,11 @@ typedef struct {
 #define BM_FLAG_TIMING_MAIN 1024u   /* with BM_FLAG_TIMING: events only around the support-counting
                                      * kernels (Gram, AND+popcount, depth-first), not around the
                                      * level bookkeeping, output and scheduling launches */
+#define BM_FLAG_NO_PROJECT 4096u    /* count every class over all n transactions: no projected views
+                                     * (by default a big class of a deep level whose prefix holds
+                                     * few of the transactions is counted over a view: its
+                                     * children's columns gathered over the prefix's
+                                     * transactions; see project_gain) */
 #define BM_FLAG_DEPTH_FIRST 2048u   /* databases with short columns (<= dfs_max_words words): mine
                                      * small subtrees with the depth-first kernel from a work queue.
                                      * Off by default (level by level measured faster there); also
@@ -156,7 +163,11 @@ typedef struct {
                                * kernels write (0 = automatic).  When it overflows the subtree
                                * phase runs again with at least four times the room; a small value
                                * exercises that path and never changes the result */
-  uint32_t reserved[1];
+  uint32_t project_gain;       /* a class on the 128/256-wide MFMA kernels with q children whose
+                               * prefix has support s is counted over a projected view when
+                               * q (n - s) >= project_gain * n: the MFMA work it saves,
+                               * q^2 (n - s), then outweighs gathering q columns (0 = default
+                               * 512; see BM_FLAG_NO_PROJECT) */
 } bm_options;
 
 uint32_t bm_abi_version(void);
@@ -258,8 +269,9 @@ bm_status bm_mine_batch(const bm_db* const* dbs, const uint32_t* minsups, uint32
  * bm_mine_batch on these databases over a coordinate search of the tuning
  * fields of bm_options -- small subtrees level by level / defaults /
  * depth-first on short columns / depth-first everywhere, mfma_min_children,
- * mfma_big_children, split_words, andpop_chunk_words, subset_max_children,
- * dfs_threads, dfs_wave_max_words -- and writes
+ * mfma_big_children, split_words, andpop_chunk_words, project_gain (or no
+ * projected views), subset_max_children, dfs_threads, dfs_wave_max_words --
+ * and writes
  * the fastest combination to *best (base's other flags kept; NULL base =
  * defaults).  Each point is the minimum of `reps` calls (0 = 3); *best_ms
  * (optional) receives its wall time.  No tuning field changes the mined

@@ -24,7 +24,7 @@ from . import _bm
 from ._bm import (BM_K_NAMES, FLAG_ALL_MFMA, FLAG_DEPTH_FIRST, FLAG_DFS_BLOCK_ONLY, FLAG_FP4_MFMA,
                   FLAG_GRAPH,
                   FLAG_INT8_MFMA,
-                  FLAG_LEVELSYNC, FLAG_NO_MFMA,
+                  FLAG_LEVELSYNC, FLAG_NO_MFMA, FLAG_NO_PROJECT,
                   FLAG_SHUFFLE, FLAG_TIMING, FLAG_TIMING_MAIN, FLAG_TRACE, MLP_PARAMS, BmError, BmOptions)
 
 __all__ = [
@@ -32,7 +32,7 @@ __all__ = [
     "bm_mine_ex", "bm_mine_batch", "bm_set_allocator", "bm_release_cached_memory", "Db", "Result", "BmError",
     "options", "FLAG_TIMING", "FLAG_NO_MFMA", "FLAG_ALL_MFMA", "FLAG_GRAPH", "FLAG_TRACE",
     "FLAG_SHUFFLE", "FLAG_LEVELSYNC", "FLAG_FP4_MFMA", "FLAG_INT8_MFMA", "FLAG_DFS_BLOCK_ONLY",
-    "FLAG_TIMING_MAIN", "FLAG_DEPTH_FIRST",
+    "FLAG_TIMING_MAIN", "FLAG_DEPTH_FIRST", "FLAG_NO_PROJECT",
     "LIB_PATH", "Model", "MLP_PARAMS", "bm_autotune",
     "autotune_cached", "options_to_dict", "options_from_dict", "shape_key", "bm_rules_mine", "Rules",
 ]
@@ -237,7 +237,7 @@ def options(flags: int = 0, mfma_min_children: int = 0, andpop_chunk_words: int 
             split_words: int = 0, shuffle_seed: int = 0, dfs_threads: int = 0,
             dfs_max_words: int = 0, mfma_big_children: int = 0,
             dfs_wave_max_words: int = 0, subset_max_children: int = 0,
-            dfs_arena_nodes: int = 0) -> BmOptions:
+            dfs_arena_nodes: int = 0, project_gain: int = 0) -> BmOptions:
     o = BmOptions()
     o.flags = flags
     o.mfma_min_children = mfma_min_children
@@ -250,6 +250,7 @@ def options(flags: int = 0, mfma_min_children: int = 0, andpop_chunk_words: int 
     o.dfs_wave_max_words = dfs_wave_max_words
     o.subset_max_children = subset_max_children
     o.dfs_arena_nodes = dfs_arena_nodes
+    o.project_gain = project_gain
     return o
 
 
@@ -371,7 +372,8 @@ def bm_autotune(dbs, minsups, model=None, base: BmOptions | None = None, reps: i
 
 
 _TUNE_FIELDS = ("flags", "mfma_min_children", "andpop_chunk_words", "split_words", "dfs_threads",
-                "dfs_max_words", "mfma_big_children", "dfs_wave_max_words", "subset_max_children")
+                "dfs_max_words", "mfma_big_children", "dfs_wave_max_words", "subset_max_children",
+                "dfs_arena_nodes", "project_gain")
 
 
 def options_to_dict(o: BmOptions) -> dict:

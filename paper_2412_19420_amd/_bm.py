@@ -31,7 +31,7 @@ lib = ctypes.CDLL(LIB_PATH)
 
 BM_MAX_LEVELS = 64
 BM_K_NAMES = ["build", "colsum", "gram_mfma", "andpop", "andpop_reg", "level", "emit", "dfs",
-              "sched", "gram_mfma_big", "gram_small"]
+              "sched", "gram_mfma_big", "gram_small", "project"]
 BM_K_COUNT = len(BM_K_NAMES)
 
 FLAG_TIMING = 1
@@ -46,6 +46,7 @@ FLAG_INT8_MFMA = 256
 FLAG_DFS_BLOCK_ONLY = 512
 FLAG_TIMING_MAIN = 1024
 FLAG_DEPTH_FIRST = 2048
+FLAG_NO_PROJECT = 4096
 MLP_PARAMS = 4801
 
 STATUS = {0: "BM_OK", 1: "BM_ERR_INVALID_ARG", 2: "BM_ERR_CSR", 3: "BM_ERR_OOM",
@@ -86,7 +87,7 @@ class BmOptions(ctypes.Structure):
         ("dfs_wave_max_words", ctypes.c_uint32),
         ("subset_max_children", ctypes.c_uint32),
         ("dfs_arena_nodes", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 1),
+        ("project_gain", ctypes.c_uint32),
     ]
 
 

@@ -29,7 +29,7 @@ CFLAGS = [
 ]
 SOURCES = ["runtime.hip", "k_build.hip", "k_gram_mfma.hip", "k_gram_big.hip", "k_gram_small.hip", "k_andpop.hip",
            "k_levels.hip",
-           "k_dfs.hip", "k_subsets.hip", "k_mlp.hip", "k_rules.hip", "model.hip", "miner.hip", "autotune.hip", "api.hip"]
+           "k_dfs.hip", "k_subsets.hip", "k_mlp.hip", "k_rules.hip", "k_project.hip", "model.hip", "miner.hip", "autotune.hip", "api.hip"]
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -73,6 +73,14 @@ bm_options autotune(const bm_db* const* dbs, const uint32_t* minsups, uint32_t c
   try_field([](bm_options& o, uint32_t v) { o.mfma_big_children = v; }, {192u, 256u, 512u, 0xffffffffu});
   try_field([](bm_options& o, uint32_t v) { o.split_words = v; }, {0u, 512u, 1024u, 2048u, 4096u});
   try_field([](bm_options& o, uint32_t v) { o.andpop_chunk_words = v; }, {128u, 256u});
+  // projected views of big deep classes: the default cost rule, more eager ones, or none
+  try_field(
+      [](bm_options& o, uint32_t v) {
+        o.flags &= ~BM_FLAG_NO_PROJECT;
+        if (v == 0) o.flags |= BM_FLAG_NO_PROJECT;
+        o.project_gain = v;
+      },
+      {0u, 16u, 64u, 512u});
   if (!(cur.flags & BM_FLAG_LEVELSYNC)) {
     // long columns: small subtrees by subset counting, up to 4, 6 or 8 children, or not at all
     try_field([](bm_options& o, uint32_t v) { o.subset_max_children = v; }, {1u, 4u, 6u, 8u});

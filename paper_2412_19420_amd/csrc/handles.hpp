@@ -89,6 +89,7 @@ struct Tuning {
   bool subsets = false;            // this call mines small subtrees by subset counting
   uint32_t tiny_q = TINY_Q;        // small-class threshold of this call
   uint32_t arena_nodes = 0;        // initial subtree-output arena (0: sized from the task count)
+  uint32_t project_gain = 512;     // big deep classes counted over projected views (0: never)
 };
 Tuning tuning_from(const bm_options* opt);
 

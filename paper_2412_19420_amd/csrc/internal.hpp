@@ -98,7 +98,7 @@ struct ClassDesc {
   uint32_t pre_off;   // offset of P's columns in the prefix-column array
   uint32_t pre_len;   // |P| (0 for the root class of single items)
   uint32_t db;        // database the class belongs to
-  uint32_t pad;
+  uint32_t proj;      // 0, or 1 + index of the class's projected column block (see ProjWork)
 };
 
 // One database of a (batched) mining call, as the kernels see it.
@@ -111,6 +111,29 @@ struct DbInfo {
   const uint32_t* colsum;  // single-item supports
   uint32_t minsup;
   uint32_t m;
+};
+
+// The database view a class kernel reads: the class's database, or, for a
+// projected class, its children's columns re-packed over the transactions that
+// hold the prefix (views[cd.proj - 1]: B = those columns in child order, n = the
+// prefix's support, W/Wp its words; the prefix is already applied).
+__host__ __device__ inline DbInfo class_view(const ClassDesc& cd, const DbInfo* dbs,
+                                             const DbInfo* views) {
+  return cd.proj ? views[cd.proj - 1] : dbs[cd.db];
+}
+// Column of child idx (item = its frequent-item index) in a class's view.
+__host__ __device__ inline uint32_t class_col(const ClassDesc& cd, const DbInfo& v, uint32_t idx,
+                                              uint32_t item) {
+  return cd.proj ? idx : (v.f1 ? v.f1[item] : item);
+}
+
+// One projected class of a level step.  row_off: the supports of the step's
+// earlier projected prefixes summed, i.e. where this class's transactions
+// start when all the step's prefixes' transactions are counted in class order.
+struct ProjWork {
+  uint64_t row_off;
+  uint32_t cls;  // class index in the step
+  uint32_t pad;
 };
 
 // One unit of kernel work: a block pair (bi <= bl) of a class's q x q triangle
@@ -148,6 +171,7 @@ struct ClassArgs {
   const uint32_t* child_item; // item of each child (indexed by class child0 + i)
   const ClassDesc* cls;
   const uint32_t* pre_cols;   // prefix column ids
+  const DbInfo* views;        // projected classes' views (ClassDesc::proj)
   const Task* tasks;
   const uint64_t* ntasks;     // device-side task count
   uint32_t* tri;              // per-class triangles of supports (accumulated atomically)

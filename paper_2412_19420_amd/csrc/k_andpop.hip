@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_andpop(ClassArgs a) {
   for (uint64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
     const Task task = a.tasks[t];
     const ClassDesc cd = a.cls[task.cls];
-    const DbInfo db = a.dbs[cd.db];
+    const DbInfo db = class_view(cd, a.dbs, a.views);
     const uint32_t q = cd.q;
     const uint32_t i0 = (uint32_t)task.bi * AP_BLOCK, l0 = (uint32_t)task.bl * AP_BLOCK;
     const int NI = (int)min<uint32_t>(AP_BLOCK, q - i0);
@@ -63,10 +63,10 @@ __global__ __launch_bounds__(256) void k_andpop(ClassArgs a) {
       uint64_t off = ~0ull;
       if (r < 16 && r < NI) {
         const uint32_t item = a.child_item[cd.child0 + i0 + r];
-        off = (uint64_t)(db.f1 ? db.f1[item] : item) * db.Wp;
+        off = (uint64_t)class_col(cd, db, i0 + r, item) * db.Wp;
       } else if (!diag && r >= 16 && r - 16 < NL) {
         const uint32_t item = a.child_item[cd.child0 + l0 + (r - 16)];
-        off = (uint64_t)(db.f1 ? db.f1[item] : item) * db.Wp;
+        off = (uint64_t)class_col(cd, db, l0 + (r - 16), item) * db.Wp;
       }
       s_col[r] = off;
     }
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_andpop(ClassArgs a) {
     }
 
     const uint32_t* pre = a.pre_cols + cd.pre_off;
-    const uint32_t pre_len = cd.pre_len;
+    const uint32_t pre_len = cd.proj ? 0u : cd.pre_len;  // a view has the prefix applied
     const uint32_t w0 = task.w0, w1 = task.w1;
     const uint32_t nch = (w1 - w0 + TC - 1) / TC;
 
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_andpop_reg(ClassArgs a) {
   for (uint64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
     const Task task = a.tasks[t];
     const ClassDesc cd = a.cls[task.cls];
-    const DbInfo db = a.dbs[cd.db];
+    const DbInfo db = class_view(cd, a.dbs, a.views);
     const int q = (int)cd.q;
     const uint64_t* col[TQ];
 #pragma unroll
@@ -158,11 +158,11 @@ __global__ __launch_bounds__(256) void k_andpop_reg(ClassArgs a) {
       col[i] = db.B;
       if (i < q) {
         const uint32_t item = a.child_item[cd.child0 + i];
-        col[i] = db.B + (uint64_t)(db.f1 ? db.f1[item] : item) * db.Wp;
+        col[i] = db.B + (uint64_t)class_col(cd, db, i, item) * db.Wp;
       }
     }
     const uint32_t* pre = a.pre_cols + cd.pre_off;
-    const uint32_t pre_len = cd.pre_len;
+    const uint32_t pre_len = cd.proj ? 0u : cd.pre_len;  // a view has the prefix applied
     uint32_t acc[TNP];
 #pragma unroll
     for (int p = 0; p < TNP; ++p) acc[p] = 0;

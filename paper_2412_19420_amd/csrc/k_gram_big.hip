@@ -80,7 +80,7 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint32_t* sR,
   for (uint64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
     const Task task = a.tasks[t];
     const ClassDesc cd = a.cls[task.cls];
-    const DbInfo db = a.dbs[cd.db];
+    const DbInfo db = class_view(cd, a.dbs, a.views);
     const uint64_t Wp = db.Wp;
     const uint32_t q = cd.q;
     const uint32_t half = task.bi & 1u;
@@ -99,12 +99,12 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint32_t* sR,
       colp[p] = nullptr;
       if ((p < BNSC || !diag) && idx < q) {
         const uint32_t item = a.child_item[cd.child0 + idx];
-        const uint32_t col = db.f1 ? db.f1[item] : item;
+        const uint32_t col = class_col(cd, db, idx, item);
         colp[p] = db.B + (uint64_t)col * Wp + 2 * sub;
       }
     }
     const uint32_t* pre = a.pre_cols + cd.pre_off;
-    const uint32_t pre_len = cd.pre_len;
+    const uint32_t pre_len = cd.proj ? 0u : cd.pre_len;  // a view has the prefix applied
 
     uint4 reg[NP];
     uint64_t m0 = ~0ull, m1 = ~0ull;

@@ -158,7 +158,7 @@ __device__ __forceinline__ void gram_tiles(const ClassArgs& a, uint32_t* sA, uin
   for (uint64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
     const Task task = a.tasks[t];
     const ClassDesc cd = a.cls[task.cls];
-    const DbInfo db = a.dbs[cd.db];
+    const DbInfo db = class_view(cd, a.dbs, a.views);
     const uint64_t Wp = db.Wp;
     const uint32_t q = cd.q;
     const uint32_t I0 = (uint32_t)task.bi * T, L0 = (uint32_t)task.bl * T;
@@ -178,12 +178,12 @@ __device__ __forceinline__ void gram_tiles(const ClassArgs& a, uint32_t* sA, uin
       colp[p] = nullptr;
       if (p < nload && idx < q) {
         const uint32_t item = a.child_item[cd.child0 + idx];
-        const uint32_t col = db.f1 ? db.f1[item] : item;
+        const uint32_t col = class_col(cd, db, idx, item);
         colp[p] = db.B + (uint64_t)col * Wp + 2 * sub;
       }
     }
     const uint32_t* pre = a.pre_cols + cd.pre_off;
-    const uint32_t pre_len = cd.pre_len;
+    const uint32_t pre_len = cd.proj ? 0u : cd.pre_len;  // a view has the prefix applied
 
     uint4 reg[2 * NS];
     uint64_t m0 = ~0ull, m1 = ~0ull;

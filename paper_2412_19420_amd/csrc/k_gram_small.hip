@@ -73,7 +73,7 @@ __device__ __forceinline__ void small_task(const ClassArgs& a, const Task& task,
   const int r = lane & 31, h = lane >> 5;
   const int sc = lane >> 3, sl = lane & 7;  // staging: column sc + 8 (p & 3), 16-byte slot sl
   const ClassDesc cd = a.cls[task.cls];
-  const DbInfo db = a.dbs[cd.db];
+  const DbInfo db = class_view(cd, a.dbs, a.views);
   const uint64_t Wp = db.Wp;
   const uint32_t q = cd.q;
   const uint32_t I0 = (uint32_t)task.bi * SB, L0 = (uint32_t)task.bl * SB;
@@ -86,12 +86,12 @@ __device__ __forceinline__ void small_task(const ClassArgs& a, const Task& task,
     colp[p] = nullptr;
     if (idx < q) {
       const uint32_t item = a.child_item[cd.child0 + idx];
-      colp[p] = db.B + (uint64_t)(db.f1 ? db.f1[item] : item) * Wp + 2 * sl +
+      colp[p] = db.B + (uint64_t)class_col(cd, db, idx, item) * Wp + 2 * sl +
                 (DIAG ? SKW * (p >> 2) : 0);
     }
   }
   const uint32_t* pre = a.pre_cols + cd.pre_off;
-  const uint32_t pre_len = cd.pre_len;
+  const uint32_t pre_len = cd.proj ? 0u : cd.pre_len;  // a view has the prefix applied
 
   uint4 reg[8];
   uint4 msk[DIAG ? 2 : 1];

@@ -118,7 +118,9 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
     const ClassDesc* __restrict__ cls, const DbInfo* __restrict__ dbs,
     const uint32_t* __restrict__ tri, uint32_t mfma_min_q, uint32_t big_q, uint32_t small_on,
     uint32_t tiny_q, uint32_t* __restrict__ cnt, uint32_t* __restrict__ is_cls,
-    uint64_t* __restrict__ tri_sz, unsigned long long* __restrict__ st) {
+    uint64_t* __restrict__ tri_sz, unsigned long long* __restrict__ st,
+    const uint32_t* __restrict__ supp, uint32_t proj_on, uint32_t* __restrict__ pflag,
+    uint32_t* __restrict__ prows, uint64_t* __restrict__ pwords) {
   __shared__ unsigned long long s_st[NC_COUNT];
   if (threadIdx.x < NC_COUNT) s_st[threadIdx.x] = 0;
   __syncthreads();
@@ -132,8 +134,10 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
   for (uint64_t i = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6; i < n; i += nwaves) {
     const int32_t c = pcls[parent[i]];
     uint32_t kc = 0;
+    uint64_t n_db = 0;
     if (c >= 0) {
       const ClassDesc cd = cls[c];
+      n_db = dbs[cd.db].n;
       const uint64_t li = i - cd.child0;
       if (li + 1 < cd.q) {
         const uint64_t rs = cd.tri_off + tri_index(li, li + 1, cd.q);
@@ -163,6 +167,20 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
       const uint64_t tsz = cl ? (uint64_t)kc * (kc - 1) / 2 : 0ull;
       is_cls[i] = cl ? 1u : 0u;
       tri_sz[i] = tsz;
+      if (proj_on) {
+        // the class's prefix is this node's itemset: its support is the node's
+        const uint32_t sp = supp[i];
+        const bool pj = cl && project_class(kind, kc, sp, n_db, proj_on);
+        pflag[i] = pj ? 1u : 0u;
+        prows[i] = pj ? sp : 0u;
+        pwords[i] = pj ? (uint64_t)kc * view_padded_words(sp) : 0ull;
+        if (pj) {
+          const int b = kind == 3 ? NC_PJ_CAND_B - NC_PJ_CAND_M : 0;
+          loc[NC_PJ_CAND_M + b] += tsz;
+          loc[NC_PJ_WORK_M + b] += (unsigned long long)sp * tsz;
+          loc[NC_PJ_COLS] += kc;
+        }
+      }
       if (cl) {
         loc[ST_CAND_M + kind] += tsz;
         loc[ST_COLS_M + kind] += kc + k;
@@ -290,14 +308,15 @@ __device__ inline ClassWork class_work(const ClassDesc& cd, const DbInfo& d, uin
 // Number of tasks of each class, per kernel.  With dfs set, every small class
 // becomes one depth-first subtree task instead of level-synchronous tasks.
 __global__ void k_class_task_counts(const ClassDesc* __restrict__ cls, uint64_t ncls,
-                                    const DbInfo* __restrict__ dbs, uint32_t mfma_min_q,
+                                    const DbInfo* __restrict__ dbs,
+                                    const DbInfo* __restrict__ views, uint32_t mfma_min_q,
                                     TaskGeom geo, uint32_t dfs, uint32_t* __restrict__ cm,
                                     uint32_t* __restrict__ cv, uint32_t* __restrict__ ct,
                                     uint32_t* __restrict__ cb, uint32_t* __restrict__ cs) {
   for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < ncls;
        c += (uint64_t)gridDim.x * blockDim.x) {
     const ClassDesc cd = cls[c];
-    const ClassWork w = class_work(cd, dbs[cd.db], mfma_min_q, geo);
+    const ClassWork w = class_work(cd, class_view(cd, dbs, views), mfma_min_q, geo);
     const uint32_t nt = w.npairs * w.nsplit;
     cm[c] = w.kind == 0 ? nt : 0u;
     cv[c] = w.kind == 1 ? nt : 0u;
@@ -310,7 +329,8 @@ __global__ void k_class_task_counts(const ClassDesc* __restrict__ cls, uint64_t 
 // Workgroup per class: write its tasks at the scanned offsets (with dfs set, small
 // classes become depth-first subtree tasks whose children are level `level`).
 __global__ void k_write_class_tasks(const ClassDesc* __restrict__ cls, uint64_t ncls,
-                                    const DbInfo* __restrict__ dbs, uint32_t mfma_min_q,
+                                    const DbInfo* __restrict__ dbs,
+                                    const DbInfo* __restrict__ views, uint32_t mfma_min_q,
                                     TaskGeom geo, const uint64_t* __restrict__ om,
                                     const uint64_t* __restrict__ ov, const uint64_t* __restrict__ ot,
                                     Task* __restrict__ tm, Task* __restrict__ tv,
@@ -322,7 +342,7 @@ __global__ void k_write_class_tasks(const ClassDesc* __restrict__ cls, uint64_t 
   const int lane = threadIdx.x;
   for (uint64_t c = blockIdx.x; c < ncls; c += gridDim.x) {
     const ClassDesc cd = cls[c];
-    const ClassWork w = class_work(cd, dbs[cd.db], mfma_min_q, geo);
+    const ClassWork w = class_work(cd, class_view(cd, dbs, views), mfma_min_q, geo);
     if (w.kind == 2 && dt) {
       if (lane == 0) {
         DfsTask k;
@@ -366,10 +386,30 @@ __device__ inline void fill_classes_body(const LevelPost& a, uint64_t t0, uint64
     cd.pre_off = ci * k;
     cd.pre_len = k;
     cd.db = d;
-    cd.pad = 0;
+    cd.proj = 0;
+    DbInfo view = a.dbs[d];
+    if (a.views && a.pflag[i]) {
+      // the projected view: the children's columns over the prefix's rows,
+      // written by the projection kernels before the step's class kernels
+      const uint32_t slot = (uint32_t)a.pslot[i];
+      const uint64_t sp = a.nodesupp[i];
+      cd.proj = slot + 1;
+      view.B = a.vbuf + a.pword_off[i];
+      view.Wp = view_padded_words(sp);
+      view.W = view_words(sp);
+      view.n = sp;
+      view.f1 = nullptr;
+      view.m = q;
+      a.views[slot] = view;
+      ProjWork pw;
+      pw.row_off = a.prow_off[i];
+      pw.cls = ci;
+      pw.pad = 0;
+      a.pwork[slot] = pw;
+    }
     a.ocls[ci] = cd;
     {
-      const ClassWork w = class_work(cd, a.dbs[d], a.mfma_min_q, a.geo);
+      const ClassWork w = class_work(cd, view, a.mfma_min_q, a.geo);
       const uint32_t nt = w.npairs * w.nsplit;
       a.cm[ci] = w.kind == 0 ? nt : 0u;
       a.cv[ci] = w.kind == 1 ? nt : 0u;
@@ -556,11 +596,12 @@ void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const in
                         const ClassDesc* cls, const DbInfo* dbs, const uint32_t* tri,
                         uint32_t mfma_min_q, uint32_t big_q, uint32_t small_on, uint32_t tiny_q,
                         uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz, unsigned long long* st,
-                        hipStream_t s) {
+                        const uint32_t* supp, uint32_t proj_on, uint32_t* pflag, uint32_t* prows,
+                        uint64_t* pwords, hipStream_t s) {
   if (n == 0) return;
   k_node_counts<<<grid_for(n, kThreads / 64, 4096), kThreads, 0, s>>>(
       n, k, parent, pcls, cls, dbs, tri, mfma_min_q, big_q, small_on, tiny_q, cnt, is_cls, tri_sz,
-      st);
+      st, supp, proj_on, pflag, prows, pwords);
   BM_LAUNCH_CHECK();
 }
 
@@ -574,23 +615,26 @@ void launch_level_post(LevelPost a, hipStream_t s) {
 }
 
 void launch_class_task_counts(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs,
-                              uint32_t mfma_min_q, const TaskGeom& geo, bool dfs, uint32_t* cm,
-                              uint32_t* cv, uint32_t* ct, uint32_t* cb, uint32_t* cs, hipStream_t s) {
+                              const DbInfo* views, uint32_t mfma_min_q, const TaskGeom& geo,
+                              bool dfs, uint32_t* cm, uint32_t* cv, uint32_t* ct, uint32_t* cb,
+                              uint32_t* cs, hipStream_t s) {
   if (ncls == 0) return;
-  k_class_task_counts<<<grid_for(ncls, kThreads), kThreads, 0, s>>>(cls, ncls, dbs, mfma_min_q, geo,
+  k_class_task_counts<<<grid_for(ncls, kThreads), kThreads, 0, s>>>(cls, ncls, dbs, views,
+                                                                     mfma_min_q, geo,
                                                                      dfs ? 1u : 0u, cm, cv, ct, cb,
                                                                      cs);
   BM_LAUNCH_CHECK();
 }
 
 void launch_write_class_tasks(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs,
-                              uint32_t mfma_min_q, const TaskGeom& geo, const uint64_t* om,
+                              const DbInfo* views, uint32_t mfma_min_q, const TaskGeom& geo,
+                              const uint64_t* om,
                               const uint64_t* ov, const uint64_t* ot, Task* tm, Task* tv, Task* tt,
                               DfsTask* dt, uint32_t level, const uint64_t* ob, Task* tb,
                               const uint64_t* os, Task* ts, hipStream_t s) {
   if (ncls == 0) return;
   k_write_class_tasks<<<grid_for(ncls, 1), kThreads, 0, s>>>(
-      cls, ncls, dbs, mfma_min_q, geo, om, ov, ot, tm, tv, tt, dt, level, ob, tb, os, ts);
+      cls, ncls, dbs, views, mfma_min_q, geo, om, ov, ot, tm, tv, tt, dt, level, ob, tb, os, ts);
   BM_LAUNCH_CHECK();
 }
 

@@ -50,8 +50,31 @@ struct TaskGeom {
 enum { ST_CAND_M = 0, ST_CAND_V, ST_CAND_T, ST_CAND_B, ST_CAND_S, ST_COLS_M, ST_COLS_V, ST_COLS_T,
        ST_COLS_B, ST_COLS_S, ST_CLS_M, ST_CLS_V, ST_CLS_T, ST_CLS_B, ST_CLS_S, ST_COUNT };
 // The node-count kernel also sums the next step's task-count bounds: 128-wide
-// tile pairs, 16-wide block pairs and tiny classes (sizes for the task lists).
-enum { NC_PAIRS_M = ST_COUNT, NC_PAIRS_V, NC_TINY, NC_COUNT };
+// tile pairs, 16-wide block pairs and tiny classes (sizes for the task lists),
+// and for the projected classes on the 128-wide (M) and 256-wide (B) kernels
+// their candidates and work (the prefix's support times the class's
+// candidates), and their children.
+enum { NC_PAIRS_M = ST_COUNT, NC_PAIRS_V, NC_TINY, NC_PJ_CAND_M, NC_PJ_WORK_M, NC_PJ_CAND_B,
+       NC_PJ_WORK_B, NC_PJ_COLS, NC_COUNT };
+
+// Whether a class of q children whose prefix has support s_prefix (in a
+// database of n transactions) is projected: its children's columns are
+// re-packed over the prefix's transactions before counting.  Only classes on
+// the 128- and 256-wide MFMA kernels, where the contraction reads every column
+// many times, and only when the work it saves, about q^2 (n - s) MFMA
+// operations, outweighs gathering the q columns (about q n / 64 word loads):
+// q (n - s) >= gain * n.  gain == 0: never.
+__host__ __device__ inline bool project_class(int kind, uint32_t q, uint64_t s_prefix, uint64_t n,
+                                              uint32_t gain) {
+  return gain && (kind == 0 || kind == 3) && s_prefix < n &&
+         (double)q * (double)(n - s_prefix) >= (double)gain * (double)n;
+}
+// Words of a projected view over s transactions (unpadded, padded).
+__host__ __device__ inline uint64_t view_words(uint64_t s) { return (s + 63) / 64; }
+__host__ __device__ inline uint64_t view_padded_words(uint64_t s) {
+  const uint64_t w = (view_words(s) + 63) / 64 * 64;
+  return w ? w : 64;
+}
 
 void launch_f1_flags(const DbInfo* dbs, uint32_t ndb, const uint64_t* item_base, uint64_t total,
                      uint32_t* flags, hipStream_t s);
@@ -69,11 +92,16 @@ void launch_gather_idx(const uint64_t* arr, const uint64_t* idx, uint32_t k, uin
 // whether it becomes a class (is_cls) and its candidate triangle size
 // (tri_sz); sums the step statistics and the task-count bounds into
 // st[0, NC_COUNT) (zeroed by the caller).
+// With proj_on (the projection gain, 0 = off), also per node: whether its
+// class will be projected (pflag),
+// the length of its prefix's row list (prows: the node's support) and the
+// words of its view (pwords: children x padded view words), else zeros.
 void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const int32_t* pcls,
                         const ClassDesc* cls, const DbInfo* dbs, const uint32_t* tri,
                         uint32_t mfma_min_q, uint32_t big_q, uint32_t small_on, uint32_t tiny_q,
                         uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz, unsigned long long* st,
-                        hipStream_t s);
+                        const uint32_t* supp, uint32_t proj_on, uint32_t* pflag, uint32_t* prows,
+                        uint64_t* pwords, hipStream_t s);
 // Arguments of the launch between two level steps (k_level_post): node i < n
 // of level k writes its frequent extensions into the next level and, if it
 // has at least two, its class of the next step and that class's task counts
@@ -108,18 +136,43 @@ struct LevelPost {
   uint32_t mfma_min_q, dfs;
   uint32_t *cm, *cv, *ct, *cb, *cs;
   LevelPtrs lv;
+  // projected classes (views == NULL: none): the node-count kernel's flags,
+  // scanned into slot numbers, row-list offsets and view-word offsets
+  const uint32_t* pflag;
+  const uint64_t* pslot;
+  const uint64_t* prow_off;
+  const uint64_t* pword_off;
+  const uint32_t* nodesupp;  // supports of the level-k nodes (the prefixes)
+  uint64_t* vbuf;            // the step's view words
+  DbInfo* views;
+  ProjWork* pwork;
 };
 void launch_level_post(LevelPost a, hipStream_t s);
 void launch_class_task_counts(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs,
-                              uint32_t mfma_min_q, const TaskGeom& geo, bool dfs, uint32_t* cm,
-                              uint32_t* cv, uint32_t* ct, uint32_t* cb, uint32_t* cs, hipStream_t s);
+                              const DbInfo* views, uint32_t mfma_min_q, const TaskGeom& geo,
+                              bool dfs, uint32_t* cm, uint32_t* cv, uint32_t* ct, uint32_t* cb,
+                              uint32_t* cs, hipStream_t s);
 struct DfsTask;
 void launch_write_class_tasks(const ClassDesc* cls, uint64_t ncls, const DbInfo* dbs,
-                              uint32_t mfma_min_q, const TaskGeom& geo, const uint64_t* om,
+                              const DbInfo* views, uint32_t mfma_min_q, const TaskGeom& geo,
+                              const uint64_t* om,
                               const uint64_t* ov, const uint64_t* ot, Task* tm, Task* tv, Task* tt,
                               DfsTask* dt, uint32_t level, const uint64_t* ob, Task* tb,
                               const uint64_t* os, Task* ts, hipStream_t s);
 void launch_emit_all(const EmitArgs& a, uint64_t F, hipStream_t s);
+// Projected views of a step's nprj classes (k_project.hip): popcounts of each
+// prefix over 1,024-word chunks (cnt_tmp: nprj x view_chunks(Wmax) counts),
+// then, from their exclusive scan (off_tmp, offsets counted from the first
+// class's first row, so a class's own rows start at its ProjWork::row_off),
+// the children's columns compressed into the (zeroed) views.
+uint64_t view_chunks(uint64_t Wmax);
+void launch_project_count(const ProjWork* pw, uint32_t nprj, const ClassDesc* cls,
+                          const DbInfo* dbs, const uint32_t* pre_cols, uint64_t Wmax,
+                          uint32_t* cnt_tmp, hipStream_t s);
+void launch_project_compact(const ProjWork* pw, uint32_t nprj, const ClassDesc* cls,
+                            const DbInfo* dbs, const DbInfo* views, const uint32_t* pre_cols,
+                            const uint32_t* child_item, uint64_t Wmax, const uint64_t* off_tmp,
+                            hipStream_t s);
 // dst[i] = words[i] for i < n <= kWriteWordsMax; the words travel as a kernel
 // argument (no staging copy).
 constexpr uint32_t kWriteWordsMax = 64;

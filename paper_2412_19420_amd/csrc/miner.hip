@@ -318,6 +318,12 @@ struct StepWork {
   uint64_t ndt = 0;
   TBuf<uint32_t> ccount[5];   // tasks per class per kind (128, LDS, tiny, 256, 32-wide)
   bool counts_ready = false;  // ccount already written (by the previous step's post kernel)
+  // projected classes (written by the previous step's post kernel)
+  uint64_t nproj = 0, proj_rows = 0, proj_words = 0, proj_cols = 0;
+  TBuf<DbInfo> views;
+  TBuf<ProjWork> pwork;
+  TBuf<uint64_t> vbuf;
+  double pj_cand[2] = {0, 0}, pj_work[2] = {0, 0};  // 128-wide, 256-wide projected classes
 };
 
 // Task lists of a step's classes: counts per class on the device, scanned
@@ -341,7 +347,8 @@ void prepare_tasks(StepWork& w, const DbInfo* ddb, uint64_t Wmax, uint64_t pairs
   }
   if (!w.counts_ready) {  // else the previous step's k_level_post wrote them
     for (auto& c : w.ccount) c.alloc(w.ncls, s);
-    launch_class_task_counts(w.cls.get(), w.ncls, ddb, tu.mfma_min_q, g, dfs, w.ccount[0].get(),
+    launch_class_task_counts(w.cls.get(), w.ncls, ddb, w.views.get(), tu.mfma_min_q, g, dfs,
+                             w.ccount[0].get(),
                              w.ccount[1].get(), w.ccount[2].get(), w.ccount[3].get(),
                              w.ccount[4].get(), s);
   }
@@ -360,28 +367,52 @@ void prepare_tasks(StepWork& w, const DbInfo* ddb, uint64_t Wmax, uint64_t pairs
   w.tt.alloc(w.ub_t, s);
   w.tb.alloc(w.ub_b, s);
   w.ts.alloc(w.ub_s, s);
-  launch_write_class_tasks(w.cls.get(), w.ncls, ddb, tu.mfma_min_q, g, w.om.get(), w.ov.get(),
+  launch_write_class_tasks(w.cls.get(), w.ncls, ddb, w.views.get(), tu.mfma_min_q, g, w.om.get(),
+                           w.ov.get(),
                            w.ot.get(), w.tm.get(), w.tv.get(), w.tt.get(), dfs ? w.dt.get() : nullptr,
                            level, w.ob.get(), w.tb.get(), w.os.get(), w.ts.get(), s);
 }
 
+// Views of the step's projected classes: each child column compressed by its
+// class's prefix tidset.
+void project_views(StepWork& w, const DbInfo* ddb, const uint32_t* child_item, uint64_t Wmax,
+                   double nW, KTimer& tm, hipStream_t s) {
+  const uint32_t np = (uint32_t)w.nproj;
+  const uint64_t nc = (uint64_t)np * view_chunks(Wmax);
+  tm.begin(BM_K_PROJECT);
+  TBuf<uint32_t> cnt(nc, s);
+  TBuf<uint64_t> off(nc + 1, s);
+  launch_fill_u64(w.vbuf.get(), 0, w.proj_words, s);
+  launch_project_count(w.pwork.get(), np, w.cls.get(), ddb, w.pre.get(), Wmax, cnt.get(), s);
+  scan32(cnt.get(), off.get(), nc, s);
+  launch_project_compact(w.pwork.get(), np, w.cls.get(), ddb, w.views.get(), w.pre.get(),
+                         child_item, Wmax, off.get(), s);
+  // algorithmic bytes: the children's columns read once, the views written
+  tm.end(8.0 * nW * (double)w.proj_cols + 8.0 * (double)w.proj_words, 0.0);
+}
+
 void run_class_kernels(const DbInfo* ddb, const uint32_t* child_item, const StepWork& w,
                        const Tuning& tu, double nW, double nN, KTimer& tm, hipStream_t s) {
-  ClassArgs a{ddb, child_item, w.cls.get(), w.pre.get(), nullptr, nullptr, w.tri.get()};
+  ClassArgs a{ddb, child_item, w.cls.get(), w.pre.get(), w.views.get(), nullptr, nullptr,
+              w.tri.get()};
   const uint64_t ncu = (uint64_t)cu_count();
+  // algorithmic ops of a projected class: 2 supp(P) per candidate pair
+  auto gram_ops = [&](int kind, int pj) {
+    return 2.0 * (((double)w.st[ST_CAND_M + kind] - w.pj_cand[pj]) * nN + w.pj_work[pj]);
+  };
   if (w.ub_b && w.st[ST_CLS_B]) {
     a.tasks = w.tb.get();
     a.ntasks = w.ob.get() + w.ncls;
     tm.begin(BM_K_GRAM_MFMA_BIG);
     launch_gram_mfma_big(a, (uint32_t)std::min<uint64_t>(w.ub_b, ncu * 4), tu.mfma_fp4, s);
-    tm.end(8.0 * nW * (double)w.st[ST_COLS_B], 2.0 * (double)w.st[ST_CAND_B] * nN);
+    tm.end(8.0 * nW * (double)w.st[ST_COLS_B], gram_ops(3, 1));
   }
   if (w.ub_m && w.st[ST_CLS_M]) {
     a.tasks = w.tm.get();
     a.ntasks = w.om.get() + w.ncls;
     tm.begin(BM_K_GRAM_MFMA);
     launch_gram_mfma(a, (uint32_t)std::min<uint64_t>(w.ub_m, ncu * 4), tu.mfma_fp4, s);
-    tm.end(8.0 * nW * (double)w.st[ST_COLS_M], 2.0 * (double)w.st[ST_CAND_M] * nN);
+    tm.end(8.0 * nW * (double)w.st[ST_COLS_M], gram_ops(0, 0));
   }
   if (w.ub_s && w.st[ST_CLS_S]) {
     a.tasks = w.ts.get();
@@ -475,6 +506,8 @@ Tuning tuning_from(const bm_options* opt) {
     t.subset_q = opt->subset_max_children == 1 ? 0u : opt->subset_max_children;
   }
   t.arena_nodes = opt->dfs_arena_nodes;
+  if (opt->project_gain) t.project_gain = opt->project_gain;
+  if (opt->flags & BM_FLAG_NO_PROJECT) t.project_gain = 0;
   if (opt->flags & BM_FLAG_FP4_MFMA) t.mfma_fp4 = true;
   if (opt->flags & BM_FLAG_INT8_MFMA) t.mfma_fp4 = false;
   if (opt->flags & BM_FLAG_NO_MFMA) {
@@ -808,6 +841,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
   // the support-counting kernels; the rest only without BM_FLAG_TIMING_MAIN
   constexpr uint32_t kMainKinds = (1u << BM_K_BUILD) | (1u << BM_K_GRAM_MFMA) |
                                   (1u << BM_K_GRAM_MFMA_BIG) | (1u << BM_K_GRAM_SMALL) |
+                                  (1u << BM_K_PROJECT) |
                                   (1u << BM_K_ANDPOP) | (1u << BM_K_ANDPOP_REG) | (1u << BM_K_DFS);
   KTimer tm(!(flags & BM_FLAG_TIMING) ? 0u
             : (flags & BM_FLAG_TIMING_MAIN) ? kMainKinds
@@ -940,6 +974,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         // every class of this step is a deferred subtree: no level-synchronous
         // level k + 1, so neither node counts nor a synchronisation are needed
         if (ls_cand == 0) break;
+        if (w->nproj) project_views(*w, ddb_p, L[k].item.get(), Wmax, nW, tm, s);
         run_class_kernels(ddb_p, L[k].item.get(), *w, tu, nW, nN, tm, s);
 
         tm.begin(BM_K_LEVEL);
@@ -949,22 +984,45 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         uint64_t* dst64 = reinterpret_cast<uint64_t*>(dst);
         TBuf<uint32_t> cnt(nk, s), iscls(nk, s);
         TBuf<uint64_t> trisz(nk, s);
+        // projected classes of the next step: flags, row-list and view sizes per node
+        const bool proj = tu.project_gain != 0;
+        TBuf<uint32_t> pflag, prows;
+        TBuf<uint64_t> pwords;
+        if (proj) {
+          pflag.alloc(nk, s);
+          prows.alloc(nk, s);
+          pwords.alloc(nk, s);
+        }
         launch_node_counts(nk, k, L[k].parent.get(), pcls_prev.get(), w->cls.get(), ddb_p,
                            w->tri.get(), tu.mfma_min_q, tu.mfma_big_q, tu.mfma_small ? 1u : 0u,
-                           tu.tiny_q, cnt.get(), iscls.get(), trisz.get(), dst, s);
+                           tu.tiny_q, cnt.get(), iscls.get(), trisz.get(), dst,
+                           L[k].supp.get(), proj ? tu.project_gain : 0u, pflag.get(), prows.get(),
+                           pwords.get(),
+                           s);
         L[k].cstart.alloc(nk + 1, s);
         TBuf<uint64_t> clspos(nk + 1, s), trioff(nk + 1, s);
-        const void* ins[3] = {cnt.get(), iscls.get(), trisz.get()};
-        const bool is64[3] = {false, false, true};
-        uint64_t* outs[3] = {L[k].cstart.get(), clspos.get(), trioff.get()};
-        // totals: next level size, classes, candidates; then the counters
-        uint64_t* tot = pinned_array<uint64_t>(3 + NC_COUNT);
-        scan_many_tot(ins, is64, outs, 3, nk, mapped(tot), dst64, NC_COUNT, s);
+        TBuf<uint64_t> pslot, prow_off, pword_off;
+        if (proj) {
+          pslot.alloc(nk + 1, s);
+          prow_off.alloc(nk + 1, s);
+          pword_off.alloc(nk + 1, s);
+        }
+        const void* ins[6] = {cnt.get(), iscls.get(), trisz.get(), pflag.get(), prows.get(),
+                              pwords.get()};
+        const bool is64[6] = {false, false, true, false, false, true};
+        uint64_t* outs[6] = {L[k].cstart.get(), clspos.get(), trioff.get(), pslot.get(),
+                             prow_off.get(), pword_off.get()};
+        const int nscan = proj ? 6 : 3;
+        // totals: next level size, classes, candidates (and projected classes,
+        // their rows and view words); then the counters
+        uint64_t* tot = pinned_array<uint64_t>(6 + NC_COUNT);
+        scan_many_tot(ins, is64, outs, nscan, nk, mapped(tot), dst64, NC_COUNT, s);
         tm.end();
         BM_HIP(hipStreamSynchronize(s));
         st.host_syncs++;
         const uint64_t n_next = tot[0], ncls = tot[1], Tn = tot[2];
-        const uint64_t PM = tot[3 + NC_PAIRS_M], PV = tot[3 + NC_PAIRS_V], PT = tot[3 + NC_TINY];
+        const uint64_t* stt = tot + nscan;  // the step counters
+        const uint64_t PM = stt[NC_PAIRS_M], PV = stt[NC_PAIRS_V], PT = stt[NC_TINY];
         if (n_next == 0) break;
         if (k + 1 > BM_MAX_LEVELS)
           fail(BM_ERR_UNSUPPORTED, "frequent itemsets longer than %d items", BM_MAX_LEVELS);
@@ -1004,7 +1062,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         TBuf<int32_t> pcls_k(nk, s);
         nw->T = Tn;
         nw->tri.alloc(Tn, s);
-        for (int j = 0; j < ST_COUNT; ++j) nw->st[j] = tot[3 + j];
+        for (int j = 0; j < ST_COUNT; ++j) nw->st[j] = stt[j];
         lp.k = k;
         lp.cnt = cnt.get();
         lp.cls_pos = clspos.get();
@@ -1028,6 +1086,30 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         for (uint32_t j = 1; j <= k; ++j) {
           lp.lv.item[j] = L[j].item.get();
           lp.lv.parent[j] = L[j].parent.get();
+        }
+        if (proj && tot[3]) {
+          // views of the next step's projected classes: level_post writes their
+          // descriptors, the projection kernels fill them before the class kernels
+          if (tot[3] > 0xffffffffull) fail(BM_ERR_UNSUPPORTED, "too many projected classes");
+          nw->nproj = tot[3];
+          nw->proj_rows = tot[4];
+          nw->proj_words = tot[5];
+          nw->proj_cols = stt[NC_PJ_COLS];
+          nw->pj_cand[0] = (double)stt[NC_PJ_CAND_M];
+          nw->pj_work[0] = (double)stt[NC_PJ_WORK_M];
+          nw->pj_cand[1] = (double)stt[NC_PJ_CAND_B];
+          nw->pj_work[1] = (double)stt[NC_PJ_WORK_B];
+          nw->views.alloc(nw->nproj, s);
+          nw->pwork.alloc(nw->nproj, s);
+          nw->vbuf.alloc(nw->proj_words, s);
+          lp.pflag = pflag.get();
+          lp.pslot = pslot.get();
+          lp.prow_off = prow_off.get();
+          lp.pword_off = pword_off.get();
+          lp.nodesupp = L[k].supp.get();
+          lp.vbuf = nw->vbuf.get();
+          lp.views = nw->views.get();
+          lp.pwork = nw->pwork.get();
         }
         launch_level_post(lp, s);
         prepare_tasks(*nw, ddb_p, Wmax, PM, PV, PT, tu, tu.dfs, k + 1, s);

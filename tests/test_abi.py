@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol():
 def test_host_only_entry_points():
     lib = ctypes.CDLL(LIB)
     lib.bm_abi_version.restype = ctypes.c_uint32
-    assert lib.bm_abi_version() == 1
+    assert lib.bm_abi_version() == 2
     lib.bm_status_string.restype = ctypes.c_char_p
     lib.bm_status_string.argtypes = [ctypes.c_int]
     assert lib.bm_status_string(0) == b"ok"

@@ -162,6 +162,8 @@ def test_mine_matches_brute_force(bm, seed):
                     bm.options(flags=bm.FLAG_ALL_MFMA | bm.FLAG_INT8_MFMA, mfma_big_children=2),
                     bm.options(flags=bm.FLAG_ALL_MFMA | bm.FLAG_FP4_MFMA),
                     bm.options(flags=bm.FLAG_ALL_MFMA | bm.FLAG_FP4_MFMA, mfma_big_children=2),
+                    # every deep class on MFMA counted over a projected view
+                    bm.options(flags=bm.FLAG_ALL_MFMA, project_gain=1),
                     # subset counting of small subtrees (more than one word per column)
                     bm.options(dfs_max_words=1),
                     bm.options(flags=bm.FLAG_NO_MFMA, dfs_max_words=1, subset_max_children=8)]
@@ -565,3 +567,42 @@ def test_fp4_and_int8_identical_on_full_dense(bm):
     a = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_INT8_MFMA)).arrays()
     b = bm.bm_mine_ex(h, db.minsup, bm.options(bm.FLAG_FP4_MFMA)).arrays()
     assert_same(a, b)
+
+
+# ------------------------------------------------------------ projected views
+
+def _stats_proj(r):
+    st = r.stats()
+    return st["kernel_launches"]["project"]
+
+
+@pytest.mark.parametrize("case", ["t40_reduced", "quest", "dense_reduced", "quest_all_mfma"])
+def test_projected_views_exact(bm, case):
+    # big classes of deep levels counted over their prefix's rows only: the
+    # same arrays as the oracle, with the views on (default) and off
+    if case == "t40_reduced":
+        db, opts = gen.make_config(5, scale=0.05), {}
+    elif case == "quest":
+        db, opts = gen.make_config(2), {}
+    elif case == "dense_reduced":
+        db, opts = gen.make_config(3, scale=0.05), {"mfma_min_children": 16}
+    else:
+        db, opts = gen.make_config(2, scale=0.3), {"flags": bm.FLAG_ALL_MFMA}
+    print(f"projected views {case}: n={db.n} m={db.m} minsup={db.minsup}", flush=True)
+    _, want, cands = oracle_arrays(db, db.minsup)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    flags = opts.pop("flags", 0)
+    # gain 1: every big-kernel class whose prefix misses a transaction is projected
+    on = bm.bm_mine_ex(h, db.minsup, bm.options(flags | bm.FLAG_TIMING | bm.FLAG_LEVELSYNC,
+                                                project_gain=1, **opts))
+    off = bm.bm_mine_ex(h, db.minsup, bm.options(flags | bm.FLAG_NO_PROJECT | bm.FLAG_LEVELSYNC,
+                                                 **opts))
+    assert_same(on.arrays(), want)
+    assert_same(off.arrays(), want)
+    assert on.stats()["candidates_total"] == cands
+    print(f"projection launches: {_stats_proj(on)}", flush=True)
+    assert _stats_proj(on) > 0, "no class was projected"
+    # and with the default small-subtree routing and projection rule
+    assert_same(bm.bm_mine_ex(h, db.minsup, bm.options(flags, **opts)).arrays(), want)
+    assert_same(bm.bm_mine_ex(h, db.minsup, bm.options(flags, project_gain=1, **opts)).arrays(),
+                want)
