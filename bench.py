@@ -497,6 +497,116 @@ def run_single(args, bm, torch, dev, workload, steps, warmup, sched="none", extr
     return out
 
 
+def table_sweep(bm, torch, reps: int = 5) -> dict:
+    """The paper's Table 1/2 measurements on its kind of data: a basket stand-in
+    for Groceries (169 items, Zipf item popularity), mined at thresholds 1-5% on
+    the first n = 2,000 .. 10,000 transactions.  Per point: build + mine wall
+    time on the GPU (median of `reps`), frequent itemsets found, peak device
+    memory the library held (its allocations routed through a counting
+    allocator), the bitset matrix size, the mean support of the frequent
+    itemsets (Table 2's measure), the C++ oracle's time, and whether the GPU
+    result equals the oracle's.  Context only: the data, the subsets and the
+    machine all differ from the paper's."""
+    import gc
+    import gen
+    from oracle import cpp as ocpp
+    full = gen.make_config(1)
+    stream = torch.cuda.current_stream()
+    live, peak = {}, [0, 0]
+
+    def alloc(size, _s):
+        t = torch.empty(size, dtype=torch.uint8, device="cuda")
+        live[t.data_ptr()] = t
+        peak[0] += size
+        peak[1] = max(peak[1], peak[0])
+        return t.data_ptr()
+
+    def free(ptr, _s):
+        t = live.pop(ptr, None)
+        if t is not None:
+            peak[0] -= t.numel()
+
+    gc.collect()
+    try:
+        bm.bm_set_allocator(alloc, free)
+        counted = True
+    except bm.BmError:
+        counted = False  # a handle is still alive: no memory figures
+    points = []
+    try:
+        for n in (2000, 4000, 6000, 8000, 10000):
+            rp = full.row_ptr[:n + 1].copy()
+            ci = full.col_idx[:int(rp[-1])].copy()
+            o = ocpp.OracleDb(rp, ci, n, full.m)
+            for pct in (1, 2, 3, 4, 5):
+                minsup = gen.minsup_from_ppm(pct * 10_000, n)
+                t0 = time.perf_counter()
+                want = o.mine_arrays(minsup)
+                oracle_ms = 1e3 * (time.perf_counter() - t0)
+                times = []
+                for _ in range(reps):
+                    peak[1] = peak[0]
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    h = bm.bm_build(rp, ci, n, full.m, stream=stream)
+                    r = bm.bm_mine(h, minsup, stream=stream)
+                    got = r.arrays()
+                    times.append(1e3 * (time.perf_counter() - t1))
+                    matrix_b = h.info()[2] * full.m * 8  # padded words x items
+                    del h, r
+                same = all(np.array_equal(a.astype(np.int64), b.astype(np.int64))
+                           for a, b in zip(got, want[:3]))
+                supp = got[2].astype(np.float64)
+                points.append({
+                    "threshold_pct": pct, "n": n, "minsup": minsup,
+                    "gpu_build_mine_ms": round(float(np.median(times)), 3),
+                    "frequent_itemsets": int(len(supp)),
+                    "peak_device_mb": round(peak[1] / 2**20, 3) if counted else None,
+                    "matrix_mb": round(matrix_b / 2**20, 3) if matrix_b else None,
+                    "avg_support_pct": round(100.0 * float(supp.mean()) / n, 3) if len(supp) else None,
+                    "oracle_ms": round(oracle_ms, 3), "equals_oracle": bool(same),
+                    "table1_row": pct * 2000 == n})
+    finally:
+        gc.collect()
+        if counted:
+            bm.bm_set_allocator(None, None)
+    paper = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_tables.json")))
+    return {"data": "basket stand-in (10,000 x 169, Zipf 1.1), first n rows; thresholds as "
+                    "minsup = ceil(pct * n / 100), frequent iff supp >= minsup",
+            "points": points, "paper": {"table1": paper["table1"], "table2": paper["table2"],
+                                        "hardware": "not stated"}}
+
+
+def blocked_run(bm, torch, workload: int = 3, block_rows: int = 250_000, reps: int = 2) -> dict:
+    """Out-of-core mining of a workload from its host CSR, block_rows transactions
+    on the device at a time (every level re-reads the CSR over the host link),
+    against in-core build + mine from the same host CSR."""
+    import gen
+    db = gen.make_config(workload)
+    t_blk, t_in = [], []
+    res = None
+    for _ in range(reps + 1):  # the first call warms the pool
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = bm.bm_mine_blocked(db.row_ptr, db.col_idx, db.n, db.m, db.minsup, block_rows)
+        torch.cuda.synchronize()
+        t_blk.append(1e3 * (time.perf_counter() - t0))
+        res = r.info()
+        t0 = time.perf_counter()
+        h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+        r2 = bm.bm_mine(h, db.minsup)
+        torch.cuda.synchronize()
+        t_in.append(1e3 * (time.perf_counter() - t0))
+        assert r2.info() == res
+        del h, r, r2
+    return {"workload": WORKLOADS[workload], "block_rows": block_rows,
+            "blocks": -(-db.n // block_rows), "frequent_itemsets": res[0],
+            "blocked_ms": round(float(np.median(t_blk[1:])), 3),
+            "in_core_build_mine_ms": round(float(np.median(t_in[1:])), 3),
+            "note": "both from host CSR (upload included); the blocked run re-reads the CSR "
+                    "over the host link once per level"}
+
+
 def _secondary(args, bm, torch, dev):
     """Shorter runs of the batched and the T40-style workloads, for the record."""
     sec = {}
@@ -537,6 +647,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the shorter batched and T40-style runs after the headline")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only the Table 1/2-style sweep (threshold x transactions) as JSON")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--mfma-min-children", type=int, default=0)
     ap.add_argument("--split-words", type=int, default=0)
@@ -576,6 +688,10 @@ def main():
 
     import paper_2412_19420_amd as bm
 
+    if args.sweep:
+        print(json.dumps(table_sweep(bm, torch)), flush=True)
+        return
+
     global WORKLOAD
     WORKLOAD = args.workload
     if args.workload == 4:
@@ -587,6 +703,8 @@ def main():
     if not args.no_secondary and args.workload == 3:
         WORKLOAD = None  # traffic records belong to the headline workload
         out["config"]["secondary"] = _secondary(args, bm, torch, dev)
+        out["config"]["secondary"]["table_sweep"] = table_sweep(bm, torch)
+        out["config"]["secondary"]["out_of_core"] = blocked_run(bm, torch)
         WORKLOAD = args.workload
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(db)

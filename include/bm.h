@@ -252,6 +252,24 @@ bm_status bm_mine(const bm_db* db, uint32_t minsup, void* stream, bm_result** ou
 bm_status bm_mine_ex(const bm_db* db, uint32_t minsup, const bm_options* opt, void* stream,
                      bm_result** out);
 
+/* Out-of-core mining (the paper's block storage and block computing of large
+ * matrices: Section I, the closing paragraph of Section III, Section V): the
+ * transactions stay in host memory and the device holds only one block of
+ * block_rows transactions at a time, as column bitsets.  A first pass over the
+ * blocks sums the single-item supports; then every level step loads the
+ * blocks one after another and adds each block's candidate counts into the
+ * same supports, so every support is exact (a sum of integer counts over the
+ * blocks) and no recount pass is needed.  Small classes are mined level by
+ * level.  Device memory: the block matrix (n_items x ceil(block_rows/64)
+ * words, padded) plus the level arrays, independent of n_tx; every level re-reads
+ * the whole CSR over the host link.  row_ptr (uint64[n_tx + 1]) and col_idx
+ * (uint32[row_ptr[n_tx]]) must be host memory (else BM_ERR_INVALID_ARG); their
+ * checks and limits are bm_build's, plus block_rows >= 1 and minsup >= 1.  The
+ * result equals bm_mine on the whole database. */
+bm_status bm_mine_blocked(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n_tx,
+                          uint32_t n_items, uint32_t minsup, uint64_t block_rows,
+                          const bm_options* opt, void* stream, bm_result** out);
+
 /* Batched mining: `count` independent databases (each with its own minsup) are
  * mined together -- every level step covers the prefix classes of all of them,
  * so the whole batch needs one device->host synchronisation per itemset length

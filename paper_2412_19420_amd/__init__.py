@@ -29,7 +29,7 @@ from ._bm import (BM_K_NAMES, FLAG_ALL_MFMA, FLAG_DEPTH_FIRST, FLAG_DFS_BLOCK_ON
 
 __all__ = [
     "bm_abi_version", "bm_build", "bm_build_batch", "bm_item_support", "bm_pair_support", "bm_mine",
-    "bm_mine_ex", "bm_mine_batch", "bm_set_allocator", "bm_release_cached_memory", "Db", "Result", "BmError",
+    "bm_mine_ex", "bm_mine_batch", "bm_mine_blocked", "bm_set_allocator", "bm_release_cached_memory", "Db", "Result", "BmError",
     "options", "FLAG_TIMING", "FLAG_NO_MFMA", "FLAG_ALL_MFMA", "FLAG_GRAPH", "FLAG_TRACE",
     "FLAG_SHUFFLE", "FLAG_LEVELSYNC", "FLAG_FP4_MFMA", "FLAG_INT8_MFMA", "FLAG_DFS_BLOCK_ONLY",
     "FLAG_TIMING_MAIN", "FLAG_DEPTH_FIRST", "FLAG_NO_PROJECT",
@@ -336,6 +336,19 @@ def bm_mine_ex(db: Db, minsup: int, opts: BmOptions | None = None, stream=None) 
     op = ctypes.byref(opts) if opts is not None else None
     _bm.check(_bm.lib.bm_mine_ex(db.handle, minsup, op, _bm._stream_ptr(stream), ctypes.byref(h)),
               "bm_mine_ex")
+    return Result(h)
+
+
+def bm_mine_blocked(row_ptr, col_idx, n_tx: int, n_items: int, minsup: int, block_rows: int,
+                    opts: BmOptions | None = None, stream=None) -> Result:
+    """Out-of-core mining of a host CSR, block_rows transactions on the device at a time."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.uint64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.uint32) if col_idx is not None else None
+    h = ctypes.c_void_p()
+    _bm.check(_bm.lib.bm_mine_blocked(
+        rp.ctypes.data, ci.ctypes.data if ci is not None and ci.size else None, n_tx, n_items,
+        minsup, block_rows, ctypes.byref(opts) if opts is not None else None,
+        _bm._stream_ptr(stream), ctypes.byref(h)), "bm_mine_blocked")
     return Result(h)
 
 

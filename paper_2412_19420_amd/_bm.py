@@ -116,6 +116,9 @@ lib.bm_mine.restype = ctypes.c_int
 lib.bm_mine.argtypes = [_vp, ctypes.c_uint32, _vp, ctypes.POINTER(_vp)]
 lib.bm_mine_ex.restype = ctypes.c_int
 lib.bm_mine_ex.argtypes = [_vp, ctypes.c_uint32, ctypes.POINTER(BmOptions), _vp, ctypes.POINTER(_vp)]
+lib.bm_mine_blocked.restype = ctypes.c_int
+lib.bm_mine_blocked.argtypes = [_vp, _vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                ctypes.c_uint64, ctypes.POINTER(BmOptions), _vp, ctypes.POINTER(_vp)]
 lib.bm_mine_batch.restype = ctypes.c_int
 lib.bm_mine_batch.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint32,
                               _vp, ctypes.POINTER(BmOptions), _vp, ctypes.POINTER(_vp)]

@@ -111,6 +111,17 @@ bm_status bm_mine_ex(const bm_db* db, uint32_t minsup, const bm_options* opt, vo
   });
 }
 
+bm_status bm_mine_blocked(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n_tx,
+                          uint32_t n_items, uint32_t minsup, uint64_t block_rows,
+                          const bm_options* opt, void* stream, bm_result** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!out) bm::fail(BM_ERR_INVALID_ARG, "out is NULL");
+    *out = bm::mine_blocked(row_ptr, col_idx, n_tx, n_items, minsup, block_rows, opt,
+                            as_stream(stream));
+  });
+}
+
 bm_status bm_mine_batch(const bm_db* const* dbs, const uint32_t* minsups, uint32_t count,
                         const bm_model* sched, const bm_options* opt, void* stream,
                         bm_result** out) {

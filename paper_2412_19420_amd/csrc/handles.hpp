@@ -108,8 +108,21 @@ void pair_support_noalloc(const bm_db* db, const uint32_t* items, uint32_t k, ui
 bm_options autotune(const bm_db* const* dbs, const uint32_t* minsups, uint32_t count,
                     const bm_model* sched, const bm_options* base, uint32_t reps, hipStream_t s,
                     double* best_ms);
+// Row blocks of an out-of-core database (bm_mine_blocked): before each launch
+// of the class kernels the miner loads every block in turn into the one
+// device matrix the database handle points at, and the kernels add each
+// block's counts into the same supports.
+struct BlockSource {
+  virtual ~BlockSource() = default;
+  virtual uint64_t blocks() const = 0;
+  virtual void load(uint64_t b, hipStream_t s) = 0;
+};
 std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsups, uint32_t count,
-                                  const bm_model* sched, const bm_options* opt, hipStream_t s);
+                                  const bm_model* sched, const bm_options* opt, hipStream_t s,
+                                  BlockSource* blocks = nullptr);
+// Out-of-core mining of a host CSR, block_rows transactions at a time.
+bm_result* mine_blocked(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n, uint32_t m,
+                        uint32_t minsup, uint64_t block_rows, const bm_options* opt, hipStream_t s);
 bm_rules* rules_mine(const bm_result* r, uint32_t min_conf_ppm, uint32_t max_len, hipStream_t s);
 void rules_copy(const bm_rules* rs, uint64_t* z, uint32_t* mask, uint32_t* sx, uint32_t* sy,
                 uint32_t* sz, double* conf, double* lift, hipStream_t s);

@@ -214,6 +214,7 @@ void launch_validate(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_
                      uint32_t* err, hipStream_t s);
 void launch_pack(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint64_t* B, uint64_t Wp,
                  hipStream_t s);
+// Adds each column's popcount to colsum[j] (zero it first for plain sums).
 void launch_colsum(const uint64_t* B, uint64_t Wp, uint32_t m, uint32_t* colsum, hipStream_t s);
 // Tiled build of M and its column sums in one pass, with the CSR checks
 // (colsum and err must be zeroed; err gets the flags of launch_build_multi;

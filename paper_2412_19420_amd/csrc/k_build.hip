@@ -295,7 +295,7 @@ __global__ __launch_bounds__(kThreads) void k_colsum(const uint64_t* __restrict_
     if (threadIdx.x == 0) {
       uint32_t t = 0;
       for (int k = 0; k < kThreads / 64; ++k) t += s_part[k];
-      out[j] = t;
+      out[j] += t;  // one workgroup per column: adds to the (zeroed or running) sums
     }
     __syncthreads();
   }

@@ -824,10 +824,130 @@ void pair_support_noalloc(const bm_db* db, const uint32_t* items, uint32_t k, ui
   pair_support_impl(db, items, k, out, s, true);
 }
 
+// ------------------------------------------------------------------ out of core
+
+namespace {
+
+// The blocks of a host CSR: block b holds transactions [b R, min(n, (b+1) R)),
+// packed into the database handle's one matrix of m columns x Wp words (every
+// block the same shape: the last one's missing rows are zero bits).  Loading
+// copies the block's row offsets (rebased to 0) and item ids to the device and
+// packs them, adding the block's column popcounts into `colsum`.
+class HostBlocks : public BlockSource {
+ public:
+  HostBlocks(const uint64_t* rp, const uint32_t* ci, uint64_t n, uint32_t m, uint64_t R,
+             bm_db* db, hipStream_t s)
+      : rp_(rp), ci_(ci), n_(n), m_(m), R_(R), db_(db) {
+    nb_ = n ? (n + R - 1) / R : 0;
+    uint64_t most = 0;
+    for (uint64_t b = 0; b < nb_; ++b) {
+      const uint64_t b0 = b * R, b1 = std::min(n, b0 + R);
+      most = std::max(most, rp[b1] - rp[b0]);
+    }
+    d_rp_.reset(R + 1, s);
+    d_raw_.reset(R + 1, s);
+    d_ci_.reset(std::max<uint64_t>(most, 1), s);
+    err_.reset(1, s);
+    scratch_sum_.reset(std::max<uint32_t>(m, 1), s);
+    tiled_ = pack_tiled_ok(m, db->Wp);
+  }
+  uint64_t blocks() const override { return nb_; }
+  uint32_t* err() const { return err_.get(); }
+  // load into the matrix, the popcounts going to colsum (the database's own
+  // in the first pass, a scratch array afterwards)
+  void load_to(uint64_t b, uint32_t* colsum, hipStream_t s) {
+    if (b == cur_) return;  // already in place (a database of one block)
+    const uint64_t b0 = b * R_, b1 = std::min(n_, b0 + R_), rows = b1 - b0;
+    const uint64_t base = rp_[b0];
+    if (rp_[b1] < base) fail(BM_ERR_CSR, "row_ptr is not non-decreasing");
+    const uint64_t nnz = rp_[b1] - base;
+    // the block's row offsets, rebased to 0 on the device; the pack checks
+    // their order and clamps every range to the block's nnz item ids
+    BM_HIP(hipMemcpyAsync(d_raw_.get(), rp_ + b0, (rows + 1) * 8, hipMemcpyHostToDevice, s));
+    if (nnz) BM_HIP(hipMemcpyAsync(d_ci_.get(), ci_ + base, nnz * 4, hipMemcpyHostToDevice, s));
+    launch_rebase(d_raw_.get(), rows + 1, base, d_rp_.get(), s);
+    uint64_t* B = db_->B.get();
+    if (tiled_) {
+      launch_pack_tiled(d_rp_.get(), d_ci_.get(), rows, m_, B, db_->Wp, colsum, err_.get(), s);
+    } else {
+      // the atomic pack trusts its ranges: check them first
+      launch_validate(d_rp_.get(), d_ci_.get(), rows, nnz, m_, err_.get(), s);
+      const uint32_t e = read_back(err_.get(), s);
+      if (e & 1u) fail(BM_ERR_CSR, "row_ptr is not non-decreasing");
+      if (e & 2u) fail(BM_ERR_CSR, "an item id is >= n_items (%u)", m_);
+      launch_fill_u64(B, 0, (uint64_t)m_ * db_->Wp, s);
+      launch_pack(d_rp_.get(), d_ci_.get(), rows, B, db_->Wp, s);
+      launch_colsum(B, db_->Wp, m_, colsum, s);
+    }
+    cur_ = b;
+  }
+  void load(uint64_t b, hipStream_t s) override { load_to(b, scratch_sum_.get(), s); }
+
+ private:
+  const uint64_t* rp_;
+  const uint32_t* ci_;
+  uint64_t n_;
+  uint32_t m_;
+  uint64_t R_, nb_ = 0;
+  bm_db* db_;
+  bool tiled_ = true;
+  uint64_t cur_ = ~0ull;
+  DBuf<uint64_t> d_rp_, d_raw_;
+  DBuf<uint32_t> d_ci_, err_, scratch_sum_;
+};
+
+}  // namespace
+
+bm_result* mine_blocked(const uint64_t* row_ptr, const uint32_t* col_idx, uint64_t n, uint32_t m,
+                        uint32_t minsup, uint64_t block_rows, const bm_options* opt, hipStream_t s) {
+  if (!row_ptr) fail(BM_ERR_INVALID_ARG, "row_ptr is NULL");
+  if (is_device_ptr(row_ptr) || (col_idx && is_device_ptr(col_idx)))
+    fail(BM_ERR_INVALID_ARG, "blocked mining reads the transactions from host memory");
+  if (minsup == 0) fail(BM_ERR_INVALID_ARG, "minsup must be >= 1");
+  if (block_rows == 0) fail(BM_ERR_INVALID_ARG, "block_rows must be >= 1");
+  if (n >= (1ull << 31)) fail(BM_ERR_UNSUPPORTED, "n_tx = %llu >= 2^31", (unsigned long long)n);
+  if (row_ptr[0] != 0) fail(BM_ERR_CSR, "row_ptr[0] = %llu, expected 0",
+                            (unsigned long long)row_ptr[0]);
+  if (row_ptr[n] > 0 && !col_idx)
+    fail(BM_ERR_INVALID_ARG, "col_idx is NULL but row_ptr[n] = %llu", (unsigned long long)row_ptr[n]);
+  const uint64_t R = std::min<uint64_t>(block_rows, std::max<uint64_t>(n, 1));
+  auto db = std::make_unique<bm_db>();
+  BM_HIP(hipGetDevice(&db->device));
+  db->n = n;
+  db->m = m;
+  db->Wp = padded_words(R);
+  db->W = (R + 63) / 64;  // every block spans the same words; tasks are built once per step
+  db->B.reset((size_t)m * db->Wp, s);
+  db->colsum.reset(m, s);
+  std::unique_ptr<HostBlocks> src;
+  {
+    CallScope scope(s);  // synchronises before anything above is freed on failure
+    src.reset(new HostBlocks(row_ptr, col_idx, n, m, R, db.get(), s));
+    if (m > 0) launch_fill_u32(db->colsum.get(), 0, m, s);
+    launch_fill_u32(src->err(), 0, 1, s);
+    // first pass: the single-item supports, summed over the blocks
+    for (uint64_t b = 0; b < src->blocks() && m > 0; ++b) src->load_to(b, db->colsum.get(), s);
+    const uint32_t e = read_back(src->err(), s);
+    if (e & 1u) fail(BM_ERR_CSR, "row_ptr is not non-decreasing");
+    if (e & 2u) fail(BM_ERR_CSR, "an item id is >= n_items (%u)", m);
+  }
+  // level by level (no whole-column subtree phases) and no projected views:
+  // every kernel then sees only the block in the matrix
+  bm_options o{};
+  if (opt) o = *opt;
+  o.flags |= BM_FLAG_LEVELSYNC | BM_FLAG_NO_PROJECT;
+  o.flags &= ~(BM_FLAG_TRACE | BM_FLAG_DEPTH_FIRST);
+  const bm_db* dp = db.get();
+  auto r = mine_many(&dp, &minsup, 1, nullptr, &o, s, src.get());
+  r[0]->n_tx = n;
+  return r[0];
+}
+
 // ------------------------------------------------------------------ mining
 
 std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsups, uint32_t N,
-                                  const bm_model* sched, const bm_options* opt, hipStream_t s) {
+                                  const bm_model* sched, const bm_options* opt, hipStream_t s,
+                                  BlockSource* blocks) {
   const auto t0 = std::chrono::steady_clock::now();
   for (uint32_t d = 0; d < N; ++d)
     if (minsups[d] == 0) fail(BM_ERR_INVALID_ARG, "minsup of database %u must be >= 1", d);
@@ -974,8 +1094,16 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         // every class of this step is a deferred subtree: no level-synchronous
         // level k + 1, so neither node counts nor a synchronisation are needed
         if (ls_cand == 0) break;
-        if (w->nproj) project_views(*w, ddb_p, L[k].item.get(), Wmax, nW, tm, s);
-        run_class_kernels(ddb_p, L[k].item.get(), *w, tu, nW, nN, tm, s);
+        if (blocks) {
+          // out of core: every row block in turn, the supports summed over blocks
+          for (uint64_t b = 0; b < blocks->blocks(); ++b) {
+            blocks->load(b, s);
+            run_class_kernels(ddb_p, L[k].item.get(), *w, tu, nW, nN, tm, s);
+          }
+        } else {
+          if (w->nproj) project_views(*w, ddb_p, L[k].item.get(), Wmax, nW, tm, s);
+          run_class_kernels(ddb_p, L[k].item.get(), *w, tu, nW, nN, tm, s);
+        }
 
         tm.begin(BM_K_LEVEL);
         // each node counts the frequent entries of its triangle row (the
