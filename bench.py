@@ -152,10 +152,14 @@ DTYPE = {"fp4": "u64 bitsets; fp4 (e2m1) MFMA, fp32 accumulate (exact: counts < 
 # the copy calibration), valid only while the kernel's source is unchanged:
 # (workload, kernel, form) -> (source file, its sha256, bytes per launch).
 TRAFFIC = {
-    # dense_planted 1M x 4,096 (profiles/dense_planted_1M_hbm_traffic.md)
-    (3, "gram_mfma", "fp4"): ("k_gram_mfma.hip", "21074a5da110ee20db3c6c781868b7272afaa501a05745e03e163ca8fe03876e", 3267.4e6),
-    (3, "gram_small", "fp4"): ("k_gram_small.hip", "f5838556e51a593149d221a8305e3fde2e735c73c0970d0a561de7f91139de72", 226.9e6),
+    # dense_planted 1M x 4,096, cache-cold mine (profiles/dense_planted_1M_hbm_traffic.md)
+    (3, "gram_mfma", "fp4"): ("k_gram_mfma.hip", "b74cbde3065f32241b078f52f9348e5cb0f32aaf810e4b603ac72a20d7ed8e19", 3292.2e6),
+    (3, "gram_small", "fp4"): ("k_gram_small.hip", "4a82c6426d00e4149cdc680e6d8065aa796d675ba67c529e6b6e4cdd4e07c64e", 226.7e6),
     (3, "dfs", "fp4"): ("k_subsets.hip", "2109e75ca138125ad95a1d2f12b68e6102d64a5d0421e9effe55855d65b95f7e", 769.8e6),
+    # Quest T40-style 1M x 2,000, cache-cold mine (profiles/quest_t40_1M_hbm_traffic.md)
+    (5, "gram_mfma", "fp4"): ("k_gram_mfma.hip", "b74cbde3065f32241b078f52f9348e5cb0f32aaf810e4b603ac72a20d7ed8e19", 2462.9e6),
+    (5, "gram_small", "fp4"): ("k_gram_small.hip", "4a82c6426d00e4149cdc680e6d8065aa796d675ba67c529e6b6e4cdd4e07c64e", 118.5e6),
+    (5, "dfs", "fp4"): ("k_subsets.hip", "2109e75ca138125ad95a1d2f12b68e6102d64a5d0421e9effe55855d65b95f7e", 344.3e6),
 }
 WORKLOAD = None
 
@@ -382,8 +386,12 @@ def run_single(args, bm, torch, dev, workload, steps, warmup, sched="none", extr
             return bm.bm_mine_batch([h], [db.minsup], model=model, opts=o, stream=stream)[0]
         return bm.bm_mine_ex(h, db.minsup, o, stream=stream)
 
+    flush = torch.empty(2 << 30, dtype=torch.uint8, device=dev) if args.cold else None
+
     def step():
         h = bm.bm_build(rp, ci, db.n, db.m, stream=stream)
+        if flush is not None:  # profiling runs: a cache-cold mine call
+            flush.fill_(7)
         return h, mine(h, opts)
 
     for i in range(warmup):
@@ -609,7 +617,9 @@ def blocked_run(bm, torch, workload: int = 3, block_rows: int = 250_000, reps: i
 
 def _secondary(args, bm, torch, dev):
     """Shorter runs of the batched and the T40-style workloads, for the record."""
+    global WORKLOAD
     sec = {}
+    WORKLOAD = 4
     b = run_batched(args, bm, torch, dev, steps=3, warmup=1)
     sec["batch_256"] = {"ms_per_step_by_mode": {k: v["ms_per_step"]
                                                 for k, v in b["config"]["modes"].items()},
@@ -617,6 +627,7 @@ def _secondary(args, bm, torch, dev):
                         "candidates": b["config"]["candidates"],
                         "value_learned": b["value"], "roofline": b["roofline"]}
     t40 = {}
+    WORKLOAD = 5  # the T40-style workload's traffic records
     for name, kw in (("default", {}),
                      ("depth_first_plain", {"extra_flags": bm.FLAG_DEPTH_FIRST,
                                             "dfs_max_words": 0xFFFFFFFF}),
@@ -634,6 +645,7 @@ def _secondary(args, bm, torch, dev):
         t40[name] = e
         print(f"# T40 {name}: {r['ms_per_step']} ms/step", file=sys.stderr, flush=True)
     sec["quest_t40_1M"] = t40
+    WORKLOAD = None
     return sec
 
 
@@ -647,6 +659,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the shorter batched and T40-style runs after the headline")
+    ap.add_argument("--cold", action="store_true",
+                    help="profiling: write 2 GiB between build and mine in every step (the fill "
+                         "is inside the timed step)")
     ap.add_argument("--sweep", action="store_true",
                     help="only the Table 1/2-style sweep (threshold x transactions) as JSON")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
@@ -701,7 +716,6 @@ def main():
     out = run_single(args, bm, torch, dev, args.workload, args.steps, args.warmup, sched=args.sched)
     db = out.pop("_db")
     if not args.no_secondary and args.workload == 3:
-        WORKLOAD = None  # traffic records belong to the headline workload
         out["config"]["secondary"] = _secondary(args, bm, torch, dev)
         out["config"]["secondary"]["table_sweep"] = table_sweep(bm, torch)
         out["config"]["secondary"]["out_of_core"] = blocked_run(bm, torch)

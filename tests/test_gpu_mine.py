@@ -81,7 +81,9 @@ def test_build_from_device_pointers(bm):
     assert_same((offs.cpu().numpy(), items.cpu().numpy(), supp.cpu().numpy()), want)
 
 
-@pytest.mark.parametrize("m", [169, 20_000])  # tiled pack; more than 32 windows: untiled path
+# one to eight 512-column windows of the line-tiled pack (window edges included),
+# more than eight (the 256-row pack), more than 32 (the untiled path)
+@pytest.mark.parametrize("m", [169, 512, 513, 4096, 4097, 20_000])
 @pytest.mark.parametrize("rp_dev,ci_dev", [(False, False), (False, True), (True, False),
                                            (True, True)])
 def test_build_host_device_combinations(bm, m, rp_dev, ci_dev):
