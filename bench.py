@@ -42,7 +42,7 @@ MFMA_PEAK_TOPS = {"int8": 5000.0, "fp4": 10100.0}
 # ops = 2 n per candidate pair (one AND, one add per transaction)
 MFMA_KERNELS = {
     "gram_mfma": "k_gram_mfma (MFMA Gram of a prefix class, 128x128 tiles)",
-    "gram_mfma_big": "k_gram_mfma_big (MFMA Gram of a big prefix class, 128 x 256 halves of 256 x 256 block pairs)",
+    "gram_mfma_big": "k_gram_mfma_big (MFMA Gram of a big prefix class, 256x256 tiles, one workgroup per CU)",
     "gram_small": "k_gram_small (MFMA Gram of a mid-size class, 32x32 tiles, one wave per task)",
 }
 # streaming kernels priced against HBM: algorithmic bytes = column words read

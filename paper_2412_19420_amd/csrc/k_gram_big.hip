@@ -1,261 +1,292 @@
 // Pair supports of big prefix classes (at least mfma_big_children children)
-// as masked Gram tiles on MFMA, 256 x 256 block pairs split into 128-row
-// halves.  The contraction, the operand forms (FP4 bit planes or int8 bytes)
-// and the staging follow the 128-tile kernel in k_gram_mfma.hip; this kernel
-// only changes the tile shape per wave.
-#include <type_traits>
-
-#include "internal.hpp"
+// as masked Gram tiles on MFMA: the contraction of k_gram_mfma.hip (Eq. 2 over
+// all pairs of the class's children, FP4 bit planes, exact FP32 sums) on
+// 256 x 256 tiles.
+//
+// Kernel shape (gfx950, wave64): one workgroup of 4 waves per CU computes a
+// 256 x 256 block pair over a range of words; each wave owns a 128 x 128
+// quarter, a 4 x 4 grid of 32 x 32 accumulators (256 registers, which live in
+// the accumulation registers: one wave per SIMD).  Per word group a wave
+// builds 8 operand rows for 16 MFMAs (the 128-tile kernel: 4 for 4), so the
+// bit-plane VALU work per MFMA halves, and a stage of 16 words carries 256
+// MFMAs per wave between two barriers.  The panels are staged directly into
+// LDS as in the 128-tile kernel (gram_fp4.hpp): two stages of 2 x 256 rows,
+// 128 KiB.
+//
+// A diagonal block pair (one panel) has 36 useful 32 x 32 blocks (i <= j of
+// 8 x 8); the waves share them out 10 / 8 / 8 / 10:
+//   MODE 1 (waves 0 and 3): the upper triangle, diagonal included, of panel
+//     blocks 4h .. 4h + 3 against themselves (h = 0, 1), B taken from A;
+//   MODE 2 (waves 1 and 2): rows 2h', 2h' + 1 (h' = 0, 1) against columns
+//     4 .. 7;
+// MODE 0 (every wave of an off-diagonal pair): its 4 row blocks against its 4
+// column blocks.
+#include "gram_fp4.hpp"
 
 namespace bm {
 
 namespace {
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v8i __attribute__((ext_vector_type(8)));
-typedef int v16i __attribute__((ext_vector_type(16)));
-typedef float v16f __attribute__((ext_vector_type(16)));
+constexpr int BT = GRAM_TILE_BIG;  // 256 children per tile side
+constexpr int BROWS = 2 * BT;      // staged rows per buffer (A panel, then B panel)
+constexpr int BLOADS = BROWS / 8 / 4;  // load instructions per wave per stage (16)
 
-
-__device__ __forceinline__ v4i expand4(uint32_t v, int d0) {
-  v4i r;
-  r[0] = (int)((v >> (d0 + 0)) & 0x01010101u);
-  r[1] = (int)((v >> (d0 + 1)) & 0x01010101u);
-  r[2] = (int)((v >> (d0 + 2)) & 0x01010101u);
-  r[3] = (int)((v >> (d0 + 3)) & 0x01010101u);
-  return r;
+template <int MODE>
+__device__ __forceinline__ void big_group(const uint4 (&a)[4], const uint4 (&b)[4], const uint4& m,
+                                          v16f (&acc)[4][4]) {
+  constexpr int NA = MODE == 2 ? 2 : 4;  // A row blocks this wave builds
+  constexpr bool BSAME = MODE == 1;      // B operands are A's
+  uint32_t va[4][4], vb[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    va[i][0] = a[i].x & m.x;
+    va[i][1] = a[i].y & m.y;
+    va[i][2] = a[i].z & m.z;
+    va[i][3] = a[i].w & m.w;
+    vb[i][0] = b[i].x;
+    vb[i][1] = b[i].y;
+    vb[i][2] = b[i].z;
+    vb[i][3] = b[i].w;
+  }
+#pragma unroll
+  for (int pl = 0; pl < 4; ++pl) {
+    v8i A[4], B[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        A[i][j] = i < NA ? (int)fp4_plane(va[i][j], pl) : 0;
+        B[i][j] = BSAME ? 0 : (int)fp4_plane(vb[i][j], pl);
+      }
+      A[i][4] = A[i][5] = A[i][6] = A[i][7] = 0;
+      B[i][4] = B[i][5] = B[i][6] = B[i][7] = 0;
+    }
+    const int sc = fp4_plane_scale(pl);
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if constexpr (MODE == 1) {
+          if (j >= i) acc[i][j] = fp4_mfma(A[i], A[j], acc[i][j], sc);
+        } else {
+          acc[i][j] = fp4_mfma(A[i], B[j], acc[i][j], sc);
+        }
+      }
+  }
 }
 
-// FP4 (e2m1) form.  The e2m1 codes 0001, 0010 and 0100 are the values 0.5, 1
-// and 2, so one AND turns a 32-bit half-word v into eight FP4 elements that
-// each hold one transaction bit: plane 0 = v & 0x11111111 (bits 0, 4, .., 28
-// as 0.5), plane 1 = v & 0x22222222 (bits 1, 5, .. as 1), plane 2 =
-// v & 0x44444444 (as 2); plane 3 (bits 3, 7, ..) would land on the sign bit,
-// so it is shifted first: (v >> 2) & 0x22222222 (as 1).  One
-// v_mfma_scale_f32_32x32x64_f8f6f4 takes one plane of four consecutive words
-// (a lane's four operand dwords), and its E8M0 block scales (2, 1, 1/2, 1 on
-// both operands) make every product of two set bits exactly 1.0; four MFMAs,
-// one per plane, cover the four words.  A and B use the identical bit ->
-// (lane, element) map, so every transaction meets itself in the K sum.  FP32
-// holds every integer up to 2^24 exactly, so a task's sums are exact while its
-// counts stay at most 2^24 -- the task word split is capped at
-// GRAM_FP4_MAX_WORDS for that.
-__device__ __forceinline__ uint32_t fp4_plane(uint32_t v, int pl) {
-  return pl == 0 ? (v & 0x11111111u)
-       : pl == 1 ? (v & 0x22222222u)
-       : pl == 2 ? (v & 0x44444444u)
-                 : ((v >> 2) & 0x22222222u);
-}
-__device__ __forceinline__ int fp4_plane_scale(int pl) {  // E8M0: 2^(e - 127)
-  return pl == 0 ? 128 : pl == 2 ? 126 : 127;
+// One stage of one wave: four word groups, the next group's operands read
+// from LDS before the current group's MFMAs.  ra / rb: the wave's first A and
+// B rows at this lane, in chunks; mk: the stage's mask row.
+template <int MODE>
+__device__ __forceinline__ void big_stage(const uint4* ra, const uint4* rb, const uint4* mk,
+                                          int lane, v16f (&acc)[4][4]) {
+  constexpr int NA = MODE == 2 ? 2 : 4;
+  constexpr bool BSAME = MODE == 1;
+  const int kh = lane >> 5, sw = lane & 7;
+  uint4 a[4], b[4], m;
+  auto read = [&](int g, uint4 (&xa)[4], uint4 (&xb)[4], uint4& xm) {
+    const int c = 2 * g + kh;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      xa[i] = i < NA ? ra[i * 32 * DCH + (c ^ sw)] : make_uint4(0, 0, 0, 0);
+      xb[i] = BSAME ? make_uint4(0, 0, 0, 0) : rb[i * 32 * DCH + (c ^ sw)];
+    }
+    xm = mk[c];
+  };
+  read(0, a, b, m);
+#pragma unroll
+  for (int g = 0; g < DKW / 4; ++g) {
+    uint4 na[4], nb[4], nm;
+    if (g + 1 < DKW / 4) read(g + 1, na, nb, nm);
+    big_group<MODE>(a, b, m, acc);
+    if (g + 1 < DKW / 4) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = na[i];
+        b[i] = nb[i];
+      }
+      m = nm;
+    }
+  }
 }
 
-// Big classes: 256 x 256 block pairs, each as two tasks of 128 rows x 256
-// columns, one workgroup of 4 waves per task.  A wave owns 64 x 128 (2 x 4
-// accumulators of 32 x 32, 128 registers), so per word it builds 6 operand
-// rows for 8 MFMAs (the 128-tile kernel: 4 rows for 4), and two workgroups
-// share a CU as in the 128-tile kernel.  On a diagonal block pair the 128 rows
-// are a slice of the 256 staged columns, so only the column side is staged,
-// and a wave whose block lies wholly below the diagonal skips its MFMAs.
-constexpr int BR = GRAM_TILE_BIG / 2;  // 128 rows per task
-constexpr int BC = GRAM_TILE_BIG;      // 256 columns
-constexpr int BKW = 8;                 // words per stage
-constexpr int BLDW = 2 * BKW + 1;      // dwords per staged column row (odd: conflict-free reads)
-constexpr int BSUBS = BKW / 2;         // 16-byte slots per column per stage
-constexpr int BCSL = 256 / BSUBS;      // columns staged per pass (64)
-constexpr int BNSC = BC / BCSL;        // passes for the columns (4)
-constexpr int BNSR = BR / BCSL;        // passes for the rows (2)
+struct BigTask {
+  const uint64_t* src[BLOADS];  // this lane's chunk of each load instruction, at word 0
+  const uint32_t* pre;          // prefix columns
+  const uint64_t* pcol;         // this thread's first prefix column (j = tid / 8) at chunk tid % 8
+  uint32_t pre_len;
+  uint64_t Wp;
+  const uint64_t* B;
+  uint32_t w0, nst;
+  int mode, nload, rb0, cb0;
+  bool diag, idle;  // idle: the wave's rows or columns all lie past the last child
+};
 
-template <bool F4>
-__device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint32_t* sR, uint32_t* sC) {
-  static_assert(GRAM_KW % BKW == 0, "stages must tile the task word ranges");
+// The wave's load instructions for the stage at word w: r < 8 stage A-panel
+// rows 64 w + 8 r .. +7 (wave w), r >= 8 the same rows of the B panel.
+__device__ __forceinline__ void big_issue(const BigTask& k, uint32_t w, uint4* buf, int wave) {
+  uint4* dst = buf + (size_t)(64 * wave) * DCH;
+#pragma unroll
+  for (int r = 0; r < BLOADS; ++r)
+    if (r < k.nload)
+      __builtin_amdgcn_global_load_lds(k.src[r] + w,
+                                       dst + ((r >= 8) ? BT * DCH : 0) + 8 * (r & 7) * DCH, 16, 0,
+                                       0);
+}
+
+__device__ __forceinline__ void big_stage_step(const BigTask& k, uint32_t s, const uint4* cur,
+                                               uint4* nxt, uint4* smask, int tid,
+                                               v16f (&acc)[4][4]) {
+  const int lane = tid & 63, wave = tid >> 6;
+  const uint32_t pj0 = (uint32_t)tid >> 3, pch = (uint32_t)tid & 7;
+  __syncthreads();  // stage s is in LDS (each wave waited for its loads); stage s - 1 is done
+  const bool more = s + 1 < k.nst;
+  const uint32_t wn = k.w0 + (s + 1) * DKW;
+  const bool pre_thread = more && pj0 < k.pre_len;
+  uint4 pm = make_uint4(~0u, ~0u, ~0u, ~0u);
+  if (pre_thread) pm = load_global16(k.pcol + wn);
+  if (more) big_issue(k, wn, nxt, wave);
+  if (tid < DCH) smask[((s + 2) % 3) * DCH + tid] = make_uint4(~0u, ~0u, ~0u, ~0u);
+
+  if (!k.idle) {
+    const uint4* ra = cur + (size_t)(k.rb0 * 32 + (lane & 31)) * DCH;
+    const uint4* rb = cur + (size_t)((k.diag ? 0 : BT) + k.cb0 * 32 + (lane & 31)) * DCH;
+    const uint4* mk = smask + (s % 3) * DCH;
+    if (k.mode == 0) big_stage<0>(ra, rb, mk, lane, acc);
+    else if (k.mode == 1) big_stage<1>(ra, rb, mk, lane, acc);
+    else big_stage<2>(ra, rb, mk, lane, acc);
+  }
+
+  if (pre_thread)
+    fp4_mask_and(pm, k.B, k.Wp, k.pre, k.pre_len, pj0, pch, wn, smask + ((s + 1) % 3) * DCH);
+}
+
+__device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint4* sb0, uint4* sb1,
+                                               uint4* smask) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;  // rows wr*64 .. +63, columns wc*128 .. +127
-  const int sub = tid % BSUBS;
-  const int cslot = tid / BSUBS;
+  const int wr = wave >> 1, wc = wave & 1;
   const uint64_t ntasks = *a.ntasks;
-  constexpr int NP = BNSC + BNSR;
+  const SkRange rg = sk_range(a.tcost, ntasks);
 
-  for (uint64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
+  for (uint64_t t = rg.i; t < ntasks; ++t) {
+    const uint64_t base = a.tcost[t];
+    if (base >= rg.u1) break;
     const Task task = a.tasks[t];
+    uint32_t s_lo, s_hi;
+    if (!sk_stages(base, a.tcost[t + 1], rg,
+                   task.bi == task.bl ? GRAM_BIG_COST_DIAG : GRAM_BIG_COST_OFF, s_lo, s_hi))
+      continue;
     const ClassDesc cd = a.cls[task.cls];
     const DbInfo db = class_view(cd, a.dbs, a.views);
-    const uint64_t Wp = db.Wp;
     const uint32_t q = cd.q;
-    const uint32_t half = task.bi & 1u;
-    const uint32_t I0 = (uint32_t)task.bi * BR, L0 = (uint32_t)task.bl * BC;
-    const bool diag = (uint32_t)(task.bi >> 1) == (uint32_t)task.bl;
-    // no pair to count: every row of the wave's block exceeds every column
-    // (below the diagonal), or its rows or columns lie past the last child
-    const bool skip = I0 + wr * 64 >= L0 + wc * 128 + 128 || I0 + wr * 64 >= q || L0 + wc * 128 >= q;
-
-    // passes 0..3 stage the 256 columns, passes 4..5 the 128 rows (not on a
-    // diagonal block pair); nullptr = zero column
-    const uint64_t* colp[NP];
+    const uint32_t I0 = (uint32_t)task.bi * BT, L0 = (uint32_t)task.bl * BT;
+    BigTask k;
+    k.diag = task.bi == task.bl;
+    if (k.diag) {
+      const bool on = wave == 0 || wave == 3;
+      k.mode = on ? 1 : 2;
+      k.rb0 = on ? (wave == 0 ? 0 : 4) : (wave == 1 ? 0 : 2);
+      k.cb0 = on ? k.rb0 : 4;
+    } else {
+      k.mode = 0;
+      k.rb0 = 4 * wr;
+      k.cb0 = 4 * wc;
+    }
+    k.idle = I0 + 32u * k.rb0 >= q || L0 + 32u * k.cb0 >= q;
+    k.nload = k.diag ? BLOADS / 2 : BLOADS;
+    k.Wp = db.Wp;
+    k.B = db.B;
+    k.pre = a.pre_cols + cd.pre_off;
+    k.pre_len = cd.proj ? 0u : cd.pre_len;  // a view has the prefix applied
+    k.w0 = task.w0 + s_lo * DKW;
+    k.nst = s_hi - s_lo;
+    k.pcol = nullptr;
+    if ((uint32_t)tid / 8 < k.pre_len)
+      k.pcol = k.B + (uint64_t)k.pre[tid / 8] * k.Wp + 2 * (tid & 7);
+    // Lane L of load instruction r fetches the chunk for slot L % 8 of panel
+    // row 64 w + 8 (r % 8) + L / 8.  Children beyond q load column q - 1:
+    // their rows and columns of the tile are never written out.
+    uint32_t col[BLOADS];
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const uint32_t idx = (p < BNSC ? L0 + BCSL * p : I0 + BCSL * (p - BNSC)) + cslot;
-      colp[p] = nullptr;
-      if ((p < BNSC || !diag) && idx < q) {
-        const uint32_t item = a.child_item[cd.child0 + idx];
-        const uint32_t col = class_col(cd, db, idx, item);
-        colp[p] = db.B + (uint64_t)col * Wp + 2 * sub;
+    for (int r = 0; r < BLOADS; ++r) {
+      const uint32_t idx = ((r >= 8) ? L0 : I0) + 64 * wave + 8 * (r & 7) + (lane >> 3);
+      col[r] = idx < q ? idx : q - 1;
+    }
+    if (!cd.proj) {
+#pragma unroll
+      for (int r = 0; r < BLOADS; ++r) col[r] = a.child_item[cd.child0 + col[r]];
+      if (db.f1) {
+#pragma unroll
+        for (int r = 0; r < BLOADS; ++r) col[r] = load_global_u32(db.f1 + col[r]);
       }
     }
-    const uint32_t* pre = a.pre_cols + cd.pre_off;
-    const uint32_t pre_len = cd.proj ? 0u : cd.pre_len;  // a view has the prefix applied
-
-    uint4 reg[NP];
-    uint64_t m0 = ~0ull, m1 = ~0ull;
-    auto load_stage = [&](uint32_t w) {
-      m0 = ~0ull;
-      m1 = ~0ull;
-      for (uint32_t j = 0; j < pre_len; ++j) {
-        const uint4 x = *reinterpret_cast<const uint4*>(db.B + (uint64_t)pre[j] * Wp + w + 2 * sub);
-        m0 &= (uint64_t)x.x | ((uint64_t)x.y << 32);
-        m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
-      }
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        if (colp[p]) reg[p] = *reinterpret_cast<const uint4*>(colp[p] + w);
-        else reg[p] = make_uint4(0, 0, 0, 0);
-      }
-    };
+    for (int r = 0; r < BLOADS; ++r) {
+      const uint32_t row = 64 * wave + 8 * (r & 7) + (lane >> 3);
+      const uint32_t chunk = (uint32_t)((lane & 7) ^ (row & 7));
+      k.src[r] = db.B + (uint64_t)col[r] * k.Wp + 2 * chunk;
+    }
 
-    using Acc = typename std::conditional<F4, v16f, v16i>::type;
-    Acc acc[2][4];
+    v16f acc[4][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
 
-    const uint32_t nst = (task.w1 - task.w0) / BKW;
-    if (nst) load_stage(task.w0);
-    for (uint32_t s = 0; s < nst; ++s) {
-      __syncthreads();  // previous stage (or task) finished reading LDS
-#pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        if (p < BNSC || !diag) {
-          uint32_t* dst = (p < BNSC ? sC + (cslot + BCSL * p) * BLDW
-                                    : sR + (cslot + BCSL * (p - BNSC)) * BLDW) + 4 * sub;
-          uint4 v = reg[p];
-          // the prefix mask once per pair: on the rows, or on the columns of a
-          // diagonal block pair (whose rows are read from them)
-          if (pre_len && (diag ? p < BNSC : p >= BNSC)) {
-            v.x &= (uint32_t)m0;
-            v.y &= (uint32_t)(m0 >> 32);
-            v.z &= (uint32_t)m1;
-            v.w &= (uint32_t)(m1 >> 32);
-          }
-          dst[0] = v.x;
-          dst[1] = v.y;
-          dst[2] = v.z;
-          dst[3] = v.w;
-        }
-      }
-      __syncthreads();
-      if (s + 1 < nst) load_stage(task.w0 + (s + 1) * BKW);
-      if (skip) continue;
-
-      const uint32_t* pa = (diag ? sC + half * BR * BLDW : sR) + (wr * 64 + (lane & 31)) * BLDW +
-                           (lane >> 5);
-      const uint32_t* pb = sC + (wc * 128 + (lane & 31)) * BLDW + (lane >> 5);
-      if constexpr (F4) {
-#pragma unroll
-        for (int w4 = 0; w4 < BKW; w4 += 4) {
-          uint32_t va[2][4], vb[4][4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-#pragma unroll
-            for (int i = 0; i < 2; ++i) va[i][j] = pa[i * 32 * BLDW + 2 * (w4 + j)];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) vb[i][j] = pb[i * 32 * BLDW + 2 * (w4 + j)];
-          }
-#pragma unroll
-          for (int pl = 0; pl < 4; ++pl) {
-            v8i A[2], B[4];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-#pragma unroll
-              for (int j = 0; j < 4; ++j) A[i][j] = (int)fp4_plane(va[i][j], pl);
-              A[i][4] = A[i][5] = A[i][6] = A[i][7] = 0;
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-#pragma unroll
-              for (int j = 0; j < 4; ++j) B[i][j] = (int)fp4_plane(vb[i][j], pl);
-              B[i][4] = B[i][5] = B[i][6] = B[i][7] = 0;
-            }
-            const int sc = fp4_plane_scale(pl);
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-              for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                    A[i], B[j], acc[i][j], 4, 4, 0, sc, 0, sc);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int w = 0; w < BKW; ++w) {
-          uint32_t va[2], vb[4];
-#pragma unroll
-          for (int i = 0; i < 2; ++i) va[i] = pa[i * 32 * BLDW + 2 * w];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) vb[i] = pb[i * 32 * BLDW + 2 * w];
-#pragma unroll
-          for (int e = 0; e < 2; ++e) {
-            v4i A[2], B[4];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) A[i] = expand4(va[i], 4 * e);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) B[i] = expand4(vb[i], 4 * e);
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-              for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[i], B[j], acc[i][j], 0, 0, 0);
-          }
-        }
+    __syncthreads();  // the previous task's last stage has finished reading LDS
+    if (k.nst) {
+      big_issue(k, k.w0, sb0, wave);
+      if (tid < DCH) {  // stage 0's mask in full; stage 1's row starts at all ones
+        smask[tid] = fp4_mask_full(k.B, k.Wp, k.pre, k.pre_len, k.w0, (uint32_t)tid);
+        smask[DCH + tid] = make_uint4(~0u, ~0u, ~0u, ~0u);
       }
     }
-    if (skip) continue;
+    // even stages read sb0 and load into sb1, odd stages the other way round
+    for (uint32_t s = 0; s < k.nst; s += 2) {
+      big_stage_step(k, s, sb0, sb1, smask, tid, acc);
+      if (s + 1 < k.nst) big_stage_step(k, s + 1, sb1, sb0, smask, tid, acc);
+    }
+    if (k.idle) continue;
 
+    // 32x32 accumulator layout: lane holds column (lane & 31); register r holds
+    // row 8*(r/4) + 4*(lane/32) + (r%4).
     uint32_t* tri = a.tri + cd.tri_off;
+    const int na = k.mode == 2 ? 2 : 4;
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < 4; ++rb) {
+      if (rb >= na) break;
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const uint32_t gi = I0 + wr * 64 + rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-          const uint32_t gl = L0 + wc * 128 + cb * 32 + (lane & 31);
-          uint32_t v;
-          if constexpr (F4) v = __float2uint_rn(acc[rb][cb][r]);
-          else v = (uint32_t)acc[rb][cb][r];
+          const uint32_t gi = I0 + (k.rb0 + rb) * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const uint32_t gl = L0 + (k.cb0 + cb) * 32 + (lane & 31);
+          const uint32_t v = __float2uint_rn(acc[rb][cb][r]);  // exact integer counts
           if (gi < gl && gl < q && v) atomicAdd(tri + tri_index(gi, gl, q), v);
         }
+    }
   }
 }
 
-// two workgroups per CU: at most 256 registers per lane
-template <bool F4>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+// One workgroup per CU, one wave per SIMD: 512 registers per lane, the 256
+// accumulators in the accumulation registers.  LDS: 2 x 64 KiB of stages.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_gram_mfma_big(ClassArgs a) {
-  __shared__ uint32_t sR[BR * BLDW];
-  __shared__ uint32_t sC[BC * BLDW];
-  gram_tiles_big<F4>(a, sR, sC);
+  __shared__ uint4 sb0[BROWS * DCH];
+  __shared__ uint4 sb1[BROWS * DCH];
+  __shared__ uint4 smask[3 * DCH];
+  gram_tiles_big(a, sb0, sb1, smask);
 }
 
 }  // namespace
 
-void launch_gram_mfma_big(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s) {
+void launch_gram_mfma_big(const ClassArgs& a, uint32_t grid, hipStream_t s) {
   if (grid == 0) return;
-  if (fp4) k_gram_mfma_big<true><<<grid, 256, 0, s>>>(a);
-  else k_gram_mfma_big<false><<<grid, 256, 0, s>>>(a);
+  k_gram_mfma_big<<<grid, 256, 0, s>>>(a);
   BM_LAUNCH_CHECK();
 }
 

@@ -185,9 +185,9 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
         loc[ST_CAND_M + kind] += tsz;
         loc[ST_COLS_M + kind] += kc + k;
         loc[ST_CLS_M + kind] += 1;
-        // 128-wide tile pairs: also a bound on a big class's 256-wide half tasks;
         // 16-wide block pairs: also a bound on a mid-size class's 32-wide ones
-        if (kind == 0 || kind == 3) loc[NC_PAIRS_M] += mfma_pairs(kc);
+        if (kind == 0) loc[NC_PAIRS_M] += mfma_pairs(kc);
+        else if (kind == 3) loc[NC_PAIRS_B] += mfma_pairs(kc, GRAM_TILE_BIG);
         else if (kind == 1 || kind == 4) loc[NC_PAIRS_V] += andpop_pairs(kc);
         else loc[NC_TINY] += 1;
       }
@@ -234,19 +234,15 @@ __device__ inline void fill_level_body(const LevelPost& a, uint64_t t0, uint64_t
 }
 
 // Task records of one class: block pairs (bi <= bl, row-major) x word splits.
-// With halves = 2 every block pair is two tasks, one per half of its rows:
-// bi then counts half blocks (bi = 2 * block + half).  Lanes stride over the
-// class's tasks.
+// Lanes stride over the class's tasks.
 __device__ void write_tasks(uint32_t ci, uint32_t q, uint32_t npairs, uint32_t block,
                             uint32_t nsplit, uint32_t split_len, uint32_t wend, Task* out,
-                            int lane, int nl, uint32_t halves = 1) {
+                            int lane, int nl) {
   const uint32_t nb = (q + block - 1) / block;
   const uint64_t total = (uint64_t)npairs * nsplit;
   for (uint64_t t = lane; t < total; t += nl) {
     uint32_t tp = (uint32_t)(t / nsplit);
     const uint32_t sp = (uint32_t)(t % nsplit);
-    const uint32_t half = tp % halves;
-    tp /= halves;
     uint32_t bi = 0;
     while (tp >= nb - bi) {
       tp -= nb - bi;
@@ -254,7 +250,7 @@ __device__ void write_tasks(uint32_t ci, uint32_t q, uint32_t npairs, uint32_t b
     }
     Task k;
     k.cls = ci;
-    k.bi = (uint16_t)(bi * halves + half);
+    k.bi = (uint16_t)bi;
     k.bl = (uint16_t)(bi + tp);
     k.w0 = sp * split_len;
     k.w1 = min(wend, (sp + 1) * split_len);
@@ -284,8 +280,8 @@ __device__ inline ClassWork class_work(const ClassDesc& cd, const DbInfo& d, uin
     w.npairs = mfma_pairs(cd.q);
     w.split = geo.split_m;
     w.block = GRAM_TILE;
-  } else if (w.kind == 3) {  // a task is one half (128 rows) of a 256 x 256 block pair
-    w.npairs = 2 * mfma_pairs(cd.q, GRAM_TILE_BIG);
+  } else if (w.kind == 3) {  // 256 x 256 block pairs
+    w.npairs = mfma_pairs(cd.q, GRAM_TILE_BIG);
     w.split = geo.split_b;
     w.block = GRAM_TILE_BIG;
   } else if (w.kind == 4) {
@@ -326,6 +322,21 @@ __global__ void k_class_task_counts(const ClassDesc* __restrict__ cls, uint64_t 
   }
 }
 
+__global__ void k_task_costs(const Task* __restrict__ tasks, const uint64_t* __restrict__ ntasks,
+                             uint64_t ub, uint32_t w_off, uint32_t w_diag,
+                             uint32_t* __restrict__ cost) {
+  const uint64_t n = *ntasks;
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ub;
+       t += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t c = 0;
+    if (t < n) {
+      const Task k = tasks[t];
+      c = (k.w1 - k.w0) / GRAM_KW * (k.bi == k.bl ? w_diag : w_off);
+    }
+    cost[t] = c;
+  }
+}
+
 // Workgroup per class: write its tasks at the scanned offsets (with dfs set, small
 // classes become depth-first subtree tasks whose children are level `level`).
 __global__ void k_write_class_tasks(const ClassDesc* __restrict__ cls, uint64_t ncls,
@@ -362,7 +373,7 @@ __global__ void k_write_class_tasks(const ClassDesc* __restrict__ cls, uint64_t 
                 : w.kind == 3 ? tb + ob[c]
                               : ts + os[c];
     write_tasks((uint32_t)c, cd.q, w.npairs, w.block, w.nsplit, w.split, w.wend, out, lane,
-                (int)blockDim.x, w.kind == 3 ? 2u : 1u);
+                (int)blockDim.x);
   }
 }
 
@@ -635,6 +646,13 @@ void launch_write_class_tasks(const ClassDesc* cls, uint64_t ncls, const DbInfo*
   if (ncls == 0) return;
   k_write_class_tasks<<<grid_for(ncls, 1), kThreads, 0, s>>>(
       cls, ncls, dbs, views, mfma_min_q, geo, om, ov, ot, tm, tv, tt, dt, level, ob, tb, os, ts);
+  BM_LAUNCH_CHECK();
+}
+
+void launch_task_costs(const Task* tasks, const uint64_t* ntasks, uint64_t ub, uint32_t w_off,
+                       uint32_t w_diag, uint32_t* cost, hipStream_t s) {
+  if (ub == 0) return;
+  k_task_costs<<<grid_for(ub, kThreads), kThreads, 0, s>>>(tasks, ntasks, ub, w_off, w_diag, cost);
   BM_LAUNCH_CHECK();
 }
 

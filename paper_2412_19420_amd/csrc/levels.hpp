@@ -49,13 +49,14 @@ struct TaskGeom {
 // 2 = register AND+popcount, 3 = MFMA 256-wide tiles, 4 = MFMA 32-wide tiles).
 enum { ST_CAND_M = 0, ST_CAND_V, ST_CAND_T, ST_CAND_B, ST_CAND_S, ST_COLS_M, ST_COLS_V, ST_COLS_T,
        ST_COLS_B, ST_COLS_S, ST_CLS_M, ST_CLS_V, ST_CLS_T, ST_CLS_B, ST_CLS_S, ST_COUNT };
-// The node-count kernel also sums the next step's task-count bounds: 128-wide
-// tile pairs, 16-wide block pairs and tiny classes (sizes for the task lists),
+// The node-count kernel also sums the next step's task counts: 128-wide tile
+// pairs, 16-wide block pairs and tiny classes (sizes for the task lists), the
+// 256-wide tile pairs of big classes (NC_PAIRS_B, at the end),
 // and for the projected classes on the 128-wide (M) and 256-wide (B) kernels
 // their candidates and work (the prefix's support times the class's
 // candidates), and their children.
 enum { NC_PAIRS_M = ST_COUNT, NC_PAIRS_V, NC_TINY, NC_PJ_CAND_M, NC_PJ_WORK_M, NC_PJ_CAND_B,
-       NC_PJ_WORK_B, NC_PJ_COLS, NC_COUNT };
+       NC_PJ_WORK_B, NC_PJ_COLS, NC_PAIRS_B, NC_COUNT };
 
 // Whether a class of q children whose prefix has support s_prefix (in a
 // database of n transactions) is projected: its children's columns are
@@ -184,8 +185,8 @@ void launch_expand_pairs(uint32_t k, const uint32_t* items, const uint32_t* cols
                          const uint32_t* tri, uint32_t* out, hipStream_t s);
 
 // Host-side helpers shared by the miner and the pair-support call.
-inline uint32_t host_mfma_pairs(uint32_t q) {
-  const uint32_t nb = (q + GRAM_TILE - 1) / GRAM_TILE;
+inline uint32_t host_mfma_pairs(uint32_t q, uint32_t tile = GRAM_TILE) {
+  const uint32_t nb = (q + tile - 1) / tile;
   return nb * (nb + 1) / 2;
 }
 // Kernel that evaluates a class of q children: 0 = MFMA (128-wide tiles),

@@ -270,8 +270,8 @@ uint64_t round_up(uint64_t a, uint64_t b) { return ceil_div(a, b) * b; }
 
 // Word-split lengths for a step: enough tasks to fill the chip, not shorter
 // than a minimum that keeps per-task overheads small.
-TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_v, uint64_t classes_t,
-                   const Tuning& tu) {
+TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_b, uint64_t pairs_v,
+                   uint64_t classes_t, const Tuning& tu) {
   const uint64_t target = (uint64_t)cu_count() * 8;
   const uint64_t W = std::max<uint64_t>(1, Wmax);
   TaskGeom g{};
@@ -286,8 +286,27 @@ TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_v, uint64_t c
   g.split_m = (uint32_t)pick(pairs_m, 1024, GRAM_KW);
   g.split_v = (uint32_t)pick(pairs_v, 512, 1);
   g.split_t = (uint32_t)pick(classes_t, 2048, 64);  // tiny-class loads read 4-word groups
-  // a 128 x 256 task holds about two 128-wide tiles: split its words further
-  g.split_b = (uint32_t)pick((pairs_m + 1) / 2, 256, GRAM_KW);
+  // 256-wide tiles run one workgroup per CU and end in 64K atomic adds each:
+  // a few long tasks per CU, the split count chosen so that the tasks fill
+  // whole rounds of the CUs (rounds x task length, plus about 128 words of
+  // per-task cost, is least)
+  g.split_b = GRAM_KW;
+  if (tu.split_words) {
+    g.split_b = (uint32_t)round_up(tu.split_words, GRAM_KW);
+  } else if (pairs_b) {
+    const uint64_t slots = (uint64_t)cu_count();
+    const uint64_t ns_max = std::max<uint64_t>(1, std::min<uint64_t>(64, W / 512));
+    uint64_t best = 1;
+    double best_cost = 1e300;
+    for (uint64_t ns = 1; ns <= ns_max; ++ns) {
+      const double cost = (double)ceil_div(pairs_b * ns, slots) * ((double)W / ns + 128.0);
+      if (cost < best_cost * 0.999) {
+        best_cost = cost;
+        best = ns;
+      }
+    }
+    g.split_b = (uint32_t)round_up(ceil_div(W, best), GRAM_KW);
+  }
   // 32-wide block pairs number about a quarter of the 16-wide ones, and each
   // is one wave's task: two per workgroup slot (measured 8% faster on the
   // T40-style workload than four, and no slower on the dense one)
@@ -311,6 +330,7 @@ struct StepWork {
   TBuf<Task> tm, tv, tt, tb, ts;
   uint64_t ub_m = 0, ub_v = 0, ub_t = 0, ub_b = 0, ub_s = 0;  // task-count upper bounds (host)
   TBuf<uint64_t> om, ov, ot, ob, os;  // task offsets per class (+ total at [ncls])
+  TBuf<uint64_t> pcm, pcb;  // FP4 Gram kernels: prefix sums of the task costs (tm, tb)
   TBuf<uint32_t> tri;
   uint64_t T = 0;
   uint64_t st[ST_COUNT] = {};
@@ -329,13 +349,13 @@ struct StepWork {
 // Task lists of a step's classes: counts per class on the device, scanned
 // offsets, then the records.  The kernels read the totals from device memory;
 // the host only sizes buffers from upper bounds.
-void prepare_tasks(StepWork& w, const DbInfo* ddb, uint64_t Wmax, uint64_t pairs_m,
+void prepare_tasks(StepWork& w, const DbInfo* ddb, uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_b,
                    uint64_t pairs_v, uint64_t classes_t, const Tuning& tu, bool dfs, uint32_t level,
                    hipStream_t s) {
-  const TaskGeom g = make_geom(Wmax, pairs_m, pairs_v, classes_t, tu);
+  const TaskGeom g = make_geom(Wmax, pairs_m, pairs_b, pairs_v, classes_t, tu);
   const uint64_t Wm = round_up(std::max<uint64_t>(1, Wmax), GRAM_KW);
   w.ub_m = pairs_m * ceil_div(Wm, g.split_m);
-  w.ub_b = g.big_q < 0xffffffffu ? pairs_m * ceil_div(Wm, g.split_b) : 0;
+  w.ub_b = pairs_b * ceil_div(Wm, g.split_b);
   w.ub_v = tu.mfma_small ? 0 : pairs_v * ceil_div(std::max<uint64_t>(1, Wmax), g.split_v);
   w.ub_s = tu.mfma_small ? pairs_v * ceil_div(round_up(std::max<uint64_t>(1, Wmax), GRAM_SMALL_KW),
                                               g.split_s)
@@ -371,6 +391,21 @@ void prepare_tasks(StepWork& w, const DbInfo* ddb, uint64_t Wmax, uint64_t pairs
                            w.ov.get(),
                            w.ot.get(), w.tm.get(), w.tv.get(), w.tt.get(), dfs ? w.dt.get() : nullptr,
                            level, w.ob.get(), w.tb.get(), w.os.get(), w.ts.get(), s);
+  if (tu.mfma_fp4) {  // the FP4 Gram kernels split their launch's stages evenly by cost
+    auto costs = [&](const Task* t, const uint64_t* nt, uint64_t ub, uint32_t w_off,
+                     uint32_t w_diag, TBuf<uint64_t>& P) {
+      if (!ub) return;
+      TBuf<uint32_t> c(ub, s);
+      launch_task_costs(t, nt, ub, w_off, w_diag, c.get(), s);
+      P.alloc(ub + 1, s);
+      const void* cin[1] = {c.get()};
+      const bool c64[1] = {false};
+      uint64_t* cout[1] = {P.get()};
+      scan_many(cin, c64, cout, 1, ub, s);
+    };
+    costs(w.tm.get(), w.om.get() + w.ncls, w.ub_m, GRAM_COST_OFF, GRAM_COST_DIAG, w.pcm);
+    costs(w.tb.get(), w.ob.get() + w.ncls, w.ub_b, GRAM_BIG_COST_OFF, GRAM_BIG_COST_DIAG, w.pcb);
+  }
 }
 
 // Views of the step's projected classes: each child column compressed by its
@@ -403,15 +438,22 @@ void run_class_kernels(const DbInfo* ddb, const uint32_t* child_item, const Step
   if (w.ub_b && w.st[ST_CLS_B]) {
     a.tasks = w.tb.get();
     a.ntasks = w.ob.get() + w.ncls;
+    a.tcost = w.pcb.get();
     tm.begin(BM_K_GRAM_MFMA_BIG);
-    launch_gram_mfma_big(a, (uint32_t)std::min<uint64_t>(w.ub_b, ncu * 4), tu.mfma_fp4, s);
+    // one workgroup per CU, each with an equal share of the stages
+    launch_gram_mfma_big(a, (uint32_t)ncu, s);
     tm.end(8.0 * nW * (double)w.st[ST_COLS_B], gram_ops(3, 1));
   }
   if (w.ub_m && w.st[ST_CLS_M]) {
     a.tasks = w.tm.get();
     a.ntasks = w.om.get() + w.ncls;
+    a.tcost = w.pcm.get();
     tm.begin(BM_K_GRAM_MFMA);
-    launch_gram_mfma(a, (uint32_t)std::min<uint64_t>(w.ub_m, ncu * 4), tu.mfma_fp4, s);
+    // FP4: two workgroups per CU (all resident at once), each with an equal
+    // share of the stages; int8: a grid-stride loop over the tasks
+    launch_gram_mfma(a, tu.mfma_fp4 ? (uint32_t)(ncu * 2)
+                                    : (uint32_t)std::min<uint64_t>(w.ub_m, ncu * 4),
+                     tu.mfma_fp4, s);
     tm.end(8.0 * nW * (double)w.st[ST_COLS_M], gram_ops(0, 0));
   }
   if (w.ub_s && w.st[ST_CLS_S]) {
@@ -446,14 +488,15 @@ void host_classes(StepWork& w, const std::vector<ClassDesc>& hc, const DbInfo* d
   upload(w.cls.get(), hc, s);
   w.pre.alloc(1, s);
   launch_fill_u32(w.pre.get(), 0, 1, s);
-  uint64_t pm = 0, pv = 0, ct = 0;
+  uint64_t pm = 0, pb = 0, pv = 0, ct = 0;
   w.T = 0;
   for (const auto& c : hc) {
     const uint64_t tsz = (uint64_t)c.q * (c.q - 1) / 2;
     w.T += tsz;
     const int kind =
         class_kind(c.q, tu.mfma_min_q, tu.mfma_big_q, tu.mfma_small ? 1u : 0u, tu.tiny_q);
-    if (is_mfma_kind(kind)) pm += host_mfma_pairs(c.q);
+    if (kind == 0) pm += host_mfma_pairs(c.q);
+    else if (kind == 3) pb += host_mfma_pairs(c.q, GRAM_TILE_BIG);
     else if (kind == 1 || kind == 4) pv += host_andpop_pairs(c.q);
     else ct += 1;
     w.st[ST_CAND_M + kind] += tsz;
@@ -462,7 +505,7 @@ void host_classes(StepWork& w, const std::vector<ClassDesc>& hc, const DbInfo* d
   }
   w.tri.alloc(w.T, s);
   launch_fill_u32(w.tri.get(), 0, w.T, s);
-  prepare_tasks(w, ddb, Wmax, pm, pv, ct, tu, dfs, 1, s);
+  prepare_tasks(w, ddb, Wmax, pm, pb, pv, ct, tu, dfs, 1, s);
 }
 
 struct Level {
@@ -510,6 +553,7 @@ Tuning tuning_from(const bm_options* opt) {
   if (opt->flags & BM_FLAG_NO_PROJECT) t.project_gain = 0;
   if (opt->flags & BM_FLAG_FP4_MFMA) t.mfma_fp4 = true;
   if (opt->flags & BM_FLAG_INT8_MFMA) t.mfma_fp4 = false;
+  if (!t.mfma_fp4) t.mfma_big_q = 0xffffffffu;  // the 256-wide kernel has the FP4 form only
   if (opt->flags & BM_FLAG_NO_MFMA) {
     t.mfma_min_q = 0xffffffffu;
     t.mfma_small = false;
@@ -1150,7 +1194,8 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         st.host_syncs++;
         const uint64_t n_next = tot[0], ncls = tot[1], Tn = tot[2];
         const uint64_t* stt = tot + nscan;  // the step counters
-        const uint64_t PM = stt[NC_PAIRS_M], PV = stt[NC_PAIRS_V], PT = stt[NC_TINY];
+        const uint64_t PM = stt[NC_PAIRS_M], PB = stt[NC_PAIRS_B], PV = stt[NC_PAIRS_V],
+                       PT = stt[NC_TINY];
         if (n_next == 0) break;
         if (k + 1 > BM_MAX_LEVELS)
           fail(BM_ERR_UNSUPPORTED, "frequent itemsets longer than %d items", BM_MAX_LEVELS);
@@ -1201,7 +1246,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         lp.pcls_out = pcls_k.get();
         lp.ztri = nw->tri.get();
         lp.nz = Tn;
-        lp.geo = make_geom(Wmax, PM, PV, PT, tu);
+        lp.geo = make_geom(Wmax, PM, PB, PV, PT, tu);
         lp.mfma_min_q = tu.mfma_min_q;
         lp.dfs = tu.dfs ? 1u : 0u;
         for (auto& c : nw->ccount) c.alloc(ncls, s);
@@ -1240,7 +1285,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
           lp.pwork = nw->pwork.get();
         }
         launch_level_post(lp, s);
-        prepare_tasks(*nw, ddb_p, Wmax, PM, PV, PT, tu, tu.dfs, k + 1, s);
+        prepare_tasks(*nw, ddb_p, Wmax, PM, PB, PV, PT, tu, tu.dfs, k + 1, s);
         tm.end();
         w = std::move(nw);
         pcls_prev = pcls_k;

@@ -242,14 +242,15 @@ def _load_full_fixture(name):
             int(z["candidates"][0]), str(z["input_sha256"][0]))
 
 
-def _full_exact(bm, k, fixture, certify_sample):
+def _full_exact(bm, k, fixture, certify_sample, **opts):
     from golden.make_full_fixtures import input_digest
     db = gen.make_config(k)
     want, cands, in_sha = _load_full_fixture(fixture)
     assert input_digest(db) == in_sha, "the generator no longer yields the fixture's input"
-    print(f"workload {k} full size: n={db.n} m={db.m} nnz={db.nnz}", flush=True)
+    print(f"workload {k} full size: n={db.n} m={db.m} nnz={db.nnz} options {opts}", flush=True)
     h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
-    r = bm.bm_mine_ex(h, db.minsup, bm.options(flags=bm.FLAG_TIMING))
+    flags = opts.pop("flags", 0)
+    r = bm.bm_mine_ex(h, db.minsup, bm.options(flags=flags | bm.FLAG_TIMING, **opts))
     got = r.arrays()
     st = r.stats()
     print(f"mined {len(got[2])} sets, {st['candidates_total']} candidates, {st['wall_ms']:.1f} ms",
@@ -268,6 +269,14 @@ def _full_exact(bm, k, fixture, certify_sample):
 def test_mine_dense_planted_full_exact(bm):
     _, _, st = _full_exact(bm, 3, "full_dense_planted_1M.npz", 3000)
     assert st["n_frequent_items"] > 2000
+
+
+@pytest.mark.parametrize("big", [1000, 0xFFFFFFFF])
+def test_mine_dense_planted_full_exact_tile_widths(bm, big):
+    # the root class (2,187 children) on the 256-wide tiles (big = 1000) and on
+    # the 128-wide ones (big off), against the same stored arrays
+    _, _, st = _full_exact(bm, 3, "full_dense_planted_1M.npz", 500, mfma_big_children=big)
+    assert (st["kernel_launches"]["gram_mfma_big"] > 0) == (big == 1000)
 
 
 def test_mine_quest_long_full_exact(bm):
@@ -560,6 +569,23 @@ def test_subset_counters_at_their_16_bit_limit(bm):
     r = bm.bm_mine_ex(h, 1, bm.options(split_words=1 << 19))
     assert r.stats()["dfs_tasks"] == 1
     assert r.to_list() == [((0,), n), ((0, 1), n), ((1,), n)]
+
+
+@pytest.mark.parametrize("big", [2, 130, 257])
+def test_mine_dense_reduced_big_tiles_exact(bm, big):
+    # every class of at least `big` children on the 256-wide tiles: partial last
+    # tiles, diagonal and off-diagonal block pairs, prefixes of every length
+    db = gen.dense_planted(seed=5, n=60_000, m=1200, n_patterns=50, pat_rate=0.03,
+                           minsup_ppm=12_000)
+    _, want, cands = oracle_arrays(db, db.minsup)
+    print(f"dense reduced, big tiles from {big} children: n={db.n} m={db.m}", flush=True)
+    h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
+    for flags in (bm.FLAG_LEVELSYNC, 0):
+        r = bm.bm_mine_ex(h, db.minsup, bm.options(flags | bm.FLAG_TIMING | bm.FLAG_ALL_MFMA,
+                                                   mfma_big_children=big))
+        assert r.stats()["kernel_launches"]["gram_mfma_big"] > 0
+        assert_same(r.arrays(), want)
+        assert r.stats()["candidates_total"] == cands
 
 
 def test_fp4_and_int8_identical_on_full_dense(bm):
