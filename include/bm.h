@@ -150,7 +150,7 @@ typedef struct {
                                * take subset counting (0 = default 4,096; 0xffffffff = always
                                * short) */
   uint32_t mfma_big_children; /* MFMA classes with at least this many children use 256-wide
-                               * tiles (0 = default: never) */
+                               * tiles, FP4 form only (0 = default: never) */
   uint32_t dfs_wave_max_words;/* subtree tasks of databases with at most this many words per
                                * column run one stack per wave, the others one per workgroup
                                * (0 = default 1024; see BM_FLAG_DFS_BLOCK_ONLY) */

@@ -112,7 +112,8 @@ __device__ __forceinline__ void big_stage(const uint4* ra, const uint4* rb, cons
 }
 
 struct BigTask {
-  const uint64_t* src[BLOADS];  // this lane's chunk of each load instruction, at word 0
+  uint32_t col[BLOADS];         // column of this lane's row in each load instruction
+  uint32_t choff;               // word offset of this lane's chunk (the same in every row)
   const uint32_t* pre;          // prefix columns
   const uint64_t* pcol;         // this thread's first prefix column (j = tid / 8) at chunk tid % 8
   uint32_t pre_len;
@@ -130,7 +131,7 @@ __device__ __forceinline__ void big_issue(const BigTask& k, uint32_t w, uint4* b
 #pragma unroll
   for (int r = 0; r < BLOADS; ++r)
     if (r < k.nload)
-      __builtin_amdgcn_global_load_lds(k.src[r] + w,
+      __builtin_amdgcn_global_load_lds(k.B + (uint64_t)k.col[r] * k.Wp + k.choff + w,
                                        dst + ((r >= 8) ? BT * DCH : 0) + 8 * (r & 7) * DCH, 16, 0,
                                        0);
 }
@@ -206,28 +207,23 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint4* sb0, u
     if ((uint32_t)tid / 8 < k.pre_len)
       k.pcol = k.B + (uint64_t)k.pre[tid / 8] * k.Wp + 2 * (tid & 7);
     // Lane L of load instruction r fetches the chunk for slot L % 8 of panel
-    // row 64 w + 8 (r % 8) + L / 8.  Children beyond q load column q - 1:
-    // their rows and columns of the tile are never written out.
-    uint32_t col[BLOADS];
+    // row 64 w + 8 (r % 8) + L / 8, i.e. chunk (L % 8) ^ (L / 8 % 8) of that
+    // row's column.  Children beyond q load column q - 1: their rows and
+    // columns of the tile are never written out.
 #pragma unroll
     for (int r = 0; r < BLOADS; ++r) {
       const uint32_t idx = ((r >= 8) ? L0 : I0) + 64 * wave + 8 * (r & 7) + (lane >> 3);
-      col[r] = idx < q ? idx : q - 1;
+      k.col[r] = idx < q ? idx : q - 1;
     }
     if (!cd.proj) {
 #pragma unroll
-      for (int r = 0; r < BLOADS; ++r) col[r] = a.child_item[cd.child0 + col[r]];
+      for (int r = 0; r < BLOADS; ++r) k.col[r] = a.child_item[cd.child0 + k.col[r]];
       if (db.f1) {
 #pragma unroll
-        for (int r = 0; r < BLOADS; ++r) col[r] = load_global_u32(db.f1 + col[r]);
+        for (int r = 0; r < BLOADS; ++r) k.col[r] = load_global_u32(db.f1 + k.col[r]);
       }
     }
-#pragma unroll
-    for (int r = 0; r < BLOADS; ++r) {
-      const uint32_t row = 64 * wave + 8 * (r & 7) + (lane >> 3);
-      const uint32_t chunk = (uint32_t)((lane & 7) ^ (row & 7));
-      k.src[r] = db.B + (uint64_t)col[r] * k.Wp + 2 * chunk;
-    }
+    k.choff = 2 * (uint32_t)((lane & 7) ^ ((lane >> 3) & 7));
 
     v16f acc[4][4];
 #pragma unroll
