@@ -298,7 +298,9 @@ bool scan_multi_tiles(const ScanMulti& sm, int count, uint64_t n, uint64_t* tmp,
 // class kernels
 // fp4: the scaled e2m1 MFMA form (64 transactions per instruction, exact FP32
 // integer sums for counts up to 2^24); else int8 x int8 -> int32.
-void launch_gram_mfma(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s);
+// masked: some class of the launch has a prefix (FP4 form: without, a lighter
+// kernel that never reads a mask; every class must then have none)
+void launch_gram_mfma(const ClassArgs& a, uint32_t grid, bool fp4, bool masked, hipStream_t s);
 // Same contraction with 256 x 256 tiles (tasks index 256-wide blocks).
 void launch_gram_mfma_big(const ClassArgs& a, uint32_t grid, hipStream_t s);  // FP4 form only
 // Cost of each FP4 Gram task: its stages (GRAM_KW words each) times w_diag on

@@ -137,6 +137,9 @@ __device__ __forceinline__ void pack_tile(PackSmem<ECAP>& sm, const uint64_t* __
   const uint64_t e1 = max(e0, s_rp[nr]);
   const uint32_t nwin = (m + PK_CW - 1) / PK_CW;
   const bool single_chunk = e1 - e0 <= ECAP;
+  // the bitmap starts clear; each window's write-out clears what it read, so
+  // a window needs no clearing pass (and no barrier for one)
+  for (int i = tid; i < PK_CW * PK_LD; i += PK_T) X[i] = 0ull;
   for (uint64_t ea = e0; ea < e1 || (ea == e0 && e0 == e1); ea += ECAP) {
     const uint64_t eb = min<uint64_t>(e1, ea + ECAP);
     const int ne = (int)(eb - ea);
@@ -171,13 +174,10 @@ __device__ __forceinline__ void pack_tile(PackSmem<ECAP>& sm, const uint64_t* __
       }
       for (; e < b; ++e) s_e[e - ea] |= (uint32_t)r;
     }
+    __syncthreads();  // rows filled in before the window passes read the entries
     for (uint32_t win = 0; win < nwin; ++win) {
       const uint32_t c0 = win * PK_CW;
       const uint32_t cw = min<uint32_t>(PK_CW, m - c0);
-      if (single_chunk || ea == e0) {
-        for (int i = tid; i < PK_CW * PK_LD; i += PK_T) X[i] = 0ull;
-      }
-      __syncthreads();
       if (!single_chunk && ea != e0) {
         // several chunks: accumulate this window on top of what B already holds
         const int wi = tid & (PK_KR - 1), cs = tid / PK_KR;
@@ -207,6 +207,7 @@ __device__ __forceinline__ void pack_tile(PackSmem<ECAP>& sm, const uint64_t* __
       const int wi = tid & (PK_KR - 1), cs = tid / PK_KR;
       for (uint32_t c = cs; c < cw; c += PK_T / PK_KR) {
         const unsigned long long v = X[c * PK_LD + wi];
+        X[c * PK_LD + wi] = 0ull;  // clear for the next window as it is written out
         B[(uint64_t)(c0 + c) * Wp + blk * PK_KR + wi] = v;
         if (last) {
           uint32_t pc = (uint32_t)__popcll(v);

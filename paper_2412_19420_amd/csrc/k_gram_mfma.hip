@@ -247,8 +247,11 @@ __device__ __forceinline__ void fp4_group(const uint4 (&a)[2], const uint4 (&b)[
 // One stage of one wave: four word groups, the next group's operands read
 // from LDS before the current group's MFMAs.  ra / rb: the wave's first A and
 // B rows at this lane (row l % 32 of the first block), in chunks; mk: the
-// stage's mask row.
-template <int MODE>
+// stage's mask row, read only with MASK.  Launches whose classes have no
+// prefix (the root classes) use a kernel without the mask reads and ANDs: 5%
+// faster on the dense root, and the masked code paths in the same kernel would
+// cost the unmasked ones registers.
+template <int MODE, bool MASK>
 __device__ __forceinline__ void fp4_stage(const uint4* ra, const uint4* rb, const uint4* mk,
                                           int lane, v16f (&acc)[2][2]) {
   constexpr int NA = MODE == 2 ? 1 : 2;
@@ -262,7 +265,7 @@ __device__ __forceinline__ void fp4_stage(const uint4* ra, const uint4* rb, cons
       xa[i] = i < NA ? ra[i * 32 * DCH + (c ^ sw)] : make_uint4(0, 0, 0, 0);
       xb[i] = BSAME ? make_uint4(0, 0, 0, 0) : rb[i * 32 * DCH + (c ^ sw)];
     }
-    xm = mk[c];
+    xm = MASK ? mk[c] : make_uint4(~0u, ~0u, ~0u, ~0u);
   };
   read(0, a, b, m);
 #pragma unroll
@@ -308,6 +311,7 @@ __device__ __forceinline__ void fp4_issue(const Fp4Task& k, uint32_t w, uint4* b
 
 // Stage s of a task: wait for its loads (the barrier), start stage s + 1's
 // loads into the other buffer, multiply stage s.
+template <bool MASK>
 __device__ __forceinline__ void fp4_stage_step(const Fp4Task& k, uint32_t s, const uint4* cur,
                                                uint4* nxt, uint4* smask, int tid,
                                                v16f (&acc)[2][2]) {
@@ -331,15 +335,16 @@ __device__ __forceinline__ void fp4_stage_step(const Fp4Task& k, uint32_t s, con
   // a wave in its MFMA section outranks the other workgroup's waves that are
   // issuing loads
   __builtin_amdgcn_s_setprio(3);
-  if (k.mode == 0) fp4_stage<0>(ra, rb, mk, lane, acc);
-  else if (k.mode == 1) fp4_stage<1>(ra, rb, mk, lane, acc);
-  else fp4_stage<2>(ra, rb, mk, lane, acc);
+  if (k.mode == 0) fp4_stage<0, MASK>(ra, rb, mk, lane, acc);
+  else if (k.mode == 1) fp4_stage<1, MASK>(ra, rb, mk, lane, acc);
+  else fp4_stage<2, MASK>(ra, rb, mk, lane, acc);
   __builtin_amdgcn_s_setprio(0);
 
   if (pre_thread)
     fp4_mask_and(pm, k.B, k.Wp, k.pre, k.pre_len, pj0, pch, wn, smask + ((s + 1) % 3) * DCH);
 }
 
+template <bool MASK>
 __device__ __forceinline__ void gram_tiles_fp4(const ClassArgs& a, uint4* sb0, uint4* sb1,
                                                uint4* smask) {
   constexpr int T = GRAM_TILE;  // 128 children per tile side
@@ -421,8 +426,8 @@ __device__ __forceinline__ void gram_tiles_fp4(const ClassArgs& a, uint4* sb0, u
     }
     // even stages read sb0 and load into sb1, odd stages the other way round
     for (uint32_t s = 0; s < k.nst; s += 2) {
-      fp4_stage_step(k, s, sb0, sb1, smask, tid, acc);
-      if (s + 1 < k.nst) fp4_stage_step(k, s + 1, sb1, sb0, smask, tid, acc);
+      fp4_stage_step<MASK>(k, s, sb0, sb1, smask, tid, acc);
+      if (s + 1 < k.nst) fp4_stage_step<MASK>(k, s + 1, sb1, sb0, smask, tid, acc);
     }
 
     // 32x32 accumulator layout: lane holds column (lane & 31); register r holds
@@ -445,7 +450,7 @@ __device__ __forceinline__ void gram_tiles_fp4(const ClassArgs& a, uint4* sb0, u
 // Two workgroups per CU (two waves per SIMD; LDS: 2 x 64 KiB of stages): the
 // register budget is capped at 256 so the three stage variants do not push the
 // kernel to one wave.
-template <bool F4>
+template <bool F4, bool MASK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_gram_mfma(ClassArgs a) {
   if constexpr (F4) {
@@ -453,7 +458,7 @@ void k_gram_mfma(ClassArgs a) {
     __shared__ uint4 sb0[2 * GRAM_TILE * DCH];
     __shared__ uint4 sb1[2 * GRAM_TILE * DCH];
     __shared__ uint4 smask[3 * DCH];
-    gram_tiles_fp4(a, sb0, sb1, smask);
+    gram_tiles_fp4<MASK>(a, sb0, sb1, smask);
   } else {
     constexpr int KW = 16;
     __shared__ uint32_t sA[GRAM_TILE * (2 * KW + 1)];
@@ -464,10 +469,11 @@ void k_gram_mfma(ClassArgs a) {
 
 }  // namespace
 
-void launch_gram_mfma(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s) {
+void launch_gram_mfma(const ClassArgs& a, uint32_t grid, bool fp4, bool masked, hipStream_t s) {
   if (grid == 0) return;
-  if (fp4) k_gram_mfma<true><<<grid, 256, 0, s>>>(a);
-  else k_gram_mfma<false><<<grid, 256, 0, s>>>(a);
+  if (fp4 && masked) k_gram_mfma<true, true><<<grid, 256, 0, s>>>(a);
+  else if (fp4) k_gram_mfma<true, false><<<grid, 256, 0, s>>>(a);
+  else k_gram_mfma<false, true><<<grid, 256, 0, s>>>(a);
   BM_LAUNCH_CHECK();
 }
 

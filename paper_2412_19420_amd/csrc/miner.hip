@@ -270,8 +270,8 @@ uint64_t round_up(uint64_t a, uint64_t b) { return ceil_div(a, b) * b; }
 
 // Word-split lengths for a step: enough tasks to fill the chip, not shorter
 // than a minimum that keeps per-task overheads small.
-TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_b, uint64_t pairs_v,
-                   uint64_t classes_t, const Tuning& tu) {
+TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_v, uint64_t classes_t,
+                   const Tuning& tu) {
   const uint64_t target = (uint64_t)cu_count() * 8;
   const uint64_t W = std::max<uint64_t>(1, Wmax);
   TaskGeom g{};
@@ -281,32 +281,20 @@ TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_b, uint64_t p
     ns = std::min<uint64_t>(ns, std::max<uint64_t>(1, W / min_len));
     return round_up(ceil_div(W, ns), align);
   };
-  // at least 1,024 words: each task ends in 16K atomic adds of its tile, so
-  // short ones (the T40-style level 4 got 489 words) pay for them twice over
-  g.split_m = (uint32_t)pick(pairs_m, 1024, GRAM_KW);
+  // The FP4 Gram kernels split each launch's stages evenly over their
+  // workgroups by cost, whatever the task lengths, so their tasks are whole
+  // block pairs (up to the FP4 word cap below): every task boundary a
+  // workgroup crosses costs a flush of 16K (128-wide) or 64K (256-wide)
+  // atomic adds.  The int8 form deals tasks out round-robin: enough of them
+  // to fill the chip, at least 1,024 words each (the flush paid twice over
+  // below that).
+  const uint32_t whole = (uint32_t)round_up(W, GRAM_KW);
+  g.split_m = tu.split_words ? (uint32_t)round_up(tu.split_words, GRAM_KW)
+              : tu.mfma_fp4  ? whole
+                             : (uint32_t)pick(pairs_m, 1024, GRAM_KW);
   g.split_v = (uint32_t)pick(pairs_v, 512, 1);
   g.split_t = (uint32_t)pick(classes_t, 2048, 64);  // tiny-class loads read 4-word groups
-  // 256-wide tiles run one workgroup per CU and end in 64K atomic adds each:
-  // a few long tasks per CU, the split count chosen so that the tasks fill
-  // whole rounds of the CUs (rounds x task length, plus about 128 words of
-  // per-task cost, is least)
-  g.split_b = GRAM_KW;
-  if (tu.split_words) {
-    g.split_b = (uint32_t)round_up(tu.split_words, GRAM_KW);
-  } else if (pairs_b) {
-    const uint64_t slots = (uint64_t)cu_count();
-    const uint64_t ns_max = std::max<uint64_t>(1, std::min<uint64_t>(64, W / 512));
-    uint64_t best = 1;
-    double best_cost = 1e300;
-    for (uint64_t ns = 1; ns <= ns_max; ++ns) {
-      const double cost = (double)ceil_div(pairs_b * ns, slots) * ((double)W / ns + 128.0);
-      if (cost < best_cost * 0.999) {
-        best_cost = cost;
-        best = ns;
-      }
-    }
-    g.split_b = (uint32_t)round_up(ceil_div(W, best), GRAM_KW);
-  }
+  g.split_b = tu.split_words ? (uint32_t)round_up(tu.split_words, GRAM_KW) : whole;
   // 32-wide block pairs number about a quarter of the 16-wide ones, and each
   // is one wave's task: two per workgroup slot (measured 8% faster on the
   // T40-style workload than four, and no slower on the dense one)
@@ -325,6 +313,7 @@ TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_b, uint64_t p
 // Device-side work of one level step.
 struct StepWork {
   uint64_t ncls = 0;
+  bool prefixed = true;  // some class may have a prefix (the FP4 Gram kernels then apply masks)
   TBuf<ClassDesc> cls;
   TBuf<uint32_t> pre;
   TBuf<Task> tm, tv, tt, tb, ts;
@@ -352,7 +341,7 @@ struct StepWork {
 void prepare_tasks(StepWork& w, const DbInfo* ddb, uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_b,
                    uint64_t pairs_v, uint64_t classes_t, const Tuning& tu, bool dfs, uint32_t level,
                    hipStream_t s) {
-  const TaskGeom g = make_geom(Wmax, pairs_m, pairs_b, pairs_v, classes_t, tu);
+  const TaskGeom g = make_geom(Wmax, pairs_m, pairs_v, classes_t, tu);
   const uint64_t Wm = round_up(std::max<uint64_t>(1, Wmax), GRAM_KW);
   w.ub_m = pairs_m * ceil_div(Wm, g.split_m);
   w.ub_b = pairs_b * ceil_div(Wm, g.split_b);
@@ -453,7 +442,7 @@ void run_class_kernels(const DbInfo* ddb, const uint32_t* child_item, const Step
     // share of the stages; int8: a grid-stride loop over the tasks
     launch_gram_mfma(a, tu.mfma_fp4 ? (uint32_t)(ncu * 2)
                                     : (uint32_t)std::min<uint64_t>(w.ub_m, ncu * 4),
-                     tu.mfma_fp4, s);
+                     tu.mfma_fp4, w.prefixed, s);
     tm.end(8.0 * nW * (double)w.st[ST_COLS_M], gram_ops(0, 0));
   }
   if (w.ub_s && w.st[ST_CLS_S]) {
@@ -484,6 +473,8 @@ void run_class_kernels(const DbInfo* ddb, const uint32_t* child_item, const Step
 void host_classes(StepWork& w, const std::vector<ClassDesc>& hc, const DbInfo* ddb, uint64_t Wmax,
                   const Tuning& tu, bool dfs, hipStream_t s) {
   w.ncls = hc.size();
+  w.prefixed = false;
+  for (const auto& c : hc) w.prefixed |= c.pre_len > 0;
   w.cls.alloc(w.ncls, s);
   upload(w.cls.get(), hc, s);
   w.pre.alloc(1, s);
@@ -1246,7 +1237,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         lp.pcls_out = pcls_k.get();
         lp.ztri = nw->tri.get();
         lp.nz = Tn;
-        lp.geo = make_geom(Wmax, PM, PB, PV, PT, tu);
+        lp.geo = make_geom(Wmax, PM, PV, PT, tu);
         lp.mfma_min_q = tu.mfma_min_q;
         lp.dfs = tu.dfs ? 1u : 0u;
         for (auto& c : nw->ccount) c.alloc(ncls, s);
