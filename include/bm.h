@@ -72,7 +72,8 @@ enum {
   BM_K_EMIT = 6,      /* canonical-order output (and the merge of depth-first output) */
   BM_K_DFS = 7,       /* persistent depth-first subtree kernel (small classes) */
   BM_K_SCHED = 8,     /* cost-model features, prediction and task ordering */
-  BM_K_GRAM_MFMA_BIG = 9, /* as BM_K_GRAM_MFMA with 256 x 256 tiles (classes of >= 256 children) */
+  BM_K_GRAM_MFMA_BIG = 9, /* as BM_K_GRAM_MFMA with 256 x 256 tiles (classes of at least
+                           * mfma_big_children children; FP4 form only) */
   BM_K_GRAM_SMALL = 10,   /* MFMA Gram of mid-size classes, one wave per 32 x 32 block pair */
   BM_K_PROJECT = 11,      /* projected views of big deep classes: prefix row lists and the
                            * children's columns gathered over them */
