@@ -79,12 +79,13 @@ constexpr int DCH = DKW / 2;   // 16-byte chunks per column per stage
 static_assert(GRAM_KW % DKW == 0, "stages must tile the task word ranges");
 
 // Chunk pch of the stage at word w of this thread's prefix columns j =
-// pj0, pj0 + 32, ... (pcol: column pj0 at chunk pch; pm holds the first one,
+// pj0, pj0 + stride, ... (stride = threads / 8; pm holds column pj0's chunk,
 // loaded earlier), ANDed into mask row `row`.
 __device__ __forceinline__ void fp4_mask_and(uint4 pm, const uint64_t* B, uint64_t Wp,
                                              const uint32_t* pre, uint32_t pre_len, uint32_t pj0,
-                                             uint32_t pch, uint32_t w, uint4* row) {
-  for (uint32_t j = pj0 + 32; j < pre_len; j += 32) {  // prefixes of more than 32 items
+                                             uint32_t pch, uint32_t w, uint4* row,
+                                             uint32_t stride) {
+  for (uint32_t j = pj0 + stride; j < pre_len; j += stride) {  // prefixes longer than stride
     const uint4 x = load_global16(B + (uint64_t)pre[j] * Wp + w + 2 * pch);
     pm.x &= x.x;
     pm.y &= x.y;
@@ -126,26 +127,26 @@ struct SkRange {
   uint64_t i;       // the last task with P[i] <= u0
 };
 // Called by every thread of the workgroup (it synchronises): the last i in
-// [0, n] with P[i] <= u0, by rounds of 256-way sampling.
+// [0, n] with P[i] <= u0, by rounds of blockDim.x-way sampling.
 __device__ __forceinline__ SkRange sk_range(const uint64_t* P, uint64_t n) {
   SkRange r;
   const uint64_t C = P[n];
   const uint64_t G = gridDim.x, b = blockIdx.x;
   r.u0 = C * b / G;
   r.u1 = C * (b + 1) / G;
-  const uint64_t k = threadIdx.x;
+  const uint64_t k = threadIdx.x, nt = blockDim.x;
   uint64_t lo = 0, hi = n;  // P[lo] <= u0 (P[0] = 0); the answer lies in [lo, hi]
   while (hi > lo) {
     const uint64_t m = hi - lo;  // candidates lo + 1 .. hi
-    if (m <= 256) {
+    if (m <= nt) {
       const int t = k < m && P[lo + 1 + k] <= r.u0;
       lo += (uint64_t)__syncthreads_count(t);  // the true ones are a prefix
       break;
     }
-    const uint64_t idx = lo + (k + 1) * m / 256;  // thread 255 samples hi
+    const uint64_t idx = lo + (k + 1) * m / nt;  // the last thread samples hi
     const uint64_t c = (uint64_t)__syncthreads_count(P[idx] <= r.u0);
-    const uint64_t nlo = c ? lo + c * m / 256 : lo;
-    const uint64_t nhi = c < 256 ? lo + (c + 1) * m / 256 - 1 : hi;
+    const uint64_t nlo = c ? lo + c * m / nt : lo;
+    const uint64_t nhi = c < nt ? lo + (c + 1) * m / nt - 1 : hi;
     lo = nlo;
     hi = nhi;
   }

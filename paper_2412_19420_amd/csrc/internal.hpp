@@ -302,16 +302,16 @@ bool scan_multi_tiles(const ScanMulti& sm, int count, uint64_t n, uint64_t* tmp,
 // kernel that never reads a mask; every class must then have none)
 void launch_gram_mfma(const ClassArgs& a, uint32_t grid, bool fp4, bool masked, hipStream_t s);
 // Same contraction with 256 x 256 tiles (tasks index 256-wide blocks).
-void launch_gram_mfma_big(const ClassArgs& a, uint32_t grid, hipStream_t s);  // FP4 form only
+void launch_gram_mfma_big(const ClassArgs& a, uint32_t grid, bool masked, hipStream_t s);  // FP4 only
 // Cost of each FP4 Gram task: its stages (GRAM_KW words each) times w_diag on
 // a diagonal block pair, else w_off; 0 for t in [*ntasks, ub).
 void launch_task_costs(const Task* tasks, const uint64_t* ntasks, uint64_t ub, uint32_t w_off,
                        uint32_t w_diag, uint32_t* cost, hipStream_t s);
 // Per-stage costs of the two FP4 Gram kernels, off and on the diagonal: the
-// most MFMAs any one wave issues per word group (128-wide tiles 16 / 12,
-// 256-wide tiles 64 / 40).
+// most MFMAs any one wave issues per word group (128-wide tiles 16 / 12;
+// 256-wide tiles 32 / 32, their diagonal waves computing whole grids).
 constexpr uint32_t GRAM_COST_OFF = 4, GRAM_COST_DIAG = 3;
-constexpr uint32_t GRAM_BIG_COST_OFF = 8, GRAM_BIG_COST_DIAG = 5;
+constexpr uint32_t GRAM_BIG_COST_OFF = 1, GRAM_BIG_COST_DIAG = 1;
 // Mid-size classes: one wave per 32 x 32 block pair (tasks index 32-wide blocks).
 void launch_gram_small(const ClassArgs& a, uint32_t grid, bool fp4, hipStream_t s);
 // Longest word range one MFMA task may cover in the fp4 form (2^24 transactions).

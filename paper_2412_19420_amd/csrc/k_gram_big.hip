@@ -3,46 +3,46 @@
 // all pairs of the class's children, FP4 bit planes, exact FP32 sums) on
 // 256 x 256 tiles.
 //
-// Kernel shape (gfx950, wave64): one workgroup of 4 waves per CU computes a
-// 256 x 256 block pair over a range of words; each wave owns a 128 x 128
-// quarter, a 4 x 4 grid of 32 x 32 accumulators (256 registers, which live in
-// the accumulation registers: one wave per SIMD).  Per word group a wave
-// builds 8 operand rows for 16 MFMAs (the 128-tile kernel: 4 for 4), so the
-// bit-plane VALU work per MFMA halves, and a stage of 16 words carries 256
-// MFMAs per wave between two barriers.  The panels are staged directly into
-// LDS as in the 128-tile kernel (gram_fp4.hpp): two stages of 2 x 256 rows,
-// 128 KiB.
+// Kernel shape (gfx950, wave64): one workgroup of 8 waves per CU computes a
+// 256 x 256 block pair over a range of words; wave (r, c), r < 4, c < 2, owns
+// rows 64 r .. 64 r + 63 and columns 128 c .. 128 c + 127, a 2 x 4 grid of
+// 32 x 32 accumulators (128 registers; two waves per SIMD).  Per word group a
+// wave builds 6 operand rows for 8 MFMAs (the 128-tile kernel: 4 for 4), a
+// stage of 16 words carries 128 MFMAs per wave between two barriers (64 in
+// the 128-tile kernel), and the panels of a stage (512 rows, 64 KiB) feed 8
+// waves: half the load bytes per MFMA.  Staging, swizzle and prefix masks are
+// the 128-tile kernel's (gram_fp4.hpp); two stages take 128 KiB of LDS.
 //
-// A diagonal block pair (one panel) has 36 useful 32 x 32 blocks (i <= j of
-// 8 x 8); the waves share them out 10 / 8 / 8 / 10:
-//   MODE 1 (waves 0 and 3): the upper triangle, diagonal included, of panel
-//     blocks 4h .. 4h + 3 against themselves (h = 0, 1), B taken from A;
-//   MODE 2 (waves 1 and 2): rows 2h', 2h' + 1 (h' = 0, 1) against columns
-//     4 .. 7;
-// MODE 0 (every wave of an off-diagonal pair): its 4 row blocks against its 4
-// column blocks.
+// A diagonal block pair has one panel (256 columns, loaded once and read for
+// both sides).  Its waves of columns 0 .. 127 and rows 128 .. 255 lie wholly
+// below the diagonal and only stage loads; every other wave computes its full
+// 2 x 4 grid, and the write-out keeps the pairs above the diagonal.
 #include "gram_fp4.hpp"
 
 namespace bm {
 
 namespace {
 
-constexpr int BT = GRAM_TILE_BIG;  // 256 children per tile side
-constexpr int BROWS = 2 * BT;      // staged rows per buffer (A panel, then B panel)
-constexpr int BLOADS = BROWS / 8 / 4;  // load instructions per wave per stage (16)
+constexpr int BT = GRAM_TILE_BIG;       // 256 children per tile side
+constexpr int BROWS = 2 * BT;           // staged rows per buffer (A panel, then B panel)
+constexpr int BWAVES = 8;
+constexpr int BTHREADS = 64 * BWAVES;   // 512
+constexpr int BLOADS = BROWS / 8 / BWAVES;  // load instructions per wave per stage (8)
 
-template <int MODE>
-__device__ __forceinline__ void big_group(const uint4 (&a)[4], const uint4 (&b)[4], const uint4& m,
-                                          v16f (&acc)[4][4]) {
-  constexpr int NA = MODE == 2 ? 2 : 4;  // A row blocks this wave builds
-  constexpr bool BSAME = MODE == 1;      // B operands are A's
-  uint32_t va[4][4], vb[4][4];
+// One word group: 2 A row blocks against 4 B column blocks, four planes.
+template <bool MASK>
+__device__ __forceinline__ void big_group(const uint4 (&a)[2], const uint4 (&b)[4], const uint4& m,
+                                          v16f (&acc)[2][4]) {
+  uint32_t va[2][4], vb[4][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    va[i][0] = MASK ? a[i].x & m.x : a[i].x;
+    va[i][1] = MASK ? a[i].y & m.y : a[i].y;
+    va[i][2] = MASK ? a[i].z & m.z : a[i].z;
+    va[i][3] = MASK ? a[i].w & m.w : a[i].w;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    va[i][0] = a[i].x & m.x;
-    va[i][1] = a[i].y & m.y;
-    va[i][2] = a[i].z & m.z;
-    va[i][3] = a[i].w & m.w;
     vb[i][0] = b[i].x;
     vb[i][1] = b[i].y;
     vb[i][2] = b[i].z;
@@ -50,124 +50,119 @@ __device__ __forceinline__ void big_group(const uint4 (&a)[4], const uint4 (&b)[
   }
 #pragma unroll
   for (int pl = 0; pl < 4; ++pl) {
-    v8i A[4], B[4];
+    v8i A[2], B[4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) A[i][j] = (int)fp4_plane(va[i][j], pl);
+      A[i][4] = A[i][5] = A[i][6] = A[i][7] = 0;
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        A[i][j] = i < NA ? (int)fp4_plane(va[i][j], pl) : 0;
-        B[i][j] = BSAME ? 0 : (int)fp4_plane(vb[i][j], pl);
-      }
-      A[i][4] = A[i][5] = A[i][6] = A[i][7] = 0;
+      for (int j = 0; j < 4; ++j) B[i][j] = (int)fp4_plane(vb[i][j], pl);
       B[i][4] = B[i][5] = B[i][6] = B[i][7] = 0;
     }
     const int sc = fp4_plane_scale(pl);
 #pragma unroll
-    for (int i = 0; i < NA; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if constexpr (MODE == 1) {
-          if (j >= i) acc[i][j] = fp4_mfma(A[i], A[j], acc[i][j], sc);
-        } else {
-          acc[i][j] = fp4_mfma(A[i], B[j], acc[i][j], sc);
-        }
-      }
+      for (int j = 0; j < 4; ++j) acc[i][j] = fp4_mfma(A[i], B[j], acc[i][j], sc);
   }
 }
 
 // One stage of one wave: four word groups, the next group's operands read
 // from LDS before the current group's MFMAs.  ra / rb: the wave's first A and
-// B rows at this lane, in chunks; mk: the stage's mask row.
-template <int MODE>
+// B rows at this lane, in chunks; mk: the stage's mask row (read with MASK).
+template <bool MASK>
 __device__ __forceinline__ void big_stage(const uint4* ra, const uint4* rb, const uint4* mk,
-                                          int lane, v16f (&acc)[4][4]) {
-  constexpr int NA = MODE == 2 ? 2 : 4;
-  constexpr bool BSAME = MODE == 1;
+                                          int lane, v16f (&acc)[2][4]) {
   const int kh = lane >> 5, sw = lane & 7;
-  uint4 a[4], b[4], m;
-  auto read = [&](int g, uint4 (&xa)[4], uint4 (&xb)[4], uint4& xm) {
+  uint4 a[2], b[4], m;
+  auto read = [&](int g, uint4 (&xa)[2], uint4 (&xb)[4], uint4& xm) {
     const int c = 2 * g + kh;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      xa[i] = i < NA ? ra[i * 32 * DCH + (c ^ sw)] : make_uint4(0, 0, 0, 0);
-      xb[i] = BSAME ? make_uint4(0, 0, 0, 0) : rb[i * 32 * DCH + (c ^ sw)];
-    }
-    xm = mk[c];
+    for (int i = 0; i < 2; ++i) xa[i] = ra[i * 32 * DCH + (c ^ sw)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) xb[i] = rb[i * 32 * DCH + (c ^ sw)];
+    xm = MASK ? mk[c] : make_uint4(~0u, ~0u, ~0u, ~0u);
   };
   read(0, a, b, m);
 #pragma unroll
   for (int g = 0; g < DKW / 4; ++g) {
-    uint4 na[4], nb[4], nm;
+    uint4 na[2], nb[4], nm;
     if (g + 1 < DKW / 4) read(g + 1, na, nb, nm);
-    big_group<MODE>(a, b, m, acc);
+    big_group<MASK>(a, b, m, acc);
     if (g + 1 < DKW / 4) {
+      a[0] = na[0];
+      a[1] = na[1];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = na[i];
-        b[i] = nb[i];
-      }
+      for (int i = 0; i < 4; ++i) b[i] = nb[i];
       m = nm;
     }
   }
 }
 
 struct BigTask {
-  uint32_t col[BLOADS];         // column of this lane's row in each load instruction
-  uint32_t choff;               // word offset of this lane's chunk (the same in every row)
-  const uint32_t* pre;          // prefix columns
-  const uint64_t* pcol;         // this thread's first prefix column (j = tid / 8) at chunk tid % 8
+  uint32_t col[BLOADS];  // column of this lane's row in each load instruction
+  uint32_t choff;        // word offset of this lane's chunk (the same in every row)
+  const uint32_t* pre;   // prefix columns
+  const uint64_t* pcol;  // this thread's first prefix column (j = tid / 8) at chunk tid % 8
   uint32_t pre_len;
   uint64_t Wp;
   const uint64_t* B;
   uint32_t w0, nst;
-  int mode, nload, rb0, cb0;
-  bool diag, idle;  // idle: the wave's rows or columns all lie past the last child
+  int nload, rb0, cb0;
+  bool diag, idle;  // idle: the wave's block lies below the diagonal or past the last child
 };
 
-// The wave's load instructions for the stage at word w: r < 8 stage A-panel
-// rows 64 w + 8 r .. +7 (wave w), r >= 8 the same rows of the B panel.
+// The wave's load instructions for the stage at word w: r < 4 stage A-panel
+// rows 32 w + 8 r .. +7 (wave w), r >= 4 the same rows of the B panel.
 __device__ __forceinline__ void big_issue(const BigTask& k, uint32_t w, uint4* buf, int wave) {
-  uint4* dst = buf + (size_t)(64 * wave) * DCH;
+  uint4* dst = buf + (size_t)(32 * wave) * DCH;
 #pragma unroll
   for (int r = 0; r < BLOADS; ++r)
     if (r < k.nload)
       __builtin_amdgcn_global_load_lds(k.B + (uint64_t)k.col[r] * k.Wp + k.choff + w,
-                                       dst + ((r >= 8) ? BT * DCH : 0) + 8 * (r & 7) * DCH, 16, 0,
+                                       dst + ((r >= 4) ? BT * DCH : 0) + 8 * (r & 3) * DCH, 16, 0,
                                        0);
 }
 
+template <bool MASK>
 __device__ __forceinline__ void big_stage_step(const BigTask& k, uint32_t s, const uint4* cur,
                                                uint4* nxt, uint4* smask, int tid,
-                                               v16f (&acc)[4][4]) {
+                                               v16f (&acc)[2][4]) {
   const int lane = tid & 63, wave = tid >> 6;
   const uint32_t pj0 = (uint32_t)tid >> 3, pch = (uint32_t)tid & 7;
   __syncthreads();  // stage s is in LDS (each wave waited for its loads); stage s - 1 is done
   const bool more = s + 1 < k.nst;
   const uint32_t wn = k.w0 + (s + 1) * DKW;
-  const bool pre_thread = more && pj0 < k.pre_len;
+  const bool pre_thread = MASK && more && pj0 < k.pre_len;
   uint4 pm = make_uint4(~0u, ~0u, ~0u, ~0u);
   if (pre_thread) pm = load_global16(k.pcol + wn);
   if (more) big_issue(k, wn, nxt, wave);
-  if (tid < DCH) smask[((s + 2) % 3) * DCH + tid] = make_uint4(~0u, ~0u, ~0u, ~0u);
+  if (MASK && tid < DCH) smask[((s + 2) % 3) * DCH + tid] = make_uint4(~0u, ~0u, ~0u, ~0u);
 
   if (!k.idle) {
     const uint4* ra = cur + (size_t)(k.rb0 * 32 + (lane & 31)) * DCH;
     const uint4* rb = cur + (size_t)((k.diag ? 0 : BT) + k.cb0 * 32 + (lane & 31)) * DCH;
-    const uint4* mk = smask + (s % 3) * DCH;
-    if (k.mode == 0) big_stage<0>(ra, rb, mk, lane, acc);
-    else if (k.mode == 1) big_stage<1>(ra, rb, mk, lane, acc);
-    else big_stage<2>(ra, rb, mk, lane, acc);
+    // a wave in its MFMA section outranks the waves issuing loads
+    __builtin_amdgcn_s_setprio(3);
+    big_stage<MASK>(ra, rb, smask + (s % 3) * DCH, lane, acc);
+    __builtin_amdgcn_s_setprio(0);
   }
 
   if (pre_thread)
-    fp4_mask_and(pm, k.B, k.Wp, k.pre, k.pre_len, pj0, pch, wn, smask + ((s + 1) % 3) * DCH);
+    fp4_mask_and(pm, k.B, k.Wp, k.pre, k.pre_len, pj0, pch, wn, smask + ((s + 1) % 3) * DCH,
+                 BTHREADS / 8);
 }
 
+template <bool MASK>
 __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint4* sb0, uint4* sb1,
                                                uint4* smask) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave >> 1, wc = wave & 1;  // rows 64 wr .., columns 128 wc ..
   const uint64_t ntasks = *a.ntasks;
   const SkRange rg = sk_range(a.tcost, ntasks);
 
@@ -185,17 +180,9 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint4* sb0, u
     const uint32_t I0 = (uint32_t)task.bi * BT, L0 = (uint32_t)task.bl * BT;
     BigTask k;
     k.diag = task.bi == task.bl;
-    if (k.diag) {
-      const bool on = wave == 0 || wave == 3;
-      k.mode = on ? 1 : 2;
-      k.rb0 = on ? (wave == 0 ? 0 : 4) : (wave == 1 ? 0 : 2);
-      k.cb0 = on ? k.rb0 : 4;
-    } else {
-      k.mode = 0;
-      k.rb0 = 4 * wr;
-      k.cb0 = 4 * wc;
-    }
-    k.idle = I0 + 32u * k.rb0 >= q || L0 + 32u * k.cb0 >= q;
+    k.rb0 = 2 * wr;  // 32-wide row blocks of the panel
+    k.cb0 = 4 * wc;  // 32-wide column blocks
+    k.idle = (k.diag && wc == 0 && wr >= 2) || I0 + 32u * k.rb0 >= q || L0 + 32u * k.cb0 >= q;
     k.nload = k.diag ? BLOADS / 2 : BLOADS;
     k.Wp = db.Wp;
     k.B = db.B;
@@ -204,15 +191,15 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint4* sb0, u
     k.w0 = task.w0 + s_lo * DKW;
     k.nst = s_hi - s_lo;
     k.pcol = nullptr;
-    if ((uint32_t)tid / 8 < k.pre_len)
+    if (MASK && (uint32_t)tid / 8 < k.pre_len)
       k.pcol = k.B + (uint64_t)k.pre[tid / 8] * k.Wp + 2 * (tid & 7);
     // Lane L of load instruction r fetches the chunk for slot L % 8 of panel
-    // row 64 w + 8 (r % 8) + L / 8, i.e. chunk (L % 8) ^ (L / 8 % 8) of that
+    // row 32 w + 8 (r % 4) + L / 8, i.e. chunk (L % 8) ^ (L / 8 % 8) of that
     // row's column.  Children beyond q load column q - 1: their rows and
     // columns of the tile are never written out.
 #pragma unroll
     for (int r = 0; r < BLOADS; ++r) {
-      const uint32_t idx = ((r >= 8) ? L0 : I0) + 64 * wave + 8 * (r & 7) + (lane >> 3);
+      const uint32_t idx = ((r >= 4) ? L0 : I0) + 32 * wave + 8 * (r & 3) + (lane >> 3);
       k.col[r] = idx < q ? idx : q - 1;
     }
     if (!cd.proj) {
@@ -225,9 +212,9 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint4* sb0, u
     }
     k.choff = 2 * (uint32_t)((lane & 7) ^ ((lane >> 3) & 7));
 
-    v16f acc[4][4];
+    v16f acc[2][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -236,25 +223,23 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint4* sb0, u
     __syncthreads();  // the previous task's last stage has finished reading LDS
     if (k.nst) {
       big_issue(k, k.w0, sb0, wave);
-      if (tid < DCH) {  // stage 0's mask in full; stage 1's row starts at all ones
+      if (MASK && tid < DCH) {  // stage 0's mask in full; stage 1's row starts at all ones
         smask[tid] = fp4_mask_full(k.B, k.Wp, k.pre, k.pre_len, k.w0, (uint32_t)tid);
         smask[DCH + tid] = make_uint4(~0u, ~0u, ~0u, ~0u);
       }
     }
     // even stages read sb0 and load into sb1, odd stages the other way round
     for (uint32_t s = 0; s < k.nst; s += 2) {
-      big_stage_step(k, s, sb0, sb1, smask, tid, acc);
-      if (s + 1 < k.nst) big_stage_step(k, s + 1, sb1, sb0, smask, tid, acc);
+      big_stage_step<MASK>(k, s, sb0, sb1, smask, tid, acc);
+      if (s + 1 < k.nst) big_stage_step<MASK>(k, s + 1, sb1, sb0, smask, tid, acc);
     }
     if (k.idle) continue;
 
     // 32x32 accumulator layout: lane holds column (lane & 31); register r holds
     // row 8*(r/4) + 4*(lane/32) + (r%4).
     uint32_t* tri = a.tri + cd.tri_off;
-    const int na = k.mode == 2 ? 2 : 4;
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      if (rb >= na) break;
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
@@ -264,25 +249,25 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint4* sb0, u
           const uint32_t v = __float2uint_rn(acc[rb][cb][r]);  // exact integer counts
           if (gi < gl && gl < q && v) atomicAdd(tri + tri_index(gi, gl, q), v);
         }
-    }
   }
 }
 
-// One workgroup per CU, one wave per SIMD: 512 registers per lane, the 256
-// accumulators in the accumulation registers.  LDS: 2 x 64 KiB of stages.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+// One workgroup per CU, two waves per SIMD (256 registers per lane).
+template <bool MASK>
+__global__ __launch_bounds__(BTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_gram_mfma_big(ClassArgs a) {
   __shared__ uint4 sb0[BROWS * DCH];
   __shared__ uint4 sb1[BROWS * DCH];
   __shared__ uint4 smask[3 * DCH];
-  gram_tiles_big(a, sb0, sb1, smask);
+  gram_tiles_big<MASK>(a, sb0, sb1, smask);
 }
 
 }  // namespace
 
-void launch_gram_mfma_big(const ClassArgs& a, uint32_t grid, hipStream_t s) {
+void launch_gram_mfma_big(const ClassArgs& a, uint32_t grid, bool masked, hipStream_t s) {
   if (grid == 0) return;
-  k_gram_mfma_big<<<grid, 256, 0, s>>>(a);
+  if (masked) k_gram_mfma_big<true><<<grid, BTHREADS, 0, s>>>(a);
+  else k_gram_mfma_big<false><<<grid, BTHREADS, 0, s>>>(a);
   BM_LAUNCH_CHECK();
 }
 

@@ -341,7 +341,7 @@ __device__ __forceinline__ void fp4_stage_step(const Fp4Task& k, uint32_t s, con
   __builtin_amdgcn_s_setprio(0);
 
   if (pre_thread)
-    fp4_mask_and(pm, k.B, k.Wp, k.pre, k.pre_len, pj0, pch, wn, smask + ((s + 1) % 3) * DCH);
+    fp4_mask_and(pm, k.B, k.Wp, k.pre, k.pre_len, pj0, pch, wn, smask + ((s + 1) % 3) * DCH, 32);
 }
 
 template <bool MASK>

@@ -430,7 +430,7 @@ void run_class_kernels(const DbInfo* ddb, const uint32_t* child_item, const Step
     a.tcost = w.pcb.get();
     tm.begin(BM_K_GRAM_MFMA_BIG);
     // one workgroup per CU, each with an equal share of the stages
-    launch_gram_mfma_big(a, (uint32_t)ncu, s);
+    launch_gram_mfma_big(a, (uint32_t)ncu, w.prefixed, s);
     tm.end(8.0 * nW * (double)w.st[ST_COLS_B], gram_ops(3, 1));
   }
   if (w.ub_m && w.st[ST_CLS_M]) {
