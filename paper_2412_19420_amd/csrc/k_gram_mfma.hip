@@ -323,11 +323,11 @@ __device__ __forceinline__ void fp4_stage_step(const Fp4Task& k, uint32_t s, con
   const uint32_t wn = k.w0 + (s + 1) * DKW;
   // this thread's first prefix chunk of stage s + 1, issued before the stage
   // loads so that waiting for it does not wait for them
-  const bool pre_thread = more && pj0 < k.pre_len;
+  const bool pre_thread = MASK && more && pj0 < k.pre_len;
   uint4 pm = make_uint4(~0u, ~0u, ~0u, ~0u);
   if (pre_thread) pm = load_global16(k.pcol + wn);
   if (more) fp4_issue(k, wn, nxt, wave);
-  if (tid < DCH) smask[((s + 2) % 3) * DCH + tid] = make_uint4(~0u, ~0u, ~0u, ~0u);
+  if (MASK && tid < DCH) smask[((s + 2) % 3) * DCH + tid] = make_uint4(~0u, ~0u, ~0u, ~0u);
 
   const uint4* ra = cur + (size_t)(k.rb0 * 32 + (lane & 31)) * DCH;
   const uint4* rb = cur + (size_t)((k.diag ? 0 : T) + k.cb0 * 32 + (lane & 31)) * DCH;
@@ -381,7 +381,7 @@ __device__ __forceinline__ void gram_tiles_fp4(const ClassArgs& a, uint4* sb0, u
     k.w0 = task.w0 + s_lo * DKW;
     k.nst = s_hi - s_lo;
     k.pcol = nullptr;
-    if ((uint32_t)tid / 8 < k.pre_len)
+    if (MASK && (uint32_t)tid / 8 < k.pre_len)
       k.pcol = k.B + (uint64_t)k.pre[tid / 8] * k.Wp + 2 * (tid & 7);
     // Lane L of load instruction r fetches the chunk for slot L % 8 of panel
     // row 32 w + 8 (r % 4) + L / 8.  Children beyond q load column q - 1:
@@ -419,7 +419,7 @@ __device__ __forceinline__ void gram_tiles_fp4(const ClassArgs& a, uint4* sb0, u
     __syncthreads();  // the previous task's last stage has finished reading LDS
     if (k.nst) {
       fp4_issue(k, k.w0, sb0, wave);
-      if (tid < DCH) {  // stage 0's mask in full; stage 1's row starts at all ones
+      if (MASK && tid < DCH) {  // stage 0's mask in full; stage 1's row starts at all ones
         smask[tid] = fp4_mask_full(k.B, k.Wp, k.pre, k.pre_len, k.w0, (uint32_t)tid);
         smask[DCH + tid] = make_uint4(~0u, ~0u, ~0u, ~0u);
       }
@@ -447,9 +447,9 @@ __device__ __forceinline__ void gram_tiles_fp4(const ClassArgs& a, uint4* sb0, u
   }
 }
 
-// Two workgroups per CU (two waves per SIMD; LDS: 2 x 64 KiB of stages): the
-// register budget is capped at 256 so the three stage variants do not push the
-// kernel to one wave.
+// Two workgroups per CU (two waves per SIMD; each workgroup holds 64 KiB of
+// LDS stages): the register budget is capped at 256 so the three stage
+// variants do not push the kernel to one wave.
 template <bool F4, bool MASK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_gram_mfma(ClassArgs a) {

@@ -143,17 +143,17 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
         const uint64_t rs = cd.tri_off + tri_index(li, li + 1, cd.q);
         const uint64_t len = cd.q - li - 1;
         const uint32_t minsup = dbs[cd.db].minsup;
-        // eight 64-entry chunks per pass: their loads are in flight together
+        // sixteen 64-entry chunks per pass: their loads are in flight together
         // (a level-1 row is as long as the number of frequent items)
-        for (uint64_t t0 = 0; t0 < len; t0 += 512) {
-          uint32_t v[8];
+        for (uint64_t t0 = 0; t0 < len; t0 += 1024) {
+          uint32_t v[16];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
+          for (int u = 0; u < 16; ++u) {
             const uint64_t t = t0 + 64 * u + lane;
             v[u] = t < len ? tri[rs + t] : 0u;
           }
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
+          for (int u = 0; u < 16; ++u) {
             const bool f = t0 + 64 * u + lane < len && v[u] >= minsup;
             kc += (uint32_t)__popcll(__ballot(f));
           }
