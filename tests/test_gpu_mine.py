@@ -580,9 +580,11 @@ def test_mine_dense_reduced_big_tiles_exact(bm, big):
     _, want, cands = oracle_arrays(db, db.minsup)
     print(f"dense reduced, big tiles from {big} children: n={db.n} m={db.m}", flush=True)
     h = bm.bm_build(db.row_ptr, db.col_idx, db.n, db.m)
-    for flags in (bm.FLAG_LEVELSYNC, 0):
+    # short word splits too: every workgroup's cost slice then cuts through
+    # many tasks, whose partial sums add up
+    for flags, split in ((bm.FLAG_LEVELSYNC, 0), (0, 0), (0, 64)):
         r = bm.bm_mine_ex(h, db.minsup, bm.options(flags | bm.FLAG_TIMING | bm.FLAG_ALL_MFMA,
-                                                   mfma_big_children=big))
+                                                   mfma_big_children=big, split_words=split))
         assert r.stats()["kernel_launches"]["gram_mfma_big"] > 0
         assert_same(r.arrays(), want)
         assert r.stats()["candidates_total"] == cands
