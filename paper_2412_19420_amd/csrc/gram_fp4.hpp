@@ -116,24 +116,38 @@ __device__ __forceinline__ uint4 fp4_mask_full(const uint64_t* B, uint64_t Wp,
 }
 
 // Balanced split of a launch's work (stream-K).  The tasks' costs laid end to
-// end (P: exclusive prefix sums, n + 1 entries) are cut into gridDim.x equal
+// end (P: exclusive prefix sums, n + 1 entries) are cut into gridDim.x
 // ranges, one per workgroup; the workgroup of range [u0, u1) runs, of each
 // task whose cost span meets it, the stages whose first cost unit lies in the
-// range.  Every stage runs exactly once, every workgroup gets the same cost
-// (up to one stage at each end), and partial tasks add their partial sums
-// atomically like whole ones.
+// range.  Every stage runs exactly once, every workgroup gets its share of the
+// cost (up to one stage at each end), and partial tasks add their partial
+// sums atomically like whole ones.
+//
+// SKEW (a grid of two workgroups per CU): the first half of the grid is
+// dispatched first, one workgroup per CU, and wins its CU's issue
+// arbitration against the workgroup that joins it (2.6 against 3.2 us per
+// stage in a per-workgroup timeline), so the shares are 11 : 9 between the
+// halves; the slower one speeds up once the faster has finished.  Only the
+// running time depends on this; the split stays exact for any placement.
 struct SkRange {
   uint64_t u0, u1;  // this workgroup's cost range
   uint64_t i;       // the last task with P[i] <= u0
 };
+__device__ __forceinline__ uint64_t sk_share(uint64_t b, uint64_t G, bool skew) {
+  if (!skew) return b;
+  const uint64_t h = G / 2;  // weights 11 (first half), 9 (second half)
+  return b < h ? 11 * b : 11 * h + 9 * (b - h);
+}
 // Called by every thread of the workgroup (it synchronises): the last i in
 // [0, n] with P[i] <= u0, by rounds of blockDim.x-way sampling.
+template <bool SKEW>
 __device__ __forceinline__ SkRange sk_range(const uint64_t* P, uint64_t n) {
   SkRange r;
   const uint64_t C = P[n];
   const uint64_t G = gridDim.x, b = blockIdx.x;
-  r.u0 = C * b / G;
-  r.u1 = C * (b + 1) / G;
+  const uint64_t WT = sk_share(G, G, SKEW);
+  r.u0 = (uint64_t)((unsigned __int128)C * sk_share(b, G, SKEW) / WT);
+  r.u1 = (uint64_t)((unsigned __int128)C * sk_share(b + 1, G, SKEW) / WT);
   const uint64_t k = threadIdx.x, nt = blockDim.x;
   uint64_t lo = 0, hi = n;  // P[lo] <= u0 (P[0] = 0); the answer lies in [lo, hi]
   while (hi > lo) {

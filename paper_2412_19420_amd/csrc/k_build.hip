@@ -65,13 +65,17 @@ __global__ __launch_bounds__(kThreads) void k_pack(const uint64_t* __restrict__ 
 // are added to the single-item supports on the way out.
 //   * the block's item ids are loaded once, coalesced and several per thread in
 //     flight, into LDS as packed (column << 8 | local row) entries -- the row is
-//     filled in row by row -- and every column window is then replayed from LDS;
+//     filled in row by row -- and then held in registers (12 per thread), so
+//     every column window takes its bits from registers, not from LDS;
 //   * bits are set with LDS atomic ORs (idempotent: duplicate ids collapse, as
 //     M is 0/1); ids >= m are flagged;
+//   * two window bitmaps (the second over the entry buffer, free once the
+//     entries are in registers): window w is written out of one while window
+//     w + 1 is ORed into the other, one barrier per window;
 //   * row_ptr is checked on the way in (non-decreasing: flag 1); element
 //     ranges are clamped to [0, nnz] and local rows are masked, so a malformed
 //     row_ptr cannot send any access out of bounds.
-// 256-row tiles keep a workgroup's LDS at 62 KB, so two workgroups (32 waves)
+// 256-row tiles keep a workgroup's LDS at 70 KB, so two workgroups (32 waves)
 // share a CU and one's loads overlap the other's window passes: measured 15%
 // faster than 512-row tiles with one workgroup per CU on the T40-style
 // 1M x 2,000 build, 3% on the dense 1M x 4,096 one.
@@ -80,7 +84,12 @@ constexpr int PK_ROWS = PK_KR * 64;       // 256 rows
 constexpr int PK_RBITS = 8;               // bits of a local row
 constexpr int PK_CW = 512;                // columns per window
 constexpr int PK_LD = PK_KR + 1;          // padded LDS row (conflict-free OR)
-constexpr int PK_ECAP = 10240;            // staged elements per chunk (40 KB)
+// Staged elements per chunk (48 KB): a tile with more runs its window passes
+// once per chunk, later chunks adding to what B holds.  12,288 covers every
+// 256-row tile of the dense 1M x 4,096 workload (mean 9,941 ids, at most
+// 10,719), 10,240 missed 9% of them, and those tiles' second passes made the
+// build 29% slower (0.363 against 0.281 ms).
+constexpr int PK_ECAP = 12288;
 // Sparse databases (at most PK_SPARSE_ROW elements per row on average) are
 // packed with 8,192-element chunks (32 KB), measured faster on the batch of
 // 256 Quest-style databases.
@@ -108,13 +117,43 @@ struct PackSmem {
   uint64_t s_rp[PK_ROWS + 1];
 };
 
+// The bits of one column window [c0, c0 + cw) from a thread's entries, ORed
+// into the window bitmap X.  The empty asm keeps the entries in registers and
+// the per-window work recomputed from them, so values derived from all of a
+// thread's entries are not held across windows.
+template <int EPT>
+__device__ __forceinline__ void pack_or_window(uint32_t (&xe)[EPT], unsigned long long* X,
+                                               uint32_t c0, uint32_t cw) {
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) asm volatile("" : "+v"(xe[u]));
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const uint32_t x = xe[u];
+    if (x == 0xffffffffu) continue;
+    const uint32_t d = (x >> PK_RBITS) - c0;
+    if (d < cw) {
+      const int lr = x & (PK_ROWS - 1);
+      atomicOr(X + d * PK_LD + (lr >> 6), 1ull << (lr & 63));
+    }
+  }
+}
+
 template <int ECAP>
 __device__ __forceinline__ void pack_tile(PackSmem<ECAP>& sm, const uint64_t* __restrict__ rp,
                                           const uint32_t* __restrict__ ci, uint64_t n, uint64_t nnz,
                                           uint32_t m, unsigned long long* __restrict__ B, uint64_t Wp,
                                           uint32_t* __restrict__ colsum, uint32_t* __restrict__ err,
                                           uint64_t blk) {
-  unsigned long long* X = sm.X;
+  static_assert(ECAP % PK_T == 0, "whole entries per thread");
+  static_assert(ECAP * sizeof(uint32_t) >= PK_CW * PK_LD * sizeof(unsigned long long),
+                "the entry buffer holds a window bitmap");
+  constexpr int EPT = ECAP / PK_T;  // entries per thread
+  static_assert(PK_KR == 4, "a column's words are the four lanes of a quad");
+  // two window bitmaps: XA, and XB over the entry buffer once the entries are
+  // in registers -- window w is written out of one while window w + 1 is
+  // ORed into the other, so a window costs one barrier
+  unsigned long long* XA = sm.X;
+  unsigned long long* XB = reinterpret_cast<unsigned long long*>(sm.s_e);
   uint32_t* s_e = sm.s_e;
   uint64_t* s_rp = sm.s_rp;
   const int tid = threadIdx.x;
@@ -136,13 +175,13 @@ __device__ __forceinline__ void pack_tile(PackSmem<ECAP>& sm, const uint64_t* __
   const uint64_t e0 = s_rp[0];
   const uint64_t e1 = max(e0, s_rp[nr]);
   const uint32_t nwin = (m + PK_CW - 1) / PK_CW;
-  const bool single_chunk = e1 - e0 <= ECAP;
-  // the bitmap starts clear; each window's write-out clears what it read, so
-  // a window needs no clearing pass (and no barrier for one)
-  for (int i = tid; i < PK_CW * PK_LD; i += PK_T) X[i] = 0ull;
+  // XA starts clear; each window's write-out clears what it read
+  for (int i = tid; i < PK_CW * PK_LD; i += PK_T) XA[i] = 0ull;
+  const int wi = tid & (PK_KR - 1), cs = tid / PK_KR;  // write-out: word wi of columns cs, cs + 256, ..
   for (uint64_t ea = e0; ea < e1 || (ea == e0 && e0 == e1); ea += ECAP) {
     const uint64_t eb = min<uint64_t>(e1, ea + ECAP);
     const int ne = (int)(eb - ea);
+    const bool first = ea == e0, last = eb == e1;
     __syncthreads();  // previous chunk fully consumed
     for (int base = 0; base < ne; base += PK_T * PK_UNROLL) {
       uint32_t v[PK_UNROLL];
@@ -174,47 +213,40 @@ __device__ __forceinline__ void pack_tile(PackSmem<ECAP>& sm, const uint64_t* __
       }
       for (; e < b; ++e) s_e[e - ea] |= (uint32_t)r;
     }
-    __syncthreads();  // rows filled in before the window passes read the entries
+    __syncthreads();  // rows filled in before the entries are read
+    uint32_t xe[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int k = u * PK_T + tid;
+      xe[u] = k < ne ? s_e[k] : 0xffffffffu;
+    }
+    __syncthreads();  // every entry is in registers: the entry buffer becomes XB
+    for (int i = tid; i < PK_CW * PK_LD; i += PK_T) XB[i] = 0ull;
+    if (nwin) pack_or_window(xe, XA, 0, min<uint32_t>(PK_CW, m));
+    __syncthreads();
     for (uint32_t win = 0; win < nwin; ++win) {
+      unsigned long long* Xc = (win & 1) ? XB : XA;
+      unsigned long long* Xn = (win & 1) ? XA : XB;
       const uint32_t c0 = win * PK_CW;
       const uint32_t cw = min<uint32_t>(PK_CW, m - c0);
-      if (!single_chunk && ea != e0) {
-        // several chunks: accumulate this window on top of what B already holds
-        const int wi = tid & (PK_KR - 1), cs = tid / PK_KR;
-        for (uint32_t c = cs; c < cw; c += PK_T / PK_KR)
-          X[c * PK_LD + wi] = B[(uint64_t)(c0 + c) * Wp + blk * PK_KR + wi];
-        __syncthreads();
-      }
-      for (int k0 = 0; k0 < ne; k0 += 4 * PK_T) {
-        uint32_t x[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 + u * PK_T + tid;
-          x[u] = k < ne ? s_e[k] : 0xffffffffu;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (x[u] == 0xffffffffu) continue;
-          const uint32_t d = (x[u] >> PK_RBITS) - c0;
-          if (d < cw) {
-            const int lr = x[u] & (PK_ROWS - 1);
-            atomicOr(X + d * PK_LD + (lr >> 6), 1ull << (lr & 63));
-          }
-        }
-      }
-      __syncthreads();
-      const bool last = eb == e1;
-      const int wi = tid & (PK_KR - 1), cs = tid / PK_KR;
       for (uint32_t c = cs; c < cw; c += PK_T / PK_KR) {
-        const unsigned long long v = X[c * PK_LD + wi];
-        X[c * PK_LD + wi] = 0ull;  // clear for the next window as it is written out
-        B[(uint64_t)(c0 + c) * Wp + blk * PK_KR + wi] = v;
+        unsigned long long v = Xc[c * PK_LD + wi];
+        Xc[c * PK_LD + wi] = 0ull;  // clear for a later window as it is written out
+        unsigned long long* dst = B + (uint64_t)(c0 + c) * Wp + blk * PK_KR + wi;
+        // a later chunk of the tile adds to what the earlier ones wrote (this
+        // same thread wrote it)
+        if (!first) v |= *dst;
+        *dst = v;
         if (last) {
-          uint32_t pc = (uint32_t)__popcll(v);
-          for (int off = PK_KR / 2; off > 0; off >>= 1) pc += __shfl_xor(pc, off);
-          if (wi == 0 && pc) atomicAdd(colsum + c0 + c, pc);
+          // the column's four words are in the four lanes of a quad (all
+          // active together): sum their popcounts with DPP quad permutes
+          int pc = __popcll(v);
+          pc += __builtin_amdgcn_mov_dpp(pc, 0xb1, 0xf, 0xf, false);  // quad_perm 1,0,3,2
+          pc += __builtin_amdgcn_mov_dpp(pc, 0x4e, 0xf, 0xf, false);  // quad_perm 2,3,0,1
+          if (wi == 0 && pc) atomicAdd(colsum + c0 + c, (uint32_t)pc);
         }
       }
+      if (win + 1 < nwin) pack_or_window(xe, Xn, c0 + PK_CW, min<uint32_t>(PK_CW, m - c0 - PK_CW));
       __syncthreads();
     }
     if (e0 == e1) break;
@@ -225,7 +257,7 @@ __device__ __forceinline__ void pack_tile(PackSmem<ECAP>& sm, const uint64_t* __
 // One database: nnz = row_ptr[n] is read here, so the host needs no read-back
 // before the launch.  Flags row_ptr[0] != 0 (8) and a NULL col_idx with
 // nnz > 0 (4, nothing is packed).
-__global__ __launch_bounds__(PK_T) void k_pack_tiled(
+__global__ __launch_bounds__(PK_T) __attribute__((amdgpu_waves_per_eu(8))) void k_pack_tiled(
     const uint64_t* __restrict__ rp, const uint32_t* __restrict__ ci, uint64_t n, uint32_t m,
     unsigned long long* __restrict__ B, uint64_t Wp, uint32_t* __restrict__ colsum,
     uint32_t* __restrict__ err) {
@@ -264,7 +296,7 @@ __global__ __launch_bounds__(kThreads) void k_build_multi_pre(PackJob* __restric
 // one grid: block b belongs to list entry e with kstart[e] <= b < kstart[e + 1],
 // database kjob[e].
 template <int ECAP>
-__global__ __launch_bounds__(PK_T) void k_pack_tiled_multi(const PackJob* __restrict__ jobs,
+__global__ __launch_bounds__(PK_T) __attribute__((amdgpu_waves_per_eu(8))) void k_pack_tiled_multi(const PackJob* __restrict__ jobs,
                                                            const uint32_t* __restrict__ kjob,
                                                            uint32_t nk,
                                                            const uint64_t* __restrict__ kstart,

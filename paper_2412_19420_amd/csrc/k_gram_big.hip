@@ -164,7 +164,7 @@ __device__ __forceinline__ void gram_tiles_big(const ClassArgs& a, uint4* sb0, u
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;  // rows 64 wr .., columns 128 wc ..
   const uint64_t ntasks = *a.ntasks;
-  const SkRange rg = sk_range(a.tcost, ntasks);
+  const SkRange rg = sk_range<false>(a.tcost, ntasks);  // one workgroup per CU
 
   for (uint64_t t = rg.i; t < ntasks; ++t) {
     const uint64_t base = a.tcost[t];

@@ -316,7 +316,8 @@ __device__ __forceinline__ void fp4_stage_step(const Fp4Task& k, uint32_t s, con
                                                uint4* nxt, uint4* smask, int tid,
                                                v16f (&acc)[2][2]) {
   constexpr int T = GRAM_TILE;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // LDS destinations in SGPRs
   const uint32_t pj0 = (uint32_t)tid >> 3, pch = (uint32_t)tid & 7;
   __syncthreads();  // stage s is in LDS (each wave waited for its loads); stage s - 1 is done
   const bool more = s + 1 < k.nst;
@@ -352,7 +353,7 @@ __device__ __forceinline__ void gram_tiles_fp4(const ClassArgs& a, uint4* sb0, u
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const uint64_t ntasks = *a.ntasks;
-  const SkRange rg = sk_range(a.tcost, ntasks);
+  const SkRange rg = sk_range<true>(a.tcost, ntasks);  // two workgroups per CU
 
   for (uint64_t t = rg.i; t < ntasks; ++t) {
     const uint64_t base = a.tcost[t];

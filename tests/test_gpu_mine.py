@@ -110,6 +110,29 @@ def test_build_host_device_combinations(bm, m, rp_dev, ci_dev):
     assert np.array_equal(np.asarray(got).astype(np.int64), np.asarray(ref).astype(np.int64))
 
 
+# rows long enough that every 256-row tile of the pack stages its ids in two or
+# three chunks (later chunks add to what earlier ones wrote), over one, two and
+# three column windows: every pair support of every column against the oracle
+@pytest.mark.parametrize("m", [300, 1000, 1500])
+def test_build_multi_chunk_tiles_all_pairs(bm, m):
+    rng = np.random.default_rng(29)
+    n = 1_100
+    lens = rng.poisson(90, n)
+    lens[rng.random(n) < 0.03] = 0
+    lens[rng.random(n) < 0.02] = 400  # a few very long rows (duplicates included)
+    row_ptr = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(lens, out=row_ptr[1:])
+    col_idx = rng.integers(0, m, int(row_ptr[-1])).astype(np.uint32)
+    print(f"multi-chunk build m={m} nnz={len(col_idx)}", flush=True)
+    h = bm.bm_build(row_ptr, col_idx, n, m)
+    want_sums = pairs.column_sums(row_ptr, col_idx, n, m)
+    assert np.array_equal(bm.bm_item_support(h).astype(np.int64), want_sums)
+    items = np.arange(m, dtype=np.uint32)
+    got = np.asarray(bm.bm_pair_support(h, items)).astype(np.int64).reshape(m, m)
+    ref = np.asarray(pairs.pair_support(row_ptr, col_idx, n, m)).astype(np.int64)
+    assert np.array_equal(got, ref)
+
+
 # ------------------------------------------------------------ pair supports (Eq. 2)
 
 @pytest.mark.parametrize("n,m,k,density", [
