@@ -36,18 +36,6 @@ __device__ __forceinline__ v16f fp4_mfma(const v8i& A, const v8i& B, const v16f&
   return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, B, acc, 4, 4, 0, sc, 0, sc);
 }
 
-// Loads through the global address space (a generic pointer would become a
-// flat load, which also counts against the LDS counter and so makes the LDS
-// waits of the MFMA loop wait for global memory too).
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ uint4 load_global16(const uint64_t* p) {
-  const u32x4 v = *(const __attribute__((address_space(1))) u32x4*)p;
-  return make_uint4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ uint32_t load_global_u32(const uint32_t* p) {
-  return *(const __attribute__((address_space(1))) uint32_t*)p;
-}
-
 // Direct-to-LDS staging.  Each stage (DKW = 16 words = 128 bytes of every
 // panel column) travels from global memory into LDS with
 // global_load_lds_dwordx4, bypassing registers, into one of two buffers: the

@@ -117,6 +117,50 @@ struct DbInfo {
 // projected class, its children's columns re-packed over the transactions that
 // hold the prefix (views[cd.proj - 1]: B = those columns in child order, n = the
 // prefix's support, W/Wp its words; the prefix is already applied).
+// Loads through the global address space.  A pointer read from memory (a
+// column base in a DbInfo, a task's prefix list) is generic, and a load
+// through it compiles to a flat load, which also counts against the LDS
+// counter: every LDS wait of a kernel that stages through LDS would then
+// wait for its global loads in flight too.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 load_global16(const void* p) {
+  const u32x4 v = *(const __attribute__((address_space(1))) u32x4*)p;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint64_t load_global_u64(const uint64_t* p) {
+  return *(const __attribute__((address_space(1))) uint64_t*)p;
+}
+__device__ __forceinline__ uint32_t load_global_u32(const uint32_t* p) {
+  return *(const __attribute__((address_space(1))) uint32_t*)p;
+}
+
+// The AND of a class's prefix columns at words w, w + 1 (m0, m1 ANDed in
+// place; 16-byte loads at an even word).  The first PREFIX_REG columns come
+// from bases set up once per class (pc[j], nullptr beyond the prefix), so
+// their loads need no index load first and go out together with the other
+// loads of the step; further columns (prefixes longer than PREFIX_REG) are
+// read through the prefix list.
+constexpr int PREFIX_REG = 4;
+__device__ __forceinline__ void prefix_and(const uint64_t* const (&pc)[PREFIX_REG],
+                                           const uint64_t* B, uint64_t Wp, const uint32_t* pre,
+                                           uint32_t pre_len, uint32_t w, uint64_t& m0,
+                                           uint64_t& m1) {
+  uint4 x[PREFIX_REG];
+#pragma unroll
+  for (int j = 0; j < PREFIX_REG; ++j)
+    x[j] = pc[j] ? load_global16(pc[j] + w) : make_uint4(~0u, ~0u, ~0u, ~0u);
+  for (uint32_t j = PREFIX_REG; j < pre_len; ++j) {
+    const uint4 y = load_global16(B + (uint64_t)pre[j] * Wp + w);
+    m0 &= (uint64_t)y.x | ((uint64_t)y.y << 32);
+    m1 &= (uint64_t)y.z | ((uint64_t)y.w << 32);
+  }
+#pragma unroll
+  for (int j = 0; j < PREFIX_REG; ++j) {
+    m0 &= (uint64_t)x[j].x | ((uint64_t)x[j].y << 32);
+    m1 &= (uint64_t)x[j].z | ((uint64_t)x[j].w << 32);
+  }
+}
+
 __host__ __device__ inline DbInfo class_view(const ClassDesc& cd, const DbInfo* dbs,
                                              const DbInfo* views) {
   return cd.proj ? views[cd.proj - 1] : dbs[cd.db];

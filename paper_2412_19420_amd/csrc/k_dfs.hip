@@ -178,22 +178,23 @@ __global__ __launch_bounds__(NT) void k_dfs(DfsArgs a) {
 #pragma unroll
     for (int p = 0; p < TNP; ++p) acc[p] = 0;
     const uint32_t W = (uint32_t)db.W;
+    const uint32_t pre_len = c.pre_len;
+    const uint64_t* pc[PREFIX_REG];
+#pragma unroll
+    for (int j = 0; j < PREFIX_REG; ++j)
+      pc[j] = (uint32_t)j < pre_len ? db.B + (uint64_t)c.pre[j] * db.Wp : nullptr;
     // two words per thread: columns are padded to a multiple of 64 words, so
     // the 16-byte load at an even word stays inside the column
     for (uint32_t w = 2 * tid; w < W; w += 2 * NT) {
       uint64_t m0 = ~0ull, m1 = (w + 1 < W) ? ~0ull : 0ull;
-      for (uint32_t j = 0; j < c.pre_len; ++j) {
-        const uint4 x = *reinterpret_cast<const uint4*>(db.B + (uint64_t)c.pre[j] * db.Wp + w);
-        m0 &= (uint64_t)x.x | ((uint64_t)x.y << 32);
-        m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
-      }
+      prefix_and(pc, db.B, db.Wp, c.pre, pre_len, w, m0, m1);
       uint64_t x0[TQ], x1[TQ];
 #pragma unroll
       for (int i = 0; i < TQ; ++i) {
         x0[i] = 0;
         x1[i] = 0;
         if (i < q) {
-          const uint4 v = *reinterpret_cast<const uint4*>(col[i] + w);
+          const uint4 v = load_global16(col[i] + w);
           x0[i] = ((uint64_t)v.x | ((uint64_t)v.y << 32)) & m0;
           x1[i] = ((uint64_t)v.z | ((uint64_t)v.w << 32)) & m1;
         }
@@ -397,20 +398,20 @@ __global__ __launch_bounds__(256, 4) void k_dfs_wave(DfsArgs a) {
     for (int p = 0; p < TNP; ++p) acc[p] = 0;
     const uint32_t W = (uint32_t)db.W;
     const int qi = (int)q;
+    const uint64_t* pc[PREFIX_REG];
+#pragma unroll
+    for (int j = 0; j < PREFIX_REG; ++j)
+      pc[j] = (uint32_t)j < pre_len ? db.B + (uint64_t)cpre[j] * db.Wp : nullptr;
     for (uint32_t w = 2 * lane; w < W; w += 128) {
       uint64_t m0 = ~0ull, m1 = (w + 1 < W) ? ~0ull : 0ull;
-      for (uint32_t j = 0; j < pre_len; ++j) {
-        const uint4 x = *reinterpret_cast<const uint4*>(db.B + (uint64_t)cpre[j] * db.Wp + w);
-        m0 &= (uint64_t)x.x | ((uint64_t)x.y << 32);
-        m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
-      }
+      prefix_and(pc, db.B, db.Wp, cpre, pre_len, w, m0, m1);
       uint64_t x0[TQ], x1[TQ];
 #pragma unroll
       for (int i = 0; i < TQ; ++i) {
         x0[i] = 0;
         x1[i] = 0;
         if (i < qi) {
-          const uint4 v = *reinterpret_cast<const uint4*>(col[i] + w);
+          const uint4 v = load_global16(col[i] + w);
           x0[i] = ((uint64_t)v.x | ((uint64_t)v.y << 32)) & m0;
           x1[i] = ((uint64_t)v.z | ((uint64_t)v.w << 32)) & m1;
         }

@@ -56,6 +56,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 constexpr int SKW = 16;                // words per stage of a two-block task
+constexpr int SPRE = 4;                // prefix columns whose loads are issued with a stage's
 constexpr int SLD = 2 * SKW + 1;       // dwords per staged column row (odd: conflict-free reads)
 constexpr int DKW = 2 * SKW;           // a diagonal task (one block) stages twice the words
 constexpr int DLD = 2 * DKW + 1;
@@ -92,17 +93,29 @@ __device__ __forceinline__ void small_task(const ClassArgs& a, const Task& task,
   }
   const uint32_t* pre = a.pre_cols + cd.pre_off;
   const uint32_t pre_len = cd.proj ? 0u : cd.pre_len;  // a view has the prefix applied
+  // The first SPRE prefix columns are addressed once per task, and their
+  // chunks of a stage are loaded together with the stage's column chunks and
+  // ANDed only when the stage is written to LDS, so a stage costs one round
+  // trip to memory whatever the prefix length up to SPRE.  Columns beyond
+  // SPRE (prefixes of more than SPRE items) are ANDed in as they arrive.
+  constexpr int NU = DIAG ? 2 : 1;
+  const uint64_t* pcol[SPRE];
+#pragma unroll
+  for (int j = 0; j < SPRE; ++j)
+    pcol[j] = (uint32_t)j < pre_len ? db.B + (uint64_t)load_global_u32(pre + j) * Wp + 2 * sl
+                                    : nullptr;
 
   uint4 reg[8];
-  uint4 msk[DIAG ? 2 : 1];
+  uint4 pch[SPRE][NU];  // the stage's prefix chunks
+  uint4 msk[NU];        // the AND of the prefix columns beyond SPRE
   auto load_stage = [&](uint32_t w) {
 #pragma unroll
-    for (int u = 0; u < (DIAG ? 2 : 1); ++u) msk[u] = make_uint4(~0u, ~0u, ~0u, ~0u);
-    for (uint32_t j = 0; j < pre_len; ++j) {
+    for (int u = 0; u < NU; ++u) msk[u] = make_uint4(~0u, ~0u, ~0u, ~0u);
+    for (uint32_t j = SPRE; j < pre_len; ++j) {
 #pragma unroll
-      for (int u = 0; u < (DIAG ? 2 : 1); ++u) {
-        const uint4 v = *reinterpret_cast<const uint4*>(db.B + (uint64_t)pre[j] * Wp + w + 2 * sl +
-                                                        SKW * u);
+      for (int u = 0; u < NU; ++u) {
+        const uint4 v = load_global16(db.B + (uint64_t)load_global_u32(pre + j) * Wp + w +
+                                      2 * sl + SKW * u);
         msk[u].x &= v.x;
         msk[u].y &= v.y;
         msk[u].z &= v.z;
@@ -110,8 +123,13 @@ __device__ __forceinline__ void small_task(const ClassArgs& a, const Task& task,
       }
     }
 #pragma unroll
+    for (int j = 0; j < SPRE; ++j)
+#pragma unroll
+      for (int u = 0; u < NU; ++u)
+        pch[j][u] = pcol[j] ? load_global16(pcol[j] + w + SKW * u) : make_uint4(~0u, ~0u, ~0u, ~0u);
+#pragma unroll
     for (int p = 0; p < 8; ++p)
-      reg[p] = colp[p] ? *reinterpret_cast<const uint4*>(colp[p] + w) : make_uint4(0, 0, 0, 0);
+      reg[p] = colp[p] ? load_global16(colp[p] + w) : make_uint4(0, 0, 0, 0);
   };
 
   using Acc = typename std::conditional<F4, v16f, v16i>::type;
@@ -123,6 +141,15 @@ __device__ __forceinline__ void small_task(const ClassArgs& a, const Task& task,
   if (nst) load_stage(task.w0);
   for (uint32_t s = 0; s < nst; ++s) {
     wave_lds_sync();  // this wave finished reading the previous stage
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+#pragma unroll
+      for (int j = 0; j < SPRE; ++j) {
+        msk[u].x &= pch[j][u].x;
+        msk[u].y &= pch[j][u].y;
+        msk[u].z &= pch[j][u].z;
+        msk[u].w &= pch[j][u].w;
+      }
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
       // the prefix mask goes into the A side only: t & a_i & b_l needs it once

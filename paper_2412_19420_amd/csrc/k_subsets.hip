@@ -102,6 +102,10 @@ __global__ __launch_bounds__(kCountThreads) void k_subset_count(DfsArgs a,
   }
   const uint32_t* pre = a.step_pre[tk.level] + tk.pre_off;
   const uint32_t pre_len = tk.pre_len;
+  const uint64_t* pc[PREFIX_REG];
+#pragma unroll
+  for (int j = 0; j < PREFIX_REG; ++j)
+    pc[j] = (uint32_t)j < pre_len ? db.B + (uint64_t)load_global_u32(pre + j) * db.Wp : nullptr;
   {
     const int gpop = __popc(g);
     uint32_t acc[LN / 2];
@@ -110,15 +114,11 @@ __global__ __launch_bounds__(kCountThreads) void k_subset_count(DfsArgs a,
     uint32_t acc0 = 0;  // the fixed children alone (a set of two when gpop == 2)
     for (uint32_t w = w0 + 2 * tid; w < w1; w += 2 * kCountThreads) {
       uint64_t m0 = ~0ull, m1 = (w + 1 < w1) ? ~0ull : 0ull;
-      for (uint32_t j = 0; j < pre_len; ++j) {
-        const uint4 x = *reinterpret_cast<const uint4*>(db.B + (uint64_t)pre[j] * db.Wp + w);
-        m0 &= (uint64_t)x.x | ((uint64_t)x.y << 32);
-        m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
-      }
+      prefix_and(pc, db.B, db.Wp, pre, pre_len, w, m0, m1);
 #pragma unroll
       for (int i = 0; i < SQ - LQ; ++i)
         if ((g >> i) & 1) {
-          const uint4 x = *reinterpret_cast<const uint4*>(col[LQ + i] + w);
+          const uint4 x = load_global16(col[LQ + i] + w);
           m0 &= (uint64_t)x.x | ((uint64_t)x.y << 32);
           m1 &= (uint64_t)x.z | ((uint64_t)x.w << 32);
         }
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kCountThreads) void k_subset_count(DfsArgs a,
         c0[i] = 0;
         c1[i] = 0;
         if (i < ql) {
-          const uint4 v = *reinterpret_cast<const uint4*>(col[i] + w);
+          const uint4 v = load_global16(col[i] + w);
           c0[i] = (uint64_t)v.x | ((uint64_t)v.y << 32);
           c1[i] = (uint64_t)v.z | ((uint64_t)v.w << 32);
         }
