@@ -92,17 +92,28 @@ __global__ __launch_bounds__(256) void k_andpop(ClassArgs a) {
     const uint32_t w0 = task.w0, w1 = task.w1;
     const uint32_t nch = (w1 - w0 + TC - 1) / TC;
 
+    // the first PREFIX_REG prefix columns addressed once per task; every load
+    // goes through the global address space, so the LDS waits of the count
+    // loop do not wait for the next chunk's loads
+    const uint64_t* pc[PREFIX_REG];
+#pragma unroll
+    for (int j = 0; j < PREFIX_REG; ++j)
+      pc[j] = (uint32_t)j < pre_len ? db.B + (uint64_t)load_global_u32(pre + j) * db.Wp : nullptr;
     uint64_t v[RPT];
+    uint64_t pv[PREFIX_REG];
     uint64_t msk = 0;
     auto load_chunk = [&](uint32_t c) {
       const uint32_t w = w0 + c * TC + wi;
       const bool inb = w < w1;
       msk = inb ? ~0ull : 0ull;
-      for (uint32_t j = 0; j < pre_len && inb; ++j) msk &= db.B[(uint64_t)pre[j] * db.Wp + w];
+      for (uint32_t j = PREFIX_REG; j < pre_len && inb; ++j)
+        msk &= load_global_u64(db.B + (uint64_t)load_global_u32(pre + j) * db.Wp + w);
+#pragma unroll
+      for (int j = 0; j < PREFIX_REG; ++j) pv[j] = (inb && pc[j]) ? load_global_u64(pc[j] + w) : ~0ull;
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
         const uint64_t off = s_col[rg + RG * k];
-        v[k] = (inb && off != ~0ull) ? db.B[off + w] : 0ull;
+        v[k] = (inb && off != ~0ull) ? load_global_u64(db.B + off + w) : 0ull;
       }
     };
 
@@ -110,6 +121,8 @@ __global__ __launch_bounds__(256) void k_andpop(ClassArgs a) {
     load_chunk(0);
     for (uint32_t c = 0; c < nch; ++c) {
       __syncthreads();  // previous chunk counted
+#pragma unroll
+      for (int j = 0; j < PREFIX_REG; ++j) msk &= pv[j];
 #pragma unroll
       for (int k = 0; k < RPT; ++k) X[rg + RG * k][wi] = v[k] & msk;
       __syncthreads();
@@ -163,6 +176,12 @@ __global__ __launch_bounds__(256) void k_andpop_reg(ClassArgs a) {
     }
     const uint32_t* pre = a.pre_cols + cd.pre_off;
     const uint32_t pre_len = cd.proj ? 0u : cd.pre_len;  // a view has the prefix applied
+    // the first PREFIX_REG prefix columns addressed once per task, so their
+    // loads go out with the column loads (global address space throughout)
+    const uint64_t* pc[PREFIX_REG];
+#pragma unroll
+    for (int j = 0; j < PREFIX_REG; ++j)
+      pc[j] = (uint32_t)j < pre_len ? db.B + (uint64_t)load_global_u32(pre + j) * db.Wp : nullptr;
     uint32_t acc[TNP];
 #pragma unroll
     for (int p = 0; p < TNP; ++p) acc[p] = 0;
@@ -170,14 +189,12 @@ __global__ __launch_bounds__(256) void k_andpop_reg(ClassArgs a) {
       uint64_t m[4];
 #pragma unroll
       for (int h = 0; h < 4; ++h) m[h] = (w + h < task.w1) ? ~0ull : 0ull;
-      for (uint32_t j = 0; j < pre_len; ++j) {
-        const uint64_t* pc = db.B + (uint64_t)pre[j] * db.Wp + w;
-        const uint4 x = *reinterpret_cast<const uint4*>(pc);
-        const uint4 y = *reinterpret_cast<const uint4*>(pc + 2);
-        m[0] &= (uint64_t)x.x | ((uint64_t)x.y << 32);
-        m[1] &= (uint64_t)x.z | ((uint64_t)x.w << 32);
-        m[2] &= (uint64_t)y.x | ((uint64_t)y.y << 32);
-        m[3] &= (uint64_t)y.z | ((uint64_t)y.w << 32);
+      prefix_and(pc, db.B, db.Wp, pre, pre_len, w, m[0], m[1]);
+      {
+        const uint64_t* pc2[PREFIX_REG];
+#pragma unroll
+        for (int j = 0; j < PREFIX_REG; ++j) pc2[j] = pc[j] ? pc[j] + 2 : nullptr;
+        prefix_and(pc2, db.B + 2, db.Wp, pre, pre_len, w, m[2], m[3]);
       }
       uint64_t xv[TQ][4];
 #pragma unroll
@@ -185,8 +202,8 @@ __global__ __launch_bounds__(256) void k_andpop_reg(ClassArgs a) {
 #pragma unroll
         for (int h = 0; h < 4; ++h) xv[i][h] = 0;
         if (i < q) {
-          const uint4 v = *reinterpret_cast<const uint4*>(col[i] + w);
-          const uint4 u = *reinterpret_cast<const uint4*>(col[i] + w + 2);
+          const uint4 v = load_global16(col[i] + w);
+          const uint4 u = load_global16(col[i] + w + 2);
           xv[i][0] = ((uint64_t)v.x | ((uint64_t)v.y << 32)) & m[0];
           xv[i][1] = ((uint64_t)v.z | ((uint64_t)v.w << 32)) & m[1];
           xv[i][2] = ((uint64_t)u.x | ((uint64_t)u.y << 32)) & m[2];
