@@ -610,10 +610,11 @@ void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const in
                         const uint32_t* supp, uint32_t proj_on, uint32_t* pflag, uint32_t* prows,
                         uint64_t* pwords, hipStream_t s) {
   if (n == 0) return;
-  // at most 256 workgroups: each ends with a few device-wide atomic adds on
-  // the same counters, and with 4,096 of them those serialised (T40-style
-  // level steps: 214 against 156 us per mine call)
-  k_node_counts<<<grid_for(n, kThreads / 64, 256), kThreads, 0, s>>>(
+  // at most 1,024 workgroups: each ends with a few device-wide atomic adds
+  // on the same counters, and with 4,096 of them those serialised (T40-style
+  // level steps 0.46 ms per mine call, against 0.40 with 1,024 and 0.41 with
+  // 256; 256 cost the batch of 256 databases 9% on this kernel)
+  k_node_counts<<<grid_for(n, kThreads / 64, 1024), kThreads, 0, s>>>(
       n, k, parent, pcls, cls, dbs, tri, mfma_min_q, big_q, small_on, tiny_q, cnt, is_cls, tri_sz,
       st, supp, proj_on, pflag, prows, pwords);
   BM_LAUNCH_CHECK();
