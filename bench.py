@@ -153,13 +153,13 @@ DTYPE = {"fp4": "u64 bitsets; fp4 (e2m1) MFMA, fp32 accumulate (exact: counts < 
 # (workload, kernel, form) -> (source file, its sha256, bytes per launch).
 TRAFFIC = {
     # dense_planted 1M x 4,096, cache-cold mine (profiles/dense_planted_1M_hbm_traffic.md)
-    (3, "gram_mfma", "fp4"): (("k_gram_mfma.hip", "gram_fp4.hpp"), "d27932004d2f498b67268f138a80b65e54589420c4cdb6dc21e9fe2e3023fae9", 4932.8e6),
-    (3, "gram_small", "fp4"): ("k_gram_small.hip", "4a82c6426d00e4149cdc680e6d8065aa796d675ba67c529e6b6e4cdd4e07c64e", 226.7e6),
-    (3, "dfs", "fp4"): ("k_subsets.hip", "2109e75ca138125ad95a1d2f12b68e6102d64a5d0421e9effe55855d65b95f7e", 769.8e6),
+    (3, "gram_mfma", "fp4"): (("k_gram_mfma.hip", "gram_fp4.hpp", "internal.hpp"), "4995f88d9b16f234318598fd5984b77434d1ba206e5f866b52c9a8a21c6538d7", 4924.9e6),
+    (3, "gram_small", "fp4"): (("k_gram_small.hip", "internal.hpp"), "6245336f0f9c1d5710f69f47880ee96ab0678e98a7d7a598fb74b024d4287fdd", 225.5e6),
+    (3, "dfs", "fp4"): (("k_subsets.hip", "internal.hpp"), "7733ae4634918b5e502294cd009d3e1dd5e305d1f82bd7f37077fffdff1370c0", 755.8e6),
     # Quest T40-style 1M x 2,000, cache-cold mine (profiles/quest_t40_1M_hbm_traffic.md)
-    (5, "gram_mfma", "fp4"): (("k_gram_mfma.hip", "gram_fp4.hpp"), "d27932004d2f498b67268f138a80b65e54589420c4cdb6dc21e9fe2e3023fae9", 2588.4e6),
-    (5, "gram_small", "fp4"): ("k_gram_small.hip", "4a82c6426d00e4149cdc680e6d8065aa796d675ba67c529e6b6e4cdd4e07c64e", 118.5e6),
-    (5, "dfs", "fp4"): ("k_subsets.hip", "2109e75ca138125ad95a1d2f12b68e6102d64a5d0421e9effe55855d65b95f7e", 344.3e6),
+    (5, "gram_mfma", "fp4"): (("k_gram_mfma.hip", "gram_fp4.hpp", "internal.hpp"), "4995f88d9b16f234318598fd5984b77434d1ba206e5f866b52c9a8a21c6538d7", 2715.2e6),
+    (5, "gram_small", "fp4"): (("k_gram_small.hip", "internal.hpp"), "6245336f0f9c1d5710f69f47880ee96ab0678e98a7d7a598fb74b024d4287fdd", 125.7e6),
+    (5, "dfs", "fp4"): (("k_subsets.hip", "internal.hpp"), "7733ae4634918b5e502294cd009d3e1dd5e305d1f82bd7f37077fffdff1370c0", 349.3e6),
 }
 WORKLOAD = None
 
