@@ -167,10 +167,11 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
       const uint64_t tsz = cl ? (uint64_t)kc * (kc - 1) / 2 : 0ull;
       is_cls[i] = cl ? 1u : 0u;
       tri_sz[i] = tsz;
+      bool pj = false;
       if (proj_on) {
         // the class's prefix is this node's itemset: its support is the node's
         const uint32_t sp = supp[i];
-        const bool pj = cl && project_class(kind, kc, sp, n_db, proj_on);
+        pj = cl && project_class(kind, kc, sp, n_db, proj_on);
         pflag[i] = pj ? 1u : 0u;
         prows[i] = pj ? sp : 0u;
         pwords[i] = pj ? (uint64_t)kc * view_padded_words(sp) : 0ull;
@@ -182,9 +183,18 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
         }
       }
       if (cl) {
-        loc[ST_CAND_M + kind] += tsz;
+        // a narrow tail's candidates and 32-wide block pairs go to the 32-wide kernel
+        const bool tail = kind == 0 && small_on && !pj && gram_tail(kc);
+        const uint64_t qm = tail ? gram_tail_q(kc) : kc;
+        const uint64_t tm_sz = tail ? qm * (qm - 1) / 2 : tsz;
+        loc[ST_CAND_M + kind] += tm_sz;
         loc[ST_COLS_M + kind] += kc + k;
         loc[ST_CLS_M + kind] += 1;
+        if (tail) {
+          loc[ST_CAND_S] += tsz - tm_sz;
+          loc[ST_COLS_S] += kc + k;
+          loc[NC_PAIRS_V] += gram_tail_pairs(kc);
+        }
         // 16-wide block pairs: also a bound on a mid-size class's 32-wide ones
         if (kind == 0) loc[NC_PAIRS_M] += mfma_pairs(kc);
         else if (kind == 3) loc[NC_PAIRS_B] += mfma_pairs(kc, GRAM_TILE_BIG);
@@ -269,6 +279,8 @@ __device__ inline uint32_t wend_of(const DbInfo& d, int kind) {
 struct ClassWork {
   int kind;
   uint32_t npairs, nsplit, split, block, wend;
+  uint32_t qm;                                  // children the kernel's tasks cover
+  uint32_t npairs_s, nsplit_s, split_s, wend_s;  // a kind-0 class's narrow tail (32-wide)
 };
 
 __device__ inline ClassWork class_work(const ClassDesc& cd, const DbInfo& d, uint32_t mfma_min_q,
@@ -276,8 +288,17 @@ __device__ inline ClassWork class_work(const ClassDesc& cd, const DbInfo& d, uin
   ClassWork w;
   w.kind = class_kind(cd.q, mfma_min_q, geo.big_q, geo.small_on, geo.tiny_q);
   w.wend = wend_of(d, w.kind);
+  w.qm = cd.q;
+  w.npairs_s = w.nsplit_s = w.split_s = w.wend_s = 0;
   if (w.kind == 0) {
-    w.npairs = mfma_pairs(cd.q);
+    if (geo.small_on && !cd.proj && gram_tail(cd.q)) {  // (a projected class keeps its tail)
+      w.qm = gram_tail_q(cd.q);
+      w.npairs_s = gram_tail_pairs(cd.q);
+      w.split_s = geo.split_s;
+      w.wend_s = wend_of(d, 4);
+      w.nsplit_s = (w.wend_s + w.split_s - 1) / w.split_s;
+    }
+    w.npairs = mfma_pairs(w.qm);
     w.split = geo.split_m;
     w.block = GRAM_TILE;
   } else if (w.kind == 3) {  // 256 x 256 block pairs
@@ -318,7 +339,7 @@ __global__ void k_class_task_counts(const ClassDesc* __restrict__ cls, uint64_t 
     cv[c] = w.kind == 1 ? nt : 0u;
     ct[c] = w.kind == 2 ? (dfs ? 1u : nt) : 0u;
     cb[c] = w.kind == 3 ? nt : 0u;
-    cs[c] = w.kind == 4 ? nt : 0u;
+    cs[c] = (w.kind == 4 ? nt : 0u) + w.npairs_s * w.nsplit_s;
   }
 }
 
@@ -372,8 +393,23 @@ __global__ void k_write_class_tasks(const ClassDesc* __restrict__ cls, uint64_t 
                 : w.kind == 2 ? tt + ot[c]
                 : w.kind == 3 ? tb + ob[c]
                               : ts + os[c];
-    write_tasks((uint32_t)c, cd.q, w.npairs, w.block, w.nsplit, w.split, w.wend, out, lane,
+    write_tasks((uint32_t)c, w.qm, w.npairs, w.block, w.nsplit, w.split, w.wend, out, lane,
                 (int)blockDim.x);
+    if (w.npairs_s) {  // the narrow tail: 32-wide row blocks 0 .. tb against block tb
+      const uint32_t tb32 = w.npairs_s - 1;
+      const uint64_t total = (uint64_t)w.npairs_s * w.nsplit_s;
+      Task* os_out = ts + os[c];
+      for (uint64_t t = lane; t < total; t += blockDim.x) {
+        const uint32_t p = (uint32_t)(t / w.nsplit_s), sp = (uint32_t)(t % w.nsplit_s);
+        Task k;
+        k.cls = (uint32_t)c;
+        k.bi = (uint16_t)p;
+        k.bl = (uint16_t)tb32;
+        k.w0 = sp * w.split_s;
+        k.w1 = min(w.wend_s, (sp + 1) * w.split_s);
+        os_out[t] = k;
+      }
+    }
   }
 }
 
@@ -426,7 +462,7 @@ __device__ inline void fill_classes_body(const LevelPost& a, uint64_t t0, uint64
       a.cv[ci] = w.kind == 1 ? nt : 0u;
       a.ct[ci] = w.kind == 2 ? (a.dfs ? 1u : nt) : 0u;
       a.cb[ci] = w.kind == 3 ? nt : 0u;
-      a.cs[ci] = w.kind == 4 ? nt : 0u;
+      a.cs[ci] = (w.kind == 4 ? nt : 0u) + w.npairs_s * w.nsplit_s;
     }
     const uint32_t* f1 = a.dbs[d].f1;
     uint64_t x = i;

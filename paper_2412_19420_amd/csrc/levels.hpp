@@ -198,6 +198,20 @@ __host__ __device__ inline int class_kind(uint32_t q, uint32_t mfma_min_q, uint3
   if (q <= tiny_q) return 2;
   return small_on ? 4 : 1;
 }
+// Narrow tails: a class on the 128-wide tiles (kind 0) whose last column
+// block holds at most 32 children has that block's pairs computed by the
+// 32-wide kernel (when it is on): a 128-wide tile there would spend all its
+// MFMAs on a few columns.  The 128-wide tasks then cover the first
+// gram_tail_q(q) children, and the tail is gram_tail_pairs(q) 32-wide block
+// pairs: every 32-wide row block up to and including the tail's own against
+// the tail's block.
+__host__ __device__ inline bool gram_tail(uint32_t q) {
+  return q > GRAM_TILE && q - (q - 1) / GRAM_TILE * GRAM_TILE <= GRAM_SMALL_TILE;
+}
+__host__ __device__ inline uint32_t gram_tail_q(uint32_t q) { return (q - 1) / GRAM_TILE * GRAM_TILE; }
+__host__ __device__ inline uint32_t gram_tail_pairs(uint32_t q) {
+  return gram_tail_q(q) / GRAM_SMALL_TILE + 1;
+}
 // Kinds whose task word ranges are rounded to GRAM_KW (LDS-staged MFMA kernels).
 __host__ __device__ inline bool is_mfma_kind(int kind) { return kind == 0 || kind == 3; }
 inline uint32_t host_andpop_pairs(uint32_t q) {

@@ -445,7 +445,7 @@ void run_class_kernels(const DbInfo* ddb, const uint32_t* child_item, const Step
                      tu.mfma_fp4, w.prefixed, s);
     tm.end(8.0 * nW * (double)w.st[ST_COLS_M], gram_ops(0, 0));
   }
-  if (w.ub_s && w.st[ST_CLS_S]) {
+  if (w.ub_s && (w.st[ST_CLS_S] || w.st[ST_CAND_S])) {  // mid-size classes or narrow tails
     a.tasks = w.ts.get();
     a.ntasks = w.os.get() + w.ncls;
     tm.begin(BM_K_GRAM_SMALL);
@@ -486,11 +486,20 @@ void host_classes(StepWork& w, const std::vector<ClassDesc>& hc, const DbInfo* d
     w.T += tsz;
     const int kind =
         class_kind(c.q, tu.mfma_min_q, tu.mfma_big_q, tu.mfma_small ? 1u : 0u, tu.tiny_q);
+    // a narrow tail's candidates and 32-wide block pairs go to the 32-wide kernel
+    const bool tail = kind == 0 && tu.mfma_small && gram_tail(c.q);
+    const uint64_t qm = tail ? gram_tail_q(c.q) : c.q;
+    const uint64_t tm_sz = tail ? qm * (qm - 1) / 2 : tsz;
     if (kind == 0) pm += host_mfma_pairs(c.q);
     else if (kind == 3) pb += host_mfma_pairs(c.q, GRAM_TILE_BIG);
     else if (kind == 1 || kind == 4) pv += host_andpop_pairs(c.q);
     else ct += 1;
-    w.st[ST_CAND_M + kind] += tsz;
+    if (tail) {
+      pv += gram_tail_pairs(c.q);
+      w.st[ST_CAND_S] += tsz - tm_sz;
+      w.st[ST_COLS_S] += c.q;
+    }
+    w.st[ST_CAND_M + kind] += tm_sz;
     w.st[ST_COLS_M + kind] += c.q;
     w.st[ST_CLS_M + kind] += 1;
   }

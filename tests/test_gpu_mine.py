@@ -141,6 +141,10 @@ def test_build_multi_chunk_tiles_all_pairs(bm, m):
     (3_001, 300, None, 0.1),        # three MFMA tiles, ragged in both dims
     (2_433, 600, None, 0.08),       # three 256-wide MFMA tiles, ragged
     (65, 70, None, 0.5),            # one word plus one bit
+    (2_000, 129, None, 0.2),        # a narrow tail of 1 column: its pairs on the 32-wide kernel
+    (2_000, 160, None, 0.2),        # a narrow tail of 32 columns
+    (2_000, 161, None, 0.2),        # 33 columns: no tail, a ragged 128-wide tile
+    (1_500, 288, None, 0.15),       # three 128-wide blocks and a 32-column tail
 ])
 def test_pair_support_equals_gram(bm, n, m, k, density):
     print(f"pair_support n={n} m={m}", flush=True)
