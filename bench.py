@@ -152,14 +152,15 @@ DTYPE = {"fp4": "u64 bitsets; fp4 (e2m1) MFMA, fp32 accumulate (exact: counts < 
 # the copy calibration), valid only while the kernel's source is unchanged:
 # (workload, kernel, form) -> (source file, its sha256, bytes per launch).
 TRAFFIC = {
-    # dense_planted 1M x 4,096, cache-cold mine (profiles/dense_planted_1M_hbm_traffic.md)
-    (3, "gram_mfma", "fp4"): (("k_gram_mfma.hip", "gram_fp4.hpp", "internal.hpp"), "4995f88d9b16f234318598fd5984b77434d1ba206e5f866b52c9a8a21c6538d7", 4924.9e6),
-    (3, "gram_small", "fp4"): (("k_gram_small.hip", "internal.hpp"), "6245336f0f9c1d5710f69f47880ee96ab0678e98a7d7a598fb74b024d4287fdd", 225.5e6),
-    (3, "dfs", "fp4"): (("k_subsets.hip", "internal.hpp"), "7733ae4634918b5e502294cd009d3e1dd5e305d1f82bd7f37077fffdff1370c0", 755.8e6),
+    # dense_planted 1M x 4,096, cache-cold mine (profiles/dense_planted_1M_hbm_traffic.md); the
+    # Gram entries also hash the task generation, which decides the tiles a launch computes
+    (3, "gram_mfma", "fp4"): (("k_gram_mfma.hip", "gram_fp4.hpp", "internal.hpp", "k_levels.hip", "levels.hpp"), "ec111bd71f14fec826e9289d4f4c4a6d66cf8c40eda635c897b33ad6096e0fb8", 4640.1e6),
+    (3, "gram_small", "fp4"): (("k_gram_small.hip", "internal.hpp", "k_levels.hip", "levels.hpp"), "b61a9e6b21c29c1ee7e5d4e59293d02ed9c508550215fc0a5196a0793798bcd4", 274.4e6),
+    (3, "dfs", "fp4"): (("k_subsets.hip", "internal.hpp"), "7733ae4634918b5e502294cd009d3e1dd5e305d1f82bd7f37077fffdff1370c0", 757.7e6),
     # Quest T40-style 1M x 2,000, cache-cold mine (profiles/quest_t40_1M_hbm_traffic.md)
-    (5, "gram_mfma", "fp4"): (("k_gram_mfma.hip", "gram_fp4.hpp", "internal.hpp"), "4995f88d9b16f234318598fd5984b77434d1ba206e5f866b52c9a8a21c6538d7", 2715.2e6),
-    (5, "gram_small", "fp4"): (("k_gram_small.hip", "internal.hpp"), "6245336f0f9c1d5710f69f47880ee96ab0678e98a7d7a598fb74b024d4287fdd", 125.7e6),
-    (5, "dfs", "fp4"): (("k_subsets.hip", "internal.hpp"), "7733ae4634918b5e502294cd009d3e1dd5e305d1f82bd7f37077fffdff1370c0", 349.3e6),
+    (5, "gram_mfma", "fp4"): (("k_gram_mfma.hip", "gram_fp4.hpp", "internal.hpp", "k_levels.hip", "levels.hpp"), "ec111bd71f14fec826e9289d4f4c4a6d66cf8c40eda635c897b33ad6096e0fb8", 2571.7e6),
+    (5, "gram_small", "fp4"): (("k_gram_small.hip", "internal.hpp", "k_levels.hip", "levels.hpp"), "b61a9e6b21c29c1ee7e5d4e59293d02ed9c508550215fc0a5196a0793798bcd4", 221.8e6),
+    (5, "dfs", "fp4"): (("k_subsets.hip", "internal.hpp"), "7733ae4634918b5e502294cd009d3e1dd5e305d1f82bd7f37077fffdff1370c0", 348.9e6),
 }
 WORKLOAD = None
 
