@@ -134,10 +134,11 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
   for (uint64_t i = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6; i < n; i += nwaves) {
     const int32_t c = pcls[parent[i]];
     uint32_t kc = 0;
-    uint64_t n_db = 0;
+    uint64_t n_db = 0, w_db = 0;
     if (c >= 0) {
       const ClassDesc cd = cls[c];
       n_db = dbs[cd.db].n;
+      w_db = dbs[cd.db].W;
       const uint64_t li = i - cd.child0;
       if (li + 1 < cd.q) {
         const uint64_t rs = cd.tri_off + tri_index(li, li + 1, cd.q);
@@ -193,12 +194,17 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
         if (tail) {
           loc[ST_CAND_S] += tsz - tm_sz;
           loc[ST_COLS_S] += kc + k;
-          loc[NC_PAIRS_V] += gram_tail_pairs(kc);
+          // in 16-wide units, like a mid-size class's pairs: four per 32-wide pair
+          loc[NC_PAIRS_V] += 4ull * gram_tail_pairs(kc);
+          loc[NC_PAIRS_VW] += 4ull * gram_tail_pairs(kc) * w_db;
         }
         // 16-wide block pairs: also a bound on a mid-size class's 32-wide ones
         if (kind == 0) loc[NC_PAIRS_M] += mfma_pairs(kc);
         else if (kind == 3) loc[NC_PAIRS_B] += mfma_pairs(kc, GRAM_TILE_BIG);
-        else if (kind == 1 || kind == 4) loc[NC_PAIRS_V] += andpop_pairs(kc);
+        else if (kind == 1 || kind == 4) {
+          loc[NC_PAIRS_V] += andpop_pairs(kc);
+          loc[NC_PAIRS_VW] += (unsigned long long)andpop_pairs(kc) * w_db;
+        }
         else loc[NC_TINY] += 1;
       }
     }

@@ -51,12 +51,14 @@ enum { ST_CAND_M = 0, ST_CAND_V, ST_CAND_T, ST_CAND_B, ST_CAND_S, ST_COLS_M, ST_
        ST_COLS_B, ST_COLS_S, ST_CLS_M, ST_CLS_V, ST_CLS_T, ST_CLS_B, ST_CLS_S, ST_COUNT };
 // The node-count kernel also sums the next step's task counts: 128-wide tile
 // pairs, 16-wide block pairs and tiny classes (sizes for the task lists), the
-// 256-wide tile pairs of big classes (NC_PAIRS_B, at the end),
+// 256-wide tile pairs of big classes (NC_PAIRS_B), the 16-wide block pairs
+// weighted by their databases' words (NC_PAIRS_VW: the split of the 32-wide
+// kernel's word ranges),
 // and for the projected classes on the 128-wide (M) and 256-wide (B) kernels
 // their candidates and work (the prefix's support times the class's
 // candidates), and their children.
 enum { NC_PAIRS_M = ST_COUNT, NC_PAIRS_V, NC_TINY, NC_PJ_CAND_M, NC_PJ_WORK_M, NC_PJ_CAND_B,
-       NC_PJ_WORK_B, NC_PJ_COLS, NC_PAIRS_B, NC_COUNT };
+       NC_PJ_WORK_B, NC_PJ_COLS, NC_PAIRS_B, NC_PAIRS_VW, NC_COUNT };
 
 // Whether a class of q children whose prefix has support s_prefix (in a
 // database of n transactions) is projected: its children's columns are

@@ -270,8 +270,8 @@ uint64_t round_up(uint64_t a, uint64_t b) { return ceil_div(a, b) * b; }
 
 // Word-split lengths for a step: enough tasks to fill the chip, not shorter
 // than a minimum that keeps per-task overheads small.
-TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_v, uint64_t classes_t,
-                   const Tuning& tu) {
+TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_v, uint64_t pairs_vw,
+                   uint64_t classes_t, const Tuning& tu) {
   const uint64_t target = (uint64_t)cu_count() * 8;
   const uint64_t W = std::max<uint64_t>(1, Wmax);
   TaskGeom g{};
@@ -297,8 +297,16 @@ TaskGeom make_geom(uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_v, uint64_t c
   g.split_b = tu.split_words ? (uint32_t)round_up(tu.split_words, GRAM_KW) : whole;
   // 32-wide block pairs number about a quarter of the 16-wide ones, and each
   // is one wave's task: two per workgroup slot (measured 8% faster on the
-  // T40-style workload than four, and no slower on the dense one)
-  g.split_s = (uint32_t)pick((pairs_v + 3) / 4, 128, GRAM_SMALL_KW, 2);
+  // T40-style workload than four, and no slower on the dense one).  The
+  // length comes from the pairs weighted by their databases' words, so that
+  // in a batch of unequal databases the long ones are split as finely as the
+  // short ones' whole ranges (one database: the same as splitting W evenly).
+  if (tu.split_words || pairs_vw == 0) {
+    g.split_s = (uint32_t)pick((pairs_v + 3) / 4, 128, GRAM_SMALL_KW, 2);
+  } else {
+    const uint64_t len = ceil_div((pairs_vw + 3) / 4, target * 2);
+    g.split_s = (uint32_t)round_up(std::min<uint64_t>(W, std::max<uint64_t>(len, 128)), GRAM_SMALL_KW);
+  }
   g.big_q = tu.mfma_big_q;
   g.small_on = tu.mfma_small ? 1u : 0u;
   g.tiny_q = tu.tiny_q;
@@ -339,9 +347,9 @@ struct StepWork {
 // offsets, then the records.  The kernels read the totals from device memory;
 // the host only sizes buffers from upper bounds.
 void prepare_tasks(StepWork& w, const DbInfo* ddb, uint64_t Wmax, uint64_t pairs_m, uint64_t pairs_b,
-                   uint64_t pairs_v, uint64_t classes_t, const Tuning& tu, bool dfs, uint32_t level,
-                   hipStream_t s) {
-  const TaskGeom g = make_geom(Wmax, pairs_m, pairs_v, classes_t, tu);
+                   uint64_t pairs_v, uint64_t pairs_vw, uint64_t classes_t, const Tuning& tu,
+                   bool dfs, uint32_t level, hipStream_t s) {
+  const TaskGeom g = make_geom(Wmax, pairs_m, pairs_v, pairs_vw, classes_t, tu);
   const uint64_t Wm = round_up(std::max<uint64_t>(1, Wmax), GRAM_KW);
   w.ub_m = pairs_m * ceil_div(Wm, g.split_m);
   w.ub_b = pairs_b * ceil_div(Wm, g.split_b);
@@ -470,8 +478,8 @@ void run_class_kernels(const DbInfo* ddb, const uint32_t* child_item, const Step
 
 // Classes given on the host (the roots of each database, or an explicit
 // column list): records, a zeroed triangle buffer and the task lists.
-void host_classes(StepWork& w, const std::vector<ClassDesc>& hc, const DbInfo* ddb, uint64_t Wmax,
-                  const Tuning& tu, bool dfs, hipStream_t s) {
+void host_classes(StepWork& w, const std::vector<ClassDesc>& hc, const DbInfo* ddb,
+                  const DbInfo* hdb, uint64_t Wmax, const Tuning& tu, bool dfs, hipStream_t s) {
   w.ncls = hc.size();
   w.prefixed = false;
   for (const auto& c : hc) w.prefixed |= c.pre_len > 0;
@@ -479,7 +487,7 @@ void host_classes(StepWork& w, const std::vector<ClassDesc>& hc, const DbInfo* d
   upload(w.cls.get(), hc, s);
   w.pre.alloc(1, s);
   launch_fill_u32(w.pre.get(), 0, 1, s);
-  uint64_t pm = 0, pb = 0, pv = 0, ct = 0;
+  uint64_t pm = 0, pb = 0, pv = 0, pvw = 0, ct = 0;  // pvw: pv weighted by the databases' words
   w.T = 0;
   for (const auto& c : hc) {
     const uint64_t tsz = (uint64_t)c.q * (c.q - 1) / 2;
@@ -492,10 +500,13 @@ void host_classes(StepWork& w, const std::vector<ClassDesc>& hc, const DbInfo* d
     const uint64_t tm_sz = tail ? qm * (qm - 1) / 2 : tsz;
     if (kind == 0) pm += host_mfma_pairs(c.q);
     else if (kind == 3) pb += host_mfma_pairs(c.q, GRAM_TILE_BIG);
-    else if (kind == 1 || kind == 4) pv += host_andpop_pairs(c.q);
-    else ct += 1;
+    else if (kind == 1 || kind == 4) {
+      pv += host_andpop_pairs(c.q);
+      pvw += (uint64_t)host_andpop_pairs(c.q) * hdb[c.db].W;
+    } else ct += 1;
     if (tail) {
-      pv += gram_tail_pairs(c.q);
+      pv += 4ull * gram_tail_pairs(c.q);  // in 16-wide units: four per 32-wide pair
+      pvw += 4ull * gram_tail_pairs(c.q) * hdb[c.db].W;
       w.st[ST_CAND_S] += tsz - tm_sz;
       w.st[ST_COLS_S] += c.q;
     }
@@ -505,7 +516,7 @@ void host_classes(StepWork& w, const std::vector<ClassDesc>& hc, const DbInfo* d
   }
   w.tri.alloc(w.T, s);
   launch_fill_u32(w.tri.get(), 0, w.T, s);
-  prepare_tasks(w, ddb, Wmax, pm, pb, pv, ct, tu, dfs, 1, s);
+  prepare_tasks(w, ddb, Wmax, pm, pb, pv, pvw, ct, tu, dfs, 1, s);
 }
 
 struct Level {
@@ -801,7 +812,7 @@ void pair_support_impl(const bm_db* db, const uint32_t* items, uint32_t k, uint3
   std::vector<ClassDesc> hc;
   if (k >= 2) {
     hc.push_back(ClassDesc{0, 0, k, 0, 0, 0, 0});
-    host_classes(w, hc, ddb.get(), db->W, tu, false, s);
+    host_classes(w, hc, ddb.get(), hdb.data(), db->W, tu, false, s);
     KTimer tm(0u, s);
     run_class_kernels(ddb.get(), d_items.get(), w, tu, (double)db->W, (double)db->n, tm, s);
   }
@@ -1124,7 +1135,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
       TBuf<int32_t> pcls_prev(hpcls.size(), s);
       upload(pcls_prev.get(), hpcls, s);
       auto w = std::make_unique<StepWork>();
-      host_classes(*w, roots, ddb_p, Wmax, tu, tu.dfs, s);
+      host_classes(*w, roots, ddb_p, hdb.data(), Wmax, tu, tu.dfs, s);
       uint32_t k = 1;
       for (;;) {
         const uint64_t nk = L[k].n;
@@ -1195,6 +1206,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         const uint64_t n_next = tot[0], ncls = tot[1], Tn = tot[2];
         const uint64_t* stt = tot + nscan;  // the step counters
         const uint64_t PM = stt[NC_PAIRS_M], PB = stt[NC_PAIRS_B], PV = stt[NC_PAIRS_V],
+                       PVW = stt[NC_PAIRS_VW],
                        PT = stt[NC_TINY];
         if (n_next == 0) break;
         if (k + 1 > BM_MAX_LEVELS)
@@ -1246,7 +1258,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         lp.pcls_out = pcls_k.get();
         lp.ztri = nw->tri.get();
         lp.nz = Tn;
-        lp.geo = make_geom(Wmax, PM, PV, PT, tu);
+        lp.geo = make_geom(Wmax, PM, PV, PVW, PT, tu);
         lp.mfma_min_q = tu.mfma_min_q;
         lp.dfs = tu.dfs ? 1u : 0u;
         for (auto& c : nw->ccount) c.alloc(ncls, s);
@@ -1285,7 +1297,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
           lp.pwork = nw->pwork.get();
         }
         launch_level_post(lp, s);
-        prepare_tasks(*nw, ddb_p, Wmax, PM, PB, PV, PT, tu, tu.dfs, k + 1, s);
+        prepare_tasks(*nw, ddb_p, Wmax, PM, PB, PV, PVW, PT, tu, tu.dfs, k + 1, s);
         tm.end();
         w = std::move(nw);
         pcls_prev = pcls_k;
