@@ -90,15 +90,19 @@ constexpr int PK_LD = PK_KR + 1;          // padded LDS row (conflict-free OR)
 // 10,719), 10,240 missed 9% of them, and those tiles' second passes made the
 // build 29% slower (0.363 against 0.281 ms).
 constexpr int PK_ECAP = 12288;
-// Sparse databases (at most PK_SPARSE_ROW elements per row on average) are
-// packed with 8,192-element chunks (32 KB), measured faster on the batch of
-// 256 Quest-style databases.
-constexpr int PK_ECAP_SPARSE = 8192;
-constexpr int PK_SPARSE_ROW = 32;
 constexpr int PK_UNROLL = 8;
 // 16 waves per workgroup hide the latency of the staging loads and LDS atomics
 // (measured 2.1x faster than 4 waves on the dense 1M x 4,096 workload).
 constexpr int PK_T = 1024;
+// Sparse databases (at most PK_SPARSE_ROW elements per row on average: a
+// tile's mean fits one chunk) are packed by 512-thread workgroups with
+// 6,144-element chunks: 46 KB of LDS, so three tiles share a CU instead of
+// two.  Their tiles hold few ids and are bound by the latency of each tile's
+// steps, which more tiles in flight hide: the batch of 256 Quest-style
+// databases builds in 1.21 against 1.29 ms (1,024 threads, 8,192 elements).
+constexpr int PK_ECAP_SPARSE = 6144;
+constexpr int PK_T_SPARSE = 512;
+constexpr int PK_SPARSE_ROW = 24;  // 24 x 256 rows = one chunk
 
 // Workgroups are dispatched to the 8 XCDs in turn, so block b runs on XCD
 // b % 8.  Giving each XCD a contiguous range of tiles lets the 32-byte
@@ -138,16 +142,16 @@ __device__ __forceinline__ void pack_or_window(uint32_t (&xe)[EPT], unsigned lon
   }
 }
 
-template <int ECAP>
+template <int ECAP, int T>
 __device__ __forceinline__ void pack_tile(PackSmem<ECAP>& sm, const uint64_t* __restrict__ rp,
                                           const uint32_t* __restrict__ ci, uint64_t n, uint64_t nnz,
                                           uint32_t m, unsigned long long* __restrict__ B, uint64_t Wp,
                                           uint32_t* __restrict__ colsum, uint32_t* __restrict__ err,
                                           uint64_t blk) {
-  static_assert(ECAP % PK_T == 0, "whole entries per thread");
+  static_assert(ECAP % T == 0, "whole entries per thread");
   static_assert(ECAP * sizeof(uint32_t) >= PK_CW * PK_LD * sizeof(unsigned long long),
                 "the entry buffer holds a window bitmap");
-  constexpr int EPT = ECAP / PK_T;  // entries per thread
+  constexpr int EPT = ECAP / T;  // entries per thread
   static_assert(PK_KR == 4, "a column's words are the four lanes of a quad");
   // two window bitmaps: XA, and XB over the entry buffer once the entries are
   // in registers -- window w is written out of one while window w + 1 is
@@ -165,7 +169,7 @@ __device__ __forceinline__ void pack_tile(PackSmem<ECAP>& sm, const uint64_t* __
   } else {
     // the tile's rows r0 .. r0 + nr - 1 check row_ptr[r] <= row_ptr[r + 1], so
     // the tiles together check every row
-    for (int t = tid; t <= nr; t += PK_T) {
+    for (int t = tid; t <= nr; t += T) {
       const uint64_t v = rp[r0 + t];
       s_rp[t] = min(v, nnz);
       if (t < nr && rp[r0 + t + 1] < v) bad |= 1u;
@@ -176,23 +180,23 @@ __device__ __forceinline__ void pack_tile(PackSmem<ECAP>& sm, const uint64_t* __
   const uint64_t e1 = max(e0, s_rp[nr]);
   const uint32_t nwin = (m + PK_CW - 1) / PK_CW;
   // XA starts clear; each window's write-out clears what it read
-  for (int i = tid; i < PK_CW * PK_LD; i += PK_T) XA[i] = 0ull;
+  for (int i = tid; i < PK_CW * PK_LD; i += T) XA[i] = 0ull;
   const int wi = tid & (PK_KR - 1), cs = tid / PK_KR;  // write-out: word wi of columns cs, cs + 256, ..
   for (uint64_t ea = e0; ea < e1 || (ea == e0 && e0 == e1); ea += ECAP) {
     const uint64_t eb = min<uint64_t>(e1, ea + ECAP);
     const int ne = (int)(eb - ea);
     const bool first = ea == e0, last = eb == e1;
     __syncthreads();  // previous chunk fully consumed
-    for (int base = 0; base < ne; base += PK_T * PK_UNROLL) {
+    for (int base = 0; base < ne; base += T * PK_UNROLL) {
       uint32_t v[PK_UNROLL];
 #pragma unroll
       for (int u = 0; u < PK_UNROLL; ++u) {
-        const int k = base + u * PK_T + tid;
+        const int k = base + u * T + tid;
         v[u] = k < ne ? ci[ea + k] : 0u;
       }
 #pragma unroll
       for (int u = 0; u < PK_UNROLL; ++u) {
-        const int k = base + u * PK_T + tid;
+        const int k = base + u * T + tid;
         if (k < ne) {
           if (v[u] >= m) bad |= 2u;
           s_e[k] = v[u] < m ? (v[u] << PK_RBITS) : 0xffffffffu;
@@ -200,7 +204,7 @@ __device__ __forceinline__ void pack_tile(PackSmem<ECAP>& sm, const uint64_t* __
       }
     }
     __syncthreads();
-    for (int r = tid; r < nr; r += PK_T) {
+    for (int r = tid; r < nr; r += T) {
       const uint64_t a = max(s_rp[r], ea), b = max(a, min(s_rp[r + 1], eb));
       uint64_t e = a;
       for (; e + 4 <= b; e += 4) {  // four independent LDS round trips at a time
@@ -217,11 +221,11 @@ __device__ __forceinline__ void pack_tile(PackSmem<ECAP>& sm, const uint64_t* __
     uint32_t xe[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
-      const int k = u * PK_T + tid;
+      const int k = u * T + tid;
       xe[u] = k < ne ? s_e[k] : 0xffffffffu;
     }
     __syncthreads();  // every entry is in registers: the entry buffer becomes XB
-    for (int i = tid; i < PK_CW * PK_LD; i += PK_T) XB[i] = 0ull;
+    for (int i = tid; i < PK_CW * PK_LD; i += T) XB[i] = 0ull;
     if (nwin) pack_or_window(xe, XA, 0, min<uint32_t>(PK_CW, m));
     __syncthreads();
     for (uint32_t win = 0; win < nwin; ++win) {
@@ -229,7 +233,7 @@ __device__ __forceinline__ void pack_tile(PackSmem<ECAP>& sm, const uint64_t* __
       unsigned long long* Xn = (win & 1) ? XA : XB;
       const uint32_t c0 = win * PK_CW;
       const uint32_t cw = min<uint32_t>(PK_CW, m - c0);
-      for (uint32_t c = cs; c < cw; c += PK_T / PK_KR) {
+      for (uint32_t c = cs; c < cw; c += T / PK_KR) {
         unsigned long long v = Xc[c * PK_LD + wi];
         Xc[c * PK_LD + wi] = 0ull;  // clear for a later window as it is written out
         unsigned long long* dst = B + (uint64_t)(c0 + c) * Wp + blk * PK_KR + wi;
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(PK_T) __attribute__((amdgpu_waves_per_eu(8))) void 
     return;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0 && rp[0] != 0) atomicOr(err, 8u);
-  pack_tile(sm, rp, ci, n, nnz, m, B, Wp, colsum, err, xcd_tile(blockIdx.x, gridDim.x));
+  pack_tile<PK_ECAP, PK_T>(sm, rp, ci, n, nnz, m, B, Wp, colsum, err, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Batched construction, part 1 -- one workgroup per database: read nnz =
@@ -295,8 +299,8 @@ __global__ __launch_bounds__(kThreads) void k_build_multi_pre(PackJob* __restric
 // Batched construction, part 2 -- the 256-row tiles of a list of databases in
 // one grid: block b belongs to list entry e with kstart[e] <= b < kstart[e + 1],
 // database kjob[e].
-template <int ECAP>
-__global__ __launch_bounds__(PK_T) __attribute__((amdgpu_waves_per_eu(8))) void k_pack_tiled_multi(const PackJob* __restrict__ jobs,
+template <int ECAP, int T>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(8))) void k_pack_tiled_multi(const PackJob* __restrict__ jobs,
                                                            const uint32_t* __restrict__ kjob,
                                                            uint32_t nk,
                                                            const uint64_t* __restrict__ kstart,
@@ -310,8 +314,8 @@ __global__ __launch_bounds__(PK_T) __attribute__((amdgpu_waves_per_eu(8))) void 
   }
   const uint32_t jd = kjob[lo];
   const PackJob j = jobs[jd];
-  pack_tile(sm, j.rp, j.ci, j.n, j.nnz, j.m, reinterpret_cast<unsigned long long*>(j.B), j.Wp,
-            j.colsum, err + jd, b - kstart[lo]);
+  pack_tile<ECAP, T>(sm, j.rp, j.ci, j.n, j.nnz, j.m, reinterpret_cast<unsigned long long*>(j.B),
+                     j.Wp, j.colsum, err + jd, b - kstart[lo]);
 }
 
 // Support of each single item: popcount of its column, one workgroup per column.
@@ -705,9 +709,10 @@ void launch_pack_multi(const PackJob* jobs, bool sparse, const uint32_t* kjob, u
   if (nk == 0 || blocks == 0) return;
   if (blocks > 0x7fffffffull) fail(BM_ERR_UNSUPPORTED, "batch too large for one build");
   if (sparse)
-    k_pack_tiled_multi<PK_ECAP_SPARSE><<<(uint32_t)blocks, PK_T, 0, s>>>(jobs, kjob, nk, kstart, err);
+    k_pack_tiled_multi<PK_ECAP_SPARSE, PK_T_SPARSE>
+        <<<(uint32_t)blocks, PK_T_SPARSE, 0, s>>>(jobs, kjob, nk, kstart, err);
   else
-    k_pack_tiled_multi<PK_ECAP><<<(uint32_t)blocks, PK_T, 0, s>>>(jobs, kjob, nk, kstart, err);
+    k_pack_tiled_multi<PK_ECAP, PK_T><<<(uint32_t)blocks, PK_T, 0, s>>>(jobs, kjob, nk, kstart, err);
   BM_LAUNCH_CHECK();
 }
 

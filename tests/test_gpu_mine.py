@@ -513,6 +513,32 @@ def test_build_batch_matches_single_builds(bm):
         assert_same(r.arrays(), bm.bm_mine(h1, m).arrays())
 
 
+# sparse databases (few ids per row on average) whose first tiles hold long
+# rows: the batched sparse pack stages those tiles' ids in several chunks, over
+# one and two column windows; every pair support against the oracle
+def test_build_batch_sparse_multi_chunk_tiles(bm):
+    dbs = []
+    for seed, n, m in ((31, 3_000, 300), (32, 2_600, 700), (33, 2_100, 90)):
+        rng = np.random.default_rng(seed)
+        lens = rng.poisson(3, n)
+        lens[:256] = rng.poisson(60, 256)          # tile 0: about 15,000 ids
+        lens[256:300] = 400                        # tile 1: long rows, duplicates included
+        row_ptr = np.zeros(n + 1, dtype=np.uint64)
+        np.cumsum(lens, out=row_ptr[1:])
+        assert row_ptr[-1] <= 24 * n                # packed as a sparse database
+        col_idx = rng.integers(0, m, int(row_ptr[-1])).astype(np.uint32)
+        dbs.append((row_ptr, col_idx, n, m))
+    print("sparse batch build with multi-chunk tiles", flush=True)
+    hs = bm.bm_build_batch(dbs)
+    for (row_ptr, col_idx, n, m), h in zip(dbs, hs):
+        want_sums = pairs.column_sums(row_ptr, col_idx, n, m)
+        assert np.array_equal(bm.bm_item_support(h).astype(np.int64), want_sums)
+        items = np.arange(m, dtype=np.uint32)
+        got = np.asarray(bm.bm_pair_support(h, items)).astype(np.int64).reshape(m, m)
+        ref = np.asarray(pairs.pair_support(row_ptr, col_idx, n, m)).astype(np.int64)
+        assert np.array_equal(got, ref)
+
+
 @pytest.mark.parametrize("case", ["bad_item", "decreasing", "nonzero_start"])
 def test_build_batch_errors_name_the_database(bm, case):
     good = gen.random_small(1, 100, 10, density=0.3)
