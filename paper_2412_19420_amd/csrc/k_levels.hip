@@ -109,14 +109,50 @@ __device__ inline uint32_t andpop_pairs(uint32_t q, uint32_t block = AP_BLOCK) {
   return nb * (nb + 1) / 2 - ((q % block) == 1 ? 1u : 0u);
 }
 
+// Rows of at most this many entries are counted (and written out) by one
+// lane, longer ones by a whole wave.
+constexpr uint32_t NODE_LANE_ROW = 16;
+
+}  // namespace
+
+// Nodes per wave of the node-count and next-level kernels: up to 64 (one per
+// lane) when rows are short, fewer as rows grow (a long row takes the whole
+// wave, node after node), and few enough that the level still spreads over
+// about 2,048 waves.
+uint32_t node_batch(uint64_t n, uint64_t tri_total) {
+  const uint64_t avg = n ? tri_total / n : 0;
+  const uint64_t units = std::max<uint64_t>(1, (avg + NODE_LANE_ROW - 1) / NODE_LANE_ROW);
+  uint64_t b = std::max<uint64_t>(1, 64 / units);
+  b = std::min<uint64_t>(b, std::max<uint64_t>(1, n / 2048));
+  return (uint32_t)b;
+}
+
+namespace {
+
+// loc[base + idx] += v for a run-time idx < n, with constant indices only, so
+// the counters stay in registers (a run-time index would put them in scratch)
+__device__ __forceinline__ void loc_add(unsigned long long (&loc)[NC_COUNT], int base, int idx,
+                                        int n, unsigned long long v) {
+#pragma unroll
+  for (int j = 0; j < 5; ++j)
+    if (j < n && j == idx) loc[base + j] += v;
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int j) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, j);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), j);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Per node of level k: number of frequent children, and what it contributes
 // to the next step if it becomes a class.  Also accumulates per-step totals
 // (candidates, columns read, classes per kernel) for the statistics, and the
 // next step's task-count bounds.
 __global__ __launch_bounds__(kThreads) void k_node_counts(
-    uint64_t n, uint32_t k, const uint32_t* __restrict__ parent, const int32_t* __restrict__ pcls,
-    const ClassDesc* __restrict__ cls, const DbInfo* __restrict__ dbs,
-    const uint32_t* __restrict__ tri, uint32_t mfma_min_q, uint32_t big_q, uint32_t small_on,
+    uint64_t n, uint32_t nb, uint32_t k, const uint32_t* __restrict__ parent,
+    const int32_t* __restrict__ pcls, const ClassDesc* __restrict__ cls,
+    const DbInfo* __restrict__ dbs, const uint32_t* __restrict__ tri, uint32_t mfma_min_q,
+    uint32_t big_q, uint32_t small_on,
     uint32_t tiny_q, uint32_t* __restrict__ cnt, uint32_t* __restrict__ is_cls,
     uint64_t* __restrict__ tri_sz, unsigned long long* __restrict__ st,
     const uint32_t* __restrict__ supp, uint32_t proj_on, uint32_t* __restrict__ pflag,
@@ -128,40 +164,64 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
   unsigned long long loc[NC_COUNT];
 #pragma unroll
   for (int j = 0; j < NC_COUNT; ++j) loc[j] = 0;
-  // wave per node: its frequent extensions are the entries of its row of its
-  // class's triangle that meet the class's threshold
+  // a node's frequent extensions are the entries of its row of its class's
+  // triangle that meet the class's threshold.  Nodes go to waves nb at a
+  // time: each lane fetches its own node's class, database and row, so the
+  // chain of dependent loads is paid once per nb nodes; a row of at most
+  // NODE_LANE_ROW entries is then counted by its lane, a longer one by the
+  // whole wave, one such node after another.
+  const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t i = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6; i < n; i += nwaves) {
-    const int32_t c = pcls[parent[i]];
-    uint32_t kc = 0;
-    uint64_t n_db = 0, w_db = 0;
-    if (c >= 0) {
-      const ClassDesc cd = cls[c];
-      n_db = dbs[cd.db].n;
-      w_db = dbs[cd.db].W;
-      const uint64_t li = i - cd.child0;
-      if (li + 1 < cd.q) {
-        const uint64_t rs = cd.tri_off + tri_index(li, li + 1, cd.q);
-        const uint64_t len = cd.q - li - 1;
-        const uint32_t minsup = dbs[cd.db].minsup;
-        // sixteen 64-entry chunks per pass: their loads are in flight together
-        // (a level-1 row is as long as the number of frequent items)
-        for (uint64_t t0 = 0; t0 < len; t0 += 1024) {
-          uint32_t v[16];
-#pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const uint64_t t = t0 + 64 * u + lane;
-            v[u] = t < len ? tri[rs + t] : 0u;
-          }
-#pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const bool f = t0 + 64 * u + lane < len && v[u] >= minsup;
-            kc += (uint32_t)__popcll(__ballot(f));
-          }
+  for (uint64_t i0 = wave * nb; i0 < n; i0 += nwaves * nb) {
+    const uint64_t i = i0 + lane;
+    const bool mine = (uint32_t)lane < nb && i < n;
+    uint64_t n_db = 0, w_db = 0, rs = 0, len = 0;
+    uint32_t minsup = 0;
+    if (mine) {
+      const int32_t c = pcls[parent[i]];
+      if (c >= 0) {
+        const ClassDesc cd = cls[c];
+        n_db = dbs[cd.db].n;
+        w_db = dbs[cd.db].W;
+        const uint64_t li = i - cd.child0;
+        if (li + 1 < cd.q) {
+          rs = cd.tri_off + tri_index(li, li + 1, cd.q);
+          len = cd.q - li - 1;
+          minsup = dbs[cd.db].minsup;
         }
       }
     }
-    if (lane == 0) {
+    uint32_t kc = 0;
+    if (len <= NODE_LANE_ROW) {  // the lane's own row: its loads in flight together
+      uint32_t v[NODE_LANE_ROW];
+#pragma unroll
+      for (uint32_t u = 0; u < NODE_LANE_ROW; ++u) v[u] = u < len ? tri[rs + u] : 0u;
+#pragma unroll
+      for (uint32_t u = 0; u < NODE_LANE_ROW; ++u) kc += (u < len && v[u] >= minsup) ? 1u : 0u;
+    }
+    for (uint64_t lm = __ballot(len > NODE_LANE_ROW); lm; lm &= lm - 1) {
+      const int j = __builtin_ctzll(lm);
+      const uint64_t rj = readlane64(rs, j), lj = readlane64(len, j);
+      const uint32_t mj = (uint32_t)__builtin_amdgcn_readlane((int)minsup, j);
+      // sixteen 64-entry chunks per pass: their loads are in flight together
+      // (a level-1 row is as long as the number of frequent items)
+      uint32_t sum = 0;
+      for (uint64_t t0 = 0; t0 < lj; t0 += 1024) {
+        uint32_t v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const uint64_t t = t0 + 64 * u + lane;
+          v[u] = t < lj ? tri[rj + t] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const bool f = t0 + 64 * u + lane < lj && v[u] >= mj;
+          sum += (uint32_t)__popcll(__ballot(f));
+        }
+      }
+      if (lane == j) kc = sum;
+    }
+    if (mine) {
       cnt[i] = kc;
       const bool cl = kc >= 2;
       const int kind = cl ? class_kind(kc, mfma_min_q, big_q, small_on, tiny_q) : -1;
@@ -178,8 +238,8 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
         pwords[i] = pj ? (uint64_t)kc * view_padded_words(sp) : 0ull;
         if (pj) {
           const int b = kind == 3 ? NC_PJ_CAND_B - NC_PJ_CAND_M : 0;
-          loc[NC_PJ_CAND_M + b] += tsz;
-          loc[NC_PJ_WORK_M + b] += (unsigned long long)sp * tsz;
+          loc_add(loc, NC_PJ_CAND_M, b, 3, tsz);
+          loc_add(loc, NC_PJ_WORK_M, b, 3, (unsigned long long)sp * tsz);
           loc[NC_PJ_COLS] += kc;
         }
       }
@@ -188,9 +248,9 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
         const bool tail = kind == 0 && small_on && !pj && gram_tail(kc);
         const uint64_t qm = tail ? gram_tail_q(kc) : kc;
         const uint64_t tm_sz = tail ? qm * (qm - 1) / 2 : tsz;
-        loc[ST_CAND_M + kind] += tm_sz;
-        loc[ST_COLS_M + kind] += kc + k;
-        loc[ST_CLS_M + kind] += 1;
+        loc_add(loc, ST_CAND_M, kind, 5, tm_sz);
+        loc_add(loc, ST_COLS_M, kind, 5, kc + k);
+        loc_add(loc, ST_CLS_M, kind, 5, 1);
         if (tail) {
           loc[ST_CAND_S] += tsz - tm_sz;
           loc[ST_COLS_S] += kc + k;
@@ -209,42 +269,82 @@ __global__ __launch_bounds__(kThreads) void k_node_counts(
       }
     }
   }
-  for (int j = 0; j < NC_COUNT; ++j)
-    if (loc[j]) atomicAdd(&s_st[j], loc[j]);
+  // the wave's sums, one LDS atomic per counter
+#pragma unroll
+  for (int j = 0; j < NC_COUNT; ++j) {
+    unsigned long long x = loc[j];
+    if (__ballot(x != 0)) {
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+      if (lane == 0) atomicAdd(&s_st[j], x);
+    }
+  }
   __syncthreads();
   if (threadIdx.x < NC_COUNT && s_st[threadIdx.x]) atomicAdd(&st[threadIdx.x], s_st[threadIdx.x]);
 }
 
-// Wave per node: write the node's frequent extensions into the next level.
-// Threads [t0, t0 + nt) of a launch take part.
+// The nodes' frequent extensions written into the next level, nb nodes per
+// wave as in the node-count kernel: a short row by its node's lane, a long
+// one by the whole wave.  Threads [t0, t0 + nt) of a launch take part.
 __device__ inline void fill_level_body(const LevelPost& a, uint64_t t0, uint64_t nt) {
   const int lane = threadIdx.x & 63;
   const uint64_t wave0 = t0 >> 6;
   const uint64_t nwaves = nt >> 6;
-  for (uint64_t i = wave0; i < a.n; i += nwaves) {
-    const int32_t c = a.pcls[a.parent[i]];
-    if (c < 0) continue;
-    const ClassDesc cd = a.cls[c];
-    const uint64_t li = i - cd.child0;
-    if (li + 1 >= cd.q) continue;
-    const uint64_t rs = cd.tri_off + tri_index(li, li + 1, cd.q);
-    const uint64_t len = cd.q - li - 1;
-    const uint32_t minsup = a.dbs[cd.db].minsup;
-    // the node's children start at child_start[i], in row order
-    uint64_t base = a.child_start[i];
-    for (uint64_t t0 = 0; t0 < len; t0 += 64) {
-      const uint64_t t = t0 + lane;
-      const uint32_t v = t < len ? a.tri[rs + t] : 0u;
-      const bool f = t < len && v >= minsup;
-      const uint64_t m = __ballot(f);
-      if (f) {
-        const uint64_t pos = base + (uint64_t)__popcll(m & ((1ull << lane) - 1));
-        a.nitem[pos] = a.child_item[cd.child0 + li + 1 + t];
-        a.nparent[pos] = (uint32_t)i;
-        a.nsupp[pos] = v;
-        a.ndbv[pos] = cd.db;
+  const uint32_t nb = a.nb;
+  for (uint64_t i0 = wave0 * nb; i0 < a.n; i0 += nwaves * nb) {
+    const uint64_t i = i0 + lane;
+    uint64_t rs = 0, len = 0, base = 0, ci = 0;  // row, its length, first slot, first child
+    uint32_t minsup = 0, db = 0;
+    if ((uint32_t)lane < nb && i < a.n) {
+      const int32_t c = a.pcls[a.parent[i]];
+      if (c >= 0) {
+        const ClassDesc cd = a.cls[c];
+        const uint64_t li = i - cd.child0;
+        if (li + 1 < cd.q) {
+          rs = cd.tri_off + tri_index(li, li + 1, cd.q);
+          len = cd.q - li - 1;
+          minsup = a.dbs[cd.db].minsup;
+          base = a.child_start[i];  // the node's children, in row order
+          ci = cd.child0 + li + 1;
+          db = cd.db;
+        }
       }
-      base += (uint64_t)__popcll(m);
+    }
+    if (len <= NODE_LANE_ROW) {
+      uint32_t v[NODE_LANE_ROW];
+#pragma unroll
+      for (uint32_t u = 0; u < NODE_LANE_ROW; ++u) v[u] = u < len ? a.tri[rs + u] : 0u;
+#pragma unroll
+      for (uint32_t u = 0; u < NODE_LANE_ROW; ++u) {
+        if (u < len && v[u] >= minsup) {
+          a.nitem[base] = a.child_item[ci + u];
+          a.nparent[base] = (uint32_t)i;
+          a.nsupp[base] = v[u];
+          a.ndbv[base] = db;
+          ++base;
+        }
+      }
+    }
+    for (uint64_t lm = __ballot(len > NODE_LANE_ROW); lm; lm &= lm - 1) {
+      const int j = __builtin_ctzll(lm);
+      const uint64_t rj = readlane64(rs, j), lj = readlane64(len, j), cj = readlane64(ci, j);
+      uint64_t bj = readlane64(base, j);
+      const uint32_t mj = (uint32_t)__builtin_amdgcn_readlane((int)minsup, j);
+      const uint32_t dj = (uint32_t)__builtin_amdgcn_readlane((int)db, j);
+      const uint32_t ij = (uint32_t)(i0 + (uint64_t)j);
+      for (uint64_t t0 = 0; t0 < lj; t0 += 64) {
+        const uint64_t t = t0 + lane;
+        const uint32_t v = t < lj ? a.tri[rj + t] : 0u;
+        const bool f = t < lj && v >= mj;
+        const uint64_t m = __ballot(f);
+        if (f) {
+          const uint64_t pos = bj + (uint64_t)__popcll(m & ((1ull << lane) - 1));
+          a.nitem[pos] = a.child_item[cj + t];
+          a.nparent[pos] = ij;
+          a.nsupp[pos] = v;
+          a.ndbv[pos] = dj;
+        }
+        bj += (uint64_t)__popcll(m);
+      }
     }
   }
 }
@@ -645,26 +745,28 @@ void launch_gather_idx(const uint64_t* arr, const uint64_t* idx, uint32_t k, uin
 }
 
 
-void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const int32_t* pcls,
-                        const ClassDesc* cls, const DbInfo* dbs, const uint32_t* tri,
-                        uint32_t mfma_min_q, uint32_t big_q, uint32_t small_on, uint32_t tiny_q,
-                        uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz, unsigned long long* st,
-                        const uint32_t* supp, uint32_t proj_on, uint32_t* pflag, uint32_t* prows,
-                        uint64_t* pwords, hipStream_t s) {
+void launch_node_counts(uint64_t n, uint32_t nb, uint32_t k, const uint32_t* parent,
+                        const int32_t* pcls, const ClassDesc* cls, const DbInfo* dbs,
+                        const uint32_t* tri, uint32_t mfma_min_q, uint32_t big_q, uint32_t small_on,
+                        uint32_t tiny_q, uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz,
+                        unsigned long long* st, const uint32_t* supp, uint32_t proj_on,
+                        uint32_t* pflag, uint32_t* prows, uint64_t* pwords, hipStream_t s) {
   if (n == 0) return;
+  if (nb == 0 || nb > 64) fail(BM_ERR_INVALID_ARG, "node batch %u outside 1..64", nb);
   // at most 1,024 workgroups: each ends with a few device-wide atomic adds
   // on the same counters, and with 4,096 of them those serialised (T40-style
   // level steps 0.46 ms per mine call, against 0.40 with 1,024 and 0.41 with
   // 256; 256 cost the batch of 256 databases 9% on this kernel)
-  k_node_counts<<<grid_for(n, kThreads / 64, 1024), kThreads, 0, s>>>(
-      n, k, parent, pcls, cls, dbs, tri, mfma_min_q, big_q, small_on, tiny_q, cnt, is_cls, tri_sz,
-      st, supp, proj_on, pflag, prows, pwords);
+  k_node_counts<<<grid_for((n + nb - 1) / nb, kThreads / 64, 1024), kThreads, 0, s>>>(
+      n, nb, k, parent, pcls, cls, dbs, tri, mfma_min_q, big_q, small_on, tiny_q, cnt, is_cls,
+      tri_sz, st, supp, proj_on, pflag, prows, pwords);
   BM_LAUNCH_CHECK();
 }
 
 void launch_level_post(LevelPost a, hipStream_t s) {
   if (a.n == 0) return;
-  a.b_level = grid_for(a.n * 64, kThreads);
+  if (a.nb == 0 || a.nb > 64) fail(BM_ERR_INVALID_ARG, "node batch %u outside 1..64", a.nb);
+  a.b_level = grid_for((a.n + a.nb - 1) / a.nb * 64, kThreads);
   a.b_cls = a.ocls ? grid_for(a.n, kThreads) : 0u;
   const uint32_t bz = a.nz ? grid_for(a.nz, kThreads, 16384) : 0u;
   k_level_post<<<a.b_level + a.b_cls + bz, kThreads, 0, s>>>(a);

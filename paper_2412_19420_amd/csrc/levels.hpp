@@ -99,7 +99,11 @@ void launch_gather_idx(const uint64_t* arr, const uint64_t* idx, uint32_t k, uin
 // class will be projected (pflag),
 // the length of its prefix's row list (prows: the node's support) and the
 // words of its view (pwords: children x padded view words), else zeros.
-void launch_node_counts(uint64_t n, uint32_t k, const uint32_t* parent, const int32_t* pcls,
+// Nodes per wave of the node-count and next-level kernels for n nodes whose
+// rows hold tri_total entries in all.
+uint32_t node_batch(uint64_t n, uint64_t tri_total);
+void launch_node_counts(uint64_t n, uint32_t nb, uint32_t k, const uint32_t* parent,
+                        const int32_t* pcls,
                         const ClassDesc* cls, const DbInfo* dbs, const uint32_t* tri,
                         uint32_t mfma_min_q, uint32_t big_q, uint32_t small_on, uint32_t tiny_q,
                         uint32_t* cnt, uint32_t* is_cls, uint64_t* tri_sz, unsigned long long* st,
@@ -133,6 +137,7 @@ struct LevelPost {
   int32_t* pcls_out;
   uint32_t* ztri;
   uint64_t nz;
+  uint32_t nb;              // nodes per wave (node_batch)
   uint32_t b_level, b_cls;  // set by the launcher
   // the next step's per-class task counts (as k_class_task_counts writes them)
   TaskGeom geo;

@@ -1176,7 +1176,8 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
           prows.alloc(nk, s);
           pwords.alloc(nk, s);
         }
-        launch_node_counts(nk, k, L[k].parent.get(), pcls_prev.get(), w->cls.get(), ddb_p,
+        const uint32_t nb = node_batch(nk, w->T);
+        launch_node_counts(nk, nb, k, L[k].parent.get(), pcls_prev.get(), w->cls.get(), ddb_p,
                            w->tri.get(), tu.mfma_min_q, tu.mfma_big_q, tu.mfma_small ? 1u : 0u,
                            tu.tiny_q, cnt.get(), iscls.get(), trisz.get(), dst,
                            L[k].supp.get(), proj ? tu.project_gain : 0u, pflag.get(), prows.get(),
@@ -1222,6 +1223,7 @@ std::vector<bm_result*> mine_many(const bm_db* const* dbs, const uint32_t* minsu
         tm.begin(BM_K_LEVEL);
         LevelPost lp{};
         lp.n = nk;
+        lp.nb = nb;
         lp.parent = L[k].parent.get();
         lp.pcls = pcls_prev.get();
         lp.cls = w->cls.get();
