@@ -154,13 +154,13 @@ DTYPE = {"fp4": "u64 bitsets; fp4 (e2m1) MFMA, fp32 accumulate (exact: counts < 
 TRAFFIC = {
     # dense_planted 1M x 4,096, cache-cold mine (profiles/dense_planted_1M_hbm_traffic.md); the
     # Gram entries also hash the task generation, which decides the tiles a launch computes
-    (3, "gram_mfma", "fp4"): (("k_gram_mfma.hip", "gram_fp4.hpp", "internal.hpp", "k_levels.hip", "levels.hpp"), "1b59d1049385041072b969421da8f8d954d2114badf8885c27e6d5f1e24fd14b", 4637.2e6),
-    (3, "gram_small", "fp4"): (("k_gram_small.hip", "internal.hpp", "k_levels.hip", "levels.hpp"), "dd183be8c45c46f454014b614ab49ff3262122155e4f03f15df71d22dcf11940", 268.3e6),
-    (3, "dfs", "fp4"): (("k_subsets.hip", "internal.hpp"), "7733ae4634918b5e502294cd009d3e1dd5e305d1f82bd7f37077fffdff1370c0", 757.8e6),
+    (3, "gram_mfma", "fp4"): (("k_gram_mfma.hip", "gram_fp4.hpp", "internal.hpp", "k_levels.hip", "levels.hpp"), "055731e3058b3b9b94648cdf4e84114a80ec5c0ce9e8a835f4df54a2859eed81", 4638.5e6),
+    (3, "gram_small", "fp4"): (("k_gram_small.hip", "internal.hpp", "k_levels.hip", "levels.hpp"), "44bb72ce0203840d6ad79e12213a2df5cc569f441796155f30dc025e4406650d", 268.2e6),
+    (3, "dfs", "fp4"): (("k_subsets.hip", "internal.hpp"), "7733ae4634918b5e502294cd009d3e1dd5e305d1f82bd7f37077fffdff1370c0", 756.7e6),
     # Quest T40-style 1M x 2,000, cache-cold mine (profiles/quest_t40_1M_hbm_traffic.md)
-    (5, "gram_mfma", "fp4"): (("k_gram_mfma.hip", "gram_fp4.hpp", "internal.hpp", "k_levels.hip", "levels.hpp"), "1b59d1049385041072b969421da8f8d954d2114badf8885c27e6d5f1e24fd14b", 2572.6e6),
-    (5, "gram_small", "fp4"): (("k_gram_small.hip", "internal.hpp", "k_levels.hip", "levels.hpp"), "dd183be8c45c46f454014b614ab49ff3262122155e4f03f15df71d22dcf11940", 217.1e6),
-    (5, "dfs", "fp4"): (("k_subsets.hip", "internal.hpp"), "7733ae4634918b5e502294cd009d3e1dd5e305d1f82bd7f37077fffdff1370c0", 348.1e6),
+    (5, "gram_mfma", "fp4"): (("k_gram_mfma.hip", "gram_fp4.hpp", "internal.hpp", "k_levels.hip", "levels.hpp"), "055731e3058b3b9b94648cdf4e84114a80ec5c0ce9e8a835f4df54a2859eed81", 2569.1e6),
+    (5, "gram_small", "fp4"): (("k_gram_small.hip", "internal.hpp", "k_levels.hip", "levels.hpp"), "44bb72ce0203840d6ad79e12213a2df5cc569f441796155f30dc025e4406650d", 217.4e6),
+    (5, "dfs", "fp4"): (("k_subsets.hip", "internal.hpp"), "7733ae4634918b5e502294cd009d3e1dd5e305d1f82bd7f37077fffdff1370c0", 347.7e6),
 }
 WORKLOAD = None
 
