@@ -331,8 +331,10 @@ constexpr int WSCAP = 24;  // stack entries per wave: <= 6 + 5 + ... + 1 pending
 // step, the 28 pair counts are reduced by a transposing butterfly (lane 2p
 // ends up with pair p after 32 shuffles), and lane i records child i.  No
 // workgroup barrier is ever taken, so four waves per workgroup mine four
-// subtrees independently.
-__global__ __launch_bounds__(256, 4) void k_dfs_wave(DfsArgs a) {
+// subtrees independently.  Three workgroups per CU: 144 VGPRs and no spills
+// (the 128-VGPR bound of four spilled 12 registers and measured 5% slower on
+// the batch of 256 databases).
+__global__ __launch_bounds__(256, 3) void k_dfs_wave(DfsArgs a) {
   __shared__ Entry s_stack[4][WSCAP];
   __shared__ uint32_t s_pre[4][BM_MAX_LEVELS];
   __shared__ WorkerStats s_ws[4];
