@@ -8,7 +8,7 @@ prefixes (masked Gram on MFMA for large prefix classes, subset counting or
 AND+popcount for small ones), and the canonical-order result (bm_mine).
 Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--workload 3]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--workload 3]
 
 value = candidate supports counted per second of step wall time (pairs of
 frequent items plus every longer candidate; the two parts are reported
@@ -624,7 +624,7 @@ def _secondary(args, bm, torch, dev):
     global WORKLOAD
     sec = {}
     WORKLOAD = 4
-    b = run_batched(args, bm, torch, dev, steps=3, warmup=1)
+    b = run_batched(args, bm, torch, dev, steps=10, warmup=3)
     sec["batch_256"] = {"ms_per_step_by_mode": {k: v["ms_per_step"]
                                                 for k, v in b["config"]["modes"].items()},
                         "mine_ms_by_mode": {k: v["mine_ms"] for k, v in b["config"]["modes"].items()},
@@ -637,7 +637,7 @@ def _secondary(args, bm, torch, dev):
                                             "dfs_max_words": 0xFFFFFFFF}),
                      ("depth_first_learned", {"extra_flags": bm.FLAG_DEPTH_FIRST,
                                               "dfs_max_words": 0xFFFFFFFF, "sched": "learned"})):
-        r = run_single(args, bm, torch, dev, 5, 3, 1, cold_steps=3 if name == "default" else 0,
+        r = run_single(args, bm, torch, dev, 5, 10, 3, cold_steps=3 if name == "default" else 0,
                        quiet=True, **kw)
         e = {"ms_per_step": r["ms_per_step"], "mine_ms": r["config"]["mine_ms"],
              "candidates": r["config"]["candidates"], "value": r["value"]}
@@ -656,8 +656,8 @@ def _secondary(args, bm, torch, dev):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", type=int, default=3, choices=sorted(WORKLOADS),
                     help="1-3, 5: one database; 4: the batch of 256 (mode comparison)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
