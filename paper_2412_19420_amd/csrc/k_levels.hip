@@ -11,10 +11,11 @@
 //     pairs of children; supports land in the step's triangle buffer, class by
 //     class, row by row -- which is exactly lexicographic order of the
 //     candidate itemsets;
-//   * a wave per node counts the entries of its triangle row that meet its
-//     database's minsup; an exclusive scan over the nodes gives each node's
-//     first child in level k+1, and the wave's in-row ballot ranks place the
-//     children after it, so the next level comes out already sorted;
+//   * each node's entries of its triangle row that meet its database's
+//     minsup are counted (a lane per node for short rows, the whole wave for
+//     long ones); an exclusive scan over the nodes gives each node's first
+//     child in level k+1, and in-row ranks place the children after it, so the
+//     next level comes out already sorted;
 //   * a node with c >= 2 frequent children becomes a class of the next step.
 #include "internal.hpp"
 #include <algorithm>
