@@ -154,12 +154,12 @@ DTYPE = {"fp4": "u64 bitsets; fp4 (e2m1) MFMA, fp32 accumulate (exact: counts < 
 TRAFFIC = {
     # dense_planted 1M x 4,096, cache-cold mine (profiles/dense_planted_1M_hbm_traffic.md); the
     # Gram entries also hash the task generation, which decides the tiles a launch computes
-    (3, "gram_mfma", "fp4"): (("k_gram_mfma.hip", "gram_fp4.hpp", "internal.hpp", "k_levels.hip", "levels.hpp"), "055731e3058b3b9b94648cdf4e84114a80ec5c0ce9e8a835f4df54a2859eed81", 4638.5e6),
-    (3, "gram_small", "fp4"): (("k_gram_small.hip", "internal.hpp", "k_levels.hip", "levels.hpp"), "44bb72ce0203840d6ad79e12213a2df5cc569f441796155f30dc025e4406650d", 268.2e6),
+    (3, "gram_mfma", "fp4"): (("k_gram_mfma.hip", "gram_fp4.hpp", "internal.hpp", "k_levels.hip", "levels.hpp"), "b5b0d612e6a4a81393ecb9db6a59bb527a591ef697d7322eaf29f9e57f7b5edd", 4638.5e6),
+    (3, "gram_small", "fp4"): (("k_gram_small.hip", "internal.hpp", "k_levels.hip", "levels.hpp"), "12aff1a997e66c468caaba250b2bd88f261c9f6dedc5743b57be77b9ead886b4", 268.2e6),
     (3, "dfs", "fp4"): (("k_subsets.hip", "internal.hpp"), "7733ae4634918b5e502294cd009d3e1dd5e305d1f82bd7f37077fffdff1370c0", 756.7e6),
     # Quest T40-style 1M x 2,000, cache-cold mine (profiles/quest_t40_1M_hbm_traffic.md)
-    (5, "gram_mfma", "fp4"): (("k_gram_mfma.hip", "gram_fp4.hpp", "internal.hpp", "k_levels.hip", "levels.hpp"), "055731e3058b3b9b94648cdf4e84114a80ec5c0ce9e8a835f4df54a2859eed81", 2569.1e6),
-    (5, "gram_small", "fp4"): (("k_gram_small.hip", "internal.hpp", "k_levels.hip", "levels.hpp"), "44bb72ce0203840d6ad79e12213a2df5cc569f441796155f30dc025e4406650d", 217.4e6),
+    (5, "gram_mfma", "fp4"): (("k_gram_mfma.hip", "gram_fp4.hpp", "internal.hpp", "k_levels.hip", "levels.hpp"), "b5b0d612e6a4a81393ecb9db6a59bb527a591ef697d7322eaf29f9e57f7b5edd", 2569.1e6),
+    (5, "gram_small", "fp4"): (("k_gram_small.hip", "internal.hpp", "k_levels.hip", "levels.hpp"), "12aff1a997e66c468caaba250b2bd88f261c9f6dedc5743b57be77b9ead886b4", 217.4e6),
     (5, "dfs", "fp4"): (("k_subsets.hip", "internal.hpp"), "7733ae4634918b5e502294cd009d3e1dd5e305d1f82bd7f37077fffdff1370c0", 347.7e6),
 }
 WORKLOAD = None
