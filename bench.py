@@ -686,8 +686,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); multi-GPU runs are not part "
-              "of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the library runs on one GPU "
+              "and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
